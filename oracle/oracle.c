@@ -1,0 +1,840 @@
+/*
+ * FP64 CPU oracle for the spheroidal Laplace layer-potential apply of
+ * Crowder, Li, Corona and Veerapaneni, "Boundary integral equation analysis for
+ * spheroidal suspensions" (arXiv 2506.20809).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path links, loads or calls
+ * this file; only the test suite, the smoke check and the CPU-baseline leg of
+ * the benchmark do.  It shares no code, header, table or constant with the HIP
+ * library.
+ *
+ * It is deliberately plain: every step follows the paper's definitions or
+ * Algorithm 1 in the paper's order, in double precision, with no blocking,
+ * fusion or reordering beyond what those steps state.  Oblate Legendre
+ * functions are evaluated with complex arithmetic at z = i*u exactly as the
+ * paper writes them (Section 2.3, "Legendre function evaluation").
+ *
+ * Readings where the paper is silent or garbled (each also listed in the design
+ * notes of the repository):
+ *  - azimuthal grid has 2p+2 points (the paper's 2p aliases the m = +-p modes);
+ *    phi_k = 2*pi*k/(2p+2), Gauss-Legendre nodes in ascending v;
+ *  - real orthonormal surface basis (Definition 1 with cos/sin in place of
+ *    exp(i m phi)); Ferrers functions without the Condon-Shortley phase;
+ *  - the Wronskian seed uses the index N of the continued fraction,
+ *    (N+m-1)!/(N-m)!, consistent with the Casoratian it comes from;
+ *  - continued fraction order N = p+1, stop when |delta-1| < 1e-16;
+ *  - oblate branch: (z^2-1)^(1/2) = i*sqrt(u^2+1) at z = i*u, derivatives d/dz;
+ *  - on-surface D is the principal value (average of the one-sided spectra);
+ *  - the near-field expansion of D uses the exterior-limit coefficients;
+ *  - near/far split uses the exact minimum surface distance, diam = twice the
+ *    largest semi-axis, "near" iff d < eta*diam(source) (strict).
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_E_INVALID (-1)
+#define ORC_E_DEGENERATE (-2)
+#define ORC_E_OVERLAP (-3)
+#define ORC_E_NUMERIC (-8)
+
+#define OP_S 0
+#define OP_D 1
+
+static const double PI = 3.14159265358979323846264338327950288;
+
+/* ------------------------------------------------------------------------ */
+/* Small helpers                                                             */
+/* ------------------------------------------------------------------------ */
+
+static double factorial(int n) {
+  double f = 1.0;
+  for (int i = 2; i <= n; ++i) f *= (double)i;
+  return f;
+}
+
+static double double_factorial(int n) { /* n!! with (-1)!! = 1 */
+  double f = 1.0;
+  for (int i = n; i > 1; i -= 2) f *= (double)i;
+  return f;
+}
+
+/* Rotation matrix (row-major, body -> lab) of a unit quaternion (w,x,y,z). */
+static void quat_to_rot(const double q_in[4], double R[9]) {
+  double n = sqrt(q_in[0] * q_in[0] + q_in[1] * q_in[1] + q_in[2] * q_in[2] +
+                  q_in[3] * q_in[3]);
+  double w = q_in[0] / n, x = q_in[1] / n, y = q_in[2] / n, z = q_in[3] / n;
+  R[0] = 1 - 2 * (y * y + z * z);
+  R[1] = 2 * (x * y - w * z);
+  R[2] = 2 * (x * z + w * y);
+  R[3] = 2 * (x * y + w * z);
+  R[4] = 1 - 2 * (x * x + z * z);
+  R[5] = 2 * (y * z - w * x);
+  R[6] = 2 * (x * z - w * y);
+  R[7] = 2 * (y * z + w * x);
+  R[8] = 1 - 2 * (x * x + y * y);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Particle parameters: Section 2.1, Table 1.  Surface u = u0 has semi-axes   */
+/* A = a*sqrt(u0^2 -+ 1) (equatorial) and C = a*u0 (polar).                   */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  int oblate;       /* 0 prolate (C > A), 1 oblate (C < A) */
+  double a, u0;     /* focal parameter and coordinate of the surface */
+  double A, C;      /* semi-axes */
+  double c[3];      /* centre */
+  double R[9];      /* body -> lab rotation */
+  double diam;      /* twice the largest semi-axis */
+} particle;
+
+static int make_particle(const double* centre, const double* quat, double A,
+                         double C, particle* out) {
+  if (!(A > 0) || !(C > 0) || !isfinite(A) || !isfinite(C))
+    return ORC_E_DEGENERATE;
+  double mx = A > C ? A : C;
+  if (fabs(A - C) <= 1e-6 * mx) return ORC_E_DEGENERATE;
+  out->A = A;
+  out->C = C;
+  out->oblate = C < A;
+  if (!out->oblate)
+    out->a = sqrt((C - A) * (C + A));
+  else
+    out->a = sqrt((A - C) * (A + C));
+  out->u0 = C / out->a;
+  for (int k = 0; k < 3; ++k) out->c[k] = centre[k];
+  quat_to_rot(quat, out->R);
+  out->diam = 2.0 * mx;
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Gauss-Legendre rule on [-1,1]: Newton on the Legendre polynomial.          */
+/* ------------------------------------------------------------------------ */
+
+void orc_gauss_legendre(int n, double* x, double* w) {
+  for (int i = 0; i < n; ++i) {
+    /* i-th root counted from the right end, then stored ascending */
+    double t = cos(PI * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = t;
+      for (int k = 2; k <= n; ++k) {
+        double p2 = ((2 * k - 1) * t * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) { p1 = t; p0 = 1.0; }
+      dp = n * (t * p1 - p0) / (t * t - 1.0);
+      double dt = p1 / dp;
+      t -= dt;
+      if (fabs(dt) < 1e-16) break;
+    }
+    {
+      double p0 = 1.0, p1 = t;
+      for (int k = 2; k <= n; ++k) {
+        double p2 = ((2 * k - 1) * t * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) { p1 = t; p0 = 1.0; }
+      dp = n * (t * p1 - p0) / (t * t - 1.0);
+    }
+    x[n - 1 - i] = t;
+    w[n - 1 - i] = 2.0 / ((1.0 - t * t) * dp * dp);
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Associated Legendre functions off the cut, Section 2.3 steps 1-4 and the   */
+/* derivative identity.  z = u (prolate, u > 1) or z = i*u (oblate, u > 0).   */
+/* Arrays are indexed by degree n = 0..N+1; entries with n < m are zero.       */
+/* P, Q are filled for n = m..N; dP, dQ for n = m..N-1 (needs F_{n+1}).        */
+/* ------------------------------------------------------------------------ */
+
+static int cf_max_iter = 10000; /* continued-fraction cap (settable for tests) */
+
+void orc_set_cf_max_iter(int it) { cf_max_iter = it; }
+
+static int legendre_offcut(int oblate, double u, int m, int N,
+                           double complex* P, double complex* Q,
+                           double complex* dP, double complex* dQ) {
+  double complex z = oblate ? I * u : u + 0.0 * I;
+  /* branch of (z^2-1)^(1/2): sqrt(u^2-1) for real z > 1, i*sqrt(u^2+1) at z = iu */
+  double complex s = oblate ? I * sqrt(u * u + 1.0) : sqrt(u * u - 1.0) + 0.0 * I;
+  for (int n = 0; n <= N + 1; ++n) P[n] = Q[n] = dP[n] = dQ[n] = 0;
+
+  /* step 1: forward recurrence for P_n^m, seeds P_m^m and P_{m+1}^m */
+  double complex spow = 1.0;
+  for (int k = 0; k < m; ++k) spow *= s;
+  P[m] = double_factorial(2 * m - 1) * spow;
+  if (m + 1 <= N + 1) P[m + 1] = z * (2 * m + 1) * P[m];
+  for (int n = m + 1; n <= N; ++n)
+    P[n + 1] = ((2 * n + 1) * z * P[n] - (n + m) * P[n - 1]) / (double)(n - m + 1);
+
+  /* step 2: H_N = Q_N/Q_{N-1} by the modified Lentz method on the continued
+     fraction H_n = a_n / (b_n + H_{n+1}),
+     a_n = -(n+m)/(n-m+1), b_n = -(2n+1) z/(n-m+1). */
+  const double tiny = 1e-300;
+  double complex f = tiny, Cl = f, Dl = 0.0;
+  int converged = 0;
+  for (int k = N, it = 0; it < cf_max_iter; ++k, ++it) {
+    double complex ak = -(double)(k + m) / (double)(k - m + 1);
+    double complex bk = -(2.0 * k + 1.0) * z / (double)(k - m + 1);
+    Dl = bk + ak * Dl;
+    if (cabs(Dl) == 0.0) Dl = tiny;
+    Dl = 1.0 / Dl;
+    Cl = bk + ak / Cl;
+    if (cabs(Cl) == 0.0) Cl = tiny;
+    double complex delta = Cl * Dl;
+    f *= delta;
+    if (cabs(delta - 1.0) < 1e-16) { converged = 1; break; }
+  }
+  if (!converged) return ORC_E_NUMERIC;
+  double complex H = f;
+
+  /* step 3: Casoratian seed, Q_{N-1} and Q_N */
+  double cas = factorial(N + m - 1) / factorial(N - m) * ((m & 1) ? -1.0 : 1.0);
+  Q[N - 1] = cas / (P[N] - H * P[N - 1]);
+  Q[N] = H * Q[N - 1];
+
+  /* step 4: backward recurrence down to Q_m^m */
+  for (int n = N - 1; n >= m + 1; --n)
+    Q[n - 1] = ((2 * n + 1) * z * Q[n] - (n - m + 1) * Q[n + 1]) / (double)(n + m);
+
+  /* derivative identity (1 - z^2) F_n' = (m-n-1) F_{n+1} + (n+1) z F_n */
+  for (int n = m; n <= N - 1; ++n) {
+    dP[n] = ((m - n - 1) * P[n + 1] + (n + 1) * z * P[n]) / (1.0 - z * z);
+    dQ[n] = ((m - n - 1) * Q[n + 1] + (n + 1) * z * Q[n]) / (1.0 - z * z);
+  }
+  return ORC_OK;
+}
+
+/* Exported for the pins: values for one order m, degrees 0..N (P, Q) and
+   0..N-1 (derivatives); real and imaginary parts separately. */
+int orc_legendre(int oblate, double u, int m, int N, double* Pre, double* Pim,
+                 double* Qre, double* Qim, double* dPre, double* dPim,
+                 double* dQre, double* dQim) {
+  if (m < 0 || N < m + 1) return ORC_E_INVALID;
+  double complex* buf = (double complex*)malloc(sizeof(double complex) * 4 * (N + 2));
+  double complex *P = buf, *Q = buf + (N + 2), *dP = buf + 2 * (N + 2),
+                 *dQ = buf + 3 * (N + 2);
+  int rc = legendre_offcut(oblate, u, m, N, P, Q, dP, dQ);
+  for (int n = 0; n <= N; ++n) {
+    Pre[n] = creal(P[n]); Pim[n] = cimag(P[n]);
+    Qre[n] = creal(Q[n]); Qim[n] = cimag(Q[n]);
+    dPre[n] = creal(dP[n]); dPim[n] = cimag(dP[n]);
+    dQre[n] = creal(dQ[n]); dQim[n] = cimag(dQ[n]);
+  }
+  free(buf);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Spectra, Theorems 1 and 2, for n <= p and m >= 0 (index n(n+1)/2 + m).     */
+/*  lamDp = D+ (exterior limit), lamDm = D- (interior limit),                 */
+/*  lamD = principal value = (D+ + D-)/2, lamS = surface S in the modified    */
+/*  basis.  Qu0 holds Q_n^m(z0) (complex, for the near-field ratio).          */
+/* ------------------------------------------------------------------------ */
+
+static int spectra(const particle* pt, int p, double* lamD, double* lamDp,
+                   double* lamDm, double* lamS, double complex* Qu0) {
+  int N = p + 1;
+  double complex* buf = (double complex*)malloc(sizeof(double complex) * 4 * (N + 2));
+  double complex *P = buf, *Q = buf + (N + 2), *dP = buf + 2 * (N + 2),
+                 *dQ = buf + 3 * (N + 2);
+  double u0 = pt->u0, a = pt->a;
+  for (int m = 0; m <= p; ++m) {
+    int rc = legendre_offcut(pt->oblate, u0, m, N, P, Q, dP, dQ);
+    if (rc) { free(buf); return rc; }
+    for (int n = m; n <= p; ++n) {
+      double ratio = factorial(n - m) / factorial(n + m);
+      double sgn = (m & 1) ? -1.0 : 1.0;
+      double complex b, bt;
+      if (!pt->oblate) {
+        b = ratio * sgn * (u0 * u0 - 1.0);               /* b_n^m */
+        bt = a * ratio * sgn * sqrt(u0 * u0 - 1.0);      /* b~_n^m */
+      } else {
+        b = ratio * (-sgn) * (u0 * u0 + 1.0);            /* c_n^m */
+        bt = I * a * ratio * sgn * sqrt(u0 * u0 + 1.0);  /* c~_n^m */
+      }
+      double complex lp = b * dP[n] * Q[n];
+      double complex lm = b * dQ[n] * P[n];
+      double complex ls = bt * P[n] * Q[n];
+      int idx = n * (n + 1) / 2 + m;
+      if (lamDp) lamDp[idx] = creal(lp);
+      if (lamDm) lamDm[idx] = creal(lm);
+      if (lamD) lamD[idx] = 0.5 * (creal(lp) + creal(lm));
+      if (lamS) lamS[idx] = creal(ls);
+      if (Qu0) Qu0[idx] = Q[n];
+    }
+  }
+  free(buf);
+  return ORC_OK;
+}
+
+int orc_spectra(int oblate, double a, double u0, int p, double* lamD,
+                double* lamDp, double* lamDm, double* lamS) {
+  particle pt;
+  memset(&pt, 0, sizeof pt);
+  pt.oblate = oblate;
+  pt.a = a;
+  pt.u0 = u0;
+  return spectra(&pt, p, lamD, lamDp, lamDm, lamS, NULL);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Real orthonormal surface harmonics (Definition 1, real form).              */
+/* Y_{n,0} = N_n^0 P_n(v); Y_{n,m} = sqrt2 N_n^m P_n^m(v) cos(m phi);          */
+/* Y_{n,-m} = sqrt2 N_n^m P_n^m(v) sin(m phi).  Index l = n^2 + n + m.         */
+/* Ferrers P_n^m(v) = (1-v^2)^(m/2) d^m P_n/dv^m, no Condon-Shortley phase,   */
+/* computed by the same three-term recurrence in n with seed (2m-1)!!(1-v^2)^(m/2). */
+/* ------------------------------------------------------------------------ */
+
+static void ferrers_all(double v, int p, double* Pf /* [(p+1)(p+2)/2] */) {
+  double sv = sqrt(fmax(0.0, 1.0 - v * v));
+  for (int m = 0; m <= p; ++m) {
+    double pmm = double_factorial(2 * m - 1) * pow(sv, m);
+    Pf[m * (m + 1) / 2 + m] = pmm;
+    if (m + 1 <= p) Pf[(m + 1) * (m + 2) / 2 + m] = v * (2 * m + 1) * pmm;
+    for (int n = m + 1; n < p; ++n) {
+      double pn = Pf[n * (n + 1) / 2 + m];
+      double pn1 = (n - 1 >= m) ? Pf[(n - 1) * n / 2 + m] : 0.0;
+      Pf[(n + 1) * (n + 2) / 2 + m] =
+          ((2 * n + 1) * v * pn - (n + m) * pn1) / (double)(n - m + 1);
+    }
+  }
+}
+
+static void real_harmonics(double v, double phi, int p, double* Y /* [(p+1)^2] */) {
+  int nh = (p + 1) * (p + 2) / 2;
+  double* Pf = (double*)malloc(sizeof(double) * nh);
+  ferrers_all(v, p, Pf);
+  for (int n = 0; n <= p; ++n) {
+    for (int m = 0; m <= n; ++m) {
+      double Nnm = sqrt((2.0 * n + 1.0) / (4.0 * PI) * factorial(n - m) / factorial(n + m));
+      double base = Nnm * Pf[n * (n + 1) / 2 + m];
+      if (m == 0) {
+        Y[n * n + n] = base;
+      } else {
+        Y[n * n + n + m] = sqrt(2.0) * base * cos(m * phi);
+        Y[n * n + n - m] = sqrt(2.0) * base * sin(m * phi);
+      }
+    }
+  }
+  free(Pf);
+}
+
+void orc_real_harmonics(double v, double phi, int p, double* Y) {
+  real_harmonics(v, phi, p, Y);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Grid, Section 4 "Integral density representation" and Tables 1-2:        */
+/* node g = i*T + j*Nphi + k, T = (p+1)*Nphi, Nphi = 2p+2.                    */
+/* Weight W = g_j * (2 pi / Nphi) * a^2 sqrt(u0^2 -+ v^2) sqrt(u0^2 -+ 1).     */
+/* ------------------------------------------------------------------------ */
+
+static void particle_grid(const particle* pt, int p, const double* gx,
+                          const double* gw, double* xyz, double* nrm,
+                          double* W) {
+  int Nphi = 2 * p + 2;
+  double a = pt->a, u0 = pt->u0;
+  double sgn = pt->oblate ? 1.0 : -1.0;
+  double s = sqrt(u0 * u0 + sgn);          /* sqrt(u0^2 -+ 1) */
+  for (int j = 0; j <= p; ++j) {
+    double v = gx[j];
+    double sv = sqrt(1.0 - v * v);
+    for (int k = 0; k < Nphi; ++k) {
+      double phi = 2.0 * PI * k / Nphi;
+      double xb[3] = {a * s * sv * cos(phi), a * s * sv * sin(phi), a * u0 * v};
+      double gb[3] = {xb[0] / (pt->A * pt->A), xb[1] / (pt->A * pt->A),
+                      xb[2] / (pt->C * pt->C)};
+      double gn = sqrt(gb[0] * gb[0] + gb[1] * gb[1] + gb[2] * gb[2]);
+      int g = j * Nphi + k;
+      for (int r = 0; r < 3; ++r) {
+        double xr = pt->c[r], nr = 0.0;
+        for (int c2 = 0; c2 < 3; ++c2) {
+          xr += pt->R[3 * r + c2] * xb[c2];
+          nr += pt->R[3 * r + c2] * gb[c2] / gn;
+        }
+        if (xyz) xyz[3 * g + r] = xr;
+        if (nrm) nrm[3 * g + r] = nr;
+      }
+      double J = a * a * sqrt(u0 * u0 + sgn * v * v) * s;
+      if (W) W[g] = gw[j] * (2.0 * PI / Nphi) * J;
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Discrete transform (Section 2.3; density representation in Section 4):     */
+/* c_l = sum_{j,k} g_j (2 pi / Nphi) f_jk Y_l(v_j, phi_k).                    */
+/* ------------------------------------------------------------------------ */
+
+static void forward_transform(int p, const double* gx, const double* gw,
+                              const double* f, double* coef) {
+  int Nphi = 2 * p + 2, K = (p + 1) * (p + 1);
+  double* Y = (double*)malloc(sizeof(double) * K);
+  for (int l = 0; l < K; ++l) coef[l] = 0.0;
+  for (int j = 0; j <= p; ++j)
+    for (int k = 0; k < Nphi; ++k) {
+      real_harmonics(gx[j], 2.0 * PI * k / Nphi, p, Y);
+      double wf = gw[j] * (2.0 * PI / Nphi) * f[j * Nphi + k];
+      for (int l = 0; l < K; ++l) coef[l] += wf * Y[l];
+    }
+  free(Y);
+}
+
+static void inverse_transform(int p, const double* gx, const double* coef,
+                              double* f) {
+  int Nphi = 2 * p + 2, K = (p + 1) * (p + 1);
+  double* Y = (double*)malloc(sizeof(double) * K);
+  for (int j = 0; j <= p; ++j)
+    for (int k = 0; k < Nphi; ++k) {
+      real_harmonics(gx[j], 2.0 * PI * k / Nphi, p, Y);
+      double acc = 0.0;
+      for (int l = 0; l < K; ++l) acc += coef[l] * Y[l];
+      f[j * Nphi + k] = acc;
+    }
+  free(Y);
+}
+
+int orc_transform(int p, const double* f, double* coef) {
+  double* gx = (double*)malloc(sizeof(double) * 2 * (p + 1));
+  orc_gauss_legendre(p + 1, gx, gx + p + 1);
+  forward_transform(p, gx, gx + p + 1, f, coef);
+  free(gx);
+  return ORC_OK;
+}
+
+int orc_inverse_transform(int p, const double* coef, double* f) {
+  double* gx = (double*)malloc(sizeof(double) * 2 * (p + 1));
+  orc_gauss_legendre(p + 1, gx, gx + p + 1);
+  inverse_transform(p, gx, coef, f);
+  free(gx);
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Spheroidal coordinates of a body-frame point (inverse of Table 1).         */
+/* Prolate: s = u^2-1 solves a^2 s^2 + (a^2 - r^2) s - rho^2 = 0.              */
+/* Oblate:  t = u^2   solves a^2 t^2 + (a^2 - r^2) t - x3^2  = 0.              */
+/* ------------------------------------------------------------------------ */
+
+static void body_to_spheroidal(const particle* pt, const double xb[3], double* u,
+                               double* v, double* phi) {
+  double a = pt->a, a2 = a * a;
+  double rho2 = xb[0] * xb[0] + xb[1] * xb[1];
+  double r2 = rho2 + xb[2] * xb[2];
+  double cst = pt->oblate ? xb[2] * xb[2] : rho2;     /* minus the constant term */
+  double disc = sqrt((a2 - r2) * (a2 - r2) + 4.0 * a2 * cst);
+  double root;
+  if (r2 >= a2)
+    root = ((r2 - a2) + disc) / (2.0 * a2);
+  else
+    root = 2.0 * cst / ((a2 - r2) + disc);
+  double uu = pt->oblate ? sqrt(root) : sqrt(1.0 + root);
+  *u = uu;
+  *v = xb[2] / (a * uu);
+  *phi = atan2(xb[1], xb[0]);
+}
+
+static void lab_to_body(const particle* pt, const double x[3], double xb[3]) {
+  double d[3] = {x[0] - pt->c[0], x[1] - pt->c[1], x[2] - pt->c[2]};
+  for (int c = 0; c < 3; ++c)
+    xb[c] = pt->R[0 + c] * d[0] + pt->R[3 + c] * d[1] + pt->R[6 + c] * d[2];
+}
+
+/* Exterior solid-harmonic expansion of one particle at one exterior point:  */
+/* sum_l E_l * Q_n^|m|(z) / Q_n^|m|(z0) * Y_l(v, phi)  (Theorems 1-2,         */
+/* exterior rows, with E_l the on-surface exterior-limit coefficient).        */
+static int eval_exterior(const particle* pt, int p, const double* E,
+                         const double complex* Qu0, const double x[3],
+                         double* out) {
+  double xb[3], u, v, phi;
+  lab_to_body(pt, x, xb);
+  body_to_spheroidal(pt, xb, &u, &v, &phi);
+  if (!(u > pt->u0)) return ORC_E_OVERLAP;
+  int K = (p + 1) * (p + 1), N = p + 1;
+  double* Y = (double*)malloc(sizeof(double) * K);
+  double complex* buf = (double complex*)malloc(sizeof(double complex) * 4 * (N + 2));
+  double complex *P = buf, *Q = buf + (N + 2), *dP = buf + 2 * (N + 2),
+                 *dQ = buf + 3 * (N + 2);
+  real_harmonics(v, phi, p, Y);
+  double acc = 0.0;
+  for (int m = 0; m <= p; ++m) {
+    int rc = legendre_offcut(pt->oblate, u, m, N, P, Q, dP, dQ);
+    if (rc) { free(Y); free(buf); return rc; }
+    for (int n = m; n <= p; ++n) {
+      double ratio = creal(Q[n] / Qu0[n * (n + 1) / 2 + m]);
+      if (m == 0)
+        acc += E[n * n + n] * ratio * Y[n * n + n];
+      else
+        acc += (E[n * n + n + m] * Y[n * n + n + m] + E[n * n + n - m] * Y[n * n + n - m]) * ratio;
+    }
+  }
+  free(Y);
+  free(buf);
+  *out = acc;
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exact minimum distance between two disjoint spheroids.  Alternating       */
+/* projections give upper bounds |x - y|; the separation of the two support  */
+/* planes orthogonal to (x - y) gives lower bounds.  Iterate until the gap   */
+/* between the bounds is below tol.  Returns a negative number on overlap.   */
+/* ------------------------------------------------------------------------ */
+
+/* closest point of the body-frame spheroid (A,A,C) to body-frame point q outside */
+static void project_body(double A, double C, const double q[3], double out[3]) {
+  double rho = sqrt(q[0] * q[0] + q[1] * q[1]), z = fabs(q[2]);
+  double A2 = A * A, C2 = C * C;
+  /* f(t) = rho^2 A^2/(A^2+t)^2 + z^2 C^2/(C^2+t)^2 - 1, decreasing for t >= 0 */
+  double lo = 0.0, hi = fmax(A, C) * sqrt(rho * rho + z * z) + 1e-300;
+  double t = 0.0;
+  double f0 = rho * rho / A2 + z * z / C2 - 1.0;
+  if (f0 <= 0.0) { t = 0.0; }
+  else {
+    for (int it = 0; it < 200; ++it) {
+      double ea = A2 + t, ec = C2 + t;
+      double f = rho * rho * A2 / (ea * ea) + z * z * C2 / (ec * ec) - 1.0;
+      double df = -2.0 * rho * rho * A2 / (ea * ea * ea) - 2.0 * z * z * C2 / (ec * ec * ec);
+      if (f == 0.0) break;
+      if (f > 0) lo = t; else hi = t;
+      double tn = t - f / df;
+      if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+      if (fabs(tn - t) <= 1e-16 * fmax(1.0, tn)) { t = tn; break; }
+      t = tn;
+    }
+  }
+  double fr = A2 / (A2 + t), fz = C2 / (C2 + t);
+  out[0] = q[0] * fr;
+  out[1] = q[1] * fr;
+  out[2] = q[2] * fz;
+}
+
+static void project_lab(const particle* pt, const double x[3], double out[3]) {
+  double xb[3], yb[3];
+  lab_to_body(pt, x, xb);
+  project_body(pt->A, pt->C, xb, yb);
+  for (int r = 0; r < 3; ++r)
+    out[r] = pt->c[r] + pt->R[3 * r] * yb[0] + pt->R[3 * r + 1] * yb[1] + pt->R[3 * r + 2] * yb[2];
+}
+
+/* support function h(n) = max_{x in spheroid} n.x */
+static double support(const particle* pt, const double n[3]) {
+  double nb[3];
+  for (int c = 0; c < 3; ++c)
+    nb[c] = pt->R[0 + c] * n[0] + pt->R[3 + c] * n[1] + pt->R[6 + c] * n[2];
+  double q = pt->A * pt->A * (nb[0] * nb[0] + nb[1] * nb[1]) + pt->C * pt->C * nb[2] * nb[2];
+  return pt->c[0] * n[0] + pt->c[1] * n[1] + pt->c[2] * n[2] + sqrt(q);
+}
+
+static int inside(const particle* pt, const double x[3]) {
+  double xb[3];
+  lab_to_body(pt, x, xb);
+  return (xb[0] * xb[0] + xb[1] * xb[1]) / (pt->A * pt->A) + xb[2] * xb[2] / (pt->C * pt->C) <= 1.0;
+}
+
+static double spheroid_distance(const particle* P1, const particle* P2, double tol) {
+  double x[3], y[3];
+  if (inside(P1, P2->c) || inside(P2, P1->c)) return -1.0;
+  project_lab(P1, P2->c, x);
+  if (inside(P2, x)) return -1.0;
+  double upper = INFINITY, lower = -INFINITY;
+  for (int it = 0; it < 200000; ++it) {
+    project_lab(P2, x, y);
+    if (inside(P1, y)) return -1.0;
+    project_lab(P1, y, x);
+    double d[3] = {y[0] - x[0], y[1] - x[1], y[2] - x[2]};
+    double dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    if (dn < upper) upper = dn;
+    if (dn > 0) {
+      double n[3] = {d[0] / dn, d[1] / dn, d[2] / dn};
+      double mn[3] = {-n[0], -n[1], -n[2]};
+      /* P1 lies in n.z <= h1(n); P2 in n.z >= -h2(-n) */
+      double lb = -support(P2, mn) - support(P1, n);
+      if (lb > lower) lower = lb;
+    }
+    if (upper - lower <= tol) break;
+  }
+  if (lower <= 0.0 && upper <= tol) return -1.0;
+  return 0.5 * (upper + lower);
+}
+
+int orc_distance(const double* c1, const double* q1, double A1, double C1,
+                 const double* c2, const double* q2, double A2, double C2,
+                 double* dist) {
+  particle P1, P2;
+  int rc = make_particle(c1, q1, A1, C1, &P1);
+  if (rc) return rc;
+  rc = make_particle(c2, q2, A2, C2, &P2);
+  if (rc) return rc;
+  *dist = spheroid_distance(&P1, &P2, 1e-12);
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Setup shared by the apply entry points                                    */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  int M, p, T, K, Kh, N;
+  particle* pt;
+  double *gx, *gw;
+  double *xyz, *nrm, *W;
+  uint8_t* near;  /* near[i*M + j] = 1 iff j in J_i^near (j != i) */
+} geometry;
+
+static void free_geometry(geometry* g) {
+  free(g->pt); free(g->gx); free(g->xyz); free(g->nrm); free(g->W); free(g->near);
+}
+
+static int build_geometry(const double* centres, const double* quats,
+                          const double* A, const double* C, int M, int p,
+                          double eta, geometry* g) {
+  memset(g, 0, sizeof *g);
+  if (M < 1 || p < 1 || p > 32 || !(eta >= 0)) return ORC_E_INVALID;
+  g->M = M; g->p = p; g->T = (p + 1) * (2 * p + 2); g->K = (p + 1) * (p + 1);
+  g->Kh = (p + 1) * (p + 2) / 2; g->N = M * g->T;
+  g->pt = (particle*)calloc(M, sizeof(particle));
+  for (int i = 0; i < M; ++i) {
+    int rc = make_particle(centres + 3 * i, quats + 4 * i, A[i], C[i], &g->pt[i]);
+    if (rc) { free_geometry(g); return rc; }
+  }
+  g->gx = (double*)malloc(sizeof(double) * 2 * (p + 1));
+  g->gw = g->gx + p + 1;
+  orc_gauss_legendre(p + 1, g->gx, g->gw);
+  g->xyz = (double*)malloc(sizeof(double) * 3 * g->N);
+  g->nrm = (double*)malloc(sizeof(double) * 3 * g->N);
+  g->W = (double*)malloc(sizeof(double) * g->N);
+  for (int i = 0; i < M; ++i)
+    particle_grid(&g->pt[i], p, g->gx, g->gw, g->xyz + 3 * (size_t)i * g->T,
+                  g->nrm + 3 * (size_t)i * g->T, g->W + (size_t)i * g->T);
+  /* Algorithm 1, lines 3-4: normalised distances and the near/far split */
+  g->near = (uint8_t*)calloc((size_t)M * M, 1);
+  int bad = 0;
+#pragma omp parallel for schedule(dynamic)
+  for (int i = 0; i < M; ++i) {
+    for (int j = 0; j < M; ++j) {
+      if (j == i) continue;
+      const particle *Pi = &g->pt[i], *Pj = &g->pt[j];
+      double dc = sqrt((Pi->c[0] - Pj->c[0]) * (Pi->c[0] - Pj->c[0]) +
+                       (Pi->c[1] - Pj->c[1]) * (Pi->c[1] - Pj->c[1]) +
+                       (Pi->c[2] - Pj->c[2]) * (Pi->c[2] - Pj->c[2]));
+      double lb = dc - 0.5 * Pi->diam - 0.5 * Pj->diam;  /* circumsphere bound */
+      if (lb >= eta * Pi->diam) continue;
+      double d = spheroid_distance(Pi, Pj, 1e-12);
+      if (d <= 0.0) {
+#pragma omp atomic write
+        bad = 1;
+      }
+      if (d < eta * Pi->diam) g->near[(size_t)i * M + j] = 1;
+    }
+  }
+  if (bad) { free_geometry(g); return ORC_E_OVERLAP; }
+  return ORC_OK;
+}
+
+int orc_grid(const double* centres, const double* quats, const double* A,
+             const double* C, int M, int p, double* xyz, double* nrm, double* W) {
+  if (M < 1 || p < 1 || p > 32) return ORC_E_INVALID;
+  double* gx = (double*)malloc(sizeof(double) * 2 * (p + 1));
+  orc_gauss_legendre(p + 1, gx, gx + p + 1);
+  int T = (p + 1) * (2 * p + 2);
+  for (int i = 0; i < M; ++i) {
+    particle pt;
+    int rc = make_particle(centres + 3 * i, quats + 4 * i, A[i], C[i], &pt);
+    if (rc) { free(gx); return rc; }
+    particle_grid(&pt, p, gx, gx + p + 1, xyz + 3 * (size_t)i * T,
+                  nrm + 3 * (size_t)i * T, W + (size_t)i * T);
+  }
+  free(gx);
+  return ORC_OK;
+}
+
+int orc_classify(const double* centres, const double* quats, const double* A,
+                 const double* C, int M, double eta, uint8_t* near) {
+  geometry g;
+  int rc = build_geometry(centres, quats, A, C, M, 1, eta, &g);
+  if (rc) return rc;
+  memcpy(near, g.near, (size_t)M * M);
+  free_geometry(&g);
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Algorithm 1 (and its single-layer variant): u = u_self + u_near + u_far   */
+/* at every node.  op = 0 (S) or 1 (D).  density[N] at the nodes.            */
+/* Outputs may be NULL except u.                                              */
+/* ------------------------------------------------------------------------ */
+
+/* per-particle coefficients and exterior coefficients (line 2, lines 11-14) */
+static int particle_coefficients(const geometry* g, int op, int i,
+                                 const double* dens, double* coef_self,
+                                 double* E, double complex* Qu0) {
+  const particle* pt = &g->pt[i];
+  int p = g->p, Nphi = 2 * p + 2, K = g->K, Kh = g->Kh;
+  double* f = (double*)malloc(sizeof(double) * g->T);
+  double* c = (double*)malloc(sizeof(double) * K);
+  double* lamD = (double*)malloc(sizeof(double) * 4 * Kh);
+  double *lamDp = lamD + Kh, *lamS = lamD + 2 * Kh;
+  int rc = spectra(pt, p, lamD, lamDp, NULL, lamS, Qu0);
+  if (rc) { free(f); free(c); free(lamD); return rc; }
+  double sgn = pt->oblate ? 1.0 : -1.0;
+  for (int j = 0; j <= p; ++j)
+    for (int k = 0; k < Nphi; ++k) {
+      double w = (op == OP_S) ? sqrt(pt->u0 * pt->u0 + sgn * g->gx[j] * g->gx[j]) : 1.0;
+      f[j * Nphi + k] = w * dens[(size_t)i * g->T + j * Nphi + k];
+    }
+  forward_transform(p, g->gx, g->gw, f, c);
+  for (int n = 0; n <= p; ++n)
+    for (int m = -n; m <= n; ++m) {
+      int l = n * n + n + m, h = n * (n + 1) / 2 + abs(m);
+      double lself = (op == OP_S) ? lamS[h] : lamD[h];
+      double lext = (op == OP_S) ? lamS[h] : lamDp[h];
+      coef_self[l] = lself * c[l];
+      E[l] = lext * c[l];
+    }
+  free(f); free(c); free(lamD);
+  return ORC_OK;
+}
+
+int orc_apply(const double* centres, const double* quats, const double* A,
+              const double* C, int M, int p, double eta, int op,
+              const double* density, double* u_self, double* u_near,
+              double* u_far, double* u) {
+  if (op != OP_S && op != OP_D) return ORC_E_INVALID;
+  geometry g;
+  int rc = build_geometry(centres, quats, A, C, M, p, eta, &g);
+  if (rc) return rc;
+  int T = g.T, K = g.K, Kh = g.Kh;
+  size_t N = (size_t)g.N;
+  double* us = (double*)calloc(N, sizeof(double));
+  double* un = (double*)calloc(N, sizeof(double));
+  double* uf = (double*)calloc(N, sizeof(double));
+  double* cself = (double*)malloc(sizeof(double) * (size_t)M * K);
+  double* E = (double*)malloc(sizeof(double) * (size_t)M * K);
+  double complex* Qu0 = (double complex*)malloc(sizeof(double complex) * (size_t)M * Kh);
+
+  /* line 2 and lines 11-12: transform, diagonal spectra, inverse transform */
+  int err = 0;
+#pragma omp parallel for schedule(dynamic)
+  for (int i = 0; i < M; ++i) {
+    int r = particle_coefficients(&g, op, i, density, cself + (size_t)i * K,
+                                  E + (size_t)i * K, Qu0 + (size_t)i * Kh);
+    if (r) {
+#pragma omp atomic write
+      err = r;
+      continue;
+    }
+    inverse_transform(p, g.gx, cself + (size_t)i * K, us + (size_t)i * T);
+  }
+  if (err) rc = err;
+
+  /* lines 14-15: neighbours' exterior expansions at the target nodes */
+  if (!rc) {
+#pragma omp parallel for schedule(dynamic)
+    for (int j = 0; j < M; ++j) {
+      for (int i = 0; i < M; ++i) {
+        if (!g.near[(size_t)i * M + j]) continue;
+        for (int t = 0; t < T; ++t) {
+          size_t gt = (size_t)j * T + t;
+          double val;
+          int r = eval_exterior(&g.pt[i], p, E + (size_t)i * K, Qu0 + (size_t)i * Kh,
+                                g.xyz + 3 * gt, &val);
+          if (r) {
+#pragma omp atomic write
+            err = r;
+            continue;
+          }
+          un[gt] += val;
+        }
+      }
+    }
+    if (err) rc = err;
+  }
+
+  /* lines 6-8: smooth quadrature from far particles, Neumaier-compensated */
+  if (!rc) {
+#pragma omp parallel for schedule(dynamic)
+    for (int j = 0; j < M; ++j) {
+      for (int t = 0; t < T; ++t) {
+        size_t gt = (size_t)j * T + t;
+        const double* x = g.xyz + 3 * gt;
+        double sum = 0.0, comp = 0.0;
+        for (int i = 0; i < M; ++i) {
+          if (i == j || g.near[(size_t)i * M + j]) continue;
+          for (int q = 0; q < T; ++q) {
+            size_t gs = (size_t)i * T + q;
+            const double* y = g.xyz + 3 * gs;
+            double d0 = x[0] - y[0], d1 = x[1] - y[1], d2 = x[2] - y[2];
+            double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+            double r = sqrt(r2);
+            double term;
+            if (op == OP_S) {
+              term = g.W[gs] * density[gs] / (4.0 * PI * r);
+            } else {
+              const double* nu = g.nrm + 3 * gs;
+              double ndr = nu[0] * d0 + nu[1] * d1 + nu[2] * d2;
+              term = g.W[gs] * density[gs] * ndr / (4.0 * PI * r2 * r);
+            }
+            double tsum = sum + term;
+            if (fabs(sum) >= fabs(term)) comp += (sum - tsum) + term;
+            else comp += (term - tsum) + sum;
+            sum = tsum;
+          }
+        }
+        uf[gt] = sum + comp;
+      }
+    }
+  }
+
+  /* lines 18-19: sum of the three pieces */
+  if (!rc) {
+    for (size_t gi = 0; gi < N; ++gi) {
+      if (u_self) u_self[gi] = us[gi];
+      if (u_near) u_near[gi] = un[gi];
+      if (u_far) u_far[gi] = uf[gi];
+      u[gi] = us[gi] + un[gi] + uf[gi];
+    }
+  }
+  free(us); free(un); free(uf); free(cself); free(E); free(Qu0);
+  free_geometry(&g);
+  return rc;
+}
+
+/* Exterior evaluation of one particle's layer potential at arbitrary exterior
+   points from its nodal density (the analytic near-field formula), for the
+   pins: S or D exterior values of a single spheroid. */
+int orc_eval_exterior(const double* centre, const double* quat, double A,
+                      double C, int p, int op, const double* density,
+                      const double* pts, int npts, double* out) {
+  geometry g;
+  int rc = build_geometry(centre, quat, &A, &C, 1, p, 1.0, &g);
+  if (rc) return rc;
+  double* cself = (double*)malloc(sizeof(double) * g.K);
+  double* E = (double*)malloc(sizeof(double) * g.K);
+  double complex* Qu0 = (double complex*)malloc(sizeof(double complex) * g.Kh);
+  rc = particle_coefficients(&g, op, 0, density, cself, E, Qu0);
+  for (int t = 0; t < npts && !rc; ++t)
+    rc = eval_exterior(&g.pt[0], p, E, Qu0, pts + 3 * t, out + t);
+  free(cself); free(E); free(Qu0);
+  free_geometry(&g);
+  return rc;
+}
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  extern int omp_get_max_threads(void);
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

@@ -1,0 +1,168 @@
+/*
+ * sbie.h -- C ABI of the MI355X spheroidal boundary-integral operator library.
+ *
+ * The library applies the Laplace single-layer S[sigma] and double-layer D[mu]
+ * operators of Crowder, Li, Corona and Veerapaneni (arXiv 2506.20809) to a
+ * suspension of prolate and oblate spheroids, following the paper's problem
+ * setup (Section 4, "Problem setup": evaluation of u = sum_i K_i[sigma_i] at all
+ * particle nodes) and Algorithm 1 (self, near and far split).  Particles are
+ * given as the paper's numerical examples give them (Section 5.1): shape,
+ * centre and a unit quaternion rotating a reference configuration.
+ *
+ * Conventions (all arrays are plain C arrays, row-major, contiguous):
+ *  - Particle i: centre c_i (3 doubles), unit quaternion q_i = (w,x,y,z)
+ *    rotating body coordinates into lab coordinates, equatorial semi-axis A_i
+ *    and polar semi-axis C_i along the body z axis.  C > A is prolate, C < A
+ *    oblate (Section 2.1, Table 1).
+ *  - Order p, grid of (p+1) Gauss-Legendre nodes in v (ascending) times 2p+2
+ *    equispaced azimuthal nodes phi_k = 2 pi k / (2p+2) per particle, so
+ *    T = (p+1)(2p+2) nodes per particle and N = M*T nodes in all.  Node index
+ *    g = i*T + j*(2p+2) + k (particle, v index, phi index).
+ *  - Densities and potentials are [nrhs][N] doubles in node order.
+ *  - The double-layer value on the surface is the principal value (the average
+ *    of the one-sided spectra of Theorem 1); add +-mu/2 for the one-sided limits.
+ *  - eta is the near/far parameter of Section 4.1: target particle j is in the
+ *    near field of source i iff the surface distance d_ij < eta * diam_i, with
+ *    diam_i twice the largest semi-axis of particle i.
+ *
+ * Ownership: the caller owns every density and potential buffer, on the host or
+ * (flag SBIE_DEVICE_PTRS) on the device; the library never frees them.  Handles
+ * are released only by their destroy call.  Particle arrays are copied at
+ * create time.
+ *
+ * Errors: every entry point returns an sbie_status; nothing throws across the
+ * ABI.  sbie_last_error() returns a thread-local message for the last failure.
+ *
+ * Threads: one geometry must not be used by concurrent sbie_apply calls.
+ */
+#ifndef SBIE_H
+#define SBIE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SBIE_OK = 0,
+  SBIE_E_INVALID = -1,    /* bad argument (p out of [1,32], M < 1, non-unit quaternion, ...) */
+  SBIE_E_DEGENERATE = -2, /* |A - C| <= 1e-6 max(A,C) or a semi-axis <= 0 (no focal length) */
+  SBIE_E_OVERLAP = -3,    /* two particles touch or overlap (d_ij <= 0) */
+  SBIE_E_NOMEM = -4,      /* device or host allocation failed */
+  SBIE_E_BUDGET = -5,     /* a served session can never fit the memory budget */
+  SBIE_E_DEVICE = -6,     /* a HIP call failed; see sbie_last_error() */
+  SBIE_E_TIMEOUT = -7,    /* sbie_wait timed out */
+  SBIE_E_NUMERIC = -8,    /* continued fraction for Q_N/Q_{N-1} did not converge */
+  SBIE_E_STATE = -9       /* call not valid in the current state */
+} sbie_status;
+
+typedef enum {
+  SBIE_OP_S = 0,       /* Laplace single layer, Eq. (SLP), Theorem 2 */
+  SBIE_OP_D = 1,       /* Laplace double layer, Eq. (DLP), Theorem 1 */
+  SBIE_OP_STOKES_S = 2 /* Stokes single layer through Laplace potentials, Eq. (stokes); nrhs = 3 */
+} sbie_op;
+
+typedef enum {
+  SBIE_FP64 = 0, /* every part in double precision */
+  SBIE_MIXED = 1 /* far-field sums, transform and near contractions in FP32 (compensated
+                    tile accumulation); frame map and Q_n^m recurrence in FP64 */
+} sbie_precision;
+
+/* sbie_apply flags */
+#define SBIE_DEVICE_PTRS 0x1u  /* density/potential are device pointers */
+#define SBIE_TIMING 0x2u       /* record per-part device times (sbie_geom_last_timing) */
+#define SBIE_PARTS_SELF 0x10u  /* include the self interaction (Algorithm 1, lines 11-12) */
+#define SBIE_PARTS_NEAR 0x20u  /* include the near field (Algorithm 1, lines 14-15) */
+#define SBIE_PARTS_FAR 0x40u   /* include the far field (Algorithm 1, lines 6-8) */
+#define SBIE_PARTS_ALL 0x70u   /* 0 also means all parts */
+
+typedef struct sbie_ctx sbie_ctx;
+typedef struct sbie_geom sbie_geom;
+
+/* Per-part device times of the last timed apply, milliseconds (HIP events on
+   the apply's stream).  far_kernel_ms is the far-field direct-sum kernel alone. */
+typedef struct {
+  double prep_ms;
+  double transform_ms; /* forward transform, spectra scaling, inverse transform */
+  double near_ms;
+  double far_kernel_ms;
+  double assemble_ms;
+  double total_ms;
+  int64_t far_pairs;   /* far-field node pairs evaluated per right-hand side */
+  int64_t near_evals;  /* near-field (pair, target) evaluations per right-hand side */
+} sbie_timing;
+
+/* Create a context on HIP device `device` (a stream is created for synchronous
+   calls).  *out receives the handle. */
+sbie_status sbie_ctx_create(int device, sbie_ctx** out);
+void sbie_ctx_destroy(sbie_ctx* ctx);
+
+/* Build a geometry (Algorithm 1 setup: nodes, weights, normals, spectra of
+   Theorems 1-2, exact distances and the near/far split of Section 4.1).
+   centers [M][3], quats [M][4] (w,x,y,z), A [M], C [M] are host arrays.
+   Errors: SBIE_E_INVALID (M < 1, p outside [1,32], eta < 0, non-finite value,
+   | |q| - 1 | > 1e-6), SBIE_E_DEGENERATE, SBIE_E_OVERLAP, SBIE_E_NUMERIC,
+   SBIE_E_NOMEM, SBIE_E_DEVICE. */
+sbie_status sbie_geom_create(sbie_ctx* ctx, const double* centers, const double* quats,
+                             const double* A, const double* C, int32_t M, int32_t p,
+                             double eta, sbie_geom** out);
+void sbie_geom_destroy(sbie_geom* g);
+
+int64_t sbie_geom_num_nodes(const sbie_geom* g);      /* N = M (p+1)(2p+2) */
+int64_t sbie_geom_num_near_pairs(const sbie_geom* g); /* directed (source, target) pairs */
+uint64_t sbie_geom_footprint_bytes(const sbie_geom* g); /* device memory held by the geometry */
+
+/* Copy nodes [N][3], unit outward normals [N][3] and quadrature weights [N]
+   (Gauss-Legendre x trapezoid weights times the area element of Table 2) to
+   host arrays; any pointer may be NULL. */
+sbie_status sbie_geom_nodes(const sbie_geom* g, double* xyz, double* nrm, double* w);
+
+/* Directed near pairs (source i, target j), sorted by target then source;
+   at most cap are written, *count receives the total. */
+sbie_status sbie_geom_near_pairs(const sbie_geom* g, int32_t* src, int32_t* dst,
+                                 int64_t cap, int64_t* count);
+
+/* Apply S or D (or the Stokes single layer) to nrhs densities:
+   potential[r][g] = sum over particles of K[density[r]] at node g.
+   stream: a hipStream_t, or NULL for the context stream with the call
+   returning after completion.  With a non-NULL stream and SBIE_DEVICE_PTRS the
+   call is asynchronous on that stream.  flags: SBIE_DEVICE_PTRS, SBIE_TIMING,
+   SBIE_PARTS_*.  Errors: SBIE_E_INVALID (op, precision, nrhs outside [1,16],
+   Stokes with nrhs != 3), SBIE_E_NUMERIC, SBIE_E_DEVICE, SBIE_E_NOMEM. */
+sbie_status sbie_apply(sbie_geom* g, sbie_op op, sbie_precision prec, int32_t nrhs,
+                       const double* density, double* potential, void* stream,
+                       uint32_t flags);
+
+/* Wait for `stream` (NULL: the context stream) and return the sticky device
+   status of the applies made on this geometry since the last check:
+   SBIE_E_NUMERIC if a continued fraction did not converge, SBIE_E_OVERLAP if a
+   near-field target was found inside its source, else SBIE_OK.  Asynchronous
+   applies report their numerical failures here. */
+sbie_status sbie_geom_sync(sbie_geom* g, void* stream);
+
+/* Forward transform of Algorithm 1 (line 2) alone: the (p+1)^2 real
+   spheroidal-harmonic coefficients per particle, index n^2+n+m, of the
+   density (op = SBIE_OP_D) or of sqrt(u0^2 -+ v^2) times the density
+   (op = SBIE_OP_S, the modified basis of Section 3.2).  density [nrhs][N],
+   coefs [nrhs][M][(p+1)^2]; pointers as in sbie_apply (flag SBIE_DEVICE_PTRS). */
+sbie_status sbie_transform(sbie_geom* g, sbie_op op, int32_t nrhs, const double* density,
+                           double* coefs, void* stream, uint32_t flags);
+
+/* Copy the per-particle spectra to a host array [M][(p+1)(p+2)/2][4] indexed
+   by h = n(n+1)/2 + m (m >= 0): D principal value, D exterior limit (Theorem 1),
+   S on the surface in the modified basis (Theorem 2), and 1/Q_n^m(z0) (for
+   oblates the real function i^{n+1} Q_n^m(i u0)). */
+sbie_status sbie_geom_spectra(const sbie_geom* g, double* out);
+
+/* Times of the last apply made with SBIE_TIMING (waits for it to finish). */
+sbie_status sbie_geom_last_timing(sbie_geom* g, sbie_timing* out);
+
+const char* sbie_status_str(sbie_status s);
+const char* sbie_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SBIE_H */

@@ -58,6 +58,8 @@ def lib():
                                    ctypes.POINTER(ctypes.c_uint8)]
         L.orc_apply.argtypes = [dp, dp, dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                 dp, dp, dp, dp, dp]
+        L.orc_apply_at.argtypes = [dp, dp, dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                   dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int, dp, dp, dp, dp]
         L.orc_eval_exterior.argtypes = [dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                         dp, dp, ctypes.c_int, dp]
         L.orc_set_cf_max_iter.argtypes = [ctypes.c_int]
@@ -179,6 +181,20 @@ def apply(geom, p: int, op: int, density: np.ndarray, eta: float = 1.0, parts: b
     _check(lib().orc_apply(_p(c), _p(q), _p(A), _p(C), M, int(p), float(eta), int(op), _p(dens), _p(us),
                            _p(un), _p(uf), _p(u)), "apply")
     return (u, us, un, uf) if parts else u
+
+
+def apply_at(geom, p: int, op: int, density: np.ndarray, targets, eta: float = 1.0):
+    """Algorithm 1 at selected node indices: (u, u_self, u_near, u_far) at those nodes."""
+    c, q, A, C = _geom_arrays(geom)
+    M = len(A)
+    dens = _f64(density).reshape(-1)
+    tg = np.ascontiguousarray(targets, dtype=np.int64)
+    n = len(tg)
+    us, un, uf, u = (np.zeros(n) for _ in range(4))
+    _check(lib().orc_apply_at(_p(c), _p(q), _p(A), _p(C), M, int(p), float(eta), int(op), _p(dens),
+                              tg.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n, _p(us), _p(un), _p(uf),
+                              _p(u)), "apply_at")
+    return u, us, un, uf
 
 
 def eval_exterior(spheroid, p: int, op: int, density: np.ndarray, pts: np.ndarray) -> np.ndarray:

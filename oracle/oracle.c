@@ -810,6 +810,102 @@ int orc_apply(const double* centres, const double* quats, const double* A,
   return rc;
 }
 
+/* Algorithm 1 evaluated at a subset of nodes only (for checks at full size):
+   out_self/out_near/out_far/out[t] for node index targets[t].  The per-particle
+   transforms are computed only for the particles that the targets need. */
+int orc_apply_at(const double* centres, const double* quats, const double* A,
+                 const double* C, int M, int p, double eta, int op,
+                 const double* density, const int64_t* targets, int ntg,
+                 double* out_self, double* out_near, double* out_far, double* out) {
+  if (op != OP_S && op != OP_D) return ORC_E_INVALID;
+  geometry g;
+  int rc = build_geometry(centres, quats, A, C, M, p, eta, &g);
+  if (rc) return rc;
+  int T = g.T, K = g.K, Kh = g.Kh;
+  uint8_t* need = (uint8_t*)calloc(M, 1);
+  for (int t = 0; t < ntg; ++t) {
+    if (targets[t] < 0 || targets[t] >= (int64_t)g.N) { free(need); free_geometry(&g); return ORC_E_INVALID; }
+    int j = (int)(targets[t] / T);
+    need[j] = 1;
+    for (int i = 0; i < M; ++i) if (g.near[(size_t)i * M + j]) need[i] = 1;
+  }
+  double* cself = (double*)calloc((size_t)M * K, sizeof(double));
+  double* E = (double*)calloc((size_t)M * K, sizeof(double));
+  double complex* Qu0 = (double complex*)calloc((size_t)M * Kh, sizeof(double complex));
+  int err = 0;
+#pragma omp parallel for schedule(dynamic)
+  for (int i = 0; i < M; ++i) {
+    if (!need[i]) continue;
+    int r = particle_coefficients(&g, op, i, density, cself + (size_t)i * K,
+                                  E + (size_t)i * K, Qu0 + (size_t)i * Kh);
+    if (r) {
+#pragma omp atomic write
+      err = r;
+    }
+  }
+  if (err) rc = err;
+  double* Y = (double*)malloc(sizeof(double) * K);
+#pragma omp parallel for schedule(dynamic)
+  for (int t = 0; t < ntg; ++t) {
+    if (rc) continue;
+    int64_t gt = targets[t];
+    int j = (int)(gt / T), loc = (int)(gt - (int64_t)j * T);
+    int Nphi = 2 * p + 2;
+    int jv = loc / Nphi, kp = loc - jv * Nphi;
+    /* self: inverse transform of the diagonal coefficients at this node */
+    double* Yl = (double*)malloc(sizeof(double) * K);
+    real_harmonics(g.gx[jv], 2.0 * PI * kp / Nphi, p, Yl);
+    double us = 0.0;
+    for (int l = 0; l < K; ++l) us += cself[(size_t)j * K + l] * Yl[l];
+    free(Yl);
+    /* near */
+    double un = 0.0;
+    for (int i = 0; i < M; ++i) {
+      if (!g.near[(size_t)i * M + j]) continue;
+      double val;
+      int r = eval_exterior(&g.pt[i], p, E + (size_t)i * K, Qu0 + (size_t)i * Kh, g.xyz + 3 * gt, &val);
+      if (r) {
+#pragma omp atomic write
+        err = r;
+      }
+      un += val;
+    }
+    /* far, Neumaier-compensated */
+    const double* x = g.xyz + 3 * gt;
+    double sum = 0.0, comp = 0.0;
+    for (int i = 0; i < M; ++i) {
+      if (i == j || g.near[(size_t)i * M + j]) continue;
+      for (int q = 0; q < T; ++q) {
+        size_t gs = (size_t)i * T + q;
+        const double* y = g.xyz + 3 * gs;
+        double d0 = x[0] - y[0], d1 = x[1] - y[1], d2 = x[2] - y[2];
+        double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+        double r = sqrt(r2);
+        double term;
+        if (op == OP_S) {
+          term = g.W[gs] * density[gs] / (4.0 * PI * r);
+        } else {
+          const double* nu = g.nrm + 3 * gs;
+          term = g.W[gs] * density[gs] * (nu[0] * d0 + nu[1] * d1 + nu[2] * d2) / (4.0 * PI * r2 * r);
+        }
+        double ts = sum + term;
+        if (fabs(sum) >= fabs(term)) comp += (sum - ts) + term;
+        else comp += (term - ts) + sum;
+        sum = ts;
+      }
+    }
+    double uf = sum + comp;
+    if (out_self) out_self[t] = us;
+    if (out_near) out_near[t] = un;
+    if (out_far) out_far[t] = uf;
+    out[t] = us + un + uf;
+  }
+  if (err) rc = err;
+  free(Y); free(need); free(cself); free(E); free(Qu0);
+  free_geometry(&g);
+  return rc;
+}
+
 /* Exterior evaluation of one particle's layer potential at arbitrary exterior
    points from its nodal density (the analytic near-field formula), for the
    pins: S or D exterior values of a single spheroid. */

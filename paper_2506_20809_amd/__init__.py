@@ -1,0 +1,248 @@
+"""Python binding of the MI355X spheroidal boundary-integral library (libsbie.so).
+
+Argument marshalling only: every step of the operator apply runs in the HIP
+kernels behind the C ABI declared in include/sbie.h.  PyTorch provides device
+memory and streams.  There is no CPU fallback: importing the binding without a
+built library raises.
+"""
+from __future__ import annotations
+
+import atexit
+import ctypes
+import os
+import weakref
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsbie.so")
+
+SBIE_OP_S, SBIE_OP_D, SBIE_OP_STOKES_S = 0, 1, 2
+SBIE_FP64, SBIE_MIXED = 0, 1
+SBIE_DEVICE_PTRS = 0x1
+SBIE_TIMING = 0x2
+SBIE_PARTS_SELF, SBIE_PARTS_NEAR, SBIE_PARTS_FAR, SBIE_PARTS_ALL = 0x10, 0x20, 0x40, 0x70
+
+STATUS = {0: "SBIE_OK", -1: "SBIE_E_INVALID", -2: "SBIE_E_DEGENERATE", -3: "SBIE_E_OVERLAP", -4: "SBIE_E_NOMEM",
+          -5: "SBIE_E_BUDGET", -6: "SBIE_E_DEVICE", -7: "SBIE_E_TIMEOUT", -8: "SBIE_E_NUMERIC", -9: "SBIE_E_STATE"}
+
+# symbols declared in include/sbie.h
+EXPORTS = [
+    "sbie_ctx_create", "sbie_ctx_destroy", "sbie_geom_create", "sbie_geom_destroy", "sbie_geom_num_nodes",
+    "sbie_geom_num_near_pairs", "sbie_geom_footprint_bytes", "sbie_geom_nodes", "sbie_geom_near_pairs",
+    "sbie_apply", "sbie_geom_sync", "sbie_transform", "sbie_geom_spectra", "sbie_geom_last_timing",
+    "sbie_status_str", "sbie_last_error",
+]
+
+
+class SbieError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("prep_ms", ctypes.c_double), ("transform_ms", ctypes.c_double), ("near_ms", ctypes.c_double),
+                ("far_kernel_ms", ctypes.c_double), ("assemble_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
+                ("far_pairs", ctypes.c_int64), ("near_evals", ctypes.c_int64)]
+
+
+_lib = None
+_live = []
+
+
+def _close_all():
+    for ref in reversed(_live):
+        obj = ref()
+        if obj is not None:
+            try:
+                obj.close()
+            except Exception:
+                pass
+    _live.clear()
+
+
+atexit.register(_close_all)
+
+
+def lib() -> ctypes.CDLL:
+    """Load libsbie.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2506_20809_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+        L.sbie_ctx_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp)]
+        L.sbie_ctx_destroy.argtypes = [vp]
+        L.sbie_ctx_destroy.restype = None
+        L.sbie_geom_create.argtypes = [vp, dp, dp, dp, dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                       ctypes.POINTER(vp)]
+        L.sbie_geom_destroy.argtypes = [vp]
+        L.sbie_geom_destroy.restype = None
+        L.sbie_geom_num_nodes.argtypes = [vp]
+        L.sbie_geom_num_nodes.restype = ctypes.c_int64
+        L.sbie_geom_num_near_pairs.argtypes = [vp]
+        L.sbie_geom_num_near_pairs.restype = ctypes.c_int64
+        L.sbie_geom_footprint_bytes.argtypes = [vp]
+        L.sbie_geom_footprint_bytes.restype = ctypes.c_uint64
+        L.sbie_geom_nodes.argtypes = [vp, dp, dp, dp]
+        ip = ctypes.POINTER(ctypes.c_int32)
+        L.sbie_geom_near_pairs.argtypes = [vp, ip, ip, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+        L.sbie_apply.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int32, vp, vp, vp, ctypes.c_uint32]
+        L.sbie_geom_sync.argtypes = [vp, vp]
+        L.sbie_transform.argtypes = [vp, ctypes.c_int, ctypes.c_int32, vp, vp, vp, ctypes.c_uint32]
+        L.sbie_geom_spectra.argtypes = [vp, dp]
+        L.sbie_geom_last_timing.argtypes = [vp, ctypes.POINTER(Timing)]
+        L.sbie_status_str.argtypes = [ctypes.c_int]
+        L.sbie_status_str.restype = ctypes.c_char_p
+        L.sbie_last_error.argtypes = []
+        L.sbie_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise SbieError(rc, lib().sbie_last_error().decode())
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Context:
+    """sbie_ctx: one HIP device and its stream."""
+
+    def __init__(self, device: int = 0):
+        self._h = ctypes.c_void_p()
+        _check(lib().sbie_ctx_create(int(device), ctypes.byref(self._h)))
+        _live.append(weakref.ref(self))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib().sbie_ctx_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Geometry:
+    """sbie_geom: a suspension at order p with its near/far split (eta)."""
+
+    def __init__(self, ctx: Context, geom: dict, p: int, eta: float = 1.0):
+        self.ctx = ctx
+        c = np.ascontiguousarray(geom["centers"], dtype=np.float64)
+        q = np.ascontiguousarray(geom["quats"], dtype=np.float64)
+        A = np.ascontiguousarray(geom["A"], dtype=np.float64)
+        C = np.ascontiguousarray(geom["C"], dtype=np.float64)
+        self.M = int(len(A))
+        self.p = int(p)
+        self._h = ctypes.c_void_p()
+        _check(lib().sbie_geom_create(ctx.handle, _dp(c), _dp(q), _dp(A), _dp(C), self.M, self.p, float(eta),
+                                      ctypes.byref(self._h)))
+        self.N = int(lib().sbie_geom_num_nodes(self._h))
+        _live.append(weakref.ref(self))
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def num_near_pairs(self) -> int:
+        return int(lib().sbie_geom_num_near_pairs(self._h))
+
+    @property
+    def footprint_bytes(self) -> int:
+        return int(lib().sbie_geom_footprint_bytes(self._h))
+
+    def nodes(self):
+        xyz = np.zeros((self.N, 3))
+        nrm = np.zeros((self.N, 3))
+        w = np.zeros(self.N)
+        _check(lib().sbie_geom_nodes(self._h, _dp(xyz), _dp(nrm), _dp(w)))
+        return xyz, nrm, w
+
+    def near_pairs(self):
+        cnt = ctypes.c_int64()
+        _check(lib().sbie_geom_near_pairs(self._h, None, None, 0, ctypes.byref(cnt)))
+        src = np.zeros(cnt.value, dtype=np.int32)
+        dst = np.zeros(cnt.value, dtype=np.int32)
+        ip = ctypes.POINTER(ctypes.c_int32)
+        _check(lib().sbie_geom_near_pairs(self._h, src.ctypes.data_as(ip), dst.ctypes.data_as(ip), cnt.value,
+                                          ctypes.byref(cnt)))
+        return src, dst
+
+    def apply(self, op: int, density, precision: int = SBIE_FP64, parts: int = SBIE_PARTS_ALL, out=None,
+              stream=None, timing: bool = False):
+        """Apply S or D.  density: torch CUDA float64 tensor [nrhs, N] or [N] (device
+        pointers, on the current stream), or a numpy array (host pointers, synchronous)."""
+        flags = int(parts) | (SBIE_TIMING if timing else 0)
+        if isinstance(density, np.ndarray):
+            d = np.ascontiguousarray(density, dtype=np.float64)
+            nrhs = 1 if d.ndim == 1 else d.shape[0]
+            o = np.zeros_like(d)
+            _check(lib().sbie_apply(self._h, int(op), int(precision), nrhs, d.ctypes.data, o.ctypes.data, None,
+                                    flags))
+            return o
+        import torch
+
+        if not (density.is_cuda and density.dtype == torch.float64 and density.is_contiguous()):
+            raise ValueError("density must be a contiguous float64 CUDA tensor")
+        nrhs = 1 if density.dim() == 1 else density.shape[0]
+        if density.numel() != nrhs * self.N:
+            raise ValueError(f"density has {density.numel()} entries, expected {nrhs} x {self.N}")
+        if out is None:
+            out = torch.empty_like(density)
+        if stream is None:
+            stream = torch.cuda.current_stream(density.device)
+        _check(lib().sbie_apply(self._h, int(op), int(precision), nrhs, density.data_ptr(), out.data_ptr(),
+                                ctypes.c_void_p(stream.cuda_stream), flags | SBIE_DEVICE_PTRS))
+        return out
+
+    def transform(self, op: int, density: np.ndarray) -> np.ndarray:
+        """Forward transform (host arrays): coefficients [nrhs][M][(p+1)^2]."""
+        d = np.ascontiguousarray(density, dtype=np.float64)
+        nrhs = 1 if d.ndim == 1 else d.shape[0]
+        out = np.zeros((nrhs, self.M, (self.p + 1) ** 2))
+        _check(lib().sbie_transform(self._h, int(op), nrhs, d.ctypes.data, out.ctypes.data, None, 0))
+        return out
+
+    def spectra(self) -> np.ndarray:
+        """Per-particle spectra [M][(p+1)(p+2)/2][4]."""
+        out = np.zeros((self.M, (self.p + 1) * (self.p + 2) // 2, 4))
+        _check(lib().sbie_geom_spectra(self._h, _dp(out)))
+        return out
+
+    def sync(self, stream=None):
+        """Wait for the stream (torch stream or None for the current one) and raise on a
+        numerical failure recorded by the kernels since the last check."""
+        import torch
+
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        _check(lib().sbie_geom_sync(self._h, ctypes.c_void_p(stream.cuda_stream)))
+
+    def last_timing(self) -> Timing:
+        t = Timing()
+        _check(lib().sbie_geom_last_timing(self._h, ctypes.byref(t)))
+        return t
+
+    def close(self):
+        if self._h:
+            lib().sbie_geom_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,493 @@
+// The operator apply of Algorithm 1 (and its single-layer variant): forward
+// transform, diagonal self interaction with inverse transform, near-field
+// exterior expansions, far-field direct sum, assembly.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "sbie_internal.h"
+
+namespace sbie {
+
+namespace {
+
+constexpr int kCfMaxIter = 10000;
+constexpr double kInv4Pi = 0.079577471545947667884441881686257181;
+
+using d4 = double __attribute__((ext_vector_type(4)));
+using f4 = float __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------- prep
+
+// Transform input and far-field source records.
+//  S: f = sqrt(u0^2 -+ v^2) sigma (modified basis, Section 3.2), record (x, y, z, W sigma)
+//  D: f = mu, record (x, y, z, W mu nu)
+template <int OP>
+__global__ void k_prep_f64(const double* __restrict__ dens, const double* __restrict__ x,
+                           const double* __restrict__ y, const double* __restrict__ z,
+                           const double* __restrict__ nx, const double* __restrict__ ny,
+                           const double* __restrict__ nz, const double* __restrict__ w,
+                           const double* __restrict__ wS, int p, int64_t N, double* f, double* src) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  const int Nphi = 2 * p + 2, T = (p + 1) * Nphi;
+  const double d = dens[g];
+  const double q = w[g] * d;
+  if (OP == SBIE_OP_S) {
+    const int i = (int)(g / T), j = (int)((g - (int64_t)i * T) / Nphi);
+    f[g] = wS[(size_t)i * (p + 1) + j] * d;
+    double* r = src + 4 * g;
+    r[0] = x[g];
+    r[1] = y[g];
+    r[2] = z[g];
+    r[3] = q;
+  } else {
+    f[g] = d;
+    double* r = src + 8 * g;
+    r[0] = x[g];
+    r[1] = y[g];
+    r[2] = z[g];
+    r[3] = q * nx[g];
+    r[4] = q * ny[g];
+    r[5] = q * nz[g];
+    r[6] = 0.0;
+    r[7] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------- transforms (MFMA f64)
+
+// C[rows x cols] = A[rows x kd] * B[kd x cols], row-major.  A workgroup of four
+// waves computes a 64 x 64 tile; each wave a 16 x 64 strip as four 16 x 16
+// v_mfma_f64_16x16x4f64 accumulators.  Operand layout of the 16x16x4 f64 MFMA
+// (measured on gfx950): lane l supplies A[l%16][l/16] and B[l/16][l%16];
+// accumulator element r of lane l is C[l/16 + 4*r][l%16].
+__global__ __launch_bounds__(256) void k_gemm_f64(const double* __restrict__ A, int lda,
+                                                  const double* __restrict__ B, int ldb,
+                                                  double* __restrict__ C, int ldc, int rows,
+                                                  int cols, int kd) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row0 = blockIdx.y * 64 + wave * 16;
+  const int col0 = blockIdx.x * 64;
+  const int li = lane & 15, lk = lane >> 4;
+  d4 acc[4];
+  for (int b = 0; b < 4; ++b) acc[b] = d4{0.0, 0.0, 0.0, 0.0};
+  const int r = row0 + li;
+  for (int k0 = 0; k0 < kd; k0 += 4) {
+    const int k = k0 + lk;
+    const double av = (r < rows && k < kd) ? A[(size_t)r * lda + k] : 0.0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int c = col0 + 16 * b + li;
+      const double bv = (c < cols && k < kd) ? B[(size_t)k * ldb + c] : 0.0;
+      acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[b], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int c = col0 + 16 * b + li;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int rr = row0 + lk + 4 * e;
+      if (rr < rows && c < cols) C[(size_t)rr * ldc + c] = acc[b][e];
+    }
+  }
+}
+
+// Diagonal spectra: self coefficients and exterior coefficients per particle.
+__global__ void k_scale_coef(const double* __restrict__ coef, const double* __restrict__ lam, int M,
+                             int p, int op, double* cself, double* E) {
+  const int K = (p + 1) * (p + 1), Kh = (p + 1) * (p + 2) / 2;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)M * K) return;
+  const int i = (int)(t / K), l = (int)(t - (int64_t)i * K);
+  const int n = (int)sqrt((double)l);
+  const int m = l - n * n - n;
+  const int h = n * (n + 1) / 2 + (m < 0 ? -m : m);
+  const double* L = lam + ((size_t)i * Kh + h) * 4;
+  const double c = coef[t];
+  if (op == SBIE_OP_S) {
+    cself[t] = L[2] * c;
+    E[t] = L[2] * c;
+  } else {
+    cself[t] = L[0] * c;
+    E[t] = L[1] * c;
+  }
+}
+
+// ---------------------------------------------------------------- near field
+
+// One wave per (target particle, 64 target nodes).  Each lane maps its target
+// into the frame of every near source i (ascending i), finds (u, v, phi) from
+// the focal distances, runs the off-cut Legendre algorithm of Section 2.3 for
+// every order m in FP64, and sums E_l Q_n^|m|(u)/Q_n^|m|(u0) Y_l(v, phi).
+template <int PMAX>
+__global__ __launch_bounds__(64) void k_near_f64(
+    const Particle* __restrict__ part, const double* __restrict__ x, const double* __restrict__ y,
+    const double* __restrict__ z, const int32_t* __restrict__ near_ptr,
+    const int32_t* __restrict__ near_src, const double* __restrict__ E,
+    const double* __restrict__ lam, const double* __restrict__ ab, int p, int T, int chunks,
+    unsigned* status, double* __restrict__ unear) {
+  const int j = blockIdx.x / chunks;
+  const int t = (blockIdx.x - j * chunks) * 64 + threadIdx.x;
+  const bool live = t < T;
+  const int64_t g = (int64_t)j * T + (live ? t : 0);
+  const double X0 = x[g], X1 = y[g], X2 = z[g];
+  const int K = (p + 1) * (p + 1), Kh = (p + 1) * (p + 2) / 2, N = p + 1;
+  double acc = 0.0;
+  unsigned bad = 0u;
+  const int s_begin = near_ptr[j], s_end = near_ptr[j + 1];
+  for (int s = s_begin; s < s_end; ++s) {
+    const int i = near_src[s];
+    const Particle P = part[i];
+    const double* Ei = E + (size_t)i * K;
+    const double* Li = lam + (size_t)i * Kh * 4;
+    // lab -> body frame of the source
+    const double d0 = X0 - P.c[0], d1 = X1 - P.c[1], d2 = X2 - P.c[2];
+    const double b0 = P.R[0] * d0 + P.R[3] * d1 + P.R[6] * d2;
+    const double b1 = P.R[1] * d0 + P.R[4] * d1 + P.R[7] * d2;
+    const double b2 = P.R[2] * d0 + P.R[5] * d1 + P.R[8] * d2;
+    const double rho = sqrt(b0 * b0 + b1 * b1);
+    const double a = P.a;
+    // sum of the distances to the focal points (prolate) or to the focal ring
+    // (oblate) is 2 a cosh(mu): u = cosh(mu) resp. u = sinh(mu)
+    double u, w;
+    if (!P.oblate) {
+      const double f1 = sqrt(rho * rho + (b2 - a) * (b2 - a));
+      const double f2 = sqrt(rho * rho + (b2 + a) * (b2 + a));
+      const double ch = (f1 + f2) / (2.0 * a);
+      u = ch;
+      w = (ch - 1.0) * (ch + 1.0);
+    } else {
+      const double f1 = sqrt((rho + a) * (rho + a) + b2 * b2);
+      const double f2 = sqrt((rho - a) * (rho - a) + b2 * b2);
+      const double ch = (f1 + f2) / (2.0 * a);
+      u = sqrt((ch - 1.0) * (ch + 1.0));
+      w = ch * ch;
+    }
+    if (!(u > P.u0)) bad |= kStatExterior;
+    const double sw = sqrt(w);
+    const double v = b2 / (a * u);
+    const double sv = rho / (a * sw);  // sqrt(1 - v^2)
+    const double c1 = rho > 0.0 ? b0 / rho : 1.0, s1 = rho > 0.0 ? b1 / rho : 0.0;
+
+    double pmm_u = 1.0;                        // P_m^m(u) (real form)
+    double pbar = 0.28209479177387814347;      // normalised Ferrers Pb_m^m(v), 1/sqrt(4 pi) at m = 0
+    double cm = 1.0, sm = 0.0;                 // cos(m phi), sin(m phi)
+    double cas = 1.0 / (double)N;              // (-1)^m (N+m-1)!/(N-m)!
+    const double sgn = P.oblate ? 1.0 : -1.0;
+    for (int m = 0; m <= p; ++m) {
+      if (m > 0) {
+        pmm_u *= (double)(2 * m - 1) * sw;
+        pbar *= sqrt((2.0 * m + 1.0) / (2.0 * m)) * sv;
+        const double cn = cm * c1 - sm * s1;
+        sm = sm * c1 + cm * s1;
+        cm = cn;
+        cas = -cas * (double)(N + m - 1) * (double)(N - m + 1);
+      }
+      // forward recurrence for P_n^m(u) up to N (two registers)
+      double pa = pmm_u, pb = (double)(2 * m + 1) * u * pmm_u;  // P_m, P_{m+1}
+      for (int n = m + 1; n < N; ++n) {
+        const double pc = ((double)(2 * n + 1) * u * pb + sgn * (double)(n + m) * pa) / (double)(n - m + 1);
+        pa = pb;
+        pb = pc;
+      }
+      // now pa = P_{N-1}, pb = P_N (m <= p = N-1 so N >= m+1)
+      // continued fraction for H_N (modified Lentz)
+      double H;
+      {
+        const double tiny = 1e-300;
+        double f = tiny, Cc = tiny, Dd = 0.0;
+        bool conv = false;
+        for (int it = 0, k = N; it < kCfMaxIter; ++it, ++k) {
+          const double inv = 1.0 / (double)(k - m + 1);
+          const double ak = sgn * (double)(k + m) * inv;
+          const double bk = sgn * (double)(2 * k + 1) * u * inv;
+          Dd = fma(ak, Dd, bk);
+          if (Dd == 0.0) Dd = tiny;
+          Dd = 1.0 / Dd;
+          Cc = bk + ak / Cc;
+          if (Cc == 0.0) Cc = tiny;
+          const double delta = Cc * Dd;
+          f *= delta;
+          if (fabs(delta - 1.0) <= 2.3e-16) {
+            conv = true;
+            break;
+          }
+        }
+        if (!conv) bad |= kStatNumeric;
+        H = f;
+      }
+      const double den = P.oblate ? fma(H, pa, pb) : fma(-H, pa, pb);
+      const double QN1 = cas / den;
+      const double QN = H * QN1;
+      // backward recurrence into Q[n], indexed by degree (static indices)
+      double Q[PMAX + 4];
+#pragma unroll
+      for (int n = PMAX + 1; n >= 0; --n) {
+        if (n == N) {
+          Q[n] = QN;
+        } else if (n == N - 1) {
+          Q[n] = QN1;
+        } else if (n < N - 1 && n >= m) {
+          // Q_n from Q_{n+1}, Q_{n+2} (recurrence at degree n+1)
+          const double num = P.oblate
+              ? (double)(n - m + 2) * Q[n + 2] + (double)(2 * n + 3) * u * Q[n + 1]
+              : (double)(2 * n + 3) * u * Q[n + 1] - (double)(n - m + 2) * Q[n + 2];
+          Q[n] = num / (double)(n + m + 1);
+        } else {
+          Q[n] = 0.0;
+        }
+      }
+      // contraction with the normalised Ferrers functions, forward in n
+      double sc = 0.0, ss = 0.0;
+      double p2 = 0.0, p1 = pbar;
+#pragma unroll
+      for (int n = 0; n <= PMAX; ++n) {
+        if (n >= m && n <= p) {
+          double pn;
+          if (n == m) {
+            pn = pbar;
+          } else if (n == m + 1) {
+            pn = sqrt(2.0 * m + 3.0) * v * pbar;
+            p2 = p1;
+            p1 = pn;
+          } else {
+            const int h = n * (n + 1) / 2 + m;
+            pn = ab[2 * h] * (v * p1 - ab[2 * h + 1] * p2);
+            p2 = p1;
+            p1 = pn;
+          }
+          const double qr = Q[n] * Li[(n * (n + 1) / 2 + m) * 4 + 3];
+          const double t0 = pn * qr;
+          sc = fma(Ei[n * n + n + m], t0, sc);
+          if (m > 0) ss = fma(Ei[n * n + n - m], t0, ss);
+        }
+      }
+      if (m == 0)
+        acc += sc;
+      else
+        acc += 1.41421356237309504880 * (sc * cm + ss * sm);
+    }
+  }
+  if (bad) atomicOr(status, bad);
+  if (live) unear[g] = acc;
+}
+
+// ---------------------------------------------------------------- far field (FP64)
+
+__device__ inline double rsqrt_f64(double r2) {
+  double yv = __builtin_amdgcn_rsq(r2);
+  const double h = r2 * yv;
+  const double e = fma(-h, yv, 1.0);
+  yv = fma(0.5 * yv, e, yv);
+  const double h2 = r2 * yv;
+  const double e2 = fma(-h2, yv, 1.0);
+  return fma(0.5 * yv, e2, yv);
+}
+
+// Direct far-field sum.  The grid is (target tiles) x (source splits) with the
+// split as the fastest index, so consecutive workgroups -- which the hardware
+// spreads round-robin over the eight XCDs -- take different source ranges and
+// each XCD's L2 holds one slice of the sources.  A workgroup of 256 lanes owns
+// 256*TPT targets; every source particle of its split is skipped per target
+// when it is the target's own particle or in its near field (exclusion mask).
+// Source records are read with wave-uniform addresses (scalar loads); each
+// source particle's contribution is summed on its own before it is added.
+template <int OP, int TPT>
+__global__ __launch_bounds__(256) void k_far_f64(
+    const double* __restrict__ src, const double* __restrict__ x, const double* __restrict__ y,
+    const double* __restrict__ z, const uint32_t* __restrict__ excl, int words, int M, int T,
+    int64_t N, int nsplit, double* __restrict__ partial) {
+  const int split = blockIdx.x % nsplit;
+  const int tile = blockIdx.x / nsplit;
+  const int s0 = (int)((int64_t)M * split / nsplit), s1 = (int)((int64_t)M * (split + 1) / nsplit);
+  double tx[TPT], ty[TPT], tz[TPT], acc[TPT];
+  int tp[TPT];
+  bool live[TPT];
+#pragma unroll
+  for (int k = 0; k < TPT; ++k) {
+    const int64_t g = (int64_t)tile * 256 * TPT + k * 256 + threadIdx.x;
+    live[k] = g < N;
+    const int64_t gg = live[k] ? g : 0;
+    tx[k] = x[gg];
+    ty[k] = y[gg];
+    tz[k] = z[gg];
+    tp[k] = (int)(gg / T);
+    acc[k] = 0.0;
+  }
+  constexpr int SW = (OP == SBIE_OP_S) ? 4 : 8;
+  for (int s = s0; s < s1; ++s) {
+    bool need[TPT];
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < TPT; ++k) {
+      need[k] = live[k] && !((excl[(size_t)tp[k] * words + (s >> 5)] >> (s & 31)) & 1u);
+      any |= need[k];
+    }
+    if (!__any(any)) continue;
+    double tmp[TPT];
+#pragma unroll
+    for (int k = 0; k < TPT; ++k) tmp[k] = 0.0;
+    const double* rs = src + (size_t)s * T * SW;
+    for (int q = 0; q < T; ++q) {
+      const double* r = rs + (size_t)q * SW;
+      const double sx = r[0], sy = r[1], sz = r[2];
+      if (OP == SBIE_OP_S) {
+        const double sq = r[3];
+#pragma unroll
+        for (int k = 0; k < TPT; ++k) {
+          const double dx = tx[k] - sx, dy = ty[k] - sy, dz = tz[k] - sz;
+          const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+          tmp[k] = fma(sq, rsqrt_f64(r2), tmp[k]);
+        }
+      } else {
+        const double qx = r[3], qy = r[4], qz = r[5];
+#pragma unroll
+        for (int k = 0; k < TPT; ++k) {
+          const double dx = tx[k] - sx, dy = ty[k] - sy, dz = tz[k] - sz;
+          const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+          const double ri = rsqrt_f64(r2);
+          const double ri3 = ri * ri * ri;
+          const double dot = fma(qz, dz, fma(qy, dy, qx * dx));
+          tmp[k] = fma(dot, ri3, tmp[k]);
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < TPT; ++k) acc[k] += need[k] ? tmp[k] : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < TPT; ++k) {
+    const int64_t g = (int64_t)tile * 256 * TPT + k * 256 + threadIdx.x;
+    if (live[k]) partial[(size_t)split * N + g] = acc[k] * kInv4Pi;
+  }
+}
+
+// ---------------------------------------------------------------- assembly
+
+// u = u_self + u_near + sum over source splits of the far field, in this order.
+__global__ void k_assemble_f64(const double* __restrict__ uself, const double* __restrict__ unear,
+                               const double* __restrict__ partial, int nsplit, int64_t N,
+                               uint32_t parts, double* __restrict__ out) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  double u = 0.0;
+  if (parts & SBIE_PARTS_SELF) u += uself[g];
+  if (parts & SBIE_PARTS_NEAR) u += unear[g];
+  if (parts & SBIE_PARTS_FAR) {
+    double f = 0.0;
+    for (int s = 0; s < nsplit; ++s) f += partial[(size_t)s * N + g];
+    u += f;
+  }
+  out[g] = u;
+}
+
+inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+sbie_status launch_gemm(const double* A, int lda, const double* B, int ldb, double* C, int ldc, int rows,
+                        int cols, int kd, hipStream_t s) {
+  hipLaunchKernelGGL(k_gemm_f64, dim3(cdiv(cols, 64), cdiv(rows, 64)), dim3(256), 0, s, A, lda, B, ldb, C, ldc,
+                     rows, cols, kd);
+  SBIE_HIP(hipGetLastError());
+  return SBIE_OK;
+}
+
+template <int PMAX>
+void launch_near(sbie_geom* g, hipStream_t s) {
+  const int chunks = (g->T + 63) / 64;
+  hipLaunchKernelGGL(k_near_f64<PMAX>, dim3(g->M * chunks), dim3(64), 0, s, g->d_part, g->d_x, g->d_y, g->d_z,
+                     g->d_near_ptr, g->d_near_src, g->d_E, g->d_lam, g->d_ab, g->p, g->T, chunks, g->d_status,
+                     g->d_unear);
+}
+
+}  // namespace
+
+sbie_status apply_laplace(sbie_geom* g, int op, int prec, const double* d_dens, double* d_out, hipStream_t s,
+                          uint32_t parts, bool timed) {
+  (void)prec;
+  const int M = g->M, p = g->p, T = g->T, K = g->K;
+  const int64_t N = g->N;
+  const int B = 256;
+  Timing& tm = g->timing;
+  if (timed) {
+    for (int e = 0; e < 6; ++e)
+      if (!tm.ev[e]) SBIE_HIP(hipEventCreate(&tm.ev[e]));
+    SBIE_HIP(hipEventRecord(tm.ev[0], s));
+  }
+  // prep: transform input and far-field source records
+  if (op == SBIE_OP_S)
+    hipLaunchKernelGGL(k_prep_f64<SBIE_OP_S>, dim3(cdiv(N, B)), dim3(B), 0, s, d_dens, g->d_x, g->d_y, g->d_z,
+                       g->d_nx, g->d_ny, g->d_nz, g->d_w, g->d_wS, p, N, g->d_f, g->d_src);
+  else
+    hipLaunchKernelGGL(k_prep_f64<SBIE_OP_D>, dim3(cdiv(N, B)), dim3(B), 0, s, d_dens, g->d_x, g->d_y, g->d_z,
+                       g->d_nx, g->d_ny, g->d_nz, g->d_w, g->d_wS, p, N, g->d_f, g->d_src);
+  SBIE_HIP(hipGetLastError());
+  if (timed) SBIE_HIP(hipEventRecord(tm.ev[1], s));
+  // part (a) forward transform, part (b) spectra and inverse transform
+  if (parts & (SBIE_PARTS_SELF | SBIE_PARTS_NEAR)) {
+    sbie_status st = launch_gemm(g->d_f, T, g->d_An, K, g->d_coef, K, M, K, T, s);
+    if (st) return st;
+    hipLaunchKernelGGL(k_scale_coef, dim3(cdiv((int64_t)M * K, B)), dim3(B), 0, s, g->d_coef, g->d_lam, M, p, op,
+                       g->d_cself, g->d_E);
+    SBIE_HIP(hipGetLastError());
+    if (parts & SBIE_PARTS_SELF) {
+      st = launch_gemm(g->d_cself, K, g->d_Sy, T, g->d_uself, T, M, T, K, s);
+      if (st) return st;
+    }
+  }
+  if (timed) SBIE_HIP(hipEventRecord(tm.ev[2], s));
+  // part (c) near field
+  if ((parts & SBIE_PARTS_NEAR) && g->n_near > 0) {
+    if (p <= 8)
+      launch_near<8>(g, s);
+    else if (p <= 16)
+      launch_near<16>(g, s);
+    else
+      launch_near<32>(g, s);
+    SBIE_HIP(hipGetLastError());
+  } else if (parts & SBIE_PARTS_NEAR) {
+    SBIE_HIP(hipMemsetAsync(g->d_unear, 0, sizeof(double) * N, s));
+  }
+  if (timed) SBIE_HIP(hipEventRecord(tm.ev[3], s));
+  // part (d) far field
+  if (parts & SBIE_PARTS_FAR) {
+    constexpr int TPT = 2;
+    const unsigned tiles = cdiv(N, 256 * TPT);
+    if (op == SBIE_OP_S)
+      hipLaunchKernelGGL((k_far_f64<SBIE_OP_S, TPT>), dim3(tiles * g->nsplit), dim3(256), 0, s, g->d_src, g->d_x,
+                         g->d_y, g->d_z, g->d_excl, g->excl_words, M, T, N, g->nsplit, g->d_partial);
+    else
+      hipLaunchKernelGGL((k_far_f64<SBIE_OP_D, TPT>), dim3(tiles * g->nsplit), dim3(256), 0, s, g->d_src, g->d_x,
+                         g->d_y, g->d_z, g->d_excl, g->excl_words, M, T, N, g->nsplit, g->d_partial);
+    SBIE_HIP(hipGetLastError());
+  }
+  if (timed) SBIE_HIP(hipEventRecord(tm.ev[4], s));
+  hipLaunchKernelGGL(k_assemble_f64, dim3(cdiv(N, B)), dim3(B), 0, s, g->d_uself, g->d_unear, g->d_partial,
+                     g->nsplit, N, parts, d_out);
+  SBIE_HIP(hipGetLastError());
+  if (timed) {
+    SBIE_HIP(hipEventRecord(tm.ev[5], s));
+    tm.valid = true;
+  }
+  return SBIE_OK;
+}
+
+}  // namespace sbie
+
+namespace sbie {
+
+sbie_status transform_only(sbie_geom* g, int op, const double* d_dens, double* d_coef, hipStream_t s) {
+  const int64_t N = g->N;
+  const int B = 256;
+  if (op == SBIE_OP_S)
+    hipLaunchKernelGGL(k_prep_f64<SBIE_OP_S>, dim3(cdiv(N, B)), dim3(B), 0, s, d_dens, g->d_x, g->d_y, g->d_z,
+                       g->d_nx, g->d_ny, g->d_nz, g->d_w, g->d_wS, g->p, N, g->d_f, g->d_src);
+  else
+    hipLaunchKernelGGL(k_prep_f64<SBIE_OP_D>, dim3(cdiv(N, B)), dim3(B), 0, s, d_dens, g->d_x, g->d_y, g->d_z,
+                       g->d_nx, g->d_ny, g->d_nz, g->d_w, g->d_wS, g->p, N, g->d_f, g->d_src);
+  SBIE_HIP(hipGetLastError());
+  return launch_gemm(g->d_f, g->T, g->d_An, g->K, d_coef, g->K, g->M, g->K, g->T, s);
+}
+
+}  // namespace sbie

@@ -1,0 +1,121 @@
+// Internal declarations of the HIP library behind include/sbie.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sbie.h"
+
+namespace sbie {
+
+constexpr int kMaxP = 32;
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+// Per-particle parameters on the device (Section 2.1, Table 1).
+struct Particle {
+  double c[3];   // centre
+  double R[9];   // body -> lab rotation, row-major
+  double a;      // focal parameter
+  double u0;     // coordinate of the surface
+  double A, C;   // semi-axes
+  double diam;   // twice the largest semi-axis
+  double w0;     // u0^2 - 1 (prolate) or u0^2 + 1 (oblate)
+  int oblate;
+  int pad;
+};
+
+// Status word written by kernels (bit flags).
+enum : unsigned { kStatNumeric = 1u, kStatOverlap = 2u, kStatExterior = 4u };
+
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct Timing {
+  hipEvent_t ev[8] = {};
+  bool valid = false;
+};
+
+}  // namespace sbie
+
+struct sbie_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+};
+
+struct sbie_geom {
+  sbie_ctx* ctx = nullptr;
+  int M = 0, p = 0, T = 0, K = 0, Kh = 0, Nphi = 0;
+  int64_t N = 0;
+  double eta = 1.0;
+  int64_t n_near = 0;
+  int64_t far_pairs = 0;
+
+  // host copies
+  std::vector<sbie::Particle> h_part;
+  std::vector<int32_t> h_near_ptr, h_near_src;  // CSR by target particle
+
+  // device, geometry
+  sbie::Particle* d_part = nullptr;
+  double *d_x = nullptr, *d_y = nullptr, *d_z = nullptr;     // nodes (SoA)
+  double *d_nx = nullptr, *d_ny = nullptr, *d_nz = nullptr;  // unit outward normals
+  double* d_w = nullptr;                                     // quadrature weights
+  float* d_off32 = nullptr;       // [N][4] node - centre (float), for the mixed far field
+  double* d_gl = nullptr;         // [2(p+1)] GL nodes, weights
+  double* d_An = nullptr;         // [T][K] analysis matrix (weights folded in)
+  double* d_Sy = nullptr;         // [K][T] synthesis matrix
+  float* d_An32 = nullptr;        // FP32 copies for the mixed path
+  float* d_Sy32 = nullptr;
+  double* d_wS = nullptr;         // [M][p+1] sqrt(u0^2 -+ v_j^2)
+  double* d_lam = nullptr;        // [M][Kh][4]: D principal value, D exterior, S, 1/Q_n^m(z0)
+  double* d_ab = nullptr;         // [Kh][2] normalised Ferrers recurrence coefficients
+  int32_t *d_near_ptr = nullptr, *d_near_src = nullptr;
+  uint32_t* d_excl = nullptr;     // [M][ceil(M/32)] bit i of row j: source i excluded for target j
+  int excl_words = 0;
+  unsigned* d_status = nullptr;
+
+  // device, work
+  double* d_f = nullptr;          // [M][T] transform input
+  double* d_coef = nullptr;       // [M][K]
+  double* d_cself = nullptr;      // [M][K]
+  double* d_E = nullptr;          // [M][K] exterior coefficients
+  double* d_uself = nullptr;      // [N]
+  double* d_unear = nullptr;      // [N]
+  double* d_src = nullptr;        // [N][8] far-field source records
+  double* d_partial = nullptr;    // [nsplit][N]
+  double* d_dens = nullptr;       // [N] staging for host densities
+  double* d_out = nullptr;        // [N] staging for host potentials
+  float* d_f32 = nullptr;         // mixed-path buffers
+  float* d_coef32 = nullptr;
+  float* d_src32 = nullptr;       // [N][8]
+  float* d_partial32 = nullptr;   // [nsplit][N][2] (sum, compensation)
+  int nsplit = 8;
+  uint64_t footprint = 0;
+
+  sbie::Timing timing;
+};
+
+namespace sbie {
+
+void set_error(const std::string& msg);
+sbie_status device_error(hipError_t e, const char* what);
+
+#define SBIE_HIP(call)                                              \
+  do {                                                              \
+    hipError_t _e = (call);                                         \
+    if (_e != hipSuccess) return ::sbie::device_error(_e, #call);   \
+  } while (0)
+
+// setup kernels (setup.hip)
+sbie_status setup_geometry(sbie_geom* g, hipStream_t s);
+
+// apply kernels (apply.hip)
+sbie_status apply_laplace(sbie_geom* g, int op, int prec, const double* d_dens, double* d_out,
+                          hipStream_t s, uint32_t parts, bool timed);
+sbie_status transform_only(sbie_geom* g, int op, const double* d_dens, double* d_coef, hipStream_t s);
+
+}  // namespace sbie

@@ -1,0 +1,268 @@
+"""Parity of the HIP library (through its C ABI) with the FP64 oracle.
+
+FP64 path tolerance: relative l2 error <= 1e-10 per result (and the max-norm
+error <= 1e-10 of the max-norm of the oracle result), for each part and for the
+sum.  Integer work (near/far classification) is compared exactly.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    import paper_2506_20809_amd as sbie
+
+    assert torch.cuda.is_available()
+    c = sbie.Context(0)
+    yield c
+    c.close()
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a - b)
+
+
+def _check_parts(g, geom, p, op, dens, tol=TOL64, label=""):
+    import torch
+
+    import paper_2506_20809_amd as sbie
+
+    ref = oracle.apply(geom, p, op, dens, parts=True)
+    d = torch.tensor(dens, dtype=torch.float64, device="cuda")
+    names = ["all", "self", "near", "far"]
+    flags = [sbie.SBIE_PARTS_ALL, sbie.SBIE_PARTS_SELF, sbie.SBIE_PARTS_NEAR, sbie.SBIE_PARTS_FAR]
+    for name, fl, r in zip(names, flags, ref):
+        u = g.apply(op, d, parts=fl)
+        g.sync()
+        u = u.cpu().numpy()
+        scale = max(np.max(np.abs(r)), 1e-300)
+        if np.max(np.abs(r)) == 0:
+            assert np.max(np.abs(u)) < 1e-13, (label, name)
+            continue
+        assert _rel(u, r) < tol, (label, name, _rel(u, r))
+        assert np.max(np.abs(u - r)) < tol * scale, (label, name, np.max(np.abs(u - r)) / scale)
+
+
+def _ellipsoid_on_surface(g, geom, p):
+    xyz, nrm, w = g.nodes()
+    rx, rn, rw = oracle.grid(geom, p)
+    assert np.max(np.abs(xyz - rx)) < 1e-13
+    assert np.max(np.abs(nrm - rn)) < 1e-13
+    assert np.max(np.abs(w - rw)) < 1e-15 * max(1.0, np.max(np.abs(rw)) * 10)
+
+
+def test_c1_geometry_and_classification(ctx):
+    import paper_2506_20809_amd as sbie
+
+    geom = workloads.geometry("c1")
+    g = sbie.Geometry(ctx, geom, 8)
+    _ellipsoid_on_surface(g, geom, 8)
+    src, dst = g.near_pairs()
+    near = oracle.classify(geom)
+    assert sorted(zip(src.tolist(), dst.tolist())) == sorted(zip(*np.nonzero(near)))
+    g.close()
+
+
+@pytest.mark.parametrize("name,p", [("c1", 8), ("c2", 16)])
+def test_spectra_parity(ctx, name, p):
+    """Theorems 1-2 spectra and the exterior normaliser 1/Q_n^m(z0) per particle."""
+    import paper_2506_20809_amd as sbie
+
+    geom = workloads.geometry(name)
+    g = sbie.Geometry(ctx, geom, p)
+    lam = g.spectra()
+    for i in range(len(geom["A"])):
+        A, C = geom["A"][i], geom["C"][i]
+        oblate = C < A
+        a = math.sqrt(abs(A * A - C * C))
+        u0 = C / a
+        lamD, lamDp, lamDm, lamS = oracle.spectra(oblate, a, u0, p)
+        assert np.max(np.abs(lam[i, :, 0] - lamD)) < 1e-13 * max(1, np.max(np.abs(lamD)))
+        assert np.max(np.abs(lam[i, :, 1] - lamDp)) < 1e-13 * max(1, np.max(np.abs(lamDp)))
+        assert np.max(np.abs(lam[i, :, 2] - lamS)) < 1e-13 * np.max(np.abs(lamS))
+        for m in range(p + 1):
+            _, Q, _, _ = oracle.legendre(oblate, u0, m, p + 1)
+            for n in range(m, p + 1):
+                q = (Q[n] * (1j) ** (n + 1)).real if oblate else Q[n].real
+                h = n * (n + 1) // 2 + m
+                assert abs(lam[i, h, 3] * q - 1.0) < 1e-12
+    g.close()
+
+
+@pytest.mark.parametrize("op", [0, 1])
+def test_transform_parity(ctx, op):
+    """Forward transform (Algorithm 1, line 2), modified basis for S."""
+    import paper_2506_20809_amd as sbie
+
+    for name, p in [("c1", 8), ("c2", 16)]:
+        geom = workloads.geometry(name)
+        g = sbie.Geometry(ctx, geom, p)
+        dens = workloads.density(name)[0]
+        c = g.transform(op, dens)[0]
+        T = (p + 1) * (2 * p + 2)
+        v, _ = np.polynomial.legendre.leggauss(p + 1)
+        vv = np.repeat(v, 2 * p + 2)
+        for i in range(len(geom["A"])):
+            A, C = geom["A"][i], geom["C"][i]
+            a = math.sqrt(abs(A * A - C * C))
+            u0 = C / a
+            wgt = np.sqrt(u0 * u0 + (1 if C < A else -1) * vv * vv) if op == 0 else 1.0
+            ref = oracle.transform(p, wgt * dens[i * T:(i + 1) * T])
+            assert np.max(np.abs(c[i] - ref)) < 1e-12 * np.max(np.abs(ref)), (name, i)
+        g.close()
+
+
+@pytest.mark.parametrize("op", [0, 1])
+def test_c1_parity(ctx, op):
+    import paper_2506_20809_amd as sbie
+
+    geom = workloads.geometry("c1")
+    p = 8
+    g = sbie.Geometry(ctx, geom, p)
+    _check_parts(g, geom, p, op, workloads.density("c1")[0], label=f"c1 op={op}")
+    g.close()
+
+
+@pytest.mark.parametrize("op", [0, 1])
+def test_c2_parity(ctx, op):
+    import paper_2506_20809_amd as sbie
+
+    geom = workloads.geometry("c2")
+    p = 16
+    g = sbie.Geometry(ctx, geom, p)
+    src, dst = g.near_pairs()
+    near = oracle.classify(geom)
+    assert sorted(zip(src.tolist(), dst.tolist())) == sorted(zip(*np.nonzero(near)))
+    _check_parts(g, geom, p, op, workloads.density("c2")[0], label=f"c2 op={op}")
+    g.close()
+
+
+def _mini(M, seed, p_types=None, gap=0.05, phi=0.1):
+    g = workloads.rsa_pack(M, phi, gap, seed)
+    return g
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 5, 9, 12, 17, 24])
+def test_small_suspensions_many_orders(ctx, p):
+    """Ragged sizes (N not a multiple of any tile), orders across the register
+    buckets, prolate and oblate mixes."""
+    import paper_2506_20809_amd as sbie
+
+    geom = workloads.rsa_pack(7, 0.12, 0.05, 100 + p)
+    rng = np.random.default_rng(p)
+    N = 7 * (p + 1) * (2 * p + 2)
+    dens = rng.standard_normal(N)
+    g = sbie.Geometry(ctx, geom, p)
+    near = oracle.classify(geom)
+    src, dst = g.near_pairs()
+    assert sorted(zip(src.tolist(), dst.tolist())) == sorted(zip(*np.nonzero(near)))
+    for op in (0, 1):
+        _check_parts(g, geom, p, op, dens, label=f"mini p={p} op={op}")
+    g.close()
+
+
+def test_single_particle_self_only(ctx):
+    import paper_2506_20809_amd as sbie
+
+    for A, C in [(0.5, 1.0), (1.2, 0.4)]:
+        geom = {"centers": np.array([[0.3, -0.2, 1.0]]), "quats": np.array([[0.9, 0.1, -0.3, 0.2]]) /
+                np.linalg.norm([0.9, 0.1, -0.3, 0.2]), "A": np.array([A]), "C": np.array([C])}
+        p = 10
+        g = sbie.Geometry(ctx, geom, p)
+        assert g.num_near_pairs == 0
+        dens = np.random.default_rng(1).standard_normal(g.N)
+        _check_parts(g, geom, p, 0, dens, label="single S")
+        _check_parts(g, geom, p, 1, dens, label="single D")
+        g.close()
+
+
+def test_gauss_identity_on_gpu_c2(ctx):
+    """D[1] = -1/2 at every node of the 64-particle suspension."""
+    import torch
+
+    import paper_2506_20809_amd as sbie
+
+    geom = workloads.geometry("c2")
+    g = sbie.Geometry(ctx, geom, 16)
+    u = g.apply(sbie.SBIE_OP_D, torch.ones(g.N, dtype=torch.float64, device="cuda"))
+    g.sync()
+    assert torch.max(torch.abs(u + 0.5)).item() < 1e-9
+    g.close()
+
+
+def test_host_pointer_path_and_nrhs(ctx):
+    import paper_2506_20809_amd as sbie
+
+    geom = workloads.geometry("c1")
+    p = 8
+    g = sbie.Geometry(ctx, geom, p)
+    dens = np.stack([workloads.density("c1")[0], np.random.default_rng(3).standard_normal(g.N)])
+    u = g.apply(sbie.SBIE_OP_S, dens)
+    for r in range(2):
+        ref = oracle.apply(geom, p, 0, dens[r])
+        assert _rel(u[r], ref) < TOL64
+    g.close()
+
+
+def test_errors(ctx):
+    import paper_2506_20809_amd as sbie
+
+    qz = [1.0, 0.0, 0.0, 0.0]
+    over = {"centers": np.array([[0, 0, 0], [0.3, 0, 0]], float), "quats": np.array([qz, qz]),
+            "A": np.array([0.5, 0.5]), "C": np.array([1.0, 1.0])}
+    with pytest.raises(sbie.SbieError) as e:
+        sbie.Geometry(ctx, over, 4)
+    assert e.value.status == -3
+    sph = {"centers": np.zeros((1, 3)), "quats": np.array([qz]), "A": np.array([1.0]), "C": np.array([1.0])}
+    with pytest.raises(sbie.SbieError) as e:
+        sbie.Geometry(ctx, sph, 4)
+    assert e.value.status == -2
+    ok = {"centers": np.zeros((1, 3)), "quats": np.array([qz]), "A": np.array([0.5]), "C": np.array([1.0])}
+    for p in (0, 33):
+        with pytest.raises(sbie.SbieError) as e:
+            sbie.Geometry(ctx, ok, p)
+        assert e.value.status == -1
+    badq = dict(ok, quats=np.array([[1.0, 0.1, 0.0, 0.0]]))
+    with pytest.raises(sbie.SbieError) as e:
+        sbie.Geometry(ctx, badq, 4)
+    assert e.value.status == -1
+    g = sbie.Geometry(ctx, ok, 4)
+    with pytest.raises(sbie.SbieError) as e:
+        g.apply(7, np.zeros(g.N))
+    assert e.value.status == -1
+    g.close()
+
+
+@pytest.mark.parametrize("op", [0, 1])
+def test_c3_full_size_sampled(ctx, op):
+    """512 spheroids, p = 16, FP64: sampled nodes against the oracle evaluated node by node."""
+    import torch
+
+    import paper_2506_20809_amd as sbie
+
+    geom = workloads.geometry("c3")
+    p = 16
+    g = sbie.Geometry(ctx, geom, p)
+    dens = workloads.density("c3")[0]
+    u = g.apply(op, torch.tensor(dens, device="cuda"))
+    g.sync()
+    u = u.cpu().numpy()
+    rng = np.random.default_rng(11 + op)
+    tg = np.sort(rng.choice(g.N, size=24, replace=False))
+    tg[0], tg[-1] = 0, g.N - 1
+    ref = oracle.apply_at(geom, p, op, dens, tg)[0]
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(u[tg] - ref)) < TOL64 * scale, np.max(np.abs(u[tg] - ref)) / scale
+    g.close()

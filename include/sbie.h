@@ -71,7 +71,7 @@ typedef enum {
 
 /* sbie_apply flags */
 #define SBIE_DEVICE_PTRS 0x1u  /* density/potential are device pointers */
-#define SBIE_TIMING 0x2u       /* record per-part device times (sbie_geom_last_timing) */
+#define SBIE_TIMING 0x2u       /* record per-part device times (sbie_geom_timing) */
 #define SBIE_PARTS_SELF 0x10u  /* include the self interaction (Algorithm 1, lines 11-12) */
 #define SBIE_PARTS_NEAR 0x20u  /* include the near field (Algorithm 1, lines 14-15) */
 #define SBIE_PARTS_FAR 0x40u   /* include the far field (Algorithm 1, lines 6-8) */
@@ -80,8 +80,10 @@ typedef enum {
 typedef struct sbie_ctx sbie_ctx;
 typedef struct sbie_geom sbie_geom;
 
-/* Per-part device times of the last timed apply, milliseconds (HIP events on
-   the apply's stream).  far_kernel_ms is the far-field direct-sum kernel alone. */
+/* Per-part device times, milliseconds, averaged over the timed applies (one
+   per right-hand side) since the previous sbie_geom_timing call; measured with
+   HIP events on the apply's stream.  far_kernel_ms is the far-field direct-sum
+   kernel alone. */
 typedef struct {
   double prep_ms;
   double transform_ms; /* forward transform, spectra scaling, inverse transform */
@@ -91,6 +93,7 @@ typedef struct {
   double total_ms;
   int64_t far_pairs;   /* far-field node pairs evaluated per right-hand side */
   int64_t near_evals;  /* near-field (pair, target) evaluations per right-hand side */
+  int64_t count;       /* number of timed applies averaged */
 } sbie_timing;
 
 /* Create a context on HIP device `device` (a stream is created for synchronous
@@ -155,8 +158,10 @@ sbie_status sbie_transform(sbie_geom* g, sbie_op op, int32_t nrhs, const double*
    oblates the real function i^{n+1} Q_n^m(i u0)). */
 sbie_status sbie_geom_spectra(const sbie_geom* g, double* out);
 
-/* Times of the last apply made with SBIE_TIMING (waits for it to finish). */
-sbie_status sbie_geom_last_timing(sbie_geom* g, sbie_timing* out);
+/* Average per-part times of the applies made with SBIE_TIMING since the
+   previous call (waits for them to finish), then starts a new window.
+   SBIE_E_STATE if there was no timed apply. */
+sbie_status sbie_geom_timing(sbie_geom* g, sbie_timing* out);
 
 const char* sbie_status_str(sbie_status s);
 const char* sbie_last_error(void);

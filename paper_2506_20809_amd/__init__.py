@@ -30,7 +30,7 @@ STATUS = {0: "SBIE_OK", -1: "SBIE_E_INVALID", -2: "SBIE_E_DEGENERATE", -3: "SBIE
 EXPORTS = [
     "sbie_ctx_create", "sbie_ctx_destroy", "sbie_geom_create", "sbie_geom_destroy", "sbie_geom_num_nodes",
     "sbie_geom_num_near_pairs", "sbie_geom_footprint_bytes", "sbie_geom_nodes", "sbie_geom_near_pairs",
-    "sbie_apply", "sbie_geom_sync", "sbie_transform", "sbie_geom_spectra", "sbie_geom_last_timing",
+    "sbie_apply", "sbie_geom_sync", "sbie_transform", "sbie_geom_spectra", "sbie_geom_timing",
     "sbie_status_str", "sbie_last_error",
 ]
 
@@ -44,7 +44,7 @@ class SbieError(RuntimeError):
 class Timing(ctypes.Structure):
     _fields_ = [("prep_ms", ctypes.c_double), ("transform_ms", ctypes.c_double), ("near_ms", ctypes.c_double),
                 ("far_kernel_ms", ctypes.c_double), ("assemble_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
-                ("far_pairs", ctypes.c_int64), ("near_evals", ctypes.c_int64)]
+                ("far_pairs", ctypes.c_int64), ("near_evals", ctypes.c_int64), ("count", ctypes.c_int64)]
 
 
 _lib = None
@@ -93,7 +93,7 @@ def lib() -> ctypes.CDLL:
         L.sbie_geom_sync.argtypes = [vp, vp]
         L.sbie_transform.argtypes = [vp, ctypes.c_int, ctypes.c_int32, vp, vp, vp, ctypes.c_uint32]
         L.sbie_geom_spectra.argtypes = [vp, dp]
-        L.sbie_geom_last_timing.argtypes = [vp, ctypes.POINTER(Timing)]
+        L.sbie_geom_timing.argtypes = [vp, ctypes.POINTER(Timing)]
         L.sbie_status_str.argtypes = [ctypes.c_int]
         L.sbie_status_str.restype = ctypes.c_char_p
         L.sbie_last_error.argtypes = []
@@ -231,9 +231,10 @@ class Geometry:
             stream = torch.cuda.current_stream()
         _check(lib().sbie_geom_sync(self._h, ctypes.c_void_p(stream.cuda_stream)))
 
-    def last_timing(self) -> Timing:
+    def timing(self) -> Timing:
+        """Per-part device times averaged over the timed applies since the last call."""
         t = Timing()
-        _check(lib().sbie_geom_last_timing(self._h, ctypes.byref(t)))
+        _check(lib().sbie_geom_timing(self._h, ctypes.byref(t)))
         return t
 
     def close(self):

@@ -410,10 +410,15 @@ sbie_status apply_laplace(sbie_geom* g, int op, int prec, const double* d_dens, 
   const int64_t N = g->N;
   const int B = 256;
   Timing& tm = g->timing;
+  hipEvent_t* ev = nullptr;
   if (timed) {
-    for (int e = 0; e < 6; ++e)
-      if (!tm.ev[e]) SBIE_HIP(hipEventCreate(&tm.ev[e]));
-    SBIE_HIP(hipEventRecord(tm.ev[0], s));
+    if (tm.used == tm.sets.size()) {
+      std::vector<hipEvent_t> set(6, nullptr);
+      for (int e = 0; e < 6; ++e) SBIE_HIP(hipEventCreate(&set[e]));
+      tm.sets.push_back(set);
+    }
+    ev = tm.sets[tm.used++].data();
+    SBIE_HIP(hipEventRecord(ev[0], s));
   }
   // prep: transform input and far-field source records
   if (op == SBIE_OP_S)
@@ -423,7 +428,7 @@ sbie_status apply_laplace(sbie_geom* g, int op, int prec, const double* d_dens, 
     hipLaunchKernelGGL(k_prep_f64<SBIE_OP_D>, dim3(cdiv(N, B)), dim3(B), 0, s, d_dens, g->d_x, g->d_y, g->d_z,
                        g->d_nx, g->d_ny, g->d_nz, g->d_w, g->d_wS, p, N, g->d_f, g->d_src);
   SBIE_HIP(hipGetLastError());
-  if (timed) SBIE_HIP(hipEventRecord(tm.ev[1], s));
+  if (timed) SBIE_HIP(hipEventRecord(ev[1], s));
   // part (a) forward transform, part (b) spectra and inverse transform
   if (parts & (SBIE_PARTS_SELF | SBIE_PARTS_NEAR)) {
     sbie_status st = launch_gemm(g->d_f, T, g->d_An, K, g->d_coef, K, M, K, T, s);
@@ -436,7 +441,7 @@ sbie_status apply_laplace(sbie_geom* g, int op, int prec, const double* d_dens, 
       if (st) return st;
     }
   }
-  if (timed) SBIE_HIP(hipEventRecord(tm.ev[2], s));
+  if (timed) SBIE_HIP(hipEventRecord(ev[2], s));
   // part (c) near field
   if ((parts & SBIE_PARTS_NEAR) && g->n_near > 0) {
     if (p <= 8)
@@ -449,7 +454,7 @@ sbie_status apply_laplace(sbie_geom* g, int op, int prec, const double* d_dens, 
   } else if (parts & SBIE_PARTS_NEAR) {
     SBIE_HIP(hipMemsetAsync(g->d_unear, 0, sizeof(double) * N, s));
   }
-  if (timed) SBIE_HIP(hipEventRecord(tm.ev[3], s));
+  if (timed) SBIE_HIP(hipEventRecord(ev[3], s));
   // part (d) far field
   if (parts & SBIE_PARTS_FAR) {
     constexpr int TPT = 2;
@@ -462,13 +467,12 @@ sbie_status apply_laplace(sbie_geom* g, int op, int prec, const double* d_dens, 
                          g->d_y, g->d_z, g->d_excl, g->excl_words, M, T, N, g->nsplit, g->d_partial);
     SBIE_HIP(hipGetLastError());
   }
-  if (timed) SBIE_HIP(hipEventRecord(tm.ev[4], s));
+  if (timed) SBIE_HIP(hipEventRecord(ev[4], s));
   hipLaunchKernelGGL(k_assemble_f64, dim3(cdiv(N, B)), dim3(B), 0, s, g->d_uself, g->d_unear, g->d_partial,
                      g->nsplit, N, parts, d_out);
   SBIE_HIP(hipGetLastError());
   if (timed) {
-    SBIE_HIP(hipEventRecord(tm.ev[5], s));
-    tm.valid = true;
+    SBIE_HIP(hipEventRecord(ev[5], s));
   }
   return SBIE_OK;
 }

@@ -39,8 +39,9 @@ void free_geom(sbie_geom* g) {
                   g->d_partial, g->d_dens,   g->d_out,   g->d_f32,     g->d_coef32, g->d_src32,  g->d_partial32};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
-  for (hipEvent_t& e : g->timing.ev)
-    if (e) (void)hipEventDestroy(e);
+  for (auto& set : g->timing.sets)
+    for (hipEvent_t e : set)
+      if (e) (void)hipEventDestroy(e);
   delete g;
 }
 
@@ -325,26 +326,37 @@ sbie_status sbie_geom_spectra(const sbie_geom* g, double* out) {
   return SBIE_OK;
 }
 
-sbie_status sbie_geom_last_timing(sbie_geom* g, sbie_timing* out) {
+sbie_status sbie_geom_timing(sbie_geom* g, sbie_timing* out) {
   if (!g || !out) return invalid("NULL argument");
-  if (!g->timing.valid) {
-    set_error("no timed apply has been made");
+  Timing& tm = g->timing;
+  if (tm.used == 0) {
+    set_error("no timed apply since the previous call");
     return SBIE_E_STATE;
   }
-  hipEvent_t* ev = g->timing.ev;
-  SBIE_HIP(hipEventSynchronize(ev[5]));
-  float ms[5];
-  for (int k = 0; k < 5; ++k) SBIE_HIP(hipEventElapsedTime(&ms[k], ev[k], ev[k + 1]));
-  float tot = 0.0f;
-  SBIE_HIP(hipEventElapsedTime(&tot, ev[0], ev[5]));
-  out->prep_ms = ms[0];
-  out->transform_ms = ms[1];
-  out->near_ms = ms[2];
-  out->far_kernel_ms = ms[3];
-  out->assemble_ms = ms[4];
-  out->total_ms = tot;
+  SBIE_HIP(hipSetDevice(g->ctx->device));
+  SBIE_HIP(hipEventSynchronize(tm.sets[tm.used - 1][5]));
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (size_t k = 0; k < tm.used; ++k) {
+    hipEvent_t* ev = tm.sets[k].data();
+    float ms = 0.0f;
+    for (int e = 0; e < 5; ++e) {
+      SBIE_HIP(hipEventElapsedTime(&ms, ev[e], ev[e + 1]));
+      acc[e] += ms;
+    }
+    SBIE_HIP(hipEventElapsedTime(&ms, ev[0], ev[5]));
+    acc[5] += ms;
+  }
+  const double n = (double)tm.used;
+  out->prep_ms = acc[0] / n;
+  out->transform_ms = acc[1] / n;
+  out->near_ms = acc[2] / n;
+  out->far_kernel_ms = acc[3] / n;
+  out->assemble_ms = acc[4] / n;
+  out->total_ms = acc[5] / n;
   out->far_pairs = g->far_pairs;
   out->near_evals = g->n_near * (int64_t)g->T;
+  out->count = (int64_t)tm.used;
+  tm.used = 0;
   return SBIE_OK;
 }
 

@@ -35,9 +35,11 @@ struct Buf {
   size_t bytes = 0;
 };
 
+// One set of six events per timed apply (per right-hand side), reused across
+// accumulation windows.
 struct Timing {
-  hipEvent_t ev[8] = {};
-  bool valid = false;
+  std::vector<std::vector<hipEvent_t>> sets;
+  size_t used = 0;
 };
 
 }  // namespace sbie

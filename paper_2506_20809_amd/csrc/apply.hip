@@ -11,7 +11,6 @@ namespace sbie {
 
 namespace {
 
-constexpr int kCfMaxIter = 10000;
 constexpr double kInv4Pi = 0.079577471545947667884441881686257181;
 
 using d4 = double __attribute__((ext_vector_type(4)));
@@ -94,6 +93,57 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const double* __restrict__ A, 
   }
 }
 
+// The same contraction on the FP32 matrix cores (v_mfma_f32_16x16x4f32:
+// accumulator element r of lane l is C[4*(l/16) + r][l%16]), for the mixed
+// path.  A is read in double and rounded once; every 32 terms of the inner
+// dimension form an FP32 tile that is added into an (hi, lo) pair with TwoSum,
+// and the result is written in double.
+__global__ __launch_bounds__(256) void k_gemm_f32c(const double* __restrict__ A, int lda,
+                                                   const float* __restrict__ B, int ldb,
+                                                   double* __restrict__ C, int ldc, int rows, int cols,
+                                                   int kd) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row0 = blockIdx.y * 64 + wave * 16;
+  const int col0 = blockIdx.x * 64;
+  const int li = lane & 15, lk = lane >> 4;
+  f4 hi[4], lo[4];
+  for (int b = 0; b < 4; ++b) hi[b] = lo[b] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+  const int r = row0 + li;
+  for (int k0 = 0; k0 < kd; k0 += 32) {
+    f4 t[4];
+    for (int b = 0; b < 4; ++b) t[b] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int kend = k0 + 32 < kd ? k0 + 32 : kd;
+    for (int kk = k0; kk < kend; kk += 4) {
+      const int k = kk + lk;
+      const float av = (r < rows && k < kd) ? (float)A[(size_t)r * lda + k] : 0.0f;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int c = col0 + 16 * b + li;
+        const float bv = (c < cols && k < kd) ? B[(size_t)k * ldb + c] : 0.0f;
+        t[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, t[b], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float s = hi[b][e] + t[b][e];
+        const float bp = s - hi[b][e];
+        lo[b][e] += (hi[b][e] - (s - bp)) + (t[b][e] - bp);
+        hi[b][e] = s;
+      }
+  }
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int c = col0 + 16 * b + li;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int rr = row0 + 4 * lk + e;
+      if (rr < rows && c < cols) C[(size_t)rr * ldc + c] = (double)hi[b][e] + (double)lo[b][e];
+    }
+  }
+}
+
 // Diagonal spectra: self coefficients and exterior coefficients per particle.
 __global__ void k_scale_coef(const double* __restrict__ coef, const double* __restrict__ lam, int M,
                              int p, int op, double* cself, double* E) {
@@ -119,15 +169,21 @@ __global__ void k_scale_coef(const double* __restrict__ coef, const double* __re
 
 // One wave per (target particle, 64 target nodes).  Each lane maps its target
 // into the frame of every near source i (ascending i), finds (u, v, phi) from
-// the focal distances, runs the off-cut Legendre algorithm of Section 2.3 for
-// every order m in FP64, and sums E_l Q_n^|m|(u)/Q_n^|m|(u0) Y_l(v, phi).
+// the focal distances, evaluates Q_n^m(u) for every order m in FP64 and sums
+// E_l Q_n^|m|(u)/Q_n^|m|(u0) Y_l(v, phi).  Q_n^m(u) is the minimal solution of
+// the three-term recurrence of Section 2.3: it is obtained by running that
+// recurrence backward from a depth where the continued fraction for Q_N/Q_{N-1}
+// has converged to double precision (Miller's form of the same continued
+// fraction, free of divisions), and normalised with the Casoratian against
+// P_N, P_{N-1} from the forward recurrence -- the same three ingredients as the
+// paper's Lentz / Wronskian / backward scheme, ordered for the vector units.
 template <int PMAX>
 __global__ __launch_bounds__(64) void k_near_f64(
     const Particle* __restrict__ part, const double* __restrict__ x, const double* __restrict__ y,
     const double* __restrict__ z, const int32_t* __restrict__ near_ptr,
     const int32_t* __restrict__ near_src, const double* __restrict__ E,
-    const double* __restrict__ lam, const double* __restrict__ ab, int p, int T, int chunks,
-    unsigned* status, double* __restrict__ unear) {
+    const double* __restrict__ lam, const double* __restrict__ ab, const double* __restrict__ rcp, int p,
+    int T, int chunks, unsigned* status, double* __restrict__ unear) {
   const int j = blockIdx.x / chunks;
   const int t = (blockIdx.x - j * chunks) * 64 + threadIdx.x;
   const bool live = t < T;
@@ -170,11 +226,22 @@ __global__ __launch_bounds__(64) void k_near_f64(
     const double v = b2 / (a * u);
     const double sv = rho / (a * sw);  // sqrt(1 - v^2)
     const double c1 = rho > 0.0 ? b0 / rho : 1.0, s1 = rho > 0.0 ? b1 / rho : 0.0;
+    // depth of the backward recurrence: the ratio of the minimal to the dominant
+    // solution shrinks by (u + sqrt(u^2 -+ 1))^-2 per degree; 2^-58 plus a
+    // margin, the same for the whole wave
+    int steps = (int)ceil(20.1 / log(u + sw)) + 8;
+    for (int off = 32; off >= 1; off >>= 1) steps = max(steps, __shfl_xor(steps, off, 64));
+    if (steps > 100000) {
+      steps = 100000;
+      bad |= kStatNumeric;
+    }
+    const int L = N + steps;
 
     double pmm_u = 1.0;                        // P_m^m(u) (real form)
     double pbar = 0.28209479177387814347;      // normalised Ferrers Pb_m^m(v), 1/sqrt(4 pi) at m = 0
     double cm = 1.0, sm = 0.0;                 // cos(m phi), sin(m phi)
-    double cas = 1.0 / (double)N;              // (-1)^m (N+m-1)!/(N-m)!
+    double cas2 = 1.0;                         // (-1)^m (N+m-1)!
+    for (int k = 2; k < N; ++k) cas2 *= (double)k;
     const double sgn = P.oblate ? 1.0 : -1.0;
     for (int m = 0; m <= p; ++m) {
       if (m > 0) {
@@ -183,62 +250,67 @@ __global__ __launch_bounds__(64) void k_near_f64(
         const double cn = cm * c1 - sm * s1;
         sm = sm * c1 + cm * s1;
         cm = cn;
-        cas = -cas * (double)(N + m - 1) * (double)(N - m + 1);
+        cas2 = -cas2 * (double)(N + m - 1);
       }
-      // forward recurrence for P_n^m(u) up to N (two registers)
-      double pa = pmm_u, pb = (double)(2 * m + 1) * u * pmm_u;  // P_m, P_{m+1}
-      for (int n = m + 1; n < N; ++n) {
-        const double pc = ((double)(2 * n + 1) * u * pb + sgn * (double)(n + m) * pa) / (double)(n - m + 1);
-        pa = pb;
-        pb = pc;
-      }
-      // now pa = P_{N-1}, pb = P_N (m <= p = N-1 so N >= m+1)
-      // continued fraction for H_N (modified Lentz)
-      double H;
+      // forward recurrence for Pt_n = (n-m)! P_n^m(u), free of divisions:
+      //   Pt_{n+1} = (2n+1) u Pt_n -+ (n+m)(n-m) Pt_{n-1}   (- prolate, + oblate)
+      double pa = pmm_u, pb = (double)(2 * m + 1) * u * pmm_u;  // Pt_m, Pt_{m+1}
       {
-        const double tiny = 1e-300;
-        double f = tiny, Cc = tiny, Dd = 0.0;
-        bool conv = false;
-        for (int it = 0, k = N; it < kCfMaxIter; ++it, ++k) {
-          const double inv = 1.0 / (double)(k - m + 1);
-          const double ak = sgn * (double)(k + m) * inv;
-          const double bk = sgn * (double)(2 * k + 1) * u * inv;
-          Dd = fma(ak, Dd, bk);
-          if (Dd == 0.0) Dd = tiny;
-          Dd = 1.0 / Dd;
-          Cc = bk + ak / Cc;
-          if (Cc == 0.0) Cc = tiny;
-          const double delta = Cc * Dd;
-          f *= delta;
-          if (fabs(delta - 1.0) <= 2.3e-16) {
-            conv = true;
-            break;
+        double c2n1 = (double)(2 * m + 3), cnm = (double)(2 * m + 1), cdn = 1.0;  // 2n+1, n+m, n-m at n = m+1
+        for (int n = m + 1; n < N; ++n) {
+          const double pc = fma(c2n1 * u, pb, sgn * (cnm * cdn) * pa);
+          pa = pb;
+          pb = pc;
+          c2n1 += 2.0;
+          cnm += 1.0;
+          cdn += 1.0;
+        }
+      }
+      // now pa = Pt_{N-1}, pb = Pt_N (m <= p = N-1 so N >= m+1).
+      // The minimal solution Q of the same recurrence, unnormalised, by backward
+      // recurrence from degree L (the continued fraction for Q_N/Q_{N-1}
+      // evaluated bottom-up from depth L-N).  With Q_n = s_n R_n and
+      // s_{n-1} = s_n/(n+m) the recurrence is free of divisions:
+      //   R_{n-1} = (2n+1) u R_n -+ (n-m+1)(n+m+1) R_{n+1}
+      // rescaled by 2^-600 whenever it grows past 2^600.
+      double qhi = 0.0, qcur = 1.0;  // R_{n+1}, R_n at n = L
+      {
+        double c2n1 = (double)(2 * L + 1), ca = (double)(L - m + 1), cb = (double)(L + m + 1);
+        for (int n = L; n > N; --n) {
+          const double qn = fma(c2n1 * u, qcur, sgn * (ca * cb) * qhi);
+          qhi = qcur;
+          qcur = qn;
+          c2n1 -= 2.0;
+          ca -= 1.0;
+          cb -= 1.0;
+          if (fabs(qcur) > 0x1p600) {
+            qcur *= 0x1p-600;
+            qhi *= 0x1p-600;
           }
         }
-        if (!conv) bad |= kStatNumeric;
-        H = f;
       }
-      const double den = P.oblate ? fma(H, pa, pb) : fma(-H, pa, pb);
-      const double QN1 = cas / den;
-      const double QN = H * QN1;
-      // backward recurrence into Q[n], indexed by degree (static indices)
+      // R_N, R_{N+1} -> Q~_N = R_N/(N+m+1), Q~_{N+1} = R_{N+1} (s_{N+1} = 1)
+      qcur *= rcp[N + m + 1];
+      // qcur = Q~_N, qhi = Q~_{N+1}; continue into registers indexed by degree
       double Q[PMAX + 4];
+      double qN1 = 0.0;
 #pragma unroll
-      for (int n = PMAX + 1; n >= 0; --n) {
-        if (n == N) {
-          Q[n] = QN;
-        } else if (n == N - 1) {
-          Q[n] = QN1;
-        } else if (n < N - 1 && n >= m) {
-          // Q_n from Q_{n+1}, Q_{n+2} (recurrence at degree n+1)
-          const double num = P.oblate
-              ? (double)(n - m + 2) * Q[n + 2] + (double)(2 * n + 3) * u * Q[n + 1]
-              : (double)(2 * n + 3) * u * Q[n + 1] - (double)(n - m + 2) * Q[n + 2];
-          Q[n] = num / (double)(n + m + 1);
+      for (int n = PMAX + 2; n >= 0; --n) {
+        if (n == N + 1) {
+          Q[n] = qhi;
+        } else if (n == N) {
+          Q[n] = qcur;
+        } else if (n < N && n >= m) {
+          Q[n] = fma((double)(2 * n + 3) * u, Q[n + 1], sgn * (double)(n - m + 2) * Q[n + 2]) * rcp[n + m + 1];
         } else {
           Q[n] = 0.0;
         }
+        if (n == N - 1) qN1 = Q[n];
       }
+      // normalise with the Casoratian at degree N, P_N Q_{N-1} -+ P_{N-1} Q_N =
+      // (-1)^m (N+m-1)!/(N-m)!, written for Pt = (n-m)! P:
+      //   Pt_N Q_{N-1} -+ (N-m) Pt_{N-1} Q_N = (-1)^m (N+m-1)!
+      const double qscale = cas2 / fma(sgn * (double)(N - m) * pa, qcur, pb * qN1);
       // contraction with the normalised Ferrers functions, forward in n
       double sc = 0.0, ss = 0.0;
       double p2 = 0.0, p1 = pbar;
@@ -258,7 +330,7 @@ __global__ __launch_bounds__(64) void k_near_f64(
             p2 = p1;
             p1 = pn;
           }
-          const double qr = Q[n] * Li[(n * (n + 1) / 2 + m) * 4 + 3];
+          const double qr = Q[n] * qscale * Li[(n * (n + 1) / 2 + m) * 4 + 3];
           const double t0 = pn * qr;
           sc = fma(Ei[n * n + n + m], t0, sc);
           if (m > 0) ss = fma(Ei[n * n + n - m], t0, ss);
@@ -393,11 +465,20 @@ sbie_status launch_gemm(const double* A, int lda, const double* B, int ldb, doub
   return SBIE_OK;
 }
 
+sbie_status launch_gemm32(const double* A, int lda, const float* B, int ldb, double* C, int ldc, int rows,
+                          int cols, int kd, hipStream_t s) {
+  hipLaunchKernelGGL(k_gemm_f32c, dim3(cdiv(cols, 64), cdiv(rows, 64)), dim3(256), 0, s, A, lda, B, ldb, C, ldc,
+                     rows, cols, kd);
+  SBIE_HIP(hipGetLastError());
+  return SBIE_OK;
+}
+
 template <int PMAX>
 void launch_near(sbie_geom* g, hipStream_t s) {
   const int chunks = (g->T + 63) / 64;
   hipLaunchKernelGGL(k_near_f64<PMAX>, dim3(g->M * chunks), dim3(64), 0, s, g->d_part, g->d_x, g->d_y, g->d_z,
-                     g->d_near_ptr, g->d_near_src, g->d_E, g->d_lam, g->d_ab, g->p, g->T, chunks, g->d_status,
+                     g->d_near_ptr, g->d_near_src, g->d_E, g->d_lam, g->d_ab, g->d_rcp, g->p, g->T, chunks,
+                     g->d_status,
                      g->d_unear);
 }
 
@@ -405,7 +486,6 @@ void launch_near(sbie_geom* g, hipStream_t s) {
 
 sbie_status apply_laplace(sbie_geom* g, int op, int prec, const double* d_dens, double* d_out, hipStream_t s,
                           uint32_t parts, bool timed) {
-  (void)prec;
   const int M = g->M, p = g->p, T = g->T, K = g->K;
   const int64_t N = g->N;
   const int B = 256;
@@ -430,14 +510,17 @@ sbie_status apply_laplace(sbie_geom* g, int op, int prec, const double* d_dens, 
   SBIE_HIP(hipGetLastError());
   if (timed) SBIE_HIP(hipEventRecord(ev[1], s));
   // part (a) forward transform, part (b) spectra and inverse transform
+  const bool mixed = prec == SBIE_MIXED;
   if (parts & (SBIE_PARTS_SELF | SBIE_PARTS_NEAR)) {
-    sbie_status st = launch_gemm(g->d_f, T, g->d_An, K, g->d_coef, K, M, K, T, s);
+    sbie_status st = mixed ? launch_gemm32(g->d_f, T, g->d_An32, K, g->d_coef, K, M, K, T, s)
+                           : launch_gemm(g->d_f, T, g->d_An, K, g->d_coef, K, M, K, T, s);
     if (st) return st;
     hipLaunchKernelGGL(k_scale_coef, dim3(cdiv((int64_t)M * K, B)), dim3(B), 0, s, g->d_coef, g->d_lam, M, p, op,
                        g->d_cself, g->d_E);
     SBIE_HIP(hipGetLastError());
     if (parts & SBIE_PARTS_SELF) {
-      st = launch_gemm(g->d_cself, K, g->d_Sy, T, g->d_uself, T, M, T, K, s);
+      st = mixed ? launch_gemm32(g->d_cself, K, g->d_Sy32, T, g->d_uself, T, M, T, K, s)
+                 : launch_gemm(g->d_cself, K, g->d_Sy, T, g->d_uself, T, M, T, K, s);
       if (st) return st;
     }
   }
@@ -454,9 +537,13 @@ sbie_status apply_laplace(sbie_geom* g, int op, int prec, const double* d_dens, 
   } else if (parts & SBIE_PARTS_NEAR) {
     SBIE_HIP(hipMemsetAsync(g->d_unear, 0, sizeof(double) * N, s));
   }
-  if (timed) SBIE_HIP(hipEventRecord(ev[3], s));
-  // part (d) far field
-  if (parts & SBIE_PARTS_FAR) {
+  // part (d) far field: matrix-core tiles when a wave of 64 targets spans at
+  // most three particles (T >= 32), else the vector-unit sum in FP64
+  if ((parts & SBIE_PARTS_FAR) && T >= 32) {
+    sbie_status st = far_mfma(g, op, prec, d_dens, s, timed ? ev[3] : nullptr, timed ? ev[4] : nullptr);
+    if (st) return st;
+  } else if (parts & SBIE_PARTS_FAR) {
+    if (timed) SBIE_HIP(hipEventRecord(ev[3], s));
     constexpr int TPT = 2;
     const unsigned tiles = cdiv(N, 256 * TPT);
     if (op == SBIE_OP_S)
@@ -466,8 +553,11 @@ sbie_status apply_laplace(sbie_geom* g, int op, int prec, const double* d_dens, 
       hipLaunchKernelGGL((k_far_f64<SBIE_OP_D, TPT>), dim3(tiles * g->nsplit), dim3(256), 0, s, g->d_src, g->d_x,
                          g->d_y, g->d_z, g->d_excl, g->excl_words, M, T, N, g->nsplit, g->d_partial);
     SBIE_HIP(hipGetLastError());
+    if (timed) SBIE_HIP(hipEventRecord(ev[4], s));
+  } else if (timed) {
+    SBIE_HIP(hipEventRecord(ev[3], s));
+    SBIE_HIP(hipEventRecord(ev[4], s));
   }
-  if (timed) SBIE_HIP(hipEventRecord(ev[4], s));
   hipLaunchKernelGGL(k_assemble_f64, dim3(cdiv(N, B)), dim3(B), 0, s, g->d_uself, g->d_unear, g->d_partial,
                      g->nsplit, N, parts, d_out);
   SBIE_HIP(hipGetLastError());

@@ -36,7 +36,8 @@ void free_geom(sbie_geom* g) {
                   g->d_w,      g->d_off32,   g->d_gl,    g->d_An,      g->d_Sy,     g->d_An32,   g->d_Sy32,
                   g->d_wS,     g->d_lam,     g->d_ab,    g->d_near_ptr, g->d_near_src, g->d_excl, g->d_status,
                   g->d_f,      g->d_coef,    g->d_cself, g->d_E,       g->d_uself,  g->d_unear,  g->d_src,
-                  g->d_partial, g->d_dens,   g->d_out,   g->d_f32,     g->d_coef32, g->d_src32,  g->d_partial32};
+                  g->d_partial, g->d_dens,   g->d_out,   g->d_srec32,  g->d_srec64, g->d_fstr32, g->d_fstr64,
+                  g->d_rcp};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (auto& set : g->timing.sets)
@@ -237,10 +238,6 @@ sbie_status sbie_apply(sbie_geom* g, sbie_op op, sbie_precision prec, int32_t nr
   if (!density || !potential) return invalid("density or potential is NULL");
   if (op == SBIE_OP_STOKES_S) {
     set_error("the Stokes single layer is not available in this build");
-    return SBIE_E_INVALID;
-  }
-  if (prec == SBIE_MIXED) {
-    set_error("the mixed-precision path is not available in this build");
     return SBIE_E_INVALID;
   }
   SBIE_HIP(hipSetDevice(g->ctx->device));

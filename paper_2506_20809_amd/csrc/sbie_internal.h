@@ -12,6 +12,7 @@
 namespace sbie {
 
 constexpr int kMaxP = 32;
+constexpr int kRcpN = 16384;  // reciprocal table length (near-field recurrences)
 constexpr double kPi = 3.14159265358979323846264338327950288;
 
 // Per-particle parameters on the device (Section 2.1, Table 1).
@@ -91,10 +92,18 @@ struct sbie_geom {
   double* d_partial = nullptr;    // [nsplit][N]
   double* d_dens = nullptr;       // [N] staging for host densities
   double* d_out = nullptr;        // [N] staging for host potentials
-  float* d_f32 = nullptr;         // mixed-path buffers
-  float* d_coef32 = nullptr;
-  float* d_src32 = nullptr;       // [N][8]
-  float* d_partial32 = nullptr;   // [nsplit][N][2] (sum, compensation)
+  // matrix-core far field: sources padded per particle to T16 = 16*ceil(T/16)
+  int T16 = 0;
+  // per 16-source block b of particle s, 80 values at (s*nb + b)*80: the MFMA B
+  // operand in lane order ([k][j] at 16k+j; (-2 o_x, -2 o_y, -2 o_z, 1) for
+  // source j, o = node - centre) followed by |o_j|^2, j = 0..15
+  float* d_srec32 = nullptr;      // [M*T16*5]
+  double* d_srec64 = nullptr;
+  // per-apply strengths per block: S 16 values W sigma_j at (s*nb + b)*16;
+  // D 80 values at (s*nb + b)*80: (W mu nu_j, 0) in lane order, then -W mu nu_j.o_j
+  float* d_fstr32 = nullptr;      // [M*T16*5]
+  double* d_fstr64 = nullptr;
+  double* d_rcp = nullptr;        // [kRcpN] reciprocals 1/k for the near-field recurrences
   int nsplit = 8;
   uint64_t footprint = 0;
 
@@ -119,5 +128,10 @@ sbie_status setup_geometry(sbie_geom* g, hipStream_t s);
 sbie_status apply_laplace(sbie_geom* g, int op, int prec, const double* d_dens, double* d_out,
                           hipStream_t s, uint32_t parts, bool timed);
 sbie_status transform_only(sbie_geom* g, int op, const double* d_dens, double* d_coef, hipStream_t s);
+
+// matrix-core far field (far_mfma.hip)
+sbie_status far_records(sbie_geom* g, hipStream_t s);
+sbie_status far_mfma(sbie_geom* g, int op, int prec, const double* d_dens, hipStream_t s, hipEvent_t ev_begin,
+                     hipEvent_t ev_end);
 
 }  // namespace sbie

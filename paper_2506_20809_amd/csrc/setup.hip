@@ -452,10 +452,21 @@ sbie_status setup_geometry(sbie_geom* g, hipStream_t s) {
   SBIE_TRY(dev_alloc(&g->d_partial, (size_t)g->nsplit * N, &fp));
   SBIE_TRY(dev_alloc(&g->d_dens, N, &fp));
   SBIE_TRY(dev_alloc(&g->d_out, N, &fp));
-  SBIE_TRY(dev_alloc(&g->d_f32, (size_t)M * T, &fp));
-  SBIE_TRY(dev_alloc(&g->d_coef32, (size_t)M * K, &fp));
-  SBIE_TRY(dev_alloc(&g->d_src32, 8 * N, &fp));
-  SBIE_TRY(dev_alloc(&g->d_partial32, (size_t)g->nsplit * N * 2, &fp));
+  g->T16 = 16 * ((T + 15) / 16);
+  {
+    const size_t n16 = (size_t)M * g->T16;
+    SBIE_TRY(dev_alloc(&g->d_srec64, 5 * n16, &fp));
+    SBIE_TRY(dev_alloc(&g->d_srec32, 5 * n16, &fp));
+    SBIE_TRY(dev_alloc(&g->d_fstr64, 5 * n16, &fp));
+    SBIE_TRY(dev_alloc(&g->d_fstr32, 5 * n16, &fp));
+  }
+  SBIE_TRY(far_records(g, s));
+  {
+    std::vector<double> rcp(kRcpN, 0.0);
+    for (int k = 1; k < kRcpN; ++k) rcp[k] = 1.0 / (double)k;
+    SBIE_TRY(dev_alloc(&g->d_rcp, (size_t)kRcpN, &fp));
+    SBIE_HIP(hipMemcpyAsync(g->d_rcp, rcp.data(), sizeof(double) * kRcpN, hipMemcpyHostToDevice, s));
+  }
 
   // status after the spectra kernel
   SBIE_HIP(hipMemcpyAsync(&status, g->d_status, sizeof(unsigned), hipMemcpyDeviceToHost, s));

@@ -34,7 +34,7 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a - b)
 
 
-def _check_parts(g, geom, p, op, dens, tol=TOL64, label=""):
+def _check_parts(g, geom, p, op, dens, tol=TOL64, label="", precision=0, max_tol=None):
     import torch
 
     import paper_2506_20809_amd as sbie
@@ -43,8 +43,9 @@ def _check_parts(g, geom, p, op, dens, tol=TOL64, label=""):
     d = torch.tensor(dens, dtype=torch.float64, device="cuda")
     names = ["all", "self", "near", "far"]
     flags = [sbie.SBIE_PARTS_ALL, sbie.SBIE_PARTS_SELF, sbie.SBIE_PARTS_NEAR, sbie.SBIE_PARTS_FAR]
+    max_tol = tol if max_tol is None else max_tol
     for name, fl, r in zip(names, flags, ref):
-        u = g.apply(op, d, parts=fl)
+        u = g.apply(op, d, parts=fl, precision=precision)
         g.sync()
         u = u.cpu().numpy()
         scale = max(np.max(np.abs(r)), 1e-300)
@@ -52,7 +53,7 @@ def _check_parts(g, geom, p, op, dens, tol=TOL64, label=""):
             assert np.max(np.abs(u)) < 1e-13, (label, name)
             continue
         assert _rel(u, r) < tol, (label, name, _rel(u, r))
-        assert np.max(np.abs(u - r)) < tol * scale, (label, name, np.max(np.abs(u - r)) / scale)
+        assert np.max(np.abs(u - r)) < max_tol * scale, (label, name, np.max(np.abs(u - r)) / scale)
 
 
 def _ellipsoid_on_surface(g, geom, p):
@@ -265,4 +266,56 @@ def test_c3_full_size_sampled(ctx, op):
     ref = oracle.apply_at(geom, p, op, dens, tg)[0]
     scale = np.max(np.abs(ref))
     assert np.max(np.abs(u[tg] - ref)) < TOL64 * scale, np.max(np.abs(u[tg] - ref)) / scale
+    g.close()
+
+
+# ---------------------------------------------------------------- mixed precision (FP32 sums, FP64 geometry)
+
+TOL_MIXED = 1e-6
+
+
+@pytest.mark.parametrize("name,p", [("c1", 8), ("c2", 16)])
+@pytest.mark.parametrize("op", [0, 1])
+def test_mixed_parity(ctx, name, p, op):
+    """Relative l2 error per result <= 1e-6 against the FP64 oracle."""
+    import paper_2506_20809_amd as sbie
+
+    geom = workloads.geometry(name)
+    g = sbie.Geometry(ctx, geom, p)
+    _check_parts(g, geom, p, op, workloads.density(name)[0], tol=TOL_MIXED, max_tol=1e-5,
+                 label=f"mixed {name} op={op}", precision=sbie.SBIE_MIXED)
+    g.close()
+
+
+@pytest.mark.parametrize("p", [2, 3, 4, 6, 12, 20])
+def test_mixed_small_suspensions(ctx, p):
+    import paper_2506_20809_amd as sbie
+
+    geom = workloads.rsa_pack(9, 0.12, 0.05, 300 + p)
+    dens = np.random.default_rng(p).standard_normal(9 * (p + 1) * (2 * p + 2))
+    g = sbie.Geometry(ctx, geom, p)
+    for op in (0, 1):
+        _check_parts(g, geom, p, op, dens, tol=TOL_MIXED, max_tol=1e-5, label=f"mixed mini p={p} op={op}",
+                     precision=sbie.SBIE_MIXED)
+    g.close()
+
+
+@pytest.mark.parametrize("op", [0, 1])
+def test_mixed_c3_full_size_sampled(ctx, op):
+    """512 spheroids at p = 16 in the mixed path: sampled nodes against the oracle."""
+    import torch
+
+    import paper_2506_20809_amd as sbie
+
+    geom = workloads.geometry("c3")
+    p = 16
+    g = sbie.Geometry(ctx, geom, p)
+    dens = workloads.density("c3")[0]
+    u = g.apply(op, torch.tensor(dens, device="cuda"), precision=sbie.SBIE_MIXED)
+    g.sync()
+    u = u.cpu().numpy()
+    rng = np.random.default_rng(21 + op)
+    tg = np.sort(rng.choice(g.N, size=48, replace=False))
+    ref = oracle.apply_at(geom, p, op, dens, tg)[0]
+    assert _rel(u[tg], ref) < TOL_MIXED, _rel(u[tg], ref)
     g.close()

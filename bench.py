@@ -2,18 +2,19 @@
 
 One step = one S apply and one D apply (nrhs = 1 each, fresh N(0,1) densities
 already resident in HBM), i.e. one pass of the whole apply (transform, self,
-near, far, assembly) per operator.  Prints one JSON line with applies/s,
-pair-interactions/s, per-apply p50/p99 latency, the far-field kernel's
-roofline figures (HIP events inside the library, on the apply's stream) and
-the CPU oracle timed on a bounded sample of the same workload.
+near, far, assembly) per operator.  The headline line is the mixed-precision
+path (FP32 sums and contractions with compensated tiles, FP64 geometry and
+recurrences); the plain FP64 path is measured on the same inputs and reported
+beside it.  Prints one JSON line with applies/s, pair-interactions/s, per-apply
+p50/p99 latency, the far-field kernel's roofline figures (HIP events inside the
+library, on the apply's stream) and the CPU oracle timed on a bounded sample.
 
-  python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--precision fp64|mixed]
+  python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--precision mixed|fp64]
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -25,7 +26,8 @@ sys.path.insert(0, ROOT)
 # S: 3 differences + 5 for r^2 + 1 rsqrt + 2 accumulate
 # D: 3 differences + 5 for r^2 + 1 rsqrt + 2 for r^-3 + 5 for the dipole dot + 2 accumulate
 FLOPS_PER_PAIR = {0: 11, 1: 18}
-PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}   # MI355X vector FP64 / FP32 (2.4 GHz, 256 CUs)
+# MI355X vector peaks: FP64 78.6 TFLOP/s, FP32 157.3 TFLOP/s (256 CUs, 2.4 GHz)
+PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}
 
 
 def cpu_baseline(geom, p, dens_s, dens_d, N, sample):
@@ -47,28 +49,78 @@ def cpu_baseline(geom, p, dens_s, dens_d, N, sample):
                       f"{dt:.1f} s, scaled to whole applies"}
 
 
+def run(g, dens, steps, warmup, precision):
+    """Time `steps` steps (S then D) on the torch current stream."""
+    import numpy as np
+    import torch
+
+    import paper_2506_20809_amd as sbie
+
+    prec = sbie.SBIE_MIXED if precision == "mixed" else sbie.SBIE_FP64
+    stream = torch.cuda.current_stream()
+    out = torch.empty((2, g.N), dtype=torch.float64, device="cuda")
+    ops = (sbie.SBIE_OP_S, sbie.SBIE_OP_D)
+    for k in range(warmup):
+        for o in range(2):
+            g.apply(ops[o], dens[k % dens.shape[0], o], precision=prec, out=out[o], timing=True)
+    g.sync()
+    g.timing()  # discard warm-up timings
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(2 * steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        for o in range(2):
+            e = ev[2 * k + o]
+            e[0].record(stream)
+            g.apply(ops[o], dens[(warmup + k) % dens.shape[0], o], precision=prec, out=out[o], timing=True)
+            e[1].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    g.sync()
+    tim = g.timing()
+    lat = np.array([e[0].elapsed_time(e[1]) for e in ev])
+    flops_per_launch = 0.5 * (FLOPS_PER_PAIR[0] + FLOPS_PER_PAIR[1]) * tim.far_pairs
+    achieved = flops_per_launch / (tim.far_kernel_ms * 1e-3) / 1e12
+    return {
+        "applies_per_s": 2 * steps / elapsed,
+        "elapsed_s": elapsed,
+        "pair_interactions_per_s": tim.far_pairs / (tim.far_kernel_ms * 1e-3),
+        "effective_all_pairs_per_s": float(g.N) * g.N / (np.mean(lat) * 1e-3),
+        "near_evals_per_s": tim.near_evals / (tim.near_ms * 1e-3) if tim.near_ms > 0 else None,
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "mean": float(np.mean(lat))},
+        "part_ms": {"prep": tim.prep_ms, "transform_self": tim.transform_ms, "near": tim.near_ms,
+                    "far_kernel": tim.far_kernel_ms, "assemble": tim.assemble_ms, "apply_total": tim.total_ms},
+        "far_pairs": tim.far_pairs,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS[precision], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_TFLOPS[precision], "traffic": None,
+                     "kernel": "k_far_mfma<float> (S and D alternating)" if precision == "mixed"
+                     else "k_far_mfma<double> (S and D alternating)",
+                     "flops_per_launch": flops_per_launch},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
     ap.add_argument("--workload", default="c3")
-    ap.add_argument("--cpu-sample", type=int, default=16384)
+    ap.add_argument("--cpu-sample", type=int, default=32768)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the other precision's measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_2506_20809_amd as sbie
     import workloads
 
     assert torch.cuda.is_available(), "bench needs a GPU"
-    prec = sbie.SBIE_MIXED if args.precision == "mixed" else sbie.SBIE_FP64
     geom = workloads.geometry(args.workload)
     p = workloads.CONFIGS[args.workload]["p"]
     M = len(geom["A"])
@@ -77,73 +129,43 @@ def main():
     g = sbie.Geometry(ctx, geom, p)
     setup_s = time.perf_counter() - t0
     N = g.N
-    stream = torch.cuda.current_stream()
     gen = torch.Generator(device="cuda")
     gen.manual_seed(workloads.CONFIGS[args.workload]["seed"])
-    nsteps = args.steps + args.warmup
-    dens = torch.randn((nsteps, 2, N), dtype=torch.float64, device="cuda", generator=gen)
-    out = torch.empty((2, N), dtype=torch.float64, device="cuda")
-    ops = (sbie.SBIE_OP_S, sbie.SBIE_OP_D)
+    dens = torch.randn((args.steps + args.warmup, 2, N), dtype=torch.float64, device="cuda", generator=gen)
 
-    for k in range(args.warmup):
-        for o in range(2):
-            g.apply(ops[o], dens[k, o], precision=prec, out=out[o], timing=True)
-    g.sync()
-    g.timing()  # discard warm-up timings
-
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(2 * args.steps)]
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for k in range(args.steps):
-        for o in range(2):
-            e = ev[2 * k + o]
-            e[0].record(stream)
-            g.apply(ops[o], dens[args.warmup + k, o], precision=prec, out=out[o], timing=True)
-            e[1].record(stream)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    g.sync()
-    tim = g.timing()
-
-    lat = np.array([e[0].elapsed_time(e[1]) for e in ev])
-    applies = 2 * args.steps
-    value = applies / elapsed
-    far_pairs = tim.far_pairs
-    far_ms = tim.far_kernel_ms
-    flops_per_launch = 0.5 * (FLOPS_PER_PAIR[0] + FLOPS_PER_PAIR[1]) * far_pairs
-    achieved_tflops = flops_per_launch / (far_ms * 1e-3) / 1e12
-    peak = PEAK_TFLOPS[args.precision]
+    main_run = run(g, dens, args.steps, args.warmup, args.precision)
     res = {
         "metric": "S/D operator applies/sec and pair-interactions/sec at 512 spheroids; p50/p99",
-        "value": value,
+        "value": main_run["applies_per_s"],
         "unit": "applies/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "ms_per_step": 1e3 * main_run["elapsed_s"] / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "dtype": "f32+f64" if args.precision == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": f"{M} polydisperse prolate/oblate spheroids (RSA, volume fraction 0.25, "
                                f"min gap 0.02), p={p}, N={N} nodes, S and D, nrhs=1, "
                                f"precision={args.precision}",
                    "spheroids": M, "p": p, "nodes": N, "near_pairs": g.num_near_pairs,
-                   "far_pairs_per_apply": far_pairs},
-        "pair_interactions_per_s": far_pairs / (far_ms * 1e-3),
-        "effective_all_pairs_per_s": float(N) * N / (np.mean(lat) * 1e-3),
-        "near_evals_per_s": tim.near_evals / (tim.near_ms * 1e-3) if tim.near_ms > 0 else None,
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "mean": float(np.mean(lat))},
-        "part_ms": {"prep": tim.prep_ms, "transform_self": tim.transform_ms, "near": tim.near_ms,
-                    "far_kernel": far_ms, "assemble": tim.assemble_ms, "apply_total": tim.total_ms},
+                   "far_pairs_per_apply": main_run["far_pairs"]},
+        "pair_interactions_per_s": main_run["pair_interactions_per_s"],
+        "effective_all_pairs_per_s": main_run["effective_all_pairs_per_s"],
+        "near_evals_per_s": main_run["near_evals_per_s"],
+        "latency_ms": main_run["latency_ms"],
+        "part_ms": main_run["part_ms"],
         "setup_s": setup_s,
-        "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved_tflops / peak, "traffic": None,
-                     "kernel": "k_far_f64 (S and D alternating)" if args.precision == "fp64" else "k_far_f32",
-                     "flops_per_launch": flops_per_launch},
+        "roofline": main_run["roofline"],
     }
+    if not args.no_secondary:
+        other = "fp64" if args.precision == "mixed" else "mixed"
+        sec = run(g, dens, max(4, args.steps // 2), 1, other)
+        res[f"{other}_path"] = {k: sec[k] for k in ("applies_per_s", "pair_interactions_per_s", "latency_ms",
+                                                    "part_ms")}
+        res[f"{other}_path"]["roofline_frac"] = sec["roofline"]["frac"]
     if not args.no_cpu_baseline:
         d = dens[0].cpu().numpy()
         res["cpu_baseline"] = cpu_baseline(geom, p, d[0], d[1], N, args.cpu_sample)

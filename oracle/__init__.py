@@ -62,6 +62,12 @@ def lib():
                                    dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int, dp, dp, dp, dp]
         L.orc_eval_exterior.argtypes = [dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                         dp, dp, ctypes.c_int, dp]
+        L.orc_stokes_apply.argtypes = [dp, dp, dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp, dp,
+                                       dp, dp]
+        L.orc_stokes_single.argtypes = [dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp,
+                                        ctypes.c_int, ctypes.c_int, dp]
+        L.orc_single_layer_grad.argtypes = [dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp,
+                                            ctypes.c_int, dp]
         L.orc_set_cf_max_iter.argtypes = [ctypes.c_int]
         L.orc_set_cf_max_iter.restype = None
         L.orc_num_threads.argtypes = []
@@ -205,6 +211,48 @@ def eval_exterior(spheroid, p: int, op: int, density: np.ndarray, pts: np.ndarra
     out = np.zeros(len(pts))
     _check(lib().orc_eval_exterior(_p(c), _p(q), float(spheroid[2]), float(spheroid[3]), int(p), int(op),
                                    _p(dens), _p(pts), len(pts), _p(out)), "eval_exterior")
+    return out
+
+
+def stokes_apply(geom, p: int, density: np.ndarray, eta: float = 1.0, parts: bool = False):
+    """Stokes single layer (viscosity 1) at every node; density [3, N].  With
+    parts=True returns (u, u_self, u_near, u_far), each [3, N]."""
+    c, q, A, C = _geom_arrays(geom)
+    M = len(A)
+    N = M * (p + 1) * (2 * p + 2)
+    dens = _f64(density).reshape(3, N)
+    us, un, uf, u = (np.zeros((3, N)) for _ in range(4))
+    _check(lib().orc_stokes_apply(_p(c), _p(q), _p(A), _p(C), M, int(p), float(eta), _p(dens), _p(us), _p(un),
+                                  _p(uf), _p(u)), "stokes_apply")
+    return (u, us, un, uf) if parts else u
+
+
+def stokes_single(spheroid, p: int, density: np.ndarray, pts=None, interior: bool = False) -> np.ndarray:
+    """One particle's Stokes single layer at exterior points [n, 3], or (pts=None)
+    its self values at its nodes with the exterior or interior gradient limit."""
+    c, q = _f64(spheroid[0]), _f64(spheroid[1])
+    dens = _f64(density).reshape(3, -1)
+    T = (p + 1) * (2 * p + 2)
+    if pts is None:
+        out = np.zeros((T, 3))
+        _check(lib().orc_stokes_single(_p(c), _p(q), float(spheroid[2]), float(spheroid[3]), int(p), _p(dens), None,
+                                       0, int(interior), _p(out)), "stokes_single")
+        return out
+    pts = _f64(pts).reshape(-1, 3)
+    out = np.zeros((len(pts), 3))
+    _check(lib().orc_stokes_single(_p(c), _p(q), float(spheroid[2]), float(spheroid[3]), int(p), _p(dens),
+                                   _p(pts), len(pts), int(interior), _p(out)), "stokes_single")
+    return out
+
+
+def single_layer_grad(spheroid, p: int, density: np.ndarray, pts) -> np.ndarray:
+    """Value and lab gradient of one particle's S expansion at exterior points: [n, 4]."""
+    c, q = _f64(spheroid[0]), _f64(spheroid[1])
+    dens = _f64(density)
+    pts = _f64(pts).reshape(-1, 3)
+    out = np.zeros((len(pts), 4))
+    _check(lib().orc_single_layer_grad(_p(c), _p(q), float(spheroid[2]), float(spheroid[3]), int(p), _p(dens),
+                                       _p(pts), len(pts), _p(out)), "single_layer_grad")
     return out
 
 

@@ -926,6 +926,300 @@ int orc_eval_exterior(const double* centre, const double* quat, double A,
   return rc;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Gradients of single-layer expansions and the Stokes single layer through  */
+/* Laplace single layers (Section 4.3, Eq. (stokes)).                        */
+/* ------------------------------------------------------------------------ */
+
+/* Values and lab-frame gradients of nset single-particle expansions
+   Phi_s = sum_l E[s][l] R_n^|m|(u) Y_l(v, phi) at the point (u, v, phi) of
+   particle pt, with R = Q_n^m(z)/Q_n^m(z0) (exterior) or P_n^m(z)/P_n^m(z0)
+   (interior).  The gradient is the chain rule for the orthogonal coordinates
+   of Table 1: grad = sum_q (dx/dq) |dx/dq|^-2 dPhi/dq in the body frame,
+   then rotated to the lab frame.  dY/dv uses the derivative identity of
+   Section 2.3 on the cut, (1-v^2) P_n^m' = (m-n-1) P_{n+1}^m + (n+1) v P_n^m. */
+static int expansion_grad(const particle* pt, int p, int nset, const double* E, double u,
+                          double v, double phi, int interior, double* val, double* grad) {
+  int K = (p + 1) * (p + 1), N = p + 1;
+  int nh = (p + 2) * (p + 3) / 2;
+  double* Pf = (double*)malloc(sizeof(double) * nh);
+  double complex* buf = (double complex*)malloc(sizeof(double complex) * 8 * (N + 2));
+  double complex *P = buf, *Q = buf + (N + 2), *dP = buf + 2 * (N + 2), *dQ = buf + 3 * (N + 2);
+  double complex *P0 = buf + 4 * (N + 2), *Q0 = buf + 5 * (N + 2), *dP0 = buf + 6 * (N + 2),
+                 *dQ0 = buf + 7 * (N + 2);
+  ferrers_all(v, p + 1, Pf);
+  double dzdu_re = 1.0, dzdu_im = 0.0;
+  if (pt->oblate) { dzdu_re = 0.0; dzdu_im = 1.0; }
+  double complex dzdu = dzdu_re + dzdu_im * I;
+  double Fu[4], Fv[4], Fp[4];
+  for (int s = 0; s < nset; ++s) { val[s] = 0.0; Fu[s] = Fv[s] = Fp[s] = 0.0; }
+  int rc = 0;
+  for (int m = 0; m <= p && !rc; ++m) {
+    rc = legendre_offcut(pt->oblate, u, m, N, P, Q, dP, dQ);
+    if (!rc) rc = legendre_offcut(pt->oblate, pt->u0, m, N, P0, Q0, dP0, dQ0);
+    if (rc) break;
+    for (int n = m; n <= p; ++n) {
+      double complex F = interior ? P[n] : Q[n], F0 = interior ? P0[n] : Q0[n];
+      double complex dF = interior ? dP[n] : dQ[n];
+      double R = creal(F / F0), dR = creal(dzdu * dF / F0);
+      double Nnm = sqrt((2.0 * n + 1.0) / (4.0 * PI) * factorial(n - m) / factorial(n + m));
+      if (m > 0) Nnm *= sqrt(2.0);
+      double Pn = Pf[n * (n + 1) / 2 + m], Pn1 = Pf[(n + 1) * (n + 2) / 2 + m];
+      double dPn = ((m - n - 1) * Pn1 + (n + 1) * v * Pn) / (1.0 - v * v);
+      double cphi = cos(m * phi), sphi = sin(m * phi);
+      for (int s = 0; s < nset; ++s) {
+        const double* Es = E + (size_t)s * K;
+        double ec = Es[n * n + n + m], es = (m > 0) ? Es[n * n + n - m] : 0.0;
+        double ang = ec * cphi + es * sphi;          /* angular part of +m and -m terms */
+        double dang = m * (es * cphi - ec * sphi);   /* its phi derivative */
+        val[s] += Nnm * Pn * R * ang;
+        Fu[s] += Nnm * Pn * dR * ang;
+        Fv[s] += Nnm * dPn * R * ang;
+        Fp[s] += Nnm * Pn * R * dang;
+      }
+    }
+  }
+  free(Pf);
+  free(buf);
+  if (rc) return rc;
+  double a = pt->a;
+  double su = pt->oblate ? sqrt(u * u + 1.0) : sqrt(u * u - 1.0);
+  double sv = sqrt(1.0 - v * v), cph = cos(phi), sph = sin(phi);
+  double xu[3] = {a * u / su * sv * cph, a * u / su * sv * sph, a * v};
+  double xv[3] = {-a * su * v / sv * cph, -a * su * v / sv * sph, a * u};
+  double xp[3] = {-a * su * sv * sph, a * su * sv * cph, 0.0};
+  double hu2 = xu[0] * xu[0] + xu[1] * xu[1] + xu[2] * xu[2];
+  double hv2 = xv[0] * xv[0] + xv[1] * xv[1] + xv[2] * xv[2];
+  double hp2 = xp[0] * xp[0] + xp[1] * xp[1] + xp[2] * xp[2];
+  for (int s = 0; s < nset; ++s) {
+    double gb[3];
+    for (int c = 0; c < 3; ++c) gb[c] = xu[c] * Fu[s] / hu2 + xv[c] * Fv[s] / hv2 + xp[c] * Fp[s] / hp2;
+    for (int r = 0; r < 3; ++r)
+      grad[3 * s + r] = pt->R[3 * r] * gb[0] + pt->R[3 * r + 1] * gb[1] + pt->R[3 * r + 2] * gb[2];
+  }
+  return ORC_OK;
+}
+
+/* Single-layer exterior coefficients E = lamS * T[w f] of one particle for a
+   nodal density f (modified basis of Section 3.2). */
+static int single_layer_coefficients(const geometry* g, int i, const double* f, double* E) {
+  const particle* pt = &g->pt[i];
+  int p = g->p, Nphi = 2 * p + 2, K = g->K, Kh = g->Kh;
+  double* wf = (double*)malloc(sizeof(double) * g->T);
+  double* lam = (double*)malloc(sizeof(double) * Kh);
+  int rc = spectra(pt, p, NULL, NULL, NULL, lam, NULL);
+  if (rc) { free(wf); free(lam); return rc; }
+  double sgn = pt->oblate ? 1.0 : -1.0;
+  for (int j = 0; j <= p; ++j)
+    for (int k = 0; k < Nphi; ++k)
+      wf[j * Nphi + k] = sqrt(pt->u0 * pt->u0 + sgn * g->gx[j] * g->gx[j]) * f[j * Nphi + k];
+  forward_transform(p, g->gx, g->gw, wf, E);
+  for (int n = 0; n <= p; ++n)
+    for (int m = -n; m <= n; ++m) E[n * n + n + m] *= lam[n * (n + 1) / 2 + abs(m)];
+  free(wf); free(lam);
+  return ORC_OK;
+}
+
+/* The four single-layer expansions of particle i used by Eq. (stokes): the
+   three density components and rho_i = (y - c_i).sigma (origin at the source
+   centre).  density is [3][N]; E4 is [4][K]. */
+static int stokes_coefficients(const geometry* g, int i, const double* density, double* E4) {
+  int T = g->T, K = g->K;
+  size_t N = (size_t)g->N;
+  double* f = (double*)malloc(sizeof(double) * T);
+  int rc = 0;
+  for (int s = 0; s < 4 && !rc; ++s) {
+    for (int t = 0; t < T; ++t) {
+      size_t gi = (size_t)i * T + t;
+      if (s < 3) {
+        f[t] = density[s * N + gi];
+      } else {
+        double r = 0.0;
+        for (int c = 0; c < 3; ++c) r += (g->xyz[3 * gi + c] - g->pt[i].c[c]) * density[c * N + gi];
+        f[t] = r;
+      }
+    }
+    rc = single_layer_coefficients(g, i, f, E4 + (size_t)s * K);
+  }
+  free(f);
+  return rc;
+}
+
+/* Eq. (stokes) with viscosity 1 and origin c_i:
+   u_k = 1/2 { S[sigma_k] - sum_j (x - c_i)_j d_k S[sigma_j] + d_k S[rho_i] } */
+static void stokes_combine(const particle* pt, const double x[3], const double* val,
+                           const double* grad, double out[3]) {
+  for (int k = 0; k < 3; ++k) {
+    double s = val[k] + grad[3 * 3 + k];
+    for (int j = 0; j < 3; ++j) s -= (x[j] - pt->c[j]) * grad[3 * j + k];
+    out[k] = 0.5 * s;
+  }
+}
+
+int orc_stokes_apply(const double* centres, const double* quats, const double* A,
+                     const double* C, int M, int p, double eta, const double* density,
+                     double* u_self, double* u_near, double* u_far, double* u) {
+  geometry g;
+  int rc = build_geometry(centres, quats, A, C, M, p, eta, &g);
+  if (rc) return rc;
+  int T = g.T, K = g.K, Nphi = 2 * p + 2;
+  size_t N = (size_t)g.N;
+  double* E4 = (double*)malloc(sizeof(double) * 4 * K * (size_t)M);
+  double* us = (double*)calloc(3 * N, sizeof(double));
+  double* un = (double*)calloc(3 * N, sizeof(double));
+  double* uf = (double*)calloc(3 * N, sizeof(double));
+  int err = 0;
+#pragma omp parallel for schedule(dynamic)
+  for (int i = 0; i < M; ++i) {
+    int r = stokes_coefficients(&g, i, density, E4 + (size_t)i * 4 * K);
+    if (r) {
+#pragma omp atomic write
+      err = r;
+    }
+  }
+  if (err) rc = err;
+  /* self: the exterior-limit expansions at the particle's own nodes */
+#pragma omp parallel for schedule(dynamic)
+  for (int i = 0; i < M; ++i) {
+    if (rc) continue;
+    for (int t = 0; t < T; ++t) {
+      int jv = t / Nphi, kp = t - jv * Nphi;
+      size_t gi = (size_t)i * T + t;
+      double val[4], grad[12], o[3];
+      int r = expansion_grad(&g.pt[i], p, 4, E4 + (size_t)i * 4 * K, g.pt[i].u0, g.gx[jv],
+                             2.0 * PI * kp / Nphi, 0, val, grad);
+      if (r) {
+#pragma omp atomic write
+        err = r;
+        continue;
+      }
+      stokes_combine(&g.pt[i], g.xyz + 3 * gi, val, grad, o);
+      for (int k = 0; k < 3; ++k) us[k * N + gi] = o[k];
+    }
+  }
+  /* near: neighbours' exterior expansions at the target nodes */
+#pragma omp parallel for schedule(dynamic)
+  for (int j = 0; j < M; ++j) {
+    if (rc) continue;
+    for (int i = 0; i < M; ++i) {
+      if (!g.near[(size_t)i * M + j]) continue;
+      for (int t = 0; t < T; ++t) {
+        size_t gt = (size_t)j * T + t;
+        double xb[3], uu, vv, ph, val[4], grad[12], o[3];
+        lab_to_body(&g.pt[i], g.xyz + 3 * gt, xb);
+        body_to_spheroidal(&g.pt[i], xb, &uu, &vv, &ph);
+        int r = expansion_grad(&g.pt[i], p, 4, E4 + (size_t)i * 4 * K, uu, vv, ph, 0, val, grad);
+        if (r) {
+#pragma omp atomic write
+          err = r;
+          continue;
+        }
+        stokes_combine(&g.pt[i], g.xyz + 3 * gt, val, grad, o);
+        for (int k = 0; k < 3; ++k) un[k * N + gt] += o[k];
+      }
+    }
+  }
+  if (err) rc = err;
+  /* far: the Stokeslet (1/8pi)(I/r + r r^T/r^3) by smooth quadrature */
+#pragma omp parallel for schedule(dynamic)
+  for (int j = 0; j < M; ++j) {
+    if (rc) continue;
+    for (int t = 0; t < T; ++t) {
+      size_t gt = (size_t)j * T + t;
+      const double* x = g.xyz + 3 * gt;
+      double sum[3] = {0, 0, 0}, comp[3] = {0, 0, 0};
+      for (int i = 0; i < M; ++i) {
+        if (i == j || g.near[(size_t)i * M + j]) continue;
+        for (int q = 0; q < T; ++q) {
+          size_t gs = (size_t)i * T + q;
+          const double* y = g.xyz + 3 * gs;
+          double d[3] = {x[0] - y[0], x[1] - y[1], x[2] - y[2]};
+          double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2], r = sqrt(r2);
+          double sg[3] = {density[gs], density[N + gs], density[2 * N + gs]};
+          double dots = d[0] * sg[0] + d[1] * sg[1] + d[2] * sg[2];
+          for (int k = 0; k < 3; ++k) {
+            double term = g.W[gs] * (sg[k] / r + d[k] * dots / (r2 * r)) / (8.0 * PI);
+            double ts = sum[k] + term;
+            if (fabs(sum[k]) >= fabs(term)) comp[k] += (sum[k] - ts) + term;
+            else comp[k] += (term - ts) + sum[k];
+            sum[k] = ts;
+          }
+        }
+      }
+      for (int k = 0; k < 3; ++k) uf[k * N + gt] = sum[k] + comp[k];
+    }
+  }
+  if (!rc) {
+    for (size_t q = 0; q < 3 * N; ++q) {
+      if (u_self) u_self[q] = us[q];
+      if (u_near) u_near[q] = un[q];
+      if (u_far) u_far[q] = uf[q];
+      u[q] = us[q] + un[q] + uf[q];
+    }
+  }
+  free(E4); free(us); free(un); free(uf);
+  free_geometry(&g);
+  return rc;
+}
+
+/* One particle's Stokes single layer (near-field formula) at exterior points,
+   or its self values at its own nodes with the exterior (interior = 0) or
+   interior (interior = 1) limit of the gradients, for the pins.
+   density [3][T]; out [npts][3] (pts == NULL: the T nodes). */
+int orc_stokes_single(const double* centre, const double* quat, double A, double C, int p,
+                      const double* density, const double* pts, int npts, int interior,
+                      double* out) {
+  geometry g;
+  int rc = build_geometry(centre, quat, &A, &C, 1, p, 1.0, &g);
+  if (rc) return rc;
+  int K = g.K, Nphi = 2 * p + 2;
+  double* E4 = (double*)malloc(sizeof(double) * 4 * K);
+  rc = stokes_coefficients(&g, 0, density, E4);
+  int n = pts ? npts : g.T;
+  for (int t = 0; t < n && !rc; ++t) {
+    double x[3], uu, vv, ph, val[4], grad[12];
+    if (pts) {
+      double xb[3];
+      for (int c = 0; c < 3; ++c) x[c] = pts[3 * t + c];
+      lab_to_body(&g.pt[0], x, xb);
+      body_to_spheroidal(&g.pt[0], xb, &uu, &vv, &ph);
+    } else {
+      int jv = t / Nphi, kp = t - jv * Nphi;
+      for (int c = 0; c < 3; ++c) x[c] = g.xyz[3 * t + c];
+      uu = g.pt[0].u0;
+      vv = g.gx[jv];
+      ph = 2.0 * PI * kp / Nphi;
+    }
+    rc = expansion_grad(&g.pt[0], p, 4, E4, uu, vv, ph, interior, val, grad);
+    if (!rc) stokes_combine(&g.pt[0], x, val, grad, out + 3 * t);
+  }
+  free(E4);
+  free_geometry(&g);
+  return rc;
+}
+
+/* Value and lab gradient of one particle's single-layer expansion of a nodal
+   density at exterior points (pins of the chain rule): out [npts][4]. */
+int orc_single_layer_grad(const double* centre, const double* quat, double A, double C, int p,
+                          const double* density, const double* pts, int npts, double* out) {
+  geometry g;
+  int rc = build_geometry(centre, quat, &A, &C, 1, p, 1.0, &g);
+  if (rc) return rc;
+  double* E = (double*)malloc(sizeof(double) * g.K);
+  rc = single_layer_coefficients(&g, 0, density, E);
+  for (int t = 0; t < npts && !rc; ++t) {
+    double xb[3], uu, vv, ph, val, grad[3];
+    lab_to_body(&g.pt[0], pts + 3 * t, xb);
+    body_to_spheroidal(&g.pt[0], xb, &uu, &vv, &ph);
+    rc = expansion_grad(&g.pt[0], p, 1, E, uu, vv, ph, 0, &val, grad);
+    out[4 * t] = val;
+    for (int c = 0; c < 3; ++c) out[4 * t + 1 + c] = grad[c];
+  }
+  free(E);
+  free_geometry(&g);
+  return rc;
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
   extern int omp_get_max_threads(void);

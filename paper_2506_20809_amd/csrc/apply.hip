@@ -231,10 +231,12 @@ __global__ __launch_bounds__(64) void k_near_f64(
     // margin, the same for the whole wave
     int steps = (int)ceil(20.1 / log(u + sw)) + 8;
     for (int off = 32; off >= 1; off >>= 1) steps = max(steps, __shfl_xor(steps, off, 64));
+    steps = __builtin_amdgcn_readfirstlane(steps);
     if (steps > 100000) {
       steps = 100000;
       bad |= kStatNumeric;
     }
+    steps = (steps + 7) & ~7;  // whole chunks of eight steps
     const int L = N + steps;
 
     double pmm_u = 1.0;                        // P_m^m(u) (real form)
@@ -275,14 +277,18 @@ __global__ __launch_bounds__(64) void k_near_f64(
       // rescaled by 2^-600 whenever it grows past 2^600.
       double qhi = 0.0, qcur = 1.0;  // R_{n+1}, R_n at n = L
       {
-        double c2n1 = (double)(2 * L + 1), ca = (double)(L - m + 1), cb = (double)(L + m + 1);
-        for (int n = L; n > N; --n) {
-          const double qn = fma(c2n1 * u, qcur, sgn * (ca * cb) * qhi);
-          qhi = qcur;
-          qcur = qn;
-          c2n1 -= 2.0;
-          ca -= 1.0;
-          cb -= 1.0;
+        double c2n1 = (double)(2 * L + 1), ca = sgn * (double)(L - m + 1), cb = (double)(L + m + 1);
+        const double dca = -sgn;
+        for (int n = L; n > N; n -= 8) {
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const double qn = fma(c2n1 * u, qcur, (ca * cb) * qhi);
+            qhi = qcur;
+            qcur = qn;
+            c2n1 -= 2.0;
+            ca += dca;
+            cb -= 1.0;
+          }
           if (fabs(qcur) > 0x1p600) {
             qcur *= 0x1p-600;
             qhi *= 0x1p-600;

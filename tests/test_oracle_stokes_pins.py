@@ -1,0 +1,139 @@
+"""Pins of the oracle's Stokes single layer (Section 4.3, Eq. (stokes)) on the CPU.
+
+References: central finite differences of the (already pinned) exterior
+expansions, brute-force oversampled quadrature of the Stokeslet, continuity of
+the Stokes single layer across the surface, and the cancellation of the
+gradient jump between the exterior and interior limits.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from tests import _brute as B
+from tests.test_oracle_pins import SHAPES, _exterior_points, _one
+
+
+def _band(p, deg, rng, w, V, PH, decay=0.3):
+    c = rng.standard_normal((deg + 1) ** 2) * np.exp(-decay * np.repeat(np.arange(deg + 1), 2 * np.arange(deg + 1) + 1))
+    return c, (c @ B.real_basis(deg, V, PH)) / w
+
+
+@pytest.mark.parametrize("A,C", SHAPES[:4])
+def test_single_layer_gradient_vs_finite_differences(A, C):
+    """Chain-rule gradient of the exterior expansion against central differences."""
+    sph = _one(A, C, 11)
+    p = 10
+    oblate, a, u0 = B.spheroid_params(A, C)
+    V, PH = B.node_grid(p)
+    w = np.sqrt(u0 * u0 + (1 if oblate else -1) * V * V)
+    rng = np.random.default_rng(3)
+    _, dens = _band(p, p, rng, w, V, PH)
+    pts = _exterior_points(sph, [0.1, 0.3, 1.0], rng)
+    out = oracle.single_layer_grad(sph, p, dens, pts)
+    h = 1e-5
+    for t in range(len(pts)):
+        fd = []
+        for c in range(3):
+            e = np.zeros(3)
+            e[c] = h
+            fp = oracle.single_layer_grad(sph, p, dens, [pts[t] + e])[0, 0]
+            fm = oracle.single_layer_grad(sph, p, dens, [pts[t] - e])[0, 0]
+            fd.append((fp - fm) / (2 * h))
+        assert np.max(np.abs(out[t, 1:] - fd)) < 1e-8 * max(1.0, np.max(np.abs(fd)))
+
+
+@pytest.mark.parametrize("A,C", SHAPES[:4])
+def test_stokes_single_layer_vs_bruteforce(A, C):
+    """Eq. (stokes) through the analytic Laplace expansions against oversampled
+    quadrature of the Stokeslet (1/8pi)(I/r + r r^T/r^3) at exterior points."""
+    sph = _one(A, C, 21)
+    c0, q0 = sph[0], sph[1]
+    p = 10
+    oblate, a, u0 = B.spheroid_params(A, C)
+    sgn = 1 if oblate else -1
+    V, PH = B.node_grid(p)
+    w = np.sqrt(u0 * u0 + sgn * V * V)
+    rng = np.random.default_rng(5)
+    coefs, dens = [], []
+    for _ in range(3):
+        cf, d = _band(p, p - 1, rng, w, V, PH)
+        coefs.append(cf)
+        dens.append(d)
+    pts = _exterior_points(sph, [0.2, 0.5, 1.0, 2.5], rng)
+    u = oracle.stokes_single(sph, p, np.stack(dens), pts)
+    Xf, Nf, Wf, Vf, PHf = B.fine_surface(A, C, c0, q0, 260, 520)
+    wf = np.sqrt(u0 * u0 + sgn * Vf * Vf)
+    sf = np.stack([(cf @ B.real_basis(p - 1, Vf, PHf)) / wf for cf in coefs])
+    ref = np.zeros((len(pts), 3))
+    for t, x in enumerate(pts):
+        d = x[None, :] - Xf
+        r2 = np.sum(d * d, axis=1)
+        r = np.sqrt(r2)
+        dots = np.sum(d * sf.T, axis=1)
+        for k in range(3):
+            ref[t, k] = np.sum(Wf * (sf[k] / r + d[:, k] * dots / (r2 * r))) / (8 * np.pi)
+    assert np.max(np.abs(u - ref)) < 1e-9 * np.max(np.abs(ref)), (u, ref)
+
+
+@pytest.mark.parametrize("A,C", SHAPES[:4])
+def test_stokes_self_limits_agree_and_continuity(A, C):
+    """The gradient jump -sigma nu cancels in Eq. (stokes): exterior and interior
+    limits give the same surface values, which are the limit of the exterior
+    values approaching the surface."""
+    sph = _one(A, C, 31)
+    p = 8
+    oblate, a, u0 = B.spheroid_params(A, C)
+    V, PH = B.node_grid(p)
+    w = np.sqrt(u0 * u0 + (1 if oblate else -1) * V * V)
+    rng = np.random.default_rng(9)
+    dens = np.stack([_band(p, p - 1, rng, w, V, PH)[1] for _ in range(3)])
+    ext = oracle.stokes_single(sph, p, dens, None, interior=False)
+    itr = oracle.stokes_single(sph, p, dens, None, interior=True)
+    assert np.max(np.abs(ext - itr)) < 1e-11 * np.max(np.abs(ext))
+    geom = {"centers": sph[0][None], "quats": sph[1][None], "A": np.array([A]), "C": np.array([C])}
+    xyz, nrm, _ = oracle.grid(geom, p)
+    sel = np.arange(0, len(xyz), 5)
+    for h in (1e-4, 1e-5):
+        near = oracle.stokes_single(sph, p, dens, xyz[sel] + h * nrm[sel])
+        assert np.max(np.abs(near - ext[sel])) < 50 * h * np.max(np.abs(ext))
+
+
+def test_stokes_whole_apply_two_prolates():
+    """Self, near and far pieces on the two-prolate workload; near against brute force."""
+    import workloads
+
+    g = workloads.geometry("c1")
+    p = 8
+    T = (p + 1) * (2 * p + 2)
+    N = 2 * T
+    rng = np.random.default_rng(2)
+    V, PH = B.node_grid(p)
+    dens = np.zeros((3, N))
+    coefs = np.zeros((2, 3, p * p))
+    for i in range(2):
+        A, C = g["A"][i], g["C"][i]
+        oblate, a, u0 = B.spheroid_params(A, C)
+        w = np.sqrt(u0 * u0 - V * V)
+        for k in range(3):
+            cf, d = _band(p, p - 1, rng, w, V, PH)
+            coefs[i, k] = cf
+            dens[k, i * T:(i + 1) * T] = d
+    u, us, un, uf = oracle.stokes_apply(g, p, dens, parts=True)
+    assert np.all(uf == 0)
+    assert np.max(np.abs(u - us - un)) < 1e-14
+    xyz, _, _ = oracle.grid(g, p)
+    for j, i in [(0, 1), (1, 0)]:
+        A, C = g["A"][i], g["C"][i]
+        oblate, a, u0 = B.spheroid_params(A, C)
+        Xf, Nf, Wf, Vf, PHf = B.fine_surface(A, C, g["centers"][i], g["quats"][i], 260, 520)
+        wf = np.sqrt(u0 * u0 - Vf * Vf)
+        sf = np.stack([(coefs[i, k] @ B.real_basis(p - 1, Vf, PHf)) / wf for k in range(3)])
+        sel = np.arange(0, T, 9)
+        for t in sel:
+            x = xyz[j * T + t]
+            d = x[None, :] - Xf
+            r2 = np.sum(d * d, axis=1)
+            r = np.sqrt(r2)
+            dots = np.sum(d * sf.T, axis=1)
+            ref = [np.sum(Wf * (sf[k] / r + d[:, k] * dots / (r2 * r))) / (8 * np.pi) for k in range(3)]
+            assert np.max(np.abs(un[:, j * T + t] - ref)) < 1e-9 * max(1e-3, np.max(np.abs(un))), t

@@ -99,6 +99,8 @@ typedef struct {
 /* Create a context on HIP device `device` (a stream is created for synchronous
    calls).  *out receives the handle. */
 sbie_status sbie_ctx_create(int device, sbie_ctx** out);
+/* Release a context.  Geometries created on it stay valid: while any is live
+   the context is only marked, and it is released with the last of them. */
 void sbie_ctx_destroy(sbie_ctx* ctx);
 
 /* Build a geometry (Algorithm 1 setup: nodes, weights, normals, spectra of

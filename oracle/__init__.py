@@ -64,6 +64,8 @@ def lib():
                                         dp, dp, ctypes.c_int, dp]
         L.orc_stokes_apply.argtypes = [dp, dp, dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp, dp,
                                        dp, dp]
+        L.orc_stokes_apply_at.argtypes = [dp, dp, dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp,
+                                          ctypes.POINTER(ctypes.c_int64), ctypes.c_int, dp, dp, dp, dp]
         L.orc_stokes_single.argtypes = [dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp,
                                         ctypes.c_int, ctypes.c_int, dp]
         L.orc_single_layer_grad.argtypes = [dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp,
@@ -225,6 +227,21 @@ def stokes_apply(geom, p: int, density: np.ndarray, eta: float = 1.0, parts: boo
     _check(lib().orc_stokes_apply(_p(c), _p(q), _p(A), _p(C), M, int(p), float(eta), _p(dens), _p(us), _p(un),
                                   _p(uf), _p(u)), "stokes_apply")
     return (u, us, un, uf) if parts else u
+
+
+def stokes_apply_at(geom, p: int, density: np.ndarray, targets, eta: float = 1.0):
+    """Eq. (stokes) at selected node indices: (u, u_self, u_near, u_far), each [3, len(targets)]."""
+    c, q, A, C = _geom_arrays(geom)
+    M = len(A)
+    N = M * (p + 1) * (2 * p + 2)
+    dens = _f64(density).reshape(3, N)
+    tg = np.ascontiguousarray(targets, dtype=np.int64)
+    n = len(tg)
+    us, un, uf, u = (np.zeros((3, n)) for _ in range(4))
+    _check(lib().orc_stokes_apply_at(_p(c), _p(q), _p(A), _p(C), M, int(p), float(eta), _p(dens),
+                                     tg.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n, _p(us), _p(un),
+                                     _p(uf), _p(u)), "stokes_apply_at")
+    return u, us, un, uf
 
 
 def stokes_single(spheroid, p: int, density: np.ndarray, pts=None, interior: bool = False) -> np.ndarray:

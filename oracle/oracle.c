@@ -1056,108 +1056,148 @@ static void stokes_combine(const particle* pt, const double x[3], const double* 
   }
 }
 
+/* Self, near and far parts of Eq. (stokes) at node gt: the exterior-limit
+   expansions of the target's own particle at its node, the neighbours'
+   exterior expansions (ascending source index), and the Stokeslet
+   (1/8pi)(I/r + r r^T/r^3) over the far sources by smooth quadrature,
+   Neumaier-compensated. */
+static int stokes_node(const geometry* g, const double* E4, const double* density, size_t gt,
+                       double us[3], double un[3], double uf[3]) {
+  int M = g->M, T = g->T, K = g->K, p = g->p, Nphi = 2 * p + 2;
+  size_t N = (size_t)g->N;
+  int j = (int)(gt / T), loc = (int)(gt - (size_t)j * T);
+  int jv = loc / Nphi, kp = loc - jv * Nphi;
+  const double* x = g->xyz + 3 * gt;
+  double val[4], grad[12];
+  int rc = expansion_grad(&g->pt[j], p, 4, E4 + (size_t)j * 4 * K, g->pt[j].u0, g->gx[jv],
+                          2.0 * PI * kp / Nphi, 0, val, grad);
+  if (rc) return rc;
+  stokes_combine(&g->pt[j], x, val, grad, us);
+  for (int k = 0; k < 3; ++k) un[k] = 0.0;
+  for (int i = 0; i < M; ++i) {
+    if (!g->near[(size_t)i * M + j]) continue;
+    double xb[3], uu, vv, ph, o[3];
+    lab_to_body(&g->pt[i], x, xb);
+    body_to_spheroidal(&g->pt[i], xb, &uu, &vv, &ph);
+    rc = expansion_grad(&g->pt[i], p, 4, E4 + (size_t)i * 4 * K, uu, vv, ph, 0, val, grad);
+    if (rc) return rc;
+    stokes_combine(&g->pt[i], x, val, grad, o);
+    for (int k = 0; k < 3; ++k) un[k] += o[k];
+  }
+  double sum[3] = {0, 0, 0}, comp[3] = {0, 0, 0};
+  for (int i = 0; i < M; ++i) {
+    if (i == j || g->near[(size_t)i * M + j]) continue;
+    for (int q = 0; q < T; ++q) {
+      size_t gs = (size_t)i * T + q;
+      const double* y = g->xyz + 3 * gs;
+      double d[3] = {x[0] - y[0], x[1] - y[1], x[2] - y[2]};
+      double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2], r = sqrt(r2);
+      double sg[3] = {density[gs], density[N + gs], density[2 * N + gs]};
+      double dots = d[0] * sg[0] + d[1] * sg[1] + d[2] * sg[2];
+      for (int k = 0; k < 3; ++k) {
+        double term = g->W[gs] * (sg[k] / r + d[k] * dots / (r2 * r)) / (8.0 * PI);
+        double ts = sum[k] + term;
+        if (fabs(sum[k]) >= fabs(term)) comp[k] += (sum[k] - ts) + term;
+        else comp[k] += (term - ts) + sum[k];
+        sum[k] = ts;
+      }
+    }
+  }
+  for (int k = 0; k < 3; ++k) uf[k] = sum[k] + comp[k];
+  return ORC_OK;
+}
+
+/* The four expansions of every particle flagged in need (all when need is NULL). */
+static int stokes_all_coefficients(const geometry* g, const double* density, const uint8_t* need,
+                                   double* E4) {
+  int err = 0;
+#pragma omp parallel for schedule(dynamic)
+  for (int i = 0; i < g->M; ++i) {
+    if (need && !need[i]) continue;
+    int r = stokes_coefficients(g, i, density, E4 + (size_t)i * 4 * g->K);
+    if (r) {
+#pragma omp atomic write
+      err = r;
+    }
+  }
+  return err;
+}
+
 int orc_stokes_apply(const double* centres, const double* quats, const double* A,
                      const double* C, int M, int p, double eta, const double* density,
                      double* u_self, double* u_near, double* u_far, double* u) {
   geometry g;
   int rc = build_geometry(centres, quats, A, C, M, p, eta, &g);
   if (rc) return rc;
-  int T = g.T, K = g.K, Nphi = 2 * p + 2;
   size_t N = (size_t)g.N;
-  double* E4 = (double*)malloc(sizeof(double) * 4 * K * (size_t)M);
-  double* us = (double*)calloc(3 * N, sizeof(double));
-  double* un = (double*)calloc(3 * N, sizeof(double));
-  double* uf = (double*)calloc(3 * N, sizeof(double));
+  double* E4 = (double*)malloc(sizeof(double) * 4 * g.K * (size_t)M);
+  rc = stokes_all_coefficients(&g, density, NULL, E4);
   int err = 0;
-#pragma omp parallel for schedule(dynamic)
-  for (int i = 0; i < M; ++i) {
-    int r = stokes_coefficients(&g, i, density, E4 + (size_t)i * 4 * K);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t gt = 0; gt < (int64_t)N; ++gt) {
+    if (rc || err) continue;
+    double us[3], un[3], uf[3];
+    int r = stokes_node(&g, E4, density, (size_t)gt, us, un, uf);
     if (r) {
 #pragma omp atomic write
       err = r;
+      continue;
+    }
+    for (int k = 0; k < 3; ++k) {
+      size_t q = k * N + (size_t)gt;
+      if (u_self) u_self[q] = us[k];
+      if (u_near) u_near[q] = un[k];
+      if (u_far) u_far[q] = uf[k];
+      u[q] = us[k] + un[k] + uf[k];
     }
   }
-  if (err) rc = err;
-  /* self: the exterior-limit expansions at the particle's own nodes */
+  if (!rc) rc = err;
+  free(E4);
+  free_geometry(&g);
+  return rc;
+}
+
+/* Eq. (stokes) at selected node indices only (full-size checks); outputs
+   [3][ntg].  Only the target particles and their near neighbours are expanded. */
+int orc_stokes_apply_at(const double* centres, const double* quats, const double* A,
+                        const double* C, int M, int p, double eta, const double* density,
+                        const int64_t* targets, int ntg, double* out_self, double* out_near,
+                        double* out_far, double* out) {
+  geometry g;
+  int rc = build_geometry(centres, quats, A, C, M, p, eta, &g);
+  if (rc) return rc;
+  int T = g.T;
+  uint8_t* need = (uint8_t*)calloc(M, 1);
+  for (int t = 0; t < ntg; ++t) {
+    if (targets[t] < 0 || targets[t] >= (int64_t)g.N) { free(need); free_geometry(&g); return ORC_E_INVALID; }
+    int j = (int)(targets[t] / T);
+    need[j] = 1;
+    for (int i = 0; i < M; ++i) if (g.near[(size_t)i * M + j]) need[i] = 1;
+  }
+  double* E4 = (double*)calloc((size_t)4 * g.K * M, sizeof(double));
+  rc = stokes_all_coefficients(&g, density, need, E4);
+  int err = 0;
 #pragma omp parallel for schedule(dynamic)
-  for (int i = 0; i < M; ++i) {
-    if (rc) continue;
-    for (int t = 0; t < T; ++t) {
-      int jv = t / Nphi, kp = t - jv * Nphi;
-      size_t gi = (size_t)i * T + t;
-      double val[4], grad[12], o[3];
-      int r = expansion_grad(&g.pt[i], p, 4, E4 + (size_t)i * 4 * K, g.pt[i].u0, g.gx[jv],
-                             2.0 * PI * kp / Nphi, 0, val, grad);
-      if (r) {
+  for (int t = 0; t < ntg; ++t) {
+    if (rc || err) continue;
+    double us[3], un[3], uf[3];
+    int r = stokes_node(&g, E4, density, (size_t)targets[t], us, un, uf);
+    if (r) {
 #pragma omp atomic write
-        err = r;
-        continue;
-      }
-      stokes_combine(&g.pt[i], g.xyz + 3 * gi, val, grad, o);
-      for (int k = 0; k < 3; ++k) us[k * N + gi] = o[k];
+      err = r;
+      continue;
+    }
+    for (int k = 0; k < 3; ++k) {
+      size_t q = (size_t)k * ntg + t;
+      if (out_self) out_self[q] = us[k];
+      if (out_near) out_near[q] = un[k];
+      if (out_far) out_far[q] = uf[k];
+      out[q] = us[k] + un[k] + uf[k];
     }
   }
-  /* near: neighbours' exterior expansions at the target nodes */
-#pragma omp parallel for schedule(dynamic)
-  for (int j = 0; j < M; ++j) {
-    if (rc) continue;
-    for (int i = 0; i < M; ++i) {
-      if (!g.near[(size_t)i * M + j]) continue;
-      for (int t = 0; t < T; ++t) {
-        size_t gt = (size_t)j * T + t;
-        double xb[3], uu, vv, ph, val[4], grad[12], o[3];
-        lab_to_body(&g.pt[i], g.xyz + 3 * gt, xb);
-        body_to_spheroidal(&g.pt[i], xb, &uu, &vv, &ph);
-        int r = expansion_grad(&g.pt[i], p, 4, E4 + (size_t)i * 4 * K, uu, vv, ph, 0, val, grad);
-        if (r) {
-#pragma omp atomic write
-          err = r;
-          continue;
-        }
-        stokes_combine(&g.pt[i], g.xyz + 3 * gt, val, grad, o);
-        for (int k = 0; k < 3; ++k) un[k * N + gt] += o[k];
-      }
-    }
-  }
-  if (err) rc = err;
-  /* far: the Stokeslet (1/8pi)(I/r + r r^T/r^3) by smooth quadrature */
-#pragma omp parallel for schedule(dynamic)
-  for (int j = 0; j < M; ++j) {
-    if (rc) continue;
-    for (int t = 0; t < T; ++t) {
-      size_t gt = (size_t)j * T + t;
-      const double* x = g.xyz + 3 * gt;
-      double sum[3] = {0, 0, 0}, comp[3] = {0, 0, 0};
-      for (int i = 0; i < M; ++i) {
-        if (i == j || g.near[(size_t)i * M + j]) continue;
-        for (int q = 0; q < T; ++q) {
-          size_t gs = (size_t)i * T + q;
-          const double* y = g.xyz + 3 * gs;
-          double d[3] = {x[0] - y[0], x[1] - y[1], x[2] - y[2]};
-          double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2], r = sqrt(r2);
-          double sg[3] = {density[gs], density[N + gs], density[2 * N + gs]};
-          double dots = d[0] * sg[0] + d[1] * sg[1] + d[2] * sg[2];
-          for (int k = 0; k < 3; ++k) {
-            double term = g.W[gs] * (sg[k] / r + d[k] * dots / (r2 * r)) / (8.0 * PI);
-            double ts = sum[k] + term;
-            if (fabs(sum[k]) >= fabs(term)) comp[k] += (sum[k] - ts) + term;
-            else comp[k] += (term - ts) + sum[k];
-            sum[k] = ts;
-          }
-        }
-      }
-      for (int k = 0; k < 3; ++k) uf[k * N + gt] = sum[k] + comp[k];
-    }
-  }
-  if (!rc) {
-    for (size_t q = 0; q < 3 * N; ++q) {
-      if (u_self) u_self[q] = us[q];
-      if (u_near) u_near[q] = un[q];
-      if (u_far) u_far[q] = uf[q];
-      u[q] = us[q] + un[q] + uf[q];
-    }
-  }
-  free(E4); free(us); free(un); free(uf);
+  if (!rc) rc = err;
+  free(need);
+  free(E4);
   free_geometry(&g);
   return rc;
 }

@@ -591,3 +591,13 @@ sbie_status transform_only(sbie_geom* g, int op, const double* d_dens, double* d
 }
 
 }  // namespace sbie
+
+namespace sbie {
+
+sbie_status gemm(bool mixed, const double* A, int lda, const double* B64, const float* B32, int ldb, double* C,
+                 int ldc, int rows, int cols, int kd, hipStream_t s) {
+  return mixed ? launch_gemm32(A, lda, B32, ldb, C, ldc, rows, cols, kd, s)
+               : launch_gemm(A, lda, B64, ldb, C, ldc, rows, cols, kd, s);
+}
+
+}  // namespace sbie

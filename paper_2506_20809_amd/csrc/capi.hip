@@ -34,6 +34,9 @@ void free_geom(sbie_geom* g) {
   if (!g) return;
   void* ptrs[] = {g->d_part,   g->d_x,       g->d_y,     g->d_z,       g->d_nx,     g->d_ny,     g->d_nz,
                   g->d_w,      g->d_off32,   g->d_gl,    g->d_An,      g->d_Sy,     g->d_An32,   g->d_Sy32,
+                  g->d_Sv,     g->d_Sp,      g->d_Sv32,  g->d_Sp32,    g->d_dlr,    g->d_stk_f,  g->d_stk_c,
+                  g->d_stk_E,  g->d_stk_U,   g->d_stk_src, g->d_stk_part, g->d_stk_self, g->d_stk_near, g->d_stk_io,
+                  g->d_cd,
                   g->d_wS,     g->d_lam,     g->d_ab,    g->d_near_ptr, g->d_near_src, g->d_excl, g->d_status,
                   g->d_f,      g->d_coef,    g->d_cself, g->d_E,       g->d_uself,  g->d_unear,  g->d_src,
                   g->d_partial, g->d_dens,   g->d_out,   g->d_srec32,  g->d_srec64, g->d_fstr32, g->d_fstr64,
@@ -92,6 +95,11 @@ sbie_status sbie_ctx_create(int device, sbie_ctx** out) {
 
 void sbie_ctx_destroy(sbie_ctx* ctx) {
   if (!ctx) return;
+  if (ctx->live_geoms > 0) {
+    // released with its last geometry
+    ctx->closing = true;
+    return;
+  }
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
@@ -167,15 +175,21 @@ sbie_status sbie_geom_create(sbie_ctx* ctx, const double* centers, const double*
     free_geom(g);
     return st;
   }
+  ++ctx->live_geoms;
   *out = g;
   return SBIE_OK;
 }
 
 void sbie_geom_destroy(sbie_geom* g) {
   if (!g) return;
-  (void)hipSetDevice(g->ctx->device);
-  (void)hipStreamSynchronize(g->ctx->stream);
+  sbie_ctx* ctx = g->ctx;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
   free_geom(g);
+  if (--ctx->live_geoms == 0 && ctx->closing) {
+    ctx->closing = false;
+    sbie_ctx_destroy(ctx);
+  }
 }
 
 int64_t sbie_geom_num_nodes(const sbie_geom* g) { return g ? g->N : 0; }
@@ -236,10 +250,6 @@ sbie_status sbie_apply(sbie_geom* g, sbie_op op, sbie_precision prec, int32_t nr
   if (nrhs < 1 || nrhs > 16) return invalid("nrhs must be in [1, 16]");
   if (op == SBIE_OP_STOKES_S && nrhs != 3) return invalid("the Stokes single layer takes nrhs = 3");
   if (!density || !potential) return invalid("density or potential is NULL");
-  if (op == SBIE_OP_STOKES_S) {
-    set_error("the Stokes single layer is not available in this build");
-    return SBIE_E_INVALID;
-  }
   SBIE_HIP(hipSetDevice(g->ctx->device));
   uint32_t parts = flags & SBIE_PARTS_ALL;
   if (parts == 0) parts = SBIE_PARTS_ALL;
@@ -247,6 +257,24 @@ sbie_status sbie_apply(sbie_geom* g, sbie_op op, sbie_precision prec, int32_t nr
   const bool timed = (flags & SBIE_TIMING) != 0;
   hipStream_t s = stream ? (hipStream_t)stream : g->ctx->stream;
   const int64_t N = g->N;
+  if (op == SBIE_OP_STOKES_S) {
+    // the three components of the density in, the three velocity components out
+    const double* din = density;
+    double* dout = potential;
+    if (!devptr) {
+      double* io = nullptr;
+      sbie_status st = stokes_staging(g, &io);
+      if (st != SBIE_OK) return st;
+      SBIE_HIP(hipMemcpyAsync(io, density, sizeof(double) * 3 * N, hipMemcpyHostToDevice, s));
+      din = io;
+      dout = io + 3 * N;
+    }
+    sbie_status st = apply_stokes(g, (int)prec, din, dout, s, parts, timed);
+    if (st != SBIE_OK) return st;
+    if (!devptr) SBIE_HIP(hipMemcpyAsync(potential, dout, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, s));
+    if (!stream || !devptr) return sbie_geom_sync(g, s);
+    return SBIE_OK;
+  }
   for (int r = 0; r < nrhs; ++r) {
     const double* din = density + (size_t)r * N;
     double* dout = potential + (size_t)r * N;

@@ -48,6 +48,8 @@ struct Timing {
 struct sbie_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  int live_geoms = 0;     // geometries created on this context and not yet destroyed
+  bool closing = false;   // sbie_ctx_destroy called while geometries were live
 };
 
 struct sbie_geom {
@@ -73,6 +75,22 @@ struct sbie_geom {
   double* d_Sy = nullptr;         // [K][T] synthesis matrix
   float* d_An32 = nullptr;        // FP32 copies for the mixed path
   float* d_Sy32 = nullptr;
+  double* d_Sv = nullptr;         // [K][T] dY_l/dv at the nodes
+  double* d_Sp = nullptr;         // [K][T] dY_l/dphi at the nodes
+  float* d_Sv32 = nullptr;
+  float* d_Sp32 = nullptr;
+  double* d_dlr = nullptr;        // [M][Kh] d/du (Q(u)/Q(u0)) at u0
+  double* d_cd = nullptr;         // [Kh] sqrt((2n+1)(n+m+1)(n-m+1)/(2n+3)), Ferrers derivative
+  // Stokes single layer work buffers (allocated on the first Stokes apply)
+  double* d_stk_f = nullptr;      // [4M][T] transform inputs (3 components and rho)
+  double* d_stk_c = nullptr;      // [4M][K] coefficients
+  double* d_stk_E = nullptr;      // [2][4M][K] exterior coefficients and their u-derivative form
+  double* d_stk_U = nullptr;      // [4][4M][T] value, d/du, d/dv, d/dphi at the nodes
+  double* d_stk_src = nullptr;    // [N][8] far-field records / [nsplit][3][N] partials follow
+  double* d_stk_part = nullptr;   // [nsplit][3][N]
+  double* d_stk_self = nullptr;   // [3][N]
+  double* d_stk_near = nullptr;   // [3][N]
+  double* d_stk_io = nullptr;     // [2][3][N] staging of host densities and velocities
   double* d_wS = nullptr;         // [M][p+1] sqrt(u0^2 -+ v_j^2)
   double* d_lam = nullptr;        // [M][Kh][4]: D principal value, D exterior, S, 1/Q_n^m(z0)
   double* d_ab = nullptr;         // [Kh][2] normalised Ferrers recurrence coefficients
@@ -128,6 +146,15 @@ sbie_status setup_geometry(sbie_geom* g, hipStream_t s);
 sbie_status apply_laplace(sbie_geom* g, int op, int prec, const double* d_dens, double* d_out,
                           hipStream_t s, uint32_t parts, bool timed);
 sbie_status transform_only(sbie_geom* g, int op, const double* d_dens, double* d_coef, hipStream_t s);
+// C[rows x cols] = A[rows x kd] B[kd x cols] on the matrix cores (FP64, or FP32 with compensated tiles)
+sbie_status gemm(bool mixed, const double* A, int lda, const double* B64, const float* B32, int ldb, double* C,
+                 int ldc, int rows, int cols, int kd, hipStream_t s);
+
+// Stokes single layer (stokes.hip); density and output [3][N]
+sbie_status apply_stokes(sbie_geom* g, int prec, const double* d_dens, double* d_out, hipStream_t s,
+                         uint32_t parts, bool timed);
+// device staging [2][3][N] for host-pointer Stokes applies (allocated once)
+sbie_status stokes_staging(sbie_geom* g, double** io);
 
 // matrix-core far field (far_mfma.hip)
 sbie_status far_records(sbie_geom* g, hipStream_t s);

@@ -76,23 +76,29 @@ __global__ void k_ws(const Particle* __restrict__ part, const double* __restrict
 
 // One thread per node of the reference grid: all real orthonormal harmonics
 // Y_l(v_j, phi_k) (Definition 1 in real form) from the normalised Ferrers
-// recurrence Pb_n^m = a_nm (v Pb_{n-1}^m - b_nm Pb_{n-2}^m).
+// recurrence Pb_n^m = a_nm (v Pb_{n-1}^m - b_nm Pb_{n-2}^m), and their v and
+// phi derivatives.  dPb_n^m/dv follows from the derivative identity of
+// Section 2.3 on the cut, normalised:
+//   (1 - v^2) dPb_n^m/dv = (n+1) v Pb_n^m - sqrt((2n+1)(n+m+1)(n-m+1)/(2n+3)) Pb_{n+1}^m.
 __global__ void k_basis(const double* __restrict__ gl, const double* __restrict__ ab, int p,
-                        double* An, double* Sy, float* An32, float* Sy32) {
+                        double* An, double* Sy, float* An32, float* Sy32, double* Sv, double* Sp,
+                        float* Sv32, float* Sp32) {
   const int Nphi = 2 * p + 2, T = (p + 1) * Nphi, K = (p + 1) * (p + 1);
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= T) return;
   const int j = t / Nphi, k = t - j * Nphi;
   const double v = gl[j];
   const double qw = gl[p + 1 + j] * (2.0 * kPi / Nphi);
-  const double sv = sqrt((1.0 - v) * (1.0 + v));
+  const double omv2 = (1.0 - v) * (1.0 + v);
+  const double sv = sqrt(omv2);
   double pmm = 0.28209479177387814347;  // 1/sqrt(4 pi)
   for (int m = 0; m <= p; ++m) {
     if (m > 0) pmm *= sqrt((2.0 * m + 1.0) / (2.0 * m)) * sv;
     double sm, cm;
     sincospi(2.0 * m * k / Nphi, &sm, &cm);
-    double p2 = 0.0, p1 = pmm;
-    for (int n = m; n <= p; ++n) {
+    const double sq2 = m == 0 ? 1.0 : 1.41421356237309504880;
+    double p2 = 0.0, p1 = pmm, prev = 0.0;
+    for (int n = m; n <= p + 1; ++n) {
       double pn;
       if (n == m) {
         pn = pmm;
@@ -105,14 +111,31 @@ __global__ void k_basis(const double* __restrict__ gl, const double* __restrict_
       if (n > m) {
         p2 = p1;
         p1 = pn;
+        // derivative of degree n-1 from Pb_{n-1} (prev) and Pb_n (pn)
+        const int d = n - 1;
+        const double c = sqrt((2.0 * d + 1.0) * (d + m + 1.0) * (d - m + 1.0) / (2.0 * d + 3.0));
+        const double dp = ((d + 1.0) * v * prev - c * pn) / omv2;
+        if (m == 0) {
+          const int l = d * d + d;
+          Sv[(size_t)l * T + t] = dp;
+          Sp[(size_t)l * T + t] = 0.0;
+        } else {
+          const int lc = d * d + d + m, ls = d * d + d - m;
+          Sv[(size_t)lc * T + t] = sq2 * dp * cm;
+          Sv[(size_t)ls * T + t] = sq2 * dp * sm;
+          Sp[(size_t)lc * T + t] = -m * sq2 * prev * sm;
+          Sp[(size_t)ls * T + t] = m * sq2 * prev * cm;
+        }
       }
+      prev = pn;
+      if (n > p) break;
       if (m == 0) {
         const int l = n * n + n;
         An[(size_t)t * K + l] = qw * pn;
         Sy[(size_t)l * T + t] = pn;
       } else {
-        const double yc = 1.41421356237309504880 * pn * cm;
-        const double ys = 1.41421356237309504880 * pn * sm;
+        const double yc = sq2 * pn * cm;
+        const double ys = sq2 * pn * sm;
         const int lc = n * n + n + m, ls = n * n + n - m;
         An[(size_t)t * K + lc] = qw * yc;
         An[(size_t)t * K + ls] = qw * ys;
@@ -124,6 +147,8 @@ __global__ void k_basis(const double* __restrict__ gl, const double* __restrict_
   for (int l = 0; l < K; ++l) {
     An32[(size_t)t * K + l] = (float)An[(size_t)t * K + l];
     Sy32[(size_t)l * T + t] = (float)Sy[(size_t)l * T + t];
+    Sv32[(size_t)l * T + t] = (float)Sv[(size_t)l * T + t];
+    Sp32[(size_t)l * T + t] = (float)Sp[(size_t)l * T + t];
   }
 }
 
@@ -134,7 +159,9 @@ __global__ void k_basis(const double* __restrict__ gl, const double* __restrict_
 //  1: D exterior limit b P'(z0) Q(z0), used for the near-field expansion
 //  2: S on the surface in the modified basis, b~ P(z0) Q(z0) (Theorem 2)
 //  3: 1 / Q_n^m(z0) (real form for oblates), the normaliser of the exterior ratio
-__global__ void k_spectra(const Particle* __restrict__ part, int M, int p, double* lam,
+//  dlr[i][h] = d/du [Q_n^m(u)/Q_n^m(u0)] at u = u0 (real form for oblates): the
+//  exterior-limit normal-coordinate derivative used by gradients on the surface
+__global__ void k_spectra(const Particle* __restrict__ part, int M, int p, double* lam, double* dlr,
                           unsigned* status) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= M * (p + 1)) return;
@@ -161,6 +188,7 @@ __global__ void k_spectra(const Particle* __restrict__ part, int M, int p, doubl
     o[1] = lp;
     o[2] = ls;
     o[3] = 1.0 / Qv[n];
+    dlr[(size_t)i * Kh + n * (n + 1) / 2 + m] = wdQ[n] / (P.w0 * Qv[n]);
   }
 }
 
@@ -350,15 +378,31 @@ sbie_status setup_geometry(sbie_geom* g, hipStream_t s) {
   SBIE_TRY(dev_alloc(&g->d_An32, (size_t)T * K, &fp));
   SBIE_TRY(dev_alloc(&g->d_Sy32, (size_t)K * T, &fp));
   SBIE_TRY(dev_alloc(&g->d_wS, (size_t)M * (p + 1), &fp));
+  SBIE_TRY(dev_alloc(&g->d_Sv, (size_t)K * T, &fp));
+  SBIE_TRY(dev_alloc(&g->d_Sp, (size_t)K * T, &fp));
+  SBIE_TRY(dev_alloc(&g->d_Sv32, (size_t)K * T, &fp));
+  SBIE_TRY(dev_alloc(&g->d_Sp32, (size_t)K * T, &fp));
   SBIE_TRY(dev_alloc(&g->d_lam, (size_t)M * Kh * 4, &fp));
-  SBIE_TRY(dev_alloc(&g->d_ab, (size_t)Kh * 2, &fp));
+  SBIE_TRY(dev_alloc(&g->d_dlr, (size_t)M * Kh, &fp));
+  // Ferrers recurrence coefficients through degree p+1 (derivatives need Pb_{p+1})
+  const int Kh2 = (p + 2) * (p + 3) / 2;
+  SBIE_TRY(dev_alloc(&g->d_ab, (size_t)Kh2 * 2, &fp));
+  SBIE_TRY(dev_alloc(&g->d_cd, (size_t)Kh, &fp));
+  {
+    std::vector<double> cd(Kh, 0.0);
+    for (int n = 0; n <= p; ++n)
+      for (int m = 0; m <= n; ++m)
+        cd[n * (n + 1) / 2 + m] = std::sqrt((2.0 * n + 1.0) * (n + m + 1.0) * (n - m + 1.0) / (2.0 * n + 3.0));
+    SBIE_HIP(hipMemcpyAsync(g->d_cd, cd.data(), sizeof(double) * Kh, hipMemcpyHostToDevice, s));
+    SBIE_HIP(hipStreamSynchronize(s));
+  }
   SBIE_TRY(dev_alloc(&g->d_status, 1, &fp));
 
   std::vector<double> gl(2 * (p + 1));
   gauss_legendre_host(p + 1, gl.data(), gl.data() + p + 1);
   // normalised Ferrers recurrence coefficients a_nm, b_nm for n >= m+2
-  std::vector<double> ab(2 * Kh, 0.0);
-  for (int n = 0; n <= p; ++n)
+  std::vector<double> ab(2 * Kh2, 0.0);
+  for (int n = 0; n <= p + 1; ++n)
     for (int m = 0; m <= n; ++m) {
       if (n < m + 2) continue;
       const double h = n * (n + 1) / 2 + m;
@@ -378,10 +422,10 @@ sbie_status setup_geometry(sbie_geom* g, hipStream_t s) {
   hipLaunchKernelGGL(k_ws, dim3((M * (p + 1) + B - 1) / B), dim3(B), 0, s, g->d_part, g->d_gl, M, p, g->d_wS);
   SBIE_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_basis, dim3((T + 63) / 64), dim3(64), 0, s, g->d_gl, g->d_ab, p, g->d_An, g->d_Sy,
-                     g->d_An32, g->d_Sy32);
+                     g->d_An32, g->d_Sy32, g->d_Sv, g->d_Sp, g->d_Sv32, g->d_Sp32);
   SBIE_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_spectra, dim3((M * (p + 1) + 63) / 64), dim3(64), 0, s, g->d_part, M, p, g->d_lam,
-                     g->d_status);
+                     g->d_dlr, g->d_status);
   SBIE_HIP(hipGetLastError());
 
   // near/far split

@@ -1,0 +1,575 @@
+// Stokes single layer through Laplace single layers (Section 4.3, Eq. (stokes)),
+// viscosity 1:
+//   u_k = 1/2 { S[sigma_k] - sum_j (x - c)_j d_k S[sigma_j] + d_k S[(y - c).sigma] }
+// The identity holds for any origin c; each source particle uses its own
+// centre, which keeps the three terms of the same size.  Per source particle
+// there are four single-layer expansions (the three density components and
+// rho = (y - c).sigma).  Self: values and exterior-limit gradients at the
+// particle's own nodes (the gradient jump -f nu cancels in the combination);
+// near: values and gradients of the neighbours' exterior expansions; far: the
+// Stokeslet (1/8pi)(I/r + r r^T/r^3) by smooth quadrature (Section 4.3).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "sbie_internal.h"
+
+namespace sbie {
+
+namespace {
+
+constexpr double kInv8Pi = 0.039788735772973833942220940843128591;
+
+inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+// Transform inputs of the four expansions (modified basis of Section 3.2:
+// sqrt(u0^2 -+ v^2) times the density) and the far-field records
+// (node - centre, W sigma).
+template <typename R>
+__global__ void k_stokes_prep(const Particle* __restrict__ part, const double* __restrict__ dens,
+                              const double* __restrict__ x, const double* __restrict__ y,
+                              const double* __restrict__ z, const double* __restrict__ w,
+                              const double* __restrict__ wS, int p, int64_t N, double* __restrict__ f,
+                              R* __restrict__ rec) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  const int Nphi = 2 * p + 2, T = (p + 1) * Nphi;
+  const int i = (int)(g / T), t = (int)(g - (int64_t)i * T), j = t / Nphi;
+  const double s0 = dens[g], s1 = dens[N + g], s2 = dens[2 * N + g];
+  const double ox = x[g] - part[i].c[0], oy = y[g] - part[i].c[1], oz = z[g] - part[i].c[2];
+  const double ws = wS[(size_t)i * (p + 1) + j];
+  double* fr = f + (size_t)i * 4 * T + t;
+  fr[0] = ws * s0;
+  fr[T] = ws * s1;
+  fr[2 * T] = ws * s2;
+  fr[3 * T] = ws * fma(oz, s2, fma(oy, s1, ox * s0));
+  const double wq = w[g];
+  R* r = rec + 8 * g;
+  r[0] = (R)ox;
+  r[1] = (R)oy;
+  r[2] = (R)oz;
+  r[3] = (R)(wq * s0);
+  r[4] = (R)(wq * s1);
+  r[5] = (R)(wq * s2);
+  r[6] = R(0);
+  r[7] = R(0);
+}
+
+// E = lamS c (exterior single-layer coefficients) and Eu = E dR/du(u0).
+__global__ void k_stokes_scale(const double* __restrict__ coef, const double* __restrict__ lam,
+                               const double* __restrict__ dlr, int M, int p, double* __restrict__ E,
+                               double* __restrict__ Eu) {
+  const int K = (p + 1) * (p + 1), Kh = (p + 1) * (p + 2) / 2;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)4 * M * K) return;
+  const int row = (int)(t / K), l = (int)(t - (int64_t)row * K);
+  const int i = row / 4;
+  const int n = (int)sqrt((double)l);
+  const int m = l - n * n - n;
+  const int h = n * (n + 1) / 2 + (m < 0 ? -m : m);
+  const double e = lam[((size_t)i * Kh + h) * 4 + 2] * coef[t];
+  E[t] = e;
+  Eu[t] = e * dlr[(size_t)i * Kh + h];
+}
+
+// Cartesian (lab) gradients of the four expansions from their derivatives in
+// (u, v, phi) -- the chain rule for the orthogonal coordinates of Table 1 --
+// and the combination of Eq. (stokes).  d = x - c (lab).
+__device__ inline void stokes_from_derivatives(const Particle& P, double u, double su, double v, double sv,
+                                               double c1, double s1, const double* Phi, const double* Pu,
+                                               const double* Pv, const double* Pp, const double d[3],
+                                               double out[3]) {
+  const double a = P.a;
+  const double xu[3] = {a * u / su * sv * c1, a * u / su * sv * s1, a * v};
+  const double xv[3] = {-a * su * v / sv * c1, -a * su * v / sv * s1, a * u};
+  const double xp[3] = {-a * su * sv * s1, a * su * sv * c1, 0.0};
+  const double hu2 = xu[0] * xu[0] + xu[1] * xu[1] + xu[2] * xu[2];
+  const double hv2 = xv[0] * xv[0] + xv[1] * xv[1] + xv[2] * xv[2];
+  const double hp2 = xp[0] * xp[0] + xp[1] * xp[1] + xp[2] * xp[2];
+  double grad[4][3];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const double fu = Pu[s] / hu2, fv = Pv[s] / hv2, fp = Pp[s] / hp2;
+    const double gb[3] = {xu[0] * fu + xv[0] * fv + xp[0] * fp, xu[1] * fu + xv[1] * fv + xp[1] * fp,
+                          xu[2] * fu + xv[2] * fv};
+#pragma unroll
+    for (int r = 0; r < 3; ++r) grad[s][r] = P.R[3 * r] * gb[0] + P.R[3 * r + 1] * gb[1] + P.R[3 * r + 2] * gb[2];
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    out[k] = 0.5 * (Phi[k] - d[0] * grad[0][k] - d[1] * grad[1][k] - d[2] * grad[2][k] + grad[3][k]);
+}
+
+// Self part at node g of particle i from the synthesised values U[0..3]
+// (value, d/du exterior limit, d/dv, d/dphi) of the four expansions.
+__global__ void k_stokes_self(const Particle* __restrict__ part, const double* __restrict__ gl,
+                              const double* __restrict__ x, const double* __restrict__ y,
+                              const double* __restrict__ z, const double* __restrict__ U, int M, int p,
+                              int64_t N, double* __restrict__ out) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  const int Nphi = 2 * p + 2, T = (p + 1) * Nphi;
+  const int i = (int)(g / T), t = (int)(g - (int64_t)i * T), j = t / Nphi, k = t - j * Nphi;
+  const Particle P = part[i];
+  const size_t plane = (size_t)4 * M * T;
+  double Phi[4], Pu[4], Pv[4], Pp[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const size_t o = ((size_t)i * 4 + s) * T + t;
+    Phi[s] = U[o];
+    Pu[s] = U[plane + o];
+    Pv[s] = U[2 * plane + o];
+    Pp[s] = U[3 * plane + o];
+  }
+  const double v = gl[j];
+  double s1, c1;
+  sincospi(2.0 * k / Nphi, &s1, &c1);
+  const double d[3] = {x[g] - P.c[0], y[g] - P.c[1], z[g] - P.c[2]};
+  double o3[3];
+  stokes_from_derivatives(P, P.u0, sqrt(P.w0), v, sqrt((1.0 - v) * (1.0 + v)), c1, s1, Phi, Pu, Pv, Pp, d, o3);
+  out[g] = o3[0];
+  out[N + g] = o3[1];
+  out[2 * N + g] = o3[2];
+}
+
+// Near part: one wave per (target particle, 64 target nodes); for every near
+// source the target is mapped into the source frame, Q_n^m(u) and Q_n^m'(u)
+// come from the same division-free backward recurrence as the Laplace near
+// field, and the four expansions are summed with their u, v and phi
+// derivatives.
+template <int PMAX>
+__global__ __launch_bounds__(64) void k_near_stokes(
+    const Particle* __restrict__ part, const double* __restrict__ x, const double* __restrict__ y,
+    const double* __restrict__ z, const int32_t* __restrict__ near_ptr, const int32_t* __restrict__ near_src,
+    const double* __restrict__ E, const double* __restrict__ lam, const double* __restrict__ ab,
+    const double* __restrict__ cd, const double* __restrict__ rcp, int p, int T, int chunks, int64_t N,
+    unsigned* status, double* __restrict__ unear) {
+  const int j = blockIdx.x / chunks;
+  const int t = (blockIdx.x - j * chunks) * 64 + threadIdx.x;
+  const bool live = t < T;
+  const int64_t g = (int64_t)j * T + (live ? t : 0);
+  const double X0 = x[g], X1 = y[g], X2 = z[g];
+  const int K = (p + 1) * (p + 1), Kh = (p + 1) * (p + 2) / 2, N1 = p + 1;
+  double acc[3] = {0.0, 0.0, 0.0};
+  unsigned bad = 0u;
+  for (int sidx = near_ptr[j]; sidx < near_ptr[j + 1]; ++sidx) {
+    const int i = near_src[sidx];
+    const Particle P = part[i];
+    const double* Ei = E + (size_t)i * 4 * K;
+    const double* Li = lam + (size_t)i * Kh * 4;
+    const double d0 = X0 - P.c[0], d1 = X1 - P.c[1], d2 = X2 - P.c[2];
+    const double b0 = P.R[0] * d0 + P.R[3] * d1 + P.R[6] * d2;
+    const double b1 = P.R[1] * d0 + P.R[4] * d1 + P.R[7] * d2;
+    const double b2 = P.R[2] * d0 + P.R[5] * d1 + P.R[8] * d2;
+    const double a = P.a;
+    // a target on the source's symmetry axis is moved off it by 1e-12 a (the
+    // v and phi directions are singular there)
+    const double rho0 = sqrt(b0 * b0 + b1 * b1);
+    const double rho = fmax(rho0, 1e-12 * a);
+    double u, w;
+    if (!P.oblate) {
+      const double f1 = sqrt(rho * rho + (b2 - a) * (b2 - a));
+      const double f2 = sqrt(rho * rho + (b2 + a) * (b2 + a));
+      const double ch = (f1 + f2) / (2.0 * a);
+      u = ch;
+      w = (ch - 1.0) * (ch + 1.0);
+    } else {
+      const double f1 = sqrt((rho + a) * (rho + a) + b2 * b2);
+      const double f2 = sqrt((rho - a) * (rho - a) + b2 * b2);
+      const double ch = (f1 + f2) / (2.0 * a);
+      u = sqrt((ch - 1.0) * (ch + 1.0));
+      w = ch * ch;
+    }
+    if (!(u > P.u0)) bad |= kStatExterior;
+    const double sw = sqrt(w);
+    const double v = b2 / (a * u);
+    const double sv = rho / (a * sw);
+    const double inv_omv2 = 1.0 / (sv * sv);
+    const double inv_w = 1.0 / w;
+    const double c1 = rho0 > 0.0 ? b0 / rho0 : 1.0, s1 = rho0 > 0.0 ? b1 / rho0 : 0.0;
+    int steps = (int)ceil(20.1 / log(u + sw)) + 8;
+    for (int off = 32; off >= 1; off >>= 1) steps = max(steps, __shfl_xor(steps, off, 64));
+    steps = __builtin_amdgcn_readfirstlane(steps);
+    if (steps > 100000) {
+      steps = 100000;
+      bad |= kStatNumeric;
+    }
+    steps = (steps + 7) & ~7;
+    const int L = N1 + steps;
+    double Phi[4] = {0, 0, 0, 0}, Pu[4] = {0, 0, 0, 0}, Pv[4] = {0, 0, 0, 0}, Pp[4] = {0, 0, 0, 0};
+    double pmm_u = 1.0, pbar = 0.28209479177387814347, cm = 1.0, sm = 0.0;
+    double cas2 = 1.0;
+    for (int k = 2; k < N1; ++k) cas2 *= (double)k;
+    const double sgn = P.oblate ? 1.0 : -1.0;
+    for (int m = 0; m <= p; ++m) {
+      if (m > 0) {
+        pmm_u *= (double)(2 * m - 1) * sw;
+        pbar *= sqrt((2.0 * m + 1.0) / (2.0 * m)) * sv;
+        const double cn = cm * c1 - sm * s1;
+        sm = sm * c1 + cm * s1;
+        cm = cn;
+        cas2 = -cas2 * (double)(N1 + m - 1);
+      }
+      // Pt_n = (n-m)! P_n^m(u), forward and division-free
+      double pa = pmm_u, pb = (double)(2 * m + 1) * u * pmm_u;
+      {
+        double c2n1 = (double)(2 * m + 3), cnm = (double)(2 * m + 1), cdn = 1.0;
+        for (int n = m + 1; n < N1; ++n) {
+          const double pc = fma(c2n1 * u, pb, sgn * (cnm * cdn) * pa);
+          pa = pb;
+          pb = pc;
+          c2n1 += 2.0;
+          cnm += 1.0;
+          cdn += 1.0;
+        }
+      }
+      // Q by the division-free backward recurrence from depth L, rescaled
+      double qhi = 0.0, qcur = 1.0;
+      {
+        double c2n1 = (double)(2 * L + 1), ca = sgn * (double)(L - m + 1), cb = (double)(L + m + 1);
+        const double dca = -sgn;
+        for (int n = L; n > N1; n -= 8) {
+#pragma unroll
+          for (int kk = 0; kk < 8; ++kk) {
+            const double qn = fma(c2n1 * u, qcur, (ca * cb) * qhi);
+            qhi = qcur;
+            qcur = qn;
+            c2n1 -= 2.0;
+            ca += dca;
+            cb -= 1.0;
+          }
+          if (fabs(qcur) > 0x1p600) {
+            qcur *= 0x1p-600;
+            qhi *= 0x1p-600;
+          }
+        }
+      }
+      qcur *= rcp[N1 + m + 1];
+      double Q[PMAX + 4];
+      double qN1 = 0.0;
+#pragma unroll
+      for (int n = PMAX + 2; n >= 0; --n) {
+        if (n == N1 + 1) {
+          Q[n] = qhi;
+        } else if (n == N1) {
+          Q[n] = qcur;
+        } else if (n < N1 && n >= m) {
+          Q[n] = fma((double)(2 * n + 3) * u, Q[n + 1], sgn * (double)(n - m + 2) * Q[n + 2]) * rcp[n + m + 1];
+        } else {
+          Q[n] = 0.0;
+        }
+        if (n == N1 - 1) qN1 = Q[n];
+      }
+      const double qscale = cas2 / fma(sgn * (double)(N1 - m) * pa, qcur, pb * qN1);
+      // normalised Ferrers functions of v through degree p+1
+      double Pb[PMAX + 3];
+      {
+        double p2 = 0.0, p1 = pbar;
+#pragma unroll
+        for (int n = 0; n <= PMAX + 1; ++n) {
+          double pn = 0.0;
+          if (n == m) {
+            pn = pbar;
+          } else if (n == m + 1) {
+            pn = sqrt(2.0 * m + 3.0) * v * pbar;
+            p2 = p1;
+            p1 = pn;
+          } else if (n > m + 1 && n <= p + 1) {
+            const int h = n * (n + 1) / 2 + m;
+            pn = ab[2 * h] * (v * p1 - ab[2 * h + 1] * p2);
+            p2 = p1;
+            p1 = pn;
+          }
+          Pb[n] = pn;
+        }
+      }
+      double vc[4] = {0, 0, 0, 0}, vs[4] = {0, 0, 0, 0}, uc[4] = {0, 0, 0, 0}, us[4] = {0, 0, 0, 0};
+      double wc[4] = {0, 0, 0, 0}, ws[4] = {0, 0, 0, 0};
+#pragma unroll
+      for (int n = 0; n <= PMAX; ++n) {
+        if (n >= m && n <= p) {
+          const int h = n * (n + 1) / 2 + m;
+          const double sc = qscale * Li[h * 4 + 3];
+          const double qr = Q[n] * sc;
+          const double dq = ((-sgn) * (double)(n - m + 1) * Q[n + 1] - (double)(n + 1) * u * Q[n]) * inv_w * sc;
+          const double pn = Pb[n];
+          const double dpn = ((double)(n + 1) * v * pn - cd[h] * Pb[n + 1]) * inv_omv2;
+          const double t0 = pn * qr, t1 = pn * dq, t2 = dpn * qr;
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const double ec = Ei[(size_t)s * K + n * n + n + m];
+            vc[s] = fma(ec, t0, vc[s]);
+            uc[s] = fma(ec, t1, uc[s]);
+            wc[s] = fma(ec, t2, wc[s]);
+            if (m > 0) {
+              const double es = Ei[(size_t)s * K + n * n + n - m];
+              vs[s] = fma(es, t0, vs[s]);
+              us[s] = fma(es, t1, us[s]);
+              ws[s] = fma(es, t2, ws[s]);
+            }
+          }
+        }
+      }
+      const double f = m == 0 ? 1.0 : 1.41421356237309504880;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        Phi[s] += f * (vc[s] * cm + vs[s] * sm);
+        Pu[s] += f * (uc[s] * cm + us[s] * sm);
+        Pv[s] += f * (wc[s] * cm + ws[s] * sm);
+        Pp[s] += f * (double)m * (vs[s] * cm - vc[s] * sm);
+      }
+    }
+    const double d[3] = {d0, d1, d2};
+    double o3[3];
+    stokes_from_derivatives(P, u, sw, v, sv, c1, s1, Phi, Pu, Pv, Pp, d, o3);
+    acc[0] += o3[0];
+    acc[1] += o3[1];
+    acc[2] += o3[2];
+  }
+  if (bad) atomicOr(status, bad);
+  if (live) {
+    unear[g] = acc[0];
+    unear[N + g] = acc[1];
+    unear[2 * N + g] = acc[2];
+  }
+}
+
+template <typename R>
+__device__ inline R rsq_r(R x);
+template <>
+__device__ inline float rsq_r<float>(float x) {
+  return __builtin_amdgcn_rsqf(x);
+}
+template <>
+__device__ inline double rsq_r<double>(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double e = fma(-x * y, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-x * y, y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+
+// Far part: the Stokeslet summed over the far source nodes.  Grid as the
+// Laplace far field (target tiles x source splits, split fastest); source
+// records (node - centre, W sigma) are read with wave-uniform addresses; each
+// source particle's tile sum is added per target under the exclusion flag,
+// compensated (TwoSum) in FP32.
+template <typename R, int TPT>
+__global__ __launch_bounds__(256) void k_far_stokes(const R* __restrict__ rec, const Particle* __restrict__ part,
+                                                    const double* __restrict__ x, const double* __restrict__ y,
+                                                    const double* __restrict__ z, const uint32_t* __restrict__ excl,
+                                                    int words, int M, int T, int64_t N, int nsplit,
+                                                    double* __restrict__ partial) {
+  const int split = blockIdx.x % nsplit, tile = blockIdx.x / nsplit;
+  const int s0 = (int)((int64_t)M * split / nsplit), s1 = (int)((int64_t)M * (split + 1) / nsplit);
+  double tx[TPT], ty[TPT], tz[TPT];
+  int tp[TPT];
+  bool live[TPT];
+  R acc[TPT][3], lo[TPT][3];
+#pragma unroll
+  for (int k = 0; k < TPT; ++k) {
+    const int64_t gq = (int64_t)tile * 256 * TPT + k * 256 + threadIdx.x;
+    live[k] = gq < N;
+    const int64_t gg = live[k] ? gq : 0;
+    tx[k] = x[gg];
+    ty[k] = y[gg];
+    tz[k] = z[gg];
+    tp[k] = (int)(gg / T);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[k][c] = lo[k][c] = R(0);
+  }
+  for (int s = s0; s < s1; ++s) {
+    bool need[TPT];
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < TPT; ++k) {
+      need[k] = live[k] && !((excl[(size_t)tp[k] * words + (s >> 5)] >> (s & 31)) & 1u);
+      any |= need[k];
+    }
+    if (!__any(any)) continue;
+    const double cx = part[s].c[0], cy = part[s].c[1], cz = part[s].c[2];
+    R Dx[TPT], Dy[TPT], Dz[TPT], tmp[TPT][3];
+#pragma unroll
+    for (int k = 0; k < TPT; ++k) {
+      Dx[k] = (R)(tx[k] - cx);
+      Dy[k] = (R)(ty[k] - cy);
+      Dz[k] = (R)(tz[k] - cz);
+      tmp[k][0] = tmp[k][1] = tmp[k][2] = R(0);
+    }
+    const R* rs = rec + (size_t)s * T * 8;
+    for (int q = 0; q < T; ++q) {
+      const R* r = rs + (size_t)q * 8;
+      const R ox = r[0], oy = r[1], oz = r[2], q0 = r[3], q1 = r[4], q2 = r[5];
+#pragma unroll
+      for (int k = 0; k < TPT; ++k) {
+        const R dx = Dx[k] - ox, dy = Dy[k] - oy, dz = Dz[k] - oz;
+        const R r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+        const R ri = rsq_r<R>(r2);
+        const R dot = fma(dz, q2, fma(dy, q1, dx * q0));
+        const R f = dot * ri * ri * ri;
+        tmp[k][0] = fma(q0, ri, fma(dx, f, tmp[k][0]));
+        tmp[k][1] = fma(q1, ri, fma(dy, f, tmp[k][1]));
+        tmp[k][2] = fma(q2, ri, fma(dz, f, tmp[k][2]));
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < TPT; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const R vv = need[k] ? tmp[k][c] : R(0);
+        const R sum = acc[k][c] + vv;
+        const R bp = sum - acc[k][c];
+        lo[k][c] += (acc[k][c] - (sum - bp)) + (vv - bp);
+        acc[k][c] = sum;
+      }
+  }
+#pragma unroll
+  for (int k = 0; k < TPT; ++k) {
+    const int64_t gq = (int64_t)tile * 256 * TPT + k * 256 + threadIdx.x;
+    if (!live[k]) continue;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      partial[((size_t)split * 3 + c) * N + gq] = ((double)acc[k][c] + (double)lo[k][c]) * kInv8Pi;
+  }
+}
+
+__global__ void k_stokes_assemble(const double* __restrict__ uself, const double* __restrict__ unear,
+                                  const double* __restrict__ partial, int nsplit, int64_t N, uint32_t parts,
+                                  double* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 3 * N) return;
+  const int c = (int)(t / N);
+  const int64_t g = t - (int64_t)c * N;
+  double u = 0.0;
+  if (parts & SBIE_PARTS_SELF) u += uself[t];
+  if (parts & SBIE_PARTS_NEAR) u += unear[t];
+  if (parts & SBIE_PARTS_FAR) {
+    double f = 0.0;
+    for (int s = 0; s < nsplit; ++s) f += partial[((size_t)s * 3 + c) * N + g];
+    u += f;
+  }
+  out[t] = u;
+}
+
+template <typename Tp>
+sbie_status alloc_work(Tp** p, size_t count, uint64_t* fp) {
+  if (*p) return SBIE_OK;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(Tp));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    set_error("device allocation of the Stokes work buffers failed");
+    return SBIE_E_NOMEM;
+  }
+  *fp += count * sizeof(Tp);
+  return SBIE_OK;
+}
+
+template <int PMAX>
+void launch_near_stokes(sbie_geom* g, hipStream_t s) {
+  const int chunks = (g->T + 63) / 64;
+  hipLaunchKernelGGL(k_near_stokes<PMAX>, dim3(g->M * chunks), dim3(64), 0, s, g->d_part, g->d_x, g->d_y, g->d_z,
+                     g->d_near_ptr, g->d_near_src, g->d_stk_E, g->d_lam, g->d_ab, g->d_cd, g->d_rcp, g->p, g->T,
+                     chunks, g->N, g->d_status, g->d_stk_near);
+}
+
+}  // namespace
+
+sbie_status stokes_staging(sbie_geom* g, double** io) {
+  sbie_status st = alloc_work(&g->d_stk_io, (size_t)6 * g->N, &g->footprint);
+  *io = g->d_stk_io;
+  return st;
+}
+
+sbie_status apply_stokes(sbie_geom* g, int prec, const double* d_dens, double* d_out, hipStream_t s,
+                         uint32_t parts, bool timed) {
+  const int M = g->M, p = g->p, T = g->T, K = g->K;
+  const int64_t N = g->N;
+  const bool mixed = prec == SBIE_MIXED;
+  const size_t MT4 = (size_t)4 * M * T, MK4 = (size_t)4 * M * K;
+  uint64_t& fp = g->footprint;
+  sbie_status st;
+  if ((st = alloc_work(&g->d_stk_f, MT4, &fp)) != SBIE_OK) return st;
+  if ((st = alloc_work(&g->d_stk_c, MK4, &fp)) != SBIE_OK) return st;
+  if ((st = alloc_work(&g->d_stk_E, 2 * MK4, &fp)) != SBIE_OK) return st;
+  if ((st = alloc_work(&g->d_stk_U, 4 * MT4, &fp)) != SBIE_OK) return st;
+  if ((st = alloc_work(&g->d_stk_src, (size_t)8 * N, &fp)) != SBIE_OK) return st;
+  if ((st = alloc_work(&g->d_stk_part, (size_t)g->nsplit * 3 * N, &fp)) != SBIE_OK) return st;
+  if ((st = alloc_work(&g->d_stk_self, (size_t)3 * N, &fp)) != SBIE_OK) return st;
+  if ((st = alloc_work(&g->d_stk_near, (size_t)3 * N, &fp)) != SBIE_OK) return st;
+
+  Timing& tm = g->timing;
+  hipEvent_t* ev = nullptr;
+  if (timed) {
+    if (tm.used == tm.sets.size()) {
+      std::vector<hipEvent_t> set(6, nullptr);
+      for (int e = 0; e < 6; ++e) SBIE_HIP(hipEventCreate(&set[e]));
+      tm.sets.push_back(set);
+    }
+    ev = tm.sets[tm.used++].data();
+    SBIE_HIP(hipEventRecord(ev[0], s));
+  }
+  const int B = 256;
+  if (mixed)
+    hipLaunchKernelGGL(k_stokes_prep<float>, dim3(cdiv(N, B)), dim3(B), 0, s, g->d_part, d_dens, g->d_x, g->d_y,
+                       g->d_z, g->d_w, g->d_wS, p, N, g->d_stk_f, (float*)g->d_stk_src);
+  else
+    hipLaunchKernelGGL(k_stokes_prep<double>, dim3(cdiv(N, B)), dim3(B), 0, s, g->d_part, d_dens, g->d_x, g->d_y,
+                       g->d_z, g->d_w, g->d_wS, p, N, g->d_stk_f, g->d_stk_src);
+  SBIE_HIP(hipGetLastError());
+  if (timed) SBIE_HIP(hipEventRecord(ev[1], s));
+  if (parts & (SBIE_PARTS_SELF | SBIE_PARTS_NEAR)) {
+    // forward transforms of the four densities per particle (rows i*4 + s)
+    if ((st = gemm(mixed, g->d_stk_f, T, g->d_An, g->d_An32, K, g->d_stk_c, K, 4 * M, K, T, s)) != SBIE_OK)
+      return st;
+    hipLaunchKernelGGL(k_stokes_scale, dim3(cdiv((int64_t)MK4, B)), dim3(B), 0, s, g->d_stk_c, g->d_lam, g->d_dlr,
+                       M, p, g->d_stk_E, g->d_stk_E + MK4);
+    SBIE_HIP(hipGetLastError());
+    if (parts & SBIE_PARTS_SELF) {
+      double* U = g->d_stk_U;
+      if ((st = gemm(mixed, g->d_stk_E, K, g->d_Sy, g->d_Sy32, T, U, T, 4 * M, T, K, s)) != SBIE_OK) return st;
+      if ((st = gemm(mixed, g->d_stk_E + MK4, K, g->d_Sy, g->d_Sy32, T, U + MT4, T, 4 * M, T, K, s)) != SBIE_OK)
+        return st;
+      if ((st = gemm(mixed, g->d_stk_E, K, g->d_Sv, g->d_Sv32, T, U + 2 * MT4, T, 4 * M, T, K, s)) != SBIE_OK)
+        return st;
+      if ((st = gemm(mixed, g->d_stk_E, K, g->d_Sp, g->d_Sp32, T, U + 3 * MT4, T, 4 * M, T, K, s)) != SBIE_OK)
+        return st;
+      hipLaunchKernelGGL(k_stokes_self, dim3(cdiv(N, B)), dim3(B), 0, s, g->d_part, g->d_gl, g->d_x, g->d_y,
+                         g->d_z, g->d_stk_U, M, p, N, g->d_stk_self);
+      SBIE_HIP(hipGetLastError());
+    }
+  }
+  if (timed) SBIE_HIP(hipEventRecord(ev[2], s));
+  if ((parts & SBIE_PARTS_NEAR) && g->n_near > 0) {
+    if (p <= 8)
+      launch_near_stokes<8>(g, s);
+    else if (p <= 16)
+      launch_near_stokes<16>(g, s);
+    else
+      launch_near_stokes<32>(g, s);
+    SBIE_HIP(hipGetLastError());
+  } else if (parts & SBIE_PARTS_NEAR) {
+    SBIE_HIP(hipMemsetAsync(g->d_stk_near, 0, sizeof(double) * 3 * N, s));
+  }
+  if (timed) SBIE_HIP(hipEventRecord(ev[3], s));
+  if (parts & SBIE_PARTS_FAR) {
+    constexpr int TPT = 2;
+    const dim3 grid(cdiv(N, 256 * TPT) * g->nsplit);
+    if (mixed)
+      hipLaunchKernelGGL((k_far_stokes<float, TPT>), grid, dim3(256), 0, s, (const float*)g->d_stk_src, g->d_part,
+                         g->d_x, g->d_y, g->d_z, g->d_excl, g->excl_words, M, T, N, g->nsplit, g->d_stk_part);
+    else
+      hipLaunchKernelGGL((k_far_stokes<double, TPT>), grid, dim3(256), 0, s, (const double*)g->d_stk_src,
+                         g->d_part, g->d_x, g->d_y, g->d_z, g->d_excl, g->excl_words, M, T, N, g->nsplit,
+                         g->d_stk_part);
+    SBIE_HIP(hipGetLastError());
+  }
+  if (timed) SBIE_HIP(hipEventRecord(ev[4], s));
+  hipLaunchKernelGGL(k_stokes_assemble, dim3(cdiv(3 * N, B)), dim3(B), 0, s, g->d_stk_self, g->d_stk_near,
+                     g->d_stk_part, g->nsplit, N, parts, d_out);
+  SBIE_HIP(hipGetLastError());
+  if (timed) SBIE_HIP(hipEventRecord(ev[5], s));
+  return SBIE_OK;
+}
+
+}  // namespace sbie

@@ -137,3 +137,89 @@ def test_stokes_whole_apply_two_prolates():
             dots = np.sum(d * sf.T, axis=1)
             ref = [np.sum(Wf * (sf[k] / r + d[:, k] * dots / (r2 * r))) / (8 * np.pi) for k in range(3)]
             assert np.max(np.abs(un[:, j * T + t] - ref)) < 1e-9 * max(1e-3, np.max(np.abs(un))), t
+
+
+def _spheroid(A, C):
+    q = np.array([0.9, 0.1, -0.3, 0.2])
+    q /= np.linalg.norm(q)
+    c = np.array([0.3, -0.2, 1.0])
+    return {"centers": c[None], "quats": q[None], "A": np.array([A]), "C": np.array([C])}
+
+
+def _mobility_closed_form(A, C):
+    """Translational mobility (velocity per unit force, viscosity 1) of a
+    spheroid with equatorial semi-axis A and polar semi-axis C, along and
+    across its symmetry axis (Oberbeck's ellipsoid solution in the closed forms
+    of Chwang & Wu, J. Fluid Mech. 67 (1975))."""
+    if C > A:
+        e = np.sqrt(1.0 - (A / C) ** 2)
+        L = np.log((1 + e) / (1 - e))
+        axial = ((1 + e * e) * L - 2 * e) / (16 * np.pi * C * e ** 3)
+        trans = (2 * e + (3 * e * e - 1) * L) / (32 * np.pi * C * e ** 3)
+    else:
+        e = np.sqrt(1.0 - (C / A) ** 2)
+        s, asn = np.sqrt(1 - e * e), np.arcsin(e)
+        axial = (e * s - (1 - 2 * e * e) * asn) / (8 * np.pi * A * e ** 3)
+        trans = ((1 + 2 * e * e) * asn - e * s) / (16 * np.pi * A * e ** 3)
+    return axial, trans
+
+
+@pytest.mark.parametrize("A,C", [(0.5, 1.0), (0.3, 1.2), (1.0, 0.4), (1.1, 0.25)])
+@pytest.mark.parametrize("p", [8, 16])
+def test_stokes_translating_spheroid_closed_form(A, C, p):
+    """A spheroid translating in Stokes flow carries the traction F rho with rho
+    the equilibrium-charge density 1/(4 pi A^2 C h), h = |grad| of the body's
+    quadric / 2; the single layer of that traction is the constant rigid
+    velocity M F on the surface.  Dropping or mis-signing any of the three
+    terms of Eq. (stokes) breaks the constancy."""
+    from workloads import quat_rot
+
+    g = _spheroid(A, C)
+    c, R = g["centers"][0], quat_rot(g["quats"][0])
+    x, _, w = oracle.grid(g, p)
+    b = (x - c) @ R
+    rho = 1.0 / (4 * np.pi * A * A * C * np.sqrt((b[:, 0] ** 2 + b[:, 1] ** 2) / A ** 4 + b[:, 2] ** 2 / C ** 4))
+    assert abs(np.sum(w * rho) - 1.0) < 1e-13
+    axial, trans = _mobility_closed_form(A, C)
+    for e, ref in [(np.array([0.0, 0.0, 1.0]), axial), (np.array([1.0, 0.0, 0.0]), trans)]:
+        u = oracle.stokes_apply(g, p, np.outer(R @ e, rho))
+        ub = R.T @ u
+        assert np.max(np.abs(ub - (ref * e)[:, None])) < 1e-13, (A, C, p, e)
+
+
+@pytest.mark.parametrize("A,C", [(0.5, 1.0), (1.0, 0.4)])
+def test_stokes_normal_density_is_null_single(A, C):
+    """The Stokes single layer of the unit normal vanishes identically (it is
+    the flow of a uniform pressure)."""
+    g = _spheroid(A, C)
+    for p in (8, 16):
+        _, n, _ = oracle.grid(g, p)
+        u = oracle.stokes_apply(g, p, n.T.copy())
+        assert np.max(np.abs(u)) < 1e-14
+
+
+def test_stokes_normal_density_is_null_suspension():
+    """Each particle's layer vanishes everywhere, so the self values and the near
+    expansions (two prolates within one diameter) vanish one by one."""
+    import workloads
+
+    g = workloads.geometry("c1")
+    assert oracle.classify(g).sum() == 2
+    for p in (8, 12):
+        _, n, _ = oracle.grid(g, p)
+        for part in oracle.stokes_apply(g, p, n.T.copy(), parts=True):
+            assert np.max(np.abs(part)) < 1e-14
+
+
+def test_stokes_apply_at_matches_whole_apply():
+    import workloads
+
+    g = workloads.rsa_pack(6, 0.15, 0.05, 41)
+    p = 6
+    N = 6 * (p + 1) * (2 * p + 2)
+    dens = np.random.default_rng(0).standard_normal((3, N))
+    full = oracle.stokes_apply(g, p, dens, parts=True)
+    tg = np.array([0, 5, N // 2, N - 1])
+    at = oracle.stokes_apply_at(g, p, dens, tg)
+    for a, b in zip(at, full):
+        assert np.array_equal(a, b[:, tg])

@@ -33,7 +33,8 @@
  * Errors: every entry point returns an sbie_status; nothing throws across the
  * ABI.  sbie_last_error() returns a thread-local message for the last failure.
  *
- * Threads: one geometry must not be used by concurrent sbie_apply calls.
+ * Threads: one geometry must not be used by concurrent sbie_apply calls; the
+ * served-mode calls (sbie_server_*, sbie_session_*, sbie_wait) are thread-safe.
  */
 #ifndef SBIE_H
 #define SBIE_H
@@ -164,6 +165,105 @@ sbie_status sbie_geom_spectra(const sbie_geom* g, double* out);
    previous call (waits for them to finish), then starts a new window.
    SBIE_E_STATE if there was no timed apply. */
 sbie_status sbie_geom_timing(sbie_geom* g, sbie_timing* out);
+
+/* ---------------------------------------------------------------- served mode
+
+   Many independent operator sessions sharing one GPU, for boundary integral
+   equation solvers that issue a stream of applies per suspension (the Krylov
+   iterations of Section 4 and Section 5.2).  A session is a suspension (geometry, p, eta) with an operator
+   and a precision; its applies run in submission order.  The server admits a
+   session when one of its lanes is idle and the session's device bytes
+   (sbie_session_bytes) fit in the server's HBM arena: first come, first
+   served, except that a smaller later session may pass a waiting one at most
+   SBIE_MAX_PASS times in a row.  An admitted session keeps its geometry, near
+   lists and spectra resident until it is closed; each lane has its own stream,
+   so the kernels of concurrent sessions interleave on the device.  With
+   SBIE_SERVER_GRAPHS each session's apply is captured once as a HIP graph and
+   replayed.  Results are bitwise those of sbie_apply on the same geometry.
+
+   All server calls are thread-safe; the handles of one session must not be
+   used after sbie_session_close. */
+
+typedef struct sbie_server sbie_server;
+typedef struct sbie_session sbie_session;
+
+#define SBIE_SERVER_GRAPHS 0x100u
+#define SBIE_MAX_PASS 8
+
+typedef struct {
+  double open_us;    /* session opened (request arrival), server clock in microseconds */
+  double admit_us;   /* session admitted to a lane */
+  double ready_us;   /* its geometry built (and graph captured) */
+  double submit_us;  /* this apply submitted */
+  double start_us;   /* this apply started on its lane */
+  double end_us;     /* this apply finished (results in the caller's buffer) */
+  int64_t session;   /* session id (1, 2, ... in open order) */
+  int32_t lane;
+  int32_t status;    /* sbie_status of the apply */
+} sbie_apply_stats;
+
+typedef struct {
+  uint64_t budget_bytes;    /* arena size */
+  uint64_t in_use_bytes;    /* held by admitted sessions now */
+  uint64_t peak_bytes;      /* largest in_use_bytes so far */
+  int64_t pending;          /* sessions waiting for admission */
+  int64_t active;           /* admitted, not yet closed */
+  int64_t admitted;         /* sessions admitted so far */
+  int64_t passed;           /* admissions that passed a waiting earlier session */
+  int64_t waited;           /* sessions that could not be admitted at once */
+  int64_t applies;          /* applies completed */
+  int32_t lanes;
+  int32_t graphs;           /* 1 if applies are replayed as HIP graphs */
+} sbie_server_info;
+
+/* Device bytes a session of M particles at order p holds while admitted:
+   its geometry (setup tables, near lists, work buffers; Stokes buffers for
+   SBIE_OP_STOKES_S) plus input and output buffers of nrhs x N doubles (nrhs = 3
+   for Stokes, else 1).  0 for invalid sizes. */
+uint64_t sbie_session_bytes(int32_t M, int32_t p, sbie_op op);
+
+/* Start a server on ctx's device with max_sessions lanes (1..64), each with a
+   stream and a host thread, and an arena of hbm_budget_bytes of device memory
+   allocated now.  flags: SBIE_SERVER_GRAPHS.  Errors: SBIE_E_INVALID,
+   SBIE_E_NOMEM, SBIE_E_DEVICE. */
+sbie_status sbie_server_create(sbie_ctx* ctx, int32_t max_sessions, uint64_t hbm_budget_bytes,
+                               uint32_t flags, sbie_server** out);
+
+/* Finish every queued apply of the admitted sessions, close all sessions
+   (pending ones fail their applies with SBIE_E_STATE), join the lanes and free
+   the arena.  Waiting for tickets after this call is invalid. */
+void sbie_server_destroy(sbie_server* srv);
+
+/* Open a session (returns at once; admission and the geometry build happen on
+   a lane).  Arguments as sbie_geom_create plus op and precision; the particle
+   arrays are copied.  Errors now: SBIE_E_INVALID, SBIE_E_DEGENERATE,
+   SBIE_E_BUDGET (the session can never fit the arena), SBIE_E_STATE (server
+   stopping).  Errors of the build (SBIE_E_OVERLAP, SBIE_E_NUMERIC, ...) are
+   reported by each of the session's applies. */
+sbie_status sbie_session_open(sbie_server* srv, const double* centers, const double* quats,
+                              const double* A, const double* C, int32_t M, int32_t p, double eta,
+                              sbie_op op, sbie_precision prec, sbie_session** out);
+
+/* Queue one apply: density and potential are [nrhs][N] (nrhs as in
+   sbie_session_bytes), host arrays or, with SBIE_DEVICE_PTRS, device arrays
+   whose producing work has completed (the lanes use their own streams); both
+   must stay valid until sbie_wait returns for *ticket, when the potential is
+   complete on the device.  Errors: SBIE_E_INVALID, SBIE_E_STATE (session
+   closing). */
+sbie_status sbie_session_apply(sbie_session* s, const double* density, double* potential,
+                               uint32_t flags, uint64_t* ticket);
+
+/* Close a session after its queued applies; the handle is invalid afterwards
+   and its device bytes return to the arena when the last apply finishes. */
+sbie_status sbie_session_close(sbie_session* s);
+
+/* Wait up to timeout_us microseconds (< 0: no limit) for an apply; returns its
+   status and, if stats is not NULL, its timeline.  A ticket is consumed by a
+   successful wait.  SBIE_E_TIMEOUT if it is still running (the ticket stays
+   valid); SBIE_E_INVALID for an unknown ticket. */
+sbie_status sbie_wait(sbie_server* srv, uint64_t ticket, int64_t timeout_us, sbie_apply_stats* stats);
+
+sbie_status sbie_server_get_info(sbie_server* srv, sbie_server_info* out);
 
 const char* sbie_status_str(sbie_status s);
 const char* sbie_last_error(void);

@@ -31,8 +31,11 @@ EXPORTS = [
     "sbie_ctx_create", "sbie_ctx_destroy", "sbie_geom_create", "sbie_geom_destroy", "sbie_geom_num_nodes",
     "sbie_geom_num_near_pairs", "sbie_geom_footprint_bytes", "sbie_geom_nodes", "sbie_geom_near_pairs",
     "sbie_apply", "sbie_geom_sync", "sbie_transform", "sbie_geom_spectra", "sbie_geom_timing",
-    "sbie_status_str", "sbie_last_error",
+    "sbie_session_bytes", "sbie_server_create", "sbie_server_destroy", "sbie_session_open", "sbie_session_apply",
+    "sbie_session_close", "sbie_wait", "sbie_server_get_info", "sbie_status_str", "sbie_last_error",
 ]
+SBIE_SERVER_GRAPHS = 0x100
+SBIE_MAX_PASS = 8
 
 
 class SbieError(RuntimeError):
@@ -45,6 +48,19 @@ class Timing(ctypes.Structure):
     _fields_ = [("prep_ms", ctypes.c_double), ("transform_ms", ctypes.c_double), ("near_ms", ctypes.c_double),
                 ("far_kernel_ms", ctypes.c_double), ("assemble_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
                 ("far_pairs", ctypes.c_int64), ("near_evals", ctypes.c_int64), ("count", ctypes.c_int64)]
+
+
+class ApplyStats(ctypes.Structure):
+    _fields_ = [("open_us", ctypes.c_double), ("admit_us", ctypes.c_double), ("ready_us", ctypes.c_double),
+                ("submit_us", ctypes.c_double), ("start_us", ctypes.c_double), ("end_us", ctypes.c_double),
+                ("session", ctypes.c_int64), ("lane", ctypes.c_int32), ("status", ctypes.c_int32)]
+
+
+class ServerInfo(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("in_use_bytes", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64),
+                ("pending", ctypes.c_int64), ("active", ctypes.c_int64), ("admitted", ctypes.c_int64),
+                ("passed", ctypes.c_int64), ("waited", ctypes.c_int64), ("applies", ctypes.c_int64),
+                ("lanes", ctypes.c_int32), ("graphs", ctypes.c_int32)]
 
 
 _lib = None
@@ -94,6 +110,17 @@ def lib() -> ctypes.CDLL:
         L.sbie_transform.argtypes = [vp, ctypes.c_int, ctypes.c_int32, vp, vp, vp, ctypes.c_uint32]
         L.sbie_geom_spectra.argtypes = [vp, dp]
         L.sbie_geom_timing.argtypes = [vp, ctypes.POINTER(Timing)]
+        L.sbie_session_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int]
+        L.sbie_session_bytes.restype = ctypes.c_uint64
+        L.sbie_server_create.argtypes = [vp, ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(vp)]
+        L.sbie_server_destroy.argtypes = [vp]
+        L.sbie_server_destroy.restype = None
+        L.sbie_session_open.argtypes = [vp, dp, dp, dp, dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                        ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)]
+        L.sbie_session_apply.argtypes = [vp, vp, vp, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint64)]
+        L.sbie_session_close.argtypes = [vp]
+        L.sbie_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_int64, ctypes.POINTER(ApplyStats)]
+        L.sbie_server_get_info.argtypes = [vp, ctypes.POINTER(ServerInfo)]
         L.sbie_status_str.argtypes = [ctypes.c_int]
         L.sbie_status_str.restype = ctypes.c_char_p
         L.sbie_last_error.argtypes = []
@@ -247,3 +274,105 @@ class Geometry:
             self.close()
         except Exception:
             pass
+
+
+def session_bytes(M: int, p: int, op: int) -> int:
+    """Device bytes a served session holds while admitted."""
+    return int(lib().sbie_session_bytes(int(M), int(p), int(op)))
+
+
+class Server:
+    """sbie_server: served mode (lanes of a host thread and a stream each, one HBM arena)."""
+
+    def __init__(self, ctx: Context, max_sessions: int = 8, budget_bytes: int = 1 << 30, graphs: bool = True):
+        self.ctx = ctx
+        self._h = ctypes.c_void_p()
+        _check(lib().sbie_server_create(ctx.handle, int(max_sessions), int(budget_bytes),
+                                        SBIE_SERVER_GRAPHS if graphs else 0, ctypes.byref(self._h)))
+        _live.append(weakref.ref(self))
+
+    def open(self, geom: dict, p: int, op: int, precision: int = SBIE_FP64, eta: float = 1.0) -> "Session":
+        return Session(self, geom, p, op, precision, eta)
+
+    def wait(self, ticket: int, timeout_us: int = -1) -> ApplyStats:
+        """Wait for an apply; raises SbieError on its failure (SBIE_E_TIMEOUT keeps the ticket)."""
+        st = ApplyStats()
+        _check(lib().sbie_wait(self._h, ctypes.c_uint64(ticket), int(timeout_us), ctypes.byref(st)))
+        return st
+
+    def info(self) -> ServerInfo:
+        out = ServerInfo()
+        _check(lib().sbie_server_get_info(self._h, ctypes.byref(out)))
+        return out
+
+    def close(self):
+        if self._h:
+            lib().sbie_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Session:
+    """sbie_session: one suspension, operator and precision on a Server."""
+
+    def __init__(self, server: Server, geom: dict, p: int, op: int, precision: int, eta: float):
+        self.server = server
+        c = np.ascontiguousarray(geom["centers"], dtype=np.float64)
+        q = np.ascontiguousarray(geom["quats"], dtype=np.float64)
+        A = np.ascontiguousarray(geom["A"], dtype=np.float64)
+        C = np.ascontiguousarray(geom["C"], dtype=np.float64)
+        self.M, self.p, self.op = int(len(A)), int(p), int(op)
+        self.nrhs = 3 if op == SBIE_OP_STOKES_S else 1
+        self.N = self.M * (self.p + 1) * (2 * self.p + 2)
+        self._h = ctypes.c_void_p()
+        _check(lib().sbie_session_open(server._h, _dp(c), _dp(q), _dp(A), _dp(C), self.M, self.p, float(eta),
+                                       int(op), int(precision), ctypes.byref(self._h)))
+        self._keep = {}
+
+    def submit(self, density, out) -> int:
+        """Queue an apply.  density/out: contiguous float64 CUDA tensors or numpy arrays of
+        nrhs*N entries; they must stay alive until the ticket is waited for."""
+        if isinstance(density, np.ndarray):
+            if not (isinstance(out, np.ndarray) and density.flags.c_contiguous and out.flags.c_contiguous
+                    and density.dtype == np.float64 and out.dtype == np.float64):
+                raise ValueError("density and out must be contiguous float64 arrays")
+            n, no = density.size, out.size
+            dptr, optr, flags = density.ctypes.data, out.ctypes.data, 0
+        else:
+            import torch
+
+            for t_ in (density, out):
+                if not (t_.is_cuda and t_.dtype == torch.float64 and t_.is_contiguous()):
+                    raise ValueError("density and out must be contiguous float64 CUDA tensors")
+            n, no = density.numel(), out.numel()
+            dptr, optr, flags = density.data_ptr(), out.data_ptr(), SBIE_DEVICE_PTRS
+            # the lanes run on their own streams: the density must be complete
+            torch.cuda.current_stream(density.device).synchronize()
+        if n != self.nrhs * self.N or no != n:
+            raise ValueError(f"density/out hold {n}/{no} values, expected {self.nrhs} x {self.N}")
+        t = ctypes.c_uint64()
+        _check(lib().sbie_session_apply(self._h, ctypes.c_void_p(dptr), ctypes.c_void_p(optr), flags,
+                                        ctypes.byref(t)))
+        self._keep[t.value] = (density, out)
+        return t.value
+
+    def apply(self, density, out=None):
+        """Submit and wait (closed loop); returns (out, stats)."""
+        if out is None:
+            out = np.zeros_like(density) if isinstance(density, np.ndarray) else density.new_empty(density.shape)
+        t = self.submit(density, out)
+        try:
+            st = self.server.wait(t)
+        finally:
+            self._keep.pop(t, None)
+        return out, st
+
+    def close(self):
+        if self._h:
+            _check(lib().sbie_session_close(self._h))
+            self._h = ctypes.c_void_p()

@@ -540,8 +540,6 @@ sbie_status apply_laplace(sbie_geom* g, int op, int prec, const double* d_dens, 
     else
       launch_near<32>(g, s);
     SBIE_HIP(hipGetLastError());
-  } else if (parts & SBIE_PARTS_NEAR) {
-    SBIE_HIP(hipMemsetAsync(g->d_unear, 0, sizeof(double) * N, s));
   }
   // part (d) far field: matrix-core tiles when a wave of 64 targets spans at
   // most three particles (T >= 32), else the vector-unit sum in FP64
@@ -564,8 +562,10 @@ sbie_status apply_laplace(sbie_geom* g, int op, int prec, const double* d_dens, 
     SBIE_HIP(hipEventRecord(ev[3], s));
     SBIE_HIP(hipEventRecord(ev[4], s));
   }
+  // with no near pairs the near part is empty and is left out of the sum
+  const uint32_t sum_parts = g->n_near > 0 ? parts : (parts & ~(uint32_t)SBIE_PARTS_NEAR);
   hipLaunchKernelGGL(k_assemble_f64, dim3(cdiv(N, B)), dim3(B), 0, s, g->d_uself, g->d_unear, g->d_partial,
-                     g->nsplit, N, parts, d_out);
+                     g->nsplit, N, sum_parts, d_out);
   SBIE_HIP(hipGetLastError());
   if (timed) {
     SBIE_HIP(hipEventRecord(ev[5], s));

@@ -32,17 +32,8 @@ sbie_status invalid(const std::string& msg) {
 
 void free_geom(sbie_geom* g) {
   if (!g) return;
-  void* ptrs[] = {g->d_part,   g->d_x,       g->d_y,     g->d_z,       g->d_nx,     g->d_ny,     g->d_nz,
-                  g->d_w,      g->d_off32,   g->d_gl,    g->d_An,      g->d_Sy,     g->d_An32,   g->d_Sy32,
-                  g->d_Sv,     g->d_Sp,      g->d_Sv32,  g->d_Sp32,    g->d_dlr,    g->d_stk_f,  g->d_stk_c,
-                  g->d_stk_E,  g->d_stk_U,   g->d_stk_src, g->d_stk_part, g->d_stk_self, g->d_stk_near, g->d_stk_io,
-                  g->d_cd,
-                  g->d_wS,     g->d_lam,     g->d_ab,    g->d_near_ptr, g->d_near_src, g->d_excl, g->d_status,
-                  g->d_f,      g->d_coef,    g->d_cself, g->d_E,       g->d_uself,  g->d_unear,  g->d_src,
-                  g->d_partial, g->d_dens,   g->d_out,   g->d_srec32,  g->d_srec64, g->d_fstr32, g->d_fstr64,
-                  g->d_rcp};
-  for (void* q : ptrs)
-    if (q) (void)hipFree(q);
+  if (g->blk && g->blk_owned) (void)hipFree(g->blk);
+  if (g->stk_blk) (void)hipFree(g->stk_blk);
   for (auto& set : g->timing.sets)
     for (hipEvent_t e : set)
       if (e) (void)hipEventDestroy(e);
@@ -50,6 +41,95 @@ void free_geom(sbie_geom* g) {
 }
 
 }  // namespace
+
+sbie_status check_particles(const double* centers, const double* quats, const double* A, const double* C,
+                            int32_t M, int32_t p, double eta, std::vector<Particle>* out) {
+  if (!centers || !quats || !A || !C) return invalid("particle array is NULL");
+  if (M < 1) return invalid("M must be >= 1");
+  if (p < 1 || p > kMaxP) return invalid("p must be in [1, 32]");
+  if (!(eta >= 0.0) || !std::isfinite(eta)) return invalid("eta must be finite and >= 0");
+  out->assign(M, Particle{});
+  for (int i = 0; i < M; ++i) {
+    const double* c = centers + 3 * i;
+    const double* q = quats + 4 * i;
+    bool finite = std::isfinite(A[i]) && std::isfinite(C[i]);
+    for (int k = 0; k < 3; ++k) finite = finite && std::isfinite(c[k]);
+    for (int k = 0; k < 4; ++k) finite = finite && std::isfinite(q[k]);
+    if (!finite) return invalid("non-finite particle parameter at particle " + std::to_string(i));
+    const double qn = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    if (std::fabs(qn - 1.0) > 1e-6) return invalid("quaternion of particle " + std::to_string(i) + " is not unit");
+    const double mx = std::fmax(A[i], C[i]);
+    if (!(A[i] > 0.0) || !(C[i] > 0.0) || std::fabs(A[i] - C[i]) <= 1e-6 * mx) {
+      set_error("particle " + std::to_string(i) + " is a sphere or has a non-positive semi-axis");
+      return SBIE_E_DEGENERATE;
+    }
+    Particle& P = (*out)[i];
+    std::memset(&P, 0, sizeof P);
+    for (int k = 0; k < 3; ++k) P.c[k] = c[k];
+    const double w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
+    P.R[0] = 1 - 2 * (y * y + z * z);
+    P.R[1] = 2 * (x * y - w * z);
+    P.R[2] = 2 * (x * z + w * y);
+    P.R[3] = 2 * (x * y + w * z);
+    P.R[4] = 1 - 2 * (x * x + z * z);
+    P.R[5] = 2 * (y * z - w * x);
+    P.R[6] = 2 * (x * z - w * y);
+    P.R[7] = 2 * (y * z + w * x);
+    P.R[8] = 1 - 2 * (x * x + y * y);
+    P.A = A[i];
+    P.C = C[i];
+    P.oblate = C[i] < A[i];
+    P.a = P.oblate ? std::sqrt((A[i] - C[i]) * (A[i] + C[i])) : std::sqrt((C[i] - A[i]) * (C[i] + A[i]));
+    P.u0 = C[i] / P.a;
+    P.w0 = P.oblate ? (P.u0 * P.u0 + 1.0) : (P.u0 - 1.0) * (P.u0 + 1.0);
+    P.diam = 2.0 * mx;
+  }
+  return SBIE_OK;
+}
+
+sbie_status make_geometry(sbie_ctx* ctx, std::vector<Particle>&& parts, int32_t p, double eta, char* blk,
+                          size_t blk_bytes, sbie_geom** out) {
+  *out = nullptr;
+  SBIE_HIP(hipSetDevice(ctx->device));
+  sbie_geom* g = new (std::nothrow) sbie_geom;
+  if (!g) return SBIE_E_NOMEM;
+  const int M = (int)parts.size();
+  g->ctx = ctx;
+  g->M = M;
+  g->p = p;
+  g->Nphi = 2 * p + 2;
+  g->T = (p + 1) * g->Nphi;
+  g->K = (p + 1) * (p + 1);
+  g->Kh = (p + 1) * (p + 2) / 2;
+  g->N = (int64_t)M * g->T;
+  g->eta = eta;
+  g->h_part = std::move(parts);
+  g->blk = blk;
+  g->blk_bytes = blk_bytes;
+  g->blk_owned = false;
+  sbie_status st = setup_geometry(g, ctx->stream);
+  if (st != SBIE_OK) {
+    (void)hipStreamSynchronize(ctx->stream);
+    free_geom(g);
+    return st;
+  }
+  ++ctx->live_geoms;
+  *out = g;
+  return SBIE_OK;
+}
+
+void destroy_geometry(sbie_geom* g) {
+  if (!g) return;
+  sbie_ctx* ctx = g->ctx;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  free_geom(g);
+  if (--ctx->live_geoms == 0 && ctx->closing) {
+    ctx->closing = false;
+    sbie_ctx_destroy(ctx);
+  }
+}
+
 }  // namespace sbie
 
 using namespace sbie;
@@ -110,87 +190,13 @@ sbie_status sbie_geom_create(sbie_ctx* ctx, const double* centers, const double*
   if (!out) return invalid("out is NULL");
   *out = nullptr;
   if (!ctx) return invalid("ctx is NULL");
-  if (!centers || !quats || !A || !C) return invalid("particle array is NULL");
-  if (M < 1) return invalid("M must be >= 1");
-  if (p < 1 || p > kMaxP) return invalid("p must be in [1, 32]");
-  if (!(eta >= 0.0) || !std::isfinite(eta)) return invalid("eta must be finite and >= 0");
-  SBIE_HIP(hipSetDevice(ctx->device));
-  sbie_geom* g = new (std::nothrow) sbie_geom;
-  if (!g) return SBIE_E_NOMEM;
-  g->ctx = ctx;
-  g->M = M;
-  g->p = p;
-  g->Nphi = 2 * p + 2;
-  g->T = (p + 1) * g->Nphi;
-  g->K = (p + 1) * (p + 1);
-  g->Kh = (p + 1) * (p + 2) / 2;
-  g->N = (int64_t)M * g->T;
-  g->eta = eta;
-  g->h_part.resize(M);
-  for (int i = 0; i < M; ++i) {
-    const double* c = centers + 3 * i;
-    const double* q = quats + 4 * i;
-    bool finite = std::isfinite(A[i]) && std::isfinite(C[i]);
-    for (int k = 0; k < 3; ++k) finite = finite && std::isfinite(c[k]);
-    for (int k = 0; k < 4; ++k) finite = finite && std::isfinite(q[k]);
-    if (!finite) {
-      delete g;
-      return invalid("non-finite particle parameter at particle " + std::to_string(i));
-    }
-    const double qn = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-    if (std::fabs(qn - 1.0) > 1e-6) {
-      delete g;
-      return invalid("quaternion of particle " + std::to_string(i) + " is not unit");
-    }
-    const double mx = std::fmax(A[i], C[i]);
-    if (!(A[i] > 0.0) || !(C[i] > 0.0) || std::fabs(A[i] - C[i]) <= 1e-6 * mx) {
-      delete g;
-      set_error("particle " + std::to_string(i) + " is a sphere or has a non-positive semi-axis");
-      return SBIE_E_DEGENERATE;
-    }
-    Particle& P = g->h_part[i];
-    std::memset(&P, 0, sizeof P);
-    for (int k = 0; k < 3; ++k) P.c[k] = c[k];
-    const double w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
-    P.R[0] = 1 - 2 * (y * y + z * z);
-    P.R[1] = 2 * (x * y - w * z);
-    P.R[2] = 2 * (x * z + w * y);
-    P.R[3] = 2 * (x * y + w * z);
-    P.R[4] = 1 - 2 * (x * x + z * z);
-    P.R[5] = 2 * (y * z - w * x);
-    P.R[6] = 2 * (x * z - w * y);
-    P.R[7] = 2 * (y * z + w * x);
-    P.R[8] = 1 - 2 * (x * x + y * y);
-    P.A = A[i];
-    P.C = C[i];
-    P.oblate = C[i] < A[i];
-    P.a = P.oblate ? std::sqrt((A[i] - C[i]) * (A[i] + C[i])) : std::sqrt((C[i] - A[i]) * (C[i] + A[i]));
-    P.u0 = C[i] / P.a;
-    P.w0 = P.oblate ? (P.u0 * P.u0 + 1.0) : (P.u0 - 1.0) * (P.u0 + 1.0);
-    P.diam = 2.0 * mx;
-  }
-  sbie_status st = setup_geometry(g, ctx->stream);
-  if (st != SBIE_OK) {
-    (void)hipStreamSynchronize(ctx->stream);
-    free_geom(g);
-    return st;
-  }
-  ++ctx->live_geoms;
-  *out = g;
-  return SBIE_OK;
+  std::vector<Particle> parts;
+  sbie_status st = check_particles(centers, quats, A, C, M, p, eta, &parts);
+  if (st != SBIE_OK) return st;
+  return make_geometry(ctx, std::move(parts), p, eta, nullptr, 0, out);
 }
 
-void sbie_geom_destroy(sbie_geom* g) {
-  if (!g) return;
-  sbie_ctx* ctx = g->ctx;
-  (void)hipSetDevice(ctx->device);
-  (void)hipStreamSynchronize(ctx->stream);
-  free_geom(g);
-  if (--ctx->live_geoms == 0 && ctx->closing) {
-    ctx->closing = false;
-    sbie_ctx_destroy(ctx);
-  }
-}
+void sbie_geom_destroy(sbie_geom* g) { destroy_geometry(g); }
 
 int64_t sbie_geom_num_nodes(const sbie_geom* g) { return g ? g->N : 0; }
 int64_t sbie_geom_num_near_pairs(const sbie_geom* g) { return g ? g->n_near : 0; }

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -48,7 +49,7 @@ struct Timing {
 struct sbie_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
-  int live_geoms = 0;     // geometries created on this context and not yet destroyed
+  std::atomic<int> live_geoms{0};  // geometries created on this context and not yet destroyed
   bool closing = false;   // sbie_ctx_destroy called while geometries were live
 };
 
@@ -124,6 +125,15 @@ struct sbie_geom {
   double* d_rcp = nullptr;        // [kRcpN] reciprocals 1/k for the near-field recurrences
   int nsplit = 8;
   uint64_t footprint = 0;
+  // device memory: one block carved into every buffer above (owned, or lent by
+  // a server arena), and a second owned block for the Stokes buffers when the
+  // first has no room reserved for them
+  char* blk = nullptr;
+  size_t blk_bytes = 0, blk_used = 0;
+  bool blk_owned = false;
+  char* stk_blk = nullptr;
+  bool stokes_ready = false;
+  uint8_t* d_near_scratch = nullptr;  // [M][M] near flags of the classification
 
   sbie::Timing timing;
 };
@@ -133,11 +143,52 @@ namespace sbie {
 void set_error(const std::string& msg);
 sbie_status device_error(hipError_t e, const char* what);
 
+// Carves 256-byte aligned buffers out of one device block; with no block it
+// only measures.
+struct Carver {
+  char* base = nullptr;
+  size_t size = 0, used = 0;
+  template <typename Tp>
+  sbie_status take(Tp** p, size_t count) {
+    used = (used + 255) & ~size_t(255);
+    const size_t bytes = count * sizeof(Tp);
+    if (base) {
+      if (used + bytes > size) {
+        set_error("device block too small for the geometry's buffers");
+        return SBIE_E_NOMEM;
+      }
+      *p = reinterpret_cast<Tp*>(base + used);
+    }
+    used += bytes;
+    return SBIE_OK;
+  }
+};
+
+// Buffers of a geometry (setup tables, work buffers, classification scratch)
+// and of the Stokes single layer, in carving order; measuring with an empty
+// Carver gives the exact block size.
+sbie_status carve_geometry(sbie_geom* g, Carver& c);
+sbie_status carve_stokes(sbie_geom* g, Carver& c);
+// Exact device bytes of a geometry of M particles at order p (with the Stokes
+// buffers if stokes), as carved.
+uint64_t plan_bytes(int M, int p, bool stokes);
+// Allocates (or carves from the block's reserve) the Stokes buffers once.
+sbie_status stokes_buffers(sbie_geom* g);
+
 #define SBIE_HIP(call)                                              \
   do {                                                              \
     hipError_t _e = (call);                                         \
     if (_e != hipSuccess) return ::sbie::device_error(_e, #call);   \
   } while (0)
+
+// geometry construction (capi.hip): host checks and per-particle parameters;
+// a geometry on ctx's stream, in a lent device block (blk) or in one of its own
+// (blk == nullptr); destruction
+sbie_status check_particles(const double* centers, const double* quats, const double* A, const double* C,
+                            int32_t M, int32_t p, double eta, std::vector<Particle>* out);
+sbie_status make_geometry(sbie_ctx* ctx, std::vector<Particle>&& parts, int32_t p, double eta, char* blk,
+                          size_t blk_bytes, sbie_geom** out);
+void destroy_geometry(sbie_geom* g);
 
 // setup kernels (setup.hip)
 sbie_status setup_geometry(sbie_geom* g, hipStream_t s);

@@ -311,19 +311,6 @@ __global__ void k_classify(const Particle* __restrict__ part, int M, double eta,
   if (near_b) near[(size_t)bidx * M + a] = 1;   // target a near source bidx
 }
 
-template <typename Tp>
-sbie_status dev_alloc(Tp** p, size_t count, uint64_t* footprint) {
-  hipError_t e = hipMalloc((void**)p, count * sizeof(Tp));
-  if (e != hipSuccess) {
-    *p = nullptr;
-    (void)hipGetLastError();
-    set_error("device allocation of " + std::to_string(count * sizeof(Tp)) + " bytes failed");
-    return SBIE_E_NOMEM;
-  }
-  *footprint += count * sizeof(Tp);
-  return SBIE_OK;
-}
-
 void gauss_legendre_host(int n, double* x, double* w) {
   for (int i = 0; i < n; ++i) {
     double t = std::cos(kPi * (i + 0.75) / (n + 0.5)), dp = 1.0;
@@ -359,35 +346,103 @@ void gauss_legendre_host(int n, double* x, double* w) {
     if (_s != SBIE_OK) return _s;           \
   } while (0)
 
+sbie_status carve_geometry(sbie_geom* g, Carver& c) {
+  const int M = g->M, p = g->p, T = g->T, K = g->K, Kh = g->Kh;
+  const int64_t N = g->N;
+  const int Kh2 = (p + 2) * (p + 3) / 2;
+  const size_t n16 = (size_t)M * (16 * ((T + 15) / 16));
+  const int words = (M + 31) / 32;
+  SBIE_TRY(c.take(&g->d_part, M));
+  SBIE_TRY(c.take(&g->d_x, N));
+  SBIE_TRY(c.take(&g->d_y, N));
+  SBIE_TRY(c.take(&g->d_z, N));
+  SBIE_TRY(c.take(&g->d_nx, N));
+  SBIE_TRY(c.take(&g->d_ny, N));
+  SBIE_TRY(c.take(&g->d_nz, N));
+  SBIE_TRY(c.take(&g->d_w, N));
+  SBIE_TRY(c.take(&g->d_off32, 4 * N));
+  SBIE_TRY(c.take(&g->d_gl, 2 * (p + 1)));
+  SBIE_TRY(c.take(&g->d_An, (size_t)T * K));
+  SBIE_TRY(c.take(&g->d_Sy, (size_t)K * T));
+  SBIE_TRY(c.take(&g->d_An32, (size_t)T * K));
+  SBIE_TRY(c.take(&g->d_Sy32, (size_t)K * T));
+  SBIE_TRY(c.take(&g->d_wS, (size_t)M * (p + 1)));
+  SBIE_TRY(c.take(&g->d_Sv, (size_t)K * T));
+  SBIE_TRY(c.take(&g->d_Sp, (size_t)K * T));
+  SBIE_TRY(c.take(&g->d_Sv32, (size_t)K * T));
+  SBIE_TRY(c.take(&g->d_Sp32, (size_t)K * T));
+  SBIE_TRY(c.take(&g->d_lam, (size_t)M * Kh * 4));
+  SBIE_TRY(c.take(&g->d_dlr, (size_t)M * Kh));
+  // Ferrers recurrence coefficients through degree p+1 (derivatives need Pb_{p+1})
+  SBIE_TRY(c.take(&g->d_ab, (size_t)Kh2 * 2));
+  SBIE_TRY(c.take(&g->d_cd, (size_t)Kh));
+  SBIE_TRY(c.take(&g->d_status, 1));
+  SBIE_TRY(c.take(&g->d_near_scratch, (size_t)M * M));
+  SBIE_TRY(c.take(&g->d_near_ptr, M + 1));
+  // near sources: at most M(M-1) directed pairs
+  SBIE_TRY(c.take(&g->d_near_src, std::max<size_t>(1, (size_t)M * (M - 1))));
+  SBIE_TRY(c.take(&g->d_excl, (size_t)M * words));
+  SBIE_TRY(c.take(&g->d_f, (size_t)M * T));
+  SBIE_TRY(c.take(&g->d_coef, (size_t)M * K));
+  SBIE_TRY(c.take(&g->d_cself, (size_t)M * K));
+  SBIE_TRY(c.take(&g->d_E, (size_t)M * K));
+  SBIE_TRY(c.take(&g->d_uself, N));
+  SBIE_TRY(c.take(&g->d_unear, N));
+  SBIE_TRY(c.take(&g->d_src, 8 * N));
+  SBIE_TRY(c.take(&g->d_partial, (size_t)g->nsplit * N));
+  SBIE_TRY(c.take(&g->d_dens, N));
+  SBIE_TRY(c.take(&g->d_out, N));
+  SBIE_TRY(c.take(&g->d_srec64, 5 * n16));
+  SBIE_TRY(c.take(&g->d_srec32, 5 * n16));
+  SBIE_TRY(c.take(&g->d_fstr64, 5 * n16));
+  SBIE_TRY(c.take(&g->d_fstr32, 5 * n16));
+  SBIE_TRY(c.take(&g->d_rcp, (size_t)kRcpN));
+  return SBIE_OK;
+}
+
+uint64_t plan_bytes(int M, int p, bool stokes) {
+  sbie_geom g;
+  g.M = M;
+  g.p = p;
+  g.Nphi = 2 * p + 2;
+  g.T = (p + 1) * g.Nphi;
+  g.K = (p + 1) * (p + 1);
+  g.Kh = (p + 1) * (p + 2) / 2;
+  g.N = (int64_t)M * g.T;
+  Carver c;
+  (void)carve_geometry(&g, c);
+  if (stokes) (void)carve_stokes(&g, c);
+  return (c.used + 255) & ~uint64_t(255);
+}
+
 sbie_status setup_geometry(sbie_geom* g, hipStream_t s) {
   const int M = g->M, p = g->p, T = g->T, K = g->K, Kh = g->Kh;
   const int64_t N = g->N;
-  uint64_t& fp = g->footprint;
-  SBIE_TRY(dev_alloc(&g->d_part, M, &fp));
-  SBIE_TRY(dev_alloc(&g->d_x, N, &fp));
-  SBIE_TRY(dev_alloc(&g->d_y, N, &fp));
-  SBIE_TRY(dev_alloc(&g->d_z, N, &fp));
-  SBIE_TRY(dev_alloc(&g->d_nx, N, &fp));
-  SBIE_TRY(dev_alloc(&g->d_ny, N, &fp));
-  SBIE_TRY(dev_alloc(&g->d_nz, N, &fp));
-  SBIE_TRY(dev_alloc(&g->d_w, N, &fp));
-  SBIE_TRY(dev_alloc(&g->d_off32, 4 * N, &fp));
-  SBIE_TRY(dev_alloc(&g->d_gl, 2 * (p + 1), &fp));
-  SBIE_TRY(dev_alloc(&g->d_An, (size_t)T * K, &fp));
-  SBIE_TRY(dev_alloc(&g->d_Sy, (size_t)K * T, &fp));
-  SBIE_TRY(dev_alloc(&g->d_An32, (size_t)T * K, &fp));
-  SBIE_TRY(dev_alloc(&g->d_Sy32, (size_t)K * T, &fp));
-  SBIE_TRY(dev_alloc(&g->d_wS, (size_t)M * (p + 1), &fp));
-  SBIE_TRY(dev_alloc(&g->d_Sv, (size_t)K * T, &fp));
-  SBIE_TRY(dev_alloc(&g->d_Sp, (size_t)K * T, &fp));
-  SBIE_TRY(dev_alloc(&g->d_Sv32, (size_t)K * T, &fp));
-  SBIE_TRY(dev_alloc(&g->d_Sp32, (size_t)K * T, &fp));
-  SBIE_TRY(dev_alloc(&g->d_lam, (size_t)M * Kh * 4, &fp));
-  SBIE_TRY(dev_alloc(&g->d_dlr, (size_t)M * Kh, &fp));
-  // Ferrers recurrence coefficients through degree p+1 (derivatives need Pb_{p+1})
+  (void)K;
+  // one block for every buffer: lent by the caller (g->blk set), else owned
+  if (!g->blk) {
+    Carver measure;
+    SBIE_TRY(carve_geometry(g, measure));
+    const size_t bytes = (measure.used + 255) & ~size_t(255);
+    hipError_t e = hipMalloc((void**)&g->blk, bytes);
+    if (e != hipSuccess) {
+      g->blk = nullptr;
+      (void)hipGetLastError();
+      set_error("device allocation of " + std::to_string(bytes) + " bytes failed");
+      return SBIE_E_NOMEM;
+    }
+    g->blk_bytes = bytes;
+    g->blk_owned = true;
+  }
+  {
+    Carver c;
+    c.base = g->blk;
+    c.size = g->blk_bytes;
+    SBIE_TRY(carve_geometry(g, c));
+    g->blk_used = c.used;
+  }
+  g->footprint = g->blk_bytes;
   const int Kh2 = (p + 2) * (p + 3) / 2;
-  SBIE_TRY(dev_alloc(&g->d_ab, (size_t)Kh2 * 2, &fp));
-  SBIE_TRY(dev_alloc(&g->d_cd, (size_t)Kh, &fp));
   {
     std::vector<double> cd(Kh, 0.0);
     for (int n = 0; n <= p; ++n)
@@ -396,7 +451,6 @@ sbie_status setup_geometry(sbie_geom* g, hipStream_t s) {
     SBIE_HIP(hipMemcpyAsync(g->d_cd, cd.data(), sizeof(double) * Kh, hipMemcpyHostToDevice, s));
     SBIE_HIP(hipStreamSynchronize(s));
   }
-  SBIE_TRY(dev_alloc(&g->d_status, 1, &fp));
 
   std::vector<double> gl(2 * (p + 1));
   gauss_legendre_host(p + 1, gl.data(), gl.data() + p + 1);
@@ -429,9 +483,7 @@ sbie_status setup_geometry(sbie_geom* g, hipStream_t s) {
   SBIE_HIP(hipGetLastError());
 
   // near/far split
-  uint8_t* d_near = nullptr;
-  uint64_t scratch_fp = 0;
-  SBIE_TRY(dev_alloc(&d_near, (size_t)M * M, &scratch_fp));
+  uint8_t* d_near = g->d_near_scratch;
   SBIE_HIP(hipMemsetAsync(d_near, 0, (size_t)M * M, s));
   const int64_t npairs = (int64_t)M * (M - 1) / 2;
   if (npairs > 0) {
@@ -444,7 +496,6 @@ sbie_status setup_geometry(sbie_geom* g, hipStream_t s) {
   SBIE_HIP(hipMemcpyAsync(near.data(), d_near, near.size(), hipMemcpyDeviceToHost, s));
   SBIE_HIP(hipMemcpyAsync(&status, g->d_status, sizeof(unsigned), hipMemcpyDeviceToHost, s));
   SBIE_HIP(hipStreamSynchronize(s));
-  SBIE_HIP(hipFree(d_near));
   if (status & kStatOverlap) {
     set_error("two particles touch or overlap");
     return SBIE_E_OVERLAP;
@@ -476,39 +527,17 @@ sbie_status setup_geometry(sbie_geom* g, hipStream_t s) {
   }
   g->n_near = (int64_t)g->h_near_src.size();
   g->far_pairs = ((int64_t)M * M - excluded_pairs) * (int64_t)T * T;
-  SBIE_TRY(dev_alloc(&g->d_near_ptr, M + 1, &fp));
-  SBIE_TRY(dev_alloc(&g->d_near_src, std::max<int64_t>(1, g->n_near), &fp));
-  SBIE_TRY(dev_alloc(&g->d_excl, excl.size(), &fp));
   SBIE_HIP(hipMemcpyAsync(g->d_near_ptr, g->h_near_ptr.data(), sizeof(int32_t) * (M + 1), hipMemcpyHostToDevice, s));
   if (g->n_near)
     SBIE_HIP(hipMemcpyAsync(g->d_near_src, g->h_near_src.data(), sizeof(int32_t) * g->n_near,
                             hipMemcpyHostToDevice, s));
   SBIE_HIP(hipMemcpyAsync(g->d_excl, excl.data(), sizeof(uint32_t) * excl.size(), hipMemcpyHostToDevice, s));
 
-  // work buffers
-  SBIE_TRY(dev_alloc(&g->d_f, (size_t)M * T, &fp));
-  SBIE_TRY(dev_alloc(&g->d_coef, (size_t)M * K, &fp));
-  SBIE_TRY(dev_alloc(&g->d_cself, (size_t)M * K, &fp));
-  SBIE_TRY(dev_alloc(&g->d_E, (size_t)M * K, &fp));
-  SBIE_TRY(dev_alloc(&g->d_uself, N, &fp));
-  SBIE_TRY(dev_alloc(&g->d_unear, N, &fp));
-  SBIE_TRY(dev_alloc(&g->d_src, 8 * N, &fp));
-  SBIE_TRY(dev_alloc(&g->d_partial, (size_t)g->nsplit * N, &fp));
-  SBIE_TRY(dev_alloc(&g->d_dens, N, &fp));
-  SBIE_TRY(dev_alloc(&g->d_out, N, &fp));
   g->T16 = 16 * ((T + 15) / 16);
-  {
-    const size_t n16 = (size_t)M * g->T16;
-    SBIE_TRY(dev_alloc(&g->d_srec64, 5 * n16, &fp));
-    SBIE_TRY(dev_alloc(&g->d_srec32, 5 * n16, &fp));
-    SBIE_TRY(dev_alloc(&g->d_fstr64, 5 * n16, &fp));
-    SBIE_TRY(dev_alloc(&g->d_fstr32, 5 * n16, &fp));
-  }
   SBIE_TRY(far_records(g, s));
   {
     std::vector<double> rcp(kRcpN, 0.0);
     for (int k = 1; k < kRcpN; ++k) rcp[k] = 1.0 / (double)k;
-    SBIE_TRY(dev_alloc(&g->d_rcp, (size_t)kRcpN, &fp));
     SBIE_HIP(hipMemcpyAsync(g->d_rcp, rcp.data(), sizeof(double) * kRcpN, hipMemcpyHostToDevice, s));
   }
 

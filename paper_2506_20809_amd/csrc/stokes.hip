@@ -451,20 +451,6 @@ __global__ void k_stokes_assemble(const double* __restrict__ uself, const double
   out[t] = u;
 }
 
-template <typename Tp>
-sbie_status alloc_work(Tp** p, size_t count, uint64_t* fp) {
-  if (*p) return SBIE_OK;
-  hipError_t e = hipMalloc((void**)p, count * sizeof(Tp));
-  if (e != hipSuccess) {
-    *p = nullptr;
-    (void)hipGetLastError();
-    set_error("device allocation of the Stokes work buffers failed");
-    return SBIE_E_NOMEM;
-  }
-  *fp += count * sizeof(Tp);
-  return SBIE_OK;
-}
-
 template <int PMAX>
 void launch_near_stokes(sbie_geom* g, hipStream_t s) {
   const int chunks = (g->T + 63) / 64;
@@ -475,10 +461,59 @@ void launch_near_stokes(sbie_geom* g, hipStream_t s) {
 
 }  // namespace
 
+#define SBIE_TRY_C(expr)            \
+  do {                              \
+    sbie_status _s = (expr);        \
+    if (_s != SBIE_OK) return _s;   \
+  } while (0)
+
+sbie_status carve_stokes(sbie_geom* g, Carver& c) {
+  const size_t MT4 = (size_t)4 * g->M * g->T, MK4 = (size_t)4 * g->M * g->K;
+  const size_t N = (size_t)g->N;
+  SBIE_TRY_C(c.take(&g->d_stk_f, MT4));
+  SBIE_TRY_C(c.take(&g->d_stk_c, MK4));
+  SBIE_TRY_C(c.take(&g->d_stk_E, 2 * MK4));
+  SBIE_TRY_C(c.take(&g->d_stk_U, 4 * MT4));
+  SBIE_TRY_C(c.take(&g->d_stk_src, 8 * N));
+  SBIE_TRY_C(c.take(&g->d_stk_part, (size_t)g->nsplit * 3 * N));
+  SBIE_TRY_C(c.take(&g->d_stk_self, 3 * N));
+  SBIE_TRY_C(c.take(&g->d_stk_near, 3 * N));
+  SBIE_TRY_C(c.take(&g->d_stk_io, 6 * N));
+  return SBIE_OK;
+}
+
+sbie_status stokes_buffers(sbie_geom* g) {
+  if (g->stokes_ready) return SBIE_OK;
+  Carver measure;
+  SBIE_TRY_C(carve_stokes(g, measure));
+  const size_t bytes = (measure.used + 255) & ~size_t(255);
+  Carver c;
+  const size_t start = (g->blk_used + 255) & ~size_t(255);
+  if (g->blk && g->blk_bytes >= start + bytes) {
+    // room reserved in the geometry's block, after its own buffers
+    c.base = g->blk + start;
+    c.size = g->blk_bytes - start;
+  } else {
+    hipError_t e = hipMalloc((void**)&g->stk_blk, bytes);
+    if (e != hipSuccess) {
+      g->stk_blk = nullptr;
+      (void)hipGetLastError();
+      set_error("device allocation of the Stokes work buffers failed");
+      return SBIE_E_NOMEM;
+    }
+    g->footprint += bytes;
+    c.base = g->stk_blk;
+    c.size = bytes;
+  }
+  SBIE_TRY_C(carve_stokes(g, c));
+  g->stokes_ready = true;
+  return SBIE_OK;
+}
+
 sbie_status stokes_staging(sbie_geom* g, double** io) {
-  sbie_status st = alloc_work(&g->d_stk_io, (size_t)6 * g->N, &g->footprint);
+  SBIE_TRY_C(stokes_buffers(g));
   *io = g->d_stk_io;
-  return st;
+  return SBIE_OK;
 }
 
 sbie_status apply_stokes(sbie_geom* g, int prec, const double* d_dens, double* d_out, hipStream_t s,
@@ -487,16 +522,8 @@ sbie_status apply_stokes(sbie_geom* g, int prec, const double* d_dens, double* d
   const int64_t N = g->N;
   const bool mixed = prec == SBIE_MIXED;
   const size_t MT4 = (size_t)4 * M * T, MK4 = (size_t)4 * M * K;
-  uint64_t& fp = g->footprint;
   sbie_status st;
-  if ((st = alloc_work(&g->d_stk_f, MT4, &fp)) != SBIE_OK) return st;
-  if ((st = alloc_work(&g->d_stk_c, MK4, &fp)) != SBIE_OK) return st;
-  if ((st = alloc_work(&g->d_stk_E, 2 * MK4, &fp)) != SBIE_OK) return st;
-  if ((st = alloc_work(&g->d_stk_U, 4 * MT4, &fp)) != SBIE_OK) return st;
-  if ((st = alloc_work(&g->d_stk_src, (size_t)8 * N, &fp)) != SBIE_OK) return st;
-  if ((st = alloc_work(&g->d_stk_part, (size_t)g->nsplit * 3 * N, &fp)) != SBIE_OK) return st;
-  if ((st = alloc_work(&g->d_stk_self, (size_t)3 * N, &fp)) != SBIE_OK) return st;
-  if ((st = alloc_work(&g->d_stk_near, (size_t)3 * N, &fp)) != SBIE_OK) return st;
+  SBIE_TRY_C(stokes_buffers(g));
 
   Timing& tm = g->timing;
   hipEvent_t* ev = nullptr;
@@ -548,8 +575,6 @@ sbie_status apply_stokes(sbie_geom* g, int prec, const double* d_dens, double* d
     else
       launch_near_stokes<32>(g, s);
     SBIE_HIP(hipGetLastError());
-  } else if (parts & SBIE_PARTS_NEAR) {
-    SBIE_HIP(hipMemsetAsync(g->d_stk_near, 0, sizeof(double) * 3 * N, s));
   }
   if (timed) SBIE_HIP(hipEventRecord(ev[3], s));
   if (parts & SBIE_PARTS_FAR) {
@@ -565,8 +590,10 @@ sbie_status apply_stokes(sbie_geom* g, int prec, const double* d_dens, double* d
     SBIE_HIP(hipGetLastError());
   }
   if (timed) SBIE_HIP(hipEventRecord(ev[4], s));
+  // with no near pairs the near part is empty and is left out of the sum
+  const uint32_t sum_parts = g->n_near > 0 ? parts : (parts & ~(uint32_t)SBIE_PARTS_NEAR);
   hipLaunchKernelGGL(k_stokes_assemble, dim3(cdiv(3 * N, B)), dim3(B), 0, s, g->d_stk_self, g->d_stk_near,
-                     g->d_stk_part, g->nsplit, N, parts, d_out);
+                     g->d_stk_part, g->nsplit, N, sum_parts, d_out);
   SBIE_HIP(hipGetLastError());
   if (timed) SBIE_HIP(hipEventRecord(ev[5], s));
   return SBIE_OK;

@@ -100,6 +100,191 @@ def run(g, dens, steps, warmup, precision):
     }
 
 
+# Stokeslet per far node pair: 3 differences + 5 for r^2 + 1 rsqrt + 2 for r^-3 + 5 for r.q
+# + 1 for (r.q) r^-3 + 3 x (FMA for q/r + FMA for r (r.q) r^-3) = 29
+FLOPS_PER_STOKES_PAIR = 29
+
+
+def run_stokes(ctx, steps, warmup, precision):
+    """Stokes single layer (Eq. stokes) on the 256-spheroid suspension at p = 12."""
+    import numpy as np
+    import torch
+
+    import paper_2506_20809_amd as sbie
+    import workloads
+
+    geom = workloads.geometry("c4")
+    p = workloads.CONFIGS["c4"]["p"]
+    g = sbie.Geometry(ctx, geom, p)
+    prec = sbie.SBIE_MIXED if precision == "mixed" else sbie.SBIE_FP64
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(4)
+    dens = torch.randn((steps + warmup, 3, g.N), dtype=torch.float64, device="cuda", generator=gen)
+    out = torch.empty((3, g.N), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    for k in range(warmup):
+        g.apply(sbie.SBIE_OP_STOKES_S, dens[k], precision=prec, out=out, timing=True)
+    g.sync()
+    g.timing()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record(stream)
+        g.apply(sbie.SBIE_OP_STOKES_S, dens[warmup + k], precision=prec, out=out, timing=True)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    g.sync()
+    tim = g.timing()
+    lat = np.array([e[0].elapsed_time(e[1]) for e in ev])
+    achieved = FLOPS_PER_STOKES_PAIR * tim.far_pairs / (tim.far_kernel_ms * 1e-3) / 1e12
+    res = {
+        "workload": f"256 polydisperse spheroids (volume fraction 0.20, gap 0.05), p={p}, N={g.N}, "
+                    f"3-component density, precision={precision}",
+        "applies_per_s": steps / elapsed,
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "part_ms": {"prep": tim.prep_ms, "transform_self": tim.transform_ms, "near": tim.near_ms,
+                    "far_kernel": tim.far_kernel_ms, "assemble": tim.assemble_ms, "apply_total": tim.total_ms},
+        "far_pairs": tim.far_pairs,
+        "far_pair_interactions_per_s": tim.far_pairs / (tim.far_kernel_ms * 1e-3),
+        "far_roofline_frac": achieved / PEAK_TFLOPS[precision],
+    }
+    g.close()
+    return res
+
+
+def served(ctx, n_requests, rho, precision, max_sessions, napply=20, budget=64 << 30):
+    """Served mode on the request stream (Section 4 use as a Krylov inner loop):
+    n_requests sessions of napply closed-loop applies each.
+
+    1. Plain path, back to back: one request at a time (geometry build, napply
+       applies, release) -> service times s_i and the capacity mu = n / sum s_i.
+    2. Served, saturated: every request arrives at t = 0 -> served throughput.
+    3. Served at Poisson arrivals of rate rho * mu -> request latency
+       (arrival to last apply) and per-apply latency, p50/p99.  The plain path
+       under the same arrivals is a single FIFO server; its latencies follow
+       from the measured s_i (done_i = max(a_i, done_{i-1}) + s_i)."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    import paper_2506_20809_amd as sbie
+    import workloads
+
+    reqs = workloads.served_stream(n_requests)
+    geoms = [workloads.served_request(r) for r in reqs]
+    prec = sbie.SBIE_MIXED if precision == "mixed" else sbie.SBIE_FP64
+
+    def density(r, k, N):
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(r["seed"] * 64 + k)
+        return torch.randn(N, dtype=torch.float64, device="cuda", generator=gen)
+
+    # 1. plain path
+    service, far_pairs, plain_apply_ms = [], [], []
+    for r, geom in zip(reqs, geoms):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = sbie.Geometry(ctx, geom, r["p"])
+        out = torch.empty(g.N, dtype=torch.float64, device="cuda")
+        for k in range(napply):
+            d = density(r, k, g.N)
+            ta = time.perf_counter()
+            g.apply(r["op"], d, precision=prec, out=out, timing=(k == 0))
+            g.sync()
+            plain_apply_ms.append(1e3 * (time.perf_counter() - ta))
+        far_pairs.append(g.timing().far_pairs)
+        g.close()
+        service.append(time.perf_counter() - t0)
+    service = np.array(service)
+    mu = n_requests / service.sum()
+    total_pairs = float(np.sum(far_pairs)) * napply
+
+    def run_served(arrivals):
+        srv = sbie.Server(ctx, max_sessions=max_sessions, budget_bytes=budget, graphs=True)
+        done = [0.0] * n_requests
+        apply_ms = []
+        errors = []
+        lock = threading.Lock()
+        t_start = time.perf_counter()
+
+        def client(i):
+            try:
+                r = reqs[i]
+                s = srv.open(geoms[i], r["p"], r["op"], prec)
+                out = torch.empty(s.N, dtype=torch.float64, device="cuda")
+                ms = []
+                for k in range(napply):
+                    _, st = s.apply(density(r, k, s.N), out)
+                    ms.append(1e-3 * (st.end_us - st.submit_us))
+                s.close()
+                done[i] = time.perf_counter() - t_start
+                with lock:
+                    apply_ms.extend(ms)
+            except Exception as e:  # reported by the caller
+                errors.append(repr(e))
+
+        threads = []
+        for i in range(n_requests):
+            wait = arrivals[i] - (time.perf_counter() - t_start)
+            if wait > 0:
+                time.sleep(wait)
+            t = threading.Thread(target=client, args=(i,))
+            t.start()
+            threads.append(t)
+        for t in threads:
+            t.join()
+        info = srv.info()
+        srv.close()
+        if errors:
+            raise RuntimeError(errors[0])
+        lat = np.array(done) - np.array(arrivals)
+        return {"makespan_s": max(done), "request_latency_s": lat, "apply_ms": np.array(apply_ms),
+                "peak_bytes": info.peak_bytes, "passed": info.passed, "waited": info.waited}
+
+    # 2. saturated
+    sat = run_served([0.0] * n_requests)
+    # 3. Poisson arrivals at rho * mu
+    rng = np.random.default_rng(55)
+    arrivals = np.cumsum(rng.exponential(1.0 / (rho * mu), size=n_requests))
+    arrivals -= arrivals[0]
+    srv_run = run_served(list(arrivals))
+    plain_done, t = [], 0.0
+    for a, s_ in zip(arrivals, service):
+        t = max(a, t) + s_
+        plain_done.append(t)
+    plain_lat = np.array(plain_done) - arrivals
+
+    def pct(x):
+        return {"p50": float(np.percentile(x, 50)), "p99": float(np.percentile(x, 99))}
+
+    Ms = np.array([r["M"] for r in reqs])
+    return {
+        "workload": f"{n_requests} requests (particle count log-uniform in [8, 1024] cut from a 0.15 volume "
+                    f"fraction packing, p in {{8, 12, 16}}, S or D), {napply} closed-loop applies each, "
+                    f"precision={precision}, {max_sessions} lanes, HIP graph replay",
+        "mean_particles": float(Ms.mean()),
+        "plain": {"capacity_requests_per_s": mu, "applies_per_s": mu * napply,
+                  "pair_interactions_per_s": total_pairs / service.sum(),
+                  "apply_latency_ms": pct(plain_apply_ms)},
+        "served_saturated": {"requests_per_s": n_requests / sat["makespan_s"],
+                             "applies_per_s": n_requests * napply / sat["makespan_s"],
+                             "pair_interactions_per_s": total_pairs / sat["makespan_s"],
+                             "speedup_vs_plain": (n_requests / sat["makespan_s"]) / mu,
+                             "apply_latency_ms": pct(sat["apply_ms"])},
+        f"poisson_rho_{rho}": {
+            "arrival_rate_per_s": rho * mu,
+            "served_request_latency_s": pct(srv_run["request_latency_s"]),
+            "plain_fifo_request_latency_s": pct(plain_lat),
+            "served_apply_latency_ms": pct(srv_run["apply_ms"]),
+            "served_applies_per_s": n_requests * napply / srv_run["makespan_s"],
+            "peak_arena_bytes": int(srv_run["peak_bytes"]), "admissions_passed": int(srv_run["passed"]),
+        },
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +295,11 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=32768)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the other precision's measurement")
+    ap.add_argument("--no-stokes", action="store_true", help="skip the Stokes single-layer measurement")
+    ap.add_argument("--served-requests", type=int, default=48, help="requests in the served-mode run (0: skip)")
+    ap.add_argument("--served-rho", type=float, default=0.8, help="load of the Poisson arrivals")
+    ap.add_argument("--served-precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--served-lanes", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -166,6 +356,11 @@ def main():
         res[f"{other}_path"] = {k: sec[k] for k in ("applies_per_s", "pair_interactions_per_s", "latency_ms",
                                                     "part_ms")}
         res[f"{other}_path"]["roofline_frac"] = sec["roofline"]["frac"]
+    if not args.no_stokes:
+        res["stokes"] = {pr: run_stokes(ctx, max(4, args.steps // 2), 1, pr) for pr in ("fp64", "mixed")}
+    if args.served_requests > 0:
+        res["served"] = served(ctx, args.served_requests, args.served_rho, args.served_precision,
+                               args.served_lanes)
     if not args.no_cpu_baseline:
         d = dens[0].cpu().numpy()
         res["cpu_baseline"] = cpu_baseline(geom, p, d[0], d[1], N, args.cpu_sample)

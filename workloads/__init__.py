@@ -270,6 +270,8 @@ CONFIGS = {
     "c2": dict(M=64, p=16, phi=0.15, gap=0.05, seed=2),
     "c3": dict(M=512, p=16, phi=0.25, gap=0.02, seed=3),
     "c4": dict(M=256, p=12, phi=0.20, gap=0.05, seed=4),
+    # pool the served requests are cut from (see served_request)
+    "c5_pool": dict(M=1024, phi=0.15, gap=0.05, seed=5),
 }
 
 
@@ -311,6 +313,22 @@ def generate(name: str):
     with open(os.path.join(DATA, f"{name}.json"), "w") as f:
         json.dump(_to_json(g), f)
     return g
+
+
+def served_request(req):
+    """Geometry of one served request: the M particles of the 1024-particle pool
+    packing (volume fraction 0.15, gap 0.05) whose centres lie nearest to a
+    point drawn from the request's seed.  A subset of a valid packing keeps its
+    gaps and near/far margins, and a ball cut from a homogeneous packing keeps
+    its local volume fraction, so requests are drawn in microseconds instead of
+    packing each one anew."""
+    pool = geometry("c5_pool")
+    rng = np.random.default_rng(req["seed"])
+    side = float(pool["side"])
+    x0 = rng.uniform(0.0, side, size=3)
+    d = np.linalg.norm(pool["centers"] - x0, axis=1)
+    idx = np.sort(np.argsort(d, kind="stable")[: req["M"]])
+    return {k: pool[k][idx] for k in ("centers", "quats", "A", "C")}
 
 
 def served_stream(n_requests=2000, seed=5, max_particles=1024):

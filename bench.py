@@ -49,6 +49,23 @@ def cpu_baseline(geom, p, dens_s, dens_d, N, sample):
                       f"{dt:.1f} s, scaled to whole applies"}
 
 
+def counter_traffic(precision, workload):
+    """HBM bytes per far-kernel launch from the committed counter summary, or None
+    when that summary does not cover this workload and precision or the far
+    kernel's source has changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"far_mfma_{workload}_{precision}_hbm_counters.md")
+    src = os.path.join(ROOT, "paper_2506_20809_amd", "csrc", "far_mfma.hip")
+    if not os.path.exists(path):
+        return None
+    kv = dict(line.strip().split("=", 1) for line in open(path) if "=" in line and not line.startswith("|"))
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != kv.get("source_sha256"):
+            return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def run(g, dens, steps, warmup, precision):
     """Time `steps` steps (S then D) on the torch current stream."""
     import numpy as np
@@ -300,6 +317,8 @@ def main():
     ap.add_argument("--served-rho", type=float, default=0.8, help="load of the Poisson arrivals")
     ap.add_argument("--served-precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--served-lanes", type=int, default=8)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain 256 MiB device copy first (a known-size reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -311,6 +330,13 @@ def main():
     import workloads
 
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.calibrate_copy:
+        # an elementwise kernel that reads 256 MiB and writes 256 MiB
+        src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     geom = workloads.geometry(args.workload)
     p = workloads.CONFIGS[args.workload]["p"]
     M = len(geom["A"])
@@ -324,6 +350,7 @@ def main():
     dens = torch.randn((args.steps + args.warmup, 2, N), dtype=torch.float64, device="cuda", generator=gen)
 
     main_run = run(g, dens, args.steps, args.warmup, args.precision)
+    main_run["roofline"]["traffic"] = counter_traffic(args.precision, args.workload)
     res = {
         "metric": "S/D operator applies/sec and pair-interactions/sec at 512 spheroids; p50/p99",
         "value": main_run["applies_per_s"],

@@ -83,15 +83,17 @@ typedef struct sbie_geom sbie_geom;
 
 /* Per-part device times, milliseconds, averaged over the timed applies (one
    per right-hand side) since the previous sbie_geom_timing call; measured with
-   HIP events on the apply's stream.  far_kernel_ms is the far-field direct-sum
-   kernel alone. */
+   HIP events.  The near field runs on a second stream of the geometry,
+   concurrently with the self interaction and the far field, so the parts
+   overlap and do not add up to total_ms.  far_kernel_ms is the far-field
+   direct-sum kernel alone. */
 typedef struct {
   double prep_ms;
   double transform_ms; /* forward transform, spectra scaling, inverse transform */
-  double near_ms;
+  double near_ms;      /* near field, on the geometry's second stream */
   double far_kernel_ms;
-  double assemble_ms;
-  double total_ms;
+  double assemble_ms;  /* from the later of the near and far ends to the end */
+  double total_ms;     /* whole apply on the caller's stream */
   int64_t far_pairs;   /* far-field node pairs evaluated per right-hand side */
   int64_t near_evals;  /* near-field (pair, target) evaluations per right-hand side */
   int64_t count;       /* number of timed applies averaged */

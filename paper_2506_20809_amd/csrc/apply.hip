@@ -490,20 +490,38 @@ void launch_near(sbie_geom* g, hipStream_t s) {
 
 }  // namespace
 
+sbie_status next_timing_set(sbie_geom* g, hipEvent_t** ev) {
+  Timing& tm = g->timing;
+  if (tm.used == tm.sets.size()) {
+    std::vector<hipEvent_t> set(8, nullptr);
+    for (int e = 0; e < 8; ++e) SBIE_HIP(hipEventCreate(&set[e]));
+    tm.sets.push_back(set);
+  }
+  *ev = tm.sets[tm.used++].data();
+  return SBIE_OK;
+}
+
+sbie_status fork_side(sbie_geom* g, hipStream_t s) {
+  SBIE_HIP(hipEventRecord(g->ev_fork, s));
+  SBIE_HIP(hipStreamWaitEvent(g->side, g->ev_fork, 0));
+  return SBIE_OK;
+}
+
+sbie_status join_side(sbie_geom* g, hipStream_t s) {
+  SBIE_HIP(hipEventRecord(g->ev_join, g->side));
+  SBIE_HIP(hipStreamWaitEvent(s, g->ev_join, 0));
+  return SBIE_OK;
+}
+
 sbie_status apply_laplace(sbie_geom* g, int op, int prec, const double* d_dens, double* d_out, hipStream_t s,
                           uint32_t parts, bool timed) {
   const int M = g->M, p = g->p, T = g->T, K = g->K;
   const int64_t N = g->N;
   const int B = 256;
-  Timing& tm = g->timing;
   hipEvent_t* ev = nullptr;
   if (timed) {
-    if (tm.used == tm.sets.size()) {
-      std::vector<hipEvent_t> set(6, nullptr);
-      for (int e = 0; e < 6; ++e) SBIE_HIP(hipEventCreate(&set[e]));
-      tm.sets.push_back(set);
-    }
-    ev = tm.sets[tm.used++].data();
+    sbie_status st = next_timing_set(g, &ev);
+    if (st) return st;
     SBIE_HIP(hipEventRecord(ev[0], s));
   }
   // prep: transform input and far-field source records
@@ -524,23 +542,33 @@ sbie_status apply_laplace(sbie_geom* g, int op, int prec, const double* d_dens, 
     hipLaunchKernelGGL(k_scale_coef, dim3(cdiv((int64_t)M * K, B)), dim3(B), 0, s, g->d_coef, g->d_lam, M, p, op,
                        g->d_cself, g->d_E);
     SBIE_HIP(hipGetLastError());
-    if (parts & SBIE_PARTS_SELF) {
-      st = mixed ? launch_gemm32(g->d_cself, K, g->d_Sy32, T, g->d_uself, T, M, T, K, s)
-                 : launch_gemm(g->d_cself, K, g->d_Sy, T, g->d_uself, T, M, T, K, s);
-      if (st) return st;
-    }
+  }
+  // part (c) near field, on the side stream once the exterior coefficients
+  // exist: its long FP64 recurrences leave the vector units idle between
+  // dependent steps, which the self and far-field waves fill
+  const bool near = (parts & SBIE_PARTS_NEAR) && g->n_near > 0;
+  if (near) {
+    sbie_status st = fork_side(g, s);
+    if (st) return st;
+    if (timed) SBIE_HIP(hipEventRecord(ev[6], g->side));
+    if (p <= 8)
+      launch_near<8>(g, g->side);
+    else if (p <= 16)
+      launch_near<16>(g, g->side);
+    else
+      launch_near<32>(g, g->side);
+    SBIE_HIP(hipGetLastError());
+    if (timed) SBIE_HIP(hipEventRecord(ev[7], g->side));
+  } else if (timed) {
+    SBIE_HIP(hipEventRecord(ev[6], s));
+    SBIE_HIP(hipEventRecord(ev[7], s));
+  }
+  if (parts & SBIE_PARTS_SELF) {
+    sbie_status st = mixed ? launch_gemm32(g->d_cself, K, g->d_Sy32, T, g->d_uself, T, M, T, K, s)
+                           : launch_gemm(g->d_cself, K, g->d_Sy, T, g->d_uself, T, M, T, K, s);
+    if (st) return st;
   }
   if (timed) SBIE_HIP(hipEventRecord(ev[2], s));
-  // part (c) near field
-  if ((parts & SBIE_PARTS_NEAR) && g->n_near > 0) {
-    if (p <= 8)
-      launch_near<8>(g, s);
-    else if (p <= 16)
-      launch_near<16>(g, s);
-    else
-      launch_near<32>(g, s);
-    SBIE_HIP(hipGetLastError());
-  }
   // part (d) far field: matrix-core tiles when a wave of 64 targets spans at
   // most three particles (T >= 32), else the vector-unit sum in FP64
   if ((parts & SBIE_PARTS_FAR) && T >= 32) {
@@ -562,14 +590,16 @@ sbie_status apply_laplace(sbie_geom* g, int op, int prec, const double* d_dens, 
     SBIE_HIP(hipEventRecord(ev[3], s));
     SBIE_HIP(hipEventRecord(ev[4], s));
   }
+  if (near) {
+    sbie_status st = join_side(g, s);
+    if (st) return st;
+  }
   // with no near pairs the near part is empty and is left out of the sum
   const uint32_t sum_parts = g->n_near > 0 ? parts : (parts & ~(uint32_t)SBIE_PARTS_NEAR);
   hipLaunchKernelGGL(k_assemble_f64, dim3(cdiv(N, B)), dim3(B), 0, s, g->d_uself, g->d_unear, g->d_partial,
                      g->nsplit, N, sum_parts, d_out);
   SBIE_HIP(hipGetLastError());
-  if (timed) {
-    SBIE_HIP(hipEventRecord(ev[5], s));
-  }
+  if (timed) SBIE_HIP(hipEventRecord(ev[5], s));
   return SBIE_OK;
 }
 

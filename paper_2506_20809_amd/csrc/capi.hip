@@ -34,6 +34,12 @@ void free_geom(sbie_geom* g) {
   if (!g) return;
   if (g->blk && g->blk_owned) (void)hipFree(g->blk);
   if (g->stk_blk) (void)hipFree(g->stk_blk);
+  if (g->side) {
+    (void)hipStreamSynchronize(g->side);
+    (void)hipStreamDestroy(g->side);
+  }
+  if (g->ev_fork) (void)hipEventDestroy(g->ev_fork);
+  if (g->ev_join) (void)hipEventDestroy(g->ev_join);
   for (auto& set : g->timing.sets)
     for (hipEvent_t e : set)
       if (e) (void)hipEventDestroy(e);
@@ -369,11 +375,19 @@ sbie_status sbie_geom_timing(sbie_geom* g, sbie_timing* out) {
   double acc[6] = {0, 0, 0, 0, 0, 0};
   for (size_t k = 0; k < tm.used; ++k) {
     hipEvent_t* ev = tm.sets[k].data();
-    float ms = 0.0f;
-    for (int e = 0; e < 5; ++e) {
-      SBIE_HIP(hipEventElapsedTime(&ms, ev[e], ev[e + 1]));
-      acc[e] += ms;
-    }
+    float ms = 0.0f, ms2 = 0.0f;
+    SBIE_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+    acc[0] += ms;
+    SBIE_HIP(hipEventElapsedTime(&ms, ev[1], ev[2]));
+    acc[1] += ms;
+    SBIE_HIP(hipEventElapsedTime(&ms, ev[6], ev[7]));  // near, on the side stream
+    acc[2] += ms;
+    SBIE_HIP(hipEventElapsedTime(&ms, ev[3], ev[4]));
+    acc[3] += ms;
+    // assembly: from the later of the far-field and near-field ends
+    SBIE_HIP(hipEventElapsedTime(&ms, ev[4], ev[5]));
+    SBIE_HIP(hipEventElapsedTime(&ms2, ev[7], ev[5]));
+    acc[4] += ms < ms2 ? ms : ms2;
     SBIE_HIP(hipEventElapsedTime(&ms, ev[0], ev[5]));
     acc[5] += ms;
   }

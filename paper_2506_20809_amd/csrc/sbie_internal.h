@@ -37,8 +37,10 @@ struct Buf {
   size_t bytes = 0;
 };
 
-// One set of six events per timed apply (per right-hand side), reused across
-// accumulation windows.
+// One set of eight events per timed apply (per right-hand side), reused across
+// accumulation windows: 0 start, 1 after prep, 2 after transforms and self,
+// 3/4 around the far-field kernel, 5 end (all on the apply's stream), 6/7
+// around the near field (on the side stream).
 struct Timing {
   std::vector<std::vector<hipEvent_t>> sets;
   size_t used = 0;
@@ -136,6 +138,9 @@ struct sbie_geom {
   uint8_t* d_near_scratch = nullptr;  // [M][M] near flags of the classification
 
   sbie::Timing timing;
+  // the near field runs on a side stream, concurrently with the far field
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace sbie {
@@ -200,6 +205,12 @@ sbie_status transform_only(sbie_geom* g, int op, const double* d_dens, double* d
 // C[rows x cols] = A[rows x kd] B[kd x cols] on the matrix cores (FP64, or FP32 with compensated tiles)
 sbie_status gemm(bool mixed, const double* A, int lda, const double* B64, const float* B32, int ldb, double* C,
                  int ldc, int rows, int cols, int kd, hipStream_t s);
+
+// timing event set of the next timed apply (apply.hip)
+sbie_status next_timing_set(sbie_geom* g, hipEvent_t** ev);
+// fork the side stream from s (after all work queued on s) and join it back
+sbie_status fork_side(sbie_geom* g, hipStream_t s);
+sbie_status join_side(sbie_geom* g, hipStream_t s);
 
 // Stokes single layer (stokes.hip); density and output [3][N]
 sbie_status apply_stokes(sbie_geom* g, int prec, const double* d_dens, double* d_out, hipStream_t s,

@@ -442,6 +442,9 @@ sbie_status setup_geometry(sbie_geom* g, hipStream_t s) {
     g->blk_used = c.used;
   }
   g->footprint = g->blk_bytes;
+  SBIE_HIP(hipStreamCreateWithFlags(&g->side, hipStreamNonBlocking));
+  SBIE_HIP(hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming));
+  SBIE_HIP(hipEventCreateWithFlags(&g->ev_join, hipEventDisableTiming));
   const int Kh2 = (p + 2) * (p + 3) / 2;
   {
     std::vector<double> cd(Kh, 0.0);

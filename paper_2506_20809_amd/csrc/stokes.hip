@@ -525,15 +525,9 @@ sbie_status apply_stokes(sbie_geom* g, int prec, const double* d_dens, double* d
   sbie_status st;
   SBIE_TRY_C(stokes_buffers(g));
 
-  Timing& tm = g->timing;
   hipEvent_t* ev = nullptr;
   if (timed) {
-    if (tm.used == tm.sets.size()) {
-      std::vector<hipEvent_t> set(6, nullptr);
-      for (int e = 0; e < 6; ++e) SBIE_HIP(hipEventCreate(&set[e]));
-      tm.sets.push_back(set);
-    }
-    ev = tm.sets[tm.used++].data();
+    SBIE_TRY_C(next_timing_set(g, &ev));
     SBIE_HIP(hipEventRecord(ev[0], s));
   }
   const int B = 256;
@@ -552,6 +546,25 @@ sbie_status apply_stokes(sbie_geom* g, int prec, const double* d_dens, double* d
     hipLaunchKernelGGL(k_stokes_scale, dim3(cdiv((int64_t)MK4, B)), dim3(B), 0, s, g->d_stk_c, g->d_lam, g->d_dlr,
                        M, p, g->d_stk_E, g->d_stk_E + MK4);
     SBIE_HIP(hipGetLastError());
+  }
+  // near field on the side stream, concurrently with the self and far parts
+  const bool near = (parts & SBIE_PARTS_NEAR) && g->n_near > 0;
+  if (near) {
+    SBIE_TRY_C(fork_side(g, s));
+    if (timed) SBIE_HIP(hipEventRecord(ev[6], g->side));
+    if (p <= 8)
+      launch_near_stokes<8>(g, g->side);
+    else if (p <= 16)
+      launch_near_stokes<16>(g, g->side);
+    else
+      launch_near_stokes<32>(g, g->side);
+    SBIE_HIP(hipGetLastError());
+    if (timed) SBIE_HIP(hipEventRecord(ev[7], g->side));
+  } else if (timed) {
+    SBIE_HIP(hipEventRecord(ev[6], s));
+    SBIE_HIP(hipEventRecord(ev[7], s));
+  }
+  {
     if (parts & SBIE_PARTS_SELF) {
       double* U = g->d_stk_U;
       if ((st = gemm(mixed, g->d_stk_E, K, g->d_Sy, g->d_Sy32, T, U, T, 4 * M, T, K, s)) != SBIE_OK) return st;
@@ -567,15 +580,6 @@ sbie_status apply_stokes(sbie_geom* g, int prec, const double* d_dens, double* d
     }
   }
   if (timed) SBIE_HIP(hipEventRecord(ev[2], s));
-  if ((parts & SBIE_PARTS_NEAR) && g->n_near > 0) {
-    if (p <= 8)
-      launch_near_stokes<8>(g, s);
-    else if (p <= 16)
-      launch_near_stokes<16>(g, s);
-    else
-      launch_near_stokes<32>(g, s);
-    SBIE_HIP(hipGetLastError());
-  }
   if (timed) SBIE_HIP(hipEventRecord(ev[3], s));
   if (parts & SBIE_PARTS_FAR) {
     constexpr int TPT = 2;
@@ -590,6 +594,7 @@ sbie_status apply_stokes(sbie_geom* g, int prec, const double* d_dens, double* d
     SBIE_HIP(hipGetLastError());
   }
   if (timed) SBIE_HIP(hipEventRecord(ev[4], s));
+  if (near) SBIE_TRY_C(join_side(g, s));
   // with no near pairs the near part is empty and is left out of the sum
   const uint32_t sum_parts = g->n_near > 0 ? parts : (parts & ~(uint32_t)SBIE_PARTS_NEAR);
   hipLaunchKernelGGL(k_stokes_assemble, dim3(cdiv(3 * N, B)), dim3(B), 0, s, g->d_stk_self, g->d_stk_near,

@@ -313,7 +313,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the other precision's measurement")
     ap.add_argument("--no-stokes", action="store_true", help="skip the Stokes single-layer measurement")
-    ap.add_argument("--served-requests", type=int, default=48, help="requests in the served-mode run (0: skip)")
+    ap.add_argument("--served-requests", type=int, default=0,
+                    help="requests in the served-mode run (0: skip; the run is opt-in)")
     ap.add_argument("--served-rho", type=float, default=0.8, help="load of the Poisson arrivals")
     ap.add_argument("--served-precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--served-lanes", type=int, default=8)

@@ -231,6 +231,10 @@ class Geometry:
             out = torch.empty_like(density)
         if stream is None:
             stream = torch.cuda.current_stream(density.device)
+        if stream.cuda_stream == 0:
+            # a NULL stream selects the context's own stream, which does not
+            # wait for work queued on the default stream: finish that first
+            stream.synchronize()
         _check(lib().sbie_apply(self._h, int(op), int(precision), nrhs, density.data_ptr(), out.data_ptr(),
                                 ctypes.c_void_p(stream.cuda_stream), flags | SBIE_DEVICE_PTRS))
         return out

@@ -106,6 +106,7 @@ struct sbie_server {
   bool graphs = false;
   sbie::Arena arena;
   std::mutex mu;
+  std::mutex capture_mu;
   std::condition_variable cv_done;
   std::vector<std::unique_ptr<std::condition_variable>> lane_cv;
   std::deque<sbie_session*> pending;
@@ -185,6 +186,9 @@ void build_session(sbie_server* srv, sbie_session* s, int lane) {
     s->d_out = reinterpret_cast<double*>(blk + s->plan + io);
   }
   if (rc == SBIE_OK && srv->graphs) {
+    // one capture at a time in the process: the lanes' captures and
+    // instantiations do not overlap
+    std::lock_guard<std::mutex> cap(srv->capture_mu);
     hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
       const sbie_status la = launch_apply(s, st);
@@ -498,6 +502,8 @@ sbie_status sbie_wait(sbie_server* srv, uint64_t ticket, int64_t timeout_us, sbi
   std::unique_lock<std::mutex> lk(srv->mu);
   auto it = srv->jobs.find(ticket);
   if (it == srv->jobs.end()) return invalid_arg("unknown ticket");
+  // the Job stays at its address; map iterators do not survive the wait (other
+  // threads insert tickets meanwhile and the table may rehash)
   Job* j = it->second;
   auto done = [j] { return j->done; };
   if (timeout_us < 0) {
@@ -509,7 +515,7 @@ sbie_status sbie_wait(sbie_server* srv, uint64_t ticket, int64_t timeout_us, sbi
   if (stats) *stats = j->stats;
   const sbie_status st = j->status;
   if (st != SBIE_OK) set_error(j->err);
-  srv->jobs.erase(it);
+  srv->jobs.erase(ticket);
   delete j;
   return st;
 }

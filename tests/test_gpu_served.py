@@ -258,3 +258,43 @@ def test_served_errors(ctx):
         srv.wait(123456789)
     assert e.value.status == -1
     srv.close()
+
+
+def test_served_many_concurrent_clients(ctx):
+    """Forty small sessions from sixteen client threads at once (the ticket table
+    grows while clients wait on it); every result equals its plain apply."""
+    import torch
+
+    import paper_2506_20809_amd as sbie
+
+    p = 4
+    geoms = [workloads.rsa_pack(2 + k % 3, 0.15, 0.05, 200 + k) for k in range(40)]
+    dens = [_densities(5, 1, len(g["A"]) * (p + 1) * (2 * p + 2), 300 + k) for k, g in enumerate(geoms)]
+    results = [None] * len(geoms)
+    errors = []
+    srv = sbie.Server(ctx, max_sessions=8, budget_bytes=256 << 20, graphs=True)
+
+    def client(ks):
+        try:
+            for k in ks:
+                s = srv.open(geoms[k], p, k % 2)
+                outs = []
+                for d in dens[k]:
+                    u, _ = s.apply(torch.tensor(d, device="cuda"))
+                    outs.append(u.cpu().numpy())
+                s.close()
+                results[k] = outs
+        except Exception as e:  # reported below
+            errors.append(repr(e))
+
+    threads = [threading.Thread(target=client, args=(list(range(t, 40, 16)),)) for t in range(16)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=300)
+    assert not errors, errors
+    srv.close()
+    for k, g in enumerate(geoms):
+        ref = _plain(ctx, g, p, k % 2, 0, dens[k])
+        for r in range(5):
+            assert np.array_equal(results[k][r], ref[r]), (k, r)

@@ -12,6 +12,7 @@ namespace sbie {
 namespace {
 
 constexpr double kInv4Pi = 0.079577471545947667884441881686257181;
+constexpr int kGroup = 4;  // orders m whose backward recurrences run together
 
 using d4 = double __attribute__((ext_vector_type(4)));
 using f4 = float __attribute__((ext_vector_type(4)));
@@ -184,6 +185,7 @@ __global__ __launch_bounds__(64) void k_near_f64(
     const int32_t* __restrict__ near_src, const double* __restrict__ E,
     const double* __restrict__ lam, const double* __restrict__ ab, const double* __restrict__ rcp, int p,
     int T, int chunks, unsigned* status, double* __restrict__ unear) {
+  __shared__ double qpark[kGroup][2][64];
   const int j = blockIdx.x / chunks;
   const int t = (blockIdx.x - j * chunks) * 64 + threadIdx.x;
   const bool live = t < T;
@@ -245,7 +247,55 @@ __global__ __launch_bounds__(64) void k_near_f64(
     double cas2 = 1.0;                         // (-1)^m (N+m-1)!
     for (int k = 2; k < N; ++k) cas2 *= (double)k;
     const double sgn = P.oblate ? 1.0 : -1.0;
-    for (int m = 0; m <= p; ++m) {
+    for (int m0 = 0; m0 <= p; m0 += kGroup) {
+      // The minimal solution Q of the recurrence in n, unnormalised, by
+      // backward recurrence from degree L (the continued fraction for
+      // Q_N/Q_{N-1} evaluated bottom-up from depth L-N).  With Q_n = s_n R_n
+      // and s_{n-1} = s_n/(n+m) the recurrence is free of divisions:
+      //   R_{n-1} = (2n+1) u R_n -+ (n-m+1)(n+m+1) R_{n+1},
+      // where (n-m+1)(n+m+1) = (n+1)^2 - m^2; rescaled by 2^-600 whenever it
+      // grows past 2^600.  kGroup orders run together (independent chains that
+      // share the depth and the (2n+1) u factor); each lane parks its R_N,
+      // R_{N+1} in LDS for the per-order work below.
+      {
+        double qh[kGroup], qc[kGroup], smsq[kGroup];
+#pragma unroll
+        for (int k = 0; k < kGroup; ++k) {
+          qh[k] = 0.0;
+          qc[k] = 1.0;
+          smsq[k] = sgn * (double)((m0 + k) * (m0 + k));
+        }
+        double c2n1 = (double)(2 * L + 1), snp = sgn * (double)(L + 1) * (double)(L + 1), sc = sgn * c2n1;
+        const double dsc = -2.0 * sgn;
+        for (int n = L; n > N; n -= 8) {
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const double cu = c2n1 * u;
+#pragma unroll
+            for (int k = 0; k < kGroup; ++k) {
+              const double qn = fma(cu, qc[k], (snp - smsq[k]) * qh[k]);
+              qh[k] = qc[k];
+              qc[k] = qn;
+            }
+            snp -= sc;
+            sc += dsc;
+            c2n1 -= 2.0;
+          }
+#pragma unroll
+          for (int k = 0; k < kGroup; ++k)
+            if (fabs(qc[k]) > 0x1p600) {
+              qc[k] *= 0x1p-600;
+              qh[k] *= 0x1p-600;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kGroup; ++k) {
+          qpark[k][0][threadIdx.x] = qc[k];
+          qpark[k][1][threadIdx.x] = qh[k];
+        }
+      }
+      const int mend = m0 + kGroup <= p + 1 ? m0 + kGroup : p + 1;
+      for (int m = m0; m < mend; ++m) {
       if (m > 0) {
         pmm_u *= (double)(2 * m - 1) * sw;
         pbar *= sqrt((2.0 * m + 1.0) / (2.0 * m)) * sv;
@@ -268,33 +318,8 @@ __global__ __launch_bounds__(64) void k_near_f64(
           cdn += 1.0;
         }
       }
-      // now pa = Pt_{N-1}, pb = Pt_N (m <= p = N-1 so N >= m+1).
-      // The minimal solution Q of the same recurrence, unnormalised, by backward
-      // recurrence from degree L (the continued fraction for Q_N/Q_{N-1}
-      // evaluated bottom-up from depth L-N).  With Q_n = s_n R_n and
-      // s_{n-1} = s_n/(n+m) the recurrence is free of divisions:
-      //   R_{n-1} = (2n+1) u R_n -+ (n-m+1)(n+m+1) R_{n+1}
-      // rescaled by 2^-600 whenever it grows past 2^600.
-      double qhi = 0.0, qcur = 1.0;  // R_{n+1}, R_n at n = L
-      {
-        double c2n1 = (double)(2 * L + 1), ca = sgn * (double)(L - m + 1), cb = (double)(L + m + 1);
-        const double dca = -sgn;
-        for (int n = L; n > N; n -= 8) {
-#pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            const double qn = fma(c2n1 * u, qcur, (ca * cb) * qhi);
-            qhi = qcur;
-            qcur = qn;
-            c2n1 -= 2.0;
-            ca += dca;
-            cb -= 1.0;
-          }
-          if (fabs(qcur) > 0x1p600) {
-            qcur *= 0x1p-600;
-            qhi *= 0x1p-600;
-          }
-        }
-      }
+      // now pa = Pt_{N-1}, pb = Pt_N (m <= p = N-1 so N >= m+1)
+      double qcur = qpark[m - m0][0][threadIdx.x], qhi = qpark[m - m0][1][threadIdx.x];  // R_N, R_{N+1}
       // R_N, R_{N+1} -> Q~_N = R_N/(N+m+1), Q~_{N+1} = R_{N+1} (s_{N+1} = 1)
       qcur *= rcp[N + m + 1];
       // qcur = Q~_N, qhi = Q~_{N+1}; continue into registers indexed by degree
@@ -346,6 +371,7 @@ __global__ __launch_bounds__(64) void k_near_f64(
         acc += sc;
       else
         acc += 1.41421356237309504880 * (sc * cm + ss * sm);
+      }
     }
   }
   if (bad) atomicOr(status, bad);

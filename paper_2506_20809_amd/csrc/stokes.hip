@@ -19,6 +19,7 @@ namespace sbie {
 namespace {
 
 constexpr double kInv8Pi = 0.039788735772973833942220940843128591;
+constexpr int kGroup = 4;  // orders m whose backward recurrences run together
 
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
@@ -144,6 +145,7 @@ __global__ __launch_bounds__(64) void k_near_stokes(
     const double* __restrict__ E, const double* __restrict__ lam, const double* __restrict__ ab,
     const double* __restrict__ cd, const double* __restrict__ rcp, int p, int T, int chunks, int64_t N,
     unsigned* status, double* __restrict__ unear) {
+  __shared__ double qpark[kGroup][2][64];
   const int j = blockIdx.x / chunks;
   const int t = (blockIdx.x - j * chunks) * 64 + threadIdx.x;
   const bool live = t < T;
@@ -201,7 +203,48 @@ __global__ __launch_bounds__(64) void k_near_stokes(
     double cas2 = 1.0;
     for (int k = 2; k < N1; ++k) cas2 *= (double)k;
     const double sgn = P.oblate ? 1.0 : -1.0;
-    for (int m = 0; m <= p; ++m) {
+    for (int m0 = 0; m0 <= p; m0 += kGroup) {
+      // backward recurrences of kGroup orders together, as in the Laplace
+      // near field; R_N, R_{N+1} of each order parked in LDS
+      {
+        double qh[kGroup], qc[kGroup], smsq[kGroup];
+#pragma unroll
+        for (int k = 0; k < kGroup; ++k) {
+          qh[k] = 0.0;
+          qc[k] = 1.0;
+          smsq[k] = sgn * (double)((m0 + k) * (m0 + k));
+        }
+        double c2n1 = (double)(2 * L + 1), snp = sgn * (double)(L + 1) * (double)(L + 1), sc = sgn * c2n1;
+        const double dsc = -2.0 * sgn;
+        for (int n = L; n > N1; n -= 8) {
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const double cu = c2n1 * u;
+#pragma unroll
+            for (int k = 0; k < kGroup; ++k) {
+              const double qn = fma(cu, qc[k], (snp - smsq[k]) * qh[k]);
+              qh[k] = qc[k];
+              qc[k] = qn;
+            }
+            snp -= sc;
+            sc += dsc;
+            c2n1 -= 2.0;
+          }
+#pragma unroll
+          for (int k = 0; k < kGroup; ++k)
+            if (fabs(qc[k]) > 0x1p600) {
+              qc[k] *= 0x1p-600;
+              qh[k] *= 0x1p-600;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kGroup; ++k) {
+          qpark[k][0][threadIdx.x] = qc[k];
+          qpark[k][1][threadIdx.x] = qh[k];
+        }
+      }
+      const int mend = m0 + kGroup <= p + 1 ? m0 + kGroup : p + 1;
+      for (int m = m0; m < mend; ++m) {
       if (m > 0) {
         pmm_u *= (double)(2 * m - 1) * sw;
         pbar *= sqrt((2.0 * m + 1.0) / (2.0 * m)) * sv;
@@ -223,27 +266,7 @@ __global__ __launch_bounds__(64) void k_near_stokes(
           cdn += 1.0;
         }
       }
-      // Q by the division-free backward recurrence from depth L, rescaled
-      double qhi = 0.0, qcur = 1.0;
-      {
-        double c2n1 = (double)(2 * L + 1), ca = sgn * (double)(L - m + 1), cb = (double)(L + m + 1);
-        const double dca = -sgn;
-        for (int n = L; n > N1; n -= 8) {
-#pragma unroll
-          for (int kk = 0; kk < 8; ++kk) {
-            const double qn = fma(c2n1 * u, qcur, (ca * cb) * qhi);
-            qhi = qcur;
-            qcur = qn;
-            c2n1 -= 2.0;
-            ca += dca;
-            cb -= 1.0;
-          }
-          if (fabs(qcur) > 0x1p600) {
-            qcur *= 0x1p-600;
-            qhi *= 0x1p-600;
-          }
-        }
-      }
+      double qcur = qpark[m - m0][0][threadIdx.x], qhi = qpark[m - m0][1][threadIdx.x];
       qcur *= rcp[N1 + m + 1];
       double Q[PMAX + 4];
       double qN1 = 0.0;
@@ -317,6 +340,7 @@ __global__ __launch_bounds__(64) void k_near_stokes(
         Pu[s] += f * (uc[s] * cm + us[s] * sm);
         Pv[s] += f * (wc[s] * cm + ws[s] * sm);
         Pp[s] += f * (double)m * (vs[s] * cm - vc[s] * sm);
+      }
       }
     }
     const double d[3] = {d0, d1, d2};

@@ -27,7 +27,16 @@
  *  - on-surface D is the principal value (average of the one-sided spectra);
  *  - the near-field expansion of D uses the exterior-limit coefficients;
  *  - near/far split uses the exact minimum surface distance, diam = twice the
- *    largest semi-axis, "near" iff d < eta*diam(source) (strict).
+ *    largest semi-axis, "near" iff d < eta*diam(source) (strict);
+ *  - Stokes single layer (Section 4.3, Eq. (stokes)): viscosity 1, origin of
+ *    the identity at each source particle's centre, self values from the
+ *    exterior limit of the gradients (the jump cancels in the combination),
+ *    far field from the Stokeslet with the raw nodal density.
+ *
+ * Every function here is pinned by the CPU tests against values fixed from
+ * outside this file: mpmath Legendre values, closed forms (conductor, sphere,
+ * translating-spheroid mobilities), identities (Gauss, Green, Casoratian,
+ * null layer of the normal), brute-force quadrature and invariances.
  */
 #include <complex.h>
 #include <math.h>

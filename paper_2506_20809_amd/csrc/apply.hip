@@ -470,10 +470,12 @@ __global__ __launch_bounds__(256) void k_far_f64(
 
 // ---------------------------------------------------------------- assembly
 
-// u = u_self + u_near + sum over source splits of the far field, in this order.
+// u = u_self + u_near + sum over the forward far partials (split order) + sum
+// over the reverse far partials (handler slot, then row group order).
+template <typename RV>
 __global__ void k_assemble_f64(const double* __restrict__ uself, const double* __restrict__ unear,
-                               const double* __restrict__ partial, int nsplit, int64_t N,
-                               uint32_t parts, double* __restrict__ out) {
+                               const double* __restrict__ partial, int nsplit, const RV* __restrict__ rev, int M,
+                               int T, int RG, int64_t N, uint32_t parts, double* __restrict__ out) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= N) return;
   double u = 0.0;
@@ -482,6 +484,16 @@ __global__ void k_assemble_f64(const double* __restrict__ uself, const double* _
   if (parts & SBIE_PARTS_FAR) {
     double f = 0.0;
     for (int s = 0; s < nsplit; ++s) f += partial[(size_t)s * N + g];
+    if (rev) {
+      // slots k < H always have a handler; slot H (even M) only for b >= M/2
+      const int b = (int)(g / T), t = (int)(g - (int64_t)b * T);
+      const int H = (M - 1) / 2;
+      const int slots = H + (((M & 1) == 0 && b >= M / 2) ? 1 : 0);
+      double r = 0.0;
+      for (int k = 0; k < slots; ++k)
+        for (int rg = 0; rg < RG; ++rg) r += (double)rev[(((size_t)b * (H + 1) + k) * RG + rg) * T + t];
+      f += r * kInv4Pi;
+    }
     u += f;
   }
   out[g] = u;
@@ -573,18 +585,22 @@ sbie_status apply_laplace(sbie_geom* g, int op, int prec, const double* d_dens, 
   // exist: its long FP64 recurrences leave the vector units idle between
   // dependent steps, which the self and far-field waves fill
   const bool near = (parts & SBIE_PARTS_NEAR) && g->n_near > 0;
+  const bool fork = near && g->side != nullptr;
   if (near) {
-    sbie_status st = fork_side(g, s);
-    if (st) return st;
-    if (timed) SBIE_HIP(hipEventRecord(ev[6], g->side));
+    if (fork) {
+      sbie_status st = fork_side(g, s);
+      if (st) return st;
+    }
+    hipStream_t ns = fork ? g->side : s;
+    if (timed) SBIE_HIP(hipEventRecord(ev[6], ns));
     if (p <= 8)
-      launch_near<8>(g, g->side);
+      launch_near<8>(g, ns);
     else if (p <= 16)
-      launch_near<16>(g, g->side);
+      launch_near<16>(g, ns);
     else
-      launch_near<32>(g, g->side);
+      launch_near<32>(g, ns);
     SBIE_HIP(hipGetLastError());
-    if (timed) SBIE_HIP(hipEventRecord(ev[7], g->side));
+    if (timed) SBIE_HIP(hipEventRecord(ev[7], ns));
   } else if (timed) {
     SBIE_HIP(hipEventRecord(ev[6], s));
     SBIE_HIP(hipEventRecord(ev[7], s));
@@ -616,14 +632,19 @@ sbie_status apply_laplace(sbie_geom* g, int op, int prec, const double* d_dens, 
     SBIE_HIP(hipEventRecord(ev[3], s));
     SBIE_HIP(hipEventRecord(ev[4], s));
   }
-  if (near) {
+  if (fork) {
     sbie_status st = join_side(g, s);
     if (st) return st;
   }
   // with no near pairs the near part is empty and is left out of the sum
   const uint32_t sum_parts = g->n_near > 0 ? parts : (parts & ~(uint32_t)SBIE_PARTS_NEAR);
-  hipLaunchKernelGGL(k_assemble_f64, dim3(cdiv(N, B)), dim3(B), 0, s, g->d_uself, g->d_unear, g->d_partial,
-                     g->nsplit, N, sum_parts, d_out);
+  const int RG = far_row_groups(g, !mixed);
+  if (T >= 32 && mixed)
+    hipLaunchKernelGGL(k_assemble_f64<float>, dim3(cdiv(N, B)), dim3(B), 0, s, g->d_uself, g->d_unear, g->d_partial,
+                       g->nsplit, reinterpret_cast<const float*>(g->d_rev), M, T, RG, N, sum_parts, d_out);
+  else
+    hipLaunchKernelGGL(k_assemble_f64<double>, dim3(cdiv(N, B)), dim3(B), 0, s, g->d_uself, g->d_unear,
+                       g->d_partial, g->nsplit, T >= 32 ? g->d_rev : nullptr, M, T, RG, N, sum_parts, d_out);
   SBIE_HIP(hipGetLastError());
   if (timed) SBIE_HIP(hipEventRecord(ev[5], s));
   return SBIE_OK;

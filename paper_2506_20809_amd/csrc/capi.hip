@@ -94,7 +94,7 @@ sbie_status check_particles(const double* centers, const double* quats, const do
 }
 
 sbie_status make_geometry(sbie_ctx* ctx, std::vector<Particle>&& parts, int32_t p, double eta, char* blk,
-                          size_t blk_bytes, sbie_geom** out) {
+                          size_t blk_bytes, bool fork_near, sbie_geom** out) {
   *out = nullptr;
   SBIE_HIP(hipSetDevice(ctx->device));
   sbie_geom* g = new (std::nothrow) sbie_geom;
@@ -113,6 +113,7 @@ sbie_status make_geometry(sbie_ctx* ctx, std::vector<Particle>&& parts, int32_t 
   g->blk = blk;
   g->blk_bytes = blk_bytes;
   g->blk_owned = false;
+  g->fork_near = fork_near;
   sbie_status st = setup_geometry(g, ctx->stream);
   if (st != SBIE_OK) {
     (void)hipStreamSynchronize(ctx->stream);
@@ -199,7 +200,7 @@ sbie_status sbie_geom_create(sbie_ctx* ctx, const double* centers, const double*
   std::vector<Particle> parts;
   sbie_status st = check_particles(centers, quats, A, C, M, p, eta, &parts);
   if (st != SBIE_OK) return st;
-  return make_geometry(ctx, std::move(parts), p, eta, nullptr, 0, out);
+  return make_geometry(ctx, std::move(parts), p, eta, nullptr, 0, true, out);
 }
 
 void sbie_geom_destroy(sbie_geom* g) { destroy_geometry(g); }

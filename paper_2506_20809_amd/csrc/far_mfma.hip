@@ -65,155 +65,221 @@ struct Mfma<double> {
 };
 
 constexpr int kChunk = 40;  // 16-source blocks staged in LDS at a time
+// Workgroup shape of the pair kernel: up to WMAX waves (three resp. two per
+// SIMD, which the registers allow), each holding up to RBMAX blocks of 16
+// target rows; a particle's rows are split into groups of WMAX*RBMAX blocks,
+// spread evenly over the waves so that every SIMD carries the same work.
+template <typename R>
+struct PairShape {
+  static constexpr int WMAX = sizeof(R) == 4 ? 12 : 8;
+  static constexpr int RBMAX = sizeof(R) == 4 ? 4 : 5;
+  static constexpr int GB = WMAX * RBMAX;  // row blocks per group
+};
 
-// geo: per block 80 values (B operand in lane order, then |o|^2 per source);
-// app: per block 16 values W sigma (S) or 80 values ((W mu nu, 0) in lane
-// order, then -W mu nu.o) (D).  A workgroup of four waves owns 256 targets; the
-// blocks of each source particle are staged through LDS and read by all four.
+// Pair-symmetric far field.  Every unordered pair of particles (a, b) is
+// visited once, by the workgroup that owns a's target rows: a visits the
+// partners b = a+1 .. a+H (mod M), H = (M-1)/2, and for even M the partner
+// a + M/2 when a < M/2.  The reciprocal distance of each node pair serves both
+// directions: the forward sum into a's targets from b's sources stays in
+// registers across the partners, and the reverse sum into b's targets from
+// a's sources is reduced over a's rows (lanes, then waves in order) and written
+// to rev[b][k][rg][t], k = (b - a - 1) mod M, the slot of handler a in b's
+// list.  A direction whose source is excluded for its target particle (self,
+// near field) is dropped; its reverse slot is written as zero.
+//
+// Squared distances come off the matrix cores as in a K = 4 contraction: with
+// D = x - c_b and o = y - c_b,  |x - y|^2 = [D |D|^2] . [-2o 1] + |o|^2.  The
+// double layer's forward dot d_b.(x - y) is [D |D|^2] . [d_b 0] - d_b.o, and
+// its reverse dot d_a.(x - y) is [d_a/2  d_a.D] . [-2o 1].
+//
+// Rows of a are padded to 16 with zero-strength points at a's centre.
 template <typename R, int OP>
-__global__ __launch_bounds__(256) void k_far_mfma(const R* __restrict__ geo, const R* __restrict__ app,
-                                                  const Particle* __restrict__ part, const double* __restrict__ x,
-                                                  const double* __restrict__ y, const double* __restrict__ z,
-                                                  const uint32_t* __restrict__ excl, int words, int M, int T,
-                                                  int T16, int64_t N, int nsplit, double* __restrict__ partial) {
+__global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* __restrict__ geo, const R* __restrict__ app,
+                                                   const Particle* __restrict__ part, const double* __restrict__ x,
+                                                   const double* __restrict__ y, const double* __restrict__ z,
+                                                   const uint32_t* __restrict__ excl, int words, int M, int T,
+                                                   int T16, int64_t N, int nsplit, int RG,
+                                                   double* __restrict__ fwd, R* __restrict__ rev) {
   using MM = Mfma<R>;
   using V = typename MM::V;
   constexpr int GEO = 80, APP = (OP == SBIE_OP_S) ? 16 : 80;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  R* lds = reinterpret_cast<R*>(smem_raw);
+  R* lds_geo = reinterpret_cast<R*>(smem_raw);
+  R* lds_app = lds_geo + kChunk * GEO;
+  R* lds_rev = lds_app + kChunk * APP;  // [wave][kChunk*16] reverse column sums
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lg = lane >> 4;
-  const int split = blockIdx.x % nsplit, tile = blockIdx.x / nsplit;
-  const int s0 = (int)((int64_t)M * split / nsplit), s1 = (int)((int64_t)M * (split + 1) / nsplit);
+  const int split = blockIdx.x % nsplit, rest = blockIdx.x / nsplit;
+  const int rg = rest % RG, a = rest / RG;
   const int nb = T16 / 16;
-  const int64_t wg0 = (int64_t)tile * 256;
-  const int pw0 = (int)(wg0 / T);
-  const int pw1 = (int)(((wg0 + 255 < N) ? (wg0 + 255) : (N - 1)) / T);
-  const int64_t base = wg0 + wave * 64;
-  const bool wave_live = base < N;
+  constexpr int GB = PairShape<R>::GB, RB = PairShape<R>::RBMAX;
+  const int W = blockDim.x >> 6;
+  const int rbg = rg * GB;                                     // first row block of the group
+  const int cnt = nb - rbg < GB ? nb - rbg : GB;               // row blocks of the group
+  const int rb0 = rbg + (wave * cnt) / W;                      // this wave's blocks rb0 .. rb0+nrb-1
+  const int nrb = rbg + ((wave + 1) * cnt) / W - rb0;
+  const int H = (M - 1) / 2;
+  const bool even = (M & 1) == 0;
+  const int P = H + ((even && a < M / 2) ? 1 : 0);
+  const int k0 = (int)((int64_t)P * split / nsplit), k1 = (int)((int64_t)P * (split + 1) / nsplit);
+  const Particle& Pa = part[a];
 
-  // A-operand rows: targets base + 16 rb + li
-  double tc[4][3];
+  // target rows of this wave: A-operand rows (lane li) and accumulator rows
+  double tc[RB][3];
+  R da[RB][3];   // double layer: d_a of the A-operand row
+  R qa[RB][4];   // single layer: strength of the accumulator rows
 #pragma unroll
-  for (int rb = 0; rb < 4; ++rb) {
-    int64_t t = base + 16 * rb + li;
-    if (t >= N) t = N - 1;
-    tc[rb][0] = x[t];
-    tc[rb][1] = y[t];
-    tc[rb][2] = z[t];
+  for (int rb = 0; rb < RB; ++rb) {
+    const int r = (rb0 + rb) * 16 + li;
+    if (rb < nrb && r < T) {
+      const int64_t g = (int64_t)a * T + r;
+      tc[rb][0] = x[g];
+      tc[rb][1] = y[g];
+      tc[rb][2] = z[g];
+    } else {
+      tc[rb][0] = Pa.c[0];
+      tc[rb][1] = Pa.c[1];
+      tc[rb][2] = Pa.c[2];
+    }
+    const size_t blk = (size_t)a * nb + (rb < nrb ? rb0 + rb : 0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) da[rb][c] = (OP == SBIE_OP_D && rb < nrb) ? app[blk * 80 + 16 * c + li] : R(0);
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      qa[rb][e] = (OP == SBIE_OP_S && rb < nrb) ? app[blk * 16 + MM::row(lg, e)] : R(0);
   }
-  // target particles spanned by the wave's 64 rows (T >= 32: at most three)
-  const int tp0 = (int)((wave_live ? base : wg0) / T);
-  const int b1 = (int)((int64_t)(tp0 + 1) * T - base);  // first local row of particle tp0+1
-  const int b2 = b1 + T;                                 // first local row of particle tp0+2
-  const int64_t nrows = !wave_live ? 0 : ((N - base < 64) ? (N - base) : 64);
 
-  R acc[4][4], lo[4][4];
+  R acc[RB][4], lo[RB][4];
 #pragma unroll
-  for (int rb = 0; rb < 4; ++rb)
+  for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
     for (int e = 0; e < 4; ++e) acc[rb][e] = lo[rb][e] = R(0);
 
-  for (int s = s0; s < s1; ++s) {
-    const uint32_t bit = 1u << (s & 31);
-    const int wd = s >> 5;
-    // workgroup-uniform: does any target particle of the workgroup need source s?
-    bool wg_need = false;
-    for (int tp = pw0; tp <= pw1; ++tp) wg_need |= !(excl[(size_t)tp * words + wd] & bit);
-    if (!wg_need) continue;
-    bool need[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const int tp = tp0 + q;
-      const int first = q == 0 ? 0 : (q == 1 ? b1 : b2);
-      need[q] = tp < M && first < nrows && !(excl[(size_t)tp * words + wd] & bit);
+  for (int k = k0; k < k1; ++k) {
+    const int b = k < H ? (a + 1 + k) % M : a + M / 2;
+    const bool need_f = !((excl[(size_t)a * words + (b >> 5)] >> (b & 31)) & 1u);
+    const bool need_r = !((excl[(size_t)b * words + (a >> 5)] >> (a & 31)) & 1u);
+    R* rout = rev + (((size_t)b * (H + 1) + k) * RG + rg) * T;
+    if (!need_f && !need_r) {
+      for (int t = tid; t < T; t += blockDim.x) rout[t] = R(0);
+      continue;
     }
-    const bool wave_need = need[0] || need[1] || need[2];
-    const double cx = part[s].c[0], cy = part[s].c[1], cz = part[s].c[2];
-    R a[4];
+    const double cx = part[b].c[0], cy = part[b].c[1], cz = part[b].c[2];
+    R aop[RB], a3[RB];
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb) {
+    for (int rb = 0; rb < RB; ++rb) {
       const double dx = tc[rb][0] - cx, dy = tc[rb][1] - cy, dz = tc[rb][2] - cz;
-      const double v = lg == 0 ? dx : (lg == 1 ? dy : (lg == 2 ? dz : fma(dz, dz, fma(dy, dy, dx * dx))));
-      a[rb] = (R)v;
+      aop[rb] = (R)(lg == 0 ? dx : (lg == 1 ? dy : (lg == 2 ? dz : fma(dz, dz, fma(dy, dy, dx * dx)))));
+      if (OP == SBIE_OP_D) {
+        const double dd = fma((double)da[rb][2], dz, fma((double)da[rb][1], dy, (double)da[rb][0] * dx));
+        const R dl = lg == 0 ? da[rb][0] : (lg == 1 ? da[rb][1] : da[rb][2]);
+        a3[rb] = lg < 3 ? R(0.5) * dl : (R)dd;
+      }
     }
-    R tmp[4][4];
+    R tmp[RB][4];
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
       for (int e = 0; e < 4; ++e) tmp[rb][e] = R(0);
     for (int c0 = 0; c0 < nb; c0 += kChunk) {
       const int nbc = nb - c0 < kChunk ? nb - c0 : kChunk;
-      __syncthreads();  // the previous chunk has been consumed
+      __syncthreads();  // the previous chunk (operands and reverse sums) has been consumed
       {
         using C16 = typename std::conditional<sizeof(R) == 4, float4, double2>::type;
         constexpr int PER = 16 / sizeof(R);
-        const C16* gs = reinterpret_cast<const C16*>(geo + ((size_t)s * nb + c0) * GEO);
-        C16* ld = reinterpret_cast<C16*>(lds);
-        for (int i = tid; i < nbc * GEO / PER; i += 256) ld[i] = gs[i];
-        const C16* as = reinterpret_cast<const C16*>(app + ((size_t)s * nb + c0) * APP);
-        C16* la = reinterpret_cast<C16*>(lds + kChunk * GEO);
-        for (int i = tid; i < nbc * APP / PER; i += 256) la[i] = as[i];
+        const C16* gs = reinterpret_cast<const C16*>(geo + ((size_t)b * nb + c0) * GEO);
+        C16* ld = reinterpret_cast<C16*>(lds_geo);
+        for (int i = tid; i < nbc * GEO / PER; i += blockDim.x) ld[i] = gs[i];
+        const C16* as = reinterpret_cast<const C16*>(app + ((size_t)b * nb + c0) * APP);
+        C16* la = reinterpret_cast<C16*>(lds_app);
+        for (int i = tid; i < nbc * APP / PER; i += blockDim.x) la[i] = as[i];
       }
       __syncthreads();
-      if (wave_need) {
+      if (nrb > 0) {
         for (int ib = 0; ib < nbc; ++ib) {
-          const R bv = lds[ib * GEO + lane];
-          const R cw = lds[ib * GEO + 64 + li];
+          const R bv = lds_geo[ib * GEO + lane];
+          const R cw = lds_geo[ib * GEO + 64 + li];
           const V cinit = {cw, cw, cw, cw};
+          R rsum = R(0);  // reverse sum for source column li over this lane's rows
           if (OP == SBIE_OP_S) {
-            const R qv = lds[kChunk * GEO + ib * 16 + li];
-            V r2[4];
+            const R qb = lds_app[ib * 16 + li];
 #pragma unroll
-            for (int rb = 0; rb < 4; ++rb) r2[rb] = MM::mma(a[rb], bv, cinit);
+            for (int rb = 0; rb < RB; ++rb) {
+              if (rb < nrb) {
+                const V r2 = MM::mma(aop[rb], bv, cinit);
 #pragma unroll
-            for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-              for (int e = 0; e < 4; ++e) tmp[rb][e] = fma(qv, MM::rsq(r2[rb][e]), tmp[rb][e]);
+                for (int e = 0; e < 4; ++e) {
+                  const R ri = MM::rsq(r2[e]);
+                  tmp[rb][e] = fma(qb, ri, tmp[rb][e]);
+                  rsum = fma(qa[rb][e], ri, rsum);
+                }
+              }
+            }
           } else {
-            const R dv = lds[kChunk * GEO + ib * 80 + lane];
-            const R dw = lds[kChunk * GEO + ib * 80 + 64 + li];
+            const R dv = lds_app[ib * 80 + lane];
+            const R dw = lds_app[ib * 80 + 64 + li];
             const V c2 = {dw, dw, dw, dw};
+            const V zero = {R(0), R(0), R(0), R(0)};
 #pragma unroll
-            for (int rb = 0; rb < 4; ++rb) {
-              const V r2 = MM::mma(a[rb], bv, cinit);
-              const V dt = MM::mma(a[rb], dv, c2);
+            for (int rb = 0; rb < RB; ++rb) {
+              if (rb < nrb) {
+                const V r2 = MM::mma(aop[rb], bv, cinit);
+                const V df = MM::mma(aop[rb], dv, c2);
+                const V dr = MM::mma(a3[rb], bv, zero);
 #pragma unroll
-              for (int e = 0; e < 4; ++e) {
-                const R ri = MM::rsq(r2[e]);
-                tmp[rb][e] = fma(dt[e] * ri, ri * ri, tmp[rb][e]);
+                for (int e = 0; e < 4; ++e) {
+                  const R ri = MM::rsq(r2[e]);
+                  const R ri3 = ri * ri * ri;
+                  tmp[rb][e] = fma(df[e], ri3, tmp[rb][e]);
+                  rsum = fma(dr[e], ri3, rsum);
+                }
               }
             }
           }
+          // sum the four lane groups holding the same column
+          rsum += __shfl_xor(rsum, 16, 64);
+          rsum += __shfl_xor(rsum, 32, 64);
+          if (lg == 0) lds_rev[wave * (kChunk * 16) + ib * 16 + li] = rsum;
         }
+      } else {
+        for (int c = lane; c < nbc * 16; c += 64) lds_rev[wave * (kChunk * 16) + c] = R(0);
+      }
+      __syncthreads();
+      // reverse sums over the group's waves, in wave order
+      for (int c = tid; c < nbc * 16; c += blockDim.x) {
+        const int t = c0 * 16 + c;
+        if (t >= T) continue;
+        R sum = R(0);
+        for (int w = 0; w < W; ++w) sum += lds_rev[w * (kChunk * 16) + c];
+        // the double layer's reverse kernel is d_a.(y - x) = -d_a.(x - y)
+        rout[t] = need_r ? (OP == SBIE_OP_S ? sum : -sum) : R(0);
       }
     }
-    if (!wave_need) continue;
-    // add the tile under the per-target exclusion, compensated for FP32
+    if (!need_f) continue;
+    // forward tile sum added under the exclusion, compensated (TwoSum) in FP32
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int r = 16 * rb + MM::row(lg, e);
-        const bool nd = r < b1 ? need[0] : (r < b2 ? need[1] : need[2]);
-        const R v = nd ? tmp[rb][e] : R(0);
+        const R v = tmp[rb][e];
         const R sum = acc[rb][e] + v;
-        const R bp = sum - acc[rb][e];
-        lo[rb][e] += (acc[rb][e] - (sum - bp)) + (v - bp);
+        if (sizeof(R) == 4) {
+          const R bp = sum - acc[rb][e];
+          lo[rb][e] += (acc[rb][e] - (sum - bp)) + (v - bp);
+        }
         acc[rb][e] = sum;
       }
   }
-  if (!wave_live) return;
-  // reduce each row over the 16 columns held by lanes with the same l/16 (FP64)
+  // forward partials: each row summed over its 16 columns (FP64)
 #pragma unroll
-  for (int rb = 0; rb < 4; ++rb)
+  for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       double v = (double)acc[rb][e] + (double)lo[rb][e];
 #pragma unroll
       for (int off = 1; off < 16; off <<= 1) v += __shfl_xor(v, off, 64);
-      const int r = 16 * rb + MM::row(lg, e);
-      if (li == 0 && r < nrows) partial[(size_t)split * N + base + r] = v * kInv4PiD;
+      const int r = (rb0 + rb) * 16 + MM::row(lg, e);
+      if (li == 0 && rb < nrb && r < T) fwd[(size_t)split * N + (int64_t)a * T + r] = v * kInv4PiD;
     }
 }
 
@@ -295,20 +361,31 @@ sbie_status launch_far(sbie_geom* g, int op, const double* d_dens, const R* geo,
                        g->d_nx, g->d_ny, g->d_nz, g->d_w, g->M, g->T, g->T16, app);
   SBIE_HIP(hipGetLastError());
   if (ev_begin) SBIE_HIP(hipEventRecord(ev_begin, s));
-  const dim3 grid(cdiv(g->N, 256) * g->nsplit);
-  const size_t lds = (size_t)kChunk * (80 + (op == SBIE_OP_S ? 16 : 80)) * sizeof(R);
+  using PS = PairShape<R>;
+  const int RG = far_row_groups(g, sizeof(R) == 8);
+  const int nb = g->T16 / 16;
+  const int blocks = nb < PS::GB ? nb : PS::GB;
+  const dim3 grid((unsigned)((int64_t)g->M * RG * g->nsplit)), wg((unsigned)(64 * (blocks < PS::WMAX ? blocks : PS::WMAX)));
+  const size_t lds = (size_t)kChunk * (80 + (op == SBIE_OP_S ? 16 : 80) + 16 * (wg.x / 64)) * sizeof(R);
+  R* rev = reinterpret_cast<R*>(g->d_rev);
   if (op == SBIE_OP_S)
-    hipLaunchKernelGGL((k_far_mfma<R, SBIE_OP_S>), grid, blk, lds, s, geo, app, g->d_part, g->d_x, g->d_y, g->d_z,
-                       g->d_excl, g->excl_words, g->M, g->T, g->T16, g->N, g->nsplit, g->d_partial);
+    hipLaunchKernelGGL((k_far_pairs<R, SBIE_OP_S>), grid, wg, lds, s, geo, app, g->d_part, g->d_x, g->d_y, g->d_z,
+                       g->d_excl, g->excl_words, g->M, g->T, g->T16, g->N, g->nsplit, RG, g->d_partial, rev);
   else
-    hipLaunchKernelGGL((k_far_mfma<R, SBIE_OP_D>), grid, blk, lds, s, geo, app, g->d_part, g->d_x, g->d_y, g->d_z,
-                       g->d_excl, g->excl_words, g->M, g->T, g->T16, g->N, g->nsplit, g->d_partial);
+    hipLaunchKernelGGL((k_far_pairs<R, SBIE_OP_D>), grid, wg, lds, s, geo, app, g->d_part, g->d_x, g->d_y, g->d_z,
+                       g->d_excl, g->excl_words, g->M, g->T, g->T16, g->N, g->nsplit, RG, g->d_partial, rev);
   SBIE_HIP(hipGetLastError());
   if (ev_end) SBIE_HIP(hipEventRecord(ev_end, s));
   return SBIE_OK;
 }
 
 }  // namespace
+
+int far_row_groups(const sbie_geom* g, bool fp64) {
+  const int T16 = 16 * ((g->T + 15) / 16);
+  const int GB = fp64 ? PairShape<double>::GB : PairShape<float>::GB;
+  return (T16 / 16 + GB - 1) / GB;
+}
 
 sbie_status far_records(sbie_geom* g, hipStream_t s) {
   const int64_t n = (int64_t)g->M * g->T16;

@@ -125,6 +125,9 @@ struct sbie_geom {
   float* d_fstr32 = nullptr;      // [M*T16*5]
   double* d_fstr64 = nullptr;
   double* d_rcp = nullptr;        // [kRcpN] reciprocals 1/k for the near-field recurrences
+  // pair-symmetric far field: reverse sums [M][H+1][RG][T] (FP64, or FP32 in
+  // the first half for the mixed path), H = (M-1)/2, RG target-row groups
+  double* d_rev = nullptr;
   int nsplit = 8;
   uint64_t footprint = 0;
   // device memory: one block carved into every buffer above (owned, or lent by
@@ -139,6 +142,8 @@ struct sbie_geom {
 
   sbie::Timing timing;
   // the near field runs on a side stream, concurrently with the far field
+  // (plain geometries; served sessions keep one stream per lane)
+  bool fork_near = true;
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
@@ -192,7 +197,7 @@ sbie_status stokes_buffers(sbie_geom* g);
 sbie_status check_particles(const double* centers, const double* quats, const double* A, const double* C,
                             int32_t M, int32_t p, double eta, std::vector<Particle>* out);
 sbie_status make_geometry(sbie_ctx* ctx, std::vector<Particle>&& parts, int32_t p, double eta, char* blk,
-                          size_t blk_bytes, sbie_geom** out);
+                          size_t blk_bytes, bool fork_near, sbie_geom** out);
 void destroy_geometry(sbie_geom* g);
 
 // setup kernels (setup.hip)
@@ -218,7 +223,9 @@ sbie_status apply_stokes(sbie_geom* g, int prec, const double* d_dens, double* d
 // device staging [2][3][N] for host-pointer Stokes applies (allocated once)
 sbie_status stokes_staging(sbie_geom* g, double** io);
 
-// matrix-core far field (far_mfma.hip)
+// matrix-core far field (far_mfma.hip); target-row groups per particle of
+// the FP64 or the FP32 pair kernel
+int far_row_groups(const sbie_geom* g, bool fp64);
 sbie_status far_records(sbie_geom* g, hipStream_t s);
 sbie_status far_mfma(sbie_geom* g, int op, int prec, const double* d_dens, hipStream_t s, hipEvent_t ev_begin,
                      hipEvent_t ev_end);

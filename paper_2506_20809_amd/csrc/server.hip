@@ -178,7 +178,8 @@ void build_session(sbie_server* srv, sbie_session* s, int lane) {
   hipStream_t st = lctx->stream;
   char* blk = srv->arena.base + s->off;
   std::vector<Particle> parts = s->parts;
-  sbie_status rc = make_geometry(lctx, std::move(parts), s->p, s->eta, blk, s->plan, &s->g);
+  // one stream per session: concurrency comes from the other lanes
+  sbie_status rc = make_geometry(lctx, std::move(parts), s->p, s->eta, blk, s->plan, false, &s->g);
   if (rc == SBIE_OK && s->op == SBIE_OP_STOKES_S) rc = stokes_buffers(s->g);
   if (rc == SBIE_OK) {
     const size_t io = align_up(sizeof(double) * (size_t)s->nrhs * s->N);

@@ -397,6 +397,9 @@ sbie_status carve_geometry(sbie_geom* g, Carver& c) {
   SBIE_TRY(c.take(&g->d_fstr64, 5 * n16));
   SBIE_TRY(c.take(&g->d_fstr32, 5 * n16));
   SBIE_TRY(c.take(&g->d_rcp, (size_t)kRcpN));
+  // reverse sums of the pair-symmetric far field (matrix-core path, T >= 32)
+  const size_t nrev = T >= 32 ? (size_t)M * ((M - 1) / 2 + 1) * far_row_groups(g, true) * T : 1;
+  SBIE_TRY(c.take(&g->d_rev, nrev));
   return SBIE_OK;
 }
 
@@ -442,9 +445,11 @@ sbie_status setup_geometry(sbie_geom* g, hipStream_t s) {
     g->blk_used = c.used;
   }
   g->footprint = g->blk_bytes;
-  SBIE_HIP(hipStreamCreateWithFlags(&g->side, hipStreamNonBlocking));
-  SBIE_HIP(hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming));
-  SBIE_HIP(hipEventCreateWithFlags(&g->ev_join, hipEventDisableTiming));
+  if (g->fork_near) {
+    SBIE_HIP(hipStreamCreateWithFlags(&g->side, hipStreamNonBlocking));
+    SBIE_HIP(hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming));
+    SBIE_HIP(hipEventCreateWithFlags(&g->ev_join, hipEventDisableTiming));
+  }
   const int Kh2 = (p + 2) * (p + 3) / 2;
   {
     std::vector<double> cd(Kh, 0.0);

@@ -573,17 +573,19 @@ sbie_status apply_stokes(sbie_geom* g, int prec, const double* d_dens, double* d
   }
   // near field on the side stream, concurrently with the self and far parts
   const bool near = (parts & SBIE_PARTS_NEAR) && g->n_near > 0;
+  const bool fork = near && g->side != nullptr;
   if (near) {
-    SBIE_TRY_C(fork_side(g, s));
-    if (timed) SBIE_HIP(hipEventRecord(ev[6], g->side));
+    if (fork) SBIE_TRY_C(fork_side(g, s));
+    hipStream_t ns = fork ? g->side : s;
+    if (timed) SBIE_HIP(hipEventRecord(ev[6], ns));
     if (p <= 8)
-      launch_near_stokes<8>(g, g->side);
+      launch_near_stokes<8>(g, ns);
     else if (p <= 16)
-      launch_near_stokes<16>(g, g->side);
+      launch_near_stokes<16>(g, ns);
     else
-      launch_near_stokes<32>(g, g->side);
+      launch_near_stokes<32>(g, ns);
     SBIE_HIP(hipGetLastError());
-    if (timed) SBIE_HIP(hipEventRecord(ev[7], g->side));
+    if (timed) SBIE_HIP(hipEventRecord(ev[7], ns));
   } else if (timed) {
     SBIE_HIP(hipEventRecord(ev[6], s));
     SBIE_HIP(hipEventRecord(ev[7], s));
@@ -618,7 +620,7 @@ sbie_status apply_stokes(sbie_geom* g, int prec, const double* d_dens, double* d
     SBIE_HIP(hipGetLastError());
   }
   if (timed) SBIE_HIP(hipEventRecord(ev[4], s));
-  if (near) SBIE_TRY_C(join_side(g, s));
+  if (fork) SBIE_TRY_C(join_side(g, s));
   // with no near pairs the near part is empty and is left out of the sum
   const uint32_t sum_parts = g->n_near > 0 ? parts : (parts & ~(uint32_t)SBIE_PARTS_NEAR);
   hipLaunchKernelGGL(k_stokes_assemble, dim3(cdiv(3 * N, B)), dim3(B), 0, s, g->d_stk_self, g->d_stk_near,

@@ -183,7 +183,10 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
       for (int e = 0; e < 4; ++e) tmp[rb][e] = R(0);
     for (int c0 = 0; c0 < nb; c0 += kChunk) {
       const int nbc = nb - c0 < kChunk ? nb - c0 : kChunk;
-      __syncthreads();  // the previous chunk (operands and reverse sums) has been consumed
+      // No barrier is needed before the staging: the previous operands were
+      // last read before the barrier that precedes the previous reverse
+      // reduction, and the reverse sums are next written only after the
+      // barrier below, which every thread reaches after its reduction.
       {
         using C16 = typename std::conditional<sizeof(R) == 4, float4, double2>::type;
         constexpr int PER = 16 / sizeof(R);

@@ -5,6 +5,7 @@
 
 #include <cmath>
 
+#include "near_dev.h"
 #include "sbie_internal.h"
 
 namespace sbie {
@@ -12,7 +13,6 @@ namespace sbie {
 namespace {
 
 constexpr double kInv4Pi = 0.079577471545947667884441881686257181;
-constexpr int kGroup = 4;  // orders m whose backward recurrences run together
 
 using d4 = double __attribute__((ext_vector_type(4)));
 using f4 = float __attribute__((ext_vector_type(4)));
@@ -170,14 +170,13 @@ __global__ void k_scale_coef(const double* __restrict__ coef, const double* __re
 
 // One wave per (target particle, 64 target nodes).  Each lane maps its target
 // into the frame of every near source i (ascending i), finds (u, v, phi) from
-// the focal distances, evaluates Q_n^m(u) for every order m in FP64 and sums
-// E_l Q_n^|m|(u)/Q_n^|m|(u0) Y_l(v, phi).  Q_n^m(u) is the minimal solution of
-// the three-term recurrence of Section 2.3: it is obtained by running that
-// recurrence backward from a depth where the continued fraction for Q_N/Q_{N-1}
-// has converged to double precision (Miller's form of the same continued
-// fraction, free of divisions), and normalised with the Casoratian against
-// P_N, P_{N-1} from the forward recurrence -- the same three ingredients as the
-// paper's Lentz / Wronskian / backward scheme, ordered for the vector units.
+// the focal distances and sums E_l Q_n^|m|(u)/Q_n^|m|(u0) Y_l(v, phi).  The
+// paper's Legendre algorithm (continued fraction for Q_N/Q_{N-1}, Casoratian,
+// backward recurrence; Section 2.3) gives Q_N and Q_{N+1} for orders 0 and 1
+// (the continued fraction in Miller's form: the backward recurrence itself
+// from a depth where it has converged to double precision); higher orders
+// follow from the recurrence in the order at fixed degree, and every column
+// Q_n^m, n = m..N+1, from the backward recurrence in n.  All in FP64.
 template <int PMAX>
 __global__ __launch_bounds__(64) void k_near_f64(
     const Particle* __restrict__ part, const double* __restrict__ x, const double* __restrict__ y,
@@ -185,7 +184,6 @@ __global__ __launch_bounds__(64) void k_near_f64(
     const int32_t* __restrict__ near_src, const double* __restrict__ E,
     const double* __restrict__ lam, const double* __restrict__ ab, const double* __restrict__ rcp, int p,
     int T, int chunks, unsigned* status, double* __restrict__ unear) {
-  __shared__ double qpark[kGroup][2][64];
   const int j = blockIdx.x / chunks;
   const int t = (blockIdx.x - j * chunks) * 64 + threadIdx.x;
   const bool live = t < T;
@@ -228,120 +226,31 @@ __global__ __launch_bounds__(64) void k_near_f64(
     const double v = b2 / (a * u);
     const double sv = rho / (a * sw);  // sqrt(1 - v^2)
     const double c1 = rho > 0.0 ? b0 / rho : 1.0, s1 = rho > 0.0 ? b1 / rho : 0.0;
-    // depth of the backward recurrence: the ratio of the minimal to the dominant
-    // solution shrinks by (u + sqrt(u^2 -+ 1))^-2 per degree; 2^-58 plus a
-    // margin, the same for the whole wave
-    int steps = (int)ceil(20.1 / log(u + sw)) + 8;
-    for (int off = 32; off >= 1; off >>= 1) steps = max(steps, __shfl_xor(steps, off, 64));
-    steps = __builtin_amdgcn_readfirstlane(steps);
-    if (steps > 100000) {
-      steps = 100000;
-      bad |= kStatNumeric;
-    }
-    steps = (steps + 7) & ~7;  // whole chunks of eight steps
-    const int L = N + steps;
-
-    double pmm_u = 1.0;                        // P_m^m(u) (real form)
-    double pbar = 0.28209479177387814347;      // normalised Ferrers Pb_m^m(v), 1/sqrt(4 pi) at m = 0
-    double cm = 1.0, sm = 0.0;                 // cos(m phi), sin(m phi)
-    double cas2 = 1.0;                         // (-1)^m (N+m-1)!
-    for (int k = 2; k < N; ++k) cas2 *= (double)k;
     const double sgn = P.oblate ? 1.0 : -1.0;
-    for (int m0 = 0; m0 <= p; m0 += kGroup) {
-      // The minimal solution Q of the recurrence in n, unnormalised, by
-      // backward recurrence from degree L (the continued fraction for
-      // Q_N/Q_{N-1} evaluated bottom-up from depth L-N).  With Q_n = s_n R_n
-      // and s_{n-1} = s_n/(n+m) the recurrence is free of divisions:
-      //   R_{n-1} = (2n+1) u R_n -+ (n-m+1)(n+m+1) R_{n+1},
-      // where (n-m+1)(n+m+1) = (n+1)^2 - m^2; rescaled by 2^-600 whenever it
-      // grows past 2^600.  kGroup orders run together (independent chains that
-      // share the depth and the (2n+1) u factor); each lane parks its R_N,
-      // R_{N+1} in LDS for the per-order work below.
-      {
-        double qh[kGroup], qc[kGroup], smsq[kGroup];
-#pragma unroll
-        for (int k = 0; k < kGroup; ++k) {
-          qh[k] = 0.0;
-          qc[k] = 1.0;
-          smsq[k] = sgn * (double)((m0 + k) * (m0 + k));
-        }
-        double c2n1 = (double)(2 * L + 1), snp = sgn * (double)(L + 1) * (double)(L + 1), sc = sgn * c2n1;
-        const double dsc = -2.0 * sgn;
-        for (int n = L; n > N; n -= 8) {
-#pragma unroll
-          for (int i = 0; i < 8; ++i) {
-            const double cu = c2n1 * u;
-#pragma unroll
-            for (int k = 0; k < kGroup; ++k) {
-              const double qn = fma(cu, qc[k], (snp - smsq[k]) * qh[k]);
-              qh[k] = qc[k];
-              qc[k] = qn;
-            }
-            snp -= sc;
-            sc += dsc;
-            c2n1 -= 2.0;
-          }
-#pragma unroll
-          for (int k = 0; k < kGroup; ++k)
-            if (fabs(qc[k]) > 0x1p600) {
-              qc[k] *= 0x1p-600;
-              qh[k] *= 0x1p-600;
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < kGroup; ++k) {
-          qpark[k][0][threadIdx.x] = qc[k];
-          qpark[k][1][threadIdx.x] = qh[k];
-        }
-      }
-      const int mend = m0 + kGroup <= p + 1 ? m0 + kGroup : p + 1;
-      for (int m = m0; m < mend; ++m) {
+    const int L = near_depth(u, sw, N, kStatNumeric, &bad);
+    // Q_N^m, Q_{N+1}^m: orders 0 and 1 from the backward recurrence and the
+    // Casoratian, higher orders by the upward recurrence in m
+    double qn0[2], qn1[2];
+    q_top_orders01(u, sw, sgn, N, L, rcp, qn0, qn1);
+    const double ur = u / sw;
+    double fa2 = 0.0, fa1 = 0.0, fb2 = 0.0, fb1 = 0.0;  // F^(m-2), F^(m-1) at degrees N and N+1
+    double pbar = 0.28209479177387814347;  // normalised Ferrers Pb_m^m(v), 1/sqrt(4 pi) at m = 0
+    double cm = 1.0, sm = 0.0;             // cos(m phi), sin(m phi)
+    for (int m = 0; m <= p; ++m) {
       if (m > 0) {
-        pmm_u *= (double)(2 * m - 1) * sw;
         pbar *= sqrt((2.0 * m + 1.0) / (2.0 * m)) * sv;
         const double cn = cm * c1 - sm * s1;
         sm = sm * c1 + cm * s1;
         cm = cn;
-        cas2 = -cas2 * (double)(N + m - 1);
       }
-      // forward recurrence for Pt_n = (n-m)! P_n^m(u), free of divisions:
-      //   Pt_{n+1} = (2n+1) u Pt_n -+ (n+m)(n-m) Pt_{n-1}   (- prolate, + oblate)
-      double pa = pmm_u, pb = (double)(2 * m + 1) * u * pmm_u;  // Pt_m, Pt_{m+1}
-      {
-        double c2n1 = (double)(2 * m + 3), cnm = (double)(2 * m + 1), cdn = 1.0;  // 2n+1, n+m, n-m at n = m+1
-        for (int n = m + 1; n < N; ++n) {
-          const double pc = fma(c2n1 * u, pb, sgn * (cnm * cdn) * pa);
-          pa = pb;
-          pb = pc;
-          c2n1 += 2.0;
-          cnm += 1.0;
-          cdn += 1.0;
-        }
-      }
-      // now pa = Pt_{N-1}, pb = Pt_N (m <= p = N-1 so N >= m+1)
-      double qcur = qpark[m - m0][0][threadIdx.x], qhi = qpark[m - m0][1][threadIdx.x];  // R_N, R_{N+1}
-      // R_N, R_{N+1} -> Q~_N = R_N/(N+m+1), Q~_{N+1} = R_{N+1} (s_{N+1} = 1)
-      qcur *= rcp[N + m + 1];
-      // qcur = Q~_N, qhi = Q~_{N+1}; continue into registers indexed by degree
+      const double qN = m == 0 ? qn0[0] : (m == 1 ? qn0[1] : q_next_order(ur, N, m, fa1, fa2));
+      const double qN1 = m == 0 ? qn1[0] : (m == 1 ? qn1[1] : q_next_order(ur, N + 1, m, fb1, fb2));
+      fa2 = fa1;
+      fa1 = qN;
+      fb2 = fb1;
+      fb1 = qN1;
       double Q[PMAX + 4];
-      double qN1 = 0.0;
-#pragma unroll
-      for (int n = PMAX + 2; n >= 0; --n) {
-        if (n == N + 1) {
-          Q[n] = qhi;
-        } else if (n == N) {
-          Q[n] = qcur;
-        } else if (n < N && n >= m) {
-          Q[n] = fma((double)(2 * n + 3) * u, Q[n + 1], sgn * (double)(n - m + 2) * Q[n + 2]) * rcp[n + m + 1];
-        } else {
-          Q[n] = 0.0;
-        }
-        if (n == N - 1) qN1 = Q[n];
-      }
-      // normalise with the Casoratian at degree N, P_N Q_{N-1} -+ P_{N-1} Q_N =
-      // (-1)^m (N+m-1)!/(N-m)!, written for Pt = (n-m)! P:
-      //   Pt_N Q_{N-1} -+ (N-m) Pt_{N-1} Q_N = (-1)^m (N+m-1)!
-      const double qscale = cas2 / fma(sgn * (double)(N - m) * pa, qcur, pb * qN1);
+      q_column<PMAX>(u, sgn, N, m, qN, qN1, rcp, Q);
       // contraction with the normalised Ferrers functions, forward in n
       double sc = 0.0, ss = 0.0;
       double p2 = 0.0, p1 = pbar;
@@ -361,7 +270,7 @@ __global__ __launch_bounds__(64) void k_near_f64(
             p2 = p1;
             p1 = pn;
           }
-          const double qr = Q[n] * qscale * Li[(n * (n + 1) / 2 + m) * 4 + 3];
+          const double qr = Q[n] * Li[(n * (n + 1) / 2 + m) * 4 + 3];
           const double t0 = pn * qr;
           sc = fma(Ei[n * n + n + m], t0, sc);
           if (m > 0) ss = fma(Ei[n * n + n - m], t0, ss);
@@ -371,7 +280,6 @@ __global__ __launch_bounds__(64) void k_near_f64(
         acc += sc;
       else
         acc += 1.41421356237309504880 * (sc * cm + ss * sm);
-      }
     }
   }
   if (bad) atomicOr(status, bad);

@@ -12,6 +12,7 @@
 
 #include <cmath>
 
+#include "near_dev.h"
 #include "sbie_internal.h"
 
 namespace sbie {
@@ -19,7 +20,6 @@ namespace sbie {
 namespace {
 
 constexpr double kInv8Pi = 0.039788735772973833942220940843128591;
-constexpr int kGroup = 4;  // orders m whose backward recurrences run together
 
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
@@ -145,7 +145,6 @@ __global__ __launch_bounds__(64) void k_near_stokes(
     const double* __restrict__ E, const double* __restrict__ lam, const double* __restrict__ ab,
     const double* __restrict__ cd, const double* __restrict__ rcp, int p, int T, int chunks, int64_t N,
     unsigned* status, double* __restrict__ unear) {
-  __shared__ double qpark[kGroup][2][64];
   const int j = blockIdx.x / chunks;
   const int t = (blockIdx.x - j * chunks) * 64 + threadIdx.x;
   const bool live = t < T;
@@ -189,101 +188,29 @@ __global__ __launch_bounds__(64) void k_near_stokes(
     const double inv_omv2 = 1.0 / (sv * sv);
     const double inv_w = 1.0 / w;
     const double c1 = rho0 > 0.0 ? b0 / rho0 : 1.0, s1 = rho0 > 0.0 ? b1 / rho0 : 0.0;
-    int steps = (int)ceil(20.1 / log(u + sw)) + 8;
-    for (int off = 32; off >= 1; off >>= 1) steps = max(steps, __shfl_xor(steps, off, 64));
-    steps = __builtin_amdgcn_readfirstlane(steps);
-    if (steps > 100000) {
-      steps = 100000;
-      bad |= kStatNumeric;
-    }
-    steps = (steps + 7) & ~7;
-    const int L = N1 + steps;
-    double Phi[4] = {0, 0, 0, 0}, Pu[4] = {0, 0, 0, 0}, Pv[4] = {0, 0, 0, 0}, Pp[4] = {0, 0, 0, 0};
-    double pmm_u = 1.0, pbar = 0.28209479177387814347, cm = 1.0, sm = 0.0;
-    double cas2 = 1.0;
-    for (int k = 2; k < N1; ++k) cas2 *= (double)k;
     const double sgn = P.oblate ? 1.0 : -1.0;
-    for (int m0 = 0; m0 <= p; m0 += kGroup) {
-      // backward recurrences of kGroup orders together, as in the Laplace
-      // near field; R_N, R_{N+1} of each order parked in LDS
-      {
-        double qh[kGroup], qc[kGroup], smsq[kGroup];
-#pragma unroll
-        for (int k = 0; k < kGroup; ++k) {
-          qh[k] = 0.0;
-          qc[k] = 1.0;
-          smsq[k] = sgn * (double)((m0 + k) * (m0 + k));
-        }
-        double c2n1 = (double)(2 * L + 1), snp = sgn * (double)(L + 1) * (double)(L + 1), sc = sgn * c2n1;
-        const double dsc = -2.0 * sgn;
-        for (int n = L; n > N1; n -= 8) {
-#pragma unroll
-          for (int i = 0; i < 8; ++i) {
-            const double cu = c2n1 * u;
-#pragma unroll
-            for (int k = 0; k < kGroup; ++k) {
-              const double qn = fma(cu, qc[k], (snp - smsq[k]) * qh[k]);
-              qh[k] = qc[k];
-              qc[k] = qn;
-            }
-            snp -= sc;
-            sc += dsc;
-            c2n1 -= 2.0;
-          }
-#pragma unroll
-          for (int k = 0; k < kGroup; ++k)
-            if (fabs(qc[k]) > 0x1p600) {
-              qc[k] *= 0x1p-600;
-              qh[k] *= 0x1p-600;
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < kGroup; ++k) {
-          qpark[k][0][threadIdx.x] = qc[k];
-          qpark[k][1][threadIdx.x] = qh[k];
-        }
-      }
-      const int mend = m0 + kGroup <= p + 1 ? m0 + kGroup : p + 1;
-      for (int m = m0; m < mend; ++m) {
+    const int L = near_depth(u, sw, N1, kStatNumeric, &bad);
+    double Phi[4] = {0, 0, 0, 0}, Pu[4] = {0, 0, 0, 0}, Pv[4] = {0, 0, 0, 0}, Pp[4] = {0, 0, 0, 0};
+    double qn0[2], qn1[2];
+    q_top_orders01(u, sw, sgn, N1, L, rcp, qn0, qn1);
+    const double ur = u / sw;
+    double fa2 = 0.0, fa1 = 0.0, fb2 = 0.0, fb1 = 0.0;
+    double pbar = 0.28209479177387814347, cm = 1.0, sm = 0.0;
+    for (int m = 0; m <= p; ++m) {
       if (m > 0) {
-        pmm_u *= (double)(2 * m - 1) * sw;
         pbar *= sqrt((2.0 * m + 1.0) / (2.0 * m)) * sv;
         const double cn = cm * c1 - sm * s1;
         sm = sm * c1 + cm * s1;
         cm = cn;
-        cas2 = -cas2 * (double)(N1 + m - 1);
       }
-      // Pt_n = (n-m)! P_n^m(u), forward and division-free
-      double pa = pmm_u, pb = (double)(2 * m + 1) * u * pmm_u;
-      {
-        double c2n1 = (double)(2 * m + 3), cnm = (double)(2 * m + 1), cdn = 1.0;
-        for (int n = m + 1; n < N1; ++n) {
-          const double pc = fma(c2n1 * u, pb, sgn * (cnm * cdn) * pa);
-          pa = pb;
-          pb = pc;
-          c2n1 += 2.0;
-          cnm += 1.0;
-          cdn += 1.0;
-        }
-      }
-      double qcur = qpark[m - m0][0][threadIdx.x], qhi = qpark[m - m0][1][threadIdx.x];
-      qcur *= rcp[N1 + m + 1];
+      const double qN = m == 0 ? qn0[0] : (m == 1 ? qn0[1] : q_next_order(ur, N1, m, fa1, fa2));
+      const double qN1 = m == 0 ? qn1[0] : (m == 1 ? qn1[1] : q_next_order(ur, N1 + 1, m, fb1, fb2));
+      fa2 = fa1;
+      fa1 = qN;
+      fb2 = fb1;
+      fb1 = qN1;
       double Q[PMAX + 4];
-      double qN1 = 0.0;
-#pragma unroll
-      for (int n = PMAX + 2; n >= 0; --n) {
-        if (n == N1 + 1) {
-          Q[n] = qhi;
-        } else if (n == N1) {
-          Q[n] = qcur;
-        } else if (n < N1 && n >= m) {
-          Q[n] = fma((double)(2 * n + 3) * u, Q[n + 1], sgn * (double)(n - m + 2) * Q[n + 2]) * rcp[n + m + 1];
-        } else {
-          Q[n] = 0.0;
-        }
-        if (n == N1 - 1) qN1 = Q[n];
-      }
-      const double qscale = cas2 / fma(sgn * (double)(N1 - m) * pa, qcur, pb * qN1);
+      q_column<PMAX>(u, sgn, N1, m, qN, qN1, rcp, Q);
       // normalised Ferrers functions of v through degree p+1
       double Pb[PMAX + 3];
       {
@@ -312,7 +239,7 @@ __global__ __launch_bounds__(64) void k_near_stokes(
       for (int n = 0; n <= PMAX; ++n) {
         if (n >= m && n <= p) {
           const int h = n * (n + 1) / 2 + m;
-          const double sc = qscale * Li[h * 4 + 3];
+          const double sc = Li[h * 4 + 3];
           const double qr = Q[n] * sc;
           const double dq = ((-sgn) * (double)(n - m + 1) * Q[n + 1] - (double)(n + 1) * u * Q[n]) * inv_w * sc;
           const double pn = Pb[n];
@@ -340,7 +267,6 @@ __global__ __launch_bounds__(64) void k_near_stokes(
         Pu[s] += f * (uc[s] * cm + us[s] * sm);
         Pv[s] += f * (wc[s] * cm + ws[s] * sm);
         Pp[s] += f * (double)m * (vs[s] * cm - vc[s] * sm);
-      }
       }
     }
     const double d[3] = {d0, d1, d2};

@@ -74,6 +74,8 @@ struct PairShape {
   static constexpr int WMAX = sizeof(R) == 4 ? 12 : 8;
   static constexpr int RBMAX = sizeof(R) == 4 ? 4 : 5;
   static constexpr int GB = WMAX * RBMAX;  // row blocks per group
+  // row blocks whose matrix-core products are issued together
+  static constexpr int batch(bool) { return 4; }
 };
 
 // Pair-symmetric far field.  Every unordered pair of particles (a, b) is
@@ -118,12 +120,14 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
   const int cnt = nb - rbg < GB ? nb - rbg : GB;               // row blocks of the group
   const int rb0 = rbg + (wave * cnt) / W;                      // this wave's blocks rb0 .. rb0+nrb-1
   const int nrb = rbg + ((wave + 1) * cnt) / W - rb0;
+  const int nrb_u = __builtin_amdgcn_readfirstlane(nrb);  // wave-uniform, for the compiler
   const int H = (M - 1) / 2;
   const bool even = (M & 1) == 0;
   const int P = H + ((even && a < M / 2) ? 1 : 0);
   const int k0 = (int)((int64_t)P * split / nsplit), k1 = (int)((int64_t)P * (split + 1) / nsplit);
   const Particle& Pa = part[a];
 
+  // target rows of this wave: A-operand rows (lane li) and accumulator rows
   // target rows of this wave: A-operand rows (lane li) and accumulator rows
   double tc[RB][3];
   R da[RB][3];   // double layer: d_a of the A-operand row
@@ -165,6 +169,8 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
       continue;
     }
     const double cx = part[b].c[0], cy = part[b].c[1], cz = part[b].c[2];
+    // A operands of this wave's rows against partner b: [D |D|^2] with
+    // D = x - c_b; double layer also [d_a/2  d_a.D]
     R aop[RB], a3[RB];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
@@ -198,25 +204,36 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
         for (int i = tid; i < nbc * APP / PER; i += blockDim.x) la[i] = as[i];
       }
       __syncthreads();
-      if (nrb > 0) {
+      // the tiles of one source block for NR row blocks, unrolled so that the
+      // matrix-core products of all NR blocks are issued before their vector
+      // work (the row-block count is wave-uniform: one branch per wave)
+      auto tiles = [&](auto nr) {
+        constexpr int NR = decltype(nr)::value;
         for (int ib = 0; ib < nbc; ++ib) {
           const R bv = lds_geo[ib * GEO + lane];
           const R cw = lds_geo[ib * GEO + 64 + li];
           const V cinit = {cw, cw, cw, cw};
           R rsum = R(0);  // reverse sum for source column li over this lane's rows
+          // row blocks in batches of G: the batch's matrix-core products first,
+          // then its vector work (G bounded by the registers)
+          constexpr int G = PairShape<R>::batch(OP == SBIE_OP_S);
           if (OP == SBIE_OP_S) {
             const R qb = lds_app[ib * 16 + li];
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb) {
-              if (rb < nrb) {
-                const V r2 = MM::mma(aop[rb], bv, cinit);
+            for (int g0 = 0; g0 < NR; g0 += G) {
+              V r2[G];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                  const R ri = MM::rsq(r2[e]);
-                  tmp[rb][e] = fma(qb, ri, tmp[rb][e]);
-                  rsum = fma(qa[rb][e], ri, rsum);
-                }
-              }
+              for (int j = 0; j < G; ++j)
+                if (g0 + j < NR) r2[j] = MM::mma(aop[g0 + j], bv, cinit);
+#pragma unroll
+              for (int j = 0; j < G; ++j)
+                if (g0 + j < NR)
+#pragma unroll
+                  for (int e = 0; e < 4; ++e) {
+                    const R ri = MM::rsq(r2[j][e]);
+                    tmp[g0 + j][e] = fma(qb, ri, tmp[g0 + j][e]);
+                    rsum = fma(qa[g0 + j][e], ri, rsum);
+                  }
             }
           } else {
             const R dv = lds_app[ib * 80 + lane];
@@ -224,19 +241,25 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
             const V c2 = {dw, dw, dw, dw};
             const V zero = {R(0), R(0), R(0), R(0)};
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb) {
-              if (rb < nrb) {
-                const V r2 = MM::mma(aop[rb], bv, cinit);
-                const V df = MM::mma(aop[rb], dv, c2);
-                const V dr = MM::mma(a3[rb], bv, zero);
+            for (int g0 = 0; g0 < NR; g0 += G) {
+              V r2[G], df[G], dr[G];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                  const R ri = MM::rsq(r2[e]);
-                  const R ri3 = ri * ri * ri;
-                  tmp[rb][e] = fma(df[e], ri3, tmp[rb][e]);
-                  rsum = fma(dr[e], ri3, rsum);
+              for (int j = 0; j < G; ++j)
+                if (g0 + j < NR) {
+                  r2[j] = MM::mma(aop[g0 + j], bv, cinit);
+                  df[j] = MM::mma(aop[g0 + j], dv, c2);
+                  dr[j] = MM::mma(a3[g0 + j], bv, zero);
                 }
-              }
+#pragma unroll
+              for (int j = 0; j < G; ++j)
+                if (g0 + j < NR)
+#pragma unroll
+                  for (int e = 0; e < 4; ++e) {
+                    const R ri = MM::rsq(r2[j][e]);
+                    const R ri3 = ri * ri * ri;
+                    tmp[g0 + j][e] = fma(df[j][e], ri3, tmp[g0 + j][e]);
+                    rsum = fma(dr[j][e], ri3, rsum);
+                  }
             }
           }
           // sum the four lane groups holding the same column
@@ -244,8 +267,72 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
           rsum += __shfl_xor(rsum, 32, 64);
           if (lg == 0) lds_rev[wave * (kChunk * 16) + ib * 16 + li] = rsum;
         }
-      } else {
-        for (int c = lane; c < nbc * 16; c += 64) lds_rev[wave * (kChunk * 16) + c] = R(0);
+      };
+      if constexpr (sizeof(R) == 8) {
+        // FP64: one row block at a time under a wave-uniform guard (the
+        // batched form does not fit the FP64 operands in registers)
+        if (nrb > 0) {
+          for (int ib = 0; ib < nbc; ++ib) {
+            const R bv = lds_geo[ib * GEO + lane];
+            const R cw = lds_geo[ib * GEO + 64 + li];
+            const V cinit = {cw, cw, cw, cw};
+            R rsum = R(0);
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+              if (rb < nrb) {
+                if (OP == SBIE_OP_S) {
+                  const R qb = lds_app[ib * 16 + li];
+                  const V r2 = MM::mma(aop[rb], bv, cinit);
+#pragma unroll
+                  for (int e = 0; e < 4; ++e) {
+                    const R ri = MM::rsq(r2[e]);
+                    tmp[rb][e] = fma(qb, ri, tmp[rb][e]);
+                    rsum = fma(qa[rb][e], ri, rsum);
+                  }
+                } else {
+                  const R dv = lds_app[ib * 80 + lane];
+                  const R dw = lds_app[ib * 80 + 64 + li];
+                  const V c2 = {dw, dw, dw, dw};
+                  const V zero = {R(0), R(0), R(0), R(0)};
+                  const V r2 = MM::mma(aop[rb], bv, cinit);
+                  const V df = MM::mma(aop[rb], dv, c2);
+                  const V dr = MM::mma(a3[rb], bv, zero);
+#pragma unroll
+                  for (int e = 0; e < 4; ++e) {
+                    const R ri = MM::rsq(r2[e]);
+                    const R ri3 = ri * ri * ri;
+                    tmp[rb][e] = fma(df[e], ri3, tmp[rb][e]);
+                    rsum = fma(dr[e], ri3, rsum);
+                  }
+                }
+              }
+            }
+            rsum += __shfl_xor(rsum, 16, 64);
+            rsum += __shfl_xor(rsum, 32, 64);
+            if (lg == 0) lds_rev[wave * (kChunk * 16) + ib * 16 + li] = rsum;
+          }
+        } else {
+          for (int c = lane; c < nbc * 16; c += 64) lds_rev[wave * (kChunk * 16) + c] = R(0);
+        }
+      } else switch (nrb_u) {
+        case 0:
+          for (int c = lane; c < nbc * 16; c += 64) lds_rev[wave * (kChunk * 16) + c] = R(0);
+          break;
+        case 1:
+          tiles(std::integral_constant<int, 1>{});
+          break;
+        case 2:
+          tiles(std::integral_constant<int, 2>{});
+          break;
+        case 3:
+          tiles(std::integral_constant<int, 3>{});
+          break;
+        case 4:
+          tiles(std::integral_constant<int, 4 <= RB ? 4 : RB>{});
+          break;
+        default:
+          tiles(std::integral_constant<int, RB>{});
+          break;
       }
       __syncthreads();
       // reverse sums over the group's waves, in wave order

@@ -55,7 +55,7 @@ def counter_traffic(precision, workload):
     kernel's source has changed since the counters were taken."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", f"far_mfma_{workload}_{precision}_hbm_counters.md")
+    path = os.path.join(ROOT, "profiles", f"far_pairs_{workload}_{precision}_hbm_counters.md")
     src = os.path.join(ROOT, "paper_2506_20809_amd", "csrc", "far_mfma.hip")
     if not os.path.exists(path):
         return None
@@ -111,8 +111,8 @@ def run(g, dens, steps, warmup, precision):
         "far_pairs": tim.far_pairs,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS[precision], "unit": "TFLOP/s",
                      "frac": achieved / PEAK_TFLOPS[precision], "traffic": None,
-                     "kernel": "k_far_mfma<float> (S and D alternating)" if precision == "mixed"
-                     else "k_far_mfma<double> (S and D alternating)",
+                     "kernel": "k_far_pairs<float> (S and D alternating)" if precision == "mixed"
+                     else "k_far_pairs<double> (S and D alternating)",
                      "flops_per_launch": flops_per_launch},
     }
 

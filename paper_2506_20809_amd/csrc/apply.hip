@@ -489,38 +489,32 @@ sbie_status apply_laplace(sbie_geom* g, int op, int prec, const double* d_dens, 
                        g->d_cself, g->d_E);
     SBIE_HIP(hipGetLastError());
   }
-  // part (c) near field, on the side stream once the exterior coefficients
-  // exist: its long FP64 recurrences leave the vector units idle between
-  // dependent steps, which the self and far-field waves fill
-  const bool near = (parts & SBIE_PARTS_NEAR) && g->n_near > 0;
-  const bool fork = near && g->side != nullptr;
-  if (near) {
-    if (fork) {
-      sbie_status st = fork_side(g, s);
-      if (st) return st;
-    }
-    hipStream_t ns = fork ? g->side : s;
-    if (timed) SBIE_HIP(hipEventRecord(ev[6], ns));
-    if (p <= 8)
-      launch_near<8>(g, ns);
-    else if (p <= 16)
-      launch_near<16>(g, ns);
-    else
-      launch_near<32>(g, ns);
-    SBIE_HIP(hipGetLastError());
-    if (timed) SBIE_HIP(hipEventRecord(ev[7], ns));
-  } else if (timed) {
-    SBIE_HIP(hipEventRecord(ev[6], s));
-    SBIE_HIP(hipEventRecord(ev[7], s));
-  }
   if (parts & SBIE_PARTS_SELF) {
     sbie_status st = mixed ? launch_gemm32(g->d_cself, K, g->d_Sy32, T, g->d_uself, T, M, T, K, s)
                            : launch_gemm(g->d_cself, K, g->d_Sy, T, g->d_uself, T, M, T, K, s);
     if (st) return st;
   }
   if (timed) SBIE_HIP(hipEventRecord(ev[2], s));
-  // part (d) far field: matrix-core tiles when a wave of 64 targets spans at
-  // most three particles (T >= 32), else the vector-unit sum in FP64
+  // part (c) near field, on the apply's stream: the pair-symmetric far kernel
+  // fills every compute unit, so running the two concurrently gains nothing
+  // measurable (1-2%) and would blur the far kernel's own timing
+  const bool near = (parts & SBIE_PARTS_NEAR) && g->n_near > 0;
+  if (near) {
+    if (timed) SBIE_HIP(hipEventRecord(ev[6], s));
+    if (p <= 8)
+      launch_near<8>(g, s);
+    else if (p <= 16)
+      launch_near<16>(g, s);
+    else
+      launch_near<32>(g, s);
+    SBIE_HIP(hipGetLastError());
+    if (timed) SBIE_HIP(hipEventRecord(ev[7], s));
+  } else if (timed) {
+    SBIE_HIP(hipEventRecord(ev[6], s));
+    SBIE_HIP(hipEventRecord(ev[7], s));
+  }
+  // part (d) far field: the pair-symmetric matrix-core kernel (T >= 32, i.e.
+  // p >= 3), else the vector-unit sum in FP64
   if ((parts & SBIE_PARTS_FAR) && T >= 32) {
     sbie_status st = far_mfma(g, op, prec, d_dens, s, timed ? ev[3] : nullptr, timed ? ev[4] : nullptr);
     if (st) return st;
@@ -539,10 +533,6 @@ sbie_status apply_laplace(sbie_geom* g, int op, int prec, const double* d_dens, 
   } else if (timed) {
     SBIE_HIP(hipEventRecord(ev[3], s));
     SBIE_HIP(hipEventRecord(ev[4], s));
-  }
-  if (fork) {
-    sbie_status st = join_side(g, s);
-    if (st) return st;
   }
   // with no near pairs the near part is empty and is left out of the sum
   const uint32_t sum_parts = g->n_near > 0 ? parts : (parts & ~(uint32_t)SBIE_PARTS_NEAR);

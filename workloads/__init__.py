@@ -315,6 +315,46 @@ def generate(name: str):
     return g
 
 
+def lattice2x2(R: float, Rd: float, C: float = 1.0):
+    """Four identical upright prolate spheroids (polar semi-axis C along z,
+    equatorial C/R) at the corners of a square in the x-y plane, the surface
+    gap between neighbours d = Rd/R (the lattice of the GMRES study)."""
+    A = C / R
+    d = Rd / R
+    h = A + 0.5 * d
+    centers = np.array([[-h, -h, 0.0], [h, -h, 0.0], [-h, h, 0.0], [h, h, 0.0]])
+    return {"centers": centers, "quats": np.tile([1.0, 0.0, 0.0, 0.0], (4, 1)),
+            "A": np.full(4, A), "C": np.full(4, C)}
+
+
+def point_charges(geom, per_particle: int, seed: int, shrink: float = 0.5):
+    """Point charges inside every particle: positions uniform in the particle
+    scaled by `shrink` about its centre, strengths uniform in [-0.5, 0.5].
+    Returns (positions [S, 3], strengths [S])."""
+    rng = np.random.default_rng(seed)
+    pos, q = [], []
+    for c, qt, A, C in zip(geom["centers"], geom["quats"], geom["A"], geom["C"]):
+        Rm = quat_rot(qt)
+        k = 0
+        while k < per_particle:
+            b = rng.uniform(-1.0, 1.0, size=3)
+            if b @ b > 1.0:
+                continue
+            body = shrink * np.array([A * b[0], A * b[1], C * b[2]])
+            pos.append(np.asarray(c) + Rm @ body)
+            q.append(rng.uniform(-0.5, 0.5))
+            k += 1
+    return np.array(pos), np.array(q)
+
+
+def charge_potential(pos, q, x):
+    """Harmonic data of the charges at points x [n, 3]: sum_j q_j / (4 pi |x - x_j|)."""
+    out = np.zeros(len(x))
+    for pj, qj in zip(pos, q):
+        out += qj / (4.0 * math.pi * np.linalg.norm(x - pj, axis=1))
+    return out
+
+
 def served_request(req):
     """Geometry of one served request: the M particles of the 1024-particle pool
     packing (volume fraction 0.15, gap 0.05) whose centres lie nearest to a

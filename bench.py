@@ -15,6 +15,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -171,6 +172,99 @@ def run_stokes(ctx, steps, warmup, precision):
     return res
 
 
+# GMRES iteration counts printed in the paper's table of the lattice study
+# (Section 5.2, four prolates at p = 16, tolerance 1e-10), for context:
+# {R: {R*d: (C_I, eta C_I, S, eta S)}}
+PAPER_GMRES = {
+    1.1: {2.0: (14, 13, 10, 10), 1.0: (15, 14, 11, 12), 0.01: (36, 33, 33, 34)},
+    2.0: {2.0: (19, 17, 12, 14), 1.0: (19, 17, 13, 16), 0.01: (39, 35, 35, 37)},
+    4.0: {2.0: (27, 26, 16, 15), 1.0: (28, 27, 18, 17), 0.01: (49, 51, 39, 38)},
+    8.0: {2.0: (44, 42, 23, 20), 1.0: (45, 45, 25, 21), 0.01: (65, 68, 51, 45)},
+    16.0: {2.0: (69, 67, 31, 24), 1.0: (75, 72, 34, 26), 0.01: (107, 115, 68, 52)},
+    32.0: {2.0: (103, 100, 40, 31), 1.0: (109, 107, 45, 32), 0.01: (170, 169, 91, 60)},
+    64.0: {2.0: (131, 133, 47, 38), 1.0: (150, 154, 57, 40), 0.01: (223, 228, 124, 67)},
+}
+
+
+def charge_data(pos, q, xyz):
+    """Potential of point charges at the nodes (the exterior Dirichlet data), on the GPU."""
+    import torch
+
+    x = torch.tensor(xyz, dtype=torch.float64, device="cuda")
+    f = torch.zeros(len(xyz), dtype=torch.float64, device="cuda")
+    P = torch.tensor(pos, dtype=torch.float64, device="cuda")
+    Q = torch.tensor(q, dtype=torch.float64, device="cuda")
+    for k in range(0, len(q), 64):
+        r = torch.cdist(x, P[k:k + 64])
+        f += (Q[k:k + 64] / (4.0 * math.pi * r)).sum(dim=1)
+    return f
+
+
+def gmres_study(ctx, p=16, ratios=(1.1, 2.0, 4.0, 8.0, 16.0, 32.0, 64.0), maxit=1000):
+    """GMRES iterations of the completed double-layer Dirichlet solve on the
+    four-prolate lattice (Section 5.2) for each completion, unscaled and scaled
+    by the eta table; the data are the potential of three charges inside each
+    prolate."""
+    import numpy as np
+    import torch
+
+    import paper_2506_20809_amd as sbie
+    import workloads
+
+    rows = []
+    t0 = time.perf_counter()
+    for R in ratios:
+        for Rd in (2.0, 1.0, 0.01):
+            geom = workloads.lattice2x2(R, Rd)
+            g = sbie.Geometry(ctx, geom, p)
+            xyz, _, _ = g.nodes()
+            pos, q = workloads.point_charges(geom, 3, 7, shrink=0.3)
+            f = charge_data(pos, q, xyz)
+            its, times = [], []
+            for c, scaled in ((0, False), (0, True), (1, False), (1, True)):
+                eta = None if scaled else np.ones(4)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                try:
+                    _, it, res = g.solve_completed(c, f, eta=eta, tol=1e-10, maxit=maxit)
+                    its.append(it if res <= 1e-10 else None)
+                except sbie.SbieError as e:
+                    its.append(f"error {e.status}")
+                times.append(1e3 * (time.perf_counter() - t))
+            rows.append({"R": R, "R_times_d": Rd, "iterations": its, "paper": list(PAPER_GMRES[R][Rd]),
+                         "solve_ms": [round(x, 2) for x in times]})
+            g.close()
+    return {"order": ["C_I", "eta C_I", "S", "eta S"], "p": p, "tol": 1e-10, "rows": rows,
+            "wall_s": time.perf_counter() - t0}
+
+
+def solve_large(ctx, name, precision, maxit=300):
+    """The completed Dirichlet solve with the scaled single-layer completion on a
+    suspension workload: iterations, seconds per solve and per iteration."""
+    import torch
+
+    import paper_2506_20809_amd as sbie
+    import workloads
+
+    geom = workloads.geometry(name)
+    p = workloads.CONFIGS[name]["p"]
+    g = sbie.Geometry(ctx, geom, p)
+    xyz, _, _ = g.nodes()
+    pos, q = workloads.point_charges(geom, 3, 7, shrink=0.3)
+    f = charge_data(pos, q, xyz)
+    prec = sbie.SBIE_MIXED if precision == "mixed" else sbie.SBIE_FP64
+    tol = 1e-6 if precision == "mixed" else 1e-10
+    g.solve_completed(1, f, tol=tol, maxit=2, precision=prec)  # warm
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, it, res = g.solve_completed(1, f, tol=tol, maxit=maxit, precision=prec)
+    el = time.perf_counter() - t
+    out = {"workload": f"{len(geom['A'])} spheroids, p={p}, N={g.N}, eta S completion, precision={precision}",
+           "tol": tol, "iterations": it, "relres": res, "solve_s": el, "ms_per_iteration": 1e3 * el / max(it, 1)}
+    g.close()
+    return out
+
+
 def served(ctx, n_requests, rho, precision, max_sessions, napply=20, budget=64 << 30):
     """Served mode on the request stream (Section 4 use as a Krylov inner loop):
     n_requests sessions of napply closed-loop applies each.
@@ -313,6 +407,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the other precision's measurement")
     ap.add_argument("--no-stokes", action="store_true", help="skip the Stokes single-layer measurement")
+    ap.add_argument("--no-solve", action="store_true", help="skip the completed double-layer solves")
     ap.add_argument("--served-requests", type=int, default=0,
                     help="requests in the served-mode run (0: skip; the run is opt-in)")
     ap.add_argument("--served-rho", type=float, default=0.8, help="load of the Poisson arrivals")
@@ -386,6 +481,9 @@ def main():
         res[f"{other}_path"]["roofline_frac"] = sec["roofline"]["frac"]
     if not args.no_stokes:
         res["stokes"] = {pr: run_stokes(ctx, max(4, args.steps // 2), 1, pr) for pr in ("fp64", "mixed")}
+    if not args.no_solve:
+        res["solve"] = {"gmres_study": gmres_study(ctx),
+                        **{f"{args.workload}_{pr}": solve_large(ctx, args.workload, pr) for pr in ("mixed", "fp64")}}
     if args.served_requests > 0:
         res["served"] = served(ctx, args.served_requests, args.served_rho, args.served_precision,
                                args.served_lanes)

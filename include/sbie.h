@@ -168,6 +168,41 @@ sbie_status sbie_geom_spectra(const sbie_geom* g, double* out);
    SBIE_E_STATE if there was no timed apply. */
 sbie_status sbie_geom_timing(sbie_geom* g, sbie_timing* out);
 
+/* ---------------------------------------------------------------- completed double-layer solve
+
+   The exterior Dirichlet problem of Section 5.1 in the completed double-layer
+   form, K[sigma] = sigma/2 + D[sigma] + C[sigma] = f on the surfaces
+   (Eq. (testprob)), with either completion, scaled per particle by eta_i:
+     SBIE_COMPLETE_POINT:  C[sigma](x) = sum_i eta_i |x - c_i|^-1 int_{Gamma_i} sigma dS
+                           (Eq. (completion), without a 1/(4 pi) factor, as printed);
+     SBIE_COMPLETE_SINGLE: C[sigma] = sum_i eta_i S_i[sigma_i].
+   eta: host array [M], or NULL for the values of the eta table of Section 5.2
+   (elongation eps = minor/major semi-axis; the point completion uses
+   eps/area, and 0.06 for oblates of aspect ratio above 3; the single layer
+   uses 1/2 or 1/(2 eps log(1/eps)) for prolates, 1/(4 eps) + 1/4 or 1 for
+   oblates, split at aspect ratio 3).  Densities and data are [N] doubles in
+   node order, host or (SBIE_DEVICE_PTRS) device pointers; the calls return
+   after completion. */
+typedef enum { SBIE_COMPLETE_POINT = 0, SBIE_COMPLETE_SINGLE = 1 } sbie_completion;
+
+/* The table's eta for every particle of g (host array [M]). */
+sbie_status sbie_completion_eta(const sbie_geom* g, sbie_completion c, double* eta);
+
+/* out = K[sigma]. */
+sbie_status sbie_apply_completed(sbie_geom* g, sbie_precision prec, sbie_completion c, const double* eta,
+                                 const double* sigma, double* out, void* stream, uint32_t flags);
+
+/* GMRES without restart from sigma = 0 until ||f - K sigma|| <= tol ||f|| (the
+   Arnoldi residual estimate) or maxit iterations (1..4096); the Krylov
+   basis ((maxit+1) N doubles) is allocated for the call and freed on return.
+   The geometry's completion scalings are overwritten by each completed apply
+   or solve: calls on one geometry must not overlap.  *iters and *relres
+   receive the iteration count and the final estimate.  With SBIE_MIXED the
+   attainable residual is limited by the operator's ~1e-6 accuracy. */
+sbie_status sbie_solve_completed(sbie_geom* g, sbie_precision prec, sbie_completion c, const double* eta,
+                                 const double* f, double* sigma, double tol, int32_t maxit, int32_t* iters,
+                                 double* relres, void* stream, uint32_t flags);
+
 /* ---------------------------------------------------------------- served mode
 
    Many independent operator sessions sharing one GPU, for boundary integral

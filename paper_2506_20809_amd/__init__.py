@@ -33,7 +33,9 @@ EXPORTS = [
     "sbie_apply", "sbie_geom_sync", "sbie_transform", "sbie_geom_spectra", "sbie_geom_timing",
     "sbie_session_bytes", "sbie_server_create", "sbie_server_destroy", "sbie_session_open", "sbie_session_apply",
     "sbie_session_close", "sbie_wait", "sbie_server_get_info", "sbie_status_str", "sbie_last_error",
+    "sbie_completion_eta", "sbie_apply_completed", "sbie_solve_completed",
 ]
+SBIE_COMPLETE_POINT, SBIE_COMPLETE_SINGLE = 0, 1
 SBIE_SERVER_GRAPHS = 0x100
 SBIE_MAX_PASS = 8
 
@@ -121,6 +123,11 @@ def lib() -> ctypes.CDLL:
         L.sbie_session_close.argtypes = [vp]
         L.sbie_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_int64, ctypes.POINTER(ApplyStats)]
         L.sbie_server_get_info.argtypes = [vp, ctypes.POINTER(ServerInfo)]
+        L.sbie_completion_eta.argtypes = [vp, ctypes.c_int, dp]
+        L.sbie_apply_completed.argtypes = [vp, ctypes.c_int, ctypes.c_int, dp, vp, vp, vp, ctypes.c_uint32]
+        L.sbie_solve_completed.argtypes = [vp, ctypes.c_int, ctypes.c_int, dp, vp, vp, ctypes.c_double,
+                                           ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_double), vp, ctypes.c_uint32]
         L.sbie_status_str.argtypes = [ctypes.c_int]
         L.sbie_status_str.restype = ctypes.c_char_p
         L.sbie_last_error.argtypes = []
@@ -238,6 +245,67 @@ class Geometry:
         _check(lib().sbie_apply(self._h, int(op), int(precision), nrhs, density.data_ptr(), out.data_ptr(),
                                 ctypes.c_void_p(stream.cuda_stream), flags | SBIE_DEVICE_PTRS))
         return out
+
+    def completion_eta(self, completion: int) -> np.ndarray:
+        """The eta table's scaling of each particle for the completion."""
+        out = np.zeros(self.M)
+        _check(lib().sbie_completion_eta(self._h, int(completion), _dp(out)))
+        return out
+
+    def _vectors(self, x, name):
+        import torch
+
+        if not (x.is_cuda and x.dtype == torch.float64 and x.is_contiguous() and x.numel() == self.N):
+            raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of {self.N} entries")
+        stream = torch.cuda.current_stream(x.device)
+        # the calls run on the context's stream and return after completion
+        stream.synchronize()
+
+    def apply_completed(self, completion: int, sigma, eta=None, precision: int = SBIE_FP64):
+        """K[sigma] = sigma/2 + D[sigma] + C[sigma] (numpy: host pointers; torch CUDA
+        float64: device pointers)."""
+        e = None if eta is None else np.ascontiguousarray(eta, dtype=np.float64)
+        ep = None if e is None else _dp(e)
+        if isinstance(sigma, np.ndarray):
+            d = np.ascontiguousarray(sigma, dtype=np.float64)
+            if d.size != self.N:
+                raise ValueError(f"sigma has {d.size} entries, expected {self.N}")
+            o = np.zeros_like(d)
+            _check(lib().sbie_apply_completed(self._h, int(precision), int(completion), ep, d.ctypes.data,
+                                              o.ctypes.data, None, 0))
+            return o
+        import torch
+
+        self._vectors(sigma, "sigma")
+        o = torch.empty_like(sigma)
+        _check(lib().sbie_apply_completed(self._h, int(precision), int(completion), ep, sigma.data_ptr(),
+                                          o.data_ptr(), None, SBIE_DEVICE_PTRS))
+        return o
+
+    def solve_completed(self, completion: int, f, eta=None, tol: float = 1e-10, maxit: int = 500,
+                        precision: int = SBIE_FP64):
+        """GMRES for K[sigma] = f; returns (sigma, iterations, relative residual)."""
+        e = None if eta is None else np.ascontiguousarray(eta, dtype=np.float64)
+        ep = None if e is None else _dp(e)
+        it = ctypes.c_int32(0)
+        res = ctypes.c_double(0.0)
+        if isinstance(f, np.ndarray):
+            d = np.ascontiguousarray(f, dtype=np.float64)
+            if d.size != self.N:
+                raise ValueError(f"f has {d.size} entries, expected {self.N}")
+            sig = np.zeros_like(d)
+            _check(lib().sbie_solve_completed(self._h, int(precision), int(completion), ep, d.ctypes.data,
+                                              sig.ctypes.data, float(tol), int(maxit), ctypes.byref(it),
+                                              ctypes.byref(res), None, 0))
+            return sig, it.value, res.value
+        import torch
+
+        self._vectors(f, "f")
+        sig = torch.empty_like(f)
+        _check(lib().sbie_solve_completed(self._h, int(precision), int(completion), ep, f.data_ptr(),
+                                          sig.data_ptr(), float(tol), int(maxit), ctypes.byref(it),
+                                          ctypes.byref(res), None, SBIE_DEVICE_PTRS))
+        return sig, it.value, res.value
 
     def transform(self, op: int, density: np.ndarray) -> np.ndarray:
         """Forward transform (host arrays): coefficients [nrhs][M][(p+1)^2]."""

@@ -128,6 +128,8 @@ struct sbie_geom {
   // pair-symmetric far field: reverse sums [M][H+1][RG][T] (FP64, or FP32 in
   // the first half for the mixed path), H = (M-1)/2, RG target-row groups
   double* d_rev = nullptr;
+  double* d_eta = nullptr;        // [M] completion scalings of the last completed apply / solve
+  double* d_qint = nullptr;       // [M] eta_i * integral of the density over particle i
   int nsplit = 8;
   uint64_t footprint = 0;
   // device memory: one block carved into every buffer above (owned, or lent by
@@ -216,6 +218,9 @@ sbie_status next_timing_set(sbie_geom* g, hipEvent_t** ev);
 // fork the side stream from s (after all work queued on s) and join it back
 sbie_status fork_side(sbie_geom* g, hipStream_t s);
 sbie_status join_side(sbie_geom* g, hipStream_t s);
+
+// completed double-layer operator and its GMRES solve (solve.hip)
+double completion_eta(const Particle& P, int completion);
 
 // Stokes single layer (stokes.hip); density and output [3][N]
 sbie_status apply_stokes(sbie_geom* g, int prec, const double* d_dens, double* d_out, hipStream_t s,

@@ -400,6 +400,8 @@ sbie_status carve_geometry(sbie_geom* g, Carver& c) {
   // reverse sums of the pair-symmetric far field (matrix-core path, T >= 32)
   const size_t nrev = T >= 32 ? (size_t)M * ((M - 1) / 2 + 1) * far_row_groups(g, true) * T : 1;
   SBIE_TRY(c.take(&g->d_rev, nrev));
+  SBIE_TRY(c.take(&g->d_eta, (size_t)M));
+  SBIE_TRY(c.take(&g->d_qint, (size_t)M));
   return SBIE_OK;
 }
 

@@ -68,3 +68,28 @@ def test_dirichlet_point_charges_spectral(completion):
         errs.append(np.max(np.abs(u - fx)) / np.max(np.abs(fx)))
     assert errs[0] > 10 * errs[1] > 100 * errs[2]
     assert errs[2] < 2e-6, errs
+
+
+@pytest.mark.parametrize("R,paper", [(2.0, (19, 17, 12, 14)), (4.0, (27, 26, 16, 15))])
+def test_gmres_counts_near_paper_table(R, paper):
+    """Iteration counts of the lattice study (Section 5.2, its GMRES table, column
+    R x d = 2, p = 16, tolerance 1e-10) for C_I, eta C_I, S and eta S.  The paper
+    does not state its data f; with the charges' potential as data the counts
+    agree within two iterations.  Planted on the CPU at R = 2: without the
+    completion GMRES does not converge in 300 iterations, and with the double
+    layer's sign flipped the C_I count drops to 14; the point completion with a
+    1/(4 pi) factor gives 16 against the printed 19 (18 without it, the reading
+    taken).  Signs and scalings that leave the counts close are caught by the
+    exterior point-charge pin and the eta table pin."""
+    g = workloads.lattice2x2(R, 2.0)
+    p = 16
+    xyz, _, _ = oracle.grid(g, p)
+    pos, q = workloads.point_charges(g, 3, 7, shrink=0.3)
+    f = workloads.charge_potential(pos, q, xyz)
+    got = []
+    for c, scaled in ((bie.CI, False), (bie.CI, True), (bie.CS, False), (bie.CS, True)):
+        eta = [bie.eta_table(A, C, c) if scaled else 1.0 for A, C in zip(g["A"], g["C"])]
+        _, it, res = bie.solve_dirichlet(g, p, f, c, eta, 1e-10, 200)
+        assert res <= 1e-10
+        got.append(it)
+    assert all(abs(a - b) <= 2 for a, b in zip(got, paper)), (got, paper)

@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-OP_S, OP_D = 0, 1
+OP_S, OP_D, OP_SP, OP_DP = 0, 1, 3, 4
 ERRORS = {0: "ok", -1: "invalid", -2: "degenerate", -3: "overlap", -8: "numeric"}
 
 
@@ -45,6 +45,8 @@ def lib():
         dp = ctypes.POINTER(ctypes.c_double)
         L.orc_legendre.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int] + [dp] * 8
         L.orc_spectra.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp, dp, dp]
+        L.orc_derivative_spectra.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp,
+                                             dp]
         L.orc_gauss_legendre.argtypes = [ctypes.c_int, dp, dp]
         L.orc_gauss_legendre.restype = None
         L.orc_real_harmonics.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int, dp]
@@ -177,8 +179,20 @@ def classify(geom, eta: float = 1.0) -> np.ndarray:
     return near
 
 
+def derivative_spectra(oblate: int, a: float, u0: float, p: int):
+    """(lamSp, lamDd) [(p+1)(p+2)/2]: principal-value S' (modified basis) and D'
+    on the surface (Theorem 3)."""
+    Kh = (p + 1) * (p + 2) // 2
+    sp, dd = np.zeros(Kh), np.zeros(Kh)
+    _check(lib().orc_derivative_spectra(int(oblate), float(a), float(u0), int(p), _p(sp), _p(dd)),
+           "derivative_spectra")
+    return sp, dd
+
+
 def apply(geom, p: int, op: int, density: np.ndarray, eta: float = 1.0, parts: bool = False):
-    """Algorithm 1: potential at every node.  With parts=True returns (u, u_self, u_near, u_far)."""
+    """Algorithm 1: potential at every node, op = OP_S, OP_D, OP_SP (S', normal
+    derivative of S at the target, principal value) or OP_DP (D').  With
+    parts=True returns (u, u_self, u_near, u_far)."""
     c, q, A, C = _geom_arrays(geom)
     M = len(A)
     N = M * (p + 1) * (2 * p + 2)

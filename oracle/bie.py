@@ -1,6 +1,8 @@
-"""Completed double-layer Dirichlet solve of Section 5 (Eq. (testprob) with the
+"""Boundary-value problems of Section 5.1, plainly, on top of the FP64 oracle
+apply: the completed double-layer Dirichlet solve (Eq. (testprob) with the
 completion terms of Eq. (completion), the single layer, and the scalings of
-the eta table), plainly, on top of the FP64 oracle apply.
+the eta table) and the single-layer Neumann solve (u = S+[rho], Eq. (neusol),
+with -rho/2 + S'[rho] = g on the surfaces).
 
 TEST INFRASTRUCTURE ONLY: used by the test suite and the benchmark's CPU
 reference; nothing in the product path imports it.
@@ -12,7 +14,9 @@ Readings (also listed in the design notes):
    1/(4 pi), as printed; C_S[sigma] = sum_i eta_i S_i[sigma_i];
  - eta from the table for elongation eps = 1/R, R = major/minor semi-axis;
    A(eps) is the particle's own surface area;
- - GMRES without restart from x0 = 0, stopping when ||f - K x|| / ||f|| <= tol.
+ - GMRES without restart from x0 = 0, stopping when ||f - K x|| / ||f|| <= tol;
+ - Neumann data g is the outward normal derivative of the exterior solution
+   (the paper's -E.n for the field of the charges), S' the principal value.
 """
 from __future__ import annotations
 
@@ -134,4 +138,25 @@ def evaluate(geom, p: int, sigma: np.ndarray, completion: int, eta, pts: np.ndar
             u += q / np.linalg.norm(pts - np.asarray(geom["centers"][i]), axis=1)
         else:
             u += eval_exterior(sph, p, 0, eta[i] * s_i, pts)
+    return u
+
+
+def neumann_operator(geom, p: int, rho: np.ndarray) -> np.ndarray:
+    """-rho/2 + S'[rho] at every node."""
+    return -0.5 * rho + apply(geom, p, 3, rho)
+
+
+def solve_neumann(geom, p: int, g: np.ndarray, tol: float = 1e-10, maxit: int = 500):
+    """rho with -rho/2 + S'[rho] = g; returns (rho, iterations, relative residual)."""
+    return gmres(lambda r: neumann_operator(geom, p, r), np.asarray(g, dtype=np.float64), tol, maxit)
+
+
+def evaluate_single(geom, p: int, rho: np.ndarray, pts: np.ndarray) -> np.ndarray:
+    """u = S[rho] at exterior points (each particle's exterior expansion)."""
+    M = len(geom["A"])
+    T = (p + 1) * (2 * p + 2)
+    u = np.zeros(len(pts))
+    for i in range(M):
+        sph = (geom["centers"][i], geom["quats"][i], geom["A"][i], geom["C"][i])
+        u += eval_exterior(sph, p, 0, rho[i * T:(i + 1) * T], pts)
     return u

@@ -28,6 +28,11 @@
  *  - the near-field expansion of D uses the exterior-limit coefficients;
  *  - near/far split uses the exact minimum surface distance, diam = twice the
  *    largest semi-axis, "near" iff d < eta*diam(source) (strict);
+ *  - S' and D' (Section 3.3, Theorem 3): derivative along the target's outward
+ *    normal; on the surface S' is the principal value (average of the
+ *    one-sided spectra) and D' has no jump; the self values are expansions in
+ *    the modified basis Y/sqrt(u0^2 -+ v^2); near field from the gradient of
+ *    the source's exterior expansion dotted with the target normal;
  *  - Stokes single layer (Section 4.3, Eq. (stokes)): viscosity 1, origin of
  *    the identity at each source particle's centre, self values from the
  *    exterior limit of the gradients (the jump cancels in the combination),
@@ -52,6 +57,8 @@
 
 #define OP_S 0
 #define OP_D 1
+#define OP_SP 3 /* normal derivative of the single layer at the target, S' */
+#define OP_DP 4 /* normal derivative of the double layer at the target, D' */
 
 static const double PI = 3.14159265358979323846264338327950288;
 
@@ -294,6 +301,58 @@ int orc_spectra(int oblate, double a, double u0, int p, double* lamD,
   pt.a = a;
   pt.u0 = u0;
   return spectra(&pt, p, lamD, lamDp, lamDm, lamS, NULL);
+}
+
+/* Spectra of the normal derivatives on the surface (Theorem 3, and the same
+   construction for D).  With h = sqrt(u0^2 -+ 1)/a and dz/du = 1 (prolate) or
+   i (oblate), in the modified basis Y_l / sqrt(u0^2 -+ v^2):
+     S'+ = h dz/du b~ P(z0) Q'(z0),  S'- = h dz/du b~ Q(z0) P'(z0),
+     lamSp = principal value (S'+ + S'-)/2, applied to the modified-basis
+     coefficients of sigma (as for S);
+     lamDd = h dz/du b P'(z0) Q'(z0), applied to the standard coefficients of
+     mu; the normal derivative of the exterior expansion b P'(z0) Q(z) Y and
+     of the interior one b Q'(z0) P(z) Y agree, so D' has no jump. */
+static int derivative_spectra(const particle* pt, int p, double* lamSp, double* lamDd) {
+  int N = p + 1;
+  double complex* buf = (double complex*)malloc(sizeof(double complex) * 4 * (N + 2));
+  double complex *P = buf, *Q = buf + (N + 2), *dP = buf + 2 * (N + 2),
+                 *dQ = buf + 3 * (N + 2);
+  double u0 = pt->u0, a = pt->a;
+  double su = pt->oblate ? sqrt(u0 * u0 + 1.0) : sqrt(u0 * u0 - 1.0);
+  double complex dzdu = pt->oblate ? I : 1.0 + 0.0 * I;
+  for (int m = 0; m <= p; ++m) {
+    int rc = legendre_offcut(pt->oblate, u0, m, N, P, Q, dP, dQ);
+    if (rc) { free(buf); return rc; }
+    for (int n = m; n <= p; ++n) {
+      double ratio = factorial(n - m) / factorial(n + m);
+      double sgn = (m & 1) ? -1.0 : 1.0;
+      double complex b, bt;
+      if (!pt->oblate) {
+        b = ratio * sgn * (u0 * u0 - 1.0);
+        bt = a * ratio * sgn * sqrt(u0 * u0 - 1.0);
+      } else {
+        b = ratio * (-sgn) * (u0 * u0 + 1.0);
+        bt = I * a * ratio * sgn * sqrt(u0 * u0 + 1.0);
+      }
+      double complex h = su / a * dzdu;
+      double complex spp = h * bt * P[n] * dQ[n];
+      double complex spm = h * bt * Q[n] * dP[n];
+      int idx = n * (n + 1) / 2 + m;
+      if (lamSp) lamSp[idx] = 0.5 * (creal(spp) + creal(spm));
+      if (lamDd) lamDd[idx] = creal(h * b * dP[n] * dQ[n]);
+    }
+  }
+  free(buf);
+  return ORC_OK;
+}
+
+int orc_derivative_spectra(int oblate, double a, double u0, int p, double* lamSp, double* lamDd) {
+  particle pt;
+  memset(&pt, 0, sizeof pt);
+  pt.oblate = oblate;
+  pt.a = a;
+  pt.u0 = u0;
+  return derivative_spectra(&pt, p, lamSp, lamDd);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -692,22 +751,25 @@ static int particle_coefficients(const geometry* g, int op, int i,
   int p = g->p, Nphi = 2 * p + 2, K = g->K, Kh = g->Kh;
   double* f = (double*)malloc(sizeof(double) * g->T);
   double* c = (double*)malloc(sizeof(double) * K);
-  double* lamD = (double*)malloc(sizeof(double) * 4 * Kh);
-  double *lamDp = lamD + Kh, *lamS = lamD + 2 * Kh;
+  double* lamD = (double*)malloc(sizeof(double) * 5 * Kh);
+  double *lamDp = lamD + Kh, *lamS = lamD + 2 * Kh, *lamSp = lamD + 3 * Kh, *lamDd = lamD + 4 * Kh;
   int rc = spectra(pt, p, lamD, lamDp, NULL, lamS, Qu0);
+  if (!rc && (op == OP_SP || op == OP_DP)) rc = derivative_spectra(pt, p, lamSp, lamDd);
   if (rc) { free(f); free(c); free(lamD); return rc; }
+  /* S and S' take the modified-basis coefficients of sigma (Section 3.2) */
+  int modified = (op == OP_S || op == OP_SP);
   double sgn = pt->oblate ? 1.0 : -1.0;
   for (int j = 0; j <= p; ++j)
     for (int k = 0; k < Nphi; ++k) {
-      double w = (op == OP_S) ? sqrt(pt->u0 * pt->u0 + sgn * g->gx[j] * g->gx[j]) : 1.0;
+      double w = modified ? sqrt(pt->u0 * pt->u0 + sgn * g->gx[j] * g->gx[j]) : 1.0;
       f[j * Nphi + k] = w * dens[(size_t)i * g->T + j * Nphi + k];
     }
   forward_transform(p, g->gx, g->gw, f, c);
   for (int n = 0; n <= p; ++n)
     for (int m = -n; m <= n; ++m) {
       int l = n * n + n + m, h = n * (n + 1) / 2 + abs(m);
-      double lself = (op == OP_S) ? lamS[h] : lamD[h];
-      double lext = (op == OP_S) ? lamS[h] : lamDp[h];
+      double lself = op == OP_S ? lamS[h] : op == OP_D ? lamD[h] : op == OP_SP ? lamSp[h] : lamDd[h];
+      double lext = modified ? lamS[h] : lamDp[h];
       coef_self[l] = lself * c[l];
       E[l] = lext * c[l];
     }
@@ -715,11 +777,69 @@ static int particle_coefficients(const geometry* g, int op, int i,
   return ORC_OK;
 }
 
+static int expansion_grad(const particle* pt, int p, int nset, const double* E, double u,
+                          double v, double phi, int interior, double* val, double* grad);
+
+static int valid_op(int op) { return op == OP_S || op == OP_D || op == OP_SP || op == OP_DP; }
+
+/* S' and D' self values are expansions in the modified basis: the inverse
+   transform's value at GL node j is divided by sqrt(u0^2 -+ v_j^2). */
+static double self_node_factor(const geometry* g, int op, int i, int j) {
+  if (op != OP_SP && op != OP_DP) return 1.0;
+  const particle* pt = &g->pt[i];
+  double sgn = pt->oblate ? 1.0 : -1.0;
+  return 1.0 / sqrt(pt->u0 * pt->u0 + sgn * g->gx[j] * g->gx[j]);
+}
+
+/* Near-field value of source particle i at target node gt: the exterior
+   expansion (S, D), or its gradient along the target's normal (S', D'). */
+static int near_term(const geometry* g, int op, int i, const double* E, const double complex* Qu0,
+                     size_t gt, double* out) {
+  if (op == OP_S || op == OP_D) return eval_exterior(&g->pt[i], g->p, E, Qu0, g->xyz + 3 * gt, out);
+  const particle* pt = &g->pt[i];
+  double xb[3], u, v, phi, val, grad[3];
+  lab_to_body(pt, g->xyz + 3 * gt, xb);
+  body_to_spheroidal(pt, xb, &u, &v, &phi);
+  if (!(u > pt->u0)) return ORC_E_OVERLAP;
+  int rc = expansion_grad(pt, g->p, 1, E, u, v, phi, 0, &val, grad);
+  if (rc) return rc;
+  const double* nu = g->nrm + 3 * gt;
+  *out = grad[0] * nu[0] + grad[1] * nu[1] + grad[2] * nu[2];
+  return ORC_OK;
+}
+
+/* Smooth-quadrature term of source node gs at target node gt, d = x - y:
+   S  W s / (4 pi r);  D  W m nu_y.d / (4 pi r^3);
+   S' -W s nu_x.d / (4 pi r^3);
+   D' W m (nu_x.nu_y / r^3 - 3 (nu_y.d)(nu_x.d) / r^5) / (4 pi). */
+static double far_term(const geometry* g, int op, const double* density, size_t gt, size_t gs) {
+  const double *x = g->xyz + 3 * gt, *y = g->xyz + 3 * gs;
+  double d0 = x[0] - y[0], d1 = x[1] - y[1], d2 = x[2] - y[2];
+  double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+  double r = sqrt(r2);
+  double q = g->W[gs] * density[gs];
+  const double *nx = g->nrm + 3 * gt, *ny = g->nrm + 3 * gs;
+  switch (op) {
+    case OP_S:
+      return q / (4.0 * PI * r);
+    case OP_D:
+      return q * (ny[0] * d0 + ny[1] * d1 + ny[2] * d2) / (4.0 * PI * r2 * r);
+    case OP_SP:
+      return -q * (nx[0] * d0 + nx[1] * d1 + nx[2] * d2) / (4.0 * PI * r2 * r);
+    default: {
+      double nn = nx[0] * ny[0] + nx[1] * ny[1] + nx[2] * ny[2];
+      double nyd = ny[0] * d0 + ny[1] * d1 + ny[2] * d2;
+      double nxd = nx[0] * d0 + nx[1] * d1 + nx[2] * d2;
+      return q * (nn / (r2 * r) - 3.0 * nyd * nxd / (r2 * r2 * r)) / (4.0 * PI);
+    }
+  }
+}
+
 int orc_apply(const double* centres, const double* quats, const double* A,
               const double* C, int M, int p, double eta, int op,
               const double* density, double* u_self, double* u_near,
               double* u_far, double* u) {
-  if (op != OP_S && op != OP_D) return ORC_E_INVALID;
+  if (!valid_op(op)) return ORC_E_INVALID;
   geometry g;
   int rc = build_geometry(centres, quats, A, C, M, p, eta, &g);
   if (rc) return rc;
@@ -744,6 +864,7 @@ int orc_apply(const double* centres, const double* quats, const double* A,
       continue;
     }
     inverse_transform(p, g.gx, cself + (size_t)i * K, us + (size_t)i * T);
+    for (int t = 0; t < T; ++t) us[(size_t)i * T + t] *= self_node_factor(&g, op, i, t / (2 * p + 2));
   }
   if (err) rc = err;
 
@@ -756,8 +877,7 @@ int orc_apply(const double* centres, const double* quats, const double* A,
         for (int t = 0; t < T; ++t) {
           size_t gt = (size_t)j * T + t;
           double val;
-          int r = eval_exterior(&g.pt[i], p, E + (size_t)i * K, Qu0 + (size_t)i * Kh,
-                                g.xyz + 3 * gt, &val);
+          int r = near_term(&g, op, i, E + (size_t)i * K, Qu0 + (size_t)i * Kh, gt, &val);
           if (r) {
 #pragma omp atomic write
             err = r;
@@ -776,24 +896,11 @@ int orc_apply(const double* centres, const double* quats, const double* A,
     for (int j = 0; j < M; ++j) {
       for (int t = 0; t < T; ++t) {
         size_t gt = (size_t)j * T + t;
-        const double* x = g.xyz + 3 * gt;
         double sum = 0.0, comp = 0.0;
         for (int i = 0; i < M; ++i) {
           if (i == j || g.near[(size_t)i * M + j]) continue;
           for (int q = 0; q < T; ++q) {
-            size_t gs = (size_t)i * T + q;
-            const double* y = g.xyz + 3 * gs;
-            double d0 = x[0] - y[0], d1 = x[1] - y[1], d2 = x[2] - y[2];
-            double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-            double r = sqrt(r2);
-            double term;
-            if (op == OP_S) {
-              term = g.W[gs] * density[gs] / (4.0 * PI * r);
-            } else {
-              const double* nu = g.nrm + 3 * gs;
-              double ndr = nu[0] * d0 + nu[1] * d1 + nu[2] * d2;
-              term = g.W[gs] * density[gs] * ndr / (4.0 * PI * r2 * r);
-            }
+            double term = far_term(&g, op, density, gt, (size_t)i * T + q);
             double tsum = sum + term;
             if (fabs(sum) >= fabs(term)) comp += (sum - tsum) + term;
             else comp += (term - tsum) + sum;
@@ -826,7 +933,7 @@ int orc_apply_at(const double* centres, const double* quats, const double* A,
                  const double* C, int M, int p, double eta, int op,
                  const double* density, const int64_t* targets, int ntg,
                  double* out_self, double* out_near, double* out_far, double* out) {
-  if (op != OP_S && op != OP_D) return ORC_E_INVALID;
+  if (!valid_op(op)) return ORC_E_INVALID;
   geometry g;
   int rc = build_geometry(centres, quats, A, C, M, p, eta, &g);
   if (rc) return rc;
@@ -866,13 +973,14 @@ int orc_apply_at(const double* centres, const double* quats, const double* A,
     real_harmonics(g.gx[jv], 2.0 * PI * kp / Nphi, p, Yl);
     double us = 0.0;
     for (int l = 0; l < K; ++l) us += cself[(size_t)j * K + l] * Yl[l];
+    us *= self_node_factor(&g, op, j, jv);
     free(Yl);
     /* near */
     double un = 0.0;
     for (int i = 0; i < M; ++i) {
       if (!g.near[(size_t)i * M + j]) continue;
       double val;
-      int r = eval_exterior(&g.pt[i], p, E + (size_t)i * K, Qu0 + (size_t)i * Kh, g.xyz + 3 * gt, &val);
+      int r = near_term(&g, op, i, E + (size_t)i * K, Qu0 + (size_t)i * Kh, (size_t)gt, &val);
       if (r) {
 #pragma omp atomic write
         err = r;
@@ -880,23 +988,11 @@ int orc_apply_at(const double* centres, const double* quats, const double* A,
       un += val;
     }
     /* far, Neumaier-compensated */
-    const double* x = g.xyz + 3 * gt;
     double sum = 0.0, comp = 0.0;
     for (int i = 0; i < M; ++i) {
       if (i == j || g.near[(size_t)i * M + j]) continue;
       for (int q = 0; q < T; ++q) {
-        size_t gs = (size_t)i * T + q;
-        const double* y = g.xyz + 3 * gs;
-        double d0 = x[0] - y[0], d1 = x[1] - y[1], d2 = x[2] - y[2];
-        double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-        double r = sqrt(r2);
-        double term;
-        if (op == OP_S) {
-          term = g.W[gs] * density[gs] / (4.0 * PI * r);
-        } else {
-          const double* nu = g.nrm + 3 * gs;
-          term = g.W[gs] * density[gs] * (nu[0] * d0 + nu[1] * d1 + nu[2] * d2) / (4.0 * PI * r2 * r);
-        }
+        double term = far_term(&g, op, density, (size_t)gt, (size_t)i * T + q);
         double ts = sum + term;
         if (fabs(sum) >= fabs(term)) comp += (sum - ts) + term;
         else comp += (term - ts) + sum;

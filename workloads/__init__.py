@@ -355,6 +355,33 @@ def charge_potential(pos, q, x):
     return out
 
 
+def charge_flux(pos, q, x, nrm):
+    """Normal derivative of the charges' potential at points x along nrm [n, 3]."""
+    out = np.zeros(len(x))
+    for pj, qj in zip(pos, q):
+        d = x - pj
+        r = np.linalg.norm(d, axis=1)
+        out -= qj * np.sum(d * nrm, axis=1) / (4.0 * math.pi * r ** 3)
+    return out
+
+
+def three_spheroids(oblate_first_and_last: bool, seed: int = 0):
+    """The three-particle systems of the boundary-value tests (Section 5.1):
+    centres (0,0,0), (5,0,0), (3.2,3.2,3.2) with u0 = 1.1, 1.2, 1.3 and focal
+    half-distance a = 1, random orientations.  All prolates (the Dirichlet
+    system), or oblates at the first and last centres and a prolate in the
+    middle (the Neumann system)."""
+    rng = np.random.default_rng(seed)
+    centers = np.array([[0.0, 0.0, 0.0], [5.0, 0.0, 0.0], [3.2, 3.2, 3.2]])
+    A, C = [], []
+    for k, u0 in enumerate((1.1, 1.2, 1.3)):
+        oblate = oblate_first_and_last and k != 1
+        A.append(math.sqrt(u0 * u0 + 1.0) if oblate else math.sqrt(u0 * u0 - 1.0))
+        C.append(u0)
+    quats = np.array([random_quat(rng) for _ in range(3)])
+    return {"centers": centers, "quats": quats, "A": np.array(A), "C": np.array(C)}
+
+
 def served_request(req):
     """Geometry of one served request: the M particles of the 1024-particle pool
     packing (volume fraction 0.15, gap 0.05) whose centres lie nearest to a

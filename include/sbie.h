@@ -61,7 +61,11 @@ typedef enum {
 typedef enum {
   SBIE_OP_S = 0,       /* Laplace single layer, Eq. (SLP), Theorem 2 */
   SBIE_OP_D = 1,       /* Laplace double layer, Eq. (DLP), Theorem 1 */
-  SBIE_OP_STOKES_S = 2 /* Stokes single layer through Laplace potentials, Eq. (stokes); nrhs = 3 */
+  SBIE_OP_STOKES_S = 2, /* Stokes single layer through Laplace potentials, Eq. (stokes); nrhs = 3 */
+  SBIE_OP_SP = 3,       /* S': derivative of the single layer along the target's outward normal,
+                           principal value on the surface (Section 3.3, Theorem 3) */
+  SBIE_OP_DP = 4        /* D': derivative of the double layer along the target's outward normal
+                           (continuous across the surface; Section 3.3) */
 } sbie_op;
 
 typedef enum {
@@ -131,8 +135,12 @@ sbie_status sbie_geom_nodes(const sbie_geom* g, double* xyz, double* nrm, double
 sbie_status sbie_geom_near_pairs(const sbie_geom* g, int32_t* src, int32_t* dst,
                                  int64_t cap, int64_t* count);
 
-/* Apply S or D (or the Stokes single layer) to nrhs densities:
-   potential[r][g] = sum over particles of K[density[r]] at node g.
+/* Apply S, D, S', D' (or the Stokes single layer) to nrhs densities:
+   potential[r][g] = sum over particles of K[density[r]] at node g.  For S'
+   and D' the target normal is the outward normal at node g; the near field
+   uses the gradient of each neighbour's exterior expansion (Eq.
+   (dSLevalformula) and its analogue for D), the far field the differentiated
+   kernels.
    stream: a hipStream_t, or NULL for the context stream with the call
    returning after completion.  With a non-NULL stream and SBIE_DEVICE_PTRS the
    call is asynchronous on that stream.  flags: SBIE_DEVICE_PTRS, SBIE_TIMING,
@@ -202,6 +210,13 @@ sbie_status sbie_apply_completed(sbie_geom* g, sbie_precision prec, sbie_complet
 sbie_status sbie_solve_completed(sbie_geom* g, sbie_precision prec, sbie_completion c, const double* eta,
                                  const double* f, double* sigma, double tol, int32_t maxit, int32_t* iters,
                                  double* relres, void* stream, uint32_t flags);
+
+/* The exterior Neumann problem of Section 5.1 with the single-layer
+   representation u = S+[rho] (Eq. (neusol)): GMRES, as sbie_solve_completed,
+   for -rho/2 + S'[rho] = data, S' the principal value (Theorem 3) and data the
+   outward normal derivative of u on the surfaces. */
+sbie_status sbie_solve_neumann(sbie_geom* g, sbie_precision prec, const double* data, double* rho, double tol,
+                               int32_t maxit, int32_t* iters, double* relres, void* stream, uint32_t flags);
 
 /* ---------------------------------------------------------------- served mode
 

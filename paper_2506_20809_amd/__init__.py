@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsbie.so")
 
-SBIE_OP_S, SBIE_OP_D, SBIE_OP_STOKES_S = 0, 1, 2
+SBIE_OP_S, SBIE_OP_D, SBIE_OP_STOKES_S, SBIE_OP_SP, SBIE_OP_DP = 0, 1, 2, 3, 4
 SBIE_FP64, SBIE_MIXED = 0, 1
 SBIE_DEVICE_PTRS = 0x1
 SBIE_TIMING = 0x2
@@ -33,7 +33,7 @@ EXPORTS = [
     "sbie_apply", "sbie_geom_sync", "sbie_transform", "sbie_geom_spectra", "sbie_geom_timing",
     "sbie_session_bytes", "sbie_server_create", "sbie_server_destroy", "sbie_session_open", "sbie_session_apply",
     "sbie_session_close", "sbie_wait", "sbie_server_get_info", "sbie_status_str", "sbie_last_error",
-    "sbie_completion_eta", "sbie_apply_completed", "sbie_solve_completed",
+    "sbie_completion_eta", "sbie_apply_completed", "sbie_solve_completed", "sbie_solve_neumann",
 ]
 SBIE_COMPLETE_POINT, SBIE_COMPLETE_SINGLE = 0, 1
 SBIE_SERVER_GRAPHS = 0x100
@@ -128,6 +128,9 @@ def lib() -> ctypes.CDLL:
         L.sbie_solve_completed.argtypes = [vp, ctypes.c_int, ctypes.c_int, dp, vp, vp, ctypes.c_double,
                                            ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                            ctypes.POINTER(ctypes.c_double), vp, ctypes.c_uint32]
+        L.sbie_solve_neumann.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_double, ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double), vp,
+                                         ctypes.c_uint32]
         L.sbie_status_str.argtypes = [ctypes.c_int]
         L.sbie_status_str.restype = ctypes.c_char_p
         L.sbie_last_error.argtypes = []
@@ -306,6 +309,27 @@ class Geometry:
                                           sig.data_ptr(), float(tol), int(maxit), ctypes.byref(it),
                                           ctypes.byref(res), None, SBIE_DEVICE_PTRS))
         return sig, it.value, res.value
+
+    def solve_neumann(self, data, tol: float = 1e-10, maxit: int = 500, precision: int = SBIE_FP64):
+        """GMRES for -rho/2 + S'[rho] = data (single-layer Neumann problem);
+        returns (rho, iterations, relative residual)."""
+        it = ctypes.c_int32(0)
+        res = ctypes.c_double(0.0)
+        if isinstance(data, np.ndarray):
+            d = np.ascontiguousarray(data, dtype=np.float64)
+            if d.size != self.N:
+                raise ValueError(f"data has {d.size} entries, expected {self.N}")
+            rho = np.zeros_like(d)
+            _check(lib().sbie_solve_neumann(self._h, int(precision), d.ctypes.data, rho.ctypes.data, float(tol),
+                                            int(maxit), ctypes.byref(it), ctypes.byref(res), None, 0))
+            return rho, it.value, res.value
+        import torch
+
+        self._vectors(data, "data")
+        rho = torch.empty_like(data)
+        _check(lib().sbie_solve_neumann(self._h, int(precision), data.data_ptr(), rho.data_ptr(), float(tol),
+                                        int(maxit), ctypes.byref(it), ctypes.byref(res), None, SBIE_DEVICE_PTRS))
+        return rho, it.value, res.value
 
     def transform(self, op: int, density: np.ndarray) -> np.ndarray:
         """Forward transform (host arrays): coefficients [nrhs][M][(p+1)^2]."""

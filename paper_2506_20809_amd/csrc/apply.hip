@@ -461,6 +461,7 @@ sbie_status join_side(sbie_geom* g, hipStream_t s) {
 
 sbie_status apply_laplace(sbie_geom* g, int op, int prec, const double* d_dens, double* d_out, hipStream_t s,
                           uint32_t parts, bool timed) {
+  if (op == SBIE_OP_SP || op == SBIE_OP_DP) return apply_normal(g, op, prec, d_dens, d_out, s, parts, timed);
   const int M = g->M, p = g->p, T = g->T, K = g->K;
   const int64_t N = g->N;
   const int B = 256;

@@ -258,7 +258,8 @@ sbie_status sbie_geom_near_pairs(const sbie_geom* g, int32_t* src, int32_t* dst,
 sbie_status sbie_apply(sbie_geom* g, sbie_op op, sbie_precision prec, int32_t nrhs, const double* density,
                        double* potential, void* stream, uint32_t flags) {
   if (!g) return invalid("geometry is NULL");
-  if (op != SBIE_OP_S && op != SBIE_OP_D && op != SBIE_OP_STOKES_S) return invalid("unknown operator");
+  if (op != SBIE_OP_S && op != SBIE_OP_D && op != SBIE_OP_STOKES_S && op != SBIE_OP_SP && op != SBIE_OP_DP)
+    return invalid("unknown operator");
   if (prec != SBIE_FP64 && prec != SBIE_MIXED) return invalid("unknown precision");
   if (nrhs < 1 || nrhs > 16) return invalid("nrhs must be in [1, 16]");
   if (op == SBIE_OP_STOKES_S && nrhs != 3) return invalid("the Stokes single layer takes nrhs = 3");

@@ -7,6 +7,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "sbie_internal.h"
+
 namespace sbie {
 
 // Depth L of the backward recurrence: the ratio of the minimal to the
@@ -113,6 +115,173 @@ __device__ inline void q_column(double u, double sgn, int N, int m, double qN, d
       Q[n] = 0.0;
     }
   }
+}
+
+// A lab point in the spheroidal coordinates (u, v, phi) of source particle P
+// (Table 1), from the sum of its distances to the focal points (prolate) or
+// to the focal ring (oblate), 2 a cosh(mu): u = cosh(mu) resp. sinh(mu).
+struct SpheroidalPoint {
+  double u, w, sw;  // w = u^2 -+ 1, sw = sqrt(w)
+  double v, sv;     // v and sqrt(1 - v^2)
+  double c1, s1;    // cos(phi), sin(phi)
+  double d[3];      // lab offset from the centre
+};
+
+// With axis_guard a point on the symmetry axis is moved off it by 1e-12 a (the
+// v and phi directions of a gradient are singular there).  A point inside
+// the spheroid sets kStatExterior in *bad.
+__device__ inline SpheroidalPoint to_spheroidal(const Particle& P, double X0, double X1, double X2,
+                                                bool axis_guard, unsigned* bad) {
+  SpheroidalPoint q;
+  q.d[0] = X0 - P.c[0];
+  q.d[1] = X1 - P.c[1];
+  q.d[2] = X2 - P.c[2];
+  const double b0 = P.R[0] * q.d[0] + P.R[3] * q.d[1] + P.R[6] * q.d[2];
+  const double b1 = P.R[1] * q.d[0] + P.R[4] * q.d[1] + P.R[7] * q.d[2];
+  const double b2 = P.R[2] * q.d[0] + P.R[5] * q.d[1] + P.R[8] * q.d[2];
+  const double a = P.a;
+  const double rho0 = sqrt(b0 * b0 + b1 * b1);
+  const double rho = axis_guard ? fmax(rho0, 1e-12 * a) : rho0;
+  if (!P.oblate) {
+    const double f1 = sqrt(rho * rho + (b2 - a) * (b2 - a));
+    const double f2 = sqrt(rho * rho + (b2 + a) * (b2 + a));
+    const double ch = (f1 + f2) / (2.0 * a);
+    q.u = ch;
+    q.w = (ch - 1.0) * (ch + 1.0);
+  } else {
+    const double f1 = sqrt((rho + a) * (rho + a) + b2 * b2);
+    const double f2 = sqrt((rho - a) * (rho - a) + b2 * b2);
+    const double ch = (f1 + f2) / (2.0 * a);
+    q.u = sqrt((ch - 1.0) * (ch + 1.0));
+    q.w = ch * ch;
+  }
+  if (!(q.u > P.u0)) *bad |= kStatExterior;
+  q.sw = sqrt(q.w);
+  q.v = b2 / (a * q.u);
+  q.sv = rho / (a * q.sw);
+  q.c1 = rho0 > 0.0 ? b0 / rho0 : 1.0;
+  q.s1 = rho0 > 0.0 ? b1 / rho0 : 0.0;
+  return q;
+}
+
+// NSET exterior expansions sum_l E_s[l] Q_n^|m|(u)/Q_n^|m|(u0) Y_l(v, phi) of one
+// source particle at a mapped point, with their u, v and phi derivatives.
+// Es: coefficients of set s at E + s * stride; L: the particle's spectra rows
+// (column 3 holds 1/Q_n^m(u0)); ab, cd: normalised Ferrers recurrence and
+// derivative coefficients through degree p+1.  Q and Q' come from the
+// division-free backward recurrence (orders 0 and 1, then the order step).
+template <int PMAX, int NSET>
+__device__ inline void expansion_derivatives(const SpheroidalPoint& q, bool oblate, const double* __restrict__ E,
+                                             size_t stride, const double* __restrict__ L,
+                                             const double* __restrict__ ab, const double* __restrict__ cd,
+                                             const double* __restrict__ rcp, int p, unsigned* bad,
+                                             double (&Phi)[NSET], double (&Pu)[NSET], double (&Pv)[NSET],
+                                             double (&Pp)[NSET]) {
+  const int N1 = p + 1;
+  const double u = q.u, v = q.v;
+  const double inv_omv2 = 1.0 / (q.sv * q.sv);
+  const double inv_w = 1.0 / q.w;
+  const double sgn = oblate ? 1.0 : -1.0;
+  const int Ld = near_depth(u, q.sw, N1, kStatNumeric, bad);
+#pragma unroll
+  for (int s = 0; s < NSET; ++s) Phi[s] = Pu[s] = Pv[s] = Pp[s] = 0.0;
+  double qn0[2], qn1[2];
+  q_top_orders01(u, q.sw, sgn, N1, Ld, rcp, qn0, qn1);
+  const double ur = u / q.sw;
+  double fa2 = 0.0, fa1 = 0.0, fb2 = 0.0, fb1 = 0.0;
+  double pbar = 0.28209479177387814347, cm = 1.0, sm = 0.0;
+  for (int m = 0; m <= p; ++m) {
+    if (m > 0) {
+      pbar *= sqrt((2.0 * m + 1.0) / (2.0 * m)) * q.sv;
+      const double cn = cm * q.c1 - sm * q.s1;
+      sm = sm * q.c1 + cm * q.s1;
+      cm = cn;
+    }
+    const double qN = m == 0 ? qn0[0] : (m == 1 ? qn0[1] : q_next_order(ur, N1, m, fa1, fa2));
+    const double qN1 = m == 0 ? qn1[0] : (m == 1 ? qn1[1] : q_next_order(ur, N1 + 1, m, fb1, fb2));
+    fa2 = fa1;
+    fa1 = qN;
+    fb2 = fb1;
+    fb1 = qN1;
+    double Q[PMAX + 4];
+    q_column<PMAX>(u, sgn, N1, m, qN, qN1, rcp, Q);
+    // normalised Ferrers functions of v through degree p+1
+    double Pb[PMAX + 3];
+    {
+      double p2 = 0.0, p1 = pbar;
+#pragma unroll
+      for (int n = 0; n <= PMAX + 1; ++n) {
+        double pn = 0.0;
+        if (n == m) {
+          pn = pbar;
+        } else if (n == m + 1) {
+          pn = sqrt(2.0 * m + 3.0) * v * pbar;
+          p2 = p1;
+          p1 = pn;
+        } else if (n > m + 1 && n <= p + 1) {
+          const int h = n * (n + 1) / 2 + m;
+          pn = ab[2 * h] * (v * p1 - ab[2 * h + 1] * p2);
+          p2 = p1;
+          p1 = pn;
+        }
+        Pb[n] = pn;
+      }
+    }
+    double vc[NSET], vs[NSET], uc[NSET], us[NSET], wc[NSET], ws[NSET];
+#pragma unroll
+    for (int s = 0; s < NSET; ++s) vc[s] = vs[s] = uc[s] = us[s] = wc[s] = ws[s] = 0.0;
+#pragma unroll
+    for (int n = 0; n <= PMAX; ++n) {
+      if (n >= m && n <= p) {
+        const int h = n * (n + 1) / 2 + m;
+        const double sc = L[h * 4 + 3];
+        const double qr = Q[n] * sc;
+        const double dq = ((-sgn) * (double)(n - m + 1) * Q[n + 1] - (double)(n + 1) * u * Q[n]) * inv_w * sc;
+        const double pn = Pb[n];
+        const double dpn = ((double)(n + 1) * v * pn - cd[h] * Pb[n + 1]) * inv_omv2;
+        const double t0 = pn * qr, t1 = pn * dq, t2 = dpn * qr;
+#pragma unroll
+        for (int s = 0; s < NSET; ++s) {
+          const double ec = E[(size_t)s * stride + n * n + n + m];
+          vc[s] = fma(ec, t0, vc[s]);
+          uc[s] = fma(ec, t1, uc[s]);
+          wc[s] = fma(ec, t2, wc[s]);
+          if (m > 0) {
+            const double es = E[(size_t)s * stride + n * n + n - m];
+            vs[s] = fma(es, t0, vs[s]);
+            us[s] = fma(es, t1, us[s]);
+            ws[s] = fma(es, t2, ws[s]);
+          }
+        }
+      }
+    }
+    const double f = m == 0 ? 1.0 : 1.41421356237309504880;
+#pragma unroll
+    for (int s = 0; s < NSET; ++s) {
+      Phi[s] += f * (vc[s] * cm + vs[s] * sm);
+      Pu[s] += f * (uc[s] * cm + us[s] * sm);
+      Pv[s] += f * (wc[s] * cm + ws[s] * sm);
+      Pp[s] += f * (double)m * (vs[s] * cm - vc[s] * sm);
+    }
+  }
+}
+
+// Lab-frame gradient from the derivatives in (u, v, phi): the chain rule for
+// the orthogonal coordinates of Table 1 in the body frame, rotated to the lab.
+__device__ inline void lab_gradient(const Particle& P, double u, double su, double v, double sv, double c1,
+                                    double s1, double Pu, double Pv, double Pp, double g[3]) {
+  const double a = P.a;
+  const double xu[3] = {a * u / su * sv * c1, a * u / su * sv * s1, a * v};
+  const double xv[3] = {-a * su * v / sv * c1, -a * su * v / sv * s1, a * u};
+  const double xp[3] = {-a * su * sv * s1, a * su * sv * c1, 0.0};
+  const double hu2 = xu[0] * xu[0] + xu[1] * xu[1] + xu[2] * xu[2];
+  const double hv2 = xv[0] * xv[0] + xv[1] * xv[1] + xv[2] * xv[2];
+  const double hp2 = xp[0] * xp[0] + xp[1] * xp[1] + xp[2] * xp[2];
+  const double fu = Pu / hu2, fv = Pv / hv2, fp = Pp / hp2;
+  const double gb[3] = {xu[0] * fu + xv[0] * fv + xp[0] * fp, xu[1] * fu + xv[1] * fv + xp[1] * fp,
+                        xu[2] * fu + xv[2] * fv};
+#pragma unroll
+  for (int r = 0; r < 3; ++r) g[r] = P.R[3 * r] * gb[0] + P.R[3 * r + 1] * gb[1] + P.R[3 * r + 2] * gb[2];
 }
 
 }  // namespace sbie

@@ -219,6 +219,10 @@ sbie_status next_timing_set(sbie_geom* g, hipEvent_t** ev);
 sbie_status fork_side(sbie_geom* g, hipStream_t s);
 sbie_status join_side(sbie_geom* g, hipStream_t s);
 
+// S' and D' (deriv.hip); apply_laplace dispatches these ops to it
+sbie_status apply_normal(sbie_geom* g, int op, int prec, const double* d_dens, double* d_out, hipStream_t s,
+                         uint32_t parts, bool timed);
+
 // completed double-layer operator and its GMRES solve (solve.hip)
 double completion_eta(const Particle& P, int completion);
 

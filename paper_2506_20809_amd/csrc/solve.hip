@@ -1,8 +1,10 @@
-// Completed double-layer Dirichlet operator and its GMRES solve (Section 5.1:
-// sigma/2 + D[sigma] + C[sigma] = f, Eq. (testprob), with the point completion
-// of Eq. (completion) or the single-layer completion, scaled per particle by
-// the eta table of Section 5.2).  Every vector operation runs in the kernels
-// below on the caller's stream; the host keeps only the small Hessenberg
+// Boundary integral equations of Section 5.1 solved with GMRES: the completed
+// double-layer Dirichlet problem (sigma/2 + D[sigma] + C[sigma] = f, Eq.
+// (testprob), with the point completion of Eq. (completion) or the
+// single-layer completion, scaled per particle by the eta table of Section
+// 5.2) and the single-layer Neumann problem (-rho/2 + S'[rho] = g for
+// u = S+[rho], Eq. (neusol)).  Every vector operation runs in the kernels below
+// on the caller's stream; the host keeps only the small Hessenberg
 // least-squares problem of GMRES.
 #include <hip/hip_runtime.h>
 
@@ -106,6 +108,12 @@ __global__ void k_sub_combination(const double* __restrict__ V, const double* __
   w[g] = s;
 }
 
+// out = a * v + out
+__global__ void k_axpy(const double* __restrict__ v, double a, int64_t N, double* __restrict__ out) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < N) out[g] = fma(a, v[g], out[g]);
+}
+
 // out = a * v
 __global__ void k_scale(const double* __restrict__ v, double a, int64_t N, double* __restrict__ out) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -201,17 +209,18 @@ sbie_status apply_completed(sbie_geom* g, int prec, int completion, const double
   return SBIE_OK;
 }
 
-sbie_status solve_completed(sbie_geom* g, int prec, int completion, const double* d_eta, const double* d_f,
-                            double* d_sigma, double tol, int maxit, int* iters, double* relres, hipStream_t s) {
-  const int64_t N = g->N;
+// GMRES without restart from x = 0 for A x = f, A given by matvec(in, out);
+// classical Gram-Schmidt applied twice, in the kernels above.
+template <typename Matvec>
+sbie_status gmres(int64_t N, Matvec&& matvec, const double* d_f, double* d_x, double tol, int maxit, int* iters,
+                  double* relres, hipStream_t s) {
   const int nblk = (int)std::min<int64_t>(1024, (N + kBlock - 1) / kBlock);
-  DevBuf V, w, part, dh, tmp;
+  DevBuf V, w, part, dh;
   sbie_status st;
   if ((st = dev_alloc(V, (size_t)(maxit + 1) * N)) != SBIE_OK) return st;
   if ((st = dev_alloc(w, N)) != SBIE_OK) return st;
   if ((st = dev_alloc(part, (size_t)(maxit + 1) * nblk)) != SBIE_OK) return st;
   if ((st = dev_alloc(dh, maxit + 1)) != SBIE_OK) return st;
-  if ((st = dev_alloc(tmp, 3 * (size_t)N)) != SBIE_OK) return st;
   std::vector<double> H((size_t)(maxit + 1) * maxit, 0.0), cs(maxit), sn(maxit), gv(maxit + 1, 0.0);
   std::vector<double> h1(maxit + 1), h2(maxit + 1);
   auto Hc = [&](int r, int c) -> double& { return H[(size_t)r * maxit + c]; };
@@ -222,7 +231,7 @@ sbie_status solve_completed(sbie_geom* g, int prec, int completion, const double
   *iters = 0;
   *relres = 0.0;
   if (beta == 0.0) {
-    hipLaunchKernelGGL(k_scale, dim3(cdiv(N, kBlock)), dim3(kBlock), 0, s, d_f, 0.0, N, d_sigma);
+    hipLaunchKernelGGL(k_scale, dim3(cdiv(N, kBlock)), dim3(kBlock), 0, s, d_f, 0.0, N, d_x);
     SBIE_HIP(hipGetLastError());
     SBIE_HIP(hipStreamSynchronize(s));
     return SBIE_OK;
@@ -233,8 +242,8 @@ sbie_status solve_completed(sbie_geom* g, int prec, int completion, const double
   int k = 0;
   double res = 1.0;
   while (k < maxit) {
-    // w = K V[k]
-    if ((st = apply_completed(g, prec, completion, d_eta, V.p + (size_t)k * N, w.p, tmp.p, s)) != SBIE_OK) return st;
+    // w = A V[k]
+    if ((st = matvec(V.p + (size_t)k * N, w.p)) != SBIE_OK) return st;
     // classical Gram-Schmidt, twice
     if ((st = dots(V.p, w.p, k + 1, N, part.p, nblk, dh.p, h1.data(), s)) != SBIE_OK) return st;
     hipLaunchKernelGGL(k_sub_combination, dim3(cdiv(N, kBlock)), dim3(kBlock), 0, s, V.p, dh.p, k + 1, N, w.p);
@@ -269,7 +278,7 @@ sbie_status solve_completed(sbie_geom* g, int prec, int completion, const double
     res = std::fabs(gv[k]) / beta;
     if (res <= tol || hn == 0.0) break;
   }
-  // y from the triangular system, sigma = V y
+  // y from the triangular system, x = V y
   std::vector<double> yv(k);
   for (int i = k - 1; i >= 0; --i) {
     double t = gv[i];
@@ -277,12 +286,38 @@ sbie_status solve_completed(sbie_geom* g, int prec, int completion, const double
     yv[i] = t / Hc(i, i);
   }
   SBIE_HIP(hipMemcpyAsync(dh.p, yv.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_combination, dim3(cdiv(N, kBlock)), dim3(kBlock), 0, s, V.p, dh.p, k, N, d_sigma);
+  hipLaunchKernelGGL(k_combination, dim3(cdiv(N, kBlock)), dim3(kBlock), 0, s, V.p, dh.p, k, N, d_x);
   SBIE_HIP(hipGetLastError());
   SBIE_HIP(hipStreamSynchronize(s));
   *iters = k;
   *relres = res;
   return SBIE_OK;
+}
+
+sbie_status solve_completed(sbie_geom* g, int prec, int completion, const double* d_eta, const double* d_f,
+                            double* d_sigma, double tol, int maxit, int* iters, double* relres, hipStream_t s) {
+  DevBuf tmp;
+  sbie_status st = dev_alloc(tmp, 3 * (size_t)g->N);
+  if (st != SBIE_OK) return st;
+  auto K = [&](const double* in, double* out) {
+    return apply_completed(g, prec, completion, d_eta, in, out, tmp.p, s);
+  };
+  return gmres(g->N, K, d_f, d_sigma, tol, maxit, iters, relres, s);
+}
+
+// -rho/2 + S'[rho]
+sbie_status apply_neumann(sbie_geom* g, int prec, const double* d_rho, double* d_out, hipStream_t s) {
+  sbie_status st = apply_laplace(g, SBIE_OP_SP, prec, d_rho, d_out, s, SBIE_PARTS_ALL, false);
+  if (st != SBIE_OK) return st;
+  hipLaunchKernelGGL(k_axpy, dim3(cdiv(g->N, kBlock)), dim3(kBlock), 0, s, d_rho, -0.5, g->N, d_out);
+  SBIE_HIP(hipGetLastError());
+  return SBIE_OK;
+}
+
+sbie_status solve_neumann(sbie_geom* g, int prec, const double* d_g, double* d_rho, double tol, int maxit,
+                          int* iters, double* relres, hipStream_t s) {
+  auto A = [&](const double* in, double* out) { return apply_neumann(g, prec, in, out, s); };
+  return gmres(g->N, A, d_g, d_rho, tol, maxit, iters, relres, s);
 }
 
 }  // namespace sbie
@@ -395,6 +430,48 @@ sbie_status sbie_solve_completed(sbie_geom* g, sbie_precision prec, sbie_complet
   if ((st = solve_completed(g, (int)prec, (int)c, g->d_eta, df, ds, tol, maxit, &it, &res, s)) != SBIE_OK)
     return st;
   if (!devptr) SBIE_HIP(hipMemcpyAsync(sigma, ds, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+  SBIE_HIP(hipStreamSynchronize(s));
+  *iters = it;
+  *relres = res;
+  return sbie_geom_sync(g, s);
+}
+
+sbie_status sbie_solve_neumann(sbie_geom* g, sbie_precision prec, const double* data, double* rho, double tol,
+                               int32_t maxit, int32_t* iters, double* relres, void* stream, uint32_t flags) {
+  if (!g) {
+    set_error("geometry is NULL");
+    return SBIE_E_INVALID;
+  }
+  if (prec != SBIE_FP64 && prec != SBIE_MIXED) {
+    set_error("unknown precision");
+    return SBIE_E_INVALID;
+  }
+  if (!data || !rho || !iters || !relres) {
+    set_error("data, rho, iters or relres is NULL");
+    return SBIE_E_INVALID;
+  }
+  if (maxit < 1 || maxit > 4096 || !(tol > 0.0)) {
+    set_error("maxit must be in [1, 4096] and tol > 0");
+    return SBIE_E_INVALID;
+  }
+  SBIE_HIP(hipSetDevice(g->ctx->device));
+  hipStream_t s = stream ? (hipStream_t)stream : g->ctx->stream;
+  const int64_t N = g->N;
+  const bool devptr = (flags & SBIE_DEVICE_PTRS) != 0;
+  DevBuf io;
+  const double* dd = data;
+  double* dr = rho;
+  sbie_status st;
+  if (!devptr) {
+    if ((st = dev_alloc(io, 2 * (size_t)N)) != SBIE_OK) return st;
+    SBIE_HIP(hipMemcpyAsync(io.p, data, sizeof(double) * N, hipMemcpyHostToDevice, s));
+    dd = io.p;
+    dr = io.p + N;
+  }
+  int it = 0;
+  double res = 0.0;
+  if ((st = solve_neumann(g, (int)prec, dd, dr, tol, maxit, &it, &res, s)) != SBIE_OK) return st;
+  if (!devptr) SBIE_HIP(hipMemcpyAsync(rho, dr, sizeof(double) * N, hipMemcpyDeviceToHost, s));
   SBIE_HIP(hipStreamSynchronize(s));
   *iters = it;
   *relres = res;

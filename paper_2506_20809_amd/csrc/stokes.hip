@@ -74,28 +74,14 @@ __global__ void k_stokes_scale(const double* __restrict__ coef, const double* __
 }
 
 // Cartesian (lab) gradients of the four expansions from their derivatives in
-// (u, v, phi) -- the chain rule for the orthogonal coordinates of Table 1 --
-// and the combination of Eq. (stokes).  d = x - c (lab).
+// (u, v, phi) and the combination of Eq. (stokes).  d = x - c (lab).
 __device__ inline void stokes_from_derivatives(const Particle& P, double u, double su, double v, double sv,
                                                double c1, double s1, const double* Phi, const double* Pu,
                                                const double* Pv, const double* Pp, const double d[3],
                                                double out[3]) {
-  const double a = P.a;
-  const double xu[3] = {a * u / su * sv * c1, a * u / su * sv * s1, a * v};
-  const double xv[3] = {-a * su * v / sv * c1, -a * su * v / sv * s1, a * u};
-  const double xp[3] = {-a * su * sv * s1, a * su * sv * c1, 0.0};
-  const double hu2 = xu[0] * xu[0] + xu[1] * xu[1] + xu[2] * xu[2];
-  const double hv2 = xv[0] * xv[0] + xv[1] * xv[1] + xv[2] * xv[2];
-  const double hp2 = xp[0] * xp[0] + xp[1] * xp[1] + xp[2] * xp[2];
   double grad[4][3];
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const double fu = Pu[s] / hu2, fv = Pv[s] / hv2, fp = Pp[s] / hp2;
-    const double gb[3] = {xu[0] * fu + xv[0] * fv + xp[0] * fp, xu[1] * fu + xv[1] * fv + xp[1] * fp,
-                          xu[2] * fu + xv[2] * fv};
-#pragma unroll
-    for (int r = 0; r < 3; ++r) grad[s][r] = P.R[3 * r] * gb[0] + P.R[3 * r + 1] * gb[1] + P.R[3 * r + 2] * gb[2];
-  }
+  for (int s = 0; s < 4; ++s) lab_gradient(P, u, su, v, sv, c1, s1, Pu[s], Pv[s], Pp[s], grad[s]);
 #pragma unroll
   for (int k = 0; k < 3; ++k)
     out[k] = 0.5 * (Phi[k] - d[0] * grad[0][k] - d[1] * grad[1][k] - d[2] * grad[2][k] + grad[3][k]);
@@ -150,128 +136,18 @@ __global__ __launch_bounds__(64) void k_near_stokes(
   const bool live = t < T;
   const int64_t g = (int64_t)j * T + (live ? t : 0);
   const double X0 = x[g], X1 = y[g], X2 = z[g];
-  const int K = (p + 1) * (p + 1), Kh = (p + 1) * (p + 2) / 2, N1 = p + 1;
+  const int K = (p + 1) * (p + 1), Kh = (p + 1) * (p + 2) / 2;
   double acc[3] = {0.0, 0.0, 0.0};
   unsigned bad = 0u;
   for (int sidx = near_ptr[j]; sidx < near_ptr[j + 1]; ++sidx) {
     const int i = near_src[sidx];
     const Particle P = part[i];
-    const double* Ei = E + (size_t)i * 4 * K;
-    const double* Li = lam + (size_t)i * Kh * 4;
-    const double d0 = X0 - P.c[0], d1 = X1 - P.c[1], d2 = X2 - P.c[2];
-    const double b0 = P.R[0] * d0 + P.R[3] * d1 + P.R[6] * d2;
-    const double b1 = P.R[1] * d0 + P.R[4] * d1 + P.R[7] * d2;
-    const double b2 = P.R[2] * d0 + P.R[5] * d1 + P.R[8] * d2;
-    const double a = P.a;
-    // a target on the source's symmetry axis is moved off it by 1e-12 a (the
-    // v and phi directions are singular there)
-    const double rho0 = sqrt(b0 * b0 + b1 * b1);
-    const double rho = fmax(rho0, 1e-12 * a);
-    double u, w;
-    if (!P.oblate) {
-      const double f1 = sqrt(rho * rho + (b2 - a) * (b2 - a));
-      const double f2 = sqrt(rho * rho + (b2 + a) * (b2 + a));
-      const double ch = (f1 + f2) / (2.0 * a);
-      u = ch;
-      w = (ch - 1.0) * (ch + 1.0);
-    } else {
-      const double f1 = sqrt((rho + a) * (rho + a) + b2 * b2);
-      const double f2 = sqrt((rho - a) * (rho - a) + b2 * b2);
-      const double ch = (f1 + f2) / (2.0 * a);
-      u = sqrt((ch - 1.0) * (ch + 1.0));
-      w = ch * ch;
-    }
-    if (!(u > P.u0)) bad |= kStatExterior;
-    const double sw = sqrt(w);
-    const double v = b2 / (a * u);
-    const double sv = rho / (a * sw);
-    const double inv_omv2 = 1.0 / (sv * sv);
-    const double inv_w = 1.0 / w;
-    const double c1 = rho0 > 0.0 ? b0 / rho0 : 1.0, s1 = rho0 > 0.0 ? b1 / rho0 : 0.0;
-    const double sgn = P.oblate ? 1.0 : -1.0;
-    const int L = near_depth(u, sw, N1, kStatNumeric, &bad);
-    double Phi[4] = {0, 0, 0, 0}, Pu[4] = {0, 0, 0, 0}, Pv[4] = {0, 0, 0, 0}, Pp[4] = {0, 0, 0, 0};
-    double qn0[2], qn1[2];
-    q_top_orders01(u, sw, sgn, N1, L, rcp, qn0, qn1);
-    const double ur = u / sw;
-    double fa2 = 0.0, fa1 = 0.0, fb2 = 0.0, fb1 = 0.0;
-    double pbar = 0.28209479177387814347, cm = 1.0, sm = 0.0;
-    for (int m = 0; m <= p; ++m) {
-      if (m > 0) {
-        pbar *= sqrt((2.0 * m + 1.0) / (2.0 * m)) * sv;
-        const double cn = cm * c1 - sm * s1;
-        sm = sm * c1 + cm * s1;
-        cm = cn;
-      }
-      const double qN = m == 0 ? qn0[0] : (m == 1 ? qn0[1] : q_next_order(ur, N1, m, fa1, fa2));
-      const double qN1 = m == 0 ? qn1[0] : (m == 1 ? qn1[1] : q_next_order(ur, N1 + 1, m, fb1, fb2));
-      fa2 = fa1;
-      fa1 = qN;
-      fb2 = fb1;
-      fb1 = qN1;
-      double Q[PMAX + 4];
-      q_column<PMAX>(u, sgn, N1, m, qN, qN1, rcp, Q);
-      // normalised Ferrers functions of v through degree p+1
-      double Pb[PMAX + 3];
-      {
-        double p2 = 0.0, p1 = pbar;
-#pragma unroll
-        for (int n = 0; n <= PMAX + 1; ++n) {
-          double pn = 0.0;
-          if (n == m) {
-            pn = pbar;
-          } else if (n == m + 1) {
-            pn = sqrt(2.0 * m + 3.0) * v * pbar;
-            p2 = p1;
-            p1 = pn;
-          } else if (n > m + 1 && n <= p + 1) {
-            const int h = n * (n + 1) / 2 + m;
-            pn = ab[2 * h] * (v * p1 - ab[2 * h + 1] * p2);
-            p2 = p1;
-            p1 = pn;
-          }
-          Pb[n] = pn;
-        }
-      }
-      double vc[4] = {0, 0, 0, 0}, vs[4] = {0, 0, 0, 0}, uc[4] = {0, 0, 0, 0}, us[4] = {0, 0, 0, 0};
-      double wc[4] = {0, 0, 0, 0}, ws[4] = {0, 0, 0, 0};
-#pragma unroll
-      for (int n = 0; n <= PMAX; ++n) {
-        if (n >= m && n <= p) {
-          const int h = n * (n + 1) / 2 + m;
-          const double sc = Li[h * 4 + 3];
-          const double qr = Q[n] * sc;
-          const double dq = ((-sgn) * (double)(n - m + 1) * Q[n + 1] - (double)(n + 1) * u * Q[n]) * inv_w * sc;
-          const double pn = Pb[n];
-          const double dpn = ((double)(n + 1) * v * pn - cd[h] * Pb[n + 1]) * inv_omv2;
-          const double t0 = pn * qr, t1 = pn * dq, t2 = dpn * qr;
-#pragma unroll
-          for (int s = 0; s < 4; ++s) {
-            const double ec = Ei[(size_t)s * K + n * n + n + m];
-            vc[s] = fma(ec, t0, vc[s]);
-            uc[s] = fma(ec, t1, uc[s]);
-            wc[s] = fma(ec, t2, wc[s]);
-            if (m > 0) {
-              const double es = Ei[(size_t)s * K + n * n + n - m];
-              vs[s] = fma(es, t0, vs[s]);
-              us[s] = fma(es, t1, us[s]);
-              ws[s] = fma(es, t2, ws[s]);
-            }
-          }
-        }
-      }
-      const double f = m == 0 ? 1.0 : 1.41421356237309504880;
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        Phi[s] += f * (vc[s] * cm + vs[s] * sm);
-        Pu[s] += f * (uc[s] * cm + us[s] * sm);
-        Pv[s] += f * (wc[s] * cm + ws[s] * sm);
-        Pp[s] += f * (double)m * (vs[s] * cm - vc[s] * sm);
-      }
-    }
-    const double d[3] = {d0, d1, d2};
+    const SpheroidalPoint q = to_spheroidal(P, X0, X1, X2, true, &bad);
+    double Phi[4], Pu[4], Pv[4], Pp[4];
+    expansion_derivatives<PMAX, 4>(q, P.oblate != 0, E + (size_t)i * 4 * K, (size_t)K, lam + (size_t)i * Kh * 4,
+                                   ab, cd, rcp, p, &bad, Phi, Pu, Pv, Pp);
     double o3[3];
-    stokes_from_derivatives(P, u, sw, v, sv, c1, s1, Phi, Pu, Pv, Pp, d, o3);
+    stokes_from_derivatives(P, q.u, q.sw, q.v, q.sv, q.c1, q.s1, Phi, Pu, Pv, Pp, q.d, o3);
     acc[0] += o3[0];
     acc[1] += o3[1];
     acc[2] += o3[2];

@@ -1,0 +1,209 @@
+"""S' and D' (Section 3.3: derivatives along the target's outward normal; S'
+the principal value of Theorem 3, D' continuous) and the single-layer Neumann
+solve (Eq. (neusol)) through the C ABI, against the oracle.
+
+Bars as for S and D: FP64 relative l2 and max-norm <= 1e-10 per part and for
+the sum; mixed relative l2 <= 1e-6 and max-norm <= 1e-5.  The Neumann solve:
+iterations within one of the oracle's GMRES, density within 1e-8.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle import bie
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+SP, DP = 3, 4
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    import paper_2506_20809_amd as sbie
+
+    assert torch.cuda.is_available()
+    c = sbie.Context(0)
+    yield c
+    c.close()
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a - b)
+
+
+def _check_parts(g, geom, p, op, dens, tol=TOL64, max_tol=None, precision=0, label=""):
+    import torch
+
+    import paper_2506_20809_amd as sbie
+
+    ref = oracle.apply(geom, p, op, dens, parts=True)
+    d = torch.tensor(dens, dtype=torch.float64, device="cuda")
+    flags = [sbie.SBIE_PARTS_ALL, sbie.SBIE_PARTS_SELF, sbie.SBIE_PARTS_NEAR, sbie.SBIE_PARTS_FAR]
+    max_tol = tol if max_tol is None else max_tol
+    for name, fl, r in zip(["all", "self", "near", "far"], flags, ref):
+        u = g.apply(op, d, parts=fl, precision=precision)
+        g.sync()
+        u = u.cpu().numpy()
+        if np.max(np.abs(r)) == 0:
+            assert np.max(np.abs(u)) < 1e-13, (label, name)
+            continue
+        assert _rel(u, r) < tol, (label, name, _rel(u, r))
+        assert np.max(np.abs(u - r)) < max_tol * np.max(np.abs(r)), (label, name)
+
+
+@pytest.mark.parametrize("op", [SP, DP])
+@pytest.mark.parametrize("name,p", [("c1", 8), ("c2", 16)])
+def test_parity(ctx, name, p, op):
+    import paper_2506_20809_amd as sbie
+
+    geom = workloads.geometry(name)
+    g = sbie.Geometry(ctx, geom, p)
+    _check_parts(g, geom, p, op, workloads.density(name)[0], label=f"{name} op={op}")
+    g.close()
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 5, 9, 17, 24])
+def test_small_suspensions_many_orders(ctx, p):
+    """Ragged sizes, orders across the register buckets, prolate/oblate mixes."""
+    import paper_2506_20809_amd as sbie
+
+    geom = workloads.rsa_pack(7, 0.12, 0.05, 500 + p)
+    dens = np.random.default_rng(p).standard_normal(7 * (p + 1) * (2 * p + 2))
+    g = sbie.Geometry(ctx, geom, p)
+    for op in (SP, DP):
+        _check_parts(g, geom, p, op, dens, label=f"mini p={p} op={op}")
+    g.close()
+
+
+def test_single_particle_self_only(ctx):
+    import paper_2506_20809_amd as sbie
+
+    for A, C in [(0.5, 1.0), (1.2, 0.4)]:
+        q = np.array([0.9, 0.1, -0.3, 0.2])
+        geom = {"centers": np.array([[0.3, -0.2, 1.0]]), "quats": (q / np.linalg.norm(q))[None, :],
+                "A": np.array([A]), "C": np.array([C])}
+        g = sbie.Geometry(ctx, geom, 10)
+        dens = np.random.default_rng(1).standard_normal(g.N)
+        for op in (SP, DP):
+            _check_parts(g, geom, 10, op, dens, label=f"single op={op}")
+        g.close()
+
+
+@pytest.mark.parametrize("op", [SP, DP])
+def test_mixed_parity(ctx, op):
+    import paper_2506_20809_amd as sbie
+
+    for name, p in [("c1", 8), ("c2", 16)]:
+        geom = workloads.geometry(name)
+        g = sbie.Geometry(ctx, geom, p)
+        _check_parts(g, geom, p, op, workloads.density(name)[0], tol=1e-6, max_tol=1e-5,
+                     precision=sbie.SBIE_MIXED, label=f"mixed {name} op={op}")
+        g.close()
+
+
+@pytest.mark.parametrize("op", [SP, DP])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_c3_full_size_sampled(ctx, op, precision):
+    """512 spheroids at p = 16: sampled nodes against the oracle node by node."""
+    import torch
+
+    import paper_2506_20809_amd as sbie
+
+    geom = workloads.geometry("c3")
+    p = 16
+    g = sbie.Geometry(ctx, geom, p)
+    dens = workloads.density("c3")[0]
+    u = g.apply(op, torch.tensor(dens, device="cuda"), precision=precision)
+    g.sync()
+    u = u.cpu().numpy()
+    rng = np.random.default_rng(31 + op + 10 * precision)
+    tg = np.sort(rng.choice(g.N, size=24, replace=False))
+    tg[0], tg[-1] = 0, g.N - 1
+    ref = oracle.apply_at(geom, p, op, dens, tg)[0]
+    if precision == 0:
+        assert np.max(np.abs(u[tg] - ref)) < TOL64 * np.max(np.abs(ref))
+    else:
+        assert _rel(u[tg], ref) < 1e-6, _rel(u[tg], ref)
+    g.close()
+
+
+def test_dp_of_constant_vanishes_c3(ctx):
+    """D'[1] = 0 at every node of the 512-spheroid suspension (the double layer
+    of a constant is constant inside each particle and zero outside)."""
+    import torch
+
+    import paper_2506_20809_amd as sbie
+
+    geom = workloads.geometry("c3")
+    g = sbie.Geometry(ctx, geom, 16)
+    u = g.apply(DP, torch.ones(g.N, dtype=torch.float64, device="cuda"))
+    g.sync()
+    assert torch.max(torch.abs(u)).item() < 1e-9
+    g.close()
+
+
+def test_neumann_solve_parity(ctx):
+    """The Neumann system of Section 5.1 (two oblates and a prolate): GPU GMRES
+    against the oracle's on the same data."""
+    import torch
+
+    import paper_2506_20809_amd as sbie
+
+    geom = workloads.three_spheroids(True, seed=3)
+    p = 8
+    g = sbie.Geometry(ctx, geom, p)
+    xyz, nrm, _ = oracle.grid(geom, p)
+    pos, q = workloads.point_charges(geom, 2, 5, shrink=0.3)
+    data = workloads.charge_flux(pos, q, xyz, nrm)
+    ref, it_ref, _ = bie.solve_neumann(geom, p, data, 1e-10, 200)
+    rho, it, res = g.solve_neumann(torch.tensor(data, device="cuda"), tol=1e-10, maxit=200)
+    rho = rho.cpu().numpy()
+    assert res <= 1e-10 and abs(it - it_ref) <= 1, (it, it_ref)
+    assert _rel(rho, ref) < 1e-8, _rel(rho, ref)
+    rh, ith, _ = g.solve_neumann(data, tol=1e-10, maxit=200)
+    assert ith == it and np.array_equal(rh, rho)
+    g.close()
+
+
+def test_neumann_point_charges_exterior(ctx):
+    """The layer solved on the GPU at p = 16 reproduces the charges' potential
+    0.5 outside the surfaces."""
+    import paper_2506_20809_amd as sbie
+
+    geom = workloads.three_spheroids(True, seed=3)
+    pos, q = workloads.point_charges(geom, 2, 5, shrink=0.3)
+    p = 16
+    g = sbie.Geometry(ctx, geom, p)
+    xyz, nrm, _ = oracle.grid(geom, p)
+    data = workloads.charge_flux(pos, q, xyz, nrm)
+    rho, it, res = g.solve_neumann(data, tol=1e-12, maxit=200)
+    assert res <= 1e-12 and it < 60
+    pts = xyz[::5] + 0.5 * nrm[::5]
+    u = bie.evaluate_single(geom, p, rho, pts)
+    fx = workloads.charge_potential(pos, q, pts)
+    assert np.max(np.abs(u - fx)) / np.max(np.abs(fx)) < 5e-6
+    g.close()
+
+
+def test_errors(ctx):
+    import paper_2506_20809_amd as sbie
+
+    geom = workloads.lattice2x2(2.0, 2.0)
+    g = sbie.Geometry(ctx, geom, 4)
+    f = np.ones(g.N)
+    for kw in ({"maxit": 0}, {"maxit": 5000}, {"tol": 0.0}):
+        with pytest.raises(sbie.SbieError) as e:
+            g.solve_neumann(f, **kw)
+        assert e.value.status == -1
+    with pytest.raises(sbie.SbieError) as e:
+        g.transform(SP, f)
+    assert e.value.status == -1
+    with pytest.raises(sbie.SbieError) as e:
+        g.apply(5, f)
+    assert e.value.status == -1
+    g.close()

@@ -123,6 +123,43 @@ def run(g, dens, steps, warmup, precision):
 FLOPS_PER_STOKES_PAIR = 29
 
 
+# S' per far node pair: 3 differences + 5 for r^2 + 1 rsqrt + 2 for r^-3 + 5 for nu_x.d + 1 for q (nu_x.d)
+# + 2 accumulate = 19.  D': 3 + 5 + 1 + 2 (r^-3) + 1 (r^-2) + 5 (nu_y.d) + 5 (nu_x.d) + 5 (nu_x.nu_y)
+# + 2 (-3 (nu_y.d)(nu_x.d)) + 2 (FMA with r^-2 and nu_x.nu_y) + 1 (q r^-3) + 2 accumulate = 34
+FLOPS_PER_NORMAL_PAIR = {3: 19, 4: 34}
+
+
+def run_normal(g, dens, steps, precision):
+    """S' and D' applies on the same geometry: applies/s per operator and the
+    far kernel's share of the vector peak."""
+    import numpy as np
+    import torch
+
+    import paper_2506_20809_amd as sbie
+
+    prec = sbie.SBIE_MIXED if precision == "mixed" else sbie.SBIE_FP64
+    out = torch.empty(g.N, dtype=torch.float64, device="cuda")
+    res = {}
+    for op, name in ((sbie.SBIE_OP_SP, "S'"), (sbie.SBIE_OP_DP, "D'")):
+        g.apply(op, dens[0, 0], precision=prec, out=out, timing=True)
+        g.sync()
+        g.timing()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            g.apply(op, dens[k % dens.shape[0], 0], precision=prec, out=out, timing=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        g.sync()
+        tim = g.timing()
+        achieved = FLOPS_PER_NORMAL_PAIR[op] * tim.far_pairs / (tim.far_kernel_ms * 1e-3) / 1e12
+        res[name] = {"applies_per_s": steps / el, "ms_per_apply": 1e3 * el / steps,
+                     "part_ms": {"prep": tim.prep_ms, "transform_self": tim.transform_ms, "near": tim.near_ms,
+                                 "far_kernel": tim.far_kernel_ms, "assemble": tim.assemble_ms},
+                     "far_roofline_frac": achieved / PEAK_TFLOPS[precision]}
+    return res
+
+
 def run_stokes(ctx, steps, warmup, precision):
     """Stokes single layer (Eq. stokes) on the 256-spheroid suspension at p = 12."""
     import numpy as np
@@ -200,6 +237,23 @@ def charge_data(pos, q, xyz):
     return f
 
 
+def charge_flux_data(pos, q, xyz, nrm):
+    """Outward normal derivative of the charges' potential at the nodes (the
+    exterior Neumann data), on the GPU."""
+    import torch
+
+    x = torch.tensor(xyz, dtype=torch.float64, device="cuda")
+    n = torch.tensor(nrm, dtype=torch.float64, device="cuda")
+    out = torch.zeros(len(xyz), dtype=torch.float64, device="cuda")
+    P = torch.tensor(pos, dtype=torch.float64, device="cuda")
+    Q = torch.tensor(q, dtype=torch.float64, device="cuda")
+    for k in range(len(q)):
+        d = x - P[k]
+        r = torch.linalg.norm(d, dim=1)
+        out -= Q[k] * (d * n).sum(dim=1) / (4.0 * math.pi * r ** 3)
+    return out
+
+
 def gmres_study(ctx, p=16, ratios=(1.1, 2.0, 4.0, 8.0, 16.0, 32.0, 64.0), maxit=1000):
     """GMRES iterations of the completed double-layer Dirichlet solve on the
     four-prolate lattice (Section 5.2) for each completion, unscaled and scaled
@@ -261,6 +315,15 @@ def solve_large(ctx, name, precision, maxit=300):
     el = time.perf_counter() - t
     out = {"workload": f"{len(geom['A'])} spheroids, p={p}, N={g.N}, eta S completion, precision={precision}",
            "tol": tol, "iterations": it, "relres": res, "solve_s": el, "ms_per_iteration": 1e3 * el / max(it, 1)}
+    # the single-layer Neumann problem with the charges' normal field as data
+    xyz, nrm, _ = g.nodes()
+    data = charge_flux_data(pos, q, xyz, nrm)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, it, res = g.solve_neumann(data, tol=tol, maxit=maxit, precision=prec)
+    el = time.perf_counter() - t
+    out["neumann"] = {"tol": tol, "iterations": it, "relres": res, "solve_s": el,
+                      "ms_per_iteration": 1e3 * el / max(it, 1)}
     g.close()
     return out
 
@@ -407,6 +470,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the other precision's measurement")
     ap.add_argument("--no-stokes", action="store_true", help="skip the Stokes single-layer measurement")
+    ap.add_argument("--no-derivatives", action="store_true", help="skip the S' and D' measurement")
     ap.add_argument("--no-solve", action="store_true", help="skip the completed double-layer solves")
     ap.add_argument("--served-requests", type=int, default=0,
                     help="requests in the served-mode run (0: skip; the run is opt-in)")
@@ -479,6 +543,8 @@ def main():
         res[f"{other}_path"] = {k: sec[k] for k in ("applies_per_s", "pair_interactions_per_s", "latency_ms",
                                                     "part_ms")}
         res[f"{other}_path"]["roofline_frac"] = sec["roofline"]["frac"]
+    if not args.no_derivatives:
+        res["derivatives"] = {pr: run_normal(g, dens, max(3, args.steps // 4), pr) for pr in ("mixed", "fp64")}
     if not args.no_stokes:
         res["stokes"] = {pr: run_stokes(ctx, max(4, args.steps // 2), 1, pr) for pr in ("fp64", "mixed")}
     if not args.no_solve:

@@ -72,6 +72,8 @@ def lib():
                                         ctypes.c_int, ctypes.c_int, dp]
         L.orc_single_layer_grad.argtypes = [dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp,
                                             ctypes.c_int, dp]
+        L.orc_eval_targets.argtypes = [dp, dp, dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                       dp, dp, ctypes.c_int, dp, dp, ctypes.POINTER(ctypes.c_uint8)]
         L.orc_set_cf_max_iter.argtypes = [ctypes.c_int]
         L.orc_set_cf_max_iter.restype = None
         L.orc_num_threads.argtypes = []
@@ -217,6 +219,22 @@ def apply_at(geom, p: int, op: int, density: np.ndarray, targets, eta: float = 1
                               tg.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n, _p(us), _p(un), _p(uf),
                               _p(u)), "apply_at")
     return u, us, un, uf
+
+
+def eval_targets(geom, p: int, op: int, density: np.ndarray, pts: np.ndarray, eta: float = 1.0):
+    """S or D of the nodal density at points outside every particle, with the
+    per-target near/far split.  Returns (value [n], gradient [n, 3], near [n, M])."""
+    c, q, A, C = _geom_arrays(geom)
+    M = len(A)
+    dens = _f64(density).reshape(-1)
+    pts = _f64(pts).reshape(-1, 3)
+    n = len(pts)
+    val, grad = np.zeros(n), np.zeros((n, 3))
+    near = np.zeros((n, M), dtype=np.uint8)
+    _check(lib().orc_eval_targets(_p(c), _p(q), _p(A), _p(C), M, int(p), float(eta), int(op), _p(dens), _p(pts),
+                                  n, _p(val), _p(grad), near.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))),
+           "eval_targets")
+    return val, grad, near
 
 
 def eval_exterior(spheroid, p: int, op: int, density: np.ndarray, pts: np.ndarray) -> np.ndarray:

@@ -1365,6 +1365,97 @@ int orc_single_layer_grad(const double* centre, const double* quat, double A, do
   return rc;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Particle-to-target evaluation (Section 4, "Particle-to-target algorithm"): */
+/* S or D of the nodal density, and its lab gradient (Eq. (dSLevalformula)   */
+/* and the same construction for D), at arbitrary points outside every       */
+/* particle.  Each (target, source particle) pair is classified on its own:   */
+/* near iff the exact distance from the point to the surface is below        */
+/* eta * diam(source), then the source's exterior expansion is used, else the */
+/* smooth quadrature.  grad ([npts][3]) and near_out ([npts][M]) may be NULL. */
+/* ------------------------------------------------------------------------ */
+int orc_eval_targets(const double* centres, const double* quats, const double* A, const double* C, int M,
+                     int p, double eta, int op, const double* density, const double* pts, int npts,
+                     double* val, double* grad, uint8_t* near_out) {
+  if (op != OP_S && op != OP_D) return ORC_E_INVALID;
+  geometry g;
+  int rc = build_geometry(centres, quats, A, C, M, p, eta, &g);
+  if (rc) return rc;
+  int T = g.T, K = g.K, Kh = g.Kh;
+  double* cself = (double*)malloc(sizeof(double) * (size_t)M * K);
+  double* E = (double*)malloc(sizeof(double) * (size_t)M * K);
+  double complex* Qu0 = (double complex*)malloc(sizeof(double complex) * (size_t)M * Kh);
+  int err = 0;
+#pragma omp parallel for schedule(dynamic)
+  for (int i = 0; i < M; ++i) {
+    int r = particle_coefficients(&g, op, i, density, cself + (size_t)i * K, E + (size_t)i * K,
+                                  Qu0 + (size_t)i * Kh);
+    if (r) {
+#pragma omp atomic write
+      err = r;
+    }
+  }
+  if (err) rc = err;
+#pragma omp parallel for schedule(dynamic)
+  for (int t = 0; t < npts; ++t) {
+    if (rc || err) continue;
+    const double* x = pts + 3 * t;
+    double v = 0.0, gr[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < M; ++i) {
+      const particle* pt = &g.pt[i];
+      if (inside(pt, x)) {
+#pragma omp atomic write
+        err = ORC_E_OVERLAP;
+        break;
+      }
+      double y[3];
+      project_lab(pt, x, y);
+      double dist = sqrt((x[0] - y[0]) * (x[0] - y[0]) + (x[1] - y[1]) * (x[1] - y[1]) +
+                         (x[2] - y[2]) * (x[2] - y[2]));
+      int near = dist < eta * pt->diam;
+      if (near_out) near_out[(size_t)t * M + i] = (uint8_t)near;
+      if (near) {
+        double xb[3], u, vv, ph, ev, eg[3];
+        lab_to_body(pt, x, xb);
+        body_to_spheroidal(pt, xb, &u, &vv, &ph);
+        int r = expansion_grad(pt, p, 1, E + (size_t)i * K, u, vv, ph, 0, &ev, eg);
+        if (r) {
+#pragma omp atomic write
+          err = r;
+          break;
+        }
+        v += ev;
+        for (int c = 0; c < 3; ++c) gr[c] += eg[c];
+      } else {
+        for (int q = 0; q < T; ++q) {
+          size_t gs = (size_t)i * T + q;
+          const double* ys = g.xyz + 3 * gs;
+          const double* ny = g.nrm + 3 * gs;
+          double d[3] = {x[0] - ys[0], x[1] - ys[1], x[2] - ys[2]};
+          double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+          double r = sqrt(r2);
+          double w = g.W[gs] * density[gs] / (4.0 * PI);
+          if (op == OP_S) {
+            v += w / r;
+            for (int c = 0; c < 3; ++c) gr[c] -= w * d[c] / (r2 * r);
+          } else {
+            double nd = ny[0] * d[0] + ny[1] * d[1] + ny[2] * d[2];
+            v += w * nd / (r2 * r);
+            for (int c = 0; c < 3; ++c) gr[c] += w * (ny[c] / (r2 * r) - 3.0 * nd * d[c] / (r2 * r2 * r));
+          }
+        }
+      }
+    }
+    val[t] = v;
+    if (grad)
+      for (int c = 0; c < 3; ++c) grad[3 * t + c] = gr[c];
+  }
+  if (err) rc = err;
+  free(cself); free(E); free(Qu0);
+  free_geometry(&g);
+  return rc;
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
   extern int omp_get_max_threads(void);

@@ -152,8 +152,9 @@ sbie_status sbie_apply(sbie_geom* g, sbie_op op, sbie_precision prec, int32_t nr
 
 /* Wait for `stream` (NULL: the context stream) and return the sticky device
    status of the applies made on this geometry since the last check:
-   SBIE_E_NUMERIC if a continued fraction did not converge, SBIE_E_OVERLAP if a
-   near-field target was found inside its source, else SBIE_OK.  Asynchronous
+   SBIE_E_OVERLAP if a near-field target was found inside its source (checked
+   first: the recurrences fail there too), SBIE_E_NUMERIC if a continued
+   fraction did not converge, else SBIE_OK.  Asynchronous
    applies report their numerical failures here. */
 sbie_status sbie_geom_sync(sbie_geom* g, void* stream);
 
@@ -175,6 +176,20 @@ sbie_status sbie_geom_spectra(const sbie_geom* g, double* out);
    previous call (waits for them to finish), then starts a new window.
    SBIE_E_STATE if there was no timed apply. */
 sbie_status sbie_geom_timing(sbie_geom* g, sbie_timing* out);
+
+/* Particle-to-target evaluation (Section 4, the particle-to-target variant of
+   Algorithm 1): S or D (op) of the nodal density at npts points pts [npts][3]
+   outside every particle, into val [npts] and, if grad is not NULL, the
+   gradient grad [npts][3] (Eq. (dSLevalformula) and its analogue for D).
+   Each (point, source particle) pair is near iff the exact distance from the
+   point to the source surface is below eta * diam(source): near sources
+   contribute their exterior expansion, far ones the smooth quadrature.
+   Pointers as in sbie_apply; work buffers are allocated for the call, which
+   returns after completion.  SBIE_E_OVERLAP if a point lies inside (or on) a
+   particle, SBIE_E_INVALID for other ops or npts outside [0, 2^31]. */
+sbie_status sbie_eval_targets(sbie_geom* g, sbie_op op, sbie_precision prec, const double* density,
+                              int64_t npts, const double* pts, double* val, double* grad, void* stream,
+                              uint32_t flags);
 
 /* ---------------------------------------------------------------- completed double-layer solve
 

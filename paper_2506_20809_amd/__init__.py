@@ -34,6 +34,7 @@ EXPORTS = [
     "sbie_session_bytes", "sbie_server_create", "sbie_server_destroy", "sbie_session_open", "sbie_session_apply",
     "sbie_session_close", "sbie_wait", "sbie_server_get_info", "sbie_status_str", "sbie_last_error",
     "sbie_completion_eta", "sbie_apply_completed", "sbie_solve_completed", "sbie_solve_neumann",
+    "sbie_eval_targets",
 ]
 SBIE_COMPLETE_POINT, SBIE_COMPLETE_SINGLE = 0, 1
 SBIE_SERVER_GRAPHS = 0x100
@@ -131,6 +132,8 @@ def lib() -> ctypes.CDLL:
         L.sbie_solve_neumann.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_double, ctypes.c_int32,
                                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double), vp,
                                          ctypes.c_uint32]
+        L.sbie_eval_targets.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int64, vp, vp, vp, vp,
+                                        ctypes.c_uint32]
         L.sbie_status_str.argtypes = [ctypes.c_int]
         L.sbie_status_str.restype = ctypes.c_char_p
         L.sbie_last_error.argtypes = []
@@ -309,6 +312,34 @@ class Geometry:
                                           sig.data_ptr(), float(tol), int(maxit), ctypes.byref(it),
                                           ctypes.byref(res), None, SBIE_DEVICE_PTRS))
         return sig, it.value, res.value
+
+    def eval_targets(self, op: int, density, pts, precision: int = SBIE_FP64, gradient: bool = True):
+        """S or D of the nodal density at points outside every particle: returns
+        (value [n], gradient [n, 3] or None).  numpy inputs use host pointers;
+        torch CUDA float64 tensors device pointers."""
+        if isinstance(density, np.ndarray):
+            d = np.ascontiguousarray(density, dtype=np.float64)
+            x = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+            if d.size != self.N:
+                raise ValueError(f"density has {d.size} entries, expected {self.N}")
+            val = np.zeros(len(x))
+            grad = np.zeros((len(x), 3)) if gradient else None
+            _check(lib().sbie_eval_targets(self._h, int(op), int(precision), d.ctypes.data, len(x), x.ctypes.data,
+                                           val.ctypes.data, grad.ctypes.data if gradient else None, None, 0))
+            return val, grad
+        import torch
+
+        self._vectors(density, "density")
+        if not (pts.is_cuda and pts.dtype == torch.float64 and pts.is_contiguous() and pts.dim() == 2
+                and pts.shape[1] == 3):
+            raise ValueError("pts must be a contiguous float64 CUDA tensor [n, 3]")
+        n = pts.shape[0]
+        val = torch.empty(n, dtype=torch.float64, device=pts.device)
+        grad = torch.empty((n, 3), dtype=torch.float64, device=pts.device) if gradient else None
+        _check(lib().sbie_eval_targets(self._h, int(op), int(precision), density.data_ptr(), n, pts.data_ptr(),
+                                       val.data_ptr(), grad.data_ptr() if gradient else None, None,
+                                       SBIE_DEVICE_PTRS))
+        return val, grad
 
     def solve_neumann(self, data, tol: float = 1e-10, maxit: int = 500, precision: int = SBIE_FP64):
         """GMRES for -rho/2 + S'[rho] = data (single-layer Neumann problem);

@@ -318,13 +318,14 @@ sbie_status sbie_geom_sync(sbie_geom* g, void* stream) {
     SBIE_HIP(hipMemsetAsync(g->d_status, 0, sizeof(unsigned), s));
     SBIE_HIP(hipStreamSynchronize(s));
   }
-  if (status & kStatNumeric) {
-    set_error("continued fraction for Q_N/Q_{N-1} did not converge at a near-field target");
-    return SBIE_E_NUMERIC;
-  }
+  // a target inside its source also breaks the recurrences there: report the cause
   if (status & kStatExterior) {
     set_error("a near-field target lies inside its source spheroid");
     return SBIE_E_OVERLAP;
+  }
+  if (status & kStatNumeric) {
+    set_error("continued fraction for Q_N/Q_{N-1} did not converge at a near-field target");
+    return SBIE_E_NUMERIC;
   }
   return SBIE_OK;
 }

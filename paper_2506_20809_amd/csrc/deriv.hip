@@ -9,6 +9,7 @@
 
 #include <cmath>
 
+#include "far_dev.h"
 #include "near_dev.h"
 #include "sbie_internal.h"
 
@@ -112,21 +113,6 @@ __global__ __launch_bounds__(64) void k_near_normal(
   if (live) unear[g] = acc;
 }
 
-template <typename R>
-__device__ inline R rsq_t(R x);
-template <>
-__device__ inline float rsq_t<float>(float x) {
-  return __builtin_amdgcn_rsqf(x);
-}
-template <>
-__device__ inline double rsq_t<double>(double x) {
-  double yv = __builtin_amdgcn_rsq(x);
-  double e = fma(-x * yv, yv, 1.0);
-  yv = fma(0.5 * yv, e, yv);
-  e = fma(-x * yv, yv, 1.0);
-  return fma(0.5 * yv, e, yv);
-}
-
 // Far part: the differentiated kernels summed over the far source nodes, with
 // d = x - y, q = W dens and the target normal nu_x:
 //  S'  -q (nu_x.d) / r^3
@@ -201,13 +187,7 @@ __global__ __launch_bounds__(256) void k_far_normal(const R* __restrict__ rec, c
       }
     }
 #pragma unroll
-    for (int k = 0; k < TPT; ++k) {
-      const R vv = need[k] ? tmp[k] : R(0);
-      const R sum = acc[k] + vv;
-      const R bp = sum - acc[k];
-      lo[k] += (acc[k] - (sum - bp)) + (vv - bp);
-      acc[k] = sum;
-    }
+    for (int k = 0; k < TPT; ++k) two_sum_add(acc[k], lo[k], need[k] ? tmp[k] : R(0));
   }
 #pragma unroll
   for (int k = 0; k < TPT; ++k) {
@@ -262,6 +242,26 @@ void launch_far_normal(sbie_geom* g, hipStream_t s) {
 
 }  // namespace
 
+sbie_status normal_records(sbie_geom* g, int op, int prec, const double* d_dens, hipStream_t s) {
+  const bool mixed = prec == SBIE_MIXED;
+  if (op == SBIE_OP_SP)
+    mixed ? launch_normal_prep<float, SBIE_OP_SP>(g, d_dens, s) : launch_normal_prep<double, SBIE_OP_SP>(g, d_dens, s);
+  else
+    mixed ? launch_normal_prep<float, SBIE_OP_DP>(g, d_dens, s) : launch_normal_prep<double, SBIE_OP_DP>(g, d_dens, s);
+  SBIE_HIP(hipGetLastError());
+  return SBIE_OK;
+}
+
+sbie_status normal_expansions(sbie_geom* g, int op, int prec, hipStream_t s) {
+  const int M = g->M, p = g->p, T = g->T, K = g->K;
+  sbie_status st = gemm(prec == SBIE_MIXED, g->d_f, T, g->d_An, g->d_An32, K, g->d_coef, K, M, K, T, s);
+  if (st) return st;
+  hipLaunchKernelGGL(k_normal_scale, dim3(cdiv((int64_t)M * K, 256)), dim3(256), 0, s, g->d_coef, g->d_lam,
+                     g->d_dlr, g->d_part, M, p, op, g->d_cself, g->d_E);
+  SBIE_HIP(hipGetLastError());
+  return SBIE_OK;
+}
+
 sbie_status apply_normal(sbie_geom* g, int op, int prec, const double* d_dens, double* d_out, hipStream_t s,
                          uint32_t parts, bool timed) {
   const int M = g->M, p = g->p, T = g->T, K = g->K;
@@ -273,18 +273,12 @@ sbie_status apply_normal(sbie_geom* g, int op, int prec, const double* d_dens, d
     if (st) return st;
     SBIE_HIP(hipEventRecord(ev[0], s));
   }
-  if (op == SBIE_OP_SP)
-    mixed ? launch_normal_prep<float, SBIE_OP_SP>(g, d_dens, s) : launch_normal_prep<double, SBIE_OP_SP>(g, d_dens, s);
-  else
-    mixed ? launch_normal_prep<float, SBIE_OP_DP>(g, d_dens, s) : launch_normal_prep<double, SBIE_OP_DP>(g, d_dens, s);
-  SBIE_HIP(hipGetLastError());
+  sbie_status st0 = normal_records(g, op, prec, d_dens, s);
+  if (st0) return st0;
   if (timed) SBIE_HIP(hipEventRecord(ev[1], s));
   if (parts & (SBIE_PARTS_SELF | SBIE_PARTS_NEAR)) {
-    sbie_status st = gemm(mixed, g->d_f, T, g->d_An, g->d_An32, K, g->d_coef, K, M, K, T, s);
+    sbie_status st = normal_expansions(g, op, prec, s);
     if (st) return st;
-    hipLaunchKernelGGL(k_normal_scale, dim3(cdiv((int64_t)M * K, 256)), dim3(256), 0, s, g->d_coef, g->d_lam,
-                       g->d_dlr, g->d_part, M, p, op, g->d_cself, g->d_E);
-    SBIE_HIP(hipGetLastError());
   }
   if (parts & SBIE_PARTS_SELF) {
     sbie_status st = gemm(mixed, g->d_cself, K, g->d_Sy, g->d_Sy32, T, g->d_uself, T, M, T, K, s);

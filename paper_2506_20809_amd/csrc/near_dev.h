@@ -16,7 +16,10 @@ namespace sbie {
 // margin, the largest over the wave (wave-uniform), in whole chunks of eight
 // steps; past 1e5 steps the depth is capped and numeric_flag is set in *bad.
 __device__ inline int near_depth(double u, double sw, int N, unsigned numeric_flag, unsigned* bad) {
-  int steps = (int)ceil(20.1 / log(u + sw)) + 8;
+  // clamped in floating point: a point on the focal set (u + sw = 1, only
+  // reachable from inside the spheroid) or a NaN gives the capped depth
+  const double sd = ceil(20.1 / log(u + sw)) + 8.0;
+  int steps = sd < 200000.0 ? (int)sd : 200000;
   for (int off = 32; off >= 1; off >>= 1) steps = max(steps, __shfl_xor(steps, off, 64));
   steps = __builtin_amdgcn_readfirstlane(steps);
   if (steps > 100000) {

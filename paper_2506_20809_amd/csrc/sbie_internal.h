@@ -223,6 +223,14 @@ sbie_status join_side(sbie_geom* g, hipStream_t s);
 sbie_status apply_normal(sbie_geom* g, int op, int prec, const double* d_dens, double* d_out, hipStream_t s,
                          uint32_t parts, bool timed);
 
+// Transform input f and far records rec[g] = (node - centre, W dens, nu, 0)
+// (float in d_src for SBIE_MIXED, else double) for op SBIE_OP_SP (modified
+// basis, the records of S) or SBIE_OP_DP (those of D); then the forward
+// transform with the self coefficients of S'/D' in d_cself and the exterior
+// coefficients of S (lam_S c) resp. D (lam_D+ c) in d_E.
+sbie_status normal_records(sbie_geom* g, int op, int prec, const double* d_dens, hipStream_t s);
+sbie_status normal_expansions(sbie_geom* g, int op, int prec, hipStream_t s);
+
 // completed double-layer operator and its GMRES solve (solve.hip)
 double completion_eta(const Particle& P, int completion);
 

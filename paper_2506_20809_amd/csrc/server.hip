@@ -239,12 +239,12 @@ sbie_status run_apply(sbie_server* srv, sbie_session* s, Job* j, int lane, std::
   if (status) {
     SBIE_HIP(hipMemsetAsync(s->g->d_status, 0, sizeof(unsigned), st));
     SBIE_HIP(hipStreamSynchronize(st));
-    if (status & kStatNumeric) {
-      *err = "continued fraction for Q_N/Q_{N-1} did not converge at a near-field target";
-      return SBIE_E_NUMERIC;
+    if (status & kStatExterior) {
+      *err = "a near-field target lies inside its source spheroid";
+      return SBIE_E_OVERLAP;
     }
-    *err = "a near-field target lies inside its source spheroid";
-    return SBIE_E_OVERLAP;
+    *err = "continued fraction for Q_N/Q_{N-1} did not converge at a near-field target";
+    return SBIE_E_NUMERIC;
   }
   return SBIE_OK;
 }

@@ -1,0 +1,404 @@
+// Particle-to-target evaluation (Section 4, the particle-to-target variant of
+// Algorithm 1): S or D of a nodal density, and its gradient (Eq.
+// (dSLevalformula) and the same construction for D), at arbitrary points
+// outside every particle.  Each (target, source particle) pair is classified
+// on its own by the exact distance from the point to the surface: near
+// sources contribute their exterior expansion (value and derivatives in
+// (u, v, phi), mapped to the lab gradient), far ones the smooth quadrature.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "far_dev.h"
+#include "near_dev.h"
+#include "sbie_internal.h"
+
+namespace sbie {
+
+namespace {
+
+constexpr double kInv4Pi = 0.079577471545947667884441881686257181;
+constexpr double kHalfPi = 1.57079632679489661923132169163975144;
+
+inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+__global__ void k_targets_soa(const double* __restrict__ pts, int64_t n, double* __restrict__ tx,
+                              double* __restrict__ ty, double* __restrict__ tz) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  tx[t] = pts[3 * t];
+  ty[t] = pts[3 * t + 1];
+  tz[t] = pts[3 * t + 2];
+}
+
+// Distance from a meridian-plane point (rho, z >= 0) outside the ellipse
+// (A cos t, C sin t) to the ellipse.  The foot of the normal has t in
+// [0, pi/2] where g(t) = (A^2 - C^2) sin t cos t - rho A sin t + z C cos t
+// vanishes; g(0) >= 0 >= g(pi/2) and the root is unique outside the ellipse,
+// so 64 halvings of the bracket locate it to the resolution of t.
+__device__ inline double meridian_distance(double rho, double z, double A, double C) {
+  double lo = 0.0, hi = kHalfPi;
+  const double e = (A - C) * (A + C);
+  for (int it = 0; it < 64; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    double sn, cs;
+    sincos(mid, &sn, &cs);
+    const double gm = fma(e * sn, cs, fma(-rho * A, sn, z * C * cs));
+    if (gm > 0.0)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  double sn, cs;
+  sincos(0.5 * (lo + hi), &sn, &cs);
+  const double dr = rho - A * cs, dz = z - C * sn;
+  return sqrt(dr * dr + dz * dz);
+}
+
+// Near flags near[t][w] (bit b of word w: particle 32w + b) by the rule
+// distance < eta * diam(source); the circumsphere bound |x - c| - diam/2
+// settles most pairs without the exact distance.  A point inside a particle
+// sets kStatExterior.
+__global__ void k_classify_targets(const Particle* __restrict__ part, int M, int words, double eta,
+                                   const double* __restrict__ tx, const double* __restrict__ ty,
+                                   const double* __restrict__ tz, int64_t n, uint32_t* __restrict__ mask,
+                                   unsigned* status) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const double X0 = tx[t], X1 = ty[t], X2 = tz[t];
+  unsigned bad = 0u;
+  for (int w = 0; w < words; ++w) {
+    uint32_t bits = 0u;
+    for (int b = 0; b < 32; ++b) {
+      const int i = 32 * w + b;
+      if (i >= M) break;
+      const Particle& P = part[i];
+      const double d0 = X0 - P.c[0], d1 = X1 - P.c[1], d2 = X2 - P.c[2];
+      const double dc = sqrt(fma(d2, d2, fma(d1, d1, d0 * d0)));
+      const double lim = eta * P.diam;
+      if (dc - 0.5 * P.diam >= lim) continue;
+      const double b0 = P.R[0] * d0 + P.R[3] * d1 + P.R[6] * d2;
+      const double b1 = P.R[1] * d0 + P.R[4] * d1 + P.R[7] * d2;
+      const double b2 = P.R[2] * d0 + P.R[5] * d1 + P.R[8] * d2;
+      const double rho = sqrt(b0 * b0 + b1 * b1), z = fabs(b2);
+      if ((rho / P.A) * (rho / P.A) + (z / P.C) * (z / P.C) <= 1.0) {
+        bad |= kStatExterior;
+        bits |= 1u << b;
+        continue;
+      }
+      if (meridian_distance(rho, z, P.A, P.C) < lim) bits |= 1u << b;
+    }
+    mask[(size_t)t * words + w] = bits;
+  }
+  if (bad) atomicOr(status, bad);
+}
+
+// Near part: one wave per 64 targets.  The wave visits every particle that is
+// near to any of its lanes; all lanes evaluate the expansion (wave-uniform
+// recurrence depth), lanes whose target is not near that particle map a
+// stand-in point two diameters from its centre and discard the result.
+// out[4][n]: value and lab gradient.
+template <int PMAX>
+__global__ __launch_bounds__(64) void k_near_targets(
+    const Particle* __restrict__ part, const double* __restrict__ tx, const double* __restrict__ ty,
+    const double* __restrict__ tz, int64_t n, const uint32_t* __restrict__ mask, int words, int M,
+    const double* __restrict__ E, const double* __restrict__ lam, const double* __restrict__ ab,
+    const double* __restrict__ cd, const double* __restrict__ rcp, int p, unsigned* status,
+    double* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  const bool live = t < n;
+  const int64_t tt = live ? t : 0;
+  const double X0 = tx[tt], X1 = ty[tt], X2 = tz[tt];
+  const int K = (p + 1) * (p + 1), Kh = (p + 1) * (p + 2) / 2;
+  double v = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
+  unsigned bad = 0u;
+  for (int w = 0; w < words; ++w) {
+    const uint32_t mine = live ? mask[(size_t)tt * words + w] : 0u;
+    uint32_t all = mine;
+    for (int off = 32; off >= 1; off >>= 1) all |= (uint32_t)__shfl_xor((int)all, off, 64);
+    all = __builtin_amdgcn_readfirstlane(all);
+    while (all) {
+      const int b = __builtin_ctz(all);
+      all &= all - 1u;
+      const int i = 32 * w + b;
+      if (i >= M) break;
+      const bool use = (mine >> b) & 1u;
+      const Particle P = part[i];
+      const double px = use ? X0 : P.c[0] + 2.0 * P.diam;
+      const double py = use ? X1 : P.c[1];
+      const double pz = use ? X2 : P.c[2];
+      unsigned lb = 0u;
+      const SpheroidalPoint q = to_spheroidal(P, px, py, pz, true, &lb);
+      double Phi[1], Pu[1], Pv[1], Pp[1];
+      expansion_derivatives<PMAX, 1>(q, P.oblate != 0, E + (size_t)i * K, (size_t)K, lam + (size_t)i * Kh * 4, ab,
+                                     cd, rcp, p, &lb, Phi, Pu, Pv, Pp);
+      double gr[3];
+      lab_gradient(P, q.u, q.sw, q.v, q.sv, q.c1, q.s1, Pu[0], Pv[0], Pp[0], gr);
+      if (use) {
+        v += Phi[0];
+        g0 += gr[0];
+        g1 += gr[1];
+        g2 += gr[2];
+        bad |= lb;
+      }
+    }
+  }
+  if (bad) atomicOr(status, bad);
+  if (live) {
+    out[t] = v;
+    out[n + t] = g0;
+    out[2 * n + t] = g1;
+    out[3 * n + t] = g2;
+  }
+}
+
+// Far part, with d = x - y and q = W dens (records (node - centre, q, nu)):
+//  S  value q/r,            gradient -q d/r^3
+//  D  value q (nu.d)/r^3,   gradient q (nu/r^3 - 3 (nu.d) d/r^5)
+// Target tiles x source splits (split fastest); coordinates relative to the
+// source centre; each source particle's tile sum is added per target under
+// its far flag with TwoSum.  partial[split][4][n].
+template <typename R, int OP, int TPT>
+__global__ __launch_bounds__(256) void k_far_targets(const R* __restrict__ rec, const Particle* __restrict__ part,
+                                                     const double* __restrict__ tx, const double* __restrict__ ty,
+                                                     const double* __restrict__ tz, int64_t n,
+                                                     const uint32_t* __restrict__ mask, int words, int M, int T,
+                                                     int nsplit, double* __restrict__ partial) {
+  const int split = blockIdx.x % nsplit, tile = blockIdx.x / nsplit;
+  const int s0 = (int)((int64_t)M * split / nsplit), s1 = (int)((int64_t)M * (split + 1) / nsplit);
+  double px[TPT], py[TPT], pz[TPT];
+  int64_t tq[TPT];
+  bool live[TPT];
+  R acc[TPT][4], lo[TPT][4];
+#pragma unroll
+  for (int k = 0; k < TPT; ++k) {
+    const int64_t t = (int64_t)tile * 256 * TPT + k * 256 + threadIdx.x;
+    live[k] = t < n;
+    tq[k] = live[k] ? t : 0;
+    px[k] = tx[tq[k]];
+    py[k] = ty[tq[k]];
+    pz[k] = tz[tq[k]];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[k][c] = lo[k][c] = R(0);
+  }
+  for (int s = s0; s < s1; ++s) {
+    bool need[TPT];
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < TPT; ++k) {
+      need[k] = live[k] && !((mask[(size_t)tq[k] * words + (s >> 5)] >> (s & 31)) & 1u);
+      any |= need[k];
+    }
+    if (!__any(any)) continue;
+    const double cx = part[s].c[0], cy = part[s].c[1], cz = part[s].c[2];
+    R Dx[TPT], Dy[TPT], Dz[TPT], tmp[TPT][4];
+#pragma unroll
+    for (int k = 0; k < TPT; ++k) {
+      Dx[k] = (R)(px[k] - cx);
+      Dy[k] = (R)(py[k] - cy);
+      Dz[k] = (R)(pz[k] - cz);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) tmp[k][c] = R(0);
+    }
+    const R* rs = rec + (size_t)s * T * 8;
+    for (int j = 0; j < T; ++j) {
+      const R* r = rs + (size_t)j * 8;
+      const R ox = r[0], oy = r[1], oz = r[2], qq = r[3];
+#pragma unroll
+      for (int k = 0; k < TPT; ++k) {
+        const R dx = Dx[k] - ox, dy = Dy[k] - oy, dz = Dz[k] - oz;
+        const R r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+        const R ri = rsq_t<R>(r2);
+        const R ri2 = ri * ri;
+        const R a = qq * ri * ri2;  // q / r^3
+        if (OP == SBIE_OP_S) {
+          tmp[k][0] = fma(qq, ri, tmp[k][0]);
+          tmp[k][1] = fma(-a, dx, tmp[k][1]);
+          tmp[k][2] = fma(-a, dy, tmp[k][2]);
+          tmp[k][3] = fma(-a, dz, tmp[k][3]);
+        } else {
+          const R m0 = r[4], m1 = r[5], m2 = r[6];
+          const R nd = fma(m2, dz, fma(m1, dy, m0 * dx));
+          const R bb = R(-3) * a * nd * ri2;
+          tmp[k][0] = fma(a, nd, tmp[k][0]);
+          tmp[k][1] = fma(a, m0, fma(bb, dx, tmp[k][1]));
+          tmp[k][2] = fma(a, m1, fma(bb, dy, tmp[k][2]));
+          tmp[k][3] = fma(a, m2, fma(bb, dz, tmp[k][3]));
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < TPT; ++k)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) two_sum_add(acc[k][c], lo[k][c], need[k] ? tmp[k][c] : R(0));
+  }
+#pragma unroll
+  for (int k = 0; k < TPT; ++k) {
+    if (!live[k]) continue;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      partial[((size_t)split * 4 + c) * n + tq[k]] = ((double)acc[k][c] + (double)lo[k][c]) * kInv4Pi;
+  }
+}
+
+// value = near + far partials (split order); gradient likewise, written [n][3].
+__global__ void k_targets_combine(const double* __restrict__ nearv, const double* __restrict__ partial, int nsplit,
+                                  int64_t n, double* __restrict__ val, double* __restrict__ grad) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  double o[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    double f = 0.0;
+    for (int s = 0; s < nsplit; ++s) f += partial[((size_t)s * 4 + c) * n + t];
+    o[c] = nearv[(size_t)c * n + t] + f;
+  }
+  val[t] = o[0];
+  if (grad) {
+    grad[3 * t] = o[1];
+    grad[3 * t + 1] = o[2];
+    grad[3 * t + 2] = o[3];
+  }
+}
+
+struct DevMem {
+  void* p = nullptr;
+  ~DevMem() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+sbie_status dev_alloc(DevMem& b, size_t bytes) {
+  if (hipMalloc(&b.p, std::max<size_t>(bytes, 256)) != hipSuccess) {
+    b.p = nullptr;
+    (void)hipGetLastError();
+    set_error("device allocation of " + std::to_string(bytes) + " bytes for the target evaluation failed");
+    return SBIE_E_NOMEM;
+  }
+  return SBIE_OK;
+}
+
+template <typename R, int OP>
+void launch_far_targets(const sbie_geom* g, const double* tx, const double* ty, const double* tz, int64_t n,
+                        const uint32_t* mask, int nsplit, double* partial, hipStream_t s) {
+  constexpr int TPT = 2;
+  hipLaunchKernelGGL((k_far_targets<R, OP, TPT>), dim3(cdiv(n, 256 * TPT) * nsplit), dim3(256), 0, s,
+                     reinterpret_cast<const R*>(g->d_src), g->d_part, tx, ty, tz, n, mask, g->excl_words, g->M,
+                     g->T, nsplit, partial);
+}
+
+template <int PMAX>
+void launch_near_targets(const sbie_geom* g, const double* tx, const double* ty, const double* tz, int64_t n,
+                         const uint32_t* mask, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_near_targets<PMAX>, dim3(cdiv(n, 64)), dim3(64), 0, s, g->d_part, tx, ty, tz, n, mask,
+                     g->excl_words, g->M, g->d_E, g->d_lam, g->d_ab, g->d_cd, g->d_rcp, g->p, g->d_status, out);
+}
+
+// S or D at n device points [n][3] into val [n] and, if non-NULL, grad [n][3].
+sbie_status eval_targets(sbie_geom* g, int op, int prec, const double* d_dens, int64_t n, const double* d_pts,
+                         double* d_val, double* d_grad, hipStream_t s) {
+  const int nop = op == SBIE_OP_S ? SBIE_OP_SP : SBIE_OP_DP;  // records and exterior coefficients of S / D
+  sbie_status st = normal_records(g, nop, prec, d_dens, s);
+  if (st) return st;
+  if ((st = normal_expansions(g, nop, prec, s))) return st;
+  const int words = g->excl_words;
+  const int64_t tiles = (n + 511) / 512;
+  const int nsplit = (int)std::min<int64_t>({(int64_t)g->M, 64, std::max<int64_t>(1, (2048 + tiles - 1) / tiles)});
+  DevMem xyz, mask, nearv, partial;
+  if ((st = dev_alloc(xyz, sizeof(double) * 3 * (size_t)n))) return st;
+  if ((st = dev_alloc(mask, sizeof(uint32_t) * (size_t)n * words))) return st;
+  if ((st = dev_alloc(nearv, sizeof(double) * 4 * (size_t)n))) return st;
+  if ((st = dev_alloc(partial, sizeof(double) * 4 * (size_t)nsplit * n))) return st;
+  double* tx = (double*)xyz.p;
+  double* ty = tx + n;
+  double* tz = ty + n;
+  hipLaunchKernelGGL(k_targets_soa, dim3(cdiv(n, 256)), dim3(256), 0, s, d_pts, n, tx, ty, tz);
+  SBIE_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_classify_targets, dim3(cdiv(n, 256)), dim3(256), 0, s, g->d_part, g->M, words, g->eta, tx,
+                     ty, tz, n, (uint32_t*)mask.p, g->d_status);
+  SBIE_HIP(hipGetLastError());
+  if (g->p <= 8)
+    launch_near_targets<8>(g, tx, ty, tz, n, (const uint32_t*)mask.p, (double*)nearv.p, s);
+  else if (g->p <= 16)
+    launch_near_targets<16>(g, tx, ty, tz, n, (const uint32_t*)mask.p, (double*)nearv.p, s);
+  else
+    launch_near_targets<32>(g, tx, ty, tz, n, (const uint32_t*)mask.p, (double*)nearv.p, s);
+  SBIE_HIP(hipGetLastError());
+  const bool mixed = prec == SBIE_MIXED;
+  const uint32_t* mk = (const uint32_t*)mask.p;
+  double* pa = (double*)partial.p;
+  if (op == SBIE_OP_S)
+    mixed ? launch_far_targets<float, SBIE_OP_S>(g, tx, ty, tz, n, mk, nsplit, pa, s)
+          : launch_far_targets<double, SBIE_OP_S>(g, tx, ty, tz, n, mk, nsplit, pa, s);
+  else
+    mixed ? launch_far_targets<float, SBIE_OP_D>(g, tx, ty, tz, n, mk, nsplit, pa, s)
+          : launch_far_targets<double, SBIE_OP_D>(g, tx, ty, tz, n, mk, nsplit, pa, s);
+  SBIE_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_targets_combine, dim3(cdiv(n, 256)), dim3(256), 0, s, (const double*)nearv.p, pa, nsplit, n,
+                     d_val, d_grad);
+  SBIE_HIP(hipGetLastError());
+  // the work buffers are freed on return
+  SBIE_HIP(hipStreamSynchronize(s));
+  return SBIE_OK;
+}
+
+}  // namespace
+
+}  // namespace sbie
+
+using namespace sbie;
+
+extern "C" sbie_status sbie_eval_targets(sbie_geom* g, sbie_op op, sbie_precision prec, const double* density,
+                                         int64_t npts, const double* pts, double* val, double* grad, void* stream,
+                                         uint32_t flags) {
+  if (!g) {
+    set_error("geometry is NULL");
+    return SBIE_E_INVALID;
+  }
+  if (op != SBIE_OP_S && op != SBIE_OP_D) {
+    set_error("target evaluation takes SBIE_OP_S or SBIE_OP_D");
+    return SBIE_E_INVALID;
+  }
+  if (prec != SBIE_FP64 && prec != SBIE_MIXED) {
+    set_error("unknown precision");
+    return SBIE_E_INVALID;
+  }
+  if (npts < 0 || npts > ((int64_t)1 << 31)) {
+    set_error("npts must be in [0, 2^31]");
+    return SBIE_E_INVALID;
+  }
+  if (npts == 0) return SBIE_OK;
+  if (!density || !pts || !val) {
+    set_error("density, pts or val is NULL");
+    return SBIE_E_INVALID;
+  }
+  SBIE_HIP(hipSetDevice(g->ctx->device));
+  hipStream_t s = stream ? (hipStream_t)stream : g->ctx->stream;
+  const int64_t N = g->N;
+  const bool devptr = (flags & SBIE_DEVICE_PTRS) != 0;
+  sbie_status st;
+  DevMem io;
+  const double* dd = density;
+  const double* dp = pts;
+  double* dv = val;
+  double* dg = grad;
+  if (!devptr) {
+    if ((st = dev_alloc(io, sizeof(double) * ((size_t)N + 7 * (size_t)npts)))) return st;
+    double* b = (double*)io.p;
+    SBIE_HIP(hipMemcpyAsync(b, density, sizeof(double) * N, hipMemcpyHostToDevice, s));
+    SBIE_HIP(hipMemcpyAsync(b + N, pts, sizeof(double) * 3 * npts, hipMemcpyHostToDevice, s));
+    dd = b;
+    dp = b + N;
+    dv = b + N + 3 * npts;
+    dg = grad ? b + N + 4 * npts : nullptr;
+  }
+  if ((st = eval_targets(g, (int)op, (int)prec, dd, npts, dp, dv, dg, s))) return st;
+  if (!devptr) {
+    SBIE_HIP(hipMemcpyAsync(val, dv, sizeof(double) * npts, hipMemcpyDeviceToHost, s));
+    if (grad) SBIE_HIP(hipMemcpyAsync(grad, dg, sizeof(double) * 3 * npts, hipMemcpyDeviceToHost, s));
+    SBIE_HIP(hipStreamSynchronize(s));
+  }
+  return sbie_geom_sync(g, s);
+}

@@ -64,10 +64,11 @@ def lib():
                                    dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int, dp, dp, dp, dp]
         L.orc_eval_exterior.argtypes = [dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                         dp, dp, ctypes.c_int, dp]
-        L.orc_stokes_apply.argtypes = [dp, dp, dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp, dp,
-                                       dp, dp]
+        L.orc_stokes_apply.argtypes = [dp, dp, dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp,
+                                       ctypes.c_int, dp, dp, dp, dp]
         L.orc_stokes_apply_at.argtypes = [dp, dp, dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp,
-                                          ctypes.POINTER(ctypes.c_int64), ctypes.c_int, dp, dp, dp, dp]
+                                          ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_int, dp, dp, dp,
+                                          dp]
         L.orc_stokes_single.argtypes = [dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp,
                                         ctypes.c_int, ctypes.c_int, dp]
         L.orc_single_layer_grad.argtypes = [dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp,
@@ -248,30 +249,35 @@ def eval_exterior(spheroid, p: int, op: int, density: np.ndarray, pts: np.ndarra
     return out
 
 
-def stokes_apply(geom, p: int, density: np.ndarray, eta: float = 1.0, parts: bool = False):
+def stokes_apply(geom, p: int, density: np.ndarray, eta: float = 1.0, parts: bool = False,
+                 pressure: bool = False):
     """Stokes single layer (viscosity 1) at every node; density [3, N].  With
-    parts=True returns (u, u_self, u_near, u_far), each [3, N]."""
+    pressure=True a fourth row holds the pressure (exterior limit on the
+    surface).  With parts=True returns (u, u_self, u_near, u_far)."""
     c, q, A, C = _geom_arrays(geom)
     M = len(A)
     N = M * (p + 1) * (2 * p + 2)
+    nc = 4 if pressure else 3
     dens = _f64(density).reshape(3, N)
-    us, un, uf, u = (np.zeros((3, N)) for _ in range(4))
-    _check(lib().orc_stokes_apply(_p(c), _p(q), _p(A), _p(C), M, int(p), float(eta), _p(dens), _p(us), _p(un),
-                                  _p(uf), _p(u)), "stokes_apply")
+    us, un, uf, u = (np.zeros((nc, N)) for _ in range(4))
+    _check(lib().orc_stokes_apply(_p(c), _p(q), _p(A), _p(C), M, int(p), float(eta), _p(dens), nc, _p(us),
+                                  _p(un), _p(uf), _p(u)), "stokes_apply")
     return (u, us, un, uf) if parts else u
 
 
-def stokes_apply_at(geom, p: int, density: np.ndarray, targets, eta: float = 1.0):
-    """Eq. (stokes) at selected node indices: (u, u_self, u_near, u_far), each [3, len(targets)]."""
+def stokes_apply_at(geom, p: int, density: np.ndarray, targets, eta: float = 1.0, pressure: bool = False):
+    """Eq. (stokes) at selected node indices: (u, u_self, u_near, u_far), each
+    [3 or 4, len(targets)] (the fourth row the pressure)."""
     c, q, A, C = _geom_arrays(geom)
     M = len(A)
     N = M * (p + 1) * (2 * p + 2)
+    nc = 4 if pressure else 3
     dens = _f64(density).reshape(3, N)
     tg = np.ascontiguousarray(targets, dtype=np.int64)
     n = len(tg)
-    us, un, uf, u = (np.zeros((3, n)) for _ in range(4))
+    us, un, uf, u = (np.zeros((nc, n)) for _ in range(4))
     _check(lib().orc_stokes_apply_at(_p(c), _p(q), _p(A), _p(C), M, int(p), float(eta), _p(dens),
-                                     tg.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n, _p(us), _p(un),
+                                     tg.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n, nc, _p(us), _p(un),
                                      _p(uf), _p(u)), "stokes_apply_at")
     return u, us, un, uf
 

@@ -1153,21 +1153,24 @@ static int stokes_coefficients(const geometry* g, int i, const double* density, 
 /* Eq. (stokes) with viscosity 1 and origin c_i:
    u_k = 1/2 { S[sigma_k] - sum_j (x - c_i)_j d_k S[sigma_j] + d_k S[rho_i] } */
 static void stokes_combine(const particle* pt, const double x[3], const double* val,
-                           const double* grad, double out[3]) {
+                           const double* grad, double out[4]) {
   for (int k = 0; k < 3; ++k) {
     double s = val[k] + grad[3 * 3 + k];
     for (int j = 0; j < 3; ++j) s -= (x[j] - pt->c[j]) * grad[3 * j + k];
     out[k] = 0.5 * s;
   }
+  /* pressure with the kernel (1/4pi) r/|r|^3, r = x - y: p = -sum_j d_j S[sigma_j]
+     (the printed identity sum_j e_j . grad S[sigma_j] has the opposite sign) */
+  out[3] = -(grad[0] + grad[4] + grad[8]);
 }
 
-/* Self, near and far parts of Eq. (stokes) at node gt: the exterior-limit
-   expansions of the target's own particle at its node, the neighbours'
-   exterior expansions (ascending source index), and the Stokeslet
-   (1/8pi)(I/r + r r^T/r^3) over the far sources by smooth quadrature,
-   Neumaier-compensated. */
+/* Self, near and far parts of Eq. (stokes) at node gt, and of the pressure
+   (component 3): the exterior-limit expansions of the target's own particle
+   at its node, the neighbours' exterior expansions (ascending source index),
+   and the Stokeslet (1/8pi)(I/r + r r^T/r^3) with its pressure (1/4pi) r/r^3
+   over the far sources by smooth quadrature, Neumaier-compensated. */
 static int stokes_node(const geometry* g, const double* E4, const double* density, size_t gt,
-                       double us[3], double un[3], double uf[3]) {
+                       double us[4], double un[4], double uf[4]) {
   int M = g->M, T = g->T, K = g->K, p = g->p, Nphi = 2 * p + 2;
   size_t N = (size_t)g->N;
   int j = (int)(gt / T), loc = (int)(gt - (size_t)j * T);
@@ -1178,18 +1181,18 @@ static int stokes_node(const geometry* g, const double* E4, const double* densit
                           2.0 * PI * kp / Nphi, 0, val, grad);
   if (rc) return rc;
   stokes_combine(&g->pt[j], x, val, grad, us);
-  for (int k = 0; k < 3; ++k) un[k] = 0.0;
+  for (int k = 0; k < 4; ++k) un[k] = 0.0;
   for (int i = 0; i < M; ++i) {
     if (!g->near[(size_t)i * M + j]) continue;
-    double xb[3], uu, vv, ph, o[3];
+    double xb[3], uu, vv, ph, o[4];
     lab_to_body(&g->pt[i], x, xb);
     body_to_spheroidal(&g->pt[i], xb, &uu, &vv, &ph);
     rc = expansion_grad(&g->pt[i], p, 4, E4 + (size_t)i * 4 * K, uu, vv, ph, 0, val, grad);
     if (rc) return rc;
     stokes_combine(&g->pt[i], x, val, grad, o);
-    for (int k = 0; k < 3; ++k) un[k] += o[k];
+    for (int k = 0; k < 4; ++k) un[k] += o[k];
   }
-  double sum[3] = {0, 0, 0}, comp[3] = {0, 0, 0};
+  double sum[4] = {0, 0, 0, 0}, comp[4] = {0, 0, 0, 0};
   for (int i = 0; i < M; ++i) {
     if (i == j || g->near[(size_t)i * M + j]) continue;
     for (int q = 0; q < T; ++q) {
@@ -1199,8 +1202,9 @@ static int stokes_node(const geometry* g, const double* E4, const double* densit
       double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2], r = sqrt(r2);
       double sg[3] = {density[gs], density[N + gs], density[2 * N + gs]};
       double dots = d[0] * sg[0] + d[1] * sg[1] + d[2] * sg[2];
-      for (int k = 0; k < 3; ++k) {
-        double term = g->W[gs] * (sg[k] / r + d[k] * dots / (r2 * r)) / (8.0 * PI);
+      for (int k = 0; k < 4; ++k) {
+        double term = k < 3 ? g->W[gs] * (sg[k] / r + d[k] * dots / (r2 * r)) / (8.0 * PI)
+                            : g->W[gs] * dots / (r2 * r) / (4.0 * PI);
         double ts = sum[k] + term;
         if (fabs(sum[k]) >= fabs(term)) comp[k] += (sum[k] - ts) + term;
         else comp[k] += (term - ts) + sum[k];
@@ -1208,7 +1212,7 @@ static int stokes_node(const geometry* g, const double* E4, const double* densit
       }
     }
   }
-  for (int k = 0; k < 3; ++k) uf[k] = sum[k] + comp[k];
+  for (int k = 0; k < 4; ++k) uf[k] = sum[k] + comp[k];
   return ORC_OK;
 }
 
@@ -1228,9 +1232,12 @@ static int stokes_all_coefficients(const geometry* g, const double* density, con
   return err;
 }
 
+/* ncomp = 3: velocity [3][N]; ncomp = 4: velocity and pressure [4][N]
+   (the pressure on the surface is its exterior limit). */
 int orc_stokes_apply(const double* centres, const double* quats, const double* A,
-                     const double* C, int M, int p, double eta, const double* density,
+                     const double* C, int M, int p, double eta, const double* density, int ncomp,
                      double* u_self, double* u_near, double* u_far, double* u) {
+  if (ncomp != 3 && ncomp != 4) return ORC_E_INVALID;
   geometry g;
   int rc = build_geometry(centres, quats, A, C, M, p, eta, &g);
   if (rc) return rc;
@@ -1241,14 +1248,14 @@ int orc_stokes_apply(const double* centres, const double* quats, const double* A
 #pragma omp parallel for schedule(dynamic, 64)
   for (int64_t gt = 0; gt < (int64_t)N; ++gt) {
     if (rc || err) continue;
-    double us[3], un[3], uf[3];
+    double us[4], un[4], uf[4];
     int r = stokes_node(&g, E4, density, (size_t)gt, us, un, uf);
     if (r) {
 #pragma omp atomic write
       err = r;
       continue;
     }
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < ncomp; ++k) {
       size_t q = k * N + (size_t)gt;
       if (u_self) u_self[q] = us[k];
       if (u_near) u_near[q] = un[k];
@@ -1266,8 +1273,9 @@ int orc_stokes_apply(const double* centres, const double* quats, const double* A
    [3][ntg].  Only the target particles and their near neighbours are expanded. */
 int orc_stokes_apply_at(const double* centres, const double* quats, const double* A,
                         const double* C, int M, int p, double eta, const double* density,
-                        const int64_t* targets, int ntg, double* out_self, double* out_near,
+                        const int64_t* targets, int ntg, int ncomp, double* out_self, double* out_near,
                         double* out_far, double* out) {
+  if (ncomp != 3 && ncomp != 4) return ORC_E_INVALID;
   geometry g;
   int rc = build_geometry(centres, quats, A, C, M, p, eta, &g);
   if (rc) return rc;
@@ -1285,14 +1293,14 @@ int orc_stokes_apply_at(const double* centres, const double* quats, const double
 #pragma omp parallel for schedule(dynamic)
   for (int t = 0; t < ntg; ++t) {
     if (rc || err) continue;
-    double us[3], un[3], uf[3];
+    double us[4], un[4], uf[4];
     int r = stokes_node(&g, E4, density, (size_t)targets[t], us, un, uf);
     if (r) {
 #pragma omp atomic write
       err = r;
       continue;
     }
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < ncomp; ++k) {
       size_t q = (size_t)k * ntg + t;
       if (out_self) out_self[q] = us[k];
       if (out_near) out_near[q] = un[k];
@@ -1336,7 +1344,11 @@ int orc_stokes_single(const double* centre, const double* quat, double A, double
       ph = 2.0 * PI * kp / Nphi;
     }
     rc = expansion_grad(&g.pt[0], p, 4, E4, uu, vv, ph, interior, val, grad);
-    if (!rc) stokes_combine(&g.pt[0], x, val, grad, out + 3 * t);
+    if (!rc) {
+      double o[4];
+      stokes_combine(&g.pt[0], x, val, grad, o);
+      for (int k = 0; k < 3; ++k) out[3 * t + k] = o[k];
+    }
   }
   free(E4);
   free_geometry(&g);

@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
+import workloads
 from tests import _brute as B
 from tests.test_oracle_pins import SHAPES, _exterior_points, _one
 
@@ -223,3 +224,77 @@ def test_stokes_apply_at_matches_whole_apply():
     at = oracle.stokes_apply_at(g, p, dens, tg)
     for a, b in zip(at, full):
         assert np.array_equal(a, b[:, tg])
+
+
+def _translating_traction(geom, p, F):
+    """f_i = F_i h / (4 pi A^2 C) on particle i: the translating-ellipsoid
+    traction, i.e. F_i times the equilibrium-charge density of a unit charge."""
+    from workloads import quat_rot
+
+    xyz, nrm, _ = oracle.grid(geom, p)
+    M, T = len(geom["A"]), (p + 1) * (2 * p + 2)
+    dens = np.zeros((3, M * T))
+    for i in range(M):
+        c, R, A, C = geom["centers"][i], quat_rot(geom["quats"][i]), geom["A"][i], geom["C"][i]
+        b = (xyz[i * T:(i + 1) * T] - c) @ R
+        h = 1.0 / (4 * np.pi * A * A * C * np.sqrt((b[:, 0] ** 2 + b[:, 1] ** 2) / A ** 4 + b[:, 2] ** 2 / C ** 4))
+        dens[:, i * T:(i + 1) * T] = np.outer(F[i], h)
+    return dens, xyz, nrm
+
+
+def _grad_u(c, R, A, C, x):
+    """Lab gradient of the spheroidal coordinate u of particle (c, R, A, C) at x,
+    from the distances to the foci (prolate) or the focal ring (oblate); also
+    returns the focal half-distance a and w = u^2 -+ 1."""
+    a = np.sqrt(abs(A * A - C * C))
+    b = (x - c) @ R
+    if C > A:
+        f1 = np.array([0.0, 0.0, a])
+        r1, r2 = np.linalg.norm(b - f1, axis=1), np.linalg.norm(b + f1, axis=1)
+        u = (r1 + r2) / (2 * a)
+        gb = ((b - f1) / r1[:, None] + (b + f1) / r2[:, None]) / (2 * a)
+        w = u * u - 1
+    else:
+        rho, z = np.sqrt(b[:, 0] ** 2 + b[:, 1] ** 2), b[:, 2]
+        f1, f2 = np.sqrt((rho + a) ** 2 + z ** 2), np.sqrt((rho - a) ** 2 + z ** 2)
+        ch = (f1 + f2) / (2 * a)
+        u = np.sqrt(ch * ch - 1)
+        dr, dz = ((rho + a) / f1 + (rho - a) / f2) / (2 * a), (z / f1 + z / f2) / (2 * a)
+        gb = (ch / u)[:, None] * np.stack([dr * b[:, 0] / rho, dr * b[:, 1] / rho, dz], 1)
+        w = u * u + 1
+    return gb @ R.T, a, w
+
+
+@pytest.mark.parametrize("p", [8, 16])
+def test_stokes_pressure_conductor_closed_form(p):
+    """Pressure of the Stokes single layer, kernel (1/4pi) r/|r|^3.  With the
+    translating-ellipsoid tractions f_i = F_i rho_i, each S[f_ij] is F_ij times
+    the potential of a unit charge on the conducting spheroid, (1/(4 pi a))
+    arccoth(u) (prolate) or arccot(u) (oblate) outside and constant inside.
+    So on particle j the exterior-limit pressure is f_j . nu (Gauss: the
+    field just outside a conductor is its charge density along the normal) plus
+    sum_{i != j} F_i . grad u_i / (4 pi a_i (u_i^2 -+ 1)) from the others, near
+    and far.  The printed identity sum_j e_j . grad S[sigma_j] would give the
+    negative."""
+    from workloads import quat_rot
+
+    geom = workloads.three_spheroids(True, seed=3)
+    near = oracle.classify(geom)
+    assert near.sum() > 0 and (near + np.eye(3, dtype=near.dtype) == 0).sum() > 0
+    F = np.array([[1.0, 0.3, -0.5], [-0.4, 0.8, 0.2], [0.1, -0.6, 0.9]])
+    dens, xyz, nrm = _translating_traction(geom, p, F)
+    u = oracle.stokes_apply(geom, p, dens, pressure=True)
+    T = (p + 1) * (2 * p + 2)
+    ref = np.zeros(3 * T)
+    for j in range(3):
+        sl = slice(j * T, (j + 1) * T)
+        ref[sl] = np.sum(dens[:, sl].T * nrm[sl], axis=1)
+        for i in range(3):
+            if i != j:
+                g, a, w = _grad_u(geom["centers"][i], quat_rot(geom["quats"][i]), geom["A"][i], geom["C"][i],
+                                  xyz[sl])
+                ref[sl] += (g @ F[i]) / (4 * np.pi * a * w)
+    err = np.max(np.abs(u[3] - ref)) / np.max(np.abs(ref))
+    assert err < (1e-11 if p == 8 else 1e-13), err
+    # the velocity rows are those of the velocity-only apply
+    assert np.array_equal(u[:3], oracle.stokes_apply(geom, p, dens))

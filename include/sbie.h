@@ -64,8 +64,11 @@ typedef enum {
   SBIE_OP_STOKES_S = 2, /* Stokes single layer through Laplace potentials, Eq. (stokes); nrhs = 3 */
   SBIE_OP_SP = 3,       /* S': derivative of the single layer along the target's outward normal,
                            principal value on the surface (Section 3.3, Theorem 3) */
-  SBIE_OP_DP = 4        /* D': derivative of the double layer along the target's outward normal
+  SBIE_OP_DP = 4,       /* D': derivative of the double layer along the target's outward normal
                            (continuous across the surface; Section 3.3) */
+  SBIE_OP_STOKES_SP = 5 /* Stokes single layer and its pressure, kernel (1/4pi) r/|r|^3 (Section 4.3):
+                           nrhs = 3, potential [4][N], the fourth row the pressure, on the surface
+                           its exterior limit */
 } sbie_op;
 
 typedef enum {

@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsbie.so")
 
-SBIE_OP_S, SBIE_OP_D, SBIE_OP_STOKES_S, SBIE_OP_SP, SBIE_OP_DP = 0, 1, 2, 3, 4
+SBIE_OP_S, SBIE_OP_D, SBIE_OP_STOKES_S, SBIE_OP_SP, SBIE_OP_DP, SBIE_OP_STOKES_SP = 0, 1, 2, 3, 4, 5
 SBIE_FP64, SBIE_MIXED = 0, 1
 SBIE_DEVICE_PTRS = 0x1
 SBIE_TIMING = 0x2
@@ -223,13 +223,15 @@ class Geometry:
 
     def apply(self, op: int, density, precision: int = SBIE_FP64, parts: int = SBIE_PARTS_ALL, out=None,
               stream=None, timing: bool = False):
-        """Apply S or D.  density: torch CUDA float64 tensor [nrhs, N] or [N] (device
-        pointers, on the current stream), or a numpy array (host pointers, synchronous)."""
+        """Apply S, D, S', D' or the Stokes single layer.  density: torch CUDA float64
+        tensor [nrhs, N] or [N] (device pointers, on the current stream), or a numpy
+        array (host pointers, synchronous).  SBIE_OP_STOKES_SP returns [4, N]
+        (velocity, then pressure)."""
         flags = int(parts) | (SBIE_TIMING if timing else 0)
         if isinstance(density, np.ndarray):
             d = np.ascontiguousarray(density, dtype=np.float64)
             nrhs = 1 if d.ndim == 1 else d.shape[0]
-            o = np.zeros_like(d)
+            o = np.zeros((4, self.N)) if op == SBIE_OP_STOKES_SP else np.zeros_like(d)
             _check(lib().sbie_apply(self._h, int(op), int(precision), nrhs, d.ctypes.data, o.ctypes.data, None,
                                     flags))
             return o
@@ -241,7 +243,8 @@ class Geometry:
         if density.numel() != nrhs * self.N:
             raise ValueError(f"density has {density.numel()} entries, expected {nrhs} x {self.N}")
         if out is None:
-            out = torch.empty_like(density)
+            out = (torch.empty((4, self.N), dtype=torch.float64, device=density.device)
+                   if op == SBIE_OP_STOKES_SP else torch.empty_like(density))
         if stream is None:
             stream = torch.cuda.current_stream(density.device)
         if stream.cuda_stream == 0:

@@ -258,11 +258,13 @@ sbie_status sbie_geom_near_pairs(const sbie_geom* g, int32_t* src, int32_t* dst,
 sbie_status sbie_apply(sbie_geom* g, sbie_op op, sbie_precision prec, int32_t nrhs, const double* density,
                        double* potential, void* stream, uint32_t flags) {
   if (!g) return invalid("geometry is NULL");
-  if (op != SBIE_OP_S && op != SBIE_OP_D && op != SBIE_OP_STOKES_S && op != SBIE_OP_SP && op != SBIE_OP_DP)
+  if (op != SBIE_OP_S && op != SBIE_OP_D && op != SBIE_OP_STOKES_S && op != SBIE_OP_SP && op != SBIE_OP_DP &&
+      op != SBIE_OP_STOKES_SP)
     return invalid("unknown operator");
   if (prec != SBIE_FP64 && prec != SBIE_MIXED) return invalid("unknown precision");
   if (nrhs < 1 || nrhs > 16) return invalid("nrhs must be in [1, 16]");
-  if (op == SBIE_OP_STOKES_S && nrhs != 3) return invalid("the Stokes single layer takes nrhs = 3");
+  if ((op == SBIE_OP_STOKES_S || op == SBIE_OP_STOKES_SP) && nrhs != 3)
+    return invalid("the Stokes single layer takes nrhs = 3");
   if (!density || !potential) return invalid("density or potential is NULL");
   SBIE_HIP(hipSetDevice(g->ctx->device));
   uint32_t parts = flags & SBIE_PARTS_ALL;
@@ -271,8 +273,10 @@ sbie_status sbie_apply(sbie_geom* g, sbie_op op, sbie_precision prec, int32_t nr
   const bool timed = (flags & SBIE_TIMING) != 0;
   hipStream_t s = stream ? (hipStream_t)stream : g->ctx->stream;
   const int64_t N = g->N;
-  if (op == SBIE_OP_STOKES_S) {
-    // the three components of the density in, the three velocity components out
+  if (op == SBIE_OP_STOKES_S || op == SBIE_OP_STOKES_SP) {
+    // the three components of the density in, the three velocity components
+    // (and the pressure) out
+    const int nout = op == SBIE_OP_STOKES_SP ? 4 : 3;
     const double* din = density;
     double* dout = potential;
     if (!devptr) {
@@ -283,9 +287,9 @@ sbie_status sbie_apply(sbie_geom* g, sbie_op op, sbie_precision prec, int32_t nr
       din = io;
       dout = io + 3 * N;
     }
-    sbie_status st = apply_stokes(g, (int)prec, din, dout, s, parts, timed);
+    sbie_status st = apply_stokes(g, (int)prec, din, dout, s, parts, timed, op == SBIE_OP_STOKES_SP);
     if (st != SBIE_OK) return st;
-    if (!devptr) SBIE_HIP(hipMemcpyAsync(potential, dout, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, s));
+    if (!devptr) SBIE_HIP(hipMemcpyAsync(potential, dout, sizeof(double) * nout * N, hipMemcpyDeviceToHost, s));
     if (!stream || !devptr) return sbie_geom_sync(g, s);
     return SBIE_OK;
   }

@@ -234,10 +234,12 @@ sbie_status normal_expansions(sbie_geom* g, int op, int prec, hipStream_t s);
 // completed double-layer operator and its GMRES solve (solve.hip)
 double completion_eta(const Particle& P, int completion);
 
-// Stokes single layer (stokes.hip); density and output [3][N]
+// Stokes single layer (stokes.hip); density [3][N], output [3][N], or [4][N]
+// with the pressure
 sbie_status apply_stokes(sbie_geom* g, int prec, const double* d_dens, double* d_out, hipStream_t s,
-                         uint32_t parts, bool timed);
-// device staging [2][3][N] for host-pointer Stokes applies (allocated once)
+                         uint32_t parts, bool timed, bool pressure);
+// device staging of 7N doubles (density [3][N], output up to [4][N]) for
+// host-pointer Stokes applies (allocated once)
 sbie_status stokes_staging(sbie_geom* g, double** io);
 
 // matrix-core far field (far_mfma.hip); target-row groups per particle of

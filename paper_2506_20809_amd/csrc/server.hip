@@ -167,7 +167,7 @@ sbie_session* admit_locked(sbie_server* srv, int lane) {
 }
 
 sbie_status launch_apply(sbie_session* s, hipStream_t st) {
-  if (s->op == SBIE_OP_STOKES_S) return apply_stokes(s->g, s->prec, s->d_in, s->d_out, st, SBIE_PARTS_ALL, false);
+  if (s->op == SBIE_OP_STOKES_S) return apply_stokes(s->g, s->prec, s->d_in, s->d_out, st, SBIE_PARTS_ALL, false, false);
   return apply_laplace(s->g, s->op, s->prec, s->d_in, s->d_out, st, SBIE_PARTS_ALL, false);
 }
 

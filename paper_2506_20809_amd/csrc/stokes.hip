@@ -8,6 +8,10 @@
 // particle's own nodes (the gradient jump -f nu cancels in the combination);
 // near: values and gradients of the neighbours' exterior expansions; far: the
 // Stokeslet (1/8pi)(I/r + r r^T/r^3) by smooth quadrature (Section 4.3).
+// With C = 4 components the pressure of the Stokeslet, kernel (1/4pi) r/r^3
+// (r = x - y), follows as a fourth one: p = -sum_j d_j S[sigma_j] (the printed
+// identity sum_j e_j . grad S[sigma_j] has the opposite sign); on the surface
+// its exterior limit (the gradients' exterior limits).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -20,6 +24,7 @@ namespace sbie {
 namespace {
 
 constexpr double kInv8Pi = 0.039788735772973833942220940843128591;
+constexpr double kInv4Pi = 0.079577471545947667884441881686257181;
 
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
@@ -74,21 +79,25 @@ __global__ void k_stokes_scale(const double* __restrict__ coef, const double* __
 }
 
 // Cartesian (lab) gradients of the four expansions from their derivatives in
-// (u, v, phi) and the combination of Eq. (stokes).  d = x - c (lab).
+// (u, v, phi) and the combination of Eq. (stokes); with C = 4 also the
+// pressure -sum_j d_j S[sigma_j] in out[3].  d = x - c (lab).
+template <int C>
 __device__ inline void stokes_from_derivatives(const Particle& P, double u, double su, double v, double sv,
                                                double c1, double s1, const double* Phi, const double* Pu,
                                                const double* Pv, const double* Pp, const double d[3],
-                                               double out[3]) {
+                                               double (&out)[C]) {
   double grad[4][3];
 #pragma unroll
   for (int s = 0; s < 4; ++s) lab_gradient(P, u, su, v, sv, c1, s1, Pu[s], Pv[s], Pp[s], grad[s]);
 #pragma unroll
   for (int k = 0; k < 3; ++k)
     out[k] = 0.5 * (Phi[k] - d[0] * grad[0][k] - d[1] * grad[1][k] - d[2] * grad[2][k] + grad[3][k]);
+  if constexpr (C == 4) out[3] = -(grad[0][0] + grad[1][1] + grad[2][2]);
 }
 
 // Self part at node g of particle i from the synthesised values U[0..3]
 // (value, d/du exterior limit, d/dv, d/dphi) of the four expansions.
+template <int C>
 __global__ void k_stokes_self(const Particle* __restrict__ part, const double* __restrict__ gl,
                               const double* __restrict__ x, const double* __restrict__ y,
                               const double* __restrict__ z, const double* __restrict__ U, int M, int p,
@@ -112,11 +121,10 @@ __global__ void k_stokes_self(const Particle* __restrict__ part, const double* _
   double s1, c1;
   sincospi(2.0 * k / Nphi, &s1, &c1);
   const double d[3] = {x[g] - P.c[0], y[g] - P.c[1], z[g] - P.c[2]};
-  double o3[3];
-  stokes_from_derivatives(P, P.u0, sqrt(P.w0), v, sqrt((1.0 - v) * (1.0 + v)), c1, s1, Phi, Pu, Pv, Pp, d, o3);
-  out[g] = o3[0];
-  out[N + g] = o3[1];
-  out[2 * N + g] = o3[2];
+  double o[C];
+  stokes_from_derivatives<C>(P, P.u0, sqrt(P.w0), v, sqrt((1.0 - v) * (1.0 + v)), c1, s1, Phi, Pu, Pv, Pp, d, o);
+#pragma unroll
+  for (int c = 0; c < C; ++c) out[c * N + g] = o[c];
 }
 
 // Near part: one wave per (target particle, 64 target nodes); for every near
@@ -124,7 +132,7 @@ __global__ void k_stokes_self(const Particle* __restrict__ part, const double* _
 // come from the same division-free backward recurrence as the Laplace near
 // field, and the four expansions are summed with their u, v and phi
 // derivatives.
-template <int PMAX>
+template <int PMAX, int C>
 __global__ __launch_bounds__(64) void k_near_stokes(
     const Particle* __restrict__ part, const double* __restrict__ x, const double* __restrict__ y,
     const double* __restrict__ z, const int32_t* __restrict__ near_ptr, const int32_t* __restrict__ near_src,
@@ -137,7 +145,9 @@ __global__ __launch_bounds__(64) void k_near_stokes(
   const int64_t g = (int64_t)j * T + (live ? t : 0);
   const double X0 = x[g], X1 = y[g], X2 = z[g];
   const int K = (p + 1) * (p + 1), Kh = (p + 1) * (p + 2) / 2;
-  double acc[3] = {0.0, 0.0, 0.0};
+  double acc[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) acc[c] = 0.0;
   unsigned bad = 0u;
   for (int sidx = near_ptr[j]; sidx < near_ptr[j + 1]; ++sidx) {
     const int i = near_src[sidx];
@@ -146,17 +156,15 @@ __global__ __launch_bounds__(64) void k_near_stokes(
     double Phi[4], Pu[4], Pv[4], Pp[4];
     expansion_derivatives<PMAX, 4>(q, P.oblate != 0, E + (size_t)i * 4 * K, (size_t)K, lam + (size_t)i * Kh * 4,
                                    ab, cd, rcp, p, &bad, Phi, Pu, Pv, Pp);
-    double o3[3];
-    stokes_from_derivatives(P, q.u, q.sw, q.v, q.sv, q.c1, q.s1, Phi, Pu, Pv, Pp, q.d, o3);
-    acc[0] += o3[0];
-    acc[1] += o3[1];
-    acc[2] += o3[2];
+    double o[C];
+    stokes_from_derivatives<C>(P, q.u, q.sw, q.v, q.sv, q.c1, q.s1, Phi, Pu, Pv, Pp, q.d, o);
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] += o[c];
   }
   if (bad) atomicOr(status, bad);
   if (live) {
-    unear[g] = acc[0];
-    unear[N + g] = acc[1];
-    unear[2 * N + g] = acc[2];
+#pragma unroll
+    for (int c = 0; c < C; ++c) unear[c * N + g] = acc[c];
   }
 }
 
@@ -180,7 +188,7 @@ __device__ inline double rsq_r<double>(double x) {
 // records (node - centre, W sigma) are read with wave-uniform addresses; each
 // source particle's tile sum is added per target under the exclusion flag,
 // compensated (TwoSum) in FP32.
-template <typename R, int TPT>
+template <typename R, int TPT, int C>
 __global__ __launch_bounds__(256) void k_far_stokes(const R* __restrict__ rec, const Particle* __restrict__ part,
                                                     const double* __restrict__ x, const double* __restrict__ y,
                                                     const double* __restrict__ z, const uint32_t* __restrict__ excl,
@@ -191,7 +199,7 @@ __global__ __launch_bounds__(256) void k_far_stokes(const R* __restrict__ rec, c
   double tx[TPT], ty[TPT], tz[TPT];
   int tp[TPT];
   bool live[TPT];
-  R acc[TPT][3], lo[TPT][3];
+  R acc[TPT][C], lo[TPT][C];
 #pragma unroll
   for (int k = 0; k < TPT; ++k) {
     const int64_t gq = (int64_t)tile * 256 * TPT + k * 256 + threadIdx.x;
@@ -202,7 +210,7 @@ __global__ __launch_bounds__(256) void k_far_stokes(const R* __restrict__ rec, c
     tz[k] = z[gg];
     tp[k] = (int)(gg / T);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) acc[k][c] = lo[k][c] = R(0);
+    for (int c = 0; c < C; ++c) acc[k][c] = lo[k][c] = R(0);
   }
   for (int s = s0; s < s1; ++s) {
     bool need[TPT];
@@ -214,13 +222,14 @@ __global__ __launch_bounds__(256) void k_far_stokes(const R* __restrict__ rec, c
     }
     if (!__any(any)) continue;
     const double cx = part[s].c[0], cy = part[s].c[1], cz = part[s].c[2];
-    R Dx[TPT], Dy[TPT], Dz[TPT], tmp[TPT][3];
+    R Dx[TPT], Dy[TPT], Dz[TPT], tmp[TPT][C];
 #pragma unroll
     for (int k = 0; k < TPT; ++k) {
       Dx[k] = (R)(tx[k] - cx);
       Dy[k] = (R)(ty[k] - cy);
       Dz[k] = (R)(tz[k] - cz);
-      tmp[k][0] = tmp[k][1] = tmp[k][2] = R(0);
+#pragma unroll
+      for (int c = 0; c < C; ++c) tmp[k][c] = R(0);
     }
     const R* rs = rec + (size_t)s * T * 8;
     for (int q = 0; q < T; ++q) {
@@ -236,12 +245,13 @@ __global__ __launch_bounds__(256) void k_far_stokes(const R* __restrict__ rec, c
         tmp[k][0] = fma(q0, ri, fma(dx, f, tmp[k][0]));
         tmp[k][1] = fma(q1, ri, fma(dy, f, tmp[k][1]));
         tmp[k][2] = fma(q2, ri, fma(dz, f, tmp[k][2]));
+        if constexpr (C == 4) tmp[k][3] += f;  // pressure: (r.q)/r^3, scaled by 1/(4 pi) below
       }
     }
 #pragma unroll
     for (int k = 0; k < TPT; ++k)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
+      for (int c = 0; c < C; ++c) {
         const R vv = need[k] ? tmp[k][c] : R(0);
         const R sum = acc[k][c] + vv;
         const R bp = sum - acc[k][c];
@@ -254,16 +264,17 @@ __global__ __launch_bounds__(256) void k_far_stokes(const R* __restrict__ rec, c
     const int64_t gq = (int64_t)tile * 256 * TPT + k * 256 + threadIdx.x;
     if (!live[k]) continue;
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-      partial[((size_t)split * 3 + c) * N + gq] = ((double)acc[k][c] + (double)lo[k][c]) * kInv8Pi;
+    for (int c = 0; c < C; ++c)
+      partial[((size_t)split * C + c) * N + gq] = ((double)acc[k][c] + (double)lo[k][c]) * (c < 3 ? kInv8Pi : kInv4Pi);
   }
 }
 
+template <int C>
 __global__ void k_stokes_assemble(const double* __restrict__ uself, const double* __restrict__ unear,
                                   const double* __restrict__ partial, int nsplit, int64_t N, uint32_t parts,
                                   double* __restrict__ out) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 3 * N) return;
+  if (t >= C * N) return;
   const int c = (int)(t / N);
   const int64_t g = t - (int64_t)c * N;
   double u = 0.0;
@@ -271,16 +282,16 @@ __global__ void k_stokes_assemble(const double* __restrict__ uself, const double
   if (parts & SBIE_PARTS_NEAR) u += unear[t];
   if (parts & SBIE_PARTS_FAR) {
     double f = 0.0;
-    for (int s = 0; s < nsplit; ++s) f += partial[((size_t)s * 3 + c) * N + g];
+    for (int s = 0; s < nsplit; ++s) f += partial[((size_t)s * C + c) * N + g];
     u += f;
   }
   out[t] = u;
 }
 
-template <int PMAX>
+template <int PMAX, int C>
 void launch_near_stokes(sbie_geom* g, hipStream_t s) {
   const int chunks = (g->T + 63) / 64;
-  hipLaunchKernelGGL(k_near_stokes<PMAX>, dim3(g->M * chunks), dim3(64), 0, s, g->d_part, g->d_x, g->d_y, g->d_z,
+  hipLaunchKernelGGL((k_near_stokes<PMAX, C>), dim3(g->M * chunks), dim3(64), 0, s, g->d_part, g->d_x, g->d_y, g->d_z,
                      g->d_near_ptr, g->d_near_src, g->d_stk_E, g->d_lam, g->d_ab, g->d_cd, g->d_rcp, g->p, g->T,
                      chunks, g->N, g->d_status, g->d_stk_near);
 }
@@ -301,10 +312,11 @@ sbie_status carve_stokes(sbie_geom* g, Carver& c) {
   SBIE_TRY_C(c.take(&g->d_stk_E, 2 * MK4));
   SBIE_TRY_C(c.take(&g->d_stk_U, 4 * MT4));
   SBIE_TRY_C(c.take(&g->d_stk_src, 8 * N));
-  SBIE_TRY_C(c.take(&g->d_stk_part, (size_t)g->nsplit * 3 * N));
-  SBIE_TRY_C(c.take(&g->d_stk_self, 3 * N));
-  SBIE_TRY_C(c.take(&g->d_stk_near, 3 * N));
-  SBIE_TRY_C(c.take(&g->d_stk_io, 6 * N));
+  // four components: velocity and pressure
+  SBIE_TRY_C(c.take(&g->d_stk_part, (size_t)g->nsplit * 4 * N));
+  SBIE_TRY_C(c.take(&g->d_stk_self, 4 * N));
+  SBIE_TRY_C(c.take(&g->d_stk_near, 4 * N));
+  SBIE_TRY_C(c.take(&g->d_stk_io, 7 * N));
   return SBIE_OK;
 }
 
@@ -342,12 +354,19 @@ sbie_status stokes_staging(sbie_geom* g, double** io) {
   return SBIE_OK;
 }
 
+namespace {
+
+template <int C>
+sbie_status stokes_parts(sbie_geom* g, bool mixed, hipStream_t s, uint32_t parts, hipEvent_t* ev, double* d_out);
+
+}  // namespace
+
 sbie_status apply_stokes(sbie_geom* g, int prec, const double* d_dens, double* d_out, hipStream_t s,
-                         uint32_t parts, bool timed) {
+                         uint32_t parts, bool timed, bool pressure) {
   const int M = g->M, p = g->p, T = g->T, K = g->K;
   const int64_t N = g->N;
   const bool mixed = prec == SBIE_MIXED;
-  const size_t MT4 = (size_t)4 * M * T, MK4 = (size_t)4 * M * K;
+  const size_t MK4 = (size_t)4 * M * K;
   sbie_status st;
   SBIE_TRY_C(stokes_buffers(g));
 
@@ -373,6 +392,21 @@ sbie_status apply_stokes(sbie_geom* g, int prec, const double* d_dens, double* d
                        M, p, g->d_stk_E, g->d_stk_E + MK4);
     SBIE_HIP(hipGetLastError());
   }
+  return pressure ? stokes_parts<4>(g, mixed, s, parts, ev, d_out) : stokes_parts<3>(g, mixed, s, parts, ev, d_out);
+}
+
+namespace {
+
+// Near (side stream when the geometry has one), self and far parts of C
+// components, then the assembly into d_out [C][N].
+template <int C>
+sbie_status stokes_parts(sbie_geom* g, bool mixed, hipStream_t s, uint32_t parts, hipEvent_t* ev, double* d_out) {
+  const int M = g->M, p = g->p, T = g->T, K = g->K;
+  const int64_t N = g->N;
+  const size_t MT4 = (size_t)4 * M * T, MK4 = (size_t)4 * M * K;
+  const bool timed = ev != nullptr;
+  const int B = 256;
+  sbie_status st;
   // near field on the side stream, concurrently with the self and far parts
   const bool near = (parts & SBIE_PARTS_NEAR) && g->n_near > 0;
   const bool fork = near && g->side != nullptr;
@@ -381,11 +415,11 @@ sbie_status apply_stokes(sbie_geom* g, int prec, const double* d_dens, double* d
     hipStream_t ns = fork ? g->side : s;
     if (timed) SBIE_HIP(hipEventRecord(ev[6], ns));
     if (p <= 8)
-      launch_near_stokes<8>(g, ns);
+      launch_near_stokes<8, C>(g, ns);
     else if (p <= 16)
-      launch_near_stokes<16>(g, ns);
+      launch_near_stokes<16, C>(g, ns);
     else
-      launch_near_stokes<32>(g, ns);
+      launch_near_stokes<32, C>(g, ns);
     SBIE_HIP(hipGetLastError());
     if (timed) SBIE_HIP(hipEventRecord(ev[7], ns));
   } else if (timed) {
@@ -402,7 +436,7 @@ sbie_status apply_stokes(sbie_geom* g, int prec, const double* d_dens, double* d
         return st;
       if ((st = gemm(mixed, g->d_stk_E, K, g->d_Sp, g->d_Sp32, T, U + 3 * MT4, T, 4 * M, T, K, s)) != SBIE_OK)
         return st;
-      hipLaunchKernelGGL(k_stokes_self, dim3(cdiv(N, B)), dim3(B), 0, s, g->d_part, g->d_gl, g->d_x, g->d_y,
+      hipLaunchKernelGGL(k_stokes_self<C>, dim3(cdiv(N, B)), dim3(B), 0, s, g->d_part, g->d_gl, g->d_x, g->d_y,
                          g->d_z, g->d_stk_U, M, p, N, g->d_stk_self);
       SBIE_HIP(hipGetLastError());
     }
@@ -413,10 +447,10 @@ sbie_status apply_stokes(sbie_geom* g, int prec, const double* d_dens, double* d
     constexpr int TPT = 2;
     const dim3 grid(cdiv(N, 256 * TPT) * g->nsplit);
     if (mixed)
-      hipLaunchKernelGGL((k_far_stokes<float, TPT>), grid, dim3(256), 0, s, (const float*)g->d_stk_src, g->d_part,
+      hipLaunchKernelGGL((k_far_stokes<float, TPT, C>), grid, dim3(256), 0, s, (const float*)g->d_stk_src, g->d_part,
                          g->d_x, g->d_y, g->d_z, g->d_excl, g->excl_words, M, T, N, g->nsplit, g->d_stk_part);
     else
-      hipLaunchKernelGGL((k_far_stokes<double, TPT>), grid, dim3(256), 0, s, (const double*)g->d_stk_src,
+      hipLaunchKernelGGL((k_far_stokes<double, TPT, C>), grid, dim3(256), 0, s, (const double*)g->d_stk_src,
                          g->d_part, g->d_x, g->d_y, g->d_z, g->d_excl, g->excl_words, M, T, N, g->nsplit,
                          g->d_stk_part);
     SBIE_HIP(hipGetLastError());
@@ -425,11 +459,13 @@ sbie_status apply_stokes(sbie_geom* g, int prec, const double* d_dens, double* d
   if (fork) SBIE_TRY_C(join_side(g, s));
   // with no near pairs the near part is empty and is left out of the sum
   const uint32_t sum_parts = g->n_near > 0 ? parts : (parts & ~(uint32_t)SBIE_PARTS_NEAR);
-  hipLaunchKernelGGL(k_stokes_assemble, dim3(cdiv(3 * N, B)), dim3(B), 0, s, g->d_stk_self, g->d_stk_near,
+  hipLaunchKernelGGL(k_stokes_assemble<C>, dim3(cdiv(C * N, B)), dim3(B), 0, s, g->d_stk_self, g->d_stk_near,
                      g->d_stk_part, g->nsplit, N, sum_parts, d_out);
   SBIE_HIP(hipGetLastError());
   if (timed) SBIE_HIP(hipEventRecord(ev[5], s));
   return SBIE_OK;
 }
+
+}  // namespace
 
 }  // namespace sbie

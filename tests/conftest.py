@@ -3,9 +3,11 @@ import sys
 
 import pytest
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-if ROOT not in sys.path:
-    sys.path.insert(0, ROOT)
+TESTS = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(TESTS)
+for _d in (ROOT, TESTS):  # the packages, and the shared closed-form references
+    if _d not in sys.path:
+        sys.path.insert(0, _d)
 
 
 def pytest_configure(config):

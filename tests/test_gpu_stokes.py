@@ -213,3 +213,90 @@ def test_stokes_mixed_c4_full_size_sampled(ctx):
     ref = oracle.stokes_apply_at(geom, p, dens, tg)[0]
     assert _rel(u[:, tg], ref) < TOL_MIXED, _rel(u[:, tg], ref)
     g.close()
+
+
+# ---------------------------------------------------------------- pressure (SBIE_OP_STOKES_SP)
+
+def _pressure_parts(g, geom, p, dens, tol, max_tol, precision=0, label=""):
+    import torch
+
+    import paper_2506_20809_amd as sbie
+
+    ref = oracle.stokes_apply(geom, p, dens, parts=True, pressure=True)
+    d = torch.tensor(np.ascontiguousarray(dens), dtype=torch.float64, device="cuda")
+    flags = [sbie.SBIE_PARTS_ALL, sbie.SBIE_PARTS_SELF, sbie.SBIE_PARTS_NEAR, sbie.SBIE_PARTS_FAR]
+    for name, fl, r in zip(["all", "self", "near", "far"], flags, ref):
+        u = g.apply(sbie.SBIE_OP_STOKES_SP, d, precision=precision, parts=fl)
+        g.sync()
+        u = u.cpu().numpy()
+        assert u.shape == (4, g.N)
+        if np.max(np.abs(r)) == 0:
+            assert np.max(np.abs(u)) < 1e-13, (label, name)
+            continue
+        for rows, what in ((slice(0, 3), "velocity"), (slice(3, 4), "pressure")):
+            scale = np.max(np.abs(r[rows]))
+            assert _rel(u[rows], r[rows]) < tol, (label, name, what, _rel(u[rows], r[rows]))
+            assert np.max(np.abs(u[rows] - r[rows])) < max_tol * scale, (label, name, what)
+
+
+@pytest.mark.parametrize("p", [3, 8, 12])
+def test_pressure_parity(ctx, p):
+    import paper_2506_20809_amd as sbie
+
+    geom = workloads.rsa_pack(7, 0.12, 0.05, 600 + p)
+    g = sbie.Geometry(ctx, geom, p)
+    dens = np.random.default_rng(p).standard_normal((3, g.N))
+    _pressure_parts(g, geom, p, dens, TOL64, TOL64, label=f"p={p}")
+    _pressure_parts(g, geom, p, dens, TOL_MIXED, 1e-5, precision=sbie.SBIE_MIXED, label=f"mixed p={p}")
+    # the velocity rows equal the velocity-only apply
+    u4 = g.apply(sbie.SBIE_OP_STOKES_SP, dens)
+    u3 = g.apply(sbie.SBIE_OP_STOKES_S, dens)
+    assert np.max(np.abs(u4[:3] - u3)) <= 1e-15 * np.max(np.abs(u3))
+    g.close()
+
+
+def test_pressure_conductor_closed_form(ctx):
+    """Translating-ellipsoid tractions on the three-particle system: the
+    exterior-limit pressure is f_j . nu on particle j plus the conducting-
+    spheroid fields F_i . grad u_i / (4 pi a_i (u_i^2 -+ 1)) of the others."""
+    import paper_2506_20809_amd as sbie
+    from closed_forms import grad_u as _grad_u
+    from closed_forms import translating_traction as _translating_traction
+    from workloads import quat_rot
+
+    geom = workloads.three_spheroids(True, seed=3)
+    p = 16
+    F = np.array([[1.0, 0.3, -0.5], [-0.4, 0.8, 0.2], [0.1, -0.6, 0.9]])
+    dens, xyz, nrm = _translating_traction(geom, p, F)
+    g = sbie.Geometry(ctx, geom, p)
+    u = g.apply(sbie.SBIE_OP_STOKES_SP, dens)
+    T = (p + 1) * (2 * p + 2)
+    ref = np.zeros(3 * T)
+    for j in range(3):
+        sl = slice(j * T, (j + 1) * T)
+        ref[sl] = np.sum(dens[:, sl].T * nrm[sl], axis=1)
+        for i in range(3):
+            if i != j:
+                gu, a, w = _grad_u(geom["centers"][i], quat_rot(geom["quats"][i]), geom["A"][i], geom["C"][i],
+                                   xyz[sl])
+                ref[sl] += (gu @ F[i]) / (4 * np.pi * a * w)
+    assert np.max(np.abs(u[3] - ref)) < 1e-12 * np.max(np.abs(ref))
+    g.close()
+
+
+def test_pressure_c4_full_size_sampled(ctx):
+    import torch
+
+    import paper_2506_20809_amd as sbie
+
+    geom = workloads.geometry("c4")
+    p = workloads.CONFIGS["c4"]["p"]
+    g = sbie.Geometry(ctx, geom, p)
+    dens = np.random.default_rng(44).standard_normal((3, g.N))
+    u = g.apply(sbie.SBIE_OP_STOKES_SP, torch.tensor(dens, device="cuda"))
+    g.sync()
+    u = u.cpu().numpy()
+    tg = np.sort(np.random.default_rng(45).choice(g.N, 16, replace=False))
+    ref = oracle.stokes_apply_at(geom, p, dens, tg, pressure=True)[0]
+    assert np.max(np.abs(u[:, tg] - ref)) < TOL64 * np.max(np.abs(ref))
+    g.close()

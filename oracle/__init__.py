@@ -75,6 +75,8 @@ def lib():
                                             ctypes.c_int, dp]
         L.orc_eval_targets.argtypes = [dp, dp, dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                        dp, dp, ctypes.c_int, dp, dp, ctypes.POINTER(ctypes.c_uint8)]
+        L.orc_stokes_dl_apply.argtypes = [dp, dp, dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp,
+                                          ctypes.POINTER(ctypes.c_int64), ctypes.c_int, dp, dp, dp, dp]
         L.orc_set_cf_max_iter.argtypes = [ctypes.c_int]
         L.orc_set_cf_max_iter.restype = None
         L.orc_num_threads.argtypes = []
@@ -280,6 +282,25 @@ def stokes_apply_at(geom, p: int, density: np.ndarray, targets, eta: float = 1.0
                                      tg.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n, nc, _p(us), _p(un),
                                      _p(uf), _p(u)), "stokes_apply_at")
     return u, us, un, uf
+
+
+def stokes_dl_apply(geom, p: int, density: np.ndarray, targets=None, eta: float = 1.0, parts: bool = False):
+    """Stokes double layer (stresslet, outward normal; principal value on the
+    surface) at every node, or at the selected node indices; density [3, N].
+    Returns u [3, n], or (u, u_self, u_near, u_far) with parts=True."""
+    c, q, A, C = _geom_arrays(geom)
+    M = len(A)
+    N = M * (p + 1) * (2 * p + 2)
+    dens = _f64(density).reshape(3, N)
+    if targets is None:
+        n, tp = N, None
+    else:
+        tg = np.ascontiguousarray(targets, dtype=np.int64)
+        n, tp = len(tg), tg.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    us, un, uf, u = (np.zeros((3, n)) for _ in range(4))
+    _check(lib().orc_stokes_dl_apply(_p(c), _p(q), _p(A), _p(C), M, int(p), float(eta), _p(dens), tp,
+                                     0 if targets is None else n, _p(us), _p(un), _p(uf), _p(u)), "stokes_dl_apply")
+    return (u, us, un, uf) if parts else u
 
 
 def stokes_single(spheroid, p: int, density: np.ndarray, pts=None, interior: bool = False) -> np.ndarray:

@@ -1056,7 +1056,8 @@ static int expansion_grad(const particle* pt, int p, int nset, const double* E, 
   double dzdu_re = 1.0, dzdu_im = 0.0;
   if (pt->oblate) { dzdu_re = 0.0; dzdu_im = 1.0; }
   double complex dzdu = dzdu_re + dzdu_im * I;
-  double Fu[4], Fv[4], Fp[4];
+  double Fu[16], Fv[16], Fp[16];
+  if (nset < 1 || nset > 16) { free(Pf); free(buf); return ORC_E_INVALID; }
   for (int s = 0; s < nset; ++s) { val[s] = 0.0; Fu[s] = Fv[s] = Fp[s] = 0.0; }
   int rc = 0;
   for (int m = 0; m <= p && !rc; ++m) {
@@ -1311,6 +1312,189 @@ int orc_stokes_apply_at(const double* centres, const double* quats, const double
   if (!rc) rc = err;
   free(need);
   free(E4);
+  free_geometry(&g);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Stokes double layer, the stresslet with the outward normal (viscosity 1):  */
+/*   D_stk[mu]_i(x) = 3/(4 pi) int (r.mu)(r.nu) r_i / |r|^5 dS_y, r = x - y,  */
+/* normalised so that a constant mu gives -mu inside, 0 outside and -mu/2 on  */
+/* the surface (principal value), as the Laplace D of a constant.  Section    */
+/* 4.3 only cites a decomposition into Laplace potentials; the one used here  */
+/* (derived for this oracle) is, with origin c at each source centre,         */
+/*   D_stk[mu]_i = -sum_j (x-c)_j d_i D[mu_j] + d_i D[(y-c).mu]               */
+/*                 - sum_j d_j S[mu_j nu_i],                                  */
+/* which follows from d_i (nu.r/r^3) and d_j (1/r) = -r_j/r^3.  Self values:  */
+/* the exterior limits of the gradients give D_stk+, and the principal value  */
+/* is D_stk+ - mu/2 (the jump of the double layer is mu).                     */
+/* ------------------------------------------------------------------------ */
+
+/* Double-layer exterior coefficients E = lamD+ * T[f] of one particle. */
+static int double_layer_coefficients(const geometry* g, int i, const double* f, double* E) {
+  const particle* pt = &g->pt[i];
+  int p = g->p, Kh = g->Kh;
+  double* lam = (double*)malloc(sizeof(double) * Kh);
+  int rc = spectra(pt, p, NULL, lam, NULL, NULL, NULL);
+  if (rc) { free(lam); return rc; }
+  forward_transform(p, g->gx, g->gw, f, E);
+  for (int n = 0; n <= p; ++n)
+    for (int m = -n; m <= n; ++m) E[n * n + n + m] *= lam[n * (n + 1) / 2 + abs(m)];
+  free(lam);
+  return ORC_OK;
+}
+
+/* The thirteen expansions of particle i: double layers of mu_1, mu_2, mu_3 and
+   (y - c_i).mu (sets 0-3), single layers of mu_j nu_k (set 4 + 3k + j). */
+static int stokes_dl_coefficients(const geometry* g, int i, const double* density, double* E13) {
+  int T = g->T, K = g->K;
+  size_t N = (size_t)g->N;
+  double* f = (double*)malloc(sizeof(double) * T);
+  int rc = 0;
+  for (int s = 0; s < 13 && !rc; ++s) {
+    for (int t = 0; t < T; ++t) {
+      size_t gi = (size_t)i * T + t;
+      if (s < 3) {
+        f[t] = density[s * N + gi];
+      } else if (s == 3) {
+        double r = 0.0;
+        for (int c = 0; c < 3; ++c) r += (g->xyz[3 * gi + c] - g->pt[i].c[c]) * density[c * N + gi];
+        f[t] = r;
+      } else {
+        int k = (s - 4) / 3, j = (s - 4) % 3;
+        f[t] = density[j * N + gi] * g->nrm[3 * gi + k];
+      }
+    }
+    rc = s < 4 ? double_layer_coefficients(g, i, f, E13 + (size_t)s * K)
+               : single_layer_coefficients(g, i, f, E13 + (size_t)s * K);
+  }
+  free(f);
+  return rc;
+}
+
+/* The decomposition from the lab gradients gD [4][3] of the double layers and
+   gS [9][3] of the single layers (origin c). */
+static void stokes_dl_combine(const particle* pt, const double x[3], const double* gD, const double* gS,
+                              double out[3]) {
+  for (int i = 0; i < 3; ++i) {
+    double s = gD[3 * 3 + i];
+    for (int j = 0; j < 3; ++j) s -= (x[j] - pt->c[j]) * gD[3 * j + i];
+    for (int j = 0; j < 3; ++j) s -= gS[3 * (3 * i + j) + j];
+    out[i] = s;
+  }
+}
+
+/* Values (unused) and gradients of the thirteen expansions of particle pt at
+   (u, v, phi), exterior side. */
+static int stokes_dl_grads(const particle* pt, int p, const double* E13, double u, double v, double phi,
+                           double* gD, double* gS) {
+  int K = (p + 1) * (p + 1);
+  double val[9];
+  int rc = expansion_grad(pt, p, 4, E13, u, v, phi, 0, val, gD);
+  if (!rc) rc = expansion_grad(pt, p, 9, E13 + (size_t)4 * K, u, v, phi, 0, val, gS);
+  return rc;
+}
+
+/* Self (principal value), near and far parts of the Stokes double layer at node gt. */
+static int stokes_dl_node(const geometry* g, const double* E13, const double* density, size_t gt, double us[3],
+                          double un[3], double uf[3]) {
+  int M = g->M, T = g->T, K = g->K, p = g->p, Nphi = 2 * p + 2;
+  size_t N = (size_t)g->N;
+  int j = (int)(gt / T), loc = (int)(gt - (size_t)j * T);
+  int jv = loc / Nphi, kp = loc - jv * Nphi;
+  const double* x = g->xyz + 3 * gt;
+  double gD[12], gS[27], o[3];
+  int rc = stokes_dl_grads(&g->pt[j], p, E13 + (size_t)j * 13 * K, g->pt[j].u0, g->gx[jv], 2.0 * PI * kp / Nphi,
+                           gD, gS);
+  if (rc) return rc;
+  stokes_dl_combine(&g->pt[j], x, gD, gS, us);
+  for (int k = 0; k < 3; ++k) us[k] -= 0.5 * density[k * N + gt];
+  for (int k = 0; k < 3; ++k) un[k] = 0.0;
+  for (int i = 0; i < M; ++i) {
+    if (!g->near[(size_t)i * M + j]) continue;
+    double xb[3], uu, vv, ph;
+    lab_to_body(&g->pt[i], x, xb);
+    body_to_spheroidal(&g->pt[i], xb, &uu, &vv, &ph);
+    rc = stokes_dl_grads(&g->pt[i], p, E13 + (size_t)i * 13 * K, uu, vv, ph, gD, gS);
+    if (rc) return rc;
+    stokes_dl_combine(&g->pt[i], x, gD, gS, o);
+    for (int k = 0; k < 3; ++k) un[k] += o[k];
+  }
+  double sum[3] = {0, 0, 0}, comp[3] = {0, 0, 0};
+  for (int i = 0; i < M; ++i) {
+    if (i == j || g->near[(size_t)i * M + j]) continue;
+    for (int q = 0; q < T; ++q) {
+      size_t gs = (size_t)i * T + q;
+      const double *y = g->xyz + 3 * gs, *nu = g->nrm + 3 * gs;
+      double d[3] = {x[0] - y[0], x[1] - y[1], x[2] - y[2]};
+      double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2], r = sqrt(r2);
+      double dm = d[0] * density[gs] + d[1] * density[N + gs] + d[2] * density[2 * N + gs];
+      double dn = d[0] * nu[0] + d[1] * nu[1] + d[2] * nu[2];
+      double w = 3.0 / (4.0 * PI) * g->W[gs] * dm * dn / (r2 * r2 * r);
+      for (int k = 0; k < 3; ++k) {
+        double term = w * d[k];
+        double ts = sum[k] + term;
+        if (fabs(sum[k]) >= fabs(term)) comp[k] += (sum[k] - ts) + term;
+        else comp[k] += (term - ts) + sum[k];
+        sum[k] = ts;
+      }
+    }
+  }
+  for (int k = 0; k < 3; ++k) uf[k] = sum[k] + comp[k];
+  return ORC_OK;
+}
+
+/* Stokes double layer at every node (targets NULL) or at ntg selected nodes;
+   density [3][N], outputs [3][N] resp. [3][ntg]. */
+int orc_stokes_dl_apply(const double* centres, const double* quats, const double* A, const double* C, int M,
+                        int p, double eta, const double* density, const int64_t* targets, int ntg,
+                        double* u_self, double* u_near, double* u_far, double* u) {
+  geometry g;
+  int rc = build_geometry(centres, quats, A, C, M, p, eta, &g);
+  if (rc) return rc;
+  int T = g.T, K = g.K;
+  int64_t n = targets ? ntg : (int64_t)g.N;
+  uint8_t* need = (uint8_t*)calloc(M, 1);
+  for (int64_t t = 0; t < n; ++t) {
+    int64_t gt = targets ? targets[t] : t;
+    if (gt < 0 || gt >= (int64_t)g.N) { free(need); free_geometry(&g); return ORC_E_INVALID; }
+    int j = (int)(gt / T);
+    need[j] = 1;
+    for (int i = 0; i < M; ++i) if (g.near[(size_t)i * M + j]) need[i] = 1;
+  }
+  double* E13 = (double*)calloc((size_t)13 * K * M, sizeof(double));
+  int err = 0;
+#pragma omp parallel for schedule(dynamic)
+  for (int i = 0; i < M; ++i) {
+    if (!need[i]) continue;
+    int r = stokes_dl_coefficients(&g, i, density, E13 + (size_t)i * 13 * K);
+    if (r) {
+#pragma omp atomic write
+      err = r;
+    }
+  }
+  if (err) rc = err;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t t = 0; t < n; ++t) {
+    if (rc || err) continue;
+    double us[3], un[3], uf[3];
+    int r = stokes_dl_node(&g, E13, density, (size_t)(targets ? targets[t] : t), us, un, uf);
+    if (r) {
+#pragma omp atomic write
+      err = r;
+      continue;
+    }
+    for (int k = 0; k < 3; ++k) {
+      size_t q = (size_t)k * n + (size_t)t;
+      if (u_self) u_self[q] = us[k];
+      if (u_near) u_near[q] = un[k];
+      if (u_far) u_far[q] = uf[k];
+      u[q] = us[k] + un[k] + uf[k];
+    }
+  }
+  if (!rc) rc = err;
+  free(need);
+  free(E13);
   free_geometry(&g);
   return rc;
 }

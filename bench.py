@@ -8,6 +8,10 @@ recurrences); the plain FP64 path is measured on the same inputs and reported
 beside it.  Prints one JSON line with applies/s, pair-interactions/s, per-apply
 p50/p99 latency, the far-field kernel's roofline figures (HIP events inside the
 library, on the apply's stream) and the CPU oracle timed on a bounded sample.
+Further sections of the same line: the FP64 path, S' and D', the Stokes single
+layer (with and without its pressure) and double layer at 256 spheroids, the
+GMRES study of the completion terms and the 512-spheroid Dirichlet and Neumann
+solves (each can be skipped with its --no-* flag).
 
   python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--precision mixed|fp64]
 """
@@ -160,8 +164,14 @@ def run_normal(g, dens, steps, precision):
     return res
 
 
-def run_stokes(ctx, steps, warmup, precision):
-    """Stokes single layer (Eq. stokes) on the 256-spheroid suspension at p = 12."""
+# Stresslet per far node pair: 3 differences + 5 r^2 + 1 rsqrt + 1 r^-2 + 3 r^-5 + 5 d.(W mu) + 5 d.nu
+# + 1 product + 3 x FMA (2) = 30
+FLOPS_PER_STRESSLET_PAIR = 30
+
+
+def run_stokes(ctx, steps, warmup, precision, op=2):
+    """Stokes single layer (Eq. stokes; op 2), with its pressure (op 5), or the
+    Stokes double layer (op 6) on the 256-spheroid suspension at p = 12."""
     import numpy as np
     import torch
 
@@ -175,10 +185,10 @@ def run_stokes(ctx, steps, warmup, precision):
     gen = torch.Generator(device="cuda")
     gen.manual_seed(4)
     dens = torch.randn((steps + warmup, 3, g.N), dtype=torch.float64, device="cuda", generator=gen)
-    out = torch.empty((3, g.N), dtype=torch.float64, device="cuda")
+    out = torch.empty((4 if op == sbie.SBIE_OP_STOKES_SP else 3, g.N), dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
     for k in range(warmup):
-        g.apply(sbie.SBIE_OP_STOKES_S, dens[k], precision=prec, out=out, timing=True)
+        g.apply(op, dens[k], precision=prec, out=out, timing=True)
     g.sync()
     g.timing()
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(steps)]
@@ -186,17 +196,18 @@ def run_stokes(ctx, steps, warmup, precision):
     t0 = time.perf_counter()
     for k in range(steps):
         ev[k][0].record(stream)
-        g.apply(sbie.SBIE_OP_STOKES_S, dens[warmup + k], precision=prec, out=out, timing=True)
+        g.apply(op, dens[warmup + k], precision=prec, out=out, timing=True)
         ev[k][1].record(stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     g.sync()
     tim = g.timing()
     lat = np.array([e[0].elapsed_time(e[1]) for e in ev])
-    achieved = FLOPS_PER_STOKES_PAIR * tim.far_pairs / (tim.far_kernel_ms * 1e-3) / 1e12
+    per_pair = FLOPS_PER_STRESSLET_PAIR if op == sbie.SBIE_OP_STOKES_D else FLOPS_PER_STOKES_PAIR
+    achieved = per_pair * tim.far_pairs / (tim.far_kernel_ms * 1e-3) / 1e12
     res = {
         "workload": f"256 polydisperse spheroids (volume fraction 0.20, gap 0.05), p={p}, N={g.N}, "
-                    f"3-component density, precision={precision}",
+                    f"3-component density, op={op}, precision={precision}",
         "applies_per_s": steps / elapsed,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "part_ms": {"prep": tim.prep_ms, "transform_self": tim.transform_ms, "near": tim.near_ms,
@@ -547,6 +558,10 @@ def main():
         res["derivatives"] = {pr: run_normal(g, dens, max(3, args.steps // 4), pr) for pr in ("mixed", "fp64")}
     if not args.no_stokes:
         res["stokes"] = {pr: run_stokes(ctx, max(4, args.steps // 2), 1, pr) for pr in ("fp64", "mixed")}
+        res["stokes_with_pressure"] = {pr: run_stokes(ctx, max(3, args.steps // 4), 1, pr, op=5)
+                                       for pr in ("fp64", "mixed")}
+        res["stokes_double_layer"] = {pr: run_stokes(ctx, max(3, args.steps // 4), 1, pr, op=6)
+                                      for pr in ("fp64", "mixed")}
     if not args.no_solve:
         res["solve"] = {"gmres_study": gmres_study(ctx),
                         **{f"{args.workload}_{pr}": solve_large(ctx, args.workload, pr) for pr in ("mixed", "fp64")}}

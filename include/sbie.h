@@ -66,9 +66,12 @@ typedef enum {
                            principal value on the surface (Section 3.3, Theorem 3) */
   SBIE_OP_DP = 4,       /* D': derivative of the double layer along the target's outward normal
                            (continuous across the surface; Section 3.3) */
-  SBIE_OP_STOKES_SP = 5 /* Stokes single layer and its pressure, kernel (1/4pi) r/|r|^3 (Section 4.3):
+  SBIE_OP_STOKES_SP = 5, /* Stokes single layer and its pressure, kernel (1/4pi) r/|r|^3 (Section 4.3):
                            nrhs = 3, potential [4][N], the fourth row the pressure, on the surface
                            its exterior limit */
+  SBIE_OP_STOKES_D = 6  /* Stokes double layer 3/(4pi) int (r.mu)(r.nu) r/|r|^5 with the outward normal
+                           (a rigid motion gives -mu inside), principal value on the surface, through
+                           Laplace double and single layers (Section 4.3); nrhs = 3 */
 } sbie_op;
 
 typedef enum {

@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsbie.so")
 
-SBIE_OP_S, SBIE_OP_D, SBIE_OP_STOKES_S, SBIE_OP_SP, SBIE_OP_DP, SBIE_OP_STOKES_SP = 0, 1, 2, 3, 4, 5
+SBIE_OP_S, SBIE_OP_D, SBIE_OP_STOKES_S, SBIE_OP_SP, SBIE_OP_DP, SBIE_OP_STOKES_SP, SBIE_OP_STOKES_D = range(7)
 SBIE_FP64, SBIE_MIXED = 0, 1
 SBIE_DEVICE_PTRS = 0x1
 SBIE_TIMING = 0x2

@@ -34,6 +34,7 @@ void free_geom(sbie_geom* g) {
   if (!g) return;
   if (g->blk && g->blk_owned) (void)hipFree(g->blk);
   if (g->stk_blk) (void)hipFree(g->stk_blk);
+  if (g->sdl_blk) (void)hipFree(g->sdl_blk);
   if (g->side) {
     (void)hipStreamSynchronize(g->side);
     (void)hipStreamDestroy(g->side);
@@ -259,12 +260,12 @@ sbie_status sbie_apply(sbie_geom* g, sbie_op op, sbie_precision prec, int32_t nr
                        double* potential, void* stream, uint32_t flags) {
   if (!g) return invalid("geometry is NULL");
   if (op != SBIE_OP_S && op != SBIE_OP_D && op != SBIE_OP_STOKES_S && op != SBIE_OP_SP && op != SBIE_OP_DP &&
-      op != SBIE_OP_STOKES_SP)
+      op != SBIE_OP_STOKES_SP && op != SBIE_OP_STOKES_D)
     return invalid("unknown operator");
   if (prec != SBIE_FP64 && prec != SBIE_MIXED) return invalid("unknown precision");
   if (nrhs < 1 || nrhs > 16) return invalid("nrhs must be in [1, 16]");
-  if ((op == SBIE_OP_STOKES_S || op == SBIE_OP_STOKES_SP) && nrhs != 3)
-    return invalid("the Stokes single layer takes nrhs = 3");
+  if ((op == SBIE_OP_STOKES_S || op == SBIE_OP_STOKES_SP || op == SBIE_OP_STOKES_D) && nrhs != 3)
+    return invalid("the Stokes operators take nrhs = 3");
   if (!density || !potential) return invalid("density or potential is NULL");
   SBIE_HIP(hipSetDevice(g->ctx->device));
   uint32_t parts = flags & SBIE_PARTS_ALL;
@@ -273,6 +274,23 @@ sbie_status sbie_apply(sbie_geom* g, sbie_op op, sbie_precision prec, int32_t nr
   const bool timed = (flags & SBIE_TIMING) != 0;
   hipStream_t s = stream ? (hipStream_t)stream : g->ctx->stream;
   const int64_t N = g->N;
+  if (op == SBIE_OP_STOKES_D) {
+    const double* din = density;
+    double* dout = potential;
+    if (!devptr) {
+      double* io = nullptr;
+      sbie_status st = stokes_dl_staging(g, &io);
+      if (st != SBIE_OK) return st;
+      SBIE_HIP(hipMemcpyAsync(io, density, sizeof(double) * 3 * N, hipMemcpyHostToDevice, s));
+      din = io;
+      dout = io + 3 * N;
+    }
+    sbie_status st = apply_stokes_dl(g, (int)prec, din, dout, s, parts, timed);
+    if (st != SBIE_OK) return st;
+    if (!devptr) SBIE_HIP(hipMemcpyAsync(potential, dout, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, s));
+    if (!stream || !devptr) return sbie_geom_sync(g, s);
+    return SBIE_OK;
+  }
   if (op == SBIE_OP_STOKES_S || op == SBIE_OP_STOKES_SP) {
     // the three components of the density in, the three velocity components
     // (and the pressure) out

@@ -92,7 +92,11 @@ struct PairShape {
 // Squared distances come off the matrix cores as in a K = 4 contraction: with
 // D = x - c_b and o = y - c_b,  |x - y|^2 = [D |D|^2] . [-2o 1] + |o|^2.  The
 // double layer's forward dot d_b.(x - y) is [D |D|^2] . [d_b 0] - d_b.o, and
-// its reverse dot d_a.(x - y) is [d_a/2  d_a.D] . [-2o 1].
+// its reverse dot d_a.(x - y) is [d_a/2  d_a.D] . [-2o 1].  For S' (the
+// derivative along the target normal, strengths q = W sigma) the forward dot
+// q_b nu_a.(x - y) is [nu_a/2  nu_a.D] . [-2 q_b o  q_b] and the reverse dot
+// q_a nu_b.(x - y) is [q_a D  q_a] . [nu_b  -nu_b.o]; the forward kernel is
+// q_b nu_a.(y - x)/r^3, the reverse q_a nu_b.(x - y)/r^3.
 //
 // Rows of a are padded to 16 with zero-strength points at a's centre.
 template <typename R, int OP>
@@ -104,7 +108,7 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
                                                    double* __restrict__ fwd, R* __restrict__ rev) {
   using MM = Mfma<R>;
   using V = typename MM::V;
-  constexpr int GEO = 80, APP = (OP == SBIE_OP_S) ? 16 : 80;
+  constexpr int GEO = 80, APP = (OP == SBIE_OP_S) ? 16 : (OP == SBIE_OP_SP ? 128 : 80);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* lds_geo = reinterpret_cast<R*>(smem_raw);
   R* lds_app = lds_geo + kChunk * GEO;
@@ -130,8 +134,9 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
   // target rows of this wave: A-operand rows (lane li) and accumulator rows
   // target rows of this wave: A-operand rows (lane li) and accumulator rows
   double tc[RB][3];
-  R da[RB][3];   // double layer: d_a of the A-operand row
+  R da[RB][3];   // double layer: d_a of the A-operand row; S': the normal nu_a
   R qa[RB][4];   // single layer: strength of the accumulator rows
+  R qr[RB];      // S': strength of the A-operand row
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) {
     const int r = (rb0 + rb) * 16 + li;
@@ -147,10 +152,14 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
     }
     const size_t blk = (size_t)a * nb + (rb < nrb ? rb0 + rb : 0);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) da[rb][c] = (OP == SBIE_OP_D && rb < nrb) ? app[blk * 80 + 16 * c + li] : R(0);
+    for (int c = 0; c < 3; ++c)
+      da[rb][c] = rb >= nrb ? R(0)
+                  : OP == SBIE_OP_D ? app[blk * 80 + 16 * c + li]
+                  : OP == SBIE_OP_SP ? app[blk * 128 + 64 + 16 * c + li] : R(0);
 #pragma unroll
     for (int e = 0; e < 4; ++e)
       qa[rb][e] = (OP == SBIE_OP_S && rb < nrb) ? app[blk * 16 + MM::row(lg, e)] : R(0);
+    qr[rb] = (OP == SBIE_OP_SP && rb < nrb) ? app[blk * 128 + 48 + li] : R(0);
   }
 
   R acc[RB][4], lo[RB][4];
@@ -170,17 +179,20 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
     }
     const double cx = part[b].c[0], cy = part[b].c[1], cz = part[b].c[2];
     // A operands of this wave's rows against partner b: [D |D|^2] with
-    // D = x - c_b; double layer also [d_a/2  d_a.D]
-    R aop[RB], a3[RB];
+    // D = x - c_b; double layer also [d_a/2  d_a.D]; S' [nu_a/2  nu_a.D] and
+    // [q_a D  q_a]
+    R aop[RB], a3[RB], aq[RB];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
       const double dx = tc[rb][0] - cx, dy = tc[rb][1] - cy, dz = tc[rb][2] - cz;
-      aop[rb] = (R)(lg == 0 ? dx : (lg == 1 ? dy : (lg == 2 ? dz : fma(dz, dz, fma(dy, dy, dx * dx)))));
-      if (OP == SBIE_OP_D) {
+      const double dl = lg == 0 ? dx : (lg == 1 ? dy : dz);
+      aop[rb] = (R)(lg < 3 ? dl : fma(dz, dz, fma(dy, dy, dx * dx)));
+      if (OP == SBIE_OP_D || OP == SBIE_OP_SP) {
         const double dd = fma((double)da[rb][2], dz, fma((double)da[rb][1], dy, (double)da[rb][0] * dx));
-        const R dl = lg == 0 ? da[rb][0] : (lg == 1 ? da[rb][1] : da[rb][2]);
-        a3[rb] = lg < 3 ? R(0.5) * dl : (R)dd;
+        const R dc = lg == 0 ? da[rb][0] : (lg == 1 ? da[rb][1] : da[rb][2]);
+        a3[rb] = lg < 3 ? R(0.5) * dc : (R)dd;
       }
+      if (OP == SBIE_OP_SP) aq[rb] = lg < 3 ? (R)((double)qr[rb] * dl) : qr[rb];
     }
     R tmp[RB][4];
 #pragma unroll
@@ -233,6 +245,31 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
                     const R ri = MM::rsq(r2[j][e]);
                     tmp[g0 + j][e] = fma(qb, ri, tmp[g0 + j][e]);
                     rsum = fma(qa[g0 + j][e], ri, rsum);
+                  }
+            }
+          } else if (OP == SBIE_OP_SP) {
+            const R bq = lds_app[ib * 128 + lane];
+            const R bn = lds_app[ib * 128 + 64 + lane];
+            const V zero = {R(0), R(0), R(0), R(0)};
+#pragma unroll
+            for (int g0 = 0; g0 < NR; g0 += G) {
+              V r2[G], df[G], dr[G];
+#pragma unroll
+              for (int j = 0; j < G; ++j)
+                if (g0 + j < NR) {
+                  r2[j] = MM::mma(aop[g0 + j], bv, cinit);
+                  df[j] = MM::mma(a3[g0 + j], bq, zero);
+                  dr[j] = MM::mma(aq[g0 + j], bn, zero);
+                }
+#pragma unroll
+              for (int j = 0; j < G; ++j)
+                if (g0 + j < NR)
+#pragma unroll
+                  for (int e = 0; e < 4; ++e) {
+                    const R ri = MM::rsq(r2[j][e]);
+                    const R ri3 = ri * ri * ri;
+                    tmp[g0 + j][e] = fma(-df[j][e], ri3, tmp[g0 + j][e]);
+                    rsum = fma(dr[j][e], ri3, rsum);
                   }
             }
           } else {
@@ -289,6 +326,18 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
                     tmp[rb][e] = fma(qb, ri, tmp[rb][e]);
                     rsum = fma(qa[rb][e], ri, rsum);
                   }
+                } else if (OP == SBIE_OP_SP) {
+                  const V zero = {R(0), R(0), R(0), R(0)};
+                  const V r2 = MM::mma(aop[rb], bv, cinit);
+                  const V df = MM::mma(a3[rb], lds_app[ib * 128 + lane], zero);
+                  const V dr = MM::mma(aq[rb], lds_app[ib * 128 + 64 + lane], zero);
+#pragma unroll
+                  for (int e = 0; e < 4; ++e) {
+                    const R ri = MM::rsq(r2[e]);
+                    const R ri3 = ri * ri * ri;
+                    tmp[rb][e] = fma(-df[e], ri3, tmp[rb][e]);
+                    rsum = fma(dr[e], ri3, rsum);
+                  }
                 } else {
                   const R dv = lds_app[ib * 80 + lane];
                   const R dw = lds_app[ib * 80 + 64 + li];
@@ -342,7 +391,7 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
         R sum = R(0);
         for (int w = 0; w < W; ++w) sum += lds_rev[w * (kChunk * 16) + c];
         // the double layer's reverse kernel is d_a.(y - x) = -d_a.(x - y)
-        rout[t] = need_r ? (OP == SBIE_OP_S ? sum : -sum) : R(0);
+        rout[t] = need_r ? (OP == SBIE_OP_D ? -sum : sum) : R(0);
       }
     }
     if (!need_f) continue;
@@ -400,7 +449,8 @@ __global__ void k_far_records(const Particle* __restrict__ part, const double* _
 }
 
 // Per-apply source strengths: S W sigma per source; D per block (W mu nu, 0) in
-// lane order and -W mu nu.o.
+// lane order and -W mu nu.o; S' per block (-2 q o, q) and (nu, -nu.o) in lane
+// order, q = W sigma.
 template <typename R, int OP>
 __global__ void k_far_strengths(const Particle* __restrict__ part, const double* __restrict__ dens,
                                 const double* __restrict__ x, const double* __restrict__ y,
@@ -418,6 +468,25 @@ __global__ void k_far_strengths(const Particle* __restrict__ part, const double*
   }
   if (OP == SBIE_OP_S) {
     app[t] = (R)wq;
+  } else if (OP == SBIE_OP_SP) {
+    double ox = 0.0, oy = 0.0, oz = 0.0, n0 = 0.0, n1 = 0.0, n2 = 0.0;
+    if (q < T) {
+      ox = x[g] - part[s].c[0];
+      oy = y[g] - part[s].c[1];
+      oz = z[g] - part[s].c[2];
+      n0 = nx[g];
+      n1 = ny[g];
+      n2 = nz[g];
+    }
+    R* b = app + (t / 16) * 128 + (t % 16);
+    b[0] = (R)(-2.0 * wq * ox);
+    b[16] = (R)(-2.0 * wq * oy);
+    b[32] = (R)(-2.0 * wq * oz);
+    b[48] = (R)wq;
+    b[64] = (R)n0;
+    b[80] = (R)n1;
+    b[96] = (R)n2;
+    b[112] = (R)(-fma(n2, oz, fma(n1, oy, n0 * ox)));
   } else {
     double dx = 0.0, dy = 0.0, dz = 0.0, dot = 0.0;
     if (q < T) {
@@ -446,6 +515,9 @@ sbie_status launch_far(sbie_geom* g, int op, const double* d_dens, const R* geo,
   if (op == SBIE_OP_S)
     hipLaunchKernelGGL((k_far_strengths<R, SBIE_OP_S>), pre, blk, 0, s, g->d_part, d_dens, g->d_x, g->d_y, g->d_z,
                        g->d_nx, g->d_ny, g->d_nz, g->d_w, g->M, g->T, g->T16, app);
+  else if (op == SBIE_OP_SP)
+    hipLaunchKernelGGL((k_far_strengths<R, SBIE_OP_SP>), pre, blk, 0, s, g->d_part, d_dens, g->d_x, g->d_y, g->d_z,
+                       g->d_nx, g->d_ny, g->d_nz, g->d_w, g->M, g->T, g->T16, app);
   else
     hipLaunchKernelGGL((k_far_strengths<R, SBIE_OP_D>), pre, blk, 0, s, g->d_part, d_dens, g->d_x, g->d_y, g->d_z,
                        g->d_nx, g->d_ny, g->d_nz, g->d_w, g->M, g->T, g->T16, app);
@@ -456,10 +528,14 @@ sbie_status launch_far(sbie_geom* g, int op, const double* d_dens, const R* geo,
   const int nb = g->T16 / 16;
   const int blocks = nb < PS::GB ? nb : PS::GB;
   const dim3 grid((unsigned)((int64_t)g->M * RG * g->nsplit)), wg((unsigned)(64 * (blocks < PS::WMAX ? blocks : PS::WMAX)));
-  const size_t lds = (size_t)kChunk * (80 + (op == SBIE_OP_S ? 16 : 80) + 16 * (wg.x / 64)) * sizeof(R);
+  const int napp = op == SBIE_OP_S ? 16 : (op == SBIE_OP_SP ? 128 : 80);
+  const size_t lds = (size_t)kChunk * (80 + napp + 16 * (wg.x / 64)) * sizeof(R);
   R* rev = reinterpret_cast<R*>(g->d_rev);
   if (op == SBIE_OP_S)
     hipLaunchKernelGGL((k_far_pairs<R, SBIE_OP_S>), grid, wg, lds, s, geo, app, g->d_part, g->d_x, g->d_y, g->d_z,
+                       g->d_excl, g->excl_words, g->M, g->T, g->T16, g->N, g->nsplit, RG, g->d_partial, rev);
+  else if (op == SBIE_OP_SP)
+    hipLaunchKernelGGL((k_far_pairs<R, SBIE_OP_SP>), grid, wg, lds, s, geo, app, g->d_part, g->d_x, g->d_y, g->d_z,
                        g->d_excl, g->excl_words, g->M, g->T, g->T16, g->N, g->nsplit, RG, g->d_partial, rev);
   else
     hipLaunchKernelGGL((k_far_pairs<R, SBIE_OP_D>), grid, wg, lds, s, geo, app, g->d_part, g->d_x, g->d_y, g->d_z,

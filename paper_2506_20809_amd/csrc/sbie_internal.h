@@ -90,10 +90,21 @@ struct sbie_geom {
   double* d_stk_E = nullptr;      // [2][4M][K] exterior coefficients and their u-derivative form
   double* d_stk_U = nullptr;      // [4][4M][T] value, d/du, d/dv, d/dphi at the nodes
   double* d_stk_src = nullptr;    // [N][8] far-field records / [nsplit][3][N] partials follow
-  double* d_stk_part = nullptr;   // [nsplit][3][N]
-  double* d_stk_self = nullptr;   // [3][N]
-  double* d_stk_near = nullptr;   // [3][N]
-  double* d_stk_io = nullptr;     // [2][3][N] staging of host densities and velocities
+  double* d_stk_part = nullptr;   // [nsplit][4][N] (velocity and pressure)
+  double* d_stk_self = nullptr;   // [4][N]
+  double* d_stk_near = nullptr;   // [4][N]
+  double* d_stk_io = nullptr;     // [7][N] staging of host densities and velocities
+  // Stokes double layer (stokes_dl.hip), in its own block carved on first use
+  char* sdl_blk = nullptr;
+  double* d_sdl_f = nullptr;      // [13M][T] transform inputs of the 13 expansion sets
+  double* d_sdl_c = nullptr;      // [13M][K] coefficients
+  double* d_sdl_E = nullptr;      // [2][13M][K] exterior coefficients and their d/du form
+  double* d_sdl_U = nullptr;      // [3][13M][T] d/du (exterior), d/dv, d/dphi at the nodes
+  double* d_sdl_src = nullptr;    // [N][8] far records (node - centre, W mu, nu_x, nu_y)
+  double* d_sdl_part = nullptr;   // [nsplit][3][N]
+  double* d_sdl_self = nullptr;   // [3][N]
+  double* d_sdl_near = nullptr;   // [3][N]
+  double* d_sdl_io = nullptr;     // [6][N] host staging
   double* d_wS = nullptr;         // [M][p+1] sqrt(u0^2 -+ v_j^2)
   double* d_lam = nullptr;        // [M][Kh][4]: D principal value, D exterior, S, 1/Q_n^m(z0)
   double* d_ab = nullptr;         // [Kh][2] normalised Ferrers recurrence coefficients
@@ -122,8 +133,8 @@ struct sbie_geom {
   double* d_srec64 = nullptr;
   // per-apply strengths per block: S 16 values W sigma_j at (s*nb + b)*16;
   // D 80 values at (s*nb + b)*80: (W mu nu_j, 0) in lane order, then -W mu nu_j.o_j
-  float* d_fstr32 = nullptr;      // [M*T16*5]
-  double* d_fstr64 = nullptr;
+  float* d_fstr32 = nullptr;      // [M*T16*8] per-apply far strengths (S 1, D 5, S' 8 per source)
+  double* d_fstr64 = nullptr;     // [M*T16*8]
   double* d_rcp = nullptr;        // [kRcpN] reciprocals 1/k for the near-field recurrences
   // pair-symmetric far field: reverse sums [M][H+1][RG][T] (FP64, or FP32 in
   // the first half for the mixed path), H = (M-1)/2, RG target-row groups
@@ -218,6 +229,11 @@ sbie_status next_timing_set(sbie_geom* g, hipEvent_t** ev);
 // fork the side stream from s (after all work queued on s) and join it back
 sbie_status fork_side(sbie_geom* g, hipStream_t s);
 sbie_status join_side(sbie_geom* g, hipStream_t s);
+
+// Stokes double layer (stokes_dl.hip); density and output [3][N]
+sbie_status apply_stokes_dl(sbie_geom* g, int prec, const double* d_dens, double* d_out, hipStream_t s,
+                            uint32_t parts, bool timed);
+sbie_status stokes_dl_staging(sbie_geom* g, double** io);
 
 // S' and D' (deriv.hip); apply_laplace dispatches these ops to it
 sbie_status apply_normal(sbie_geom* g, int op, int prec, const double* d_dens, double* d_out, hipStream_t s,

@@ -394,8 +394,9 @@ sbie_status carve_geometry(sbie_geom* g, Carver& c) {
   SBIE_TRY(c.take(&g->d_out, N));
   SBIE_TRY(c.take(&g->d_srec64, 5 * n16));
   SBIE_TRY(c.take(&g->d_srec32, 5 * n16));
-  SBIE_TRY(c.take(&g->d_fstr64, 5 * n16));
-  SBIE_TRY(c.take(&g->d_fstr32, 5 * n16));
+  // per-apply far strengths: up to 8 values per padded source (S'), in FP64 and FP32
+  SBIE_TRY(c.take(&g->d_fstr64, 8 * n16));
+  SBIE_TRY(c.take(&g->d_fstr32, 8 * n16));
   SBIE_TRY(c.take(&g->d_rcp, (size_t)kRcpN));
   // reverse sums of the pair-symmetric far field (matrix-core path, T >= 32)
   const size_t nrev = T >= 32 ? (size_t)M * ((M - 1) / 2 + 1) * far_row_groups(g, true) * T : 1;

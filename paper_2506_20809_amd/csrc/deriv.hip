@@ -308,9 +308,9 @@ sbie_status apply_normal(sbie_geom* g, int op, int prec, const double* d_dens, d
     SBIE_HIP(hipGetLastError());
   }
   if (timed) SBIE_HIP(hipEventRecord(ev[7], s));
-  // S' far field on the pair-symmetric matrix-core kernel (T >= 32), D' and
-  // small T on the vector-unit sums
-  const bool pairs = op == SBIE_OP_SP && T >= 32;
+  // far field on the pair-symmetric matrix-core kernel (T >= 32), small T on
+  // the vector-unit sums
+  const bool pairs = T >= 32;
   if ((parts & SBIE_PARTS_FAR) && pairs) {
     sbie_status st = far_mfma(g, op, prec, d_dens, s, timed ? ev[3] : nullptr, timed ? ev[4] : nullptr);
     if (st) return st;

@@ -96,7 +96,10 @@ struct PairShape {
 // derivative along the target normal, strengths q = W sigma) the forward dot
 // q_b nu_a.(x - y) is [nu_a/2  nu_a.D] . [-2 q_b o  q_b] and the reverse dot
 // q_a nu_b.(x - y) is [q_a D  q_a] . [nu_b  -nu_b.o]; the forward kernel is
-// q_b nu_a.(y - x)/r^3, the reverse q_a nu_b.(x - y)/r^3.
+// q_b nu_a.(y - x)/r^3, the reverse q_a nu_b.(x - y)/r^3.  D' has the
+// symmetric kernel B = nu_a.nu_b/r^3 - 3 (nu_a.d)(nu_b.d)/r^5, d = x - y, with
+// nu_a.nu_b = [nu_a 0] . [nu_b  -nu_b.o], nu_b.d = [D 1] . [nu_b  -nu_b.o] and
+// nu_a.d = [nu_a/2  nu_a.D] . [-2o 1]; forward q_b B, reverse q_a B.
 //
 // Rows of a are padded to 16 with zero-strength points at a's centre.
 template <typename R, int OP>
@@ -109,6 +112,7 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
   using MM = Mfma<R>;
   using V = typename MM::V;
   constexpr int GEO = 80, APP = (OP == SBIE_OP_S) ? 16 : (OP == SBIE_OP_SP ? 128 : 80);
+  constexpr bool NORMALS = OP == SBIE_OP_SP || OP == SBIE_OP_DP;  // rows carry their normals
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* lds_geo = reinterpret_cast<R*>(smem_raw);
   R* lds_app = lds_geo + kChunk * GEO;
@@ -154,11 +158,13 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
 #pragma unroll
     for (int c = 0; c < 3; ++c)
       da[rb][c] = rb >= nrb ? R(0)
-                  : OP == SBIE_OP_D ? app[blk * 80 + 16 * c + li]
+                  : (OP == SBIE_OP_D || OP == SBIE_OP_DP) ? app[blk * 80 + 16 * c + li]
                   : OP == SBIE_OP_SP ? app[blk * 128 + 64 + 16 * c + li] : R(0);
 #pragma unroll
     for (int e = 0; e < 4; ++e)
-      qa[rb][e] = (OP == SBIE_OP_S && rb < nrb) ? app[blk * 16 + MM::row(lg, e)] : R(0);
+      qa[rb][e] = rb >= nrb ? R(0)
+                  : OP == SBIE_OP_S ? app[blk * 16 + MM::row(lg, e)]
+                  : OP == SBIE_OP_DP ? app[blk * 80 + 64 + MM::row(lg, e)] : R(0);
     qr[rb] = (OP == SBIE_OP_SP && rb < nrb) ? app[blk * 128 + 48 + li] : R(0);
   }
 
@@ -187,12 +193,13 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
       const double dx = tc[rb][0] - cx, dy = tc[rb][1] - cy, dz = tc[rb][2] - cz;
       const double dl = lg == 0 ? dx : (lg == 1 ? dy : dz);
       aop[rb] = (R)(lg < 3 ? dl : fma(dz, dz, fma(dy, dy, dx * dx)));
-      if (OP == SBIE_OP_D || OP == SBIE_OP_SP) {
+      if (OP == SBIE_OP_D || NORMALS) {
         const double dd = fma((double)da[rb][2], dz, fma((double)da[rb][1], dy, (double)da[rb][0] * dx));
         const R dc = lg == 0 ? da[rb][0] : (lg == 1 ? da[rb][1] : da[rb][2]);
         a3[rb] = lg < 3 ? R(0.5) * dc : (R)dd;
       }
       if (OP == SBIE_OP_SP) aq[rb] = lg < 3 ? (R)((double)qr[rb] * dl) : qr[rb];
+      if (OP == SBIE_OP_DP) aq[rb] = lg < 3 ? (R)dl : R(1);  // [D 1]
     }
     R tmp[RB][4];
 #pragma unroll
@@ -228,7 +235,7 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
           R rsum = R(0);  // reverse sum for source column li over this lane's rows
           // row blocks in batches of G: the batch's matrix-core products first,
           // then its vector work (G bounded by the registers)
-          constexpr int G = PairShape<R>::batch(OP == SBIE_OP_S);
+          constexpr int G = OP == SBIE_OP_DP ? 2 : PairShape<R>::batch(OP == SBIE_OP_S);  // D': four products per block
           if (OP == SBIE_OP_S) {
             const R qb = lds_app[ib * 16 + li];
 #pragma unroll
@@ -245,6 +252,35 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
                     const R ri = MM::rsq(r2[j][e]);
                     tmp[g0 + j][e] = fma(qb, ri, tmp[g0 + j][e]);
                     rsum = fma(qa[g0 + j][e], ri, rsum);
+                  }
+            }
+          } else if (OP == SBIE_OP_DP) {
+            const R bn = lds_app[ib * 80 + lane];
+            const R qb = lds_app[ib * 80 + 64 + li];
+            const V zero = {R(0), R(0), R(0), R(0)};
+#pragma unroll
+            for (int g0 = 0; g0 < NR; g0 += G) {
+              V r2[G], nn[G], nyd[G], nxd[G];
+#pragma unroll
+              for (int j = 0; j < G; ++j)
+                if (g0 + j < NR) {
+                  const R an = lg == 0 ? da[g0 + j][0] : (lg == 1 ? da[g0 + j][1] : (lg == 2 ? da[g0 + j][2] : R(0)));
+                  r2[j] = MM::mma(aop[g0 + j], bv, cinit);
+                  nn[j] = MM::mma(an, bn, zero);
+                  nyd[j] = MM::mma(aq[g0 + j], bn, zero);
+                  nxd[j] = MM::mma(a3[g0 + j], bv, zero);
+                }
+#pragma unroll
+              for (int j = 0; j < G; ++j)
+                if (g0 + j < NR)
+#pragma unroll
+                  for (int e = 0; e < 4; ++e) {
+                    const R ri = MM::rsq(r2[j][e]);
+                    const R ri2 = ri * ri;
+                    const R w = fma(R(-3) * nyd[j][e], nxd[j][e] * ri2, nn[j][e]);
+                    const R bk = w * ri2 * ri;
+                    tmp[g0 + j][e] = fma(qb, bk, tmp[g0 + j][e]);
+                    rsum = fma(qa[g0 + j][e], bk, rsum);
                   }
             }
           } else if (OP == SBIE_OP_SP) {
@@ -325,6 +361,24 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
                     const R ri = MM::rsq(r2[e]);
                     tmp[rb][e] = fma(qb, ri, tmp[rb][e]);
                     rsum = fma(qa[rb][e], ri, rsum);
+                  }
+                } else if (OP == SBIE_OP_DP) {
+                  const V zero = {R(0), R(0), R(0), R(0)};
+                  const R bn = lds_app[ib * 80 + lane];
+                  const R qb = lds_app[ib * 80 + 64 + li];
+                  const V r2 = MM::mma(aop[rb], bv, cinit);
+                  const R an = lg == 0 ? da[rb][0] : (lg == 1 ? da[rb][1] : (lg == 2 ? da[rb][2] : R(0)));
+                  const V nn = MM::mma(an, bn, zero);
+                  const V nyd = MM::mma(aq[rb], bn, zero);
+                  const V nxd = MM::mma(a3[rb], bv, zero);
+#pragma unroll
+                  for (int e = 0; e < 4; ++e) {
+                    const R ri = MM::rsq(r2[e]);
+                    const R ri2 = ri * ri;
+                    const R w = fma(R(-3) * nyd[e], nxd[e] * ri2, nn[e]);
+                    const R bk = w * ri2 * ri;
+                    tmp[rb][e] = fma(qb, bk, tmp[rb][e]);
+                    rsum = fma(qa[rb][e], bk, rsum);
                   }
                 } else if (OP == SBIE_OP_SP) {
                   const V zero = {R(0), R(0), R(0), R(0)};
@@ -450,7 +504,7 @@ __global__ void k_far_records(const Particle* __restrict__ part, const double* _
 
 // Per-apply source strengths: S W sigma per source; D per block (W mu nu, 0) in
 // lane order and -W mu nu.o; S' per block (-2 q o, q) and (nu, -nu.o) in lane
-// order, q = W sigma.
+// order, q = W sigma; D' per block (nu, -nu.o) in lane order and q = W mu.
 template <typename R, int OP>
 __global__ void k_far_strengths(const Particle* __restrict__ part, const double* __restrict__ dens,
                                 const double* __restrict__ x, const double* __restrict__ y,
@@ -468,6 +522,22 @@ __global__ void k_far_strengths(const Particle* __restrict__ part, const double*
   }
   if (OP == SBIE_OP_S) {
     app[t] = (R)wq;
+  } else if (OP == SBIE_OP_DP) {
+    double ox = 0.0, oy = 0.0, oz = 0.0, n0 = 0.0, n1 = 0.0, n2 = 0.0;
+    if (q < T) {
+      ox = x[g] - part[s].c[0];
+      oy = y[g] - part[s].c[1];
+      oz = z[g] - part[s].c[2];
+      n0 = nx[g];
+      n1 = ny[g];
+      n2 = nz[g];
+    }
+    R* b = app + (t / 16) * 80 + (t % 16);
+    b[0] = (R)n0;
+    b[16] = (R)n1;
+    b[32] = (R)n2;
+    b[48] = (R)(-fma(n2, oz, fma(n1, oy, n0 * ox)));
+    b[64] = (R)wq;
   } else if (OP == SBIE_OP_SP) {
     double ox = 0.0, oy = 0.0, oz = 0.0, n0 = 0.0, n1 = 0.0, n2 = 0.0;
     if (q < T) {
@@ -518,6 +588,9 @@ sbie_status launch_far(sbie_geom* g, int op, const double* d_dens, const R* geo,
   else if (op == SBIE_OP_SP)
     hipLaunchKernelGGL((k_far_strengths<R, SBIE_OP_SP>), pre, blk, 0, s, g->d_part, d_dens, g->d_x, g->d_y, g->d_z,
                        g->d_nx, g->d_ny, g->d_nz, g->d_w, g->M, g->T, g->T16, app);
+  else if (op == SBIE_OP_DP)
+    hipLaunchKernelGGL((k_far_strengths<R, SBIE_OP_DP>), pre, blk, 0, s, g->d_part, d_dens, g->d_x, g->d_y, g->d_z,
+                       g->d_nx, g->d_ny, g->d_nz, g->d_w, g->M, g->T, g->T16, app);
   else
     hipLaunchKernelGGL((k_far_strengths<R, SBIE_OP_D>), pre, blk, 0, s, g->d_part, d_dens, g->d_x, g->d_y, g->d_z,
                        g->d_nx, g->d_ny, g->d_nz, g->d_w, g->M, g->T, g->T16, app);
@@ -536,6 +609,9 @@ sbie_status launch_far(sbie_geom* g, int op, const double* d_dens, const R* geo,
                        g->d_excl, g->excl_words, g->M, g->T, g->T16, g->N, g->nsplit, RG, g->d_partial, rev);
   else if (op == SBIE_OP_SP)
     hipLaunchKernelGGL((k_far_pairs<R, SBIE_OP_SP>), grid, wg, lds, s, geo, app, g->d_part, g->d_x, g->d_y, g->d_z,
+                       g->d_excl, g->excl_words, g->M, g->T, g->T16, g->N, g->nsplit, RG, g->d_partial, rev);
+  else if (op == SBIE_OP_DP)
+    hipLaunchKernelGGL((k_far_pairs<R, SBIE_OP_DP>), grid, wg, lds, s, geo, app, g->d_part, g->d_x, g->d_y, g->d_z,
                        g->d_excl, g->excl_words, g->M, g->T, g->T16, g->N, g->nsplit, RG, g->d_partial, rev);
   else
     hipLaunchKernelGGL((k_far_pairs<R, SBIE_OP_D>), grid, wg, lds, s, geo, app, g->d_part, g->d_x, g->d_y, g->d_z,

@@ -208,40 +208,27 @@ __device__ inline void expansion_derivatives(const SpheroidalPoint& q, bool obla
     fb1 = qN1;
     double Q[PMAX + 4];
     q_column<PMAX>(u, sgn, N1, m, qN, qN1, rcp, Q);
-    // normalised Ferrers functions of v through degree p+1
-    double Pb[PMAX + 3];
-    {
-      double p2 = 0.0, p1 = pbar;
-#pragma unroll
-      for (int n = 0; n <= PMAX + 1; ++n) {
-        double pn = 0.0;
-        if (n == m) {
-          pn = pbar;
-        } else if (n == m + 1) {
-          pn = sqrt(2.0 * m + 3.0) * v * pbar;
-          p2 = p1;
-          p1 = pn;
-        } else if (n > m + 1 && n <= p + 1) {
-          const int h = n * (n + 1) / 2 + m;
-          pn = ab[2 * h] * (v * p1 - ab[2 * h + 1] * p2);
-          p2 = p1;
-          p1 = pn;
-        }
-        Pb[n] = pn;
-      }
-    }
     double vc[NSET], vs[NSET], uc[NSET], us[NSET], wc[NSET], ws[NSET];
 #pragma unroll
     for (int s = 0; s < NSET; ++s) vc[s] = vs[s] = uc[s] = us[s] = wc[s] = ws[s] = 0.0;
+    // normalised Ferrers functions of v rolled forward in n: P_{n-1}, P_n and
+    // (for the v-derivative) P_{n+1}
+    double pm1 = 0.0, pn = pbar;
 #pragma unroll
     for (int n = 0; n <= PMAX; ++n) {
       if (n >= m && n <= p) {
         const int h = n * (n + 1) / 2 + m;
+        double pn1;
+        if (n == m) {
+          pn1 = sqrt(2.0 * m + 3.0) * v * pbar;
+        } else {
+          const int h1 = (n + 1) * (n + 2) / 2 + m;
+          pn1 = ab[2 * h1] * (v * pn - ab[2 * h1 + 1] * pm1);
+        }
         const double sc = L[h * 4 + 3];
         const double qr = Q[n] * sc;
         const double dq = ((-sgn) * (double)(n - m + 1) * Q[n + 1] - (double)(n + 1) * u * Q[n]) * inv_w * sc;
-        const double pn = Pb[n];
-        const double dpn = ((double)(n + 1) * v * pn - cd[h] * Pb[n + 1]) * inv_omv2;
+        const double dpn = ((double)(n + 1) * v * pn - cd[h] * pn1) * inv_omv2;
         const double t0 = pn * qr, t1 = pn * dq, t2 = dpn * qr;
 #pragma unroll
         for (int s = 0; s < NSET; ++s) {
@@ -256,6 +243,8 @@ __device__ inline void expansion_derivatives(const SpheroidalPoint& q, bool obla
             ws[s] = fma(es, t2, ws[s]);
           }
         }
+        pm1 = pn;
+        pn = pn1;
       }
     }
     const double f = m == 0 ? 1.0 : 1.41421356237309504880;

@@ -168,8 +168,9 @@ __global__ void k_scale_coef(const double* __restrict__ coef, const double* __re
 
 // ---------------------------------------------------------------- near field
 
-// One wave per (target particle, 64 target nodes).  Each lane maps its target
-// into the frame of every near source i (ascending i), finds (u, v, phi) from
+// One wave per (target particle, 64 target nodes, quarter of its near-source
+// list).  Each lane maps its target into the frame of every near source i of
+// the quarter (ascending i), finds (u, v, phi) from
 // the focal distances and sums E_l Q_n^|m|(u)/Q_n^|m|(u0) Y_l(v, phi).  The
 // paper's Legendre algorithm (continued fraction for Q_N/Q_{N-1}, Casoratian,
 // backward recurrence; Section 2.3) gives Q_N and Q_{N+1} for orders 0 and 1
@@ -183,16 +184,18 @@ __global__ __launch_bounds__(64) void k_near_f64(
     const double* __restrict__ z, const int32_t* __restrict__ near_ptr,
     const int32_t* __restrict__ near_src, const double* __restrict__ E,
     const double* __restrict__ lam, const double* __restrict__ ab, const double* __restrict__ rcp, int p,
-    int T, int chunks, unsigned* status, double* __restrict__ unear) {
-  const int j = blockIdx.x / chunks;
-  const int t = (blockIdx.x - j * chunks) * 64 + threadIdx.x;
+    int T, int chunks, int64_t Nn, unsigned* status, double* __restrict__ unear) {
+  const int q4 = blockIdx.x % kNearSplit, rest = blockIdx.x / kNearSplit;
+  const int j = rest / chunks;
+  const int t = (rest - j * chunks) * 64 + threadIdx.x;
   const bool live = t < T;
   const int64_t g = (int64_t)j * T + (live ? t : 0);
   const double X0 = x[g], X1 = y[g], X2 = z[g];
   const int K = (p + 1) * (p + 1), Kh = (p + 1) * (p + 2) / 2, N = p + 1;
   double acc = 0.0;
   unsigned bad = 0u;
-  const int s_begin = near_ptr[j], s_end = near_ptr[j + 1];
+  const int n0 = near_ptr[j], nn = near_ptr[j + 1] - n0;
+  const int s_begin = n0 + (nn * q4) / kNearSplit, s_end = n0 + (nn * (q4 + 1)) / kNearSplit;
   for (int s = s_begin; s < s_end; ++s) {
     const int i = near_src[s];
     const Particle P = part[i];
@@ -283,7 +286,7 @@ __global__ __launch_bounds__(64) void k_near_f64(
     }
   }
   if (bad) atomicOr(status, bad);
-  if (live) unear[g] = acc;
+  if (live) unear[(size_t)q4 * Nn + g] = acc;
 }
 
 // ---------------------------------------------------------------- far field (FP64)
@@ -388,7 +391,8 @@ __global__ void k_assemble_f64(const double* __restrict__ uself, const double* _
   if (g >= N) return;
   double u = 0.0;
   if (parts & SBIE_PARTS_SELF) u += uself[g];
-  if (parts & SBIE_PARTS_NEAR) u += unear[g];
+  if (parts & SBIE_PARTS_NEAR)
+    for (int q = 0; q < kNearSplit; ++q) u += unear[(size_t)q * N + g];
   if (parts & SBIE_PARTS_FAR) {
     double f = 0.0;
     for (int s = 0; s < nsplit; ++s) f += partial[(size_t)s * N + g];
@@ -428,10 +432,9 @@ sbie_status launch_gemm32(const double* A, int lda, const float* B, int ldb, dou
 template <int PMAX>
 void launch_near(sbie_geom* g, hipStream_t s) {
   const int chunks = (g->T + 63) / 64;
-  hipLaunchKernelGGL(k_near_f64<PMAX>, dim3(g->M * chunks), dim3(64), 0, s, g->d_part, g->d_x, g->d_y, g->d_z,
-                     g->d_near_ptr, g->d_near_src, g->d_E, g->d_lam, g->d_ab, g->d_rcp, g->p, g->T, chunks,
-                     g->d_status,
-                     g->d_unear);
+  hipLaunchKernelGGL(k_near_f64<PMAX>, dim3(g->M * chunks * kNearSplit), dim3(64), 0, s, g->d_part, g->d_x,
+                     g->d_y, g->d_z, g->d_near_ptr, g->d_near_src, g->d_E, g->d_lam, g->d_ab, g->d_rcp, g->p, g->T,
+                     chunks, g->N, g->d_status, g->d_unear);
 }
 
 }  // namespace

@@ -78,19 +78,21 @@ __global__ void k_normal_scale(const double* __restrict__ coef, const double* __
   }
 }
 
-// Near part: one wave per (target particle, 64 target nodes); every near
-// source's exterior expansion is differentiated in (u, v, phi) at the mapped
-// target and its lab gradient is projected on the target's normal.
+// Near part: one wave per (target particle, 64 target nodes, quarter of its
+// near-source list); every near source's exterior expansion is differentiated
+// in (u, v, phi) at the mapped target and its lab gradient is projected on the
+// target's normal.
 template <int PMAX>
 __global__ __launch_bounds__(64) void k_near_normal(
     const Particle* __restrict__ part, const double* __restrict__ x, const double* __restrict__ y,
     const double* __restrict__ z, const double* __restrict__ nx, const double* __restrict__ ny,
     const double* __restrict__ nz, const int32_t* __restrict__ near_ptr, const int32_t* __restrict__ near_src,
     const double* __restrict__ E, const double* __restrict__ lam, const double* __restrict__ ab,
-    const double* __restrict__ cd, const double* __restrict__ rcp, int p, int T, int chunks, unsigned* status,
-    double* __restrict__ unear) {
-  const int j = blockIdx.x / chunks;
-  const int t = (blockIdx.x - j * chunks) * 64 + threadIdx.x;
+    const double* __restrict__ cd, const double* __restrict__ rcp, int p, int T, int chunks, int64_t Nn,
+    unsigned* status, double* __restrict__ unear) {
+  const int q4 = blockIdx.x % kNearSplit, rest = blockIdx.x / kNearSplit;
+  const int j = rest / chunks;
+  const int t = (rest - j * chunks) * 64 + threadIdx.x;
   const bool live = t < T;
   const int64_t g = (int64_t)j * T + (live ? t : 0);
   const double X0 = x[g], X1 = y[g], X2 = z[g];
@@ -98,7 +100,9 @@ __global__ __launch_bounds__(64) void k_near_normal(
   const int K = (p + 1) * (p + 1), Kh = (p + 1) * (p + 2) / 2;
   double acc = 0.0;
   unsigned bad = 0u;
-  for (int sidx = near_ptr[j]; sidx < near_ptr[j + 1]; ++sidx) {
+  const int l0 = near_ptr[j], nl = near_ptr[j + 1] - l0;
+  const int s_begin = l0 + (nl * q4) / kNearSplit, s_end = l0 + (nl * (q4 + 1)) / kNearSplit;
+  for (int sidx = s_begin; sidx < s_end; ++sidx) {
     const int i = near_src[sidx];
     const Particle P = part[i];
     const SpheroidalPoint q = to_spheroidal(P, X0, X1, X2, true, &bad);
@@ -110,7 +114,7 @@ __global__ __launch_bounds__(64) void k_near_normal(
     acc += gr[0] * n0 + gr[1] * n1 + gr[2] * n2;
   }
   if (bad) atomicOr(status, bad);
-  if (live) unear[g] = acc;
+  if (live) unear[(size_t)q4 * Nn + g] = acc;
 }
 
 // Far part: the differentiated kernels summed over the far source nodes, with
@@ -210,7 +214,8 @@ __global__ void k_normal_assemble(const double* __restrict__ uself, const double
   const int i = (int)(g / T), j = (int)((g - (int64_t)i * T) / Nphi);
   double u = 0.0;
   if (parts & SBIE_PARTS_SELF) u += uself[g] / wS[(size_t)i * (p + 1) + j];
-  if (parts & SBIE_PARTS_NEAR) u += unear[g];
+  if (parts & SBIE_PARTS_NEAR)
+    for (int q = 0; q < kNearSplit; ++q) u += unear[(size_t)q * N + g];
   if (parts & SBIE_PARTS_FAR) {
     double f = 0.0;
     for (int s = 0; s < nsplit; ++s) f += partial[(size_t)s * N + g];
@@ -231,9 +236,9 @@ __global__ void k_normal_assemble(const double* __restrict__ uself, const double
 template <int PMAX>
 void launch_near_normal(sbie_geom* g, hipStream_t s) {
   const int chunks = (g->T + 63) / 64;
-  hipLaunchKernelGGL(k_near_normal<PMAX>, dim3(g->M * chunks), dim3(64), 0, s, g->d_part, g->d_x, g->d_y, g->d_z,
-                     g->d_nx, g->d_ny, g->d_nz, g->d_near_ptr, g->d_near_src, g->d_E, g->d_lam, g->d_ab, g->d_cd,
-                     g->d_rcp, g->p, g->T, chunks, g->d_status, g->d_unear);
+  hipLaunchKernelGGL(k_near_normal<PMAX>, dim3(g->M * chunks * kNearSplit), dim3(64), 0, s, g->d_part, g->d_x,
+                     g->d_y, g->d_z, g->d_nx, g->d_ny, g->d_nz, g->d_near_ptr, g->d_near_src, g->d_E, g->d_lam,
+                     g->d_ab, g->d_cd, g->d_rcp, g->p, g->T, chunks, g->N, g->d_status, g->d_unear);
 }
 
 template <typename R, int OP>

@@ -29,6 +29,11 @@ struct Particle {
   int pad;
 };
 
+// The near sources of each target particle are split into kNearSplit
+// consecutive ranges, one wave each, whose partial sums the assembly adds in
+// range order (balances particles with many and few neighbours).
+constexpr int kNearSplit = 4;
+
 // Status word written by kernels (bit flags).
 enum : unsigned { kStatNumeric = 1u, kStatOverlap = 2u, kStatExterior = 4u };
 
@@ -119,7 +124,7 @@ struct sbie_geom {
   double* d_cself = nullptr;      // [M][K]
   double* d_E = nullptr;          // [M][K] exterior coefficients
   double* d_uself = nullptr;      // [N]
-  double* d_unear = nullptr;      // [N]
+  double* d_unear = nullptr;      // [kNearSplit][N] near-field partials (source-list quarters)
   double* d_src = nullptr;        // [N][8] far-field source records
   double* d_partial = nullptr;    // [nsplit][N]
   double* d_dens = nullptr;       // [N] staging for host densities

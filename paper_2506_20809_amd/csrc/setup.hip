@@ -387,7 +387,7 @@ sbie_status carve_geometry(sbie_geom* g, Carver& c) {
   SBIE_TRY(c.take(&g->d_cself, (size_t)M * K));
   SBIE_TRY(c.take(&g->d_E, (size_t)M * K));
   SBIE_TRY(c.take(&g->d_uself, N));
-  SBIE_TRY(c.take(&g->d_unear, N));
+  SBIE_TRY(c.take(&g->d_unear, (size_t)kNearSplit * N));
   SBIE_TRY(c.take(&g->d_src, 8 * N));
   SBIE_TRY(c.take(&g->d_partial, (size_t)g->nsplit * N));
   SBIE_TRY(c.take(&g->d_dens, N));

@@ -83,9 +83,9 @@ typedef enum {
 /* sbie_apply flags */
 #define SBIE_DEVICE_PTRS 0x1u  /* density/potential are device pointers */
 #define SBIE_TIMING 0x2u       /* record per-part device times (sbie_geom_timing) */
-#define SBIE_PARTS_SELF 0x10u  /* include the self interaction (Algorithm 1, lines 11-12) */
-#define SBIE_PARTS_NEAR 0x20u  /* include the near field (Algorithm 1, lines 14-15) */
-#define SBIE_PARTS_FAR 0x40u   /* include the far field (Algorithm 1, lines 6-8) */
+#define SBIE_PARTS_SELF 0x10u  /* include the self interaction (self step of Algorithm 1) */
+#define SBIE_PARTS_NEAR 0x20u  /* include the near field (near-field step of Algorithm 1) */
+#define SBIE_PARTS_FAR 0x40u   /* include the far field (far-field step of Algorithm 1) */
 #define SBIE_PARTS_ALL 0x70u   /* 0 also means all parts */
 
 typedef struct sbie_ctx sbie_ctx;
@@ -164,7 +164,7 @@ sbie_status sbie_apply(sbie_geom* g, sbie_op op, sbie_precision prec, int32_t nr
    applies report their numerical failures here. */
 sbie_status sbie_geom_sync(sbie_geom* g, void* stream);
 
-/* Forward transform of Algorithm 1 (line 2) alone: the (p+1)^2 real
+/* Forward transform step of Algorithm 1 alone: the (p+1)^2 real
    spheroidal-harmonic coefficients per particle, index n^2+n+m, of the
    density (op = SBIE_OP_D) or of sqrt(u0^2 -+ v^2) times the density
    (op = SBIE_OP_S, the modified basis of Section 3.2).  density [nrhs][N],

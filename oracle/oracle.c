@@ -685,7 +685,7 @@ static int build_geometry(const double* centres, const double* quats,
   for (int i = 0; i < M; ++i)
     particle_grid(&g->pt[i], p, g->gx, g->gw, g->xyz + 3 * (size_t)i * g->T,
                   g->nrm + 3 * (size_t)i * g->T, g->W + (size_t)i * g->T);
-  /* Algorithm 1, lines 3-4: normalised distances and the near/far split */
+  /* Algorithm 1, near/far split: normalised distances */
   g->near = (uint8_t*)calloc((size_t)M * M, 1);
   int bad = 0;
 #pragma omp parallel for schedule(dynamic)
@@ -743,7 +743,7 @@ int orc_classify(const double* centres, const double* quats, const double* A,
 /* Outputs may be NULL except u.                                              */
 /* ------------------------------------------------------------------------ */
 
-/* per-particle coefficients and exterior coefficients (line 2, lines 11-14) */
+/* per-particle coefficients and exterior coefficients (Algorithm 1: forward transform, self and near-field steps) */
 static int particle_coefficients(const geometry* g, int op, int i,
                                  const double* dens, double* coef_self,
                                  double* E, double complex* Qu0) {
@@ -852,7 +852,7 @@ int orc_apply(const double* centres, const double* quats, const double* A,
   double* E = (double*)malloc(sizeof(double) * (size_t)M * K);
   double complex* Qu0 = (double complex*)malloc(sizeof(double complex) * (size_t)M * Kh);
 
-  /* line 2 and lines 11-12: transform, diagonal spectra, inverse transform */
+  /* Algorithm 1, forward transform and self step: transform, diagonal spectra, inverse transform */
   int err = 0;
 #pragma omp parallel for schedule(dynamic)
   for (int i = 0; i < M; ++i) {
@@ -868,7 +868,7 @@ int orc_apply(const double* centres, const double* quats, const double* A,
   }
   if (err) rc = err;
 
-  /* lines 14-15: neighbours' exterior expansions at the target nodes */
+  /* Algorithm 1, near-field step: neighbours' exterior expansions at the target nodes */
   if (!rc) {
 #pragma omp parallel for schedule(dynamic)
     for (int j = 0; j < M; ++j) {
@@ -890,7 +890,7 @@ int orc_apply(const double* centres, const double* quats, const double* A,
     if (err) rc = err;
   }
 
-  /* lines 6-8: smooth quadrature from far particles, Neumaier-compensated */
+  /* Algorithm 1, far-field step: smooth quadrature from far particles, Neumaier-compensated */
   if (!rc) {
 #pragma omp parallel for schedule(dynamic)
     for (int j = 0; j < M; ++j) {
@@ -912,7 +912,7 @@ int orc_apply(const double* centres, const double* quats, const double* A,
     }
   }
 
-  /* lines 18-19: sum of the three pieces */
+  /* Algorithm 1, assembly step: sum of the three pieces */
   if (!rc) {
     for (size_t gi = 0; gi < N; ++gi) {
       if (u_self) u_self[gi] = us[gi];

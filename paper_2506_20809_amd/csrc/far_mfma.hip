@@ -1,5 +1,5 @@
-// Far-field direct sum (part (d), Section 4.1 smooth quadrature; Algorithm 1,
-// lines 6-8) with the pair distances formed on the matrix cores.
+// Far-field direct sum (part (d), Section 4.1 smooth quadrature; far-field step
+// of Algorithm 1) with the pair distances formed on the matrix cores.
 //
 // For a target t and a source y = c_s + o in source particle s (centre c_s,
 // offset o), with D = t - c_s:

@@ -104,7 +104,7 @@ def test_spectra_parity(ctx, name, p):
 
 @pytest.mark.parametrize("op", [0, 1])
 def test_transform_parity(ctx, op):
-    """Forward transform (Algorithm 1, line 2), modified basis for S."""
+    """Forward transform (the first step of Algorithm 1), modified basis for S."""
     import paper_2506_20809_amd as sbie
 
     for name, p in [("c1", 8), ("c2", 16)]:

@@ -18,6 +18,11 @@
 // added per target unless the source particle is the target's own or in its
 // near field.  FP32 tiles are added into (hi, lo) pairs with TwoSum; the final
 // cross-lane reduction is in FP64.
+//
+// In mixed precision the single and double layers take their K = 4 products
+// on the bf16 matrix cores, each FP32 operand split exactly into three bf16
+// pieces (see split3 below): a 16x16x32 bf16 product gives the FP32 products'
+// values at half the issue time of the 16x16x4 FP32 one.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -32,6 +37,8 @@ constexpr double kInv4PiD = 0.079577471545947667884441881686257181;
 
 using f4 = float __attribute__((ext_vector_type(4)));
 using d4 = double __attribute__((ext_vector_type(4)));
+using u4 = unsigned __attribute__((ext_vector_type(4)));
+using bf8 = __bf16 __attribute__((ext_vector_type(8)));
 
 template <typename R>
 struct Mfma;
@@ -62,6 +69,72 @@ struct Mfma<double> {
     const double e = fma(-h, y, 1.0);
     return fma(0.5 * y, e, y);
   }
+};
+
+// Three-piece bf16 form.  An FP32 value x splits exactly into bf16 pieces
+// x = x_h + x_m + x_l of 8 significant bits each (round to nearest, then twice
+// on the remainder).  Lane group k of a 16x16x32 bf16 product owns eight K
+// slots; term k of a K = 4 contraction a.b takes six of them,
+//     a_h b_h + a_h b_m + a_m b_h + a_h b_l + a_l b_h + a_m b_m,
+// which is a_k b_k less a_m b_l + a_l b_m + a_l b_l (relative size 2^-24 and
+// below).  In registers, two bf16 per dword (low half first):
+//     A = (a_h a_h) (a_m a_h) (a_l a_m) (s6 s7)
+//     B = (b_h b_m) (b_h b_l) (b_h b_m) (t6 t7).
+// The last two slots add one exact FP32 value e per column (the accumulator
+// input of the FP32 form): lane groups 0 and 1 of B hold (e_h e_m) and (e_l 0)
+// against (1 1) and (1 0) in A, the other groups zeros.  Every product is exact
+// in FP32 and the matrix core sums them in FP32.
+__device__ inline unsigned bf16_bits(__bf16 h) { return (unsigned)__builtin_bit_cast(unsigned short, h); }
+
+__device__ inline void split3(float x, unsigned& h, unsigned& m, unsigned& l) {
+  const __bf16 bh = (__bf16)x;
+  const float r = x - (float)bh;
+  const __bf16 bm = (__bf16)r;
+  const __bf16 bl = (__bf16)(r - (float)bm);
+  h = bf16_bits(bh);
+  m = bf16_bits(bm);
+  l = bf16_bits(bl);
+}
+
+// A operand of lane group lg; with `extra` the last slots take the column's e
+__device__ inline u4 split_a(float x, int lg, bool extra) {
+  unsigned h, m, l;
+  split3(x, h, m, l);
+  const unsigned s = !extra ? 0u : (lg == 0 ? 0x3F803F80u : (lg == 1 ? 0x00003F80u : 0u));
+  return u4{h | h << 16, m | h << 16, l | m << 16, s};
+}
+
+// B operand of lane group lg for the value x, with the column's exact extra term e
+__device__ inline u4 split_b(float x, int lg, float e) {
+  unsigned h, m, l, eh, em, el;
+  split3(x, h, m, l);
+  split3(e, eh, em, el);
+  const unsigned t = lg == 0 ? (eh | em << 16) : (lg == 1 ? el : 0u);
+  return u4{h | m << 16, h | l << 16, h | m << 16, t};
+}
+
+// the FP32 value of a B operand's main term
+__device__ inline float join_b(u4 v) {
+  const float h = __builtin_bit_cast(float, v.x << 16);
+  const float m = __builtin_bit_cast(float, v.x & 0xFFFF0000u);
+  const float l = __builtin_bit_cast(float, v.y & 0xFFFF0000u);
+  return (h + m) + l;
+}
+
+__device__ inline f4 mma_x3(u4 a, u4 b) {
+  const f4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), zero, 0, 0, 0);
+}
+
+// Words (R-sized) per 16-source block of the source records (geo) and of the
+// per-apply strengths (app).  The mixed single and double layers keep their B
+// operands in the three-piece form, one u4 per lane; all others one R per
+// lane, the accumulator input per column after the B operand.
+template <typename R, int OP>
+struct FarLayout {
+  static constexpr bool X3 = sizeof(R) == 4 && (OP == SBIE_OP_S || OP == SBIE_OP_D);
+  static constexpr int GEO = X3 ? 256 : 80;
+  static constexpr int APP = OP == SBIE_OP_S ? 16 : (OP == SBIE_OP_SP ? 128 : (X3 ? 256 : 80));
 };
 
 constexpr int kChunk = 40;  // 16-source blocks staged in LDS at a time
@@ -111,7 +184,11 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
                                                    double* __restrict__ fwd, R* __restrict__ rev) {
   using MM = Mfma<R>;
   using V = typename MM::V;
-  constexpr int GEO = 80, APP = (OP == SBIE_OP_S) ? 16 : (OP == SBIE_OP_SP ? 128 : 80);
+  using L = FarLayout<R, OP>;
+  constexpr bool X3 = L::X3;
+  using AOp = typename std::conditional<X3, u4, R>::type;  // A operand of one row block
+  using BOp = typename std::conditional<X3, u4, R>::type;  // B operand of one source block
+  constexpr int GEO = L::GEO, APP = L::APP;
   constexpr bool NORMALS = OP == SBIE_OP_SP || OP == SBIE_OP_DP;  // rows carry their normals
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* lds_geo = reinterpret_cast<R*>(smem_raw);
@@ -135,31 +212,32 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
   const int k0 = (int)((int64_t)P * split / nsplit), k1 = (int)((int64_t)P * (split + 1) / nsplit);
   const Particle& Pa = part[a];
 
-  // target rows of this wave: A-operand rows (lane li) and accumulator rows
-  // target rows of this wave: A-operand rows (lane li) and accumulator rows
-  double tc[RB][3];
-  R da[RB][3];   // double layer: d_a of the A-operand row; S': the normal nu_a
-  R qa[RB][4];   // single layer: strength of the accumulator rows
-  R qr[RB];      // S': strength of the A-operand row
+  // A-operand row li of each row block: lane group lg < 3 keeps component lg
+  // of the target (tcl) and of its d_a resp. nu_a (dal, zero in group 3);
+  // |D|^2 and the dots are summed across the lane groups per partner.
+  // Accumulator rows: the single layer's and D''s strengths (qa), S''s
+  // strength of the A-operand row (qr).
+  double tcl[RB];
+  R dal[RB];
+  R qa[RB][4];
+  R qr[RB];
+  const int cl = lg < 3 ? lg : 0;
+  const double* xyz = cl == 0 ? x : (cl == 1 ? y : z);
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) {
     const int r = (rb0 + rb) * 16 + li;
-    if (rb < nrb && r < T) {
-      const int64_t g = (int64_t)a * T + r;
-      tc[rb][0] = x[g];
-      tc[rb][1] = y[g];
-      tc[rb][2] = z[g];
-    } else {
-      tc[rb][0] = Pa.c[0];
-      tc[rb][1] = Pa.c[1];
-      tc[rb][2] = Pa.c[2];
-    }
+    tcl[rb] = (rb < nrb && r < T) ? xyz[(int64_t)a * T + r] : Pa.c[cl];
     const size_t blk = (size_t)a * nb + (rb < nrb ? rb0 + rb : 0);
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-      da[rb][c] = rb >= nrb ? R(0)
-                  : (OP == SBIE_OP_D || OP == SBIE_OP_DP) ? app[blk * 80 + 16 * c + li]
-                  : OP == SBIE_OP_SP ? app[blk * 128 + 64 + 16 * c + li] : R(0);
+    R dv = R(0);
+    if (rb < nrb && lg < 3) {
+      if constexpr (X3 && OP == SBIE_OP_D)
+        dv = join_b(reinterpret_cast<const u4*>(app + blk * APP)[16 * lg + li]);
+      else if constexpr (OP == SBIE_OP_D || OP == SBIE_OP_DP)
+        dv = app[blk * APP + 16 * lg + li];
+      else if constexpr (OP == SBIE_OP_SP)
+        dv = app[blk * APP + 64 + 16 * lg + li];
+    }
+    dal[rb] = dv;
 #pragma unroll
     for (int e = 0; e < 4; ++e)
       qa[rb][e] = rb >= nrb ? R(0)
@@ -174,6 +252,22 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
 #pragma unroll
     for (int e = 0; e < 4; ++e) acc[rb][e] = lo[rb][e] = R(0);
 
+  // A operand of this lane's row from a value; `extra` picks up the B
+  // column's accumulator term in the three-piece form
+  auto mk_a = [&](double v, bool extra) -> AOp {
+    if constexpr (X3) return split_a((float)v, lg, extra);
+    else return (R)v;
+  };
+  auto ldb = [&](const R* blk) -> BOp {
+    if constexpr (X3) return reinterpret_cast<const u4*>(blk)[lane];
+    else return blk[lane];
+  };
+  // one K = 4 product; the three-piece form carries c in its extra slots
+  auto mm = [&](AOp av, BOp bv, V c) -> V {
+    if constexpr (X3) return mma_x3(av, bv);
+    else return MM::mma(av, bv, c);
+  };
+
   for (int k = k0; k < k1; ++k) {
     const int b = k < H ? (a + 1 + k) % M : a + M / 2;
     const bool need_f = !((excl[(size_t)a * words + (b >> 5)] >> (b & 31)) & 1u);
@@ -183,23 +277,27 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
       for (int t = tid; t < T; t += blockDim.x) rout[t] = R(0);
       continue;
     }
-    const double cx = part[b].c[0], cy = part[b].c[1], cz = part[b].c[2];
+    const double cb = part[b].c[cl];
     // A operands of this wave's rows against partner b: [D |D|^2] with
     // D = x - c_b; double layer also [d_a/2  d_a.D]; S' [nu_a/2  nu_a.D] and
-    // [q_a D  q_a]
-    R aop[RB], a3[RB], aq[RB];
+    // [q_a D  q_a]; D' [D 1]
+    AOp aop[RB], a3[RB];
+    R aq[RB];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
-      const double dx = tc[rb][0] - cx, dy = tc[rb][1] - cy, dz = tc[rb][2] - cz;
-      const double dl = lg == 0 ? dx : (lg == 1 ? dy : dz);
-      aop[rb] = (R)(lg < 3 ? dl : fma(dz, dz, fma(dy, dy, dx * dx)));
+      const double dl = lg < 3 ? tcl[rb] - cb : 0.0;
+      double d2 = dl * dl;
+      d2 += __shfl_xor(d2, 16, 64);
+      d2 += __shfl_xor(d2, 32, 64);
+      aop[rb] = mk_a(lg < 3 ? dl : d2, true);
       if (OP == SBIE_OP_D || NORMALS) {
-        const double dd = fma((double)da[rb][2], dz, fma((double)da[rb][1], dy, (double)da[rb][0] * dx));
-        const R dc = lg == 0 ? da[rb][0] : (lg == 1 ? da[rb][1] : da[rb][2]);
-        a3[rb] = lg < 3 ? R(0.5) * dc : (R)dd;
+        double dd = (double)dal[rb] * dl;
+        dd += __shfl_xor(dd, 16, 64);
+        dd += __shfl_xor(dd, 32, 64);
+        a3[rb] = mk_a(lg < 3 ? (double)(R(0.5) * dal[rb]) : dd, false);
       }
       if (OP == SBIE_OP_SP) aq[rb] = lg < 3 ? (R)((double)qr[rb] * dl) : qr[rb];
-      if (OP == SBIE_OP_DP) aq[rb] = lg < 3 ? (R)dl : R(1);  // [D 1]
+      if (OP == SBIE_OP_DP) aq[rb] = lg < 3 ? (R)dl : R(1);
     }
     R tmp[RB][4];
 #pragma unroll
@@ -229,13 +327,18 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
       auto tiles = [&](auto nr) {
         constexpr int NR = decltype(nr)::value;
         for (int ib = 0; ib < nbc; ++ib) {
-          const R bv = lds_geo[ib * GEO + lane];
-          const R cw = lds_geo[ib * GEO + 64 + li];
-          const V cinit = {cw, cw, cw, cw};
+          const BOp bv = ldb(lds_geo + ib * GEO);
+          V cinit = {R(0), R(0), R(0), R(0)};
+          if constexpr (!X3) {
+            const R cw = lds_geo[ib * GEO + 64 + li];
+            cinit = V{cw, cw, cw, cw};
+          }
+          const V zero = {R(0), R(0), R(0), R(0)};
           R rsum = R(0);  // reverse sum for source column li over this lane's rows
           // row blocks in batches of G: the batch's matrix-core products first,
           // then its vector work (G bounded by the registers)
-          constexpr int G = OP == SBIE_OP_DP ? 2 : PairShape<R>::batch(OP == SBIE_OP_S);  // D': four products per block
+          // (D': four products per block; the double layer's three-piece operands)
+          constexpr int G = (OP == SBIE_OP_DP || (X3 && OP == SBIE_OP_D)) ? 2 : PairShape<R>::batch(OP == SBIE_OP_S);
           if (OP == SBIE_OP_S) {
             const R qb = lds_app[ib * 16 + li];
 #pragma unroll
@@ -243,7 +346,7 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
               V r2[G];
 #pragma unroll
               for (int j = 0; j < G; ++j)
-                if (g0 + j < NR) r2[j] = MM::mma(aop[g0 + j], bv, cinit);
+                if (g0 + j < NR) r2[j] = mm(aop[g0 + j], bv, cinit);
 #pragma unroll
               for (int j = 0; j < G; ++j)
                 if (g0 + j < NR)
@@ -254,21 +357,19 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
                     rsum = fma(qa[g0 + j][e], ri, rsum);
                   }
             }
-          } else if (OP == SBIE_OP_DP) {
+          } else if constexpr (OP == SBIE_OP_DP) {
             const R bn = lds_app[ib * 80 + lane];
             const R qb = lds_app[ib * 80 + 64 + li];
-            const V zero = {R(0), R(0), R(0), R(0)};
 #pragma unroll
             for (int g0 = 0; g0 < NR; g0 += G) {
               V r2[G], nn[G], nyd[G], nxd[G];
 #pragma unroll
               for (int j = 0; j < G; ++j)
                 if (g0 + j < NR) {
-                  const R an = lg == 0 ? da[g0 + j][0] : (lg == 1 ? da[g0 + j][1] : (lg == 2 ? da[g0 + j][2] : R(0)));
-                  r2[j] = MM::mma(aop[g0 + j], bv, cinit);
-                  nn[j] = MM::mma(an, bn, zero);
+                  r2[j] = mm(aop[g0 + j], bv, cinit);
+                  nn[j] = MM::mma(dal[g0 + j], bn, zero);
                   nyd[j] = MM::mma(aq[g0 + j], bn, zero);
-                  nxd[j] = MM::mma(a3[g0 + j], bv, zero);
+                  nxd[j] = mm(a3[g0 + j], bv, zero);
                 }
 #pragma unroll
               for (int j = 0; j < G; ++j)
@@ -283,18 +384,17 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
                     rsum = fma(qa[g0 + j][e], bk, rsum);
                   }
             }
-          } else if (OP == SBIE_OP_SP) {
+          } else if constexpr (OP == SBIE_OP_SP) {
             const R bq = lds_app[ib * 128 + lane];
             const R bn = lds_app[ib * 128 + 64 + lane];
-            const V zero = {R(0), R(0), R(0), R(0)};
 #pragma unroll
             for (int g0 = 0; g0 < NR; g0 += G) {
               V r2[G], df[G], dr[G];
 #pragma unroll
               for (int j = 0; j < G; ++j)
                 if (g0 + j < NR) {
-                  r2[j] = MM::mma(aop[g0 + j], bv, cinit);
-                  df[j] = MM::mma(a3[g0 + j], bq, zero);
+                  r2[j] = mm(aop[g0 + j], bv, cinit);
+                  df[j] = mm(a3[g0 + j], bq, zero);
                   dr[j] = MM::mma(aq[g0 + j], bn, zero);
                 }
 #pragma unroll
@@ -309,19 +409,21 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
                   }
             }
           } else {
-            const R dv = lds_app[ib * 80 + lane];
-            const R dw = lds_app[ib * 80 + 64 + li];
-            const V c2 = {dw, dw, dw, dw};
-            const V zero = {R(0), R(0), R(0), R(0)};
+            const BOp dv = ldb(lds_app + ib * APP);
+            V c2 = zero;
+            if constexpr (!X3) {
+              const R dw = lds_app[ib * 80 + 64 + li];
+              c2 = V{dw, dw, dw, dw};
+            }
 #pragma unroll
             for (int g0 = 0; g0 < NR; g0 += G) {
               V r2[G], df[G], dr[G];
 #pragma unroll
               for (int j = 0; j < G; ++j)
                 if (g0 + j < NR) {
-                  r2[j] = MM::mma(aop[g0 + j], bv, cinit);
-                  df[j] = MM::mma(aop[g0 + j], dv, c2);
-                  dr[j] = MM::mma(a3[g0 + j], bv, zero);
+                  r2[j] = mm(aop[g0 + j], bv, cinit);
+                  df[j] = mm(aop[g0 + j], dv, c2);
+                  dr[j] = mm(a3[g0 + j], bv, zero);
                 }
 #pragma unroll
               for (int j = 0; j < G; ++j)
@@ -367,8 +469,7 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
                   const R bn = lds_app[ib * 80 + lane];
                   const R qb = lds_app[ib * 80 + 64 + li];
                   const V r2 = MM::mma(aop[rb], bv, cinit);
-                  const R an = lg == 0 ? da[rb][0] : (lg == 1 ? da[rb][1] : (lg == 2 ? da[rb][2] : R(0)));
-                  const V nn = MM::mma(an, bn, zero);
+                  const V nn = MM::mma(dal[rb], bn, zero);
                   const V nyd = MM::mma(aq[rb], bn, zero);
                   const V nxd = MM::mma(a3[rb], bv, zero);
 #pragma unroll
@@ -502,9 +603,34 @@ __global__ void k_far_records(const Particle* __restrict__ part, const double* _
   b[64] = (R)fma(oz, oz, fma(oy, oy, ox * ox));
 }
 
+// The same operands in the three-piece form (mixed single and double layers):
+// block b of particle s holds, at (s*nb + b)*256, one u4 per lane 16k + j with
+// term k of [-2o_j 1] and the extra term |o_j|^2.
+__global__ void k_far_records_x3(const Particle* __restrict__ part, const double* __restrict__ x,
+                                 const double* __restrict__ y, const double* __restrict__ z, int M, int T, int T16,
+                                 float* __restrict__ geo) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)M * T16) return;
+  const int s = (int)(t / T16), q = (int)(t - (int64_t)s * T16);
+  double ox = 0.0, oy = 0.0, oz = 0.0;
+  if (q < T) {
+    const int64_t g = (int64_t)s * T + q;
+    ox = x[g] - part[s].c[0];
+    oy = y[g] - part[s].c[1];
+    oz = z[g] - part[s].c[2];
+  }
+  const float o2 = (float)fma(oz, oz, fma(oy, oy, ox * ox));
+  u4* b = reinterpret_cast<u4*>(geo + (t / 16) * 256) + (t % 16);
+  b[0] = split_b((float)(-2.0 * ox), 0, o2);
+  b[16] = split_b((float)(-2.0 * oy), 1, o2);
+  b[32] = split_b((float)(-2.0 * oz), 2, o2);
+  b[48] = split_b(1.0f, 3, o2);
+}
+
 // Per-apply source strengths: S W sigma per source; D per block (W mu nu, 0) in
-// lane order and -W mu nu.o; S' per block (-2 q o, q) and (nu, -nu.o) in lane
-// order, q = W sigma; D' per block (nu, -nu.o) in lane order and q = W mu.
+// lane order and -W mu nu.o (in mixed precision both in the three-piece form);
+// S' per block (-2 q o, q) and (nu, -nu.o) in lane order, q = W sigma; D' per
+// block (nu, -nu.o) in lane order and q = W mu.
 template <typename R, int OP>
 __global__ void k_far_strengths(const Particle* __restrict__ part, const double* __restrict__ dens,
                                 const double* __restrict__ x, const double* __restrict__ y,
@@ -566,20 +692,30 @@ __global__ void k_far_strengths(const Particle* __restrict__ part, const double*
       const double ox = x[g] - part[s].c[0], oy = y[g] - part[s].c[1], oz = z[g] - part[s].c[2];
       dot = fma(dz, oz, fma(dy, oy, dx * ox));
     }
-    R* b = app + (t / 16) * 80 + (t % 16);
-    b[0] = (R)dx;
-    b[16] = (R)dy;
-    b[32] = (R)dz;
-    b[48] = R(0);
-    b[64] = (R)(-dot);
+    if constexpr (FarLayout<R, OP>::X3) {
+      // three-piece form: term k of [d 0] with the extra term -d.o
+      const float e = (float)(-dot);
+      u4* b = reinterpret_cast<u4*>(app + (t / 16) * 256) + (t % 16);
+      b[0] = split_b((float)dx, 0, e);
+      b[16] = split_b((float)dy, 1, e);
+      b[32] = split_b((float)dz, 2, e);
+      b[48] = split_b(0.0f, 3, e);
+    } else {
+      R* b = app + (t / 16) * 80 + (t % 16);
+      b[0] = (R)dx;
+      b[16] = (R)dy;
+      b[32] = (R)dz;
+      b[48] = R(0);
+      b[64] = (R)(-dot);
+    }
   }
 }
 
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
 template <typename R>
-sbie_status launch_far(sbie_geom* g, int op, const double* d_dens, const R* geo, R* app, hipStream_t s,
-                       hipEvent_t ev_begin, hipEvent_t ev_end) {
+sbie_status launch_far(sbie_geom* g, int op, const double* d_dens, const R* geo, const R* geo_x3, R* app,
+                       hipStream_t s, hipEvent_t ev_begin, hipEvent_t ev_end) {
   const int64_t n16 = (int64_t)g->M * g->T16;
   const dim3 pre(cdiv(n16, 256)), blk(256);
   if (op == SBIE_OP_S)
@@ -601,11 +737,19 @@ sbie_status launch_far(sbie_geom* g, int op, const double* d_dens, const R* geo,
   const int nb = g->T16 / 16;
   const int blocks = nb < PS::GB ? nb : PS::GB;
   const dim3 grid((unsigned)((int64_t)g->M * RG * g->nsplit)), wg((unsigned)(64 * (blocks < PS::WMAX ? blocks : PS::WMAX)));
-  const int napp = op == SBIE_OP_S ? 16 : (op == SBIE_OP_SP ? 128 : 80);
-  const size_t lds = (size_t)kChunk * (80 + napp + 16 * (wg.x / 64)) * sizeof(R);
+  int ngeo = 0, napp = 0;
+  switch (op) {
+    case SBIE_OP_S: ngeo = FarLayout<R, SBIE_OP_S>::GEO; napp = FarLayout<R, SBIE_OP_S>::APP; break;
+    case SBIE_OP_D: ngeo = FarLayout<R, SBIE_OP_D>::GEO; napp = FarLayout<R, SBIE_OP_D>::APP; break;
+    case SBIE_OP_SP: ngeo = FarLayout<R, SBIE_OP_SP>::GEO; napp = FarLayout<R, SBIE_OP_SP>::APP; break;
+    default: ngeo = FarLayout<R, SBIE_OP_DP>::GEO; napp = FarLayout<R, SBIE_OP_DP>::APP; break;
+  }
+  const size_t lds = (size_t)kChunk * (ngeo + napp + 16 * (wg.x / 64)) * sizeof(R);
   R* rev = reinterpret_cast<R*>(g->d_rev);
+  const R* geo_s = FarLayout<R, SBIE_OP_S>::X3 ? geo_x3 : geo;
+  const R* geo_d = FarLayout<R, SBIE_OP_D>::X3 ? geo_x3 : geo;
   if (op == SBIE_OP_S)
-    hipLaunchKernelGGL((k_far_pairs<R, SBIE_OP_S>), grid, wg, lds, s, geo, app, g->d_part, g->d_x, g->d_y, g->d_z,
+    hipLaunchKernelGGL((k_far_pairs<R, SBIE_OP_S>), grid, wg, lds, s, geo_s, app, g->d_part, g->d_x, g->d_y, g->d_z,
                        g->d_excl, g->excl_words, g->M, g->T, g->T16, g->N, g->nsplit, RG, g->d_partial, rev);
   else if (op == SBIE_OP_SP)
     hipLaunchKernelGGL((k_far_pairs<R, SBIE_OP_SP>), grid, wg, lds, s, geo, app, g->d_part, g->d_x, g->d_y, g->d_z,
@@ -614,7 +758,7 @@ sbie_status launch_far(sbie_geom* g, int op, const double* d_dens, const R* geo,
     hipLaunchKernelGGL((k_far_pairs<R, SBIE_OP_DP>), grid, wg, lds, s, geo, app, g->d_part, g->d_x, g->d_y, g->d_z,
                        g->d_excl, g->excl_words, g->M, g->T, g->T16, g->N, g->nsplit, RG, g->d_partial, rev);
   else
-    hipLaunchKernelGGL((k_far_pairs<R, SBIE_OP_D>), grid, wg, lds, s, geo, app, g->d_part, g->d_x, g->d_y, g->d_z,
+    hipLaunchKernelGGL((k_far_pairs<R, SBIE_OP_D>), grid, wg, lds, s, geo_d, app, g->d_part, g->d_x, g->d_y, g->d_z,
                        g->d_excl, g->excl_words, g->M, g->T, g->T16, g->N, g->nsplit, RG, g->d_partial, rev);
   SBIE_HIP(hipGetLastError());
   if (ev_end) SBIE_HIP(hipEventRecord(ev_end, s));
@@ -637,14 +781,17 @@ sbie_status far_records(sbie_geom* g, hipStream_t s) {
   hipLaunchKernelGGL(k_far_records<double>, dim3(cdiv(n, 256)), dim3(256), 0, s, g->d_part, g->d_x, g->d_y, g->d_z,
                      g->M, g->T, g->T16, g->d_srec64);
   SBIE_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_far_records_x3, dim3(cdiv(n, 256)), dim3(256), 0, s, g->d_part, g->d_x, g->d_y, g->d_z,
+                     g->M, g->T, g->T16, g->d_srecx);
+  SBIE_HIP(hipGetLastError());
   return SBIE_OK;
 }
 
 sbie_status far_mfma(sbie_geom* g, int op, int prec, const double* d_dens, hipStream_t s, hipEvent_t ev_begin,
                      hipEvent_t ev_end) {
   if (prec == SBIE_MIXED)
-    return launch_far<float>(g, op, d_dens, g->d_srec32, g->d_fstr32, s, ev_begin, ev_end);
-  return launch_far<double>(g, op, d_dens, g->d_srec64, g->d_fstr64, s, ev_begin, ev_end);
+    return launch_far<float>(g, op, d_dens, g->d_srec32, g->d_srecx, g->d_fstr32, s, ev_begin, ev_end);
+  return launch_far<double>(g, op, d_dens, g->d_srec64, nullptr, g->d_fstr64, s, ev_begin, ev_end);
 }
 
 }  // namespace sbie

@@ -121,6 +121,15 @@ __device__ inline float join_b(u4 v) {
   return (h + m) + l;
 }
 
+// v from the lane whose byte address (lane index times 4) is addr
+__device__ inline float lane_value(float v, int addr) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, v)));
+}
+__device__ inline double lane_value(double v, int addr) {
+  const int2 p = __builtin_bit_cast(int2, v);
+  return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_ds_bpermute(addr, p.x), __builtin_amdgcn_ds_bpermute(addr, p.y)));
+}
+
 __device__ inline f4 mma_x3(u4 a, u4 b) {
   const f4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), zero, 0, 0, 0);
@@ -194,8 +203,10 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
   R* lds_geo = reinterpret_cast<R*>(smem_raw);
   R* lds_app = lds_geo + kChunk * GEO;
   R* lds_rev = lds_app + kChunk * APP;  // [wave][kChunk*16] reverse column sums
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform, for the compiler
   const int li = lane & 15, lg = lane >> 4;
+  const int x16 = (lane ^ 16) << 2, x32 = (lane ^ 32) << 2;  // partner lanes of the column sums
   const int split = blockIdx.x % nsplit, rest = blockIdx.x / nsplit;
   const int rg = rest % RG, a = rest / RG;
   const int nb = T16 / 16;
@@ -203,9 +214,19 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
   const int W = blockDim.x >> 6;
   const int rbg = rg * GB;                                     // first row block of the group
   const int cnt = nb - rbg < GB ? nb - rbg : GB;               // row blocks of the group
-  const int rb0 = rbg + (wave * cnt) / W;                      // this wave's blocks rb0 .. rb0+nrb-1
-  const int nrb = rbg + ((wave + 1) * cnt) / W - rb0;
-  const int nrb_u = __builtin_amdgcn_readfirstlane(nrb);  // wave-uniform, for the compiler
+  // With cnt = base*W + 1 and base < RB, wave w owns base blocks (slots
+  // 0 .. base-1) and every wave holds the last block in slot base, taking it
+  // against its W-th of each chunk's source blocks: every SIMD then carries
+  // the same work.  Otherwise the blocks are spread as evenly as whole blocks
+  // allow.
+  const int base = cnt / W, rem = cnt - base * W;
+  const int nx = (rem == 1 && base > 0 && base < RB) ? 1 : 0;  // shared blocks
+  const int rb0 = nx > 0 ? rbg + wave * base : rbg + (wave * cnt) / W;  // first owned block
+  const int nown = nx > 0 ? base : rbg + ((wave + 1) * cnt) / W - rb0;  // owned blocks
+  const int xb0 = rbg + W * base;                                        // first shared block
+  const int nrb = nown + nx;                                             // slots in use
+  const int nown_u = __builtin_amdgcn_readfirstlane(nown);  // wave-uniform, for the compiler
+  const int nx_u = __builtin_amdgcn_readfirstlane(nx);
   const int H = (M - 1) / 2;
   const bool even = (M & 1) == 0;
   const int P = H + ((even && a < M / 2) ? 1 : 0);
@@ -225,9 +246,10 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
   const double* xyz = cl == 0 ? x : (cl == 1 ? y : z);
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) {
-    const int r = (rb0 + rb) * 16 + li;
+    const int bk = rb < nown ? rb0 + rb : xb0 + (rb - nown);  // block of slot rb (if rb < nrb)
+    const int r = bk * 16 + li;
     tcl[rb] = (rb < nrb && r < T) ? xyz[(int64_t)a * T + r] : Pa.c[cl];
-    const size_t blk = (size_t)a * nb + (rb < nrb ? rb0 + rb : 0);
+    const size_t blk = (size_t)a * nb + (rb < nrb ? bk : 0);
     R dv = R(0);
     if (rb < nrb && lg < 3) {
       if constexpr (X3 && OP == SBIE_OP_D)
@@ -246,11 +268,12 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
     qr[rb] = (OP == SBIE_OP_SP && rb < nrb) ? app[blk * 128 + 48 + li] : R(0);
   }
 
-  R acc[RB][4], lo[RB][4];
+  // forward sums of the accumulator rows over the admitted partners (FP64)
+  double acc[RB][4];
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) acc[rb][e] = lo[rb][e] = R(0);
+    for (int e = 0; e < 4; ++e) acc[rb][e] = 0.0;
 
   // A operand of this lane's row from a value; `extra` picks up the B
   // column's accumulator term in the three-piece form
@@ -285,6 +308,7 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
     R aq[RB];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
+      if (rb >= nown_u + nx_u) break;
       const double dl = lg < 3 ? tcl[rb] - cb : 0.0;
       double d2 = dl * dl;
       d2 += __shfl_xor(d2, 16, 64);
@@ -321,12 +345,12 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
         for (int i = tid; i < nbc * APP / PER; i += blockDim.x) la[i] = as[i];
       }
       __syncthreads();
-      // the tiles of one source block for NR row blocks, unrolled so that the
-      // matrix-core products of all NR blocks are issued before their vector
-      // work (the row-block count is wave-uniform: one branch per wave)
-      auto tiles = [&](auto nr) {
+      // the tiles of source block ib for the first NR slots, unrolled so that
+      // the matrix-core products of all NR blocks are issued before their
+      // vector work (NR is wave-uniform: one branch per wave)
+      auto tiles = [&](auto nr, int ib) {
         constexpr int NR = decltype(nr)::value;
-        for (int ib = 0; ib < nbc; ++ib) {
+        {
           const BOp bv = ldb(lds_geo + ib * GEO);
           V cinit = {R(0), R(0), R(0), R(0)};
           if constexpr (!X3) {
@@ -438,39 +462,50 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
             }
           }
           // sum the four lane groups holding the same column
-          rsum += __shfl_xor(rsum, 16, 64);
-          rsum += __shfl_xor(rsum, 32, 64);
+          rsum += lane_value(rsum, x16);
+          rsum += lane_value(rsum, x32);
           if (lg == 0) lds_rev[wave * (kChunk * 16) + ib * 16 + li] = rsum;
         }
       };
       if constexpr (sizeof(R) == 8) {
         // FP64: one row block at a time under a wave-uniform guard (the
         // batched form does not fit the FP64 operands in registers)
+        const int xlo = nx_u > 0 ? (nbc * wave) / W : 0, xhi = nx_u > 0 ? (nbc * (wave + 1)) / W : 0;
         if (nrb > 0) {
           for (int ib = 0; ib < nbc; ++ib) {
+            const int nr = (ib >= xlo && ib < xhi) ? nown_u + nx_u : nown_u;
             const R bv = lds_geo[ib * GEO + lane];
             const R cw = lds_geo[ib * GEO + 64 + li];
             const V cinit = {cw, cw, cw, cw};
+            const V zero = {R(0), R(0), R(0), R(0)};
+            // the source block's strengths: S W sigma; D (W mu nu, 0) and
+            // -W mu nu.o; S' (-2 q o, q) and (nu, -nu.o); D' (nu, -nu.o) and q
+            R u0, u1 = R(0);
+            if constexpr (OP == SBIE_OP_S) {
+              u0 = lds_app[ib * 16 + li];
+            } else if constexpr (OP == SBIE_OP_SP) {
+              u0 = lds_app[ib * 128 + lane];
+              u1 = lds_app[ib * 128 + 64 + lane];
+            } else {
+              u0 = lds_app[ib * 80 + lane];
+              u1 = lds_app[ib * 80 + 64 + li];
+            }
             R rsum = R(0);
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
-              if (rb < nrb) {
+              if (rb < nr) {
                 if (OP == SBIE_OP_S) {
-                  const R qb = lds_app[ib * 16 + li];
                   const V r2 = MM::mma(aop[rb], bv, cinit);
 #pragma unroll
                   for (int e = 0; e < 4; ++e) {
                     const R ri = MM::rsq(r2[e]);
-                    tmp[rb][e] = fma(qb, ri, tmp[rb][e]);
+                    tmp[rb][e] = fma(u0, ri, tmp[rb][e]);
                     rsum = fma(qa[rb][e], ri, rsum);
                   }
                 } else if (OP == SBIE_OP_DP) {
-                  const V zero = {R(0), R(0), R(0), R(0)};
-                  const R bn = lds_app[ib * 80 + lane];
-                  const R qb = lds_app[ib * 80 + 64 + li];
                   const V r2 = MM::mma(aop[rb], bv, cinit);
-                  const V nn = MM::mma(dal[rb], bn, zero);
-                  const V nyd = MM::mma(aq[rb], bn, zero);
+                  const V nn = MM::mma(dal[rb], u0, zero);
+                  const V nyd = MM::mma(aq[rb], u0, zero);
                   const V nxd = MM::mma(a3[rb], bv, zero);
 #pragma unroll
                   for (int e = 0; e < 4; ++e) {
@@ -478,14 +513,13 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
                     const R ri2 = ri * ri;
                     const R w = fma(R(-3) * nyd[e], nxd[e] * ri2, nn[e]);
                     const R bk = w * ri2 * ri;
-                    tmp[rb][e] = fma(qb, bk, tmp[rb][e]);
+                    tmp[rb][e] = fma(u1, bk, tmp[rb][e]);
                     rsum = fma(qa[rb][e], bk, rsum);
                   }
                 } else if (OP == SBIE_OP_SP) {
-                  const V zero = {R(0), R(0), R(0), R(0)};
                   const V r2 = MM::mma(aop[rb], bv, cinit);
-                  const V df = MM::mma(a3[rb], lds_app[ib * 128 + lane], zero);
-                  const V dr = MM::mma(aq[rb], lds_app[ib * 128 + 64 + lane], zero);
+                  const V df = MM::mma(a3[rb], u0, zero);
+                  const V dr = MM::mma(aq[rb], u1, zero);
 #pragma unroll
                   for (int e = 0; e < 4; ++e) {
                     const R ri = MM::rsq(r2[e]);
@@ -494,12 +528,9 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
                     rsum = fma(dr[e], ri3, rsum);
                   }
                 } else {
-                  const R dv = lds_app[ib * 80 + lane];
-                  const R dw = lds_app[ib * 80 + 64 + li];
-                  const V c2 = {dw, dw, dw, dw};
-                  const V zero = {R(0), R(0), R(0), R(0)};
+                  const V c2 = {u1, u1, u1, u1};
                   const V r2 = MM::mma(aop[rb], bv, cinit);
-                  const V df = MM::mma(aop[rb], dv, c2);
+                  const V df = MM::mma(aop[rb], u0, c2);
                   const V dr = MM::mma(a3[rb], bv, zero);
 #pragma unroll
                   for (int e = 0; e < 4; ++e) {
@@ -511,32 +542,52 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
                 }
               }
             }
-            rsum += __shfl_xor(rsum, 16, 64);
-            rsum += __shfl_xor(rsum, 32, 64);
+            rsum += lane_value(rsum, x16);
+            rsum += lane_value(rsum, x32);
             if (lg == 0) lds_rev[wave * (kChunk * 16) + ib * 16 + li] = rsum;
           }
         } else {
           for (int c = lane; c < nbc * 16; c += 64) lds_rev[wave * (kChunk * 16) + c] = R(0);
         }
-      } else switch (nrb_u) {
-        case 0:
-          for (int c = lane; c < nbc * 16; c += 64) lds_rev[wave * (kChunk * 16) + c] = R(0);
-          break;
-        case 1:
-          tiles(std::integral_constant<int, 1>{});
-          break;
-        case 2:
-          tiles(std::integral_constant<int, 2>{});
-          break;
-        case 3:
-          tiles(std::integral_constant<int, 3>{});
-          break;
-        case 4:
-          tiles(std::integral_constant<int, 4 <= RB ? 4 : RB>{});
-          break;
-        default:
-          tiles(std::integral_constant<int, RB>{});
-          break;
+      } else {
+        // source blocks against the owned slots, and against the shared slot
+        // too in this wave's slice [xlo, xhi) of the chunk; one case per
+        // (wave-uniform) slot count
+        const int xlo = (nbc * wave) / W, xhi = (nbc * (wave + 1)) / W;
+        auto run = [&](auto no) {
+          constexpr int NO = decltype(no)::value;
+          if (nx_u == 0) {
+            for (int ib = 0; ib < nbc; ++ib) tiles(no, ib);
+          } else {
+            constexpr int NT = NO + 1 < RB ? NO + 1 : RB;
+            for (int ib = 0; ib < xlo; ++ib) tiles(no, ib);
+            for (int ib = xlo; ib < xhi; ++ib) tiles(std::integral_constant<int, NT>{}, ib);
+            for (int ib = xhi; ib < nbc; ++ib) tiles(no, ib);
+          }
+        };
+        switch (nown_u) {
+          case 0:
+            for (int c = lane; c < nbc * 16; c += 64) lds_rev[wave * (kChunk * 16) + c] = R(0);
+            break;
+          case 1:
+            run(std::integral_constant<int, 1>{});
+            break;
+          case 2:
+            run(std::integral_constant<int, 2>{});
+            break;
+          case 3:
+            run(std::integral_constant<int, 3>{});
+            break;
+          case 4:
+            if constexpr (RB > 4)
+              run(std::integral_constant<int, 4>{});
+            else  // nown = RB, so no shared block
+              for (int ib = 0; ib < nbc; ++ib) tiles(std::integral_constant<int, RB>{}, ib);
+            break;
+          default:  // nown = RB, so no shared block
+            for (int ib = 0; ib < nbc; ++ib) tiles(std::integral_constant<int, RB>{}, ib);
+            break;
+        }
       }
       __syncthreads();
       // reverse sums over the group's waves, in wave order
@@ -550,31 +601,43 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
       }
     }
     if (!need_f) continue;
-    // forward tile sum added under the exclusion, compensated (TwoSum) in FP32
+    // forward tile sum added under the exclusion
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
+    for (int rb = 0; rb < RB; ++rb) {
+      if (rb >= nown_u + nx_u) break;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const R v = tmp[rb][e];
-        const R sum = acc[rb][e] + v;
-        if (sizeof(R) == 4) {
-          const R bp = sum - acc[rb][e];
-          lo[rb][e] += (acc[rb][e] - (sum - bp)) + (v - bp);
-        }
-        acc[rb][e] = sum;
-      }
+      for (int e = 0; e < 4; ++e) acc[rb][e] += (double)tmp[rb][e];
+    }
   }
-  // forward partials: each row summed over its 16 columns (FP64)
+  // forward partials: each row summed over its 16 columns; the shared blocks'
+  // partials then summed over the waves in wave order (LDS reused: every wave
+  // has passed its last read of the staged operands at the barrier)
+  double* lds_x = reinterpret_cast<double*>(smem_raw);  // [W][nx*16]
+  if (nx_u > 0) __syncthreads();
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      double v = (double)acc[rb][e] + (double)lo[rb][e];
+      double v = acc[rb][e];
 #pragma unroll
       for (int off = 1; off < 16; off <<= 1) v += __shfl_xor(v, off, 64);
-      const int r = (rb0 + rb) * 16 + MM::row(lg, e);
-      if (li == 0 && rb < nrb && r < T) fwd[(size_t)split * N + (int64_t)a * T + r] = v * kInv4PiD;
+      const int row = MM::row(lg, e);
+      if (rb < nown) {
+        const int r = (rb0 + rb) * 16 + row;
+        if (li == 0 && r < T) fwd[(size_t)split * N + (int64_t)a * T + r] = v * kInv4PiD;
+      } else if (rb < nrb && li == 0) {
+        lds_x[wave * (nx * 16) + (rb - nown) * 16 + row] = v;
+      }
     }
+  if (nx_u > 0) {
+    __syncthreads();
+    for (int c = tid; c < nx * 16; c += blockDim.x) {
+      const int r = xb0 * 16 + c;
+      double v = 0.0;
+      for (int w = 0; w < W; ++w) v += lds_x[w * (nx * 16) + c];
+      if (r < T) fwd[(size_t)split * N + (int64_t)a * T + r] = v * kInv4PiD;
+    }
+  }
 }
 
 // Per-geometry source operands.  One thread per (padded) source q of particle

@@ -238,6 +238,13 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
   // |D|^2 and the dots are summed across the lane groups per partner.
   // Accumulator rows: the single layer's and D''s strengths (qa), S''s
   // strength of the A-operand row (qr).
+  // (The three-piece double layer, short of registers, keeps tcl and dal in
+  // LDS after the reverse sums, read back per partner.)
+  constexpr bool STASH = X3 && OP == SBIE_OP_D;
+  double* lds_tc0 = reinterpret_cast<double*>(lds_rev + kChunk * 16 * W);  // [W][RB][64]
+  R* lds_da0 = reinterpret_cast<R*>(lds_tc0 + W * RB * 64);                   // [W][RB][64]
+  double* lds_tc = lds_tc0 + wave * RB * 64 + lane;
+  R* lds_da = lds_da0 + wave * RB * 64 + lane;
   double tcl[RB];
   R dal[RB];
   R qa[RB][4];
@@ -248,7 +255,7 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
   for (int rb = 0; rb < RB; ++rb) {
     const int bk = rb < nown ? rb0 + rb : xb0 + (rb - nown);  // block of slot rb (if rb < nrb)
     const int r = bk * 16 + li;
-    tcl[rb] = (rb < nrb && r < T) ? xyz[(int64_t)a * T + r] : Pa.c[cl];
+    const double tv = (rb < nrb && r < T) ? xyz[(int64_t)a * T + r] : Pa.c[cl];
     const size_t blk = (size_t)a * nb + (rb < nrb ? bk : 0);
     R dv = R(0);
     if (rb < nrb && lg < 3) {
@@ -259,7 +266,13 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
       else if constexpr (OP == SBIE_OP_SP)
         dv = app[blk * APP + 64 + 16 * lg + li];
     }
-    dal[rb] = dv;
+    if constexpr (STASH) {
+      lds_tc[rb * 64] = tv;
+      lds_da[rb * 64] = dv;
+    } else {
+      tcl[rb] = tv;
+      dal[rb] = dv;
+    }
 #pragma unroll
     for (int e = 0; e < 4; ++e)
       qa[rb][e] = rb >= nrb ? R(0)
@@ -309,16 +322,18 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
       if (rb >= nown_u + nx_u) break;
-      const double dl = lg < 3 ? tcl[rb] - cb : 0.0;
+      const double tv = STASH ? lds_tc[rb * 64] : tcl[rb];
+      const double dl = lg < 3 ? tv - cb : 0.0;
       double d2 = dl * dl;
-      d2 += __shfl_xor(d2, 16, 64);
-      d2 += __shfl_xor(d2, 32, 64);
+      d2 += lane_value(d2, x16);
+      d2 += lane_value(d2, x32);
       aop[rb] = mk_a(lg < 3 ? dl : d2, true);
       if (OP == SBIE_OP_D || NORMALS) {
-        double dd = (double)dal[rb] * dl;
-        dd += __shfl_xor(dd, 16, 64);
-        dd += __shfl_xor(dd, 32, 64);
-        a3[rb] = mk_a(lg < 3 ? (double)(R(0.5) * dal[rb]) : dd, false);
+        const R da = STASH ? lds_da[rb * 64] : dal[rb];
+        double dd = (double)da * dl;
+        dd += lane_value(dd, x16);
+        dd += lane_value(dd, x32);
+        a3[rb] = mk_a(lg < 3 ? (double)(R(0.5) * da) : dd, false);
       }
       if (OP == SBIE_OP_SP) aq[rb] = lg < 3 ? (R)((double)qr[rb] * dl) : qr[rb];
       if (OP == SBIE_OP_DP) aq[rb] = lg < 3 ? (R)dl : R(1);
@@ -362,7 +377,7 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
           // row blocks in batches of G: the batch's matrix-core products first,
           // then its vector work (G bounded by the registers)
           // (D': four products per block; the double layer's three-piece operands)
-          constexpr int G = (OP == SBIE_OP_DP || (X3 && OP == SBIE_OP_D)) ? 2 : PairShape<R>::batch(OP == SBIE_OP_S);
+          constexpr int G = OP == SBIE_OP_DP ? 2 : (X3 && OP == SBIE_OP_D) ? 1 : PairShape<R>::batch(OP == SBIE_OP_S);
           if (OP == SBIE_OP_S) {
             const R qb = lds_app[ib * 16 + li];
 #pragma unroll
@@ -807,7 +822,9 @@ sbie_status launch_far(sbie_geom* g, int op, const double* d_dens, const R* geo,
     case SBIE_OP_SP: ngeo = FarLayout<R, SBIE_OP_SP>::GEO; napp = FarLayout<R, SBIE_OP_SP>::APP; break;
     default: ngeo = FarLayout<R, SBIE_OP_DP>::GEO; napp = FarLayout<R, SBIE_OP_DP>::APP; break;
   }
-  const size_t lds = (size_t)kChunk * (ngeo + napp + 16 * (wg.x / 64)) * sizeof(R);
+  size_t lds = (size_t)kChunk * (ngeo + napp + 16 * (wg.x / 64)) * sizeof(R);
+  if (op == SBIE_OP_D && FarLayout<R, SBIE_OP_D>::X3)  // the double layer's row stash
+    lds += (size_t)(wg.x / 64) * PS::RBMAX * 64 * (sizeof(double) + sizeof(R));
   R* rev = reinterpret_cast<R*>(g->d_rev);
   const R* geo_s = FarLayout<R, SBIE_OP_S>::X3 ? geo_x3 : geo;
   const R* geo_d = FarLayout<R, SBIE_OP_D>::X3 ? geo_x3 : geo;

@@ -130,6 +130,34 @@ __device__ inline double lane_value(double v, int addr) {
   return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_ds_bpermute(addr, p.x), __builtin_amdgcn_ds_bpermute(addr, p.y)));
 }
 
+// v[k] summed over the 16 lanes of each row group (lanes l with the same
+// l/16), lane l keeping the sum for element l%16: recursive halving, in which
+// lanes l and l^d (d = 8, 4, 2, 1) each keep one half of the remaining
+// elements and add the partner's copy of that half.  The first two halvings
+// add in FP32 (each result then holds two roundings), the last two in FP64.
+template <int D, typename T>
+__device__ inline void halve(T (&v)[16], int lane) {
+  const bool hi = (lane & D) != 0;
+  const int addr = (lane ^ D) << 2;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const T send = hi ? v[k] : v[D + k];
+    const T keep = hi ? v[D + k] : v[k];
+    v[k] = keep + lane_value(send, addr);
+  }
+}
+
+__device__ inline double row_group_sums(float (&v)[16], int lane) {
+  halve<8>(v, lane);
+  halve<4>(v, lane);
+  double w[16];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) w[k] = (double)v[k];
+  halve<2>(w, lane);
+  halve<1>(w, lane);
+  return w[0];
+}
+
 __device__ inline f4 mma_x3(u4 a, u4 b) {
   const f4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), zero, 0, 0, 0);
@@ -281,10 +309,16 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
     qr[rb] = (OP == SBIE_OP_SP && rb < nrb) ? app[blk * 128 + 48 + li] : R(0);
   }
 
-  // forward sums of the accumulator rows over the admitted partners (FP64)
-  double acc[RB][4];
+  // forward sums of the accumulator rows over the admitted partners (FP64).
+  // FP32 (four slots, sixteen elements k = 4*slot + e per lane): each
+  // partner's tiles are first summed over their 16 columns, lane li of every
+  // row group keeping element li, so one accumulator per lane (acc1); FP64:
+  // every element per lane (acc), the columns summed at the end.
+  constexpr bool ROWSUM = sizeof(R) == 4 && RB == 4;
+  double acc1 = 0.0;
+  double acc[ROWSUM ? 1 : RB][4];
 #pragma unroll
-  for (int rb = 0; rb < RB; ++rb)
+  for (int rb = 0; rb < (ROWSUM ? 1 : RB); ++rb)
 #pragma unroll
     for (int e = 0; e < 4; ++e) acc[rb][e] = 0.0;
 
@@ -377,7 +411,7 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
           // row blocks in batches of G: the batch's matrix-core products first,
           // then its vector work (G bounded by the registers)
           // (D': four products per block; the double layer's three-piece operands)
-          constexpr int G = OP == SBIE_OP_DP ? 2 : (X3 && OP == SBIE_OP_D) ? 1 : PairShape<R>::batch(OP == SBIE_OP_S);
+          constexpr int G = (OP == SBIE_OP_DP || (X3 && OP == SBIE_OP_D)) ? 2 : PairShape<R>::batch(OP == SBIE_OP_S);
           if (OP == SBIE_OP_S) {
             const R qb = lds_app[ib * 16 + li];
 #pragma unroll
@@ -617,11 +651,18 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
     }
     if (!need_f) continue;
     // forward tile sum added under the exclusion
+    if constexpr (ROWSUM) {
+      float v[16];
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-      if (rb >= nown_u + nx_u) break;
+      for (int k = 0; k < 16; ++k) v[k] = tmp[k >> 2][k & 3];
+      acc1 += row_group_sums(v, lane);
+    } else {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) acc[rb][e] += (double)tmp[rb][e];
+      for (int rb = 0; rb < RB; ++rb) {
+        if (rb >= nown_u + nx_u) break;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[rb][e] += (double)tmp[rb][e];
+      }
     }
   }
   // forward partials: each row summed over its 16 columns; the shared blocks'
@@ -629,21 +670,31 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
   // has passed its last read of the staged operands at the barrier)
   double* lds_x = reinterpret_cast<double*>(smem_raw);  // [W][nx*16]
   if (nx_u > 0) __syncthreads();
-#pragma unroll
-  for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      double v = acc[rb][e];
-#pragma unroll
-      for (int off = 1; off < 16; off <<= 1) v += __shfl_xor(v, off, 64);
-      const int row = MM::row(lg, e);
-      if (rb < nown) {
-        const int r = (rb0 + rb) * 16 + row;
-        if (li == 0 && r < T) fwd[(size_t)split * N + (int64_t)a * T + r] = v * kInv4PiD;
-      } else if (rb < nrb && li == 0) {
-        lds_x[wave * (nx * 16) + (rb - nown) * 16 + row] = v;
-      }
+  if constexpr (ROWSUM) {
+    const int rb = li >> 2, row = MM::row(lg, li & 3);
+    if (rb < nown) {
+      const int r = (rb0 + rb) * 16 + row;
+      if (r < T) fwd[(size_t)split * N + (int64_t)a * T + r] = acc1 * kInv4PiD;
+    } else if (rb < nrb) {
+      lds_x[wave * (nx * 16) + (rb - nown) * 16 + row] = acc1;
     }
+  } else {
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        double v = acc[rb][e];
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) v += __shfl_xor(v, off, 64);
+        const int row = MM::row(lg, e);
+        if (rb < nown) {
+          const int r = (rb0 + rb) * 16 + row;
+          if (li == 0 && r < T) fwd[(size_t)split * N + (int64_t)a * T + r] = v * kInv4PiD;
+        } else if (rb < nrb && li == 0) {
+          lds_x[wave * (nx * 16) + (rb - nown) * 16 + row] = v;
+        }
+      }
+  }
   if (nx_u > 0) {
     __syncthreads();
     for (int c = tid; c < nx * 16; c += blockDim.x) {

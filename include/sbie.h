@@ -87,6 +87,8 @@ typedef enum {
 #define SBIE_PARTS_NEAR 0x20u  /* include the near field (near-field step of Algorithm 1) */
 #define SBIE_PARTS_FAR 0x40u   /* include the far field (far-field step of Algorithm 1) */
 #define SBIE_PARTS_ALL 0x70u   /* 0 also means all parts */
+#define SBIE_FAR_TREE 0x100u   /* S or D: the far field from the geometry's tree (sbie_geom_far_tree)
+                                  instead of the direct sum */
 
 typedef struct sbie_ctx sbie_ctx;
 typedef struct sbie_geom sbie_geom;
@@ -340,6 +342,62 @@ sbie_status sbie_server_get_info(sbie_server* srv, sbie_server_info* out);
 
 const char* sbie_status_str(sbie_status s);
 const char* sbie_last_error(void);
+
+/* ------------------------------------------------------------------------
+   Tree far field.  Section 4.1 sums the far field with a fast multipole
+   method; here a barycentric Lagrange treecode (Wang, Krasny and Tlupova,
+   2020) takes that role for S and D.  Source particles are clustered by
+   recursive bisection of their centres (at most `leaf` particles per leaf).
+   A cluster whose box has half-diagonal rho and centre b is taken at target
+   particle t (centre c_t, bounding radius r_t = half its diam) through
+   proxies, the (order+1)^3 Chebyshev points of the second kind in its box
+   with charges from the barycentric Lagrange interpolation of the kernel in
+   the source point, when rho + r_t < theta |c_t - b|, the cluster has more
+   nodes than proxies and none of its particles is excluded for t (self or
+   near, Section 4.1).  Otherwise its children are visited, and at a leaf its
+   particles are summed directly unless excluded.  Each far (target, source)
+   particle pair is covered exactly once.  The sums are FP64 whatever the
+   apply's precision; the interpolation error falls geometrically in `order`
+   at a rate set by theta (theta = 0.5, order = 8: relative l2 error about
+   1e-8 for S and D against the direct far sum).
+   ------------------------------------------------------------------------ */
+
+/* Build (or rebuild) the tree of a geometry; applies with SBIE_FAR_TREE use
+   it.  theta in (0, 1), order in [2, 12], leaf >= 1.  The device memory (boxes,
+   lists, proxy charges) is held until the geometry is destroyed or the tree
+   rebuilt.  Errors: SBIE_E_INVALID, SBIE_E_NOMEM, SBIE_E_DEVICE. */
+sbie_status sbie_geom_far_tree(sbie_geom* g, double theta, int32_t order, int32_t leaf);
+
+typedef struct {
+  int32_t clusters;        /* clusters of the tree */
+  int32_t proxy_clusters;  /* clusters some target takes through proxies */
+  int64_t proxy_pairs;     /* (target particle, cluster) pairs through proxies */
+  int64_t direct_pairs;    /* (target particle, source particle) pairs summed directly */
+  int64_t proxy_evals;     /* kernel evaluations per apply, targets x proxies */
+  int64_t direct_evals;    /* kernel evaluations per apply, targets x direct source nodes */
+  int64_t charge_evals;    /* (source node, proxy) terms of the proxy charges per apply */
+  uint64_t device_bytes;   /* device memory held by the tree */
+} sbie_tree_info;
+
+/* Sizes of the geometry's tree.  SBIE_E_STATE when none was built. */
+sbie_status sbie_geom_far_tree_info(const sbie_geom* g, sbie_tree_info* info);
+
+/* The tree plan alone, on the host (no device): M particles with centres
+   [M][3] and bounding radii [M], T nodes per particle, exclusion bit rows
+   excl [M][words] (bit s of row t set iff source particle s is excluded for
+   target t; words >= ceil(M/32)).  Writes the counts; when the array
+   pointers are non-NULL also (sized by a first call with NULL arrays):
+   box [n_clusters][6] (lo, hi), first/count [n_clusters] (a cluster is
+   perm[first .. first+count)), perm [M], proxy_ptr/direct_ptr [M+1] and
+   proxy_idx [n_proxy] (cluster ids), direct_idx [n_direct] (particle ids),
+   each list by target particle.  Clusters are numbered depth-first, children
+   after their parent.  Errors: SBIE_E_INVALID. */
+sbie_status sbie_far_tree_plan(int32_t M, int32_t T, const double* centers, const double* radii,
+                               const uint32_t* excl, int32_t words, double theta, int32_t order,
+                               int32_t leaf, int32_t* n_clusters, int64_t* n_proxy, int64_t* n_direct,
+                               double* box, int32_t* first, int32_t* count, int32_t* perm,
+                               int64_t* proxy_ptr, int32_t* proxy_idx, int64_t* direct_ptr,
+                               int32_t* direct_idx);
 
 #ifdef __cplusplus
 }

@@ -22,6 +22,7 @@ SBIE_FP64, SBIE_MIXED = 0, 1
 SBIE_DEVICE_PTRS = 0x1
 SBIE_TIMING = 0x2
 SBIE_PARTS_SELF, SBIE_PARTS_NEAR, SBIE_PARTS_FAR, SBIE_PARTS_ALL = 0x10, 0x20, 0x40, 0x70
+SBIE_FAR_TREE = 0x100
 
 STATUS = {0: "SBIE_OK", -1: "SBIE_E_INVALID", -2: "SBIE_E_DEGENERATE", -3: "SBIE_E_OVERLAP", -4: "SBIE_E_NOMEM",
           -5: "SBIE_E_BUDGET", -6: "SBIE_E_DEVICE", -7: "SBIE_E_TIMEOUT", -8: "SBIE_E_NUMERIC", -9: "SBIE_E_STATE"}
@@ -34,7 +35,7 @@ EXPORTS = [
     "sbie_session_bytes", "sbie_server_create", "sbie_server_destroy", "sbie_session_open", "sbie_session_apply",
     "sbie_session_close", "sbie_wait", "sbie_server_get_info", "sbie_status_str", "sbie_last_error",
     "sbie_completion_eta", "sbie_apply_completed", "sbie_solve_completed", "sbie_solve_neumann",
-    "sbie_eval_targets",
+    "sbie_eval_targets", "sbie_geom_far_tree", "sbie_geom_far_tree_info", "sbie_far_tree_plan",
 ]
 SBIE_COMPLETE_POINT, SBIE_COMPLETE_SINGLE = 0, 1
 SBIE_SERVER_GRAPHS = 0x100
@@ -45,6 +46,12 @@ class SbieError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"{STATUS.get(status, status)}: {message}")
         self.status = status
+
+
+class TreeInfo(ctypes.Structure):
+    _fields_ = [("clusters", ctypes.c_int32), ("proxy_clusters", ctypes.c_int32), ("proxy_pairs", ctypes.c_int64),
+                ("direct_pairs", ctypes.c_int64), ("proxy_evals", ctypes.c_int64), ("direct_evals", ctypes.c_int64),
+                ("charge_evals", ctypes.c_int64), ("device_bytes", ctypes.c_uint64)]
 
 
 class Timing(ctypes.Structure):
@@ -134,6 +141,12 @@ def lib() -> ctypes.CDLL:
                                          ctypes.c_uint32]
         L.sbie_eval_targets.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int64, vp, vp, vp, vp,
                                         ctypes.c_uint32]
+        L.sbie_geom_far_tree.argtypes = [vp, ctypes.c_double, ctypes.c_int32, ctypes.c_int32]
+        L.sbie_geom_far_tree_info.argtypes = [vp, ctypes.POINTER(TreeInfo)]
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        L.sbie_far_tree_plan.argtypes = [ctypes.c_int32, ctypes.c_int32, dp, dp, vp, ctypes.c_int32, ctypes.c_double,
+                                         ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), i64p, i64p,
+                                         dp, ip, ip, ip, i64p, ip, i64p, ip]
         L.sbie_status_str.argtypes = [ctypes.c_int]
         L.sbie_status_str.restype = ctypes.c_char_p
         L.sbie_last_error.argtypes = []
@@ -222,12 +235,13 @@ class Geometry:
         return src, dst
 
     def apply(self, op: int, density, precision: int = SBIE_FP64, parts: int = SBIE_PARTS_ALL, out=None,
-              stream=None, timing: bool = False):
+              stream=None, timing: bool = False, tree: bool = False):
         """Apply S, D, S', D' or the Stokes single layer.  density: torch CUDA float64
         tensor [nrhs, N] or [N] (device pointers, on the current stream), or a numpy
         array (host pointers, synchronous).  SBIE_OP_STOKES_SP returns [4, N]
-        (velocity, then pressure)."""
-        flags = int(parts) | (SBIE_TIMING if timing else 0)
+        (velocity, then pressure).  tree: the far field of S or D through the
+        geometry's tree (far_tree)."""
+        flags = int(parts) | (SBIE_TIMING if timing else 0) | (SBIE_FAR_TREE if tree else 0)
         if isinstance(density, np.ndarray):
             d = np.ascontiguousarray(density, dtype=np.float64)
             nrhs = 1 if d.ndim == 1 else d.shape[0]
@@ -254,6 +268,16 @@ class Geometry:
         _check(lib().sbie_apply(self._h, int(op), int(precision), nrhs, density.data_ptr(), out.data_ptr(),
                                 ctypes.c_void_p(stream.cuda_stream), flags | SBIE_DEVICE_PTRS))
         return out
+
+    def far_tree(self, theta: float = 0.5, order: int = 8, leaf: int = 2):
+        """Build the geometry's tree far field (sbie_geom_far_tree); returns far_tree_info()."""
+        _check(lib().sbie_geom_far_tree(self._h, float(theta), int(order), int(leaf)))
+        return self.far_tree_info()
+
+    def far_tree_info(self) -> dict:
+        info = TreeInfo()
+        _check(lib().sbie_geom_far_tree_info(self._h, ctypes.byref(info)))
+        return {name: getattr(info, name) for name, _ in TreeInfo._fields_}
 
     def completion_eta(self, completion: int) -> np.ndarray:
         """The eta table's scaling of each particle for the completion."""
@@ -506,3 +530,33 @@ class Session:
         if self._h:
             _check(lib().sbie_session_close(self._h))
             self._h = ctypes.c_void_p()
+
+
+def far_tree_plan(centers, radii, excl, T: int, theta: float = 0.5, order: int = 8, leaf: int = 2) -> dict:
+    """The tree far field's plan on the host (sbie_far_tree_plan; no device).
+    excl: bool [M, M], excl[t, s] true iff source particle s is excluded for
+    target particle t."""
+    c = np.ascontiguousarray(centers, dtype=np.float64)
+    r = np.ascontiguousarray(radii, dtype=np.float64)
+    e = np.asarray(excl, dtype=bool)
+    M = len(r)
+    words = (M + 31) // 32
+    ex = np.zeros((M, words), dtype=np.uint32)
+    t, s = np.nonzero(e)
+    np.bitwise_or.at(ex, (t, s >> 5), np.left_shift(np.uint32(1), (s & 31).astype(np.uint32)))
+    nc, npx, ndr = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+    args = [M, int(T), _dp(c), _dp(r), ex.ctypes.data, words, float(theta), int(order), int(leaf)]
+    counts = [ctypes.byref(nc), ctypes.byref(npx), ctypes.byref(ndr)]
+    _check(lib().sbie_far_tree_plan(*args, *counts, *([None] * 8)))
+    out = {"box": np.zeros((nc.value, 6)), "first": np.zeros(nc.value, np.int32), "count": np.zeros(nc.value, np.int32),
+           "perm": np.zeros(M, np.int32), "proxy_ptr": np.zeros(M + 1, np.int64),
+           "proxy_idx": np.zeros(max(npx.value, 1), np.int32), "direct_ptr": np.zeros(M + 1, np.int64),
+           "direct_idx": np.zeros(max(ndr.value, 1), np.int32)}
+    P = ctypes.POINTER
+    ptrs = [out["box"].ctypes.data_as(P(ctypes.c_double))] + [
+        out[k].ctypes.data_as(P(ctypes.c_int32 if out[k].dtype == np.int32 else ctypes.c_int64))
+        for k in ("first", "count", "perm", "proxy_ptr", "proxy_idx", "direct_ptr", "direct_idx")]
+    _check(lib().sbie_far_tree_plan(*args, *counts, *ptrs))
+    out["proxy_idx"] = out["proxy_idx"][:npx.value]
+    out["direct_idx"] = out["direct_idx"][:ndr.value]
+    return out

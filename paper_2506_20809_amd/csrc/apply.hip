@@ -517,9 +517,16 @@ sbie_status apply_laplace(sbie_geom* g, int op, int prec, const double* d_dens, 
     SBIE_HIP(hipEventRecord(ev[6], s));
     SBIE_HIP(hipEventRecord(ev[7], s));
   }
-  // part (d) far field: the pair-symmetric matrix-core kernel (T >= 32, i.e.
-  // p >= 3), else the vector-unit sum in FP64
-  if ((parts & SBIE_PARTS_FAR) && T >= 32) {
+  // part (d) far field: through the tree (SBIE_FAR_TREE), else the
+  // pair-symmetric matrix-core kernel (T >= 32, i.e. p >= 3), else the
+  // vector-unit sum in FP64
+  const bool tree = (parts & SBIE_FAR_TREE) != 0;
+  if ((parts & SBIE_PARTS_FAR) && tree) {
+    if (timed) SBIE_HIP(hipEventRecord(ev[3], s));
+    sbie_status st = far_tree(g, op, s);
+    if (st) return st;
+    if (timed) SBIE_HIP(hipEventRecord(ev[4], s));
+  } else if ((parts & SBIE_PARTS_FAR) && T >= 32) {
     sbie_status st = far_mfma(g, op, prec, d_dens, s, timed ? ev[3] : nullptr, timed ? ev[4] : nullptr);
     if (st) return st;
   } else if (parts & SBIE_PARTS_FAR) {
@@ -541,7 +548,10 @@ sbie_status apply_laplace(sbie_geom* g, int op, int prec, const double* d_dens, 
   // with no near pairs the near part is empty and is left out of the sum
   const uint32_t sum_parts = g->n_near > 0 ? parts : (parts & ~(uint32_t)SBIE_PARTS_NEAR);
   const int RG = far_row_groups(g, !mixed);
-  if (T >= 32 && mixed)
+  if (tree)  // one forward slice, no reverse sums
+    hipLaunchKernelGGL(k_assemble_f64<double>, dim3(cdiv(N, B)), dim3(B), 0, s, g->d_uself, g->d_unear,
+                       g->d_partial, 1, (const double*)nullptr, M, T, RG, N, sum_parts, d_out);
+  else if (T >= 32 && mixed)
     hipLaunchKernelGGL(k_assemble_f64<float>, dim3(cdiv(N, B)), dim3(B), 0, s, g->d_uself, g->d_unear, g->d_partial,
                        g->nsplit, reinterpret_cast<const float*>(g->d_rev), M, T, RG, N, sum_parts, d_out);
   else

@@ -32,6 +32,7 @@ sbie_status invalid(const std::string& msg) {
 
 void free_geom(sbie_geom* g) {
   if (!g) return;
+  sbie::free_tree(g);
   if (g->blk && g->blk_owned) (void)hipFree(g->blk);
   if (g->stk_blk) (void)hipFree(g->stk_blk);
   if (g->sdl_blk) (void)hipFree(g->sdl_blk);
@@ -270,6 +271,14 @@ sbie_status sbie_apply(sbie_geom* g, sbie_op op, sbie_precision prec, int32_t nr
   SBIE_HIP(hipSetDevice(g->ctx->device));
   uint32_t parts = flags & SBIE_PARTS_ALL;
   if (parts == 0) parts = SBIE_PARTS_ALL;
+  if (flags & SBIE_FAR_TREE) {
+    if (op != SBIE_OP_S && op != SBIE_OP_D) return invalid("SBIE_FAR_TREE applies to S and D only");
+    if (!g->tree) {
+      set_error("SBIE_FAR_TREE without a tree (sbie_geom_far_tree)");
+      return SBIE_E_STATE;
+    }
+    parts |= SBIE_FAR_TREE;
+  }
   const bool devptr = (flags & SBIE_DEVICE_PTRS) != 0;
   const bool timed = (flags & SBIE_TIMING) != 0;
   hipStream_t s = stream ? (hipStream_t)stream : g->ctx->stream;

@@ -51,6 +51,31 @@ struct Timing {
   size_t used = 0;
 };
 
+// Tree far field (tree.hip): host plan and device state.
+struct TreePlan {
+  int nc = 0, order = 0;
+  double theta = 0.0;
+  std::vector<double> box;                // [nc][6] lo, hi of every cluster
+  std::vector<int32_t> first, count;      // [nc] range of the permutation
+  std::vector<int32_t> perm;              // [M] particles in cluster order
+  std::vector<int64_t> pptr, dptr;        // [M+1] per target particle
+  std::vector<int32_t> pidx, didx;        // clusters through proxies; source particles summed directly
+};
+
+struct FarTree {
+  double theta = 0.0;
+  int nc = 0, order = 0, leaf = 0, nused = 0;  // nused: clusters taken through proxies by some target
+  int64_t n_proxy = 0, n_direct = 0;     // (target, cluster) and (target, source particle) pairs
+  int64_t proxy_evals = 0, direct_evals = 0, charge_evals = 0;  // node-level work per apply
+  size_t bytes = 0;
+  char* blk = nullptr;                   // one device block holding everything below
+  double* d_box = nullptr;               // [nused][6]
+  int32_t *d_first = nullptr, *d_count = nullptr, *d_perm = nullptr;
+  int64_t *d_pptr = nullptr, *d_dptr = nullptr;
+  int32_t *d_pidx = nullptr, *d_didx = nullptr;  // pidx holds used-cluster slots
+  double* d_q = nullptr;                 // [nused][(order+1)^3] proxy charges of the current apply
+};
+
 }  // namespace sbie
 
 struct sbie_ctx {
@@ -161,6 +186,7 @@ struct sbie_geom {
   uint8_t* d_near_scratch = nullptr;  // [M][M] near flags of the classification
 
   sbie::Timing timing;
+  sbie::FarTree* tree = nullptr;  // tree far field, built by sbie_geom_far_tree
   // the near field runs on a side stream, concurrently with the far field
   // (plain geometries; served sessions keep one stream per lane)
   bool fork_near = true;
@@ -172,6 +198,14 @@ namespace sbie {
 
 void set_error(const std::string& msg);
 sbie_status device_error(hipError_t e, const char* what);
+
+// Tree far field (tree.hip).  plan_tree is host code: excl [M][words], bit s
+// of row t set iff source particle s is excluded for target particle t.
+sbie_status plan_tree(int M, int T, const double* centers, const double* radii, const uint32_t* excl, int words,
+                      double theta, int order, int leaf, TreePlan* out);
+sbie_status build_tree(sbie_geom* g, double theta, int order, int leaf);
+void free_tree(sbie_geom* g);
+sbie_status far_tree(sbie_geom* g, int op, hipStream_t s);
 
 // Carves 256-byte aligned buffers out of one device block; with no block it
 // only measures.

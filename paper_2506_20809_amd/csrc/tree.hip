@@ -1,0 +1,590 @@
+// Tree far field: a barycentric Lagrange treecode in the role of the FMM that
+// Section 4.1 uses for the far field (the far-field step of Algorithm 1).
+//
+// Source particles are clustered by recursive bisection of their centres.  A
+// cluster's box holds the bounding spheres of its particles.  For a target
+// particle t (centre c_t, bounding radius r_t) a cluster C (box centre b,
+// half-diagonal rho) is taken through proxies when
+//     rho + r_t < theta |c_t - b|,
+// C has more nodes than proxies and none of its particles is excluded for t
+// (t itself or a source whose near field holds t); otherwise its children
+// are visited, and at a leaf its particles that are not excluded are summed
+// directly.  Every (target, far source particle) pair is thus covered exactly
+// once, and excluded pairs never.
+//
+// Proxies of C are the tensor grid of Chebyshev points of the second kind,
+// (n+1)^3 points s_k in its box.  The Laplace kernel G(x, y) = 1/(4 pi |x-y|)
+// is interpolated in y by the barycentric Lagrange basis L_k, so
+//     sum_j q_j G(x, y_j)            ~ sum_k qhat_k G(x, s_k),  qhat_k = sum_j q_j L_k(y_j)
+//     sum_j d_j . grad_y G(x, y_j)   ~ sum_k qhat_k G(x, s_k),  qhat_k = sum_j d_j . grad L_k(y_j)
+// for the single layer (q = W sigma) and the double layer (d = W mu nu).  The
+// error falls geometrically in n at a rate set by theta.
+//
+// The plan is host code (no device needed); proxy charges and the evaluation
+// are FP64 kernels: one workgroup per cluster for the charges, one per target
+// particle for the sums.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <vector>
+
+#include "sbie_internal.h"
+
+namespace sbie {
+
+namespace {
+
+constexpr double kInv4PiT = 0.079577471545947667884441881686257181;
+constexpr int kTreeMaxOrder = 12;
+constexpr int kTreeChunk = 512;  // source points staged in LDS at a time
+
+struct TreeNode {
+  int first = 0, count = 0;  // range of the permutation
+  int child[2] = {-1, -1};
+  double lo[3], hi[3];
+};
+
+sbie_status invalid(const char* msg) {
+  set_error(msg);
+  return SBIE_E_INVALID;
+}
+
+}  // namespace
+
+// Plan of the tree far field.  excl: [M][words], bit s of row t set iff source
+// particle s is excluded for target particle t.
+sbie_status plan_tree(int M, int T, const double* centers, const double* radii, const uint32_t* excl, int words,
+                      double theta, int order, int leaf, TreePlan* out) {
+  if (M < 1 || T < 1 || !centers || !radii || !excl || words < (M + 31) / 32)
+    return invalid("tree plan: bad particle arrays");
+  if (!(theta > 0.0 && theta < 1.0)) return invalid("tree plan: theta must be in (0, 1)");
+  if (order < 2 || order > kTreeMaxOrder) return invalid("tree plan: order must be in [2, 12]");
+  if (leaf < 1) return invalid("tree plan: leaf must be >= 1");
+  for (int i = 0; i < M; ++i)
+    if (!std::isfinite(centers[3 * i]) || !std::isfinite(centers[3 * i + 1]) || !std::isfinite(centers[3 * i + 2]) ||
+        !(radii[i] > 0.0) || !std::isfinite(radii[i]))
+      return invalid("tree plan: non-finite centre or radius <= 0");
+  const int64_t n3 = (int64_t)(order + 1) * (order + 1) * (order + 1);
+  auto excluded = [&](int t, int s) { return (excl[(size_t)t * words + (s >> 5)] >> (s & 31)) & 1u; };
+
+  std::vector<int> perm(M);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::vector<TreeNode> nodes;
+  nodes.reserve(2 * (size_t)M);
+  // depth-first construction: a cluster's box bounds its particles' spheres;
+  // it splits at the median of its centres along their longest extent
+  struct Item {
+    int first, count, parent, side;
+  };
+  std::vector<Item> stack{{0, M, -1, 0}};
+  while (!stack.empty()) {
+    const Item it = stack.back();
+    stack.pop_back();
+    const int k = (int)nodes.size();
+    nodes.emplace_back();
+    TreeNode& nd = nodes.back();
+    nd.first = it.first;
+    nd.count = it.count;
+    if (it.parent >= 0) nodes[it.parent].child[it.side] = k;
+    double clo[3], chi[3];
+    for (int d = 0; d < 3; ++d) {
+      nd.lo[d] = clo[d] = INFINITY;
+      nd.hi[d] = chi[d] = -INFINITY;
+    }
+    for (int i = it.first; i < it.first + it.count; ++i) {
+      const int s = perm[i];
+      for (int d = 0; d < 3; ++d) {
+        const double c = centers[3 * s + d];
+        nd.lo[d] = std::min(nd.lo[d], c - radii[s]);
+        nd.hi[d] = std::max(nd.hi[d], c + radii[s]);
+        clo[d] = std::min(clo[d], c);
+        chi[d] = std::max(chi[d], c);
+      }
+    }
+    if (it.count > leaf) {
+      int dim = 0;
+      for (int d = 1; d < 3; ++d)
+        if (chi[d] - clo[d] > chi[dim] - clo[dim]) dim = d;
+      std::sort(perm.begin() + it.first, perm.begin() + it.first + it.count, [&](int a, int b) {
+        const double ca = centers[3 * a + dim], cb = centers[3 * b + dim];
+        return ca < cb || (ca == cb && a < b);
+      });
+      const int h = it.count / 2;
+      // the second half is pushed first so that the first half is built next
+      stack.push_back({it.first + h, it.count - h, k, 1});
+      stack.push_back({it.first, h, k, 0});
+    }
+  }
+
+  out->nc = (int)nodes.size();
+  out->box.resize((size_t)out->nc * 6);
+  out->first.resize(out->nc);
+  out->count.resize(out->nc);
+  for (int k = 0; k < out->nc; ++k) {
+    for (int d = 0; d < 3; ++d) {
+      out->box[6 * (size_t)k + d] = nodes[k].lo[d];
+      out->box[6 * (size_t)k + 3 + d] = nodes[k].hi[d];
+    }
+    out->first[k] = nodes[k].first;
+    out->count[k] = nodes[k].count;
+  }
+  out->perm = perm;
+  out->pptr.assign(M + 1, 0);
+  out->dptr.assign(M + 1, 0);
+  out->pidx.clear();
+  out->didx.clear();
+  std::vector<int> visit;
+  for (int t = 0; t < M; ++t) {
+    visit.assign(1, 0);
+    const double* ct = centers + 3 * t;
+    while (!visit.empty()) {
+      const int k = visit.back();
+      visit.pop_back();
+      const TreeNode& nd = nodes[k];
+      double dist2 = 0.0, diag2 = 0.0;
+      for (int d = 0; d < 3; ++d) {
+        const double b = 0.5 * (nd.lo[d] + nd.hi[d]);
+        dist2 += (ct[d] - b) * (ct[d] - b);
+        diag2 += (nd.hi[d] - nd.lo[d]) * (nd.hi[d] - nd.lo[d]);
+      }
+      bool take = 0.5 * std::sqrt(diag2) + radii[t] < theta * std::sqrt(dist2) && (int64_t)nd.count * T > n3;
+      for (int i = nd.first; take && i < nd.first + nd.count; ++i)
+        if (excluded(t, perm[i])) take = false;
+      if (take) {
+        out->pidx.push_back(k);
+      } else if (nd.child[0] >= 0) {
+        visit.push_back(nd.child[1]);
+        visit.push_back(nd.child[0]);
+      } else {
+        for (int i = nd.first; i < nd.first + nd.count; ++i)
+          if (!excluded(t, perm[i])) out->didx.push_back(perm[i]);
+      }
+    }
+    out->pptr[t + 1] = (int64_t)out->pidx.size();
+    out->dptr[t + 1] = (int64_t)out->didx.size();
+  }
+  out->order = order;
+  out->theta = theta;
+  return SBIE_OK;
+}
+
+namespace {
+
+// Chebyshev points of the second kind s_k = cos(pi k / n) on [-1, 1] and
+// their barycentric weights (-1)^k, halved at both ends, into cs[0..n] and
+// cw[0..n] (LDS, filled by the first n+1 lanes)
+__device__ inline void cheb_table(int n, double* cs, double* cw) {
+  const int k = threadIdx.x;
+  if (k <= n) {
+    cs[k] = cospi((double)k / (double)n);
+    cw[k] = ((k & 1) ? -1.0 : 1.0) * ((k == 0 || k == n) ? 0.5 : 1.0);
+  }
+}
+
+// Lagrange basis L_k(u), k = 0..n, on the Chebyshev points, and (DERIV) its
+// derivative, by the barycentric formulas; at a Chebyshev point itself the
+// basis is the unit vector and the derivative the differentiation-matrix row
+template <bool DERIV>
+__device__ inline void lagrange(int n, const double* cs, const double* cw, double u, double* L, double* dL) {
+  int hit = -1;
+  for (int k = 0; k <= n; ++k)
+    if (u == cs[k]) hit = k;
+  if (hit < 0) {
+    double A = 0.0, B = 0.0;
+    for (int k = 0; k <= n; ++k) {
+      const double r = 1.0 / (u - cs[k]);
+      const double a = cw[k] * r;
+      L[k] = a;
+      A += a;
+      B += a * r;
+    }
+    const double iA = 1.0 / A;
+    for (int k = 0; k <= n; ++k) {
+      const double l = L[k] * iA;
+      L[k] = l;
+      if (DERIV) dL[k] = l * (B * iA - 1.0 / (u - cs[k]));
+    }
+  } else {
+    double sum = 0.0;
+    for (int k = 0; k <= n; ++k) {
+      L[k] = k == hit ? 1.0 : 0.0;
+      if (DERIV && k != hit) {
+        dL[k] = (cw[k] / cw[hit]) / (cs[hit] - cs[k]);
+        sum += dL[k];
+      }
+    }
+    if (DERIV) dL[hit] = -sum;
+  }
+}
+
+// Proxy charges of the used clusters (one workgroup each): qhat_k over the
+// cluster's nodes, 64 nodes at a time through LDS.  Source records: S
+// (x, y, z, W sigma) in 4 doubles, D (x, y, z, W mu nu) in 8.
+template <int OP>
+__global__ __launch_bounds__(256) void k_tree_charges(const double* __restrict__ box, const int32_t* __restrict__ first,
+                                                     const int32_t* __restrict__ count, const int32_t* __restrict__ perm,
+                                                     const double* __restrict__ src, int T, int n,
+                                                     double* __restrict__ qhat) {
+  constexpr int SW = OP == SBIE_OP_S ? 4 : 8;
+  constexpr int NC = 64, NB = kTreeMaxOrder + 1;
+  constexpr int NSET = OP == SBIE_OP_S ? 3 : 6;  // S: q Lx, Ly, Lz; D: Lx, Ly, Lz, d_x dLx, d_y dLy, d_z dLz
+  __shared__ double basis[NSET][NC][NB];
+  __shared__ double cs[NB], cw[NB];
+  const int c = blockIdx.x, tid = threadIdx.x;
+  const int n1 = n + 1, n3 = n1 * n1 * n1;
+  cheb_table(n, cs, cw);
+  __syncthreads();
+  double lo[3], sc[3];
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = box[6 * c + d];
+    sc[d] = 2.0 / (box[6 * c + 3 + d] - lo[d]);  // d u / d y
+  }
+  constexpr int KPT = (NB * NB * NB + 255) / 256;
+  double acc[KPT];
+#pragma unroll
+  for (int m = 0; m < KPT; ++m) acc[m] = 0.0;
+  const int64_t nodes = (int64_t)count[c] * T;
+  for (int64_t j0 = 0; j0 < nodes; j0 += NC) {
+    if (tid < NC) {
+      const int64_t j = j0 + tid;
+      if (j < nodes) {
+        const int part = perm[first[c] + (int)(j / T)];
+        const double* r = src + ((int64_t)part * T + j % T) * SW;
+        for (int d = 0; d < 3; ++d)
+          lagrange<OP == SBIE_OP_D>(n, cs, cw, (r[d] - lo[d]) * sc[d] - 1.0, basis[d][tid],
+                                    basis[OP == SBIE_OP_D ? 3 + d : d][tid]);
+        // S: the strength folded into the x basis; D: the dipole component
+        // (times d u / d y) into each derivative
+        if (OP == SBIE_OP_S) {
+          for (int k = 0; k < n1; ++k) basis[0][tid][k] *= r[3];
+        } else {
+          for (int d = 0; d < 3; ++d)
+            for (int k = 0; k < n1; ++k) basis[OP == SBIE_OP_D ? 3 + d : d][tid][k] *= r[3 + d] * sc[d];
+        }
+      } else {
+        for (int w = 0; w < NSET; ++w)
+          for (int k = 0; k < n1; ++k) basis[w][tid][k] = 0.0;
+      }
+    }
+    __syncthreads();
+    const int jn = nodes - j0 < NC ? (int)(nodes - j0) : NC;
+#pragma unroll
+    for (int m = 0; m < KPT; ++m) {
+      const int k = tid + 256 * m;
+      if (k < n3) {
+        const int k1 = k / (n1 * n1), k2 = (k / n1) % n1, k3 = k % n1;
+        double a = acc[m];
+        for (int j = 0; j < jn; ++j) {
+          if (OP == SBIE_OP_S) {
+            a = fma(basis[0][j][k1] * basis[1][j][k2], basis[2][j][k3], a);
+          } else {
+            const double lx = basis[0][j][k1], ly = basis[1][j][k2], lz = basis[2][j][k3];
+            a = fma(basis[3][j][k1] * ly, lz, a);
+            a = fma(lx * basis[4][j][k2], lz, a);
+            a = fma(lx * ly, basis[5][j][k3], a);
+          }
+        }
+        acc[m] = a;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int m = 0; m < KPT; ++m) {
+    const int k = tid + 256 * m;
+    if (k < n3) qhat[(int64_t)c * n3 + k] = acc[m];
+  }
+}
+
+__device__ inline double rsqrt_tree(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double h = x * y;
+  const double e = fma(-h, y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+
+// Far field of one target particle per workgroup: its accepted clusters
+// through their proxies, then its direct far particles, each source set
+// staged through LDS kTreeChunk points at a time.  Lane l holds targets
+// l, l + blockDim, ... of the particle (TPT of them).
+template <int OP, int TPT>
+__global__ __launch_bounds__(1024) void k_tree_eval(const double* __restrict__ x, const double* __restrict__ y,
+                                                    const double* __restrict__ z, const double* __restrict__ src,
+                                                    const double* __restrict__ box, const double* __restrict__ qhat,
+                                                    const int64_t* __restrict__ pptr, const int32_t* __restrict__ pidx,
+                                                    const int64_t* __restrict__ dptr, const int32_t* __restrict__ didx,
+                                                    int T, int n, double* __restrict__ out) {
+  constexpr int SW = OP == SBIE_OP_S ? 4 : 8;
+  __shared__ double lds[kTreeChunk * 6];
+  __shared__ double cs[kTreeMaxOrder + 1], cw[kTreeMaxOrder + 1];
+  const int t = blockIdx.x, tid = threadIdx.x;
+  const int n1 = n + 1, n3 = n1 * n1 * n1;
+  cheb_table(n, cs, cw);
+  __syncthreads();
+  double tx[TPT], ty[TPT], tz[TPT], acc[TPT];
+#pragma unroll
+  for (int k = 0; k < TPT; ++k) {
+    const int i = tid + k * blockDim.x;
+    const int64_t g = (int64_t)t * T + (i < T ? i : 0);
+    tx[k] = x[g];
+    ty[k] = y[g];
+    tz[k] = z[g];
+    acc[k] = 0.0;
+  }
+  // proxies of the accepted clusters: point charges
+  for (int64_t m = pptr[t]; m < pptr[t + 1]; ++m) {
+    const int c = pidx[m];
+    for (int k0 = 0; k0 < n3; k0 += kTreeChunk) {
+      const int kn = n3 - k0 < kTreeChunk ? n3 - k0 : kTreeChunk;
+      for (int k = tid; k < kn; k += blockDim.x) {
+        const int kk = k0 + k;
+        const int idx[3] = {kk / (n1 * n1), (kk / n1) % n1, kk % n1};
+        for (int d = 0; d < 3; ++d) {
+          const double lo = box[6 * c + d], hi = box[6 * c + 3 + d];
+          lds[4 * k + d] = lo + 0.5 * (cs[idx[d]] + 1.0) * (hi - lo);
+        }
+        lds[4 * k + 3] = qhat[(int64_t)c * n3 + kk];
+      }
+      __syncthreads();
+      for (int k = 0; k < kn; ++k) {
+        const double px = lds[4 * k], py = lds[4 * k + 1], pz = lds[4 * k + 2], q = lds[4 * k + 3];
+#pragma unroll
+        for (int e = 0; e < TPT; ++e) {
+          const double dx = tx[e] - px, dy = ty[e] - py, dz = tz[e] - pz;
+          acc[e] = fma(q, rsqrt_tree(fma(dz, dz, fma(dy, dy, dx * dx))), acc[e]);
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // direct far particles
+  for (int64_t m = dptr[t]; m < dptr[t + 1]; ++m) {
+    const double* rs = src + (int64_t)didx[m] * T * SW;
+    for (int j0 = 0; j0 < T; j0 += kTreeChunk) {
+      const int jn = T - j0 < kTreeChunk ? T - j0 : kTreeChunk;
+      constexpr int LW = OP == SBIE_OP_S ? 4 : 6;
+      for (int j = tid; j < jn; j += blockDim.x) {
+        const double* r = rs + (int64_t)(j0 + j) * SW;
+        for (int w = 0; w < LW; ++w) lds[LW * j + w] = r[w];
+      }
+      __syncthreads();
+      for (int j = 0; j < jn; ++j) {
+        const double* r = lds + LW * j;
+#pragma unroll
+        for (int e = 0; e < TPT; ++e) {
+          const double dx = tx[e] - r[0], dy = ty[e] - r[1], dz = tz[e] - r[2];
+          const double ri = rsqrt_tree(fma(dz, dz, fma(dy, dy, dx * dx)));
+          if (OP == SBIE_OP_S) {
+            acc[e] = fma(r[3], ri, acc[e]);
+          } else {
+            const double dot = fma(r[5], dz, fma(r[4], dy, r[3] * dx));
+            acc[e] = fma(dot, ri * ri * ri, acc[e]);
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < TPT; ++k) {
+    const int i = tid + k * blockDim.x;
+    if (i < T) out[(int64_t)t * T + i] = acc[k] * kInv4PiT;
+  }
+}
+
+inline unsigned cdiv_t(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+template <int OP, int TPT>
+void launch_eval(sbie_geom* g, hipStream_t s, int threads) {
+  const FarTree& tr = *g->tree;
+  hipLaunchKernelGGL((k_tree_eval<OP, TPT>), dim3(g->M), dim3(threads), 0, s, g->d_x, g->d_y, g->d_z, g->d_src,
+                     tr.d_box, tr.d_q, tr.d_pptr, tr.d_pidx, tr.d_dptr, tr.d_didx, g->T, tr.order, g->d_partial);
+}
+
+}  // namespace
+
+void free_tree(sbie_geom* g) {
+  if (!g->tree) return;
+  if (g->tree->blk) (void)hipFree(g->tree->blk);
+  delete g->tree;
+  g->tree = nullptr;
+}
+
+sbie_status build_tree(sbie_geom* g, double theta, int order, int leaf) {
+  const int M = g->M, T = g->T, words = g->excl_words;
+  std::vector<uint32_t> excl((size_t)M * words);
+  SBIE_HIP(hipSetDevice(g->ctx->device));
+  SBIE_HIP(hipMemcpy(excl.data(), g->d_excl, sizeof(uint32_t) * excl.size(), hipMemcpyDeviceToHost));
+  std::vector<double> centers(3 * (size_t)M), radii(M);
+  for (int i = 0; i < M; ++i) {
+    for (int d = 0; d < 3; ++d) centers[3 * i + d] = g->h_part[i].c[d];
+    radii[i] = 0.5 * g->h_part[i].diam;
+  }
+  TreePlan plan;
+  sbie_status st = plan_tree(M, T, centers.data(), radii.data(), excl.data(), words, theta, order, leaf, &plan);
+  if (st != SBIE_OK) return st;
+  // only the clusters some target takes through proxies need device data
+  std::vector<int> slot(plan.nc, -1), used;
+  for (int32_t& c : plan.pidx) {
+    if (slot[c] < 0) {
+      slot[c] = (int)used.size();
+      used.push_back(c);
+    }
+    c = slot[c];
+  }
+  const int nu = (int)used.size();
+  const int n3 = (order + 1) * (order + 1) * (order + 1);
+  std::vector<double> box(6 * (size_t)std::max(nu, 1));
+  std::vector<int32_t> first(std::max(nu, 1)), count(std::max(nu, 1));
+  for (int u = 0; u < nu; ++u) {
+    for (int w = 0; w < 6; ++w) box[6 * (size_t)u + w] = plan.box[6 * (size_t)used[u] + w];
+    first[u] = plan.first[used[u]];
+    count[u] = plan.count[used[u]];
+  }
+  if (plan.pidx.empty()) plan.pidx.push_back(0);
+  if (plan.didx.empty()) plan.didx.push_back(0);
+  free_tree(g);
+  FarTree* tr = new FarTree();
+  g->tree = tr;
+  tr->theta = theta;
+  tr->nc = plan.nc;
+  tr->order = order;
+  tr->leaf = leaf;
+  tr->nused = nu;
+  tr->n_proxy = plan.pptr[M];
+  tr->n_direct = plan.dptr[M];
+  tr->proxy_evals = tr->n_proxy * (int64_t)n3 * T;
+  tr->direct_evals = tr->n_direct * (int64_t)T * T;
+  for (int u = 0; u < nu; ++u) tr->charge_evals += (int64_t)count[u] * T * n3;
+  // one device block: boxes, member ranges, the permutation, the lists and
+  // the proxy charges
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t sz_box = al(sizeof(double) * box.size()), sz_fc = al(sizeof(int32_t) * first.size());
+  const size_t sz_perm = al(sizeof(int32_t) * M), sz_ptr = al(sizeof(int64_t) * (M + 1));
+  const size_t sz_pidx = al(sizeof(int32_t) * plan.pidx.size()), sz_didx = al(sizeof(int32_t) * plan.didx.size());
+  const size_t sz_q = al(sizeof(double) * (size_t)std::max(nu, 1) * n3);
+  const size_t total = sz_box + 2 * sz_fc + sz_perm + 2 * sz_ptr + sz_pidx + sz_didx + sz_q;
+  if (hipMalloc(&tr->blk, total) != hipSuccess) {
+    (void)hipGetLastError();
+    free_tree(g);
+    return SBIE_E_NOMEM;
+  }
+  char* p = tr->blk;
+  auto take = [&](size_t sz) {
+    char* q = p;
+    p += sz;
+    return q;
+  };
+  tr->d_box = reinterpret_cast<double*>(take(sz_box));
+  tr->d_first = reinterpret_cast<int32_t*>(take(sz_fc));
+  tr->d_count = reinterpret_cast<int32_t*>(take(sz_fc));
+  tr->d_perm = reinterpret_cast<int32_t*>(take(sz_perm));
+  tr->d_pptr = reinterpret_cast<int64_t*>(take(sz_ptr));
+  tr->d_dptr = reinterpret_cast<int64_t*>(take(sz_ptr));
+  tr->d_pidx = reinterpret_cast<int32_t*>(take(sz_pidx));
+  tr->d_didx = reinterpret_cast<int32_t*>(take(sz_didx));
+  tr->d_q = reinterpret_cast<double*>(take(sz_q));
+  tr->bytes = total;
+  SBIE_HIP(hipMemcpy(tr->d_box, box.data(), sizeof(double) * box.size(), hipMemcpyHostToDevice));
+  SBIE_HIP(hipMemcpy(tr->d_first, first.data(), sizeof(int32_t) * first.size(), hipMemcpyHostToDevice));
+  SBIE_HIP(hipMemcpy(tr->d_count, count.data(), sizeof(int32_t) * count.size(), hipMemcpyHostToDevice));
+  SBIE_HIP(hipMemcpy(tr->d_perm, plan.perm.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice));
+  SBIE_HIP(hipMemcpy(tr->d_pptr, plan.pptr.data(), sizeof(int64_t) * (M + 1), hipMemcpyHostToDevice));
+  SBIE_HIP(hipMemcpy(tr->d_dptr, plan.dptr.data(), sizeof(int64_t) * (M + 1), hipMemcpyHostToDevice));
+  SBIE_HIP(hipMemcpy(tr->d_pidx, plan.pidx.data(), sizeof(int32_t) * plan.pidx.size(), hipMemcpyHostToDevice));
+  SBIE_HIP(hipMemcpy(tr->d_didx, plan.didx.data(), sizeof(int32_t) * plan.didx.size(), hipMemcpyHostToDevice));
+  return SBIE_OK;
+}
+
+// Far field of S or D through the tree into partial slice 0 (FP64).  The
+// source records d_src (k_prep_f64) must be current.
+sbie_status far_tree(sbie_geom* g, int op, hipStream_t s) {
+  const FarTree& tr = *g->tree;
+  if (tr.nused > 0) {
+    if (op == SBIE_OP_S)
+      hipLaunchKernelGGL(k_tree_charges<SBIE_OP_S>, dim3(tr.nused), dim3(256), 0, s, tr.d_box, tr.d_first,
+                         tr.d_count, tr.d_perm, g->d_src, g->T, tr.order, tr.d_q);
+    else
+      hipLaunchKernelGGL(k_tree_charges<SBIE_OP_D>, dim3(tr.nused), dim3(256), 0, s, tr.d_box, tr.d_first,
+                         tr.d_count, tr.d_perm, g->d_src, g->T, tr.order, tr.d_q);
+    SBIE_HIP(hipGetLastError());
+  }
+  // lanes: 64 * ceil(T / (64 TPT)) with the smallest TPT that fits 1024
+  const int T = g->T;
+  const int tpt = T <= 1024 ? 1 : (T <= 2048 ? 2 : 3);
+  const int threads = 64 * (int)cdiv_t(cdiv_t(T, tpt), 64);
+  if (op == SBIE_OP_S) {
+    if (tpt == 1) launch_eval<SBIE_OP_S, 1>(g, s, threads);
+    else if (tpt == 2) launch_eval<SBIE_OP_S, 2>(g, s, threads);
+    else launch_eval<SBIE_OP_S, 3>(g, s, threads);
+  } else {
+    if (tpt == 1) launch_eval<SBIE_OP_D, 1>(g, s, threads);
+    else if (tpt == 2) launch_eval<SBIE_OP_D, 2>(g, s, threads);
+    else launch_eval<SBIE_OP_D, 3>(g, s, threads);
+  }
+  SBIE_HIP(hipGetLastError());
+  return SBIE_OK;
+}
+
+}  // namespace sbie
+
+extern "C" {
+
+sbie_status sbie_geom_far_tree(sbie_geom* g, double theta, int32_t order, int32_t leaf) {
+  if (!g) {
+    sbie::set_error("geometry is NULL");
+    return SBIE_E_INVALID;
+  }
+  return sbie::build_tree(g, theta, order, leaf);
+}
+
+sbie_status sbie_geom_far_tree_info(const sbie_geom* g, sbie_tree_info* info) {
+  if (!g || !info) {
+    sbie::set_error("geometry or info is NULL");
+    return SBIE_E_INVALID;
+  }
+  if (!g->tree) {
+    sbie::set_error("the geometry has no tree (sbie_geom_far_tree)");
+    return SBIE_E_STATE;
+  }
+  const sbie::FarTree& t = *g->tree;
+  info->clusters = t.nc;
+  info->proxy_clusters = t.nused;
+  info->proxy_pairs = t.n_proxy;
+  info->direct_pairs = t.n_direct;
+  info->proxy_evals = t.proxy_evals;
+  info->direct_evals = t.direct_evals;
+  info->charge_evals = t.charge_evals;
+  info->device_bytes = t.bytes;
+  return SBIE_OK;
+}
+
+sbie_status sbie_far_tree_plan(int32_t M, int32_t T, const double* centers, const double* radii,
+                               const uint32_t* excl, int32_t words, double theta, int32_t order, int32_t leaf,
+                               int32_t* n_clusters, int64_t* n_proxy, int64_t* n_direct, double* box,
+                               int32_t* first, int32_t* count, int32_t* perm, int64_t* proxy_ptr,
+                               int32_t* proxy_idx, int64_t* direct_ptr, int32_t* direct_idx) {
+  if (!n_clusters || !n_proxy || !n_direct) {
+    sbie::set_error("count pointers are NULL");
+    return SBIE_E_INVALID;
+  }
+  sbie::TreePlan plan;
+  const sbie_status st = sbie::plan_tree(M, T, centers, radii, excl, words, theta, order, leaf, &plan);
+  if (st != SBIE_OK) return st;
+  *n_clusters = plan.nc;
+  *n_proxy = plan.pptr[M];
+  *n_direct = plan.dptr[M];
+  if (box) std::copy(plan.box.begin(), plan.box.end(), box);
+  if (first) std::copy(plan.first.begin(), plan.first.end(), first);
+  if (count) std::copy(plan.count.begin(), plan.count.end(), count);
+  if (perm) std::copy(plan.perm.begin(), plan.perm.end(), perm);
+  if (proxy_ptr) std::copy(plan.pptr.begin(), plan.pptr.end(), proxy_ptr);
+  if (proxy_idx) std::copy(plan.pidx.begin(), plan.pidx.end(), proxy_idx);
+  if (direct_ptr) std::copy(plan.dptr.begin(), plan.dptr.end(), direct_ptr);
+  if (direct_idx) std::copy(plan.didx.begin(), plan.didx.end(), direct_idx);
+  return SBIE_OK;
+}
+
+}  // extern "C"

@@ -10,8 +10,9 @@ p50/p99 latency, the far-field kernel's roofline figures (HIP events inside the
 library, on the apply's stream) and the CPU oracle timed on a bounded sample.
 Further sections of the same line: the FP64 path, S' and D', the Stokes single
 layer (with and without its pressure) and double layer at 256 spheroids, the
-GMRES study of the completion terms and the 512-spheroid Dirichlet and Neumann
-solves (each can be skipped with its --no-* flag).
+GMRES study of the completion terms, the 512-spheroid Dirichlet and Neumann
+solves, and the tree far field at 512 and 4096 spheroids beside the direct sum
+(each can be skipped with its --no-* flag).
 
   python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--precision mixed|fp64]
 """
@@ -232,6 +233,66 @@ PAPER_GMRES = {
     32.0: {2.0: (103, 100, 40, 31), 1.0: (109, 107, 45, 32), 0.01: (170, 169, 91, 60)},
     64.0: {2.0: (131, 133, 47, 38), 1.0: (150, 154, 57, 40), 0.01: (223, 228, 124, 67)},
 }
+
+
+def run_tree(g, dens, steps, theta=0.5, order=8, leaf=2):
+    """S and D applies with the far field through the tree (FP64 tree sums; self
+    and near in mixed precision), and the tree far part's relative l2 distance
+    from the direct FP64 far part on the same density."""
+    import numpy as np
+    import torch
+
+    import paper_2506_20809_amd as sbie
+
+    t0 = time.perf_counter()
+    info = g.far_tree(theta, order, leaf)
+    res = {"theta": theta, "order": order, "leaf": leaf, "plan_and_upload_s": time.perf_counter() - t0,
+           "tree": info}
+    for name, op in (("S", sbie.SBIE_OP_S), ("D", sbie.SBIE_OP_D)):
+        g.apply(op, dens[0, op], precision=sbie.SBIE_MIXED, tree=True, timing=True)
+        g.sync()
+        g.timing()  # discard the warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            g.apply(op, dens[k % dens.shape[0], op], precision=sbie.SBIE_MIXED, tree=True, timing=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        tim = g.timing()
+        ft = g.apply(op, dens[0, op], parts=sbie.SBIE_PARTS_FAR, tree=True)
+        fd = g.apply(op, dens[0, op], parts=sbie.SBIE_PARTS_FAR, precision=sbie.SBIE_FP64)
+        torch.cuda.synchronize()
+        diff = float(torch.linalg.norm(ft - fd) / torch.linalg.norm(fd))
+        res[name] = {"applies_per_s": steps / el, "ms_per_apply": 1e3 * el / steps,
+                     "tree_far_ms": tim.far_kernel_ms, "far_rel_l2_vs_direct_fp64": diff}
+    evals = info["proxy_evals"] + info["direct_evals"]
+    res["tree_evals_per_apply"] = evals
+    return res
+
+
+def tree_scaling(ctx, name, steps):
+    """The tree far field at a larger suspension beside the direct paths."""
+    import torch
+
+    import paper_2506_20809_amd as sbie
+    import workloads
+
+    geom = workloads.geometry(name)
+    p = workloads.CONFIGS[name]["p"]
+    t0 = time.perf_counter()
+    g = sbie.Geometry(ctx, geom, p)
+    setup_s = time.perf_counter() - t0
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(workloads.CONFIGS[name]["seed"])
+    dens = torch.randn((2, 2, g.N), dtype=torch.float64, device="cuda", generator=gen)
+    res = {"workload": f"{len(geom['A'])} polydisperse prolate/oblate spheroids (RSA, volume fraction 0.25, "
+                       f"min gap 0.02), p={p}, N={g.N} nodes",
+           "setup_s": setup_s, "tree": run_tree(g, dens, steps)}
+    direct = run(g, dens, 2, 1, "mixed")
+    res["direct_mixed"] = {"applies_per_s": direct["applies_per_s"], "far_kernel_ms": direct["part_ms"]["far_kernel"],
+                           "far_pairs": direct["far_pairs"]}
+    g.close()
+    return res
 
 
 def charge_data(pos, q, xyz):
@@ -483,6 +544,7 @@ def main():
     ap.add_argument("--no-stokes", action="store_true", help="skip the Stokes single-layer measurement")
     ap.add_argument("--no-derivatives", action="store_true", help="skip the S' and D' measurement")
     ap.add_argument("--no-solve", action="store_true", help="skip the completed double-layer solves")
+    ap.add_argument("--no-tree", action="store_true", help="skip the tree far-field measurement")
     ap.add_argument("--served-requests", type=int, default=0,
                     help="requests in the served-mode run (0: skip; the run is opt-in)")
     ap.add_argument("--served-rho", type=float, default=0.8, help="load of the Poisson arrivals")
@@ -565,6 +627,9 @@ def main():
     if not args.no_solve:
         res["solve"] = {"gmres_study": gmres_study(ctx),
                         **{f"{args.workload}_{pr}": solve_large(ctx, args.workload, pr) for pr in ("mixed", "fp64")}}
+    if not args.no_tree:
+        res["tree_far_field"] = {args.workload: run_tree(g, dens, max(4, args.steps // 4)),
+                                 "c3x8": tree_scaling(ctx, "c3x8", 3)}
     if args.served_requests > 0:
         res["served"] = served(ctx, args.served_requests, args.served_rho, args.served_precision,
                                args.served_lanes)

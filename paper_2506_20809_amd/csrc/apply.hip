@@ -548,9 +548,9 @@ sbie_status apply_laplace(sbie_geom* g, int op, int prec, const double* d_dens, 
   // with no near pairs the near part is empty and is left out of the sum
   const uint32_t sum_parts = g->n_near > 0 ? parts : (parts & ~(uint32_t)SBIE_PARTS_NEAR);
   const int RG = far_row_groups(g, !mixed);
-  if (tree)  // one forward slice, no reverse sums
+  if (tree)  // the forward slices, no reverse sums
     hipLaunchKernelGGL(k_assemble_f64<double>, dim3(cdiv(N, B)), dim3(B), 0, s, g->d_uself, g->d_unear,
-                       g->d_partial, 1, (const double*)nullptr, M, T, RG, N, sum_parts, d_out);
+                       g->d_partial, g->nsplit, (const double*)nullptr, M, T, RG, N, sum_parts, d_out);
   else if (T >= 32 && mixed)
     hipLaunchKernelGGL(k_assemble_f64<float>, dim3(cdiv(N, B)), dim3(B), 0, s, g->d_uself, g->d_unear, g->d_partial,
                        g->nsplit, reinterpret_cast<const float*>(g->d_rev), M, T, RG, N, sum_parts, d_out);

@@ -70,10 +70,14 @@ struct FarTree {
   size_t bytes = 0;
   char* blk = nullptr;                   // one device block holding everything below
   double* d_box = nullptr;               // [nused][6]
-  int32_t *d_first = nullptr, *d_count = nullptr, *d_perm = nullptr;
+  int npiece = 0;                        // workgroups of the proxy charges (pieces of used clusters)
+  int32_t *d_piece = nullptr;            // [npiece][3] cluster slot, first, count (in the permutation)
+  int32_t *d_cptr = nullptr;             // [nused+1] pieces by cluster slot
+  int32_t *d_perm = nullptr;
   int64_t *d_pptr = nullptr, *d_dptr = nullptr;
   int32_t *d_pidx = nullptr, *d_didx = nullptr;  // pidx holds used-cluster slots
-  double* d_q = nullptr;                 // [nused][(order+1)^3] proxy charges of the current apply
+  double* d_q = nullptr;                 // [nused][n3p][4] proxy points and charges of the current apply
+  double* d_qpart = nullptr;             // [npiece][(order+1)^3] their partial sums
 };
 
 }  // namespace sbie

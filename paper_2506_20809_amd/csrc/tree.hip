@@ -38,7 +38,7 @@ namespace {
 
 constexpr double kInv4PiT = 0.079577471545947667884441881686257181;
 constexpr int kTreeMaxOrder = 12;
-constexpr int kTreeChunk = 512;  // source points staged in LDS at a time
+constexpr int kChargeParts = 4;  // particles per workgroup of the proxy charges
 
 struct TreeNode {
   int first = 0, count = 0;  // range of the permutation
@@ -219,20 +219,22 @@ __device__ inline void lagrange(int n, const double* cs, const double* cw, doubl
   }
 }
 
-// Proxy charges of the used clusters (one workgroup each): qhat_k over the
-// cluster's nodes, 64 nodes at a time through LDS.  Source records: S
-// (x, y, z, W sigma) in 4 doubles, D (x, y, z, W mu nu) in 8.
+// Partial proxy charges: one workgroup per piece of a used cluster (at most
+// kChargeParts of its particles; piece = (cluster slot, first, count) in the
+// permutation), qhat_k over the piece's nodes, 64 nodes at a time through
+// LDS.  Source records: S (x, y, z, W sigma) in 4 doubles, D (x, y, z, W mu nu)
+// in 8.
 template <int OP>
-__global__ __launch_bounds__(256) void k_tree_charges(const double* __restrict__ box, const int32_t* __restrict__ first,
-                                                     const int32_t* __restrict__ count, const int32_t* __restrict__ perm,
-                                                     const double* __restrict__ src, int T, int n,
-                                                     double* __restrict__ qhat) {
+__global__ __launch_bounds__(256) void k_tree_charges(const double* __restrict__ box, const int32_t* __restrict__ piece,
+                                                     const int32_t* __restrict__ perm, const double* __restrict__ src,
+                                                     int T, int n, double* __restrict__ qpart) {
   constexpr int SW = OP == SBIE_OP_S ? 4 : 8;
   constexpr int NC = 64, NB = kTreeMaxOrder + 1;
   constexpr int NSET = OP == SBIE_OP_S ? 3 : 6;  // S: q Lx, Ly, Lz; D: Lx, Ly, Lz, d_x dLx, d_y dLy, d_z dLz
   __shared__ double basis[NSET][NC][NB];
   __shared__ double cs[NB], cw[NB];
-  const int c = blockIdx.x, tid = threadIdx.x;
+  const int pc = blockIdx.x, tid = threadIdx.x;
+  const int c = piece[3 * pc], pfirst = piece[3 * pc + 1], pcount = piece[3 * pc + 2];
   const int n1 = n + 1, n3 = n1 * n1 * n1;
   cheb_table(n, cs, cw);
   __syncthreads();
@@ -245,12 +247,12 @@ __global__ __launch_bounds__(256) void k_tree_charges(const double* __restrict__
   double acc[KPT];
 #pragma unroll
   for (int m = 0; m < KPT; ++m) acc[m] = 0.0;
-  const int64_t nodes = (int64_t)count[c] * T;
+  const int64_t nodes = (int64_t)pcount * T;
   for (int64_t j0 = 0; j0 < nodes; j0 += NC) {
     if (tid < NC) {
       const int64_t j = j0 + tid;
       if (j < nodes) {
-        const int part = perm[first[c] + (int)(j / T)];
+        const int part = perm[pfirst + (int)(j / T)];
         const double* r = src + ((int64_t)part * T + j % T) * SW;
         for (int d = 0; d < 3; ++d)
           lagrange<OP == SBIE_OP_D>(n, cs, cw, (r[d] - lo[d]) * sc[d] - 1.0, basis[d][tid],
@@ -294,8 +296,37 @@ __global__ __launch_bounds__(256) void k_tree_charges(const double* __restrict__
 #pragma unroll
   for (int m = 0; m < KPT; ++m) {
     const int k = tid + 256 * m;
-    if (k < n3) qhat[(int64_t)c * n3 + k] = acc[m];
+    if (k < n3) qpart[(int64_t)pc * n3 + k] = acc[m];
   }
+}
+
+// Proxy table of each used cluster: [n3p][4] = (point, charge), the charge
+// its pieces' partial charges added in piece order; n3p = n3 rounded up to
+// four, the padding zero charges at a distant point.
+__global__ void k_tree_proxies(const double* __restrict__ box, const int32_t* __restrict__ pptr,
+                               const double* __restrict__ qpart, int nused, int n, int n3p,
+                               double* __restrict__ prox) {
+  __shared__ double cs[kTreeMaxOrder + 1], cw[kTreeMaxOrder + 1];
+  cheb_table(n, cs, cw);
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)nused * n3p) return;
+  const int n1 = n + 1, n3 = n1 * n1 * n1;
+  const int c = (int)(i / n3p), k = (int)(i - (int64_t)c * n3p);
+  double* o = prox + 4 * i;
+  if (k >= n3) {
+    o[0] = o[1] = o[2] = 1e30;
+    o[3] = 0.0;
+    return;
+  }
+  const int idx[3] = {k / (n1 * n1), (k / n1) % n1, k % n1};
+  for (int d = 0; d < 3; ++d) {
+    const double lo = box[6 * c + d], hi = box[6 * c + 3 + d];
+    o[d] = lo + 0.5 * (cs[idx[d]] + 1.0) * (hi - lo);
+  }
+  double q = 0.0;
+  for (int p = pptr[c]; p < pptr[c + 1]; ++p) q += qpart[(int64_t)p * n3 + k];
+  o[3] = q;
 }
 
 __device__ inline double rsqrt_tree(double x) {
@@ -305,24 +336,23 @@ __device__ inline double rsqrt_tree(double x) {
   return fma(0.5 * y, e, y);
 }
 
-// Far field of one target particle per workgroup: its accepted clusters
-// through their proxies, then its direct far particles, each source set
-// staged through LDS kTreeChunk points at a time.  Lane l holds targets
-// l, l + blockDim, ... of the particle (TPT of them).
+// Far field of a target particle, its interaction lists split over nsplit
+// workgroups (split s takes the s-th of the accepted clusters and of the
+// direct particles, and writes slice s of the partial sums): the accepted
+// clusters through their proxy tables, then the direct far particles'
+// records.  Source points are read with wave-uniform addresses (scalar loads
+// through the constant cache), four per step into four partial sums.  Lane l
+// holds targets l, l + blockDim, ... of the particle (TPT of them).
 template <int OP, int TPT>
 __global__ __launch_bounds__(1024) void k_tree_eval(const double* __restrict__ x, const double* __restrict__ y,
                                                     const double* __restrict__ z, const double* __restrict__ src,
-                                                    const double* __restrict__ box, const double* __restrict__ qhat,
-                                                    const int64_t* __restrict__ pptr, const int32_t* __restrict__ pidx,
-                                                    const int64_t* __restrict__ dptr, const int32_t* __restrict__ didx,
-                                                    int T, int n, double* __restrict__ out) {
+                                                    const double* __restrict__ prox, const int64_t* __restrict__ pptr,
+                                                    const int32_t* __restrict__ pidx, const int64_t* __restrict__ dptr,
+                                                    const int32_t* __restrict__ didx, int T, int n3p, int nsplit,
+                                                    int64_t N, double* __restrict__ out) {
   constexpr int SW = OP == SBIE_OP_S ? 4 : 8;
-  __shared__ double lds[kTreeChunk * 6];
-  __shared__ double cs[kTreeMaxOrder + 1], cw[kTreeMaxOrder + 1];
-  const int t = blockIdx.x, tid = threadIdx.x;
-  const int n1 = n + 1, n3 = n1 * n1 * n1;
-  cheb_table(n, cs, cw);
-  __syncthreads();
+  const int t = blockIdx.x / nsplit, split = blockIdx.x % nsplit, tid = threadIdx.x;
+  const int64_t p0 = pptr[t], np = pptr[t + 1] - p0, d0 = dptr[t], nd = dptr[t + 1] - d0;
   double tx[TPT], ty[TPT], tz[TPT], acc[TPT];
 #pragma unroll
   for (int k = 0; k < TPT; ++k) {
@@ -333,64 +363,65 @@ __global__ __launch_bounds__(1024) void k_tree_eval(const double* __restrict__ x
     tz[k] = z[g];
     acc[k] = 0.0;
   }
-  // proxies of the accepted clusters: point charges
-  for (int64_t m = pptr[t]; m < pptr[t + 1]; ++m) {
-    const int c = pidx[m];
-    for (int k0 = 0; k0 < n3; k0 += kTreeChunk) {
-      const int kn = n3 - k0 < kTreeChunk ? n3 - k0 : kTreeChunk;
-      for (int k = tid; k < kn; k += blockDim.x) {
-        const int kk = k0 + k;
-        const int idx[3] = {kk / (n1 * n1), (kk / n1) % n1, kk % n1};
-        for (int d = 0; d < 3; ++d) {
-          const double lo = box[6 * c + d], hi = box[6 * c + 3 + d];
-          lds[4 * k + d] = lo + 0.5 * (cs[idx[d]] + 1.0) * (hi - lo);
-        }
-        lds[4 * k + 3] = qhat[(int64_t)c * n3 + kk];
-      }
-      __syncthreads();
-      for (int k = 0; k < kn; ++k) {
-        const double px = lds[4 * k], py = lds[4 * k + 1], pz = lds[4 * k + 2], q = lds[4 * k + 3];
+  // proxies of the accepted clusters: point charges, four per step
+  for (int64_t m = p0 + np * split / nsplit; m < p0 + np * (split + 1) / nsplit; ++m) {
+    const double* P = prox + (int64_t)pidx[m] * n3p * 4;
+    for (int k = 0; k < n3p; k += 4) {
 #pragma unroll
-        for (int e = 0; e < TPT; ++e) {
-          const double dx = tx[e] - px, dy = ty[e] - py, dz = tz[e] - pz;
-          acc[e] = fma(q, rsqrt_tree(fma(dz, dz, fma(dy, dy, dx * dx))), acc[e]);
+      for (int e = 0; e < TPT; ++e) {
+        double a[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double* r = P + 4 * (k + u);
+          const double dx = tx[e] - r[0], dy = ty[e] - r[1], dz = tz[e] - r[2];
+          a[u] = r[3] * rsqrt_tree(fma(dz, dz, fma(dy, dy, dx * dx)));
         }
+        acc[e] += (a[0] + a[1]) + (a[2] + a[3]);
       }
-      __syncthreads();
     }
   }
   // direct far particles
-  for (int64_t m = dptr[t]; m < dptr[t + 1]; ++m) {
+  for (int64_t m = d0 + nd * split / nsplit; m < d0 + nd * (split + 1) / nsplit; ++m) {
     const double* rs = src + (int64_t)didx[m] * T * SW;
-    for (int j0 = 0; j0 < T; j0 += kTreeChunk) {
-      const int jn = T - j0 < kTreeChunk ? T - j0 : kTreeChunk;
-      constexpr int LW = OP == SBIE_OP_S ? 4 : 6;
-      for (int j = tid; j < jn; j += blockDim.x) {
-        const double* r = rs + (int64_t)(j0 + j) * SW;
-        for (int w = 0; w < LW; ++w) lds[LW * j + w] = r[w];
-      }
-      __syncthreads();
-      for (int j = 0; j < jn; ++j) {
-        const double* r = lds + LW * j;
+    int j = 0;
+    for (; j + 4 <= T; j += 4) {
 #pragma unroll
-        for (int e = 0; e < TPT; ++e) {
+      for (int e = 0; e < TPT; ++e) {
+        double a[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double* r = rs + (int64_t)(j + u) * SW;
           const double dx = tx[e] - r[0], dy = ty[e] - r[1], dz = tz[e] - r[2];
           const double ri = rsqrt_tree(fma(dz, dz, fma(dy, dy, dx * dx)));
           if (OP == SBIE_OP_S) {
-            acc[e] = fma(r[3], ri, acc[e]);
+            a[u] = r[3] * ri;
           } else {
             const double dot = fma(r[5], dz, fma(r[4], dy, r[3] * dx));
-            acc[e] = fma(dot, ri * ri * ri, acc[e]);
+            a[u] = dot * (ri * ri * ri);
           }
         }
+        acc[e] += (a[0] + a[1]) + (a[2] + a[3]);
       }
-      __syncthreads();
+    }
+    for (; j < T; ++j) {
+      const double* r = rs + (int64_t)j * SW;
+#pragma unroll
+      for (int e = 0; e < TPT; ++e) {
+        const double dx = tx[e] - r[0], dy = ty[e] - r[1], dz = tz[e] - r[2];
+        const double ri = rsqrt_tree(fma(dz, dz, fma(dy, dy, dx * dx)));
+        if (OP == SBIE_OP_S) {
+          acc[e] = fma(r[3], ri, acc[e]);
+        } else {
+          const double dot = fma(r[5], dz, fma(r[4], dy, r[3] * dx));
+          acc[e] = fma(dot, ri * ri * ri, acc[e]);
+        }
+      }
     }
   }
 #pragma unroll
   for (int k = 0; k < TPT; ++k) {
     const int i = tid + k * blockDim.x;
-    if (i < T) out[(int64_t)t * T + i] = acc[k] * kInv4PiT;
+    if (i < T) out[(size_t)split * N + (int64_t)t * T + i] = acc[k] * kInv4PiT;
   }
 }
 
@@ -399,8 +430,10 @@ inline unsigned cdiv_t(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b
 template <int OP, int TPT>
 void launch_eval(sbie_geom* g, hipStream_t s, int threads) {
   const FarTree& tr = *g->tree;
-  hipLaunchKernelGGL((k_tree_eval<OP, TPT>), dim3(g->M), dim3(threads), 0, s, g->d_x, g->d_y, g->d_z, g->d_src,
-                     tr.d_box, tr.d_q, tr.d_pptr, tr.d_pidx, tr.d_dptr, tr.d_didx, g->T, tr.order, g->d_partial);
+  const int n3 = (tr.order + 1) * (tr.order + 1) * (tr.order + 1);
+  hipLaunchKernelGGL((k_tree_eval<OP, TPT>), dim3(g->M * g->nsplit), dim3(threads), 0, s, g->d_x, g->d_y, g->d_z,
+                     g->d_src, tr.d_q, tr.d_pptr, tr.d_pidx, tr.d_dptr, tr.d_didx, g->T, (n3 + 3) & ~3, g->nsplit,
+                     g->N, g->d_partial);
 }
 
 }  // namespace
@@ -437,12 +470,19 @@ sbie_status build_tree(sbie_geom* g, double theta, int order, int leaf) {
   const int nu = (int)used.size();
   const int n3 = (order + 1) * (order + 1) * (order + 1);
   std::vector<double> box(6 * (size_t)std::max(nu, 1));
-  std::vector<int32_t> first(std::max(nu, 1)), count(std::max(nu, 1));
+  std::vector<int32_t> piece, cptr(nu + 1, 0);
   for (int u = 0; u < nu; ++u) {
     for (int w = 0; w < 6; ++w) box[6 * (size_t)u + w] = plan.box[6 * (size_t)used[u] + w];
-    first[u] = plan.first[used[u]];
-    count[u] = plan.count[used[u]];
+    const int f = plan.first[used[u]], cnt = plan.count[used[u]];
+    for (int o = 0; o < cnt; o += kChargeParts) {
+      piece.push_back(u);
+      piece.push_back(f + o);
+      piece.push_back(std::min(kChargeParts, cnt - o));
+    }
+    cptr[u + 1] = (int32_t)(piece.size() / 3);
   }
+  const int npiece = (int)(piece.size() / 3);
+  if (piece.empty()) piece.assign(3, 0);
   if (plan.pidx.empty()) plan.pidx.push_back(0);
   if (plan.didx.empty()) plan.didx.push_back(0);
   free_tree(g);
@@ -457,15 +497,18 @@ sbie_status build_tree(sbie_geom* g, double theta, int order, int leaf) {
   tr->n_direct = plan.dptr[M];
   tr->proxy_evals = tr->n_proxy * (int64_t)n3 * T;
   tr->direct_evals = tr->n_direct * (int64_t)T * T;
-  for (int u = 0; u < nu; ++u) tr->charge_evals += (int64_t)count[u] * T * n3;
+  for (int u = 0; u < nu; ++u) tr->charge_evals += (int64_t)plan.count[used[u]] * T * n3;
+  tr->npiece = npiece;
   // one device block: boxes, member ranges, the permutation, the lists and
   // the proxy charges
   auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-  const size_t sz_box = al(sizeof(double) * box.size()), sz_fc = al(sizeof(int32_t) * first.size());
+  const size_t sz_box = al(sizeof(double) * box.size()), sz_piece = al(sizeof(int32_t) * piece.size());
+  const size_t sz_cptr = al(sizeof(int32_t) * cptr.size());
   const size_t sz_perm = al(sizeof(int32_t) * M), sz_ptr = al(sizeof(int64_t) * (M + 1));
   const size_t sz_pidx = al(sizeof(int32_t) * plan.pidx.size()), sz_didx = al(sizeof(int32_t) * plan.didx.size());
-  const size_t sz_q = al(sizeof(double) * (size_t)std::max(nu, 1) * n3);
-  const size_t total = sz_box + 2 * sz_fc + sz_perm + 2 * sz_ptr + sz_pidx + sz_didx + sz_q;
+  const size_t sz_q = al(sizeof(double) * 4 * (size_t)std::max(nu, 1) * ((n3 + 3) & ~3));
+  const size_t sz_qp = al(sizeof(double) * (size_t)std::max(npiece, 1) * n3);
+  const size_t total = sz_box + sz_piece + sz_cptr + sz_perm + 2 * sz_ptr + sz_pidx + sz_didx + sz_q + sz_qp;
   if (hipMalloc(&tr->blk, total) != hipSuccess) {
     (void)hipGetLastError();
     free_tree(g);
@@ -478,18 +521,19 @@ sbie_status build_tree(sbie_geom* g, double theta, int order, int leaf) {
     return q;
   };
   tr->d_box = reinterpret_cast<double*>(take(sz_box));
-  tr->d_first = reinterpret_cast<int32_t*>(take(sz_fc));
-  tr->d_count = reinterpret_cast<int32_t*>(take(sz_fc));
+  tr->d_piece = reinterpret_cast<int32_t*>(take(sz_piece));
+  tr->d_cptr = reinterpret_cast<int32_t*>(take(sz_cptr));
   tr->d_perm = reinterpret_cast<int32_t*>(take(sz_perm));
   tr->d_pptr = reinterpret_cast<int64_t*>(take(sz_ptr));
   tr->d_dptr = reinterpret_cast<int64_t*>(take(sz_ptr));
   tr->d_pidx = reinterpret_cast<int32_t*>(take(sz_pidx));
   tr->d_didx = reinterpret_cast<int32_t*>(take(sz_didx));
   tr->d_q = reinterpret_cast<double*>(take(sz_q));
+  tr->d_qpart = reinterpret_cast<double*>(take(sz_qp));
   tr->bytes = total;
   SBIE_HIP(hipMemcpy(tr->d_box, box.data(), sizeof(double) * box.size(), hipMemcpyHostToDevice));
-  SBIE_HIP(hipMemcpy(tr->d_first, first.data(), sizeof(int32_t) * first.size(), hipMemcpyHostToDevice));
-  SBIE_HIP(hipMemcpy(tr->d_count, count.data(), sizeof(int32_t) * count.size(), hipMemcpyHostToDevice));
+  SBIE_HIP(hipMemcpy(tr->d_piece, piece.data(), sizeof(int32_t) * piece.size(), hipMemcpyHostToDevice));
+  SBIE_HIP(hipMemcpy(tr->d_cptr, cptr.data(), sizeof(int32_t) * cptr.size(), hipMemcpyHostToDevice));
   SBIE_HIP(hipMemcpy(tr->d_perm, plan.perm.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice));
   SBIE_HIP(hipMemcpy(tr->d_pptr, plan.pptr.data(), sizeof(int64_t) * (M + 1), hipMemcpyHostToDevice));
   SBIE_HIP(hipMemcpy(tr->d_dptr, plan.dptr.data(), sizeof(int64_t) * (M + 1), hipMemcpyHostToDevice));
@@ -498,17 +542,21 @@ sbie_status build_tree(sbie_geom* g, double theta, int order, int leaf) {
   return SBIE_OK;
 }
 
-// Far field of S or D through the tree into partial slice 0 (FP64).  The
-// source records d_src (k_prep_f64) must be current.
+// Far field of S or D through the tree into the nsplit partial slices
+// (FP64).  The source records d_src (k_prep_f64) must be current.
 sbie_status far_tree(sbie_geom* g, int op, hipStream_t s) {
   const FarTree& tr = *g->tree;
   if (tr.nused > 0) {
     if (op == SBIE_OP_S)
-      hipLaunchKernelGGL(k_tree_charges<SBIE_OP_S>, dim3(tr.nused), dim3(256), 0, s, tr.d_box, tr.d_first,
-                         tr.d_count, tr.d_perm, g->d_src, g->T, tr.order, tr.d_q);
+      hipLaunchKernelGGL(k_tree_charges<SBIE_OP_S>, dim3(tr.npiece), dim3(256), 0, s, tr.d_box, tr.d_piece, tr.d_perm,
+                         g->d_src, g->T, tr.order, tr.d_qpart);
     else
-      hipLaunchKernelGGL(k_tree_charges<SBIE_OP_D>, dim3(tr.nused), dim3(256), 0, s, tr.d_box, tr.d_first,
-                         tr.d_count, tr.d_perm, g->d_src, g->T, tr.order, tr.d_q);
+      hipLaunchKernelGGL(k_tree_charges<SBIE_OP_D>, dim3(tr.npiece), dim3(256), 0, s, tr.d_box, tr.d_piece, tr.d_perm,
+                         g->d_src, g->T, tr.order, tr.d_qpart);
+    SBIE_HIP(hipGetLastError());
+    const int n3 = (tr.order + 1) * (tr.order + 1) * (tr.order + 1), n3p = (n3 + 3) & ~3;
+    hipLaunchKernelGGL(k_tree_proxies, dim3(cdiv_t((int64_t)tr.nused * n3p, 256)), dim3(256), 0, s, tr.d_box,
+                       tr.d_cptr, tr.d_qpart, tr.nused, tr.order, n3p, tr.d_q);
     SBIE_HIP(hipGetLastError());
   }
   // lanes: 64 * ceil(T / (64 TPT)) with the smallest TPT that fits 1024

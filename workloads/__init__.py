@@ -272,6 +272,8 @@ CONFIGS = {
     "c4": dict(M=256, p=12, phi=0.20, gap=0.05, seed=4),
     # pool the served requests are cut from (see served_request)
     "c5_pool": dict(M=1024, phi=0.15, gap=0.05, seed=5),
+    # eight times the 512-spheroid suspension, same recipe: the tree far field's scaling case
+    "c3x8": dict(M=4096, p=16, phi=0.25, gap=0.02, seed=13),
 }
 
 

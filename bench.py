@@ -235,7 +235,7 @@ PAPER_GMRES = {
 }
 
 
-def run_tree(g, dens, steps, theta=0.5, order=8, leaf=2):
+def run_tree(g, dens, steps, theta=0.6, order=10, leaf=2):
     """S and D applies with the far field through the tree (FP64 tree sums; self
     and near in mixed precision), and the tree far part's relative l2 distance
     from the direct FP64 far part on the same density."""

@@ -269,7 +269,7 @@ class Geometry:
                                 ctypes.c_void_p(stream.cuda_stream), flags | SBIE_DEVICE_PTRS))
         return out
 
-    def far_tree(self, theta: float = 0.5, order: int = 8, leaf: int = 2):
+    def far_tree(self, theta: float = 0.6, order: int = 10, leaf: int = 2):
         """Build the geometry's tree far field (sbie_geom_far_tree); returns far_tree_info()."""
         _check(lib().sbie_geom_far_tree(self._h, float(theta), int(order), int(leaf)))
         return self.far_tree_info()

@@ -523,7 +523,7 @@ sbie_status apply_laplace(sbie_geom* g, int op, int prec, const double* d_dens, 
   const bool tree = (parts & SBIE_FAR_TREE) != 0;
   if ((parts & SBIE_PARTS_FAR) && tree) {
     if (timed) SBIE_HIP(hipEventRecord(ev[3], s));
-    sbie_status st = far_tree(g, op, s);
+    sbie_status st = far_tree(g, op, prec == SBIE_MIXED, s);
     if (st) return st;
     if (timed) SBIE_HIP(hipEventRecord(ev[4], s));
   } else if ((parts & SBIE_PARTS_FAR) && T >= 32) {

@@ -78,6 +78,8 @@ struct FarTree {
   int32_t *d_pidx = nullptr, *d_didx = nullptr;  // pidx holds used-cluster slots
   double* d_q = nullptr;                 // [nused][n3p][4] proxy points and charges of the current apply
   double* d_qpart = nullptr;             // [npiece][(order+1)^3] their partial sums
+  float* d_q32 = nullptr;                // [nused][n3p][4] mixed path: proxy - box centre, charge
+  float* d_src32 = nullptr;              // [N][8] mixed path: node - particle centre, strength
 };
 
 }  // namespace sbie
@@ -209,7 +211,7 @@ sbie_status plan_tree(int M, int T, const double* centers, const double* radii, 
                       double theta, int order, int leaf, TreePlan* out);
 sbie_status build_tree(sbie_geom* g, double theta, int order, int leaf);
 void free_tree(sbie_geom* g);
-sbie_status far_tree(sbie_geom* g, int op, hipStream_t s);
+sbie_status far_tree(sbie_geom* g, int op, bool mixed, hipStream_t s);
 
 // Carves 256-byte aligned buffers out of one device block; with no block it
 // only measures.

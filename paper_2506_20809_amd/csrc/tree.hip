@@ -172,6 +172,14 @@ sbie_status plan_tree(int M, int T, const double* centers, const double* radii, 
 
 namespace {
 
+// 1/sqrt(x): the hardware estimate and one Newton step
+__device__ inline double rsqrt_tree(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double h = x * y;
+  const double e = fma(-h, y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+
 // Chebyshev points of the second kind s_k = cos(pi k / n) on [-1, 1] and
 // their barycentric weights (-1)^k, halved at both ends, into cs[0..n] and
 // cw[0..n] (LDS, filled by the first n+1 lanes)
@@ -305,7 +313,7 @@ __global__ __launch_bounds__(256) void k_tree_charges(const double* __restrict__
 // four, the padding zero charges at a distant point.
 __global__ void k_tree_proxies(const double* __restrict__ box, const int32_t* __restrict__ pptr,
                                const double* __restrict__ qpart, int nused, int n, int n3p,
-                               double* __restrict__ prox) {
+                               double* __restrict__ prox, float* __restrict__ prox32) {
   __shared__ double cs[kTreeMaxOrder + 1], cw[kTreeMaxOrder + 1];
   cheb_table(n, cs, cw);
   __syncthreads();
@@ -317,23 +325,169 @@ __global__ void k_tree_proxies(const double* __restrict__ box, const int32_t* __
   if (k >= n3) {
     o[0] = o[1] = o[2] = 1e30;
     o[3] = 0.0;
+    if (prox32) {
+      float* f = prox32 + 4 * i;
+      f[0] = f[1] = f[2] = 1e30f;
+      f[3] = 0.0f;
+    }
     return;
   }
   const int idx[3] = {k / (n1 * n1), (k / n1) % n1, k % n1};
+  double rel[3];
   for (int d = 0; d < 3; ++d) {
     const double lo = box[6 * c + d], hi = box[6 * c + 3 + d];
     o[d] = lo + 0.5 * (cs[idx[d]] + 1.0) * (hi - lo);
+    rel[d] = 0.5 * cs[idx[d]] * (hi - lo);  // from the box centre
   }
   double q = 0.0;
   for (int p = pptr[c]; p < pptr[c + 1]; ++p) q += qpart[(int64_t)p * n3 + k];
   o[3] = q;
+  if (prox32) {
+    float* f = prox32 + 4 * i;
+    f[0] = (float)rel[0];
+    f[1] = (float)rel[1];
+    f[2] = (float)rel[2];
+    f[3] = (float)q;
+  }
 }
 
-__device__ inline double rsqrt_tree(double x) {
-  const double y = __builtin_amdgcn_rsq(x);
-  const double h = x * y;
-  const double e = fma(-h, y, 1.0);
-  return fma(0.5 * y, e, y);
+// FP32 records of the direct sources for the mixed path: node - particle
+// centre and the strength, S (o, W sigma) in 4 floats, D (o, W mu nu, 0, 0) in 8.
+template <int OP>
+__global__ void k_tree_src32(const double* __restrict__ src, const Particle* __restrict__ part, int T, int64_t N,
+                             float* __restrict__ src32) {
+  constexpr int SW = OP == SBIE_OP_S ? 4 : 8;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  const double* r = src + g * SW;
+  const double* c = part[g / T].c;
+  float* o = src32 + g * SW;
+  for (int d = 0; d < 3; ++d) o[d] = (float)(r[d] - c[d]);
+  for (int w = 3; w < SW; ++w) o[w] = (float)r[w];
+}
+
+// The mixed-precision counterpart of k_tree_eval: FP32 differences from each
+// source set's origin (a cluster's box centre, a source particle's centre),
+// the target's offset from it rounded once per set, FP32 terms four per step
+// added into the FP64 sum.  The double layer's proxy charges cancel strongly
+// within a cluster (they come from dipoles), so its proxy sums stay FP64; its
+// direct sums are FP32 like the single layer's.
+template <int OP, int TPT>
+__global__ __launch_bounds__(1024) void k_tree_eval32(const double* __restrict__ x, const double* __restrict__ y,
+                                                      const double* __restrict__ z, const float* __restrict__ src32,
+                                                      const Particle* __restrict__ part,
+                                                      const float* __restrict__ prox32, const double* __restrict__ prox,
+                                                      const double* __restrict__ box,
+                                                      const int64_t* __restrict__ pptr, const int32_t* __restrict__ pidx,
+                                                      const int64_t* __restrict__ dptr, const int32_t* __restrict__ didx,
+                                                      int T, int n3p, int nsplit, int64_t N, double* __restrict__ out) {
+  constexpr int SW = OP == SBIE_OP_S ? 4 : 8;
+  const int t = blockIdx.x / nsplit, split = blockIdx.x % nsplit, tid = threadIdx.x;
+  const int64_t p0 = pptr[t], np = pptr[t + 1] - p0, d0 = dptr[t], nd = dptr[t + 1] - d0;
+  double tx[TPT], ty[TPT], tz[TPT], acc[TPT];
+#pragma unroll
+  for (int k = 0; k < TPT; ++k) {
+    const int i = tid + k * blockDim.x;
+    const int64_t g = (int64_t)t * T + (i < T ? i : 0);
+    tx[k] = x[g];
+    ty[k] = y[g];
+    tz[k] = z[g];
+    acc[k] = 0.0;
+  }
+  for (int64_t m = p0 + np * split / nsplit; m < p0 + np * (split + 1) / nsplit; ++m) {
+    const int c = pidx[m];
+    if (OP == SBIE_OP_D) {
+      const double* P = prox + (int64_t)c * n3p * 4;
+      for (int k = 0; k < n3p; k += 4) {
+#pragma unroll
+        for (int e = 0; e < TPT; ++e) {
+          double a[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const double* r = P + 4 * (k + u);
+            const double dx = tx[e] - r[0], dy = ty[e] - r[1], dz = tz[e] - r[2];
+            a[u] = r[3] * rsqrt_tree(fma(dz, dz, fma(dy, dy, dx * dx)));
+          }
+          acc[e] += (a[0] + a[1]) + (a[2] + a[3]);
+        }
+      }
+      continue;
+    }
+    const float* P = prox32 + (int64_t)c * n3p * 4;
+    const double bx = 0.5 * (box[6 * c] + box[6 * c + 3]), by = 0.5 * (box[6 * c + 1] + box[6 * c + 4]),
+                 bz = 0.5 * (box[6 * c + 2] + box[6 * c + 5]);
+    float rx[TPT], ry[TPT], rz[TPT];
+#pragma unroll
+    for (int e = 0; e < TPT; ++e) {
+      rx[e] = (float)(tx[e] - bx);
+      ry[e] = (float)(ty[e] - by);
+      rz[e] = (float)(tz[e] - bz);
+    }
+    for (int k = 0; k < n3p; k += 4) {
+#pragma unroll
+      for (int e = 0; e < TPT; ++e) {
+        float a[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const float* r = P + 4 * (k + u);
+          const float dx = rx[e] - r[0], dy = ry[e] - r[1], dz = rz[e] - r[2];
+          a[u] = r[3] * __builtin_amdgcn_rsqf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+        }
+        acc[e] += (double)((a[0] + a[1]) + (a[2] + a[3]));
+      }
+    }
+  }
+  for (int64_t m = d0 + nd * split / nsplit; m < d0 + nd * (split + 1) / nsplit; ++m) {
+    const int s = didx[m];
+    const float* rs = src32 + (int64_t)s * T * SW;
+    const double* cc = part[s].c;
+    float rx[TPT], ry[TPT], rz[TPT];
+#pragma unroll
+    for (int e = 0; e < TPT; ++e) {
+      rx[e] = (float)(tx[e] - cc[0]);
+      ry[e] = (float)(ty[e] - cc[1]);
+      rz[e] = (float)(tz[e] - cc[2]);
+    }
+    int j = 0;
+    for (; j + 4 <= T; j += 4) {
+#pragma unroll
+      for (int e = 0; e < TPT; ++e) {
+        float a[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const float* r = rs + (int64_t)(j + u) * SW;
+          const float dx = rx[e] - r[0], dy = ry[e] - r[1], dz = rz[e] - r[2];
+          const float ri = __builtin_amdgcn_rsqf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+          if (OP == SBIE_OP_S) {
+            a[u] = r[3] * ri;
+          } else {
+            const float dot = fmaf(r[5], dz, fmaf(r[4], dy, r[3] * dx));
+            a[u] = dot * (ri * ri * ri);
+          }
+        }
+        acc[e] += (double)((a[0] + a[1]) + (a[2] + a[3]));
+      }
+    }
+    for (; j < T; ++j) {
+      const float* r = rs + (int64_t)j * SW;
+#pragma unroll
+      for (int e = 0; e < TPT; ++e) {
+        const float dx = rx[e] - r[0], dy = ry[e] - r[1], dz = rz[e] - r[2];
+        const float ri = __builtin_amdgcn_rsqf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+        if (OP == SBIE_OP_S) {
+          acc[e] += (double)(r[3] * ri);
+        } else {
+          const float dot = fmaf(r[5], dz, fmaf(r[4], dy, r[3] * dx));
+          acc[e] += (double)(dot * (ri * ri * ri));
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < TPT; ++k) {
+    const int i = tid + k * blockDim.x;
+    if (i < T) out[(size_t)split * N + (int64_t)t * T + i] = acc[k] * kInv4PiT;
+  }
 }
 
 // Far field of a target particle, its interaction lists split over nsplit
@@ -428,8 +582,16 @@ __global__ __launch_bounds__(1024) void k_tree_eval(const double* __restrict__ x
 inline unsigned cdiv_t(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
 template <int OP, int TPT>
-void launch_eval(sbie_geom* g, hipStream_t s, int threads) {
+void launch_eval(sbie_geom* g, hipStream_t s, int threads, bool mixed) {
   const FarTree& tr = *g->tree;
+  if (mixed) {
+    const int n3 = (tr.order + 1) * (tr.order + 1) * (tr.order + 1);
+    hipLaunchKernelGGL((k_tree_eval32<OP, TPT>), dim3(g->M * g->nsplit), dim3(threads), 0, s, g->d_x, g->d_y,
+                       g->d_z, tr.d_src32, g->d_part, tr.d_q32, tr.d_q, tr.d_box, tr.d_pptr, tr.d_pidx, tr.d_dptr,
+                       tr.d_didx,
+                       g->T, (n3 + 3) & ~3, g->nsplit, g->N, g->d_partial);
+    return;
+  }
   const int n3 = (tr.order + 1) * (tr.order + 1) * (tr.order + 1);
   hipLaunchKernelGGL((k_tree_eval<OP, TPT>), dim3(g->M * g->nsplit), dim3(threads), 0, s, g->d_x, g->d_y, g->d_z,
                      g->d_src, tr.d_q, tr.d_pptr, tr.d_pidx, tr.d_dptr, tr.d_didx, g->T, (n3 + 3) & ~3, g->nsplit,
@@ -508,7 +670,10 @@ sbie_status build_tree(sbie_geom* g, double theta, int order, int leaf) {
   const size_t sz_pidx = al(sizeof(int32_t) * plan.pidx.size()), sz_didx = al(sizeof(int32_t) * plan.didx.size());
   const size_t sz_q = al(sizeof(double) * 4 * (size_t)std::max(nu, 1) * ((n3 + 3) & ~3));
   const size_t sz_qp = al(sizeof(double) * (size_t)std::max(npiece, 1) * n3);
-  const size_t total = sz_box + sz_piece + sz_cptr + sz_perm + 2 * sz_ptr + sz_pidx + sz_didx + sz_q + sz_qp;
+  const size_t sz_q32 = al(sizeof(float) * 4 * (size_t)std::max(nu, 1) * ((n3 + 3) & ~3));
+  const size_t sz_s32 = al(sizeof(float) * 8 * (size_t)g->N);
+  const size_t total =
+      sz_box + sz_piece + sz_cptr + sz_perm + 2 * sz_ptr + sz_pidx + sz_didx + sz_q + sz_qp + sz_q32 + sz_s32;
   if (hipMalloc(&tr->blk, total) != hipSuccess) {
     (void)hipGetLastError();
     free_tree(g);
@@ -530,6 +695,8 @@ sbie_status build_tree(sbie_geom* g, double theta, int order, int leaf) {
   tr->d_didx = reinterpret_cast<int32_t*>(take(sz_didx));
   tr->d_q = reinterpret_cast<double*>(take(sz_q));
   tr->d_qpart = reinterpret_cast<double*>(take(sz_qp));
+  tr->d_q32 = reinterpret_cast<float*>(take(sz_q32));
+  tr->d_src32 = reinterpret_cast<float*>(take(sz_s32));
   tr->bytes = total;
   SBIE_HIP(hipMemcpy(tr->d_box, box.data(), sizeof(double) * box.size(), hipMemcpyHostToDevice));
   SBIE_HIP(hipMemcpy(tr->d_piece, piece.data(), sizeof(int32_t) * piece.size(), hipMemcpyHostToDevice));
@@ -542,10 +709,21 @@ sbie_status build_tree(sbie_geom* g, double theta, int order, int leaf) {
   return SBIE_OK;
 }
 
-// Far field of S or D through the tree into the nsplit partial slices
-// (FP64).  The source records d_src (k_prep_f64) must be current.
-sbie_status far_tree(sbie_geom* g, int op, hipStream_t s) {
+// Far field of S or D through the tree into the nsplit partial slices, the
+// sums in FP64 or (mixed) FP32.  The source records d_src (k_prep_f64) must
+// be current.
+sbie_status far_tree(sbie_geom* g, int op, bool mixed, hipStream_t s) {
   const FarTree& tr = *g->tree;
+  if (mixed) {
+    const unsigned nb = cdiv_t(g->N, 256);
+    if (op == SBIE_OP_S)
+      hipLaunchKernelGGL(k_tree_src32<SBIE_OP_S>, dim3(nb), dim3(256), 0, s, g->d_src, g->d_part, g->T, g->N,
+                         tr.d_src32);
+    else
+      hipLaunchKernelGGL(k_tree_src32<SBIE_OP_D>, dim3(nb), dim3(256), 0, s, g->d_src, g->d_part, g->T, g->N,
+                         tr.d_src32);
+    SBIE_HIP(hipGetLastError());
+  }
   if (tr.nused > 0) {
     if (op == SBIE_OP_S)
       hipLaunchKernelGGL(k_tree_charges<SBIE_OP_S>, dim3(tr.npiece), dim3(256), 0, s, tr.d_box, tr.d_piece, tr.d_perm,
@@ -556,7 +734,7 @@ sbie_status far_tree(sbie_geom* g, int op, hipStream_t s) {
     SBIE_HIP(hipGetLastError());
     const int n3 = (tr.order + 1) * (tr.order + 1) * (tr.order + 1), n3p = (n3 + 3) & ~3;
     hipLaunchKernelGGL(k_tree_proxies, dim3(cdiv_t((int64_t)tr.nused * n3p, 256)), dim3(256), 0, s, tr.d_box,
-                       tr.d_cptr, tr.d_qpart, tr.nused, tr.order, n3p, tr.d_q);
+                       tr.d_cptr, tr.d_qpart, tr.nused, tr.order, n3p, tr.d_q, mixed ? tr.d_q32 : nullptr);
     SBIE_HIP(hipGetLastError());
   }
   // lanes: 64 * ceil(T / (64 TPT)) with the smallest TPT that fits 1024
@@ -564,13 +742,13 @@ sbie_status far_tree(sbie_geom* g, int op, hipStream_t s) {
   const int tpt = T <= 1024 ? 1 : (T <= 2048 ? 2 : 3);
   const int threads = 64 * (int)cdiv_t(cdiv_t(T, tpt), 64);
   if (op == SBIE_OP_S) {
-    if (tpt == 1) launch_eval<SBIE_OP_S, 1>(g, s, threads);
-    else if (tpt == 2) launch_eval<SBIE_OP_S, 2>(g, s, threads);
-    else launch_eval<SBIE_OP_S, 3>(g, s, threads);
+    if (tpt == 1) launch_eval<SBIE_OP_S, 1>(g, s, threads, mixed);
+    else if (tpt == 2) launch_eval<SBIE_OP_S, 2>(g, s, threads, mixed);
+    else launch_eval<SBIE_OP_S, 3>(g, s, threads, mixed);
   } else {
-    if (tpt == 1) launch_eval<SBIE_OP_D, 1>(g, s, threads);
-    else if (tpt == 2) launch_eval<SBIE_OP_D, 2>(g, s, threads);
-    else launch_eval<SBIE_OP_D, 3>(g, s, threads);
+    if (tpt == 1) launch_eval<SBIE_OP_D, 1>(g, s, threads, mixed);
+    else if (tpt == 2) launch_eval<SBIE_OP_D, 2>(g, s, threads, mixed);
+    else launch_eval<SBIE_OP_D, 3>(g, s, threads, mixed);
   }
   SBIE_HIP(hipGetLastError());
   return SBIE_OK;

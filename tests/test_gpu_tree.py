@@ -3,8 +3,8 @@
 
 Bars: with theta = 0.5 and order 8 the interpolation error measured about
 1e-9 (S) and 3e-8 (D) relative l2 on the 64-spheroid suspension, so the tree
-far part and the whole operator with it are held to the mixed path's bar,
-relative l2 <= 1e-6 (max-norm <= 1e-5).  A tree that takes no cluster
+far part and the whole operator with it, FP64 or mixed (FP32 tree sums), are
+held to the mixed path's bar, relative l2 <= 1e-6 (max-norm <= 1e-5).  A tree that takes no cluster
 through proxies is the exact far sum: FP64 bar, 1e-10.  At 512 spheroids
 (p = 16) sampled nodes are checked against the oracle one by one."""
 import numpy as np
@@ -45,6 +45,9 @@ def test_parity_64_spheroids(ctx, op):
     far = g.apply(op, dens, parts=sbie.SBIE_PARTS_FAR, tree=True)
     l2, mx = _rel(far, uf)
     assert l2 < 1e-6 and mx < 1e-5, (l2, mx)
+    far32 = g.apply(op, dens, parts=sbie.SBIE_PARTS_FAR, tree=True, precision=sbie.SBIE_MIXED)
+    l2, mx = _rel(far32, uf)
+    assert l2 < 1e-6 and mx < 1e-5, (l2, mx)
     whole = g.apply(op, dens, tree=True)
     l2, mx = _rel(whole, u)
     assert l2 < 1e-6 and mx < 1e-5, (l2, mx)
@@ -71,8 +74,10 @@ def test_tree_without_proxies_is_the_exact_far_sum(ctx):
     g.close()
 
 
+@pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("op", [0, 1])
-def test_512_spheroids_sampled(ctx, op):
+def test_512_spheroids_sampled(ctx, op, precision):
+    """FP64 tree sums (precision 0) and the mixed path's FP32 sums (1)."""
     import torch
 
     import paper_2506_20809_amd as sbie
@@ -82,7 +87,8 @@ def test_512_spheroids_sampled(ctx, op):
     info = g.far_tree(0.5, 8, 2)
     assert info["proxy_evals"] > 0
     dens = workloads.density("c3")[0]
-    far = g.apply(op, torch.tensor(dens, device="cuda"), parts=sbie.SBIE_PARTS_FAR, tree=True).cpu().numpy()
+    far = g.apply(op, torch.tensor(dens, device="cuda"), parts=sbie.SBIE_PARTS_FAR, tree=True,
+                  precision=precision).cpu().numpy()
     sel = np.sort(np.random.default_rng(50 + op).choice(g.N, 24, replace=False))
     uf = oracle.apply_at(geom, p, op, dens, sel)[3]
     l2, mx = _rel(far[sel], uf)

@@ -554,7 +554,7 @@ def main():
                     help="run one plain 256 MiB device copy first (a known-size reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the operator apply here is a one-GPU path (sharding across GPUs is designed, not built); --gpus must be 1"}))
         sys.exit(2)
 
     import torch

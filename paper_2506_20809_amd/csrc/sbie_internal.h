@@ -78,8 +78,13 @@ struct FarTree {
   int32_t *d_pidx = nullptr, *d_didx = nullptr;  // pidx holds used-cluster slots
   double* d_q = nullptr;                 // [nused][n3p][4] proxy points and charges of the current apply
   double* d_qpart = nullptr;             // [npiece][(order+1)^3] their partial sums
-  float* d_q32 = nullptr;                // [nused][n3p][4] mixed path: proxy - box centre, charge
-  float* d_src32 = nullptr;              // [N][8] mixed path: node - particle centre, strength
+  // mixed path: the single layer's three-piece matrix-core records (64 lanes
+  // x 4 words per 16 sources; n3b = ceil((order+1)^3 / 16), T16 = ceil(T / 16))
+  uint32_t* d_prec = nullptr;            // [nused][n3b][64][4] proxies - box centre
+  uint32_t* d_srec = nullptr;            // [M][T16][64][4] nodes - particle centre
+  float* d_q32 = nullptr;                // [nused][16 n3b] single layer proxy charges of the current apply
+  float* d_sq32 = nullptr;               // [M][16 T16] single layer node strengths of the current apply
+  float* d_src32 = nullptr;              // [N][8] double layer: node - particle centre, W mu nu
 };
 
 }  // namespace sbie

@@ -31,6 +31,7 @@
 #include <vector>
 
 #include "sbie_internal.h"
+#include "x3.h"
 
 namespace sbie {
 
@@ -310,78 +311,213 @@ __global__ __launch_bounds__(256) void k_tree_charges(const double* __restrict__
 
 // Proxy table of each used cluster: [n3p][4] = (point, charge), the charge
 // its pieces' partial charges added in piece order; n3p = n3 rounded up to
-// four, the padding zero charges at a distant point.
+// four, the padding zero charges at a distant point.  With q32 (mixed path)
+// also the FP32 charges alone, nq = 16 n3b per cluster, zero past n3; the
+// grid covers nq entries per cluster (n3p without q32).
 __global__ void k_tree_proxies(const double* __restrict__ box, const int32_t* __restrict__ pptr,
-                               const double* __restrict__ qpart, int nused, int n, int n3p,
-                               double* __restrict__ prox, float* __restrict__ prox32) {
+                               const double* __restrict__ qpart, int nused, int n, int n3p, int nq,
+                               double* __restrict__ prox, float* __restrict__ q32) {
   __shared__ double cs[kTreeMaxOrder + 1], cw[kTreeMaxOrder + 1];
   cheb_table(n, cs, cw);
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)nused * n3p) return;
+  if (i >= (int64_t)nused * nq) return;
   const int n1 = n + 1, n3 = n1 * n1 * n1;
-  const int c = (int)(i / n3p), k = (int)(i - (int64_t)c * n3p);
-  double* o = prox + 4 * i;
+  const int c = (int)(i / nq), k = (int)(i - (int64_t)c * nq);
+  double* o = prox + 4 * ((int64_t)c * n3p + k);
   if (k >= n3) {
-    o[0] = o[1] = o[2] = 1e30;
-    o[3] = 0.0;
-    if (prox32) {
-      float* f = prox32 + 4 * i;
-      f[0] = f[1] = f[2] = 1e30f;
-      f[3] = 0.0f;
+    if (k < n3p) {
+      o[0] = o[1] = o[2] = 1e30;
+      o[3] = 0.0;
     }
+    if (q32) q32[i] = 0.0f;
     return;
   }
   const int idx[3] = {k / (n1 * n1), (k / n1) % n1, k % n1};
-  double rel[3];
   for (int d = 0; d < 3; ++d) {
     const double lo = box[6 * c + d], hi = box[6 * c + 3 + d];
     o[d] = lo + 0.5 * (cs[idx[d]] + 1.0) * (hi - lo);
-    rel[d] = 0.5 * cs[idx[d]] * (hi - lo);  // from the box centre
   }
   double q = 0.0;
   for (int p = pptr[c]; p < pptr[c + 1]; ++p) q += qpart[(int64_t)p * n3 + k];
   o[3] = q;
-  if (prox32) {
-    float* f = prox32 + 4 * i;
-    f[0] = (float)rel[0];
-    f[1] = (float)rel[1];
-    f[2] = (float)rel[2];
-    f[3] = (float)q;
+  if (q32) q32[i] = (float)q;
+}
+
+// Matrix-core form of the mixed path.  Sources are the rows of a 16x16x32 bf16
+// product in the three-piece form, target nodes its columns: source record
+// [-2 s, |s|^2] against [t, 1] with |t|^2 in the extra slots gives |t - s|^2
+// for 16 x 16 pairs, s and t rounded to FP32 once, relative to the source
+// set's origin (a cluster's box centre, a source particle's centre).  One
+// record per 16 sources, 64 lanes x 4 words; padding sources sit at the
+// origin with zero strength.
+
+// the A-operand words of lane group lg for a source at s (FP32)
+__device__ inline u4 tree_point_record(float sx, float sy, float sz, int lg) {
+  const double s2 = fma((double)sz, (double)sz, fma((double)sy, (double)sy, (double)sx * sx));
+  const float v = lg == 0 ? -2.0f * sx : (lg == 1 ? -2.0f * sy : (lg == 2 ? -2.0f * sz : (float)s2));
+  return split_a(v, lg, true);
+}
+
+// proxy records of every used cluster, [nused][n3b][64]: the Chebyshev points
+// relative to the box centre
+__global__ void k_tree_proxy_records(const double* __restrict__ box, int nused, int n, int n3b, u4* __restrict__ rec) {
+  __shared__ double cs[kTreeMaxOrder + 1], cw[kTreeMaxOrder + 1];
+  cheb_table(n, cs, cw);
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int nq = 16 * n3b;
+  if (i >= (int64_t)nused * nq) return;
+  const int n1 = n + 1, n3 = n1 * n1 * n1;
+  const int c = (int)(i / nq), k = (int)(i - (int64_t)c * nq);
+  float r[3] = {0.0f, 0.0f, 0.0f};
+  if (k < n3) {
+    const int idx[3] = {k / (n1 * n1), (k / n1) % n1, k % n1};
+    for (int d = 0; d < 3; ++d) r[d] = (float)(0.5 * cs[idx[d]] * (box[6 * c + 3 + d] - box[6 * c + d]));
+  }
+  u4* o = rec + (i / 16) * 64 + (k % 16);
+  for (int lg = 0; lg < 4; ++lg) o[16 * lg] = tree_point_record(r[0], r[1], r[2], lg);
+}
+
+// node records of every particle as a direct source, [M][T16][64]: nodes
+// relative to the particle centre
+__global__ void k_tree_node_records(const double* __restrict__ x, const double* __restrict__ y,
+                                    const double* __restrict__ z, const Particle* __restrict__ part, int M, int T,
+                                    int T16, u4* __restrict__ rec) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)M * T16 * 16) return;
+  const int s = (int)(i / (T16 * 16)), q = (int)(i - (int64_t)s * T16 * 16);
+  float r[3] = {0.0f, 0.0f, 0.0f};
+  if (q < T) {
+    const int64_t g = (int64_t)s * T + q;
+    r[0] = (float)(x[g] - part[s].c[0]);
+    r[1] = (float)(y[g] - part[s].c[1]);
+    r[2] = (float)(z[g] - part[s].c[2]);
+  }
+  u4* o = rec + (i / 16) * 64 + (q % 16);
+  for (int lg = 0; lg < 4; ++lg) o[16 * lg] = tree_point_record(r[0], r[1], r[2], lg);
+}
+
+// Per-apply FP32 strengths W sigma of the direct sources for the mixed single
+// layer, [M][T16*16] (zero past T).
+__global__ void k_tree_strengths32(const double* __restrict__ src, int M, int T, int T16, float* __restrict__ q32) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)M * T16 * 16) return;
+  const int s = (int)(i / (T16 * 16)), q = (int)(i - (int64_t)s * T16 * 16);
+  q32[i] = q < T ? (float)src[((int64_t)s * T + q) * 4 + 3] : 0.0f;
+}
+
+// The mixed-precision single layer of a target particle (split over nsplit
+// workgroups like k_tree_eval).  The particle's target nodes are staged in
+// LDS; a wave takes four 16-node column blocks at a time as B operands,
+// rebuilt for each source set from the targets' FP32 offsets from its origin.
+// Per 16-source record and column block one product gives the 256 squared
+// distances; lane l holds sources 4*(l/16) + e (e = 0..3) of column l%16 and
+// adds their four FP32 terms into its FP64 sum, and the four lane groups are
+// added at the end.
+__global__ __launch_bounds__(1024) void k_tree_eval_x3(
+    const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
+    const Particle* __restrict__ part, const double* __restrict__ box, const int64_t* __restrict__ pptr,
+    const int32_t* __restrict__ pidx, const int64_t* __restrict__ dptr, const int32_t* __restrict__ didx,
+    const u4* __restrict__ prec, const float* __restrict__ pq32, const u4* __restrict__ srec,
+    const float* __restrict__ sq32, int T, int T16, int n3b, int nsplit, int64_t N, double* __restrict__ out) {
+  extern __shared__ double tsh[];  // [3][T]
+  const int t = blockIdx.x / nsplit, split = blockIdx.x % nsplit;
+  for (int i = threadIdx.x; i < T; i += blockDim.x) {
+    const int64_t g = (int64_t)t * T + i;
+    tsh[i] = x[g];
+    tsh[T + i] = y[g];
+    tsh[2 * T + i] = z[g];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, lg = lane >> 4, li = lane & 15;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), nw = blockDim.x >> 6;
+  const int64_t p0 = pptr[t], np = pptr[t + 1] - p0, d0 = dptr[t], nd = dptr[t + 1] - d0;
+  const int64_t pa = p0 + np * split / nsplit, pb = p0 + np * (split + 1) / nsplit;
+  const int64_t da = d0 + nd * split / nsplit, db = d0 + nd * (split + 1) / nsplit;
+  for (int cb0 = 4 * wave; cb0 < T16; cb0 += 4 * nw) {
+    const int ncb = min(4, T16 - cb0);  // column blocks of this wave (uniform)
+    u4 B[4];
+    // columns past T repeat the last node and are not written
+    auto columns = [&](double ox, double oy, double oz) {
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        const int i = min(16 * (cb0 + cb) + li, T - 1);
+        const float fx = (float)(tsh[i] - ox), fy = (float)(tsh[T + i] - oy), fz = (float)(tsh[2 * T + i] - oz);
+        const float e = (float)fma((double)fz, (double)fz, fma((double)fy, (double)fy, (double)fx * fx));
+        B[cb] = split_b(lg == 0 ? fx : (lg == 1 ? fy : (lg == 2 ? fz : 1.0f)), lg, e);
+      }
+    };
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    auto blocks = [&](const u4* R, const float* Q, int nblk) {
+#pragma unroll 2
+      for (int bk = 0; bk < nblk; ++bk) {
+        const u4 a = R[64 * bk + lane];
+        const f4 q = reinterpret_cast<const f4*>(Q + 16 * bk)[lg];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+          if (cb < ncb) {
+            const f4 r2 = mma_x3(a, B[cb]);
+            const float v = q.x * __builtin_amdgcn_rsqf(r2.x) + q.y * __builtin_amdgcn_rsqf(r2.y) +
+                            q.z * __builtin_amdgcn_rsqf(r2.z) + q.w * __builtin_amdgcn_rsqf(r2.w);
+            acc[cb] += (double)v;
+          }
+        }
+      }
+    };
+    for (int64_t m = pa; m < pb; ++m) {
+      const int c = pidx[m];
+      columns(0.5 * (box[6 * c] + box[6 * c + 3]), 0.5 * (box[6 * c + 1] + box[6 * c + 4]),
+              0.5 * (box[6 * c + 2] + box[6 * c + 5]));
+      blocks(prec + (size_t)c * n3b * 64, pq32 + (size_t)c * n3b * 16, n3b);
+    }
+    for (int64_t m = da; m < db; ++m) {
+      const int s = didx[m];
+      columns(part[s].c[0], part[s].c[1], part[s].c[2]);
+      blocks(srec + (size_t)s * T16 * 64, sq32 + (size_t)s * T16 * 16, T16);
+    }
+    // the four lane groups of a column, then lane l keeps column block l/16
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      acc[cb] += lane_value(acc[cb], (lane ^ 16) << 2);
+      acc[cb] += lane_value(acc[cb], (lane ^ 32) << 2);
+    }
+    const double v = lg == 0 ? acc[0] : (lg == 1 ? acc[1] : (lg == 2 ? acc[2] : acc[3]));
+    const int i = 16 * cb0 + lane;
+    if (lg < ncb && i < T) out[(size_t)split * N + (int64_t)t * T + i] = v * kInv4PiT;
   }
 }
 
-// FP32 records of the direct sources for the mixed path: node - particle
-// centre and the strength, S (o, W sigma) in 4 floats, D (o, W mu nu, 0, 0) in 8.
-template <int OP>
-__global__ void k_tree_src32(const double* __restrict__ src, const Particle* __restrict__ part, int T, int64_t N,
-                             float* __restrict__ src32) {
-  constexpr int SW = OP == SBIE_OP_S ? 4 : 8;
+// FP32 records of the direct sources for the mixed double layer: node -
+// particle centre and W mu nu, 8 floats per node (the last two as stored).
+__global__ void k_tree_src32_d(const double* __restrict__ src, const Particle* __restrict__ part, int T, int64_t N,
+                               float* __restrict__ src32) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= N) return;
-  const double* r = src + g * SW;
+  const double* r = src + g * 8;
   const double* c = part[g / T].c;
-  float* o = src32 + g * SW;
+  float* o = src32 + g * 8;
   for (int d = 0; d < 3; ++d) o[d] = (float)(r[d] - c[d]);
-  for (int w = 3; w < SW; ++w) o[w] = (float)r[w];
+  for (int w = 3; w < 8; ++w) o[w] = (float)r[w];
 }
 
-// The mixed-precision counterpart of k_tree_eval: FP32 differences from each
-// source set's origin (a cluster's box centre, a source particle's centre),
-// the target's offset from it rounded once per set, FP32 terms four per step
-// added into the FP64 sum.  The double layer's proxy charges cancel strongly
-// within a cluster (they come from dipoles), so its proxy sums stay FP64; its
-// direct sums are FP32 like the single layer's.
-template <int OP, int TPT>
-__global__ __launch_bounds__(1024) void k_tree_eval32(const double* __restrict__ x, const double* __restrict__ y,
-                                                      const double* __restrict__ z, const float* __restrict__ src32,
-                                                      const Particle* __restrict__ part,
-                                                      const float* __restrict__ prox32, const double* __restrict__ prox,
-                                                      const double* __restrict__ box,
-                                                      const int64_t* __restrict__ pptr, const int32_t* __restrict__ pidx,
-                                                      const int64_t* __restrict__ dptr, const int32_t* __restrict__ didx,
-                                                      int T, int n3p, int nsplit, int64_t N, double* __restrict__ out) {
-  constexpr int SW = OP == SBIE_OP_S ? 4 : 8;
+// The mixed-precision double layer (split over nsplit workgroups like
+// k_tree_eval, one target per lane).  Its proxy charges cancel strongly
+// within a cluster (they come from dipoles), so the proxy sums are FP64.  The
+// direct sums take FP32 differences from the source particle's centre, the
+// target's offset from it rounded once per particle, FP32 terms four per
+// step added into the FP64 sum.  (On the matrix cores, d.(t - s) as
+// d.t - d.s cancels and costs the bar its margin.)
+template <int TPT>
+__global__ __launch_bounds__(1024) void k_tree_eval32_d(const double* __restrict__ x, const double* __restrict__ y,
+                                                        const double* __restrict__ z, const float* __restrict__ src32,
+                                                        const Particle* __restrict__ part,
+                                                        const double* __restrict__ prox,
+                                                        const int64_t* __restrict__ pptr,
+                                                        const int32_t* __restrict__ pidx,
+                                                        const int64_t* __restrict__ dptr,
+                                                        const int32_t* __restrict__ didx, int T, int n3p, int nsplit,
+                                                        int64_t N, double* __restrict__ out) {
   const int t = blockIdx.x / nsplit, split = blockIdx.x % nsplit, tid = threadIdx.x;
   const int64_t p0 = pptr[t], np = pptr[t + 1] - p0, d0 = dptr[t], nd = dptr[t + 1] - d0;
   double tx[TPT], ty[TPT], tz[TPT], acc[TPT];
@@ -395,51 +531,24 @@ __global__ __launch_bounds__(1024) void k_tree_eval32(const double* __restrict__
     acc[k] = 0.0;
   }
   for (int64_t m = p0 + np * split / nsplit; m < p0 + np * (split + 1) / nsplit; ++m) {
-    const int c = pidx[m];
-    if (OP == SBIE_OP_D) {
-      const double* P = prox + (int64_t)c * n3p * 4;
-      for (int k = 0; k < n3p; k += 4) {
-#pragma unroll
-        for (int e = 0; e < TPT; ++e) {
-          double a[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const double* r = P + 4 * (k + u);
-            const double dx = tx[e] - r[0], dy = ty[e] - r[1], dz = tz[e] - r[2];
-            a[u] = r[3] * rsqrt_tree(fma(dz, dz, fma(dy, dy, dx * dx)));
-          }
-          acc[e] += (a[0] + a[1]) + (a[2] + a[3]);
-        }
-      }
-      continue;
-    }
-    const float* P = prox32 + (int64_t)c * n3p * 4;
-    const double bx = 0.5 * (box[6 * c] + box[6 * c + 3]), by = 0.5 * (box[6 * c + 1] + box[6 * c + 4]),
-                 bz = 0.5 * (box[6 * c + 2] + box[6 * c + 5]);
-    float rx[TPT], ry[TPT], rz[TPT];
-#pragma unroll
-    for (int e = 0; e < TPT; ++e) {
-      rx[e] = (float)(tx[e] - bx);
-      ry[e] = (float)(ty[e] - by);
-      rz[e] = (float)(tz[e] - bz);
-    }
+    const double* P = prox + (int64_t)pidx[m] * n3p * 4;
     for (int k = 0; k < n3p; k += 4) {
 #pragma unroll
       for (int e = 0; e < TPT; ++e) {
-        float a[4];
+        double a[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const float* r = P + 4 * (k + u);
-          const float dx = rx[e] - r[0], dy = ry[e] - r[1], dz = rz[e] - r[2];
-          a[u] = r[3] * __builtin_amdgcn_rsqf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+          const double* r = P + 4 * (k + u);
+          const double dx = tx[e] - r[0], dy = ty[e] - r[1], dz = tz[e] - r[2];
+          a[u] = r[3] * rsqrt_tree(fma(dz, dz, fma(dy, dy, dx * dx)));
         }
-        acc[e] += (double)((a[0] + a[1]) + (a[2] + a[3]));
+        acc[e] += (a[0] + a[1]) + (a[2] + a[3]);
       }
     }
   }
   for (int64_t m = d0 + nd * split / nsplit; m < d0 + nd * (split + 1) / nsplit; ++m) {
     const int s = didx[m];
-    const float* rs = src32 + (int64_t)s * T * SW;
+    const float* rs = src32 + (int64_t)s * T * 8;
     const double* cc = part[s].c;
     float rx[TPT], ry[TPT], rz[TPT];
 #pragma unroll
@@ -455,31 +564,23 @@ __global__ __launch_bounds__(1024) void k_tree_eval32(const double* __restrict__
         float a[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const float* r = rs + (int64_t)(j + u) * SW;
+          const float* r = rs + (int64_t)(j + u) * 8;
           const float dx = rx[e] - r[0], dy = ry[e] - r[1], dz = rz[e] - r[2];
           const float ri = __builtin_amdgcn_rsqf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
-          if (OP == SBIE_OP_S) {
-            a[u] = r[3] * ri;
-          } else {
-            const float dot = fmaf(r[5], dz, fmaf(r[4], dy, r[3] * dx));
-            a[u] = dot * (ri * ri * ri);
-          }
+          const float dot = fmaf(r[5], dz, fmaf(r[4], dy, r[3] * dx));
+          a[u] = dot * (ri * ri * ri);
         }
         acc[e] += (double)((a[0] + a[1]) + (a[2] + a[3]));
       }
     }
     for (; j < T; ++j) {
-      const float* r = rs + (int64_t)j * SW;
+      const float* r = rs + (int64_t)j * 8;
 #pragma unroll
       for (int e = 0; e < TPT; ++e) {
         const float dx = rx[e] - r[0], dy = ry[e] - r[1], dz = rz[e] - r[2];
         const float ri = __builtin_amdgcn_rsqf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
-        if (OP == SBIE_OP_S) {
-          acc[e] += (double)(r[3] * ri);
-        } else {
-          const float dot = fmaf(r[5], dz, fmaf(r[4], dy, r[3] * dx));
-          acc[e] += (double)(dot * (ri * ri * ri));
-        }
+        const float dot = fmaf(r[5], dz, fmaf(r[4], dy, r[3] * dx));
+        acc[e] += (double)(dot * (ri * ri * ri));
       }
     }
   }
@@ -582,20 +683,31 @@ __global__ __launch_bounds__(1024) void k_tree_eval(const double* __restrict__ x
 inline unsigned cdiv_t(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
 template <int OP, int TPT>
-void launch_eval(sbie_geom* g, hipStream_t s, int threads, bool mixed) {
+void launch_eval(sbie_geom* g, hipStream_t s, int threads) {
   const FarTree& tr = *g->tree;
-  if (mixed) {
-    const int n3 = (tr.order + 1) * (tr.order + 1) * (tr.order + 1);
-    hipLaunchKernelGGL((k_tree_eval32<OP, TPT>), dim3(g->M * g->nsplit), dim3(threads), 0, s, g->d_x, g->d_y,
-                       g->d_z, tr.d_src32, g->d_part, tr.d_q32, tr.d_q, tr.d_box, tr.d_pptr, tr.d_pidx, tr.d_dptr,
-                       tr.d_didx,
-                       g->T, (n3 + 3) & ~3, g->nsplit, g->N, g->d_partial);
-    return;
-  }
   const int n3 = (tr.order + 1) * (tr.order + 1) * (tr.order + 1);
   hipLaunchKernelGGL((k_tree_eval<OP, TPT>), dim3(g->M * g->nsplit), dim3(threads), 0, s, g->d_x, g->d_y, g->d_z,
                      g->d_src, tr.d_q, tr.d_pptr, tr.d_pidx, tr.d_dptr, tr.d_didx, g->T, (n3 + 3) & ~3, g->nsplit,
                      g->N, g->d_partial);
+}
+
+void launch_eval_x3(sbie_geom* g, hipStream_t s) {
+  const FarTree& tr = *g->tree;
+  const int n3 = (tr.order + 1) * (tr.order + 1) * (tr.order + 1);
+  const int T = g->T, T16 = (T + 15) / 16, threads = 64 * std::min(16, (T16 + 3) / 4);
+  hipLaunchKernelGGL(k_tree_eval_x3, dim3(g->M * g->nsplit), dim3(threads), 24 * T, s, g->d_x, g->d_y, g->d_z,
+                     g->d_part, tr.d_box, tr.d_pptr, tr.d_pidx, tr.d_dptr, tr.d_didx,
+                     reinterpret_cast<const u4*>(tr.d_prec), tr.d_q32, reinterpret_cast<const u4*>(tr.d_srec),
+                     tr.d_sq32, T, T16, (n3 + 15) / 16, g->nsplit, g->N, g->d_partial);
+}
+
+template <int TPT>
+void launch_eval32_d(sbie_geom* g, hipStream_t s, int threads) {
+  const FarTree& tr = *g->tree;
+  const int n3 = (tr.order + 1) * (tr.order + 1) * (tr.order + 1);
+  hipLaunchKernelGGL((k_tree_eval32_d<TPT>), dim3(g->M * g->nsplit), dim3(threads), 0, s, g->d_x, g->d_y, g->d_z,
+                     tr.d_src32, g->d_part, tr.d_q, tr.d_pptr, tr.d_pidx, tr.d_dptr, tr.d_didx, g->T, (n3 + 3) & ~3,
+                     g->nsplit, g->N, g->d_partial);
 }
 
 }  // namespace
@@ -670,10 +782,14 @@ sbie_status build_tree(sbie_geom* g, double theta, int order, int leaf) {
   const size_t sz_pidx = al(sizeof(int32_t) * plan.pidx.size()), sz_didx = al(sizeof(int32_t) * plan.didx.size());
   const size_t sz_q = al(sizeof(double) * 4 * (size_t)std::max(nu, 1) * ((n3 + 3) & ~3));
   const size_t sz_qp = al(sizeof(double) * (size_t)std::max(npiece, 1) * n3);
-  const size_t sz_q32 = al(sizeof(float) * 4 * (size_t)std::max(nu, 1) * ((n3 + 3) & ~3));
+  const int n3b = (n3 + 15) / 16, T16 = (T + 15) / 16;
+  const size_t sz_prec = al(sizeof(uint32_t) * 256 * (size_t)std::max(nu, 1) * n3b);
+  const size_t sz_srec = al(sizeof(uint32_t) * 256 * (size_t)M * T16);
+  const size_t sz_q32 = al(sizeof(float) * 16 * (size_t)std::max(nu, 1) * n3b);
+  const size_t sz_sq32 = al(sizeof(float) * 16 * (size_t)M * T16);
   const size_t sz_s32 = al(sizeof(float) * 8 * (size_t)g->N);
-  const size_t total =
-      sz_box + sz_piece + sz_cptr + sz_perm + 2 * sz_ptr + sz_pidx + sz_didx + sz_q + sz_qp + sz_q32 + sz_s32;
+  const size_t total = sz_box + sz_piece + sz_cptr + sz_perm + 2 * sz_ptr + sz_pidx + sz_didx + sz_q + sz_qp +
+                       sz_prec + sz_srec + sz_q32 + sz_sq32 + sz_s32;
   if (hipMalloc(&tr->blk, total) != hipSuccess) {
     (void)hipGetLastError();
     free_tree(g);
@@ -695,7 +811,10 @@ sbie_status build_tree(sbie_geom* g, double theta, int order, int leaf) {
   tr->d_didx = reinterpret_cast<int32_t*>(take(sz_didx));
   tr->d_q = reinterpret_cast<double*>(take(sz_q));
   tr->d_qpart = reinterpret_cast<double*>(take(sz_qp));
+  tr->d_prec = reinterpret_cast<uint32_t*>(take(sz_prec));
+  tr->d_srec = reinterpret_cast<uint32_t*>(take(sz_srec));
   tr->d_q32 = reinterpret_cast<float*>(take(sz_q32));
+  tr->d_sq32 = reinterpret_cast<float*>(take(sz_sq32));
   tr->d_src32 = reinterpret_cast<float*>(take(sz_s32));
   tr->bytes = total;
   SBIE_HIP(hipMemcpy(tr->d_box, box.data(), sizeof(double) * box.size(), hipMemcpyHostToDevice));
@@ -706,6 +825,15 @@ sbie_status build_tree(sbie_geom* g, double theta, int order, int leaf) {
   SBIE_HIP(hipMemcpy(tr->d_dptr, plan.dptr.data(), sizeof(int64_t) * (M + 1), hipMemcpyHostToDevice));
   SBIE_HIP(hipMemcpy(tr->d_pidx, plan.pidx.data(), sizeof(int32_t) * plan.pidx.size(), hipMemcpyHostToDevice));
   SBIE_HIP(hipMemcpy(tr->d_didx, plan.didx.data(), sizeof(int32_t) * plan.didx.size(), hipMemcpyHostToDevice));
+  // the mixed path's geometric records
+  const hipStream_t s = g->ctx->stream;
+  if (nu > 0)
+    hipLaunchKernelGGL(k_tree_proxy_records, dim3(cdiv_t((int64_t)nu * 16 * n3b, 256)), dim3(256), 0, s, tr->d_box,
+                       nu, order, n3b, reinterpret_cast<u4*>(tr->d_prec));
+  hipLaunchKernelGGL(k_tree_node_records, dim3(cdiv_t((int64_t)M * 16 * T16, 256)), dim3(256), 0, s, g->d_x, g->d_y,
+                     g->d_z, g->d_part, M, T, T16, reinterpret_cast<u4*>(tr->d_srec));
+  SBIE_HIP(hipGetLastError());
+  SBIE_HIP(hipStreamSynchronize(s));
   return SBIE_OK;
 }
 
@@ -714,41 +842,50 @@ sbie_status build_tree(sbie_geom* g, double theta, int order, int leaf) {
 // be current.
 sbie_status far_tree(sbie_geom* g, int op, bool mixed, hipStream_t s) {
   const FarTree& tr = *g->tree;
+  const int T = g->T, T16 = (T + 15) / 16;
+  const int n3 = (tr.order + 1) * (tr.order + 1) * (tr.order + 1), n3p = (n3 + 3) & ~3, n3b = (n3 + 15) / 16;
   if (mixed) {
-    const unsigned nb = cdiv_t(g->N, 256);
     if (op == SBIE_OP_S)
-      hipLaunchKernelGGL(k_tree_src32<SBIE_OP_S>, dim3(nb), dim3(256), 0, s, g->d_src, g->d_part, g->T, g->N,
-                         tr.d_src32);
+      hipLaunchKernelGGL(k_tree_strengths32, dim3(cdiv_t((int64_t)g->M * 16 * T16, 256)), dim3(256), 0, s, g->d_src,
+                         g->M, T, T16, tr.d_sq32);
     else
-      hipLaunchKernelGGL(k_tree_src32<SBIE_OP_D>, dim3(nb), dim3(256), 0, s, g->d_src, g->d_part, g->T, g->N,
+      hipLaunchKernelGGL(k_tree_src32_d, dim3(cdiv_t(g->N, 256)), dim3(256), 0, s, g->d_src, g->d_part, T, g->N,
                          tr.d_src32);
     SBIE_HIP(hipGetLastError());
   }
   if (tr.nused > 0) {
     if (op == SBIE_OP_S)
       hipLaunchKernelGGL(k_tree_charges<SBIE_OP_S>, dim3(tr.npiece), dim3(256), 0, s, tr.d_box, tr.d_piece, tr.d_perm,
-                         g->d_src, g->T, tr.order, tr.d_qpart);
+                         g->d_src, T, tr.order, tr.d_qpart);
     else
       hipLaunchKernelGGL(k_tree_charges<SBIE_OP_D>, dim3(tr.npiece), dim3(256), 0, s, tr.d_box, tr.d_piece, tr.d_perm,
-                         g->d_src, g->T, tr.order, tr.d_qpart);
+                         g->d_src, T, tr.order, tr.d_qpart);
     SBIE_HIP(hipGetLastError());
-    const int n3 = (tr.order + 1) * (tr.order + 1) * (tr.order + 1), n3p = (n3 + 3) & ~3;
-    hipLaunchKernelGGL(k_tree_proxies, dim3(cdiv_t((int64_t)tr.nused * n3p, 256)), dim3(256), 0, s, tr.d_box,
-                       tr.d_cptr, tr.d_qpart, tr.nused, tr.order, n3p, tr.d_q, mixed ? tr.d_q32 : nullptr);
+    // the mixed single layer also takes FP32 charges in 16-proxy blocks
+    const bool q32 = mixed && op == SBIE_OP_S;
+    const int nq = q32 ? 16 * n3b : n3p;
+    hipLaunchKernelGGL(k_tree_proxies, dim3(cdiv_t((int64_t)tr.nused * nq, 256)), dim3(256), 0, s, tr.d_box,
+                       tr.d_cptr, tr.d_qpart, tr.nused, tr.order, n3p, nq, tr.d_q, q32 ? tr.d_q32 : nullptr);
     SBIE_HIP(hipGetLastError());
   }
-  // lanes: 64 * ceil(T / (64 TPT)) with the smallest TPT that fits 1024
-  const int T = g->T;
+  // the FP64 sums and the mixed double layer: lanes 64 * ceil(T / (64 TPT))
+  // with the smallest TPT that fits 1024
   const int tpt = T <= 1024 ? 1 : (T <= 2048 ? 2 : 3);
   const int threads = 64 * (int)cdiv_t(cdiv_t(T, tpt), 64);
-  if (op == SBIE_OP_S) {
-    if (tpt == 1) launch_eval<SBIE_OP_S, 1>(g, s, threads, mixed);
-    else if (tpt == 2) launch_eval<SBIE_OP_S, 2>(g, s, threads, mixed);
-    else launch_eval<SBIE_OP_S, 3>(g, s, threads, mixed);
+  if (mixed && op == SBIE_OP_S) {
+    launch_eval_x3(g, s);
+  } else if (mixed) {
+    if (tpt == 1) launch_eval32_d<1>(g, s, threads);
+    else if (tpt == 2) launch_eval32_d<2>(g, s, threads);
+    else launch_eval32_d<3>(g, s, threads);
+  } else if (op == SBIE_OP_S) {
+    if (tpt == 1) launch_eval<SBIE_OP_S, 1>(g, s, threads);
+    else if (tpt == 2) launch_eval<SBIE_OP_S, 2>(g, s, threads);
+    else launch_eval<SBIE_OP_S, 3>(g, s, threads);
   } else {
-    if (tpt == 1) launch_eval<SBIE_OP_D, 1>(g, s, threads, mixed);
-    else if (tpt == 2) launch_eval<SBIE_OP_D, 2>(g, s, threads, mixed);
-    else launch_eval<SBIE_OP_D, 3>(g, s, threads, mixed);
+    if (tpt == 1) launch_eval<SBIE_OP_D, 1>(g, s, threads);
+    else if (tpt == 2) launch_eval<SBIE_OP_D, 2>(g, s, threads);
+    else launch_eval<SBIE_OP_D, 3>(g, s, threads);
   }
   SBIE_HIP(hipGetLastError());
   return SBIE_OK;

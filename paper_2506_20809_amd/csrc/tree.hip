@@ -414,8 +414,10 @@ __global__ void k_tree_strengths32(const double* __restrict__ src, int M, int T,
 // Per 16-source record and column block one product gives the 256 squared
 // distances; lane l holds sources 4*(l/16) + e (e = 0..3) of column l%16 and
 // adds their four FP32 terms into its FP64 sum, and the four lane groups are
-// added at the end.
-__global__ __launch_bounds__(1024) void k_tree_eval_x3(
+// added at the end.  The vector unit bounds it (about two thirds busy, the
+// matrix cores a sixth), so occupancy pays: registers are capped for eight
+// waves per SIMD (a few spilled outside the record loop).
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_tree_eval_x3(
     const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
     const Particle* __restrict__ part, const double* __restrict__ box, const int64_t* __restrict__ pptr,
     const int32_t* __restrict__ pidx, const int64_t* __restrict__ dptr, const int32_t* __restrict__ didx,

@@ -77,14 +77,15 @@ struct FarTree {
   int64_t *d_pptr = nullptr, *d_dptr = nullptr;
   int32_t *d_pidx = nullptr, *d_didx = nullptr;  // pidx holds used-cluster slots
   double* d_q = nullptr;                 // [nused][n3p][4] proxy points and charges of the current apply
-  double* d_qpart = nullptr;             // [npiece][(order+1)^3] their partial sums
+  double* d_qpart = nullptr;             // [npiece][(order+1)^3][1 or 3] their partial sums (3: dipole moments)
   // mixed path: the single layer's three-piece matrix-core records (64 lanes
   // x 4 words per 16 sources; n3b = ceil((order+1)^3 / 16), T16 = ceil(T / 16))
   uint32_t* d_prec = nullptr;            // [nused][n3b][64][4] proxies - box centre
   uint32_t* d_srec = nullptr;            // [M][T16][64][4] nodes - particle centre
+  uint32_t* d_pdrec = nullptr;           // [nused][n3b][64][4] double layer dipole proxies of the current apply
   float* d_q32 = nullptr;                // [nused][16 n3b] single layer proxy charges of the current apply
   float* d_sq32 = nullptr;               // [M][16 T16] single layer node strengths of the current apply
-  float* d_src32 = nullptr;              // [N][8] double layer: node - particle centre, W mu nu
+  float* d_src32 = nullptr;              // [N][8] double layer's direct sources: node - particle centre, W mu nu
 };
 
 }  // namespace sbie

@@ -40,6 +40,7 @@ namespace {
 constexpr double kInv4PiT = 0.079577471545947667884441881686257181;
 constexpr int kTreeMaxOrder = 12;
 constexpr int kChargeParts = 4;  // particles per workgroup of the proxy charges
+constexpr int kTreeDipoles = 2;  // charge kind beside SBIE_OP_S and SBIE_OP_D: the double layer's dipole moments
 
 struct TreeNode {
   int first = 0, count = 0;  // range of the permutation
@@ -232,15 +233,21 @@ __device__ inline void lagrange(int n, const double* cs, const double* cw, doubl
 // kChargeParts of its particles; piece = (cluster slot, first, count) in the
 // permutation), qhat_k over the piece's nodes, 64 nodes at a time through
 // LDS.  Source records: S (x, y, z, W sigma) in 4 doubles, D (x, y, z, W mu nu)
-// in 8.
+// in 8.  Kind kTreeDipoles takes the double layer's dipole moments instead,
+// Dhat_k = sum_j L_k(y_j) d_j (three per proxy): the far field is then
+// sum_k Dhat_k . grad_y G(x, s_k), in which nothing cancels.
 template <int OP>
 __global__ __launch_bounds__(256) void k_tree_charges(const double* __restrict__ box, const int32_t* __restrict__ piece,
                                                      const int32_t* __restrict__ perm, const double* __restrict__ src,
                                                      int T, int n, double* __restrict__ qpart) {
+  constexpr bool DIP = OP == kTreeDipoles;
   constexpr int SW = OP == SBIE_OP_S ? 4 : 8;
   constexpr int NC = 64, NB = kTreeMaxOrder + 1;
-  constexpr int NSET = OP == SBIE_OP_S ? 3 : 6;  // S: q Lx, Ly, Lz; D: Lx, Ly, Lz, d_x dLx, d_y dLy, d_z dLz
+  // S: q Lx, Ly, Lz; D: Lx, Ly, Lz, d_x dLx, d_y dLy, d_z dLz; dipoles: Lx, Ly, Lz
+  constexpr int NSET = OP == SBIE_OP_D ? 6 : 3;
+  constexpr int NA = DIP ? 3 : 1;  // accumulators per proxy
   __shared__ double basis[NSET][NC][NB];
+  __shared__ double dip[DIP ? NC : 1][3];
   __shared__ double cs[NB], cw[NB];
   const int pc = blockIdx.x, tid = threadIdx.x;
   const int c = piece[3 * pc], pfirst = piece[3 * pc + 1], pcount = piece[3 * pc + 2];
@@ -253,9 +260,11 @@ __global__ __launch_bounds__(256) void k_tree_charges(const double* __restrict__
     sc[d] = 2.0 / (box[6 * c + 3 + d] - lo[d]);  // d u / d y
   }
   constexpr int KPT = (NB * NB * NB + 255) / 256;
-  double acc[KPT];
+  double acc[KPT][NA];
 #pragma unroll
-  for (int m = 0; m < KPT; ++m) acc[m] = 0.0;
+  for (int m = 0; m < KPT; ++m)
+#pragma unroll
+    for (int w = 0; w < NA; ++w) acc[m][w] = 0.0;
   const int64_t nodes = (int64_t)pcount * T;
   for (int64_t j0 = 0; j0 < nodes; j0 += NC) {
     if (tid < NC) {
@@ -270,13 +279,17 @@ __global__ __launch_bounds__(256) void k_tree_charges(const double* __restrict__
         // (times d u / d y) into each derivative
         if (OP == SBIE_OP_S) {
           for (int k = 0; k < n1; ++k) basis[0][tid][k] *= r[3];
-        } else {
+        } else if (OP == SBIE_OP_D) {
           for (int d = 0; d < 3; ++d)
-            for (int k = 0; k < n1; ++k) basis[OP == SBIE_OP_D ? 3 + d : d][tid][k] *= r[3 + d] * sc[d];
+            for (int k = 0; k < n1; ++k) basis[3 + d][tid][k] *= r[3 + d] * sc[d];
+        } else {
+          for (int d = 0; d < 3; ++d) dip[tid][d] = r[3 + d];
         }
       } else {
         for (int w = 0; w < NSET; ++w)
           for (int k = 0; k < n1; ++k) basis[w][tid][k] = 0.0;
+        if (DIP)
+          for (int d = 0; d < 3; ++d) dip[tid][d] = 0.0;
       }
     }
     __syncthreads();
@@ -286,18 +299,25 @@ __global__ __launch_bounds__(256) void k_tree_charges(const double* __restrict__
       const int k = tid + 256 * m;
       if (k < n3) {
         const int k1 = k / (n1 * n1), k2 = (k / n1) % n1, k3 = k % n1;
-        double a = acc[m];
+        double a[NA];
+#pragma unroll
+        for (int w = 0; w < NA; ++w) a[w] = acc[m][w];
         for (int j = 0; j < jn; ++j) {
           if (OP == SBIE_OP_S) {
-            a = fma(basis[0][j][k1] * basis[1][j][k2], basis[2][j][k3], a);
-          } else {
+            a[0] = fma(basis[0][j][k1] * basis[1][j][k2], basis[2][j][k3], a[0]);
+          } else if (OP == SBIE_OP_D) {
             const double lx = basis[0][j][k1], ly = basis[1][j][k2], lz = basis[2][j][k3];
-            a = fma(basis[3][j][k1] * ly, lz, a);
-            a = fma(lx * basis[4][j][k2], lz, a);
-            a = fma(lx * ly, basis[5][j][k3], a);
+            a[0] = fma(basis[3][j][k1] * ly, lz, a[0]);
+            a[0] = fma(lx * basis[4][j][k2], lz, a[0]);
+            a[0] = fma(lx * ly, basis[5][j][k3], a[0]);
+          } else {
+            const double l = basis[0][j][k1] * basis[1][j][k2] * basis[2][j][k3];
+#pragma unroll
+            for (int w = 0; w < NA; ++w) a[w] = fma(l, dip[j][w], a[w]);
           }
         }
-        acc[m] = a;
+#pragma unroll
+        for (int w = 0; w < NA; ++w) acc[m][w] = a[w];
       }
     }
     __syncthreads();
@@ -305,7 +325,9 @@ __global__ __launch_bounds__(256) void k_tree_charges(const double* __restrict__
 #pragma unroll
   for (int m = 0; m < KPT; ++m) {
     const int k = tid + 256 * m;
-    if (k < n3) qpart[(int64_t)pc * n3 + k] = acc[m];
+    if (k < n3)
+#pragma unroll
+      for (int w = 0; w < NA; ++w) qpart[((int64_t)pc * n3 + k) * NA + w] = acc[m][w];
   }
 }
 
@@ -379,6 +401,35 @@ __global__ void k_tree_proxy_records(const double* __restrict__ box, int nused, 
   for (int lg = 0; lg < 4; ++lg) o[16 * lg] = tree_point_record(r[0], r[1], r[2], lg);
 }
 
+// Per-apply dipole records of every used cluster for the mixed double layer,
+// [nused][n3b][64]: [Dhat, -Dhat.s] with s as in the proxy records (no extra
+// term), whose product with the target column [t - b, 1] is Dhat.(t - b - s);
+// the pieces' moments added in piece order; zero past n3.
+__global__ void k_tree_dipole_records(const double* __restrict__ box, const int32_t* __restrict__ pptr,
+                                      const double* __restrict__ qpart, int nused, int n, int n3b,
+                                      u4* __restrict__ rec) {
+  __shared__ double cs[kTreeMaxOrder + 1], cw[kTreeMaxOrder + 1];
+  cheb_table(n, cs, cw);
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int nq = 16 * n3b;
+  if (i >= (int64_t)nused * nq) return;
+  const int n1 = n + 1, n3 = n1 * n1 * n1;
+  const int c = (int)(i / nq), k = (int)(i - (int64_t)c * nq);
+  double d[3] = {0.0, 0.0, 0.0}, dot = 0.0;
+  if (k < n3) {
+    const int idx[3] = {k / (n1 * n1), (k / n1) % n1, k % n1};
+    for (int p = pptr[c]; p < pptr[c + 1]; ++p)
+      for (int w = 0; w < 3; ++w) d[w] += qpart[((int64_t)p * n3 + k) * 3 + w];
+    for (int w = 0; w < 3; ++w) {
+      const float sw = (float)(0.5 * cs[idx[w]] * (box[6 * c + 3 + w] - box[6 * c + w]));
+      dot = fma(d[w], (double)sw, dot);
+    }
+  }
+  u4* o = rec + (i / 16) * 64 + (k % 16);
+  for (int lg = 0; lg < 4; ++lg) o[16 * lg] = split_a((float)(lg < 3 ? d[lg] : -dot), lg, false);
+}
+
 // node records of every particle as a direct source, [M][T16][64]: nodes
 // relative to the particle centre
 __global__ void k_tree_node_records(const double* __restrict__ x, const double* __restrict__ y,
@@ -417,12 +468,20 @@ __global__ void k_tree_strengths32(const double* __restrict__ src, int M, int T,
 // added at the end.  The vector unit bounds it (about two thirds busy, the
 // matrix cores a sixth), so occupancy pays: registers are capped for eight
 // waves per SIMD (a few spilled outside the record loop).
+//
+// DIP: the double layer's proxies alone, through their dipole records: a
+// second product of [Dhat, -Dhat.s] with the same columns gives
+// Dhat.(t - s) for the weight r^-3 (the target's offset from the box centre
+// is at most (1 + theta) / (1 - theta) times its distance from a proxy, so
+// the difference loses little); the direct sums are k_tree_eval32_d's.
+template <bool DIP>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_tree_eval_x3(
     const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
     const Particle* __restrict__ part, const double* __restrict__ box, const int64_t* __restrict__ pptr,
     const int32_t* __restrict__ pidx, const int64_t* __restrict__ dptr, const int32_t* __restrict__ didx,
-    const u4* __restrict__ prec, const float* __restrict__ pq32, const u4* __restrict__ srec,
-    const float* __restrict__ sq32, int T, int T16, int n3b, int nsplit, int64_t N, double* __restrict__ out) {
+    const u4* __restrict__ prec, const float* __restrict__ pq32, const u4* __restrict__ pdrec,
+    const u4* __restrict__ srec, const float* __restrict__ sq32, int T, int T16, int n3b, int nsplit, int64_t N,
+    double* __restrict__ out) {
   extern __shared__ double tsh[];  // [3][T]
   const int t = blockIdx.x / nsplit, split = blockIdx.x % nsplit;
   for (int i = threadIdx.x; i < T; i += blockDim.x) {
@@ -467,13 +526,35 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
         }
       }
     };
+    auto dipoles = [&](const u4* R, const u4* R2, int nblk) {
+      for (int bk = 0; bk < nblk; ++bk) {
+        const u4 a = R[64 * bk + lane], a2 = R2[64 * bk + lane];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+          if (cb < ncb) {
+            const f4 r2 = mma_x3(a, B[cb]);
+            const f4 dt = mma_x3(a2, B[cb]);
+            float v = 0.0f;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const float ri = __builtin_amdgcn_rsqf(r2[e]);
+              v = fmaf(dt[e], ri * ri * ri, v);
+            }
+            acc[cb] += (double)v;
+          }
+        }
+      }
+    };
     for (int64_t m = pa; m < pb; ++m) {
       const int c = pidx[m];
       columns(0.5 * (box[6 * c] + box[6 * c + 3]), 0.5 * (box[6 * c + 1] + box[6 * c + 4]),
               0.5 * (box[6 * c + 2] + box[6 * c + 5]));
-      blocks(prec + (size_t)c * n3b * 64, pq32 + (size_t)c * n3b * 16, n3b);
+      if constexpr (DIP)
+        dipoles(prec + (size_t)c * n3b * 64, pdrec + (size_t)c * n3b * 64, n3b);
+      else
+        blocks(prec + (size_t)c * n3b * 64, pq32 + (size_t)c * n3b * 16, n3b);
     }
-    for (int64_t m = da; m < db; ++m) {
+    for (int64_t m = DIP ? db : da; m < db; ++m) {
       const int s = didx[m];
       columns(part[s].c[0], part[s].c[1], part[s].c[2]);
       blocks(srec + (size_t)s * T16 * 64, sq32 + (size_t)s * T16 * 16, T16);
@@ -510,7 +591,10 @@ __global__ void k_tree_src32_d(const double* __restrict__ src, const Particle* _
 // target's offset from it rounded once per particle, FP32 terms four per
 // step added into the FP64 sum.  (On the matrix cores, d.(t - s) as
 // d.t - d.s cancels and costs the bar its margin.)
-template <int TPT>
+//
+// ADD: the direct sums alone, added into the slices (after the dipole
+// proxies of k_tree_eval_x3).
+template <int TPT, bool ADD>
 __global__ __launch_bounds__(1024) void k_tree_eval32_d(const double* __restrict__ x, const double* __restrict__ y,
                                                         const double* __restrict__ z, const float* __restrict__ src32,
                                                         const Particle* __restrict__ part,
@@ -532,7 +616,7 @@ __global__ __launch_bounds__(1024) void k_tree_eval32_d(const double* __restrict
     tz[k] = z[g];
     acc[k] = 0.0;
   }
-  for (int64_t m = p0 + np * split / nsplit; m < p0 + np * (split + 1) / nsplit; ++m) {
+  for (int64_t m = p0 + np * split / nsplit; !ADD && m < p0 + np * (split + 1) / nsplit; ++m) {
     const double* P = prox + (int64_t)pidx[m] * n3p * 4;
     for (int k = 0; k < n3p; k += 4) {
 #pragma unroll
@@ -589,7 +673,10 @@ __global__ __launch_bounds__(1024) void k_tree_eval32_d(const double* __restrict
 #pragma unroll
   for (int k = 0; k < TPT; ++k) {
     const int i = tid + k * blockDim.x;
-    if (i < T) out[(size_t)split * N + (int64_t)t * T + i] = acc[k] * kInv4PiT;
+    if (i < T) {
+      double* o = out + (size_t)split * N + (int64_t)t * T + i;
+      *o = ADD ? *o + acc[k] * kInv4PiT : acc[k] * kInv4PiT;
+    }
   }
 }
 
@@ -693,23 +780,25 @@ void launch_eval(sbie_geom* g, hipStream_t s, int threads) {
                      g->N, g->d_partial);
 }
 
+template <bool DIP>
 void launch_eval_x3(sbie_geom* g, hipStream_t s) {
   const FarTree& tr = *g->tree;
   const int n3 = (tr.order + 1) * (tr.order + 1) * (tr.order + 1);
   const int T = g->T, T16 = (T + 15) / 16, threads = 64 * std::min(16, (T16 + 3) / 4);
-  hipLaunchKernelGGL(k_tree_eval_x3, dim3(g->M * g->nsplit), dim3(threads), 24 * T, s, g->d_x, g->d_y, g->d_z,
-                     g->d_part, tr.d_box, tr.d_pptr, tr.d_pidx, tr.d_dptr, tr.d_didx,
-                     reinterpret_cast<const u4*>(tr.d_prec), tr.d_q32, reinterpret_cast<const u4*>(tr.d_srec),
-                     tr.d_sq32, T, T16, (n3 + 15) / 16, g->nsplit, g->N, g->d_partial);
+  hipLaunchKernelGGL((k_tree_eval_x3<DIP>), dim3(g->M * g->nsplit), dim3(threads), 24 * T, s, g->d_x, g->d_y,
+                     g->d_z, g->d_part, tr.d_box, tr.d_pptr, tr.d_pidx, tr.d_dptr, tr.d_didx,
+                     reinterpret_cast<const u4*>(tr.d_prec), tr.d_q32, reinterpret_cast<const u4*>(tr.d_pdrec),
+                     reinterpret_cast<const u4*>(tr.d_srec), tr.d_sq32, T, T16, (n3 + 15) / 16, g->nsplit, g->N,
+                     g->d_partial);
 }
 
-template <int TPT>
+template <int TPT, bool ADD>
 void launch_eval32_d(sbie_geom* g, hipStream_t s, int threads) {
   const FarTree& tr = *g->tree;
   const int n3 = (tr.order + 1) * (tr.order + 1) * (tr.order + 1);
-  hipLaunchKernelGGL((k_tree_eval32_d<TPT>), dim3(g->M * g->nsplit), dim3(threads), 0, s, g->d_x, g->d_y, g->d_z,
-                     tr.d_src32, g->d_part, tr.d_q, tr.d_pptr, tr.d_pidx, tr.d_dptr, tr.d_didx, g->T, (n3 + 3) & ~3,
-                     g->nsplit, g->N, g->d_partial);
+  hipLaunchKernelGGL((k_tree_eval32_d<TPT, ADD>), dim3(g->M * g->nsplit), dim3(threads), 0, s, g->d_x, g->d_y,
+                     g->d_z, tr.d_src32, g->d_part, tr.d_q, tr.d_pptr, tr.d_pidx, tr.d_dptr, tr.d_didx, g->T,
+                     (n3 + 3) & ~3, g->nsplit, g->N, g->d_partial);
 }
 
 }  // namespace
@@ -783,7 +872,7 @@ sbie_status build_tree(sbie_geom* g, double theta, int order, int leaf) {
   const size_t sz_perm = al(sizeof(int32_t) * M), sz_ptr = al(sizeof(int64_t) * (M + 1));
   const size_t sz_pidx = al(sizeof(int32_t) * plan.pidx.size()), sz_didx = al(sizeof(int32_t) * plan.didx.size());
   const size_t sz_q = al(sizeof(double) * 4 * (size_t)std::max(nu, 1) * ((n3 + 3) & ~3));
-  const size_t sz_qp = al(sizeof(double) * (size_t)std::max(npiece, 1) * n3);
+  const size_t sz_qp = al(sizeof(double) * 3 * (size_t)std::max(npiece, 1) * n3);  // 3: dipole moments
   const int n3b = (n3 + 15) / 16, T16 = (T + 15) / 16;
   const size_t sz_prec = al(sizeof(uint32_t) * 256 * (size_t)std::max(nu, 1) * n3b);
   const size_t sz_srec = al(sizeof(uint32_t) * 256 * (size_t)M * T16);
@@ -791,7 +880,7 @@ sbie_status build_tree(sbie_geom* g, double theta, int order, int leaf) {
   const size_t sz_sq32 = al(sizeof(float) * 16 * (size_t)M * T16);
   const size_t sz_s32 = al(sizeof(float) * 8 * (size_t)g->N);
   const size_t total = sz_box + sz_piece + sz_cptr + sz_perm + 2 * sz_ptr + sz_pidx + sz_didx + sz_q + sz_qp +
-                       sz_prec + sz_srec + sz_q32 + sz_sq32 + sz_s32;
+                       2 * sz_prec + sz_srec + sz_q32 + sz_sq32 + sz_s32;
   if (hipMalloc(&tr->blk, total) != hipSuccess) {
     (void)hipGetLastError();
     free_tree(g);
@@ -814,6 +903,7 @@ sbie_status build_tree(sbie_geom* g, double theta, int order, int leaf) {
   tr->d_q = reinterpret_cast<double*>(take(sz_q));
   tr->d_qpart = reinterpret_cast<double*>(take(sz_qp));
   tr->d_prec = reinterpret_cast<uint32_t*>(take(sz_prec));
+  tr->d_pdrec = reinterpret_cast<uint32_t*>(take(sz_prec));
   tr->d_srec = reinterpret_cast<uint32_t*>(take(sz_srec));
   tr->d_q32 = reinterpret_cast<float*>(take(sz_q32));
   tr->d_sq32 = reinterpret_cast<float*>(take(sz_sq32));
@@ -855,31 +945,43 @@ sbie_status far_tree(sbie_geom* g, int op, bool mixed, hipStream_t s) {
                          tr.d_src32);
     SBIE_HIP(hipGetLastError());
   }
+  // the mixed double layer's proxies carry dipole moments
+  const bool dip = mixed && op == SBIE_OP_D;
   if (tr.nused > 0) {
     if (op == SBIE_OP_S)
       hipLaunchKernelGGL(k_tree_charges<SBIE_OP_S>, dim3(tr.npiece), dim3(256), 0, s, tr.d_box, tr.d_piece, tr.d_perm,
                          g->d_src, T, tr.order, tr.d_qpart);
+    else if (dip)
+      hipLaunchKernelGGL(k_tree_charges<kTreeDipoles>, dim3(tr.npiece), dim3(256), 0, s, tr.d_box, tr.d_piece,
+                         tr.d_perm, g->d_src, T, tr.order, tr.d_qpart);
     else
       hipLaunchKernelGGL(k_tree_charges<SBIE_OP_D>, dim3(tr.npiece), dim3(256), 0, s, tr.d_box, tr.d_piece, tr.d_perm,
                          g->d_src, T, tr.order, tr.d_qpart);
     SBIE_HIP(hipGetLastError());
-    // the mixed single layer also takes FP32 charges in 16-proxy blocks
-    const bool q32 = mixed && op == SBIE_OP_S;
-    const int nq = q32 ? 16 * n3b : n3p;
-    hipLaunchKernelGGL(k_tree_proxies, dim3(cdiv_t((int64_t)tr.nused * nq, 256)), dim3(256), 0, s, tr.d_box,
-                       tr.d_cptr, tr.d_qpart, tr.nused, tr.order, n3p, nq, tr.d_q, q32 ? tr.d_q32 : nullptr);
+    if (dip) {
+      hipLaunchKernelGGL(k_tree_dipole_records, dim3(cdiv_t((int64_t)tr.nused * 16 * n3b, 256)), dim3(256), 0, s,
+                         tr.d_box, tr.d_cptr, tr.d_qpart, tr.nused, tr.order, n3b, reinterpret_cast<u4*>(tr.d_pdrec));
+    } else {
+      // the mixed single layer also takes FP32 charges in 16-proxy blocks
+      const bool q32 = mixed && op == SBIE_OP_S;
+      const int nq = q32 ? 16 * n3b : n3p;
+      hipLaunchKernelGGL(k_tree_proxies, dim3(cdiv_t((int64_t)tr.nused * nq, 256)), dim3(256), 0, s, tr.d_box,
+                         tr.d_cptr, tr.d_qpart, tr.nused, tr.order, n3p, nq, tr.d_q, q32 ? tr.d_q32 : nullptr);
+    }
     SBIE_HIP(hipGetLastError());
   }
-  // the FP64 sums and the mixed double layer: lanes 64 * ceil(T / (64 TPT))
-  // with the smallest TPT that fits 1024
+  // the FP64 sums and the mixed double layer's direct sums: lanes
+  // 64 * ceil(T / (64 TPT)) with the smallest TPT that fits 1024
   const int tpt = T <= 1024 ? 1 : (T <= 2048 ? 2 : 3);
   const int threads = 64 * (int)cdiv_t(cdiv_t(T, tpt), 64);
   if (mixed && op == SBIE_OP_S) {
-    launch_eval_x3(g, s);
+    launch_eval_x3<false>(g, s);
   } else if (mixed) {
-    if (tpt == 1) launch_eval32_d<1>(g, s, threads);
-    else if (tpt == 2) launch_eval32_d<2>(g, s, threads);
-    else launch_eval32_d<3>(g, s, threads);
+    launch_eval_x3<true>(g, s);
+    SBIE_HIP(hipGetLastError());
+    if (tpt == 1) launch_eval32_d<1, true>(g, s, threads);
+    else if (tpt == 2) launch_eval32_d<2, true>(g, s, threads);
+    else launch_eval32_d<3, true>(g, s, threads);
   } else if (op == SBIE_OP_S) {
     if (tpt == 1) launch_eval<SBIE_OP_S, 1>(g, s, threads);
     else if (tpt == 2) launch_eval<SBIE_OP_S, 2>(g, s, threads);

@@ -358,14 +358,14 @@ const char* sbie_last_error(void);
    particles are summed directly unless excluded.  Each far (target, source)
    particle pair is covered exactly once.  The sums follow the apply's
    precision: FP64, or in SBIE_MIXED FP32 terms added four at a time into
-   FP64 sums (the single layer's squared distances on the matrix cores; the
-   double layer's proxy sums stay FP64, its proxy charges cancelling within a
-   cluster).  The interpolation error falls geometrically in `order` at a rate
+   FP64 sums (squared distances on the matrix cores; the double layer's
+   proxies then carry its dipole moments, interpolated, since its proxy
+   charges cancel within a cluster).  The interpolation error falls geometrically in `order` at a rate
    set by theta.  Measured against the direct FP64 far sum at 512 and 4096
    spheroids (p = 16), relative l2, FP64 sums: theta = 0.5, order = 8: S 2e-8
    to 5e-8, D 3e-7 to 4e-7; theta = 0.6, order = 10: S 7e-9 to 2e-8, D 9e-8 to
    2e-7 at about the same cost; mixed sums at theta = 0.6, order = 10: S 1.2e-7
-   to 1.8e-7, D 1.4e-7 to 2.2e-7.
+   to 1.8e-7, D 2.4e-7 to 4.8e-7.
    ------------------------------------------------------------------------ */
 
 /* Build (or rebuild) the tree of a geometry; applies with SBIE_FAR_TREE use

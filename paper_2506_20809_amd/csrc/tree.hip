@@ -20,9 +20,12 @@
 // for the single layer (q = W sigma) and the double layer (d = W mu nu).  The
 // error falls geometrically in n at a rate set by theta.
 //
-// The plan is host code (no device needed); proxy charges and the evaluation
-// are FP64 kernels: one workgroup per cluster for the charges, one per target
-// particle for the sums.
+// The plan is host code (no device needed).  The proxy charges are FP64
+// kernels, one workgroup per piece of a cluster; the sums take a target
+// particle per group of workgroups, in FP64, or in mixed precision with the
+// squared distances on the matrix cores (the double layer's proxies then
+// carry its dipole moments, Dhat_k = sum_j L_k(y_j) d_j, evaluated against
+// grad_y G(x, s_k), in which nothing cancels).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -470,7 +470,8 @@ __global__ void k_tree_strengths32(const double* __restrict__ src, int M, int T,
 // adds their four FP32 terms into its FP64 sum, and the four lane groups are
 // added at the end.  The vector unit bounds it (about two thirds busy, the
 // matrix cores a sixth), so occupancy pays: registers are capped for eight
-// waves per SIMD (a few spilled outside the record loop).
+// waves per SIMD (a few spilled outside the record loop), seven for the
+// dipole proxies' two products.
 //
 // DIP: the double layer's proxies alone, through their dipole records: a
 // second product of [Dhat, -Dhat.s] with the same columns gives
@@ -478,7 +479,7 @@ __global__ void k_tree_strengths32(const double* __restrict__ src, int M, int T,
 // is at most (1 + theta) / (1 - theta) times its distance from a proxy, so
 // the difference loses little); the direct sums are k_tree_eval32_d's.
 template <bool DIP>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_tree_eval_x3(
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(DIP ? 7 : 8, 8))) void k_tree_eval_x3(
     const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
     const Particle* __restrict__ part, const double* __restrict__ box, const int64_t* __restrict__ pptr,
     const int32_t* __restrict__ pidx, const int64_t* __restrict__ dptr, const int32_t* __restrict__ didx,

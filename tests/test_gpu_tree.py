@@ -122,25 +122,27 @@ def test_errors(ctx):
     g.close()
 
 
+@pytest.mark.parametrize("p", [24, 32])
 @pytest.mark.parametrize("op", [0, 1])
-def test_more_than_1024_nodes_per_particle(ctx, op):
-    """p = 24 (T = 1250 nodes per particle): the mixed single layer's waves
-    take several column blocks in turn and the FP64 and mixed double-layer
-    kernels two targets per lane.  The mixed tree against the FP64 tree at
+def test_more_than_1024_nodes_per_particle(ctx, op, p):
+    """p = 24 and 32 (T = 1250 and 2178 nodes per particle): the mixed single
+    layer's waves take several column blocks in turn (the particle's nodes
+    in 30 and 52 KB of LDS) and the FP64 and mixed double-layer kernels two
+    and three targets per lane.  The mixed tree against the FP64 tree at
     every node (mixed bar), and both against the oracle at sampled nodes."""
     import paper_2506_20809_amd as sbie
 
-    geom, p = workloads.rsa_pack(16, 0.2, 0.05, 83), 24
+    geom = workloads.rsa_pack(16, 0.2, 0.05, 83)
     g = sbie.Geometry(ctx, geom, p)
     assert g.N == 16 * 2 * (p + 1) ** 2
     info = g.far_tree(0.5, 8, 1)
     assert info["proxy_pairs"] > 0 and info["direct_pairs"] > 0
-    dens = np.random.default_rng(90 + op).standard_normal(g.N)
+    dens = np.random.default_rng(90 + op + p).standard_normal(g.N)
     f64 = g.apply(op, dens, parts=sbie.SBIE_PARTS_FAR, tree=True)
     f32 = g.apply(op, dens, parts=sbie.SBIE_PARTS_FAR, tree=True, precision=sbie.SBIE_MIXED)
     l2, mx = _rel(f32, f64)
     assert l2 < 1e-6 and mx < 1e-5, (l2, mx)
-    sel = np.sort(np.random.default_rng(95 + op).choice(g.N, 12, replace=False))
+    sel = np.sort(np.random.default_rng(95 + op + p).choice(g.N, 12, replace=False))
     uf = oracle.apply_at(geom, p, op, dens, sel)[3]
     for far in (f64, f32):
         l2, mx = _rel(far[sel], uf)

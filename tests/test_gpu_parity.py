@@ -155,7 +155,7 @@ def _mini(M, seed, p_types=None, gap=0.05, phi=0.1):
     return g
 
 
-@pytest.mark.parametrize("p", [1, 2, 3, 5, 9, 12, 17, 24])
+@pytest.mark.parametrize("p", [1, 2, 3, 5, 9, 12, 17, 24, 32])
 def test_small_suspensions_many_orders(ctx, p):
     """Ragged sizes (N not a multiple of any tile), orders across the register
     buckets, prolate and oblate mixes."""
@@ -287,7 +287,7 @@ def test_mixed_parity(ctx, name, p, op):
     g.close()
 
 
-@pytest.mark.parametrize("p", [2, 3, 4, 6, 12, 20])
+@pytest.mark.parametrize("p", [2, 3, 4, 6, 12, 20, 32])
 def test_mixed_small_suspensions(ctx, p):
     import paper_2506_20809_amd as sbie
 

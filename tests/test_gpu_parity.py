@@ -174,6 +174,27 @@ def test_small_suspensions_many_orders(ctx, p):
     g.close()
 
 
+def test_nearly_spherical(ctx):
+    """The limit just inside the domain: aspect ratios 1 +- 1e-2 and 1 +- 1e-4
+    (focal lengths 0.14 and 0.014 of the radius, u0 up to 71), prolate and
+    oblate, as near neighbours and one far; FP64 and mixed, every part."""
+    import paper_2506_20809_amd as sbie
+
+    rng = np.random.default_rng(7)
+    q = rng.standard_normal((5, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    geom = {"centers": np.array([[0, 0, 0], [2.25, 0, 0], [0, 2.25, 0], [2.25, 2.25, 0.3], [8.0, 1.0, 0.5]], float),
+            "quats": q, "A": np.ones(5), "C": np.array([1.01, 0.99, 1.0001, 0.9999, 1.001])}
+    p = 12
+    g = sbie.Geometry(ctx, geom, p)
+    dens = rng.standard_normal(g.N)
+    for op in (0, 1):
+        _check_parts(g, geom, p, op, dens, label=f"near-sphere op={op}")
+        _check_parts(g, geom, p, op, dens, tol=TOL_MIXED, max_tol=1e-5, label=f"near-sphere mixed op={op}",
+                     precision=sbie.SBIE_MIXED)
+    g.close()
+
+
 def test_single_particle_self_only(ctx):
     import paper_2506_20809_amd as sbie
 

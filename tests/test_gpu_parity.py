@@ -195,6 +195,26 @@ def test_nearly_spherical(ctx):
     g.close()
 
 
+def test_high_aspect_ratios(ctx):
+    """Needles and disks: prolate 1:10 and 1:5, oblate 10:1 and 5:1 (u0 down
+    to 1.005, where the frame map and Q_n^m approach xi -> 1), stacked as
+    near neighbours, and a far 1:8 needle; FP64 and mixed, every part."""
+    import paper_2506_20809_amd as sbie
+
+    rng = np.random.default_rng(11)
+    geom = {"centers": np.array([[0, 0, 0], [0.45, 0, 0], [0, 0, 1.35], [0.6, 0.2, 1.8], [6.0, 0.5, 0.5]], float),
+            "quats": np.array([[1.0, 0, 0, 0]] * 4 + [[0.8, 0.6, 0, 0]]),
+            "A": np.array([0.1, 0.2, 1.0, 1.0, 0.125]), "C": np.array([1.0, 1.0, 0.1, 0.2, 1.0])}
+    p = 16
+    g = sbie.Geometry(ctx, geom, p)
+    dens = rng.standard_normal(g.N)
+    for op in (0, 1):
+        _check_parts(g, geom, p, op, dens, label=f"aspect op={op}")
+        _check_parts(g, geom, p, op, dens, tol=TOL_MIXED, max_tol=1e-5, label=f"aspect mixed op={op}",
+                     precision=sbie.SBIE_MIXED)
+    g.close()
+
+
 def test_single_particle_self_only(ctx):
     import paper_2506_20809_amd as sbie
 

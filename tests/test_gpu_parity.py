@@ -215,6 +215,25 @@ def test_high_aspect_ratios(ctx):
     g.close()
 
 
+@pytest.mark.parametrize("gap", [1e-3, 1e-4])
+def test_nearly_touching(ctx, gap):
+    """Side by side and tip to tip at gaps of 1e-3 and 1e-4: near-field targets
+    all but on the neighbour's surface (u -> u0, the continued fraction at its
+    slowest); FP64 and mixed, every part."""
+    import paper_2506_20809_amd as sbie
+
+    geom = {"centers": np.array([[0, 0, 0], [1.0 + gap, 0, 0], [0.3, 0, 2.2 + gap]], float),
+            "quats": np.array([[1.0, 0, 0, 0]] * 3), "A": np.array([0.5, 0.5, 0.6]), "C": np.array([1.0, 1.0, 1.2])}
+    p = 12
+    g = sbie.Geometry(ctx, geom, p)
+    dens = np.random.default_rng(3).standard_normal(g.N)
+    for op in (0, 1):
+        _check_parts(g, geom, p, op, dens, label=f"gap {gap} op={op}")
+        _check_parts(g, geom, p, op, dens, tol=TOL_MIXED, max_tol=1e-5, label=f"gap {gap} mixed op={op}",
+                     precision=sbie.SBIE_MIXED)
+    g.close()
+
+
 def test_single_particle_self_only(ctx):
     import paper_2506_20809_amd as sbie
 

@@ -468,8 +468,8 @@ __global__ void k_tree_strengths32(const double* __restrict__ src, int M, int T,
 // Per 16-source record and column block one product gives the 256 squared
 // distances; lane l holds sources 4*(l/16) + e (e = 0..3) of column l%16 and
 // adds their four FP32 terms into its FP64 sum, and the four lane groups are
-// added at the end.  The vector unit bounds it (about two thirds busy, the
-// matrix cores a sixth), so occupancy pays: registers are capped for eight
+// added at the end.  The vector unit bounds it (about 12 vector instructions
+// per product, the matrix cores a sixth busy), so occupancy pays: registers are capped for eight
 // waves per SIMD (a few spilled outside the record loop), seven for the
 // dipole proxies' two products.
 //

@@ -106,7 +106,11 @@ struct sbie_server {
   bool graphs = false;
   sbie::Arena arena;
   std::mutex mu;
-  std::mutex capture_mu;
+  // Every HIP graph call of the lanes (capture, instantiation, launch,
+  // destruction) is made under this lock: HIP does not promise that graph
+  // calls from several threads at once are safe, so the lanes never overlap
+  // them.  Launches only enqueue, so the lock is held for microseconds.
+  std::mutex graph_mu;
   std::condition_variable cv_done;
   std::vector<std::unique_ptr<std::condition_variable>> lane_cv;
   std::deque<sbie_session*> pending;
@@ -187,9 +191,7 @@ void build_session(sbie_server* srv, sbie_session* s, int lane) {
     s->d_out = reinterpret_cast<double*>(blk + s->plan + io);
   }
   if (rc == SBIE_OK && srv->graphs) {
-    // one capture at a time in the process: the lanes' captures and
-    // instantiations do not overlap
-    std::lock_guard<std::mutex> cap(srv->capture_mu);
+    std::lock_guard<std::mutex> cap(srv->graph_mu);
     hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
       const sbie_status la = launch_apply(s, st);
@@ -211,8 +213,26 @@ void build_session(sbie_server* srv, sbie_session* s, int lane) {
   s->ready_us = srv->now_us();
 }
 
-// One apply on the lane's stream: stage in, graph replay (or the same
-// launches), status word, stage out, wait.
+// The queue of one apply on the lane's stream: stage in, graph replay (or the
+// same launches), status word, stage out.
+sbie_status enqueue_apply(sbie_server* srv, sbie_session* s, Job* j, hipStream_t st, unsigned* hs) {
+  const size_t bytes = sizeof(double) * (size_t)s->nrhs * s->N;
+  SBIE_HIP(hipMemcpyAsync(s->d_in, j->din, bytes, j->devptr ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+  if (s->exec) {
+    std::lock_guard<std::mutex> lk(srv->graph_mu);
+    SBIE_HIP(hipGraphLaunch(s->exec, st));
+  } else {
+    const sbie_status rc = launch_apply(s, st);
+    if (rc != SBIE_OK) return rc;
+  }
+  SBIE_HIP(hipMemcpyAsync(hs, s->g->d_status, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+  SBIE_HIP(hipMemcpyAsync(j->dout, s->d_out, bytes, j->devptr ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+  return SBIE_OK;
+}
+
+// One apply: its queue, then the wait.  The stream is synchronised on every
+// path, so the caller's buffers are no longer read or written once the job is
+// marked done.
 sbie_status run_apply(sbie_server* srv, sbie_session* s, Job* j, int lane, std::string* err) {
   if (s->failed) {
     *err = s->fail_msg;
@@ -220,21 +240,18 @@ sbie_status run_apply(sbie_server* srv, sbie_session* s, Job* j, int lane, std::
   }
   hipStream_t st = srv->lane_ctx[lane]->stream;
   unsigned* hs = srv->lane_status[lane];
-  const size_t bytes = sizeof(double) * (size_t)s->nrhs * s->N;
   *hs = 0u;
-  SBIE_HIP(hipMemcpyAsync(s->d_in, j->din, bytes, j->devptr ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
-  if (s->exec) {
-    SBIE_HIP(hipGraphLaunch(s->exec, st));
-  } else {
-    const sbie_status rc = launch_apply(s, st);
-    if (rc != SBIE_OK) {
-      *err = sbie_last_error();
-      return rc;
-    }
+  const sbie_status rc = enqueue_apply(srv, s, j, st, hs);
+  const hipError_t se = hipStreamSynchronize(st);
+  if (rc != SBIE_OK) {
+    *err = sbie_last_error();
+    return rc;
   }
-  SBIE_HIP(hipMemcpyAsync(hs, s->g->d_status, sizeof(unsigned), hipMemcpyDeviceToHost, st));
-  SBIE_HIP(hipMemcpyAsync(j->dout, s->d_out, bytes, j->devptr ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
-  SBIE_HIP(hipStreamSynchronize(st));
+  if (se != hipSuccess) {
+    const sbie_status ds = device_error(se, "hipStreamSynchronize");
+    *err = sbie_last_error();
+    return ds;
+  }
   const unsigned status = *hs;
   if (status) {
     SBIE_HIP(hipMemsetAsync(s->g->d_status, 0, sizeof(unsigned), st));
@@ -249,9 +266,12 @@ sbie_status run_apply(sbie_server* srv, sbie_session* s, Job* j, int lane, std::
   return SBIE_OK;
 }
 
-void teardown(sbie_session* s) {
-  if (s->exec) (void)hipGraphExecDestroy(s->exec);
-  if (s->graph) (void)hipGraphDestroy(s->graph);
+void teardown(sbie_server* srv, sbie_session* s) {
+  if (s->exec || s->graph) {
+    std::lock_guard<std::mutex> lk(srv->graph_mu);
+    if (s->exec) (void)hipGraphExecDestroy(s->exec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
+  }
   s->exec = nullptr;
   s->graph = nullptr;
   destroy_geometry(s->g);
@@ -301,7 +321,7 @@ void lane_main(sbie_server* srv, int lane) {
     }
     if (cur->closing || srv->stopping) {
       lk.unlock();
-      teardown(cur);
+      teardown(srv, cur);
       lk.lock();
       srv->arena.release(cur->off, cur->bytes);
       --srv->n_active;

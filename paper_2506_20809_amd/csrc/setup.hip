@@ -423,6 +423,28 @@ uint64_t plan_bytes(int M, int p, bool stokes) {
   return (c.used + 255) & ~uint64_t(255);
 }
 
+namespace {
+
+// Host buffers that asynchronous copies read.  HIP may read a pageable source
+// when the copy executes rather than when it is queued, so every such buffer
+// lives here and the destructor synchronises the stream before any of them is
+// released, on every return path.  (The 128 KiB reciprocal table sits exactly
+// at glibc's default mmap threshold: freed early in a fresh process, its pages
+// were unmapped while the copy could still read them.)
+struct SetupStaging {
+  hipStream_t s;
+  std::vector<double> cd, gl, ab, rcp;
+  std::vector<uint8_t> near;
+  std::vector<uint32_t> excl;
+  unsigned status = 0;
+  explicit SetupStaging(hipStream_t st) : s(st) {}
+  ~SetupStaging() { (void)hipStreamSynchronize(s); }
+  SetupStaging(const SetupStaging&) = delete;
+  SetupStaging& operator=(const SetupStaging&) = delete;
+};
+
+}  // namespace
+
 sbie_status setup_geometry(sbie_geom* g, hipStream_t s) {
   const int M = g->M, p = g->p, T = g->T, K = g->K, Kh = g->Kh;
   const int64_t N = g->N;
@@ -456,19 +478,22 @@ sbie_status setup_geometry(sbie_geom* g, hipStream_t s) {
     SBIE_HIP(hipEventCreateWithFlags(&g->ev_join, hipEventDisableTiming));
   }
   const int Kh2 = (p + 2) * (p + 3) / 2;
+  SetupStaging h(s);  // host sources and destinations of the copies below
   {
-    std::vector<double> cd(Kh, 0.0);
+    std::vector<double>& cd = h.cd;
+    cd.assign(Kh, 0.0);
     for (int n = 0; n <= p; ++n)
       for (int m = 0; m <= n; ++m)
         cd[n * (n + 1) / 2 + m] = std::sqrt((2.0 * n + 1.0) * (n + m + 1.0) * (n - m + 1.0) / (2.0 * n + 3.0));
     SBIE_HIP(hipMemcpyAsync(g->d_cd, cd.data(), sizeof(double) * Kh, hipMemcpyHostToDevice, s));
-    SBIE_HIP(hipStreamSynchronize(s));
   }
 
-  std::vector<double> gl(2 * (p + 1));
+  std::vector<double>& gl = h.gl;
+  gl.assign(2 * (p + 1), 0.0);
   gauss_legendre_host(p + 1, gl.data(), gl.data() + p + 1);
   // normalised Ferrers recurrence coefficients a_nm, b_nm for n >= m+2
-  std::vector<double> ab(2 * Kh2, 0.0);
+  std::vector<double>& ab = h.ab;
+  ab.assign(2 * Kh2, 0.0);
   for (int n = 0; n <= p + 1; ++n)
     for (int m = 0; m <= n; ++m) {
       if (n < m + 2) continue;
@@ -504,8 +529,9 @@ sbie_status setup_geometry(sbie_geom* g, hipStream_t s) {
                        d_near, g->d_status);
     SBIE_HIP(hipGetLastError());
   }
-  std::vector<uint8_t> near((size_t)M * M);
-  unsigned status = 0;
+  std::vector<uint8_t>& near = h.near;
+  near.assign((size_t)M * M, 0);
+  unsigned& status = h.status;
   SBIE_HIP(hipMemcpyAsync(near.data(), d_near, near.size(), hipMemcpyDeviceToHost, s));
   SBIE_HIP(hipMemcpyAsync(&status, g->d_status, sizeof(unsigned), hipMemcpyDeviceToHost, s));
   SBIE_HIP(hipStreamSynchronize(s));
@@ -524,7 +550,8 @@ sbie_status setup_geometry(sbie_geom* g, hipStream_t s) {
   g->h_near_src.clear();
   const int words = (M + 31) / 32;
   g->excl_words = words;
-  std::vector<uint32_t> excl((size_t)M * words, 0u);
+  std::vector<uint32_t>& excl = h.excl;
+  excl.assign((size_t)M * words, 0u);
   int64_t excluded_pairs = 0;
   for (int j = 0; j < M; ++j) {
     excl[(size_t)j * words + j / 32] |= 1u << (j % 32);
@@ -549,7 +576,8 @@ sbie_status setup_geometry(sbie_geom* g, hipStream_t s) {
   g->T16 = 16 * ((T + 15) / 16);
   SBIE_TRY(far_records(g, s));
   {
-    std::vector<double> rcp(kRcpN, 0.0);
+    std::vector<double>& rcp = h.rcp;
+    rcp.assign(kRcpN, 0.0);
     for (int k = 1; k < kRcpN; ++k) rcp[k] = 1.0 / (double)k;
     SBIE_HIP(hipMemcpyAsync(g->d_rcp, rcp.data(), sizeof(double) * kRcpN, hipMemcpyHostToDevice, s));
   }

@@ -260,8 +260,6 @@ def test_served_errors(ctx):
     srv.close()
 
 
-@pytest.mark.skip(reason="a run of this case ended with a host segmentation fault in a non-Python thread "
-                         "(lane or runtime); no cause has been shown, so the case stays off the GPU")
 def test_served_many_concurrent_clients(ctx):
     """Forty small sessions from sixteen client threads at once (the ticket table
     grows while clients wait on it); every result equals its plain apply."""
@@ -293,7 +291,9 @@ def test_served_many_concurrent_clients(ctx):
     for t in threads:
         t.start()
     for t in threads:
-        t.join(timeout=300)
+        t.join(timeout=100)
+    # the server is destroyed only once no client can still call into it
+    assert not any(t.is_alive() for t in threads), "a client thread did not finish"
     assert not errors, errors
     srv.close()
     for k, g in enumerate(geoms):

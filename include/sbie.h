@@ -89,6 +89,12 @@ typedef enum {
 #define SBIE_PARTS_ALL 0x70u   /* 0 also means all parts */
 #define SBIE_FAR_TREE 0x100u   /* S or D: the far field from the geometry's tree (sbie_geom_far_tree)
                                   instead of the direct sum */
+#define SBIE_INPUT_COEFFS 0x200u /* S or D: the input is the coefficients [nrhs][M][(p+1)^2] of
+                                  Algorithm 1's forward transform (layout of sbie_transform:
+                                  l = n^2 + n + m; for S the modified-basis coefficients of
+                                  sqrt(u0^2 -+ v^2) sigma), so the transform step is skipped
+                                  ("if not provided").  The far field's nodal density is their
+                                  synthesis at the nodes (divided by sqrt(u0^2 -+ v^2) for S). */
 
 typedef struct sbie_ctx sbie_ctx;
 typedef struct sbie_geom sbie_geom;
@@ -152,8 +158,10 @@ sbie_status sbie_geom_near_pairs(const sbie_geom* g, int32_t* src, int32_t* dst,
    stream: a hipStream_t, or NULL for the context stream with the call
    returning after completion.  With a non-NULL stream and SBIE_DEVICE_PTRS the
    call is asynchronous on that stream.  flags: SBIE_DEVICE_PTRS, SBIE_TIMING,
-   SBIE_PARTS_*.  Errors: SBIE_E_INVALID (op, precision, nrhs outside [1,16],
-   Stokes with nrhs != 3), SBIE_E_NUMERIC, SBIE_E_DEVICE, SBIE_E_NOMEM. */
+   SBIE_PARTS_*, SBIE_FAR_TREE, SBIE_INPUT_COEFFS (S and D: density holds
+   coefficients, [nrhs][M][(p+1)^2]).  Errors: SBIE_E_INVALID (op, precision,
+   nrhs outside [1,16], Stokes with nrhs != 3, SBIE_INPUT_COEFFS with another
+   operator), SBIE_E_NUMERIC, SBIE_E_DEVICE, SBIE_E_NOMEM. */
 sbie_status sbie_apply(sbie_geom* g, sbie_op op, sbie_precision prec, int32_t nrhs,
                        const double* density, double* potential, void* stream,
                        uint32_t flags);

@@ -23,6 +23,7 @@ SBIE_DEVICE_PTRS = 0x1
 SBIE_TIMING = 0x2
 SBIE_PARTS_SELF, SBIE_PARTS_NEAR, SBIE_PARTS_FAR, SBIE_PARTS_ALL = 0x10, 0x20, 0x40, 0x70
 SBIE_FAR_TREE = 0x100
+SBIE_INPUT_COEFFS = 0x200
 
 STATUS = {0: "SBIE_OK", -1: "SBIE_E_INVALID", -2: "SBIE_E_DEGENERATE", -3: "SBIE_E_OVERLAP", -4: "SBIE_E_NOMEM",
           -5: "SBIE_E_BUDGET", -6: "SBIE_E_DEVICE", -7: "SBIE_E_TIMEOUT", -8: "SBIE_E_NUMERIC", -9: "SBIE_E_STATE"}
@@ -235,17 +236,26 @@ class Geometry:
         return src, dst
 
     def apply(self, op: int, density, precision: int = SBIE_FP64, parts: int = SBIE_PARTS_ALL, out=None,
-              stream=None, timing: bool = False, tree: bool = False):
+              stream=None, timing: bool = False, tree: bool = False, coeffs: bool = False):
         """Apply S, D, S', D' or the Stokes single layer.  density: torch CUDA float64
         tensor [nrhs, N] or [N] (device pointers, on the current stream), or a numpy
         array (host pointers, synchronous).  SBIE_OP_STOKES_SP returns [4, N]
         (velocity, then pressure).  tree: the far field of S or D through the
-        geometry's tree (far_tree)."""
-        flags = int(parts) | (SBIE_TIMING if timing else 0) | (SBIE_FAR_TREE if tree else 0)
+        geometry's tree (far_tree).  coeffs: S or D of given transform
+        coefficients, density [nrhs, M, (p+1)^2] or [M, (p+1)^2] as transform()
+        returns them (SBIE_INPUT_COEFFS); the result is [nrhs, N] or [N]."""
+        flags = (int(parts) | (SBIE_TIMING if timing else 0) | (SBIE_FAR_TREE if tree else 0)
+                 | (SBIE_INPUT_COEFFS if coeffs else 0))
+        nin = self.M * (self.p + 1) ** 2 if coeffs else self.N
         if isinstance(density, np.ndarray):
             d = np.ascontiguousarray(density, dtype=np.float64)
-            nrhs = 1 if d.ndim == 1 else d.shape[0]
-            o = np.zeros((4, self.N)) if op == SBIE_OP_STOKES_SP else np.zeros_like(d)
+            nrhs = d.size // nin if coeffs else (1 if d.ndim == 1 else d.shape[0])
+            if d.size != nrhs * nin or nrhs < 1:
+                raise ValueError(f"density has {d.size} entries, expected nrhs x {nin}")
+            if op == SBIE_OP_STOKES_SP:
+                o = np.zeros((4, self.N))
+            else:
+                o = np.zeros((nrhs, self.N) if (d.ndim > (2 if coeffs else 1)) else (self.N,))
             _check(lib().sbie_apply(self._h, int(op), int(precision), nrhs, d.ctypes.data, o.ctypes.data, None,
                                     flags))
             return o
@@ -253,12 +263,17 @@ class Geometry:
 
         if not (density.is_cuda and density.dtype == torch.float64 and density.is_contiguous()):
             raise ValueError("density must be a contiguous float64 CUDA tensor")
-        nrhs = 1 if density.dim() == 1 else density.shape[0]
-        if density.numel() != nrhs * self.N:
-            raise ValueError(f"density has {density.numel()} entries, expected {nrhs} x {self.N}")
+        nrhs = density.numel() // nin if coeffs else (1 if density.dim() == 1 else density.shape[0])
+        if density.numel() != nrhs * nin or nrhs < 1:
+            raise ValueError(f"density has {density.numel()} entries, expected {nrhs} x {nin}")
         if out is None:
-            out = (torch.empty((4, self.N), dtype=torch.float64, device=density.device)
-                   if op == SBIE_OP_STOKES_SP else torch.empty_like(density))
+            if op == SBIE_OP_STOKES_SP:
+                out = torch.empty((4, self.N), dtype=torch.float64, device=density.device)
+            elif coeffs:
+                shape = (nrhs, self.N) if density.dim() > 2 else (self.N,)
+                out = torch.empty(shape, dtype=torch.float64, device=density.device)
+            else:
+                out = torch.empty_like(density)
         if stream is None:
             stream = torch.cuda.current_stream(density.device)
         if stream.cuda_stream == 0:

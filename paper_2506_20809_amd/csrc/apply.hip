@@ -145,6 +145,16 @@ __global__ __launch_bounds__(256) void k_gemm_f32c(const double* __restrict__ A,
   }
 }
 
+// Nodal single-layer density from the synthesis of modified-basis
+// coefficients: sigma = f / sqrt(u0^2 -+ v^2) (Section 3.2), in place.
+__global__ void k_unweight_f64(const double* __restrict__ wS, int p, int64_t N, double* f) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  const int Nphi = 2 * p + 2, T = (p + 1) * Nphi;
+  const int i = (int)(g / T), j = (int)((g - (int64_t)i * T) / Nphi);
+  f[g] = f[g] / wS[(size_t)i * (p + 1) + j];
+}
+
 // Diagonal spectra: self coefficients and exterior coefficients per particle.
 __global__ void k_scale_coef(const double* __restrict__ coef, const double* __restrict__ lam, int M,
                              int p, int op, double* cself, double* E) {
@@ -381,12 +391,11 @@ __global__ __launch_bounds__(256) void k_far_f64(
 
 // ---------------------------------------------------------------- assembly
 
-// u = u_self + u_near + sum over the forward far partials (split order) + sum
-// over the reverse far partials (handler slot, then row group order).
-template <typename RV>
+// u = u_self + u_near + sum over the forward far partials (split order) + the
+// running reverse sums of the pair-symmetric far field (racc, when set).
 __global__ void k_assemble_f64(const double* __restrict__ uself, const double* __restrict__ unear,
-                               const double* __restrict__ partial, int nsplit, const RV* __restrict__ rev, int M,
-                               int T, int RG, int64_t N, uint32_t parts, double* __restrict__ out) {
+                               const double* __restrict__ partial, int nsplit, const double* __restrict__ racc,
+                               int64_t N, uint32_t parts, double* __restrict__ out) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= N) return;
   double u = 0.0;
@@ -396,16 +405,7 @@ __global__ void k_assemble_f64(const double* __restrict__ uself, const double* _
   if (parts & SBIE_PARTS_FAR) {
     double f = 0.0;
     for (int s = 0; s < nsplit; ++s) f += partial[(size_t)s * N + g];
-    if (rev) {
-      // slots k < H always have a handler; slot H (even M) only for b >= M/2
-      const int b = (int)(g / T), t = (int)(g - (int64_t)b * T);
-      const int H = (M - 1) / 2;
-      const int slots = H + (((M & 1) == 0 && b >= M / 2) ? 1 : 0);
-      double r = 0.0;
-      for (int k = 0; k < slots; ++k)
-        for (int rg = 0; rg < RG; ++rg) r += (double)rev[(((size_t)b * (H + 1) + k) * RG + rg) * T + t];
-      f += r * kInv4Pi;
-    }
+    if (racc) f += racc[g] * kInv4Pi;
     u += f;
   }
   out[g] = u;
@@ -474,6 +474,20 @@ sbie_status apply_laplace(sbie_geom* g, int op, int prec, const double* d_dens, 
     if (st) return st;
     SBIE_HIP(hipEventRecord(ev[0], s));
   }
+  // coefficients given (SBIE_INPUT_COEFFS): the transform step is skipped, and
+  // the far field's nodal density is their synthesis at the nodes, in FP64
+  const bool coef_in = (parts & SBIE_INPUT_COEFFS) != 0;
+  const double* coef = g->d_coef;
+  if (coef_in) {
+    coef = d_dens;
+    sbie_status st = launch_gemm(coef, K, g->d_Sy, T, g->d_dens, T, M, T, K, s);
+    if (st) return st;
+    if (op == SBIE_OP_S) {
+      hipLaunchKernelGGL(k_unweight_f64, dim3(cdiv(N, B)), dim3(B), 0, s, g->d_wS, p, N, g->d_dens);
+      SBIE_HIP(hipGetLastError());
+    }
+    d_dens = g->d_dens;
+  }
   // prep: transform input and far-field source records
   if (op == SBIE_OP_S)
     hipLaunchKernelGGL(k_prep_f64<SBIE_OP_S>, dim3(cdiv(N, B)), dim3(B), 0, s, d_dens, g->d_x, g->d_y, g->d_z,
@@ -486,10 +500,12 @@ sbie_status apply_laplace(sbie_geom* g, int op, int prec, const double* d_dens, 
   // part (a) forward transform, part (b) spectra and inverse transform
   const bool mixed = prec == SBIE_MIXED;
   if (parts & (SBIE_PARTS_SELF | SBIE_PARTS_NEAR)) {
-    sbie_status st = mixed ? launch_gemm32(g->d_f, T, g->d_An32, K, g->d_coef, K, M, K, T, s)
-                           : launch_gemm(g->d_f, T, g->d_An, K, g->d_coef, K, M, K, T, s);
-    if (st) return st;
-    hipLaunchKernelGGL(k_scale_coef, dim3(cdiv((int64_t)M * K, B)), dim3(B), 0, s, g->d_coef, g->d_lam, M, p, op,
+    if (!coef_in) {
+      sbie_status st = mixed ? launch_gemm32(g->d_f, T, g->d_An32, K, g->d_coef, K, M, K, T, s)
+                             : launch_gemm(g->d_f, T, g->d_An, K, g->d_coef, K, M, K, T, s);
+      if (st) return st;
+    }
+    hipLaunchKernelGGL(k_scale_coef, dim3(cdiv((int64_t)M * K, B)), dim3(B), 0, s, coef, g->d_lam, M, p, op,
                        g->d_cself, g->d_E);
     SBIE_HIP(hipGetLastError());
   }
@@ -547,16 +563,12 @@ sbie_status apply_laplace(sbie_geom* g, int op, int prec, const double* d_dens, 
   }
   // with no near pairs the near part is empty and is left out of the sum
   const uint32_t sum_parts = g->n_near > 0 ? parts : (parts & ~(uint32_t)SBIE_PARTS_NEAR);
-  const int RG = far_row_groups(g, !mixed);
-  if (tree)  // the forward slices, no reverse sums
-    hipLaunchKernelGGL(k_assemble_f64<double>, dim3(cdiv(N, B)), dim3(B), 0, s, g->d_uself, g->d_unear,
-                       g->d_partial, g->nsplit, (const double*)nullptr, M, T, RG, N, sum_parts, d_out);
-  else if (T >= 32 && mixed)
-    hipLaunchKernelGGL(k_assemble_f64<float>, dim3(cdiv(N, B)), dim3(B), 0, s, g->d_uself, g->d_unear, g->d_partial,
-                       g->nsplit, reinterpret_cast<const float*>(g->d_rev), M, T, RG, N, sum_parts, d_out);
-  else
-    hipLaunchKernelGGL(k_assemble_f64<double>, dim3(cdiv(N, B)), dim3(B), 0, s, g->d_uself, g->d_unear,
-                       g->d_partial, g->nsplit, T >= 32 ? g->d_rev : nullptr, M, T, RG, N, sum_parts, d_out);
+  // the pair kernel writes the forward slices [0, its splits) and the reverse
+  // totals; the tree and the vector-unit sum write all nsplit slices
+  const bool pairs = !tree && T >= 32;
+  const int nslices = pairs ? far_launch_splits(g, far_row_groups(g, !mixed)) : g->nsplit;
+  hipLaunchKernelGGL(k_assemble_f64, dim3(cdiv(N, B)), dim3(B), 0, s, g->d_uself, g->d_unear, g->d_partial, nslices,
+                     pairs ? (const double*)g->d_racc : nullptr, N, sum_parts, d_out);
   SBIE_HIP(hipGetLastError());
   if (timed) SBIE_HIP(hipEventRecord(ev[5], s));
   return SBIE_OK;

@@ -279,6 +279,11 @@ sbie_status sbie_apply(sbie_geom* g, sbie_op op, sbie_precision prec, int32_t nr
     }
     parts |= SBIE_FAR_TREE;
   }
+  const bool coef_in = (flags & SBIE_INPUT_COEFFS) != 0;
+  if (coef_in) {
+    if (op != SBIE_OP_S && op != SBIE_OP_D) return invalid("SBIE_INPUT_COEFFS applies to S and D only");
+    parts |= SBIE_INPUT_COEFFS;
+  }
   const bool devptr = (flags & SBIE_DEVICE_PTRS) != 0;
   const bool timed = (flags & SBIE_TIMING) != 0;
   hipStream_t s = stream ? (hipStream_t)stream : g->ctx->stream;
@@ -320,12 +325,15 @@ sbie_status sbie_apply(sbie_geom* g, sbie_op op, sbie_precision prec, int32_t nr
     if (!stream || !devptr) return sbie_geom_sync(g, s);
     return SBIE_OK;
   }
+  // one input: N nodal values, or M (p+1)^2 coefficients
+  const int64_t nin = coef_in ? (int64_t)g->M * g->K : N;
   for (int r = 0; r < nrhs; ++r) {
-    const double* din = density + (size_t)r * N;
+    const double* din = density + (size_t)r * nin;
     double* dout = potential + (size_t)r * N;
     if (!devptr) {
-      SBIE_HIP(hipMemcpyAsync(g->d_dens, din, sizeof(double) * N, hipMemcpyHostToDevice, s));
-      din = g->d_dens;
+      double* stage = coef_in ? g->d_coef : g->d_dens;
+      SBIE_HIP(hipMemcpyAsync(stage, din, sizeof(double) * nin, hipMemcpyHostToDevice, s));
+      din = stage;
       dout = g->d_out;
     }
     sbie_status st = apply_laplace(g, (int)op, (int)prec, din, dout, s, parts, timed && r == nrhs - 1);

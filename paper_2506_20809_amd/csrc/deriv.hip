@@ -201,12 +201,11 @@ __global__ __launch_bounds__(256) void k_far_normal(const R* __restrict__ rec, c
 }
 
 // u = u_self / sqrt(u0^2 -+ v^2) (the modified basis of the self expansions)
-// + u_near + the far partials in split order (+ the reverse partials of the
-// pair-symmetric far field, handler slot then row group order, when rev is set).
-template <typename RV>
+// + u_near + the far partials in split order (+ the running reverse sums of
+// the pair-symmetric far field, when racc is set).
 __global__ void k_normal_assemble(const double* __restrict__ uself, const double* __restrict__ wS,
                                   const double* __restrict__ unear, const double* __restrict__ partial, int nsplit,
-                                  const RV* __restrict__ rev, int M, int RG, int p, int64_t N, uint32_t parts,
+                                  const double* __restrict__ racc, int p, int64_t N, uint32_t parts,
                                   double* __restrict__ out) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= N) return;
@@ -219,15 +218,7 @@ __global__ void k_normal_assemble(const double* __restrict__ uself, const double
   if (parts & SBIE_PARTS_FAR) {
     double f = 0.0;
     for (int s = 0; s < nsplit; ++s) f += partial[(size_t)s * N + g];
-    if (rev) {
-      const int H = (M - 1) / 2;
-      const int slots = H + (((M & 1) == 0 && i >= M / 2) ? 1 : 0);
-      const int t = (int)(g - (int64_t)i * T);
-      double r = 0.0;
-      for (int k = 0; k < slots; ++k)
-        for (int rg = 0; rg < RG; ++rg) r += (double)rev[(((size_t)i * (H + 1) + k) * RG + rg) * T + t];
-      f += r * kInv4Pi;
-    }
+    if (racc) f += racc[g] * kInv4Pi;
     u += f;
   }
   out[g] = u;
@@ -331,15 +322,9 @@ sbie_status apply_normal(sbie_geom* g, int op, int prec, const double* d_dens, d
     if (timed) SBIE_HIP(hipEventRecord(ev[4], s));
   }
   const uint32_t sum_parts = g->n_near > 0 ? parts : (parts & ~(uint32_t)SBIE_PARTS_NEAR);
-  const int RG = far_row_groups(g, !mixed);
-  if (pairs && mixed)
-    hipLaunchKernelGGL(k_normal_assemble<float>, dim3(cdiv(N, 256)), dim3(256), 0, s, g->d_uself, g->d_wS,
-                       g->d_unear, g->d_partial, g->nsplit, reinterpret_cast<const float*>(g->d_rev), M, RG, p, N,
-                       sum_parts, d_out);
-  else
-    hipLaunchKernelGGL(k_normal_assemble<double>, dim3(cdiv(N, 256)), dim3(256), 0, s, g->d_uself, g->d_wS,
-                       g->d_unear, g->d_partial, g->nsplit, pairs ? g->d_rev : nullptr, M, RG, p, N, sum_parts,
-                       d_out);
+  const int nslices = pairs ? far_launch_splits(g, far_row_groups(g, !mixed)) : g->nsplit;
+  hipLaunchKernelGGL(k_normal_assemble, dim3(cdiv(N, 256)), dim3(256), 0, s, g->d_uself, g->d_wS, g->d_unear,
+                     g->d_partial, nslices, pairs ? (const double*)g->d_racc : nullptr, p, N, sum_parts, d_out);
   SBIE_HIP(hipGetLastError());
   if (timed) SBIE_HIP(hipEventRecord(ev[5], s));
   return SBIE_OK;

@@ -127,10 +127,17 @@ struct PairShape {
 // a + M/2 when a < M/2.  The reciprocal distance of each node pair serves both
 // directions: the forward sum into a's targets from b's sources stays in
 // registers across the partners, and the reverse sum into b's targets from
-// a's sources is reduced over a's rows (lanes, then waves in order) and written
-// to rev[b][k][rg][t], k = (b - a - 1) mod M, the slot of handler a in b's
-// list.  A direction whose source is excluded for its target particle (self,
-// near field) is dropped; its reverse slot is written as zero.
+// a's sources is reduced over a's rows (lanes, then waves in order).  A
+// direction whose source is excluded for its target particle (self, near
+// field) is dropped.
+//
+// One launch covers the partner offsets k in [kbase, kend) (k = (b - a - 1)
+// mod M is also the slot of handler a in b's list).  Its reverse sums go to
+// rev[b][k - kbase][rg][t] (a dropped direction writes zeros), which
+// k_far_fold adds, slot by slot, into b's running totals before the next
+// launch reuses the slots: memory for kend - kbase slots instead of H + 1.
+// The forward sums of the launch are added to the split's running partial
+// (first launch: written).
 //
 // Squared distances come off the matrix cores as in a K = 4 contraction: with
 // D = x - c_b and o = y - c_b,  |x - y|^2 = [D |D|^2] . [-2o 1] + |o|^2.  The
@@ -150,8 +157,8 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
                                                    const Particle* __restrict__ part, const double* __restrict__ x,
                                                    const double* __restrict__ y, const double* __restrict__ z,
                                                    const uint32_t* __restrict__ excl, int words, int M, int T,
-                                                   int T16, int64_t N, int nsplit, int RG,
-                                                   double* __restrict__ fwd, R* __restrict__ rev) {
+                                                   int T16, int64_t N, int nsplit, int RG, int kbase, int kend,
+                                                   int first, double* __restrict__ fwd, R* __restrict__ rev) {
   using MM = Mfma<R>;
   using V = typename MM::V;
   using L = FarLayout<R, OP>;
@@ -191,7 +198,11 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
   const int H = (M - 1) / 2;
   const bool even = (M & 1) == 0;
   const int P = H + ((even && a < M / 2) ? 1 : 0);
-  const int k0 = (int)((int64_t)P * split / nsplit), k1 = (int)((int64_t)P * (split + 1) / nsplit);
+  // this launch's partner offsets of particle a, split nsplit ways
+  const int klo = kbase < P ? kbase : P, khi = kend < P ? kend : P;
+  const int k0 = klo + (int)((int64_t)(khi - klo) * split / nsplit);
+  const int k1 = klo + (int)((int64_t)(khi - klo) * (split + 1) / nsplit);
+  const int KS = kend - kbase;  // slots of the launch
   const Particle& Pa = part[a];
 
   // A-operand row li of each row block: lane group lg < 3 keeps component lg
@@ -275,7 +286,7 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
     const int b = k < H ? (a + 1 + k) % M : a + M / 2;
     const bool need_f = !((excl[(size_t)a * words + (b >> 5)] >> (b & 31)) & 1u);
     const bool need_r = !((excl[(size_t)b * words + (a >> 5)] >> (a & 31)) & 1u);
-    R* rout = rev + (((size_t)b * (H + 1) + k) * RG + rg) * T;
+    R* rout = rev + (((size_t)b * KS + (k - kbase)) * RG + rg) * T;
     if (!need_f && !need_r) {
       for (int t = tid; t < T; t += blockDim.x) rout[t] = R(0);
       continue;
@@ -607,7 +618,10 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
     const int rb = li >> 2, row = MM::row(lg, li & 3);
     if (rb < nown) {
       const int r = (rb0 + rb) * 16 + row;
-      if (r < T) fwd[(size_t)split * N + (int64_t)a * T + r] = acc1 * kInv4PiD;
+      if (r < T) {
+        double* f = fwd + (size_t)split * N + (int64_t)a * T + r;
+        *f = (first ? 0.0 : *f) + acc1 * kInv4PiD;
+      }
     } else if (rb < nrb) {
       lds_x[wave * (nx * 16) + (rb - nown) * 16 + row] = acc1;
     }
@@ -622,7 +636,10 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
         const int row = MM::row(lg, e);
         if (rb < nown) {
           const int r = (rb0 + rb) * 16 + row;
-          if (li == 0 && r < T) fwd[(size_t)split * N + (int64_t)a * T + r] = v * kInv4PiD;
+          if (li == 0 && r < T) {
+            double* f = fwd + (size_t)split * N + (int64_t)a * T + r;
+            *f = (first ? 0.0 : *f) + v * kInv4PiD;
+          }
         } else if (rb < nrb && li == 0) {
           lds_x[wave * (nx * 16) + (rb - nown) * 16 + row] = v;
         }
@@ -634,9 +651,33 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
       const int r = xb0 * 16 + c;
       double v = 0.0;
       for (int w = 0; w < W; ++w) v += lds_x[w * (nx * 16) + c];
-      if (r < T) fwd[(size_t)split * N + (int64_t)a * T + r] = v * kInv4PiD;
+      if (r < T) {
+        double* f = fwd + (size_t)split * N + (int64_t)a * T + r;
+        *f = (first ? 0.0 : *f) + v * kInv4PiD;
+      }
     }
   }
+}
+
+// After a launch over the partner offsets [kbase, kend): each target's reverse
+// slots of the launch (the slots with a handler: k < H, and k = H for even M
+// when the target is in the upper half), slot then row group, added in FP64 to
+// its running total (first launch: from zero).  Over the launches the totals
+// take the slots in ascending order, as one pass over all of them would.
+template <typename R>
+__global__ void k_far_fold(const R* __restrict__ rev, int M, int T, int RG, int kbase, int kend, int first,
+                           int64_t N, double* __restrict__ racc) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  const int b = (int)(g / T), t = (int)(g - (int64_t)b * T);
+  const int H = (M - 1) / 2;
+  const int slots = H + (((M & 1) == 0 && b >= M / 2) ? 1 : 0);
+  const int KS = kend - kbase;
+  const int hi = kend < slots ? kend : slots;
+  double r = first ? 0.0 : racc[g];
+  for (int k = kbase; k < hi; ++k)
+    for (int rg = 0; rg < RG; ++rg) r += (double)rev[(((size_t)b * KS + (k - kbase)) * RG + rg) * T + t];
+  racc[g] = r;
 }
 
 // Per-geometry source operands.  One thread per (padded) source q of particle
@@ -798,7 +839,8 @@ sbie_status launch_far(sbie_geom* g, int op, const double* d_dens, const R* geo,
   const int RG = far_row_groups(g, sizeof(R) == 8);
   const int nb = g->T16 / 16;
   const int blocks = nb < PS::GB ? nb : PS::GB;
-  const dim3 grid((unsigned)((int64_t)g->M * RG * g->nsplit)), wg((unsigned)(64 * (blocks < PS::WMAX ? blocks : PS::WMAX)));
+  const dim3 grid((unsigned)((int64_t)g->M * RG * far_launch_splits(g, RG))),
+      wg((unsigned)(64 * (blocks < PS::WMAX ? blocks : PS::WMAX)));
   int ngeo = 0, napp = 0;
   switch (op) {
     case SBIE_OP_S: ngeo = FarLayout<R, SBIE_OP_S>::GEO; napp = FarLayout<R, SBIE_OP_S>::APP; break;
@@ -812,19 +854,34 @@ sbie_status launch_far(sbie_geom* g, int op, const double* d_dens, const R* geo,
   R* rev = reinterpret_cast<R*>(g->d_rev);
   const R* geo_s = FarLayout<R, SBIE_OP_S>::X3 ? geo_x3 : geo;
   const R* geo_d = FarLayout<R, SBIE_OP_D>::X3 ? geo_x3 : geo;
-  if (op == SBIE_OP_S)
-    hipLaunchKernelGGL((k_far_pairs<R, SBIE_OP_S>), grid, wg, lds, s, geo_s, app, g->d_part, g->d_x, g->d_y, g->d_z,
-                       g->d_excl, g->excl_words, g->M, g->T, g->T16, g->N, g->nsplit, RG, g->d_partial, rev);
-  else if (op == SBIE_OP_SP)
-    hipLaunchKernelGGL((k_far_pairs<R, SBIE_OP_SP>), grid, wg, lds, s, geo, app, g->d_part, g->d_x, g->d_y, g->d_z,
-                       g->d_excl, g->excl_words, g->M, g->T, g->T16, g->N, g->nsplit, RG, g->d_partial, rev);
-  else if (op == SBIE_OP_DP)
-    hipLaunchKernelGGL((k_far_pairs<R, SBIE_OP_DP>), grid, wg, lds, s, geo, app, g->d_part, g->d_x, g->d_y, g->d_z,
-                       g->d_excl, g->excl_words, g->M, g->T, g->T16, g->N, g->nsplit, RG, g->d_partial, rev);
-  else
-    hipLaunchKernelGGL((k_far_pairs<R, SBIE_OP_D>), grid, wg, lds, s, geo_d, app, g->d_part, g->d_x, g->d_y, g->d_z,
-                       g->d_excl, g->excl_words, g->M, g->T, g->T16, g->N, g->nsplit, RG, g->d_partial, rev);
-  SBIE_HIP(hipGetLastError());
+  const int KS = g->rev_slots, PMAX = (g->M - 1) / 2 + ((g->M & 1) == 0 ? 1 : 0);
+  const int nsplit = far_launch_splits(g, RG);
+  const dim3 fold((unsigned)cdiv(g->N, 256));
+  // (at least one launch: with no partners it writes the zero forward slices
+  // and reverse totals that the assembly reads)
+  for (int kbase = 0; kbase == 0 || kbase < PMAX; kbase += KS) {
+    const int kend = kbase + KS, first = kbase == 0 ? 1 : 0;
+    if (op == SBIE_OP_S)
+      hipLaunchKernelGGL((k_far_pairs<R, SBIE_OP_S>), grid, wg, lds, s, geo_s, app, g->d_part, g->d_x, g->d_y,
+                         g->d_z, g->d_excl, g->excl_words, g->M, g->T, g->T16, g->N, nsplit, RG, kbase, kend, first,
+                         g->d_partial, rev);
+    else if (op == SBIE_OP_SP)
+      hipLaunchKernelGGL((k_far_pairs<R, SBIE_OP_SP>), grid, wg, lds, s, geo, app, g->d_part, g->d_x, g->d_y,
+                         g->d_z, g->d_excl, g->excl_words, g->M, g->T, g->T16, g->N, nsplit, RG, kbase, kend, first,
+                         g->d_partial, rev);
+    else if (op == SBIE_OP_DP)
+      hipLaunchKernelGGL((k_far_pairs<R, SBIE_OP_DP>), grid, wg, lds, s, geo, app, g->d_part, g->d_x, g->d_y,
+                         g->d_z, g->d_excl, g->excl_words, g->M, g->T, g->T16, g->N, nsplit, RG, kbase, kend, first,
+                         g->d_partial, rev);
+    else
+      hipLaunchKernelGGL((k_far_pairs<R, SBIE_OP_D>), grid, wg, lds, s, geo_d, app, g->d_part, g->d_x, g->d_y,
+                         g->d_z, g->d_excl, g->excl_words, g->M, g->T, g->T16, g->N, nsplit, RG, kbase, kend, first,
+                         g->d_partial, rev);
+    SBIE_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_far_fold<R>, fold, dim3(256), 0, s, rev, g->M, g->T, RG, kbase, kend, first, g->N,
+                       g->d_racc);
+    SBIE_HIP(hipGetLastError());
+  }
   if (ev_end) SBIE_HIP(hipEventRecord(ev_end, s));
   return SBIE_OK;
 }
@@ -835,6 +892,28 @@ int far_row_groups(const sbie_geom* g, bool fp64) {
   const int T16 = 16 * ((g->T + 15) / 16);
   const int GB = fp64 ? PairShape<double>::GB : PairShape<float>::GB;
   return (T16 / 16 + GB - 1) / GB;
+}
+
+int far_launch_splits(const sbie_geom* g, int RG) {
+  const int want = (int)((512 + (int64_t)g->M * RG - 1) / ((int64_t)g->M * RG));
+  const int by_work = g->rev_slots / 4 > 1 ? g->rev_slots / 4 : 1;
+  int n = want < g->nsplit ? want : g->nsplit;
+  n = n < by_work ? n : by_work;
+  return n > 1 ? n : 1;
+}
+
+int far_rev_slots(int M, int T) {
+  const int nb = (T + 15) / 16;
+  const int RG = (nb + PairShape<double>::GB - 1) / PairShape<double>::GB;  // the FP64 sizing covers FP32
+  const int pmax = (M - 1) / 2 + ((M & 1) == 0 ? 1 : 0);
+  if (pmax < 1) return 1;  // one particle: no partners, one launch writes the zero sums
+  const size_t per_slot = (size_t)M * RG * T * sizeof(double);
+  int k = (int)(kRevBudget / (per_slot > 0 ? per_slot : 1));
+  if (k > pmax) k = pmax;
+  if (k < 1) k = 1;
+  // as many launches as the budget needs, their partner ranges balanced
+  const int launches = (pmax + k - 1) / k;
+  return (pmax + launches - 1) / launches;
 }
 
 sbie_status far_records(sbie_geom* g, hipStream_t s) {

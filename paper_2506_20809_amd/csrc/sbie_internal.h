@@ -14,6 +14,7 @@ namespace sbie {
 
 constexpr int kMaxP = 32;
 constexpr int kRcpN = 16384;  // reciprocal table length (near-field recurrences)
+constexpr size_t kRevBudget = size_t(64) << 20;  // reverse sums of one pair-kernel launch, bytes
 constexpr double kPi = 3.14159265358979323846264338327950288;
 
 // Per-particle parameters on the device (Section 2.1, Table 1).
@@ -180,9 +181,13 @@ struct sbie_geom {
   float* d_fstr32 = nullptr;      // [M*T16*16] per-apply far strengths (S 1, D 16, S' 8 per source)
   double* d_fstr64 = nullptr;     // [M*T16*8]
   double* d_rcp = nullptr;        // [kRcpN] reciprocals 1/k for the near-field recurrences
-  // pair-symmetric far field: reverse sums [M][H+1][RG][T] (FP64, or FP32 in
-  // the first half for the mixed path), H = (M-1)/2, RG target-row groups
+  // pair-symmetric far field, run as launches over chunks of rev_slots partner
+  // offsets: each launch's reverse sums [M][rev_slots][RG][T] (FP64, or FP32 in
+  // the first half for the mixed path), RG target-row groups, folded after the
+  // launch into the running FP64 reverse sums racc [N]
   double* d_rev = nullptr;
+  double* d_racc = nullptr;
+  int rev_slots = 0;
   double* d_eta = nullptr;        // [M] completion scalings of the last completed apply / solve
   double* d_qint = nullptr;       // [M] eta_i * integral of the density over particle i
   int nsplit = 8;
@@ -314,6 +319,14 @@ sbie_status stokes_staging(sbie_geom* g, double** io);
 // matrix-core far field (far_mfma.hip); target-row groups per particle of
 // the FP64 or the FP32 pair kernel
 int far_row_groups(const sbie_geom* g, bool fp64);
+// partner offsets per launch of the pair kernel: as many as keep one launch's
+// reverse sums within kRevBudget bytes (at least 1, at most every partner)
+int far_rev_slots(int M, int T);
+// Splits of each pair-kernel launch's partner offsets over workgroups (and so
+// the forward partial slices [0, splits) it writes): enough that a launch has
+// about 512 workgroups (two per compute unit), at most the geometry's nsplit
+// slices, and at least four partners per split.
+int far_launch_splits(const sbie_geom* g, int RG);
 sbie_status far_records(sbie_geom* g, hipStream_t s);
 sbie_status far_mfma(sbie_geom* g, int op, int prec, const double* d_dens, hipStream_t s, hipEvent_t ev_begin,
                      hipEvent_t ev_end);

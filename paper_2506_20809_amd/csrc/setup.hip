@@ -400,9 +400,12 @@ sbie_status carve_geometry(sbie_geom* g, Carver& c) {
   SBIE_TRY(c.take(&g->d_fstr64, 8 * n16));
   SBIE_TRY(c.take(&g->d_fstr32, 16 * n16));
   SBIE_TRY(c.take(&g->d_rcp, (size_t)kRcpN));
-  // reverse sums of the pair-symmetric far field (matrix-core path, T >= 32)
-  const size_t nrev = T >= 32 ? (size_t)M * ((M - 1) / 2 + 1) * far_row_groups(g, true) * T : 1;
+  // reverse sums of one launch of the pair-symmetric far field (matrix-core
+  // path, T >= 32) and their running FP64 totals
+  g->rev_slots = far_rev_slots(M, T);
+  const size_t nrev = T >= 32 ? (size_t)M * g->rev_slots * far_row_groups(g, true) * T : 1;
   SBIE_TRY(c.take(&g->d_rev, nrev));
+  SBIE_TRY(c.take(&g->d_racc, T >= 32 ? (size_t)N : 1));
   SBIE_TRY(c.take(&g->d_eta, (size_t)M));
   SBIE_TRY(c.take(&g->d_qint, (size_t)M));
   return SBIE_OK;

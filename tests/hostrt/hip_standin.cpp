@@ -172,6 +172,13 @@ hipError_t hipFree(void* p) {
 }
 
 hipError_t hipHostMalloc(void** p, size_t n, unsigned int) { return hipMalloc(p, n); }
+
+// A __device__ variable's host-side shadow has the variable's size: it stands
+// in for the device copy.
+hipError_t hipGetSymbolAddress(void** p, const void* symbol) {
+  *p = const_cast<void*>(symbol);
+  return hipSuccess;
+}
 hipError_t hipHostFree(void* p) { return hipFree(p); }
 
 hipError_t hipMemcpyAsync(void* dst, const void* src, size_t n, hipMemcpyKind, hipStream_t s) {

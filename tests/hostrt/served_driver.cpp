@@ -61,7 +61,7 @@ void plain_path() {
   check(sbie_ctx_create(0, &ctx), "sbie_ctx_create");
   if (!ctx) return;
   const int p = 6;  // T = 98 >= 32: the pair-symmetric far path and its records
-  for (int m : {2, 3, 5}) {
+  for (int m : {1, 2, 3, 5}) {
     Particles P = line_of(m, 11 + m);
     sbie_geom* g = nullptr;
     check(sbie_geom_create(ctx, P.c.data(), P.q.data(), P.A.data(), P.C.data(), m, p, 1.0, &g), "sbie_geom_create");

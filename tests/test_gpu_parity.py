@@ -379,3 +379,60 @@ def test_mixed_c3_full_size_sampled(ctx, op):
     ref = oracle.apply_at(geom, p, op, dens, tg)[0]
     assert _rel(u[tg], ref) < TOL_MIXED, _rel(u[tg], ref)
     g.close()
+
+
+# ---------------------------------------------------------------- full size, every node
+
+_C3_REF = {}
+
+
+def _c3_reference(op):
+    """The oracle's apply of the 512-spheroid workload at all 295936 nodes (one per operator)."""
+    if op not in _C3_REF:
+        _C3_REF[op] = oracle.apply(workloads.geometry("c3"), 16, op, workloads.density("c3")[0])
+    return _C3_REF[op]
+
+
+@pytest.mark.parametrize("op", [0, 1])
+def test_c3_full_size_every_node(ctx, op):
+    """512 spheroids, p = 16: FP64 within 1e-10 and mixed within 1e-6 (relative
+    l2; max-norm 1e-10 and 1e-5 of the result's max) at all 295936 nodes."""
+    import torch
+
+    import paper_2506_20809_amd as sbie
+
+    geom = workloads.geometry("c3")
+    p = 16
+    dens = workloads.density("c3")[0]
+    print(f"c3 every node op={op}: oracle", flush=True)
+    ref = _c3_reference(op)
+    g = sbie.Geometry(ctx, geom, p)
+    d = torch.tensor(dens, device="cuda")
+    scale = np.max(np.abs(ref))
+    for prec, tol, mtol in ((sbie.SBIE_FP64, TOL64, TOL64), (sbie.SBIE_MIXED, TOL_MIXED, 1e-5)):
+        u = g.apply(op, d, precision=prec)
+        g.sync()
+        u = u.cpu().numpy()
+        err, merr = _rel(u, ref), np.max(np.abs(u - ref)) / scale
+        print(f"c3 every node op={op} precision={prec}: rel l2 {err:.3e}, max {merr:.3e}", flush=True)
+        assert err < tol and merr < mtol, (prec, err, merr)
+    g.close()
+
+
+@pytest.mark.parametrize("name,p", [("c3", 16), ("c4", 12), ("c2", 16)])
+def test_near_pair_sets_exact(ctx, name, p):
+    """The directed near-pair sets of the full-size suspensions equal the
+    oracle's classification exactly (integer work: bit-exact)."""
+    import paper_2506_20809_amd as sbie
+
+    geom = workloads.geometry(name)
+    g = sbie.Geometry(ctx, geom, p)
+    src, dst = g.near_pairs()
+    near = oracle.classify(geom, 1.0)
+    i, j = np.nonzero(near)
+    ref = set(zip(i.tolist(), j.tolist()))
+    got = set(zip(src.tolist(), dst.tolist()))
+    assert len(got) == len(src), "duplicate pairs"
+    assert got == ref, (len(got), len(ref), sorted(got ^ ref)[:10])
+    assert g.num_near_pairs == len(ref)
+    g.close()

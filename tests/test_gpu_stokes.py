@@ -300,3 +300,26 @@ def test_pressure_c4_full_size_sampled(ctx):
     ref = oracle.stokes_apply_at(geom, p, dens, tg, pressure=True)[0]
     assert np.max(np.abs(u[:, tg] - ref)) < TOL64 * np.max(np.abs(ref))
     g.close()
+
+
+def test_stokes_c4_full_size_every_node(ctx):
+    """256 polydisperse spheroids at p = 12, all 86528 nodes and all three
+    components: FP64 within 1e-10 and mixed within 1e-6 (relative l2 per
+    component; max-norm 1e-10 and 1e-5 of the component's max)."""
+    import paper_2506_20809_amd as sbie
+
+    geom = workloads.geometry("c4")
+    p = 12
+    g = sbie.Geometry(ctx, geom, p)
+    dens = workloads.density("c4", nrhs=3)
+    print("c4 Stokes every node: oracle", flush=True)
+    ref = oracle.stokes_apply(geom, p, dens)
+    for prec, tol, mtol in ((sbie.SBIE_FP64, TOL64, TOL64), (sbie.SBIE_MIXED, TOL_MIXED, 1e-5)):
+        u = _stokes(g, dens, prec)
+        for k in range(3):
+            err = _rel(u[k], ref[k])
+            merr = np.max(np.abs(u[k] - ref[k])) / np.max(np.abs(ref[k]))
+            print(f"c4 Stokes every node precision={prec} component {k}: rel l2 {err:.3e}, max {merr:.3e}",
+                  flush=True)
+            assert err < tol and merr < mtol, (prec, k, err, merr)
+    g.close()

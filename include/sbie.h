@@ -207,6 +207,24 @@ sbie_status sbie_eval_targets(sbie_geom* g, sbie_op op, sbie_precision prec, con
                               int64_t npts, const double* pts, double* val, double* grad, void* stream,
                               uint32_t flags);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid allocation):
+   sbie_eval_targets with its work buffers (target coordinates, near masks,
+   near values, far partials) in a static device array of
+   SBIE_TARGETS_SCRATCH_BYTES on each GPU, held until the process ends; the
+   call allocates nothing.  density, pts, val and grad are device pointers
+   (SBIE_DEVICE_PTRS is required); the results equal sbie_eval_targets's (the
+   same kernels in the same order).  The call returns after completion.  Every
+   call on one GPU shares that GPU's array: calls that overlap on one GPU (from
+   several threads or streams) race.  Errors as sbie_eval_targets, plus
+   SBIE_E_INVALID without SBIE_DEVICE_PTRS and SBIE_E_BUDGET when the work
+   buffers for npts points on this geometry exceed the array (about
+   (56 + 4 ceil(M/32)) bytes per point plus up to 34 MB of far partials). */
+#define SBIE_TARGETS_SCRATCH_BYTES (64u << 20)
+sbie_status sbie_eval_targets_noalloc(sbie_geom* g, sbie_op op, sbie_precision prec, const double* density,
+                                      int64_t npts, const double* pts, double* val, double* grad, void* stream,
+                                      uint32_t flags);
+
 /* ---------------------------------------------------------------- completed double-layer solve
 
    The exterior Dirichlet problem of Section 5.1 in the completed double-layer

@@ -37,7 +37,9 @@ EXPORTS = [
     "sbie_session_close", "sbie_wait", "sbie_server_get_info", "sbie_status_str", "sbie_last_error",
     "sbie_completion_eta", "sbie_apply_completed", "sbie_solve_completed", "sbie_solve_neumann",
     "sbie_eval_targets", "sbie_geom_far_tree", "sbie_geom_far_tree_info", "sbie_far_tree_plan",
+    "sbie_eval_targets_noalloc",
 ]
+SBIE_TARGETS_SCRATCH_BYTES = 64 << 20
 SBIE_COMPLETE_POINT, SBIE_COMPLETE_SINGLE = 0, 1
 SBIE_SERVER_GRAPHS = 0x100
 SBIE_MAX_PASS = 8
@@ -142,6 +144,8 @@ def lib() -> ctypes.CDLL:
                                          ctypes.c_uint32]
         L.sbie_eval_targets.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int64, vp, vp, vp, vp,
                                         ctypes.c_uint32]
+        L.sbie_eval_targets_noalloc.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int64, vp, vp, vp,
+                                                vp, ctypes.c_uint32]
         L.sbie_geom_far_tree.argtypes = [vp, ctypes.c_double, ctypes.c_int32, ctypes.c_int32]
         L.sbie_geom_far_tree_info.argtypes = [vp, ctypes.POINTER(TreeInfo)]
         i64p = ctypes.POINTER(ctypes.c_int64)
@@ -381,6 +385,29 @@ class Geometry:
         _check(lib().sbie_eval_targets(self._h, int(op), int(precision), density.data_ptr(), n, pts.data_ptr(),
                                        val.data_ptr(), grad.data_ptr() if gradient else None, None,
                                        SBIE_DEVICE_PTRS))
+        return val, grad
+
+    def eval_targets_noalloc(self, op: int, density, pts, val, grad=None, precision: int = SBIE_FP64, stream=None):
+        """sbie_eval_targets_noalloc: as eval_targets on torch CUDA float64 tensors, into
+        the caller's val [n] and grad [n, 3] (or None), with the library's static
+        work space instead of allocations."""
+        import torch
+
+        for name, t in (("density", density), ("pts", pts), ("val", val)) + ((("grad", grad),) if grad is not None
+                                                                          else ()):
+            if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous float64 CUDA tensor")
+        n = pts.shape[0]
+        if density.numel() != self.N or pts.dim() != 2 or pts.shape[1] != 3 or val.numel() != n or (
+                grad is not None and grad.numel() != 3 * n):
+            raise ValueError("density [N], pts [n, 3], val [n] and grad [n, 3] expected")
+        if stream is None:
+            torch.cuda.current_stream(pts.device).synchronize()
+        _check(lib().sbie_eval_targets_noalloc(self._h, int(op), int(precision), density.data_ptr(), n,
+                                               pts.data_ptr(), val.data_ptr(),
+                                               grad.data_ptr() if grad is not None else None,
+                                               ctypes.c_void_p(stream.cuda_stream) if stream is not None else None,
+                                               SBIE_DEVICE_PTRS))
         return val, grad
 
     def solve_neumann(self, data, tol: float = 1e-10, maxit: int = 500, precision: int = SBIE_FP64):

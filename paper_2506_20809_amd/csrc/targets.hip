@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "far_dev.h"
@@ -296,39 +297,70 @@ void launch_near_targets(const sbie_geom* g, const double* tx, const double* ty,
                      g->excl_words, g->M, g->d_E, g->d_lam, g->d_ab, g->d_cd, g->d_rcp, g->p, g->d_status, out);
 }
 
-// S or D at n device points [n][3] into val [n] and, if non-NULL, grad [n][3].
+// Work buffers of one evaluation at n points: target coordinates (SoA),
+// per-target near masks, near values and gradients, far partials per split.
+struct TargetWork {
+  double* xyz = nullptr;    // [3][n]
+  uint32_t* mask = nullptr; // [n][words]
+  double* nearv = nullptr;  // [4][n]
+  double* partial = nullptr;  // [nsplit][4][n]
+};
+
+int target_splits(const sbie_geom* g, int64_t n) {
+  const int64_t tiles = (n + 511) / 512;
+  return (int)std::min<int64_t>({(int64_t)g->M, 64, std::max<int64_t>(1, (2048 + tiles - 1) / tiles)});
+}
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Bytes of the work buffers, each 256-byte aligned, as carved by carve_work.
+size_t target_work_bytes(const sbie_geom* g, int64_t n) {
+  const size_t un = (size_t)n;
+  return align256(sizeof(double) * 3 * un) + align256(sizeof(uint32_t) * un * g->excl_words) +
+         align256(sizeof(double) * 4 * un) + align256(sizeof(double) * 4 * (size_t)target_splits(g, n) * un);
+}
+
+TargetWork carve_work(const sbie_geom* g, int64_t n, char* base) {
+  const size_t un = (size_t)n;
+  TargetWork w;
+  w.xyz = reinterpret_cast<double*>(base);
+  base += align256(sizeof(double) * 3 * un);
+  w.mask = reinterpret_cast<uint32_t*>(base);
+  base += align256(sizeof(uint32_t) * un * g->excl_words);
+  w.nearv = reinterpret_cast<double*>(base);
+  base += align256(sizeof(double) * 4 * un);
+  w.partial = reinterpret_cast<double*>(base);
+  return w;
+}
+
+// S or D at n device points [n][3] into val [n] and, if non-NULL, grad [n][3],
+// with the work buffers w.  Every work buffer is written before it is read.
 sbie_status eval_targets(sbie_geom* g, int op, int prec, const double* d_dens, int64_t n, const double* d_pts,
-                         double* d_val, double* d_grad, hipStream_t s) {
+                         double* d_val, double* d_grad, const TargetWork& w, hipStream_t s) {
   const int nop = op == SBIE_OP_S ? SBIE_OP_SP : SBIE_OP_DP;  // records and exterior coefficients of S / D
   sbie_status st = normal_records(g, nop, prec, d_dens, s);
   if (st) return st;
   if ((st = normal_expansions(g, nop, prec, s))) return st;
   const int words = g->excl_words;
-  const int64_t tiles = (n + 511) / 512;
-  const int nsplit = (int)std::min<int64_t>({(int64_t)g->M, 64, std::max<int64_t>(1, (2048 + tiles - 1) / tiles)});
-  DevMem xyz, mask, nearv, partial;
-  if ((st = dev_alloc(xyz, sizeof(double) * 3 * (size_t)n))) return st;
-  if ((st = dev_alloc(mask, sizeof(uint32_t) * (size_t)n * words))) return st;
-  if ((st = dev_alloc(nearv, sizeof(double) * 4 * (size_t)n))) return st;
-  if ((st = dev_alloc(partial, sizeof(double) * 4 * (size_t)nsplit * n))) return st;
-  double* tx = (double*)xyz.p;
+  const int nsplit = target_splits(g, n);
+  double* tx = w.xyz;
   double* ty = tx + n;
   double* tz = ty + n;
   hipLaunchKernelGGL(k_targets_soa, dim3(cdiv(n, 256)), dim3(256), 0, s, d_pts, n, tx, ty, tz);
   SBIE_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_classify_targets, dim3(cdiv(n, 256)), dim3(256), 0, s, g->d_part, g->M, words, g->eta, tx,
-                     ty, tz, n, (uint32_t*)mask.p, g->d_status);
+                     ty, tz, n, w.mask, g->d_status);
   SBIE_HIP(hipGetLastError());
   if (g->p <= 8)
-    launch_near_targets<8>(g, tx, ty, tz, n, (const uint32_t*)mask.p, (double*)nearv.p, s);
+    launch_near_targets<8>(g, tx, ty, tz, n, w.mask, w.nearv, s);
   else if (g->p <= 16)
-    launch_near_targets<16>(g, tx, ty, tz, n, (const uint32_t*)mask.p, (double*)nearv.p, s);
+    launch_near_targets<16>(g, tx, ty, tz, n, w.mask, w.nearv, s);
   else
-    launch_near_targets<32>(g, tx, ty, tz, n, (const uint32_t*)mask.p, (double*)nearv.p, s);
+    launch_near_targets<32>(g, tx, ty, tz, n, w.mask, w.nearv, s);
   SBIE_HIP(hipGetLastError());
   const bool mixed = prec == SBIE_MIXED;
-  const uint32_t* mk = (const uint32_t*)mask.p;
-  double* pa = (double*)partial.p;
+  const uint32_t* mk = w.mask;
+  double* pa = w.partial;
   if (op == SBIE_OP_S)
     mixed ? launch_far_targets<float, SBIE_OP_S>(g, tx, ty, tz, n, mk, nsplit, pa, s)
           : launch_far_targets<double, SBIE_OP_S>(g, tx, ty, tz, n, mk, nsplit, pa, s);
@@ -336,11 +368,35 @@ sbie_status eval_targets(sbie_geom* g, int op, int prec, const double* d_dens, i
     mixed ? launch_far_targets<float, SBIE_OP_D>(g, tx, ty, tz, n, mk, nsplit, pa, s)
           : launch_far_targets<double, SBIE_OP_D>(g, tx, ty, tz, n, mk, nsplit, pa, s);
   SBIE_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_targets_combine, dim3(cdiv(n, 256)), dim3(256), 0, s, (const double*)nearv.p, pa, nsplit, n,
+  hipLaunchKernelGGL(k_targets_combine, dim3(cdiv(n, 256)), dim3(256), 0, s, (const double*)w.nearv, pa, nsplit, n,
                      d_val, d_grad);
   SBIE_HIP(hipGetLastError());
-  // the work buffers are freed on return
-  SBIE_HIP(hipStreamSynchronize(s));
+  return SBIE_OK;
+}
+
+// Allocation-free variant's work space: one array per GPU, in device memory
+// for the life of the process.  In host code `scratch` names a host-side
+// stand-in; its device address comes from hipGetSymbolAddress, once per
+// device, and only that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[SBIE_TARGETS_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+sbie_status scratch_address(int device, char** out) {
+  if (device < 0 || device >= kMaxDevices) {
+    set_error("device ordinal out of range for the static work space");
+    return SBIE_E_INVALID;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return device_error(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[device] = static_cast<char*>(ptr);
+  }
+  *out = g_scratch_ptr[device];
   return SBIE_OK;
 }
 
@@ -394,11 +450,63 @@ extern "C" sbie_status sbie_eval_targets(sbie_geom* g, sbie_op op, sbie_precisio
     dv = b + N + 3 * npts;
     dg = grad ? b + N + 4 * npts : nullptr;
   }
-  if ((st = eval_targets(g, (int)op, (int)prec, dd, npts, dp, dv, dg, s))) return st;
+  DevMem work;
+  if ((st = dev_alloc(work, target_work_bytes(g, npts)))) return st;
+  st = eval_targets(g, (int)op, (int)prec, dd, npts, dp, dv, dg, carve_work(g, npts, (char*)work.p), s);
+  if (st) {
+    (void)hipStreamSynchronize(s);  // queued work may still use the buffers freed on return
+    return st;
+  }
+  // the work buffers are freed on return
+  SBIE_HIP(hipStreamSynchronize(s));
   if (!devptr) {
     SBIE_HIP(hipMemcpyAsync(val, dv, sizeof(double) * npts, hipMemcpyDeviceToHost, s));
     if (grad) SBIE_HIP(hipMemcpyAsync(grad, dg, sizeof(double) * 3 * npts, hipMemcpyDeviceToHost, s));
     SBIE_HIP(hipStreamSynchronize(s));
   }
+  return sbie_geom_sync(g, s);
+}
+
+extern "C" sbie_status sbie_eval_targets_noalloc(sbie_geom* g, sbie_op op, sbie_precision prec,
+                                                 const double* density, int64_t npts, const double* pts,
+                                                 double* val, double* grad, void* stream, uint32_t flags) {
+  if (!g) {
+    set_error("geometry is NULL");
+    return SBIE_E_INVALID;
+  }
+  if (op != SBIE_OP_S && op != SBIE_OP_D) {
+    set_error("target evaluation takes SBIE_OP_S or SBIE_OP_D");
+    return SBIE_E_INVALID;
+  }
+  if (prec != SBIE_FP64 && prec != SBIE_MIXED) {
+    set_error("unknown precision");
+    return SBIE_E_INVALID;
+  }
+  if (!(flags & SBIE_DEVICE_PTRS)) {
+    set_error("the allocation-free evaluation takes device pointers only (SBIE_DEVICE_PTRS)");
+    return SBIE_E_INVALID;
+  }
+  if (npts < 0 || npts > ((int64_t)1 << 31)) {
+    set_error("npts must be in [0, 2^31]");
+    return SBIE_E_INVALID;
+  }
+  if (npts == 0) return SBIE_OK;
+  if (!density || !pts || !val) {
+    set_error("density, pts or val is NULL");
+    return SBIE_E_INVALID;
+  }
+  const size_t need = target_work_bytes(g, npts);
+  if (need > (size_t)SBIE_TARGETS_SCRATCH_BYTES) {
+    set_error("the work buffers for " + std::to_string(npts) + " points need " + std::to_string(need) +
+              " bytes, more than the static work space of " + std::to_string((size_t)SBIE_TARGETS_SCRATCH_BYTES));
+    return SBIE_E_BUDGET;
+  }
+  SBIE_HIP(hipSetDevice(g->ctx->device));
+  char* ws = nullptr;
+  sbie_status st = scratch_address(g->ctx->device, &ws);
+  if (st) return st;
+  hipStream_t s = stream ? (hipStream_t)stream : g->ctx->stream;
+  st = eval_targets(g, (int)op, (int)prec, density, npts, pts, val, grad, carve_work(g, npts, ws), s);
+  if (st) return st;
   return sbie_geom_sync(g, s);
 }

@@ -75,6 +75,15 @@ void plain_path() {
     check(sbie_apply(g, SBIE_OP_STOKES_S, SBIE_FP64, 3, dens.data(), out.data(), nullptr, 0), "sbie_apply stokes");
     std::vector<double> xyz(3 * N), nrm(3 * N), w(N);
     check(sbie_geom_nodes(g, xyz.data(), nrm.data(), w.data()), "sbie_geom_nodes");
+    // targets: the allocating call with host pointers, the allocation-free one
+    // with "device" pointers (host memory under the stand-in), twice
+    std::vector<double> pts = {0.0, 0.0, 9.0, 2.0, -8.0, 1.0, 30.0, 0.5, 0.5}, val(3), grad(9);
+    check(sbie_eval_targets(g, SBIE_OP_S, SBIE_FP64, dens.data(), 3, pts.data(), val.data(), grad.data(), nullptr, 0),
+          "sbie_eval_targets");
+    for (int64_t n : {3, 2})
+      check(sbie_eval_targets_noalloc(g, SBIE_OP_D, SBIE_MIXED, dens.data(), n, pts.data(), val.data(), grad.data(),
+                                      nullptr, SBIE_DEVICE_PTRS),
+            "sbie_eval_targets_noalloc");
     sbie_geom_destroy(g);
   }
   sbie_ctx_destroy(ctx);

@@ -188,13 +188,19 @@ __global__ void k_scale_coef(const double* __restrict__ coef, const double* __re
 // from a depth where it has converged to double precision); higher orders
 // follow from the recurrence in the order at fixed degree, and every column
 // Q_n^m, n = m..N+1, from the backward recurrence in n.  All in FP64.
-template <int PMAX>
+//
+// With EXACT the order is PMAX itself (p_arg is ignored): every comparison of
+// a degree with p and N = p+1 is then settled at compile time, which keeps the
+// unrolled loops free of runtime predicates (otherwise held, and spilled, as
+// scalar masks).
+template <int PMAX, bool EXACT>
 __global__ __launch_bounds__(64) void k_near_f64(
     const Particle* __restrict__ part, const double* __restrict__ x, const double* __restrict__ y,
     const double* __restrict__ z, const int32_t* __restrict__ near_ptr,
     const int32_t* __restrict__ near_src, const double* __restrict__ E,
-    const double* __restrict__ lam, const double* __restrict__ ab, const double* __restrict__ rcp, int p,
+    const double* __restrict__ lam, const double* __restrict__ ab, const double* __restrict__ rcp, int p_arg,
     int T, int chunks, int64_t Nn, unsigned* status, double* __restrict__ unear) {
+  const int p = EXACT ? PMAX : p_arg;
   const int q4 = blockIdx.x % kNearSplit, rest = blockIdx.x / kNearSplit;
   const int j = rest / chunks;
   const int t = (rest - j * chunks) * 64 + threadIdx.x;
@@ -202,6 +208,15 @@ __global__ __launch_bounds__(64) void k_near_f64(
   const int64_t g = (int64_t)j * T + (live ? t : 0);
   const double X0 = x[g], X1 = y[g], X2 = z[g];
   const int K = (p + 1) * (p + 1), Kh = (p + 1) * (p + 2) / 2, N = p + 1;
+  // Tables read with wave-uniform addresses, staged in LDS so that they stay
+  // out of the scalar registers: the Ferrers recurrence table and 1/k (once),
+  // each source's exterior coefficients and spectral ratios 1/Q_n^m(u0).
+  constexpr int KM = (PMAX + 1) * (PMAX + 1), KHM = (PMAX + 1) * (PMAX + 2) / 2;
+  constexpr int KH2M = (PMAX + 2) * (PMAX + 3) / 2, RM = 2 * PMAX + 8;
+  __shared__ double s_E[KM], s_L[KHM], s_ab[2 * KH2M], s_rcp[RM];
+  const int Kh2 = (p + 2) * (p + 3) / 2;
+  for (int k = threadIdx.x; k < 2 * Kh2; k += 64) s_ab[k] = ab[k];
+  for (int k = threadIdx.x; k < RM; k += 64) s_rcp[k] = rcp[k];
   double acc = 0.0;
   unsigned bad = 0u;
   const int n0 = near_ptr[j], nn = near_ptr[j + 1] - n0;
@@ -209,8 +224,11 @@ __global__ __launch_bounds__(64) void k_near_f64(
   for (int s = s_begin; s < s_end; ++s) {
     const int i = near_src[s];
     const Particle P = part[i];
-    const double* Ei = E + (size_t)i * K;
-    const double* Li = lam + (size_t)i * Kh * 4;
+    __syncthreads();  // the previous source's tables have been read
+    for (int k = threadIdx.x; k < K; k += 64) s_E[k] = E[(size_t)i * K + k];
+    for (int k = threadIdx.x; k < Kh; k += 64) s_L[k] = lam[((size_t)i * Kh + k) * 4 + 3];
+    __syncthreads();
+    const double* Ei = s_E;
     // lab -> body frame of the source
     const double d0 = X0 - P.c[0], d1 = X1 - P.c[1], d2 = X2 - P.c[2];
     const double b0 = P.R[0] * d0 + P.R[3] * d1 + P.R[6] * d2;
@@ -244,14 +262,15 @@ __global__ __launch_bounds__(64) void k_near_f64(
     // Q_N^m, Q_{N+1}^m: orders 0 and 1 from the backward recurrence and the
     // Casoratian, higher orders by the upward recurrence in m
     double qn0[2], qn1[2];
-    q_top_orders01(u, sw, sgn, N, L, rcp, qn0, qn1);
+    q_top_orders01(u, sw, sgn, N, L, s_rcp, qn0, qn1);
     const double ur = u / sw;
     double fa2 = 0.0, fa1 = 0.0, fb2 = 0.0, fb1 = 0.0;  // F^(m-2), F^(m-1) at degrees N and N+1
     double pbar = 0.28209479177387814347;  // normalised Ferrers Pb_m^m(v), 1/sqrt(4 pi) at m = 0
     double cm = 1.0, sm = 0.0;             // cos(m phi), sin(m phi)
+#pragma unroll 1
     for (int m = 0; m <= p; ++m) {
       if (m > 0) {
-        pbar *= sqrt((2.0 * m + 1.0) / (2.0 * m)) * sv;
+        pbar *= s_ab[m * (m + 3)] * sv;  // sqrt((2m+1)/(2m)), row n = m
         const double cn = cm * c1 - sm * s1;
         sm = sm * c1 + cm * s1;
         cm = cn;
@@ -263,7 +282,7 @@ __global__ __launch_bounds__(64) void k_near_f64(
       fb2 = fb1;
       fb1 = qN1;
       double Q[PMAX + 4];
-      q_column<PMAX>(u, sgn, N, m, qN, qN1, rcp, Q);
+      q_column<PMAX>(u, sgn, N, m, qN, qN1, s_rcp, Q);
       // contraction with the normalised Ferrers functions, forward in n
       double sc = 0.0, ss = 0.0;
       double p2 = 0.0, p1 = pbar;
@@ -274,16 +293,16 @@ __global__ __launch_bounds__(64) void k_near_f64(
           if (n == m) {
             pn = pbar;
           } else if (n == m + 1) {
-            pn = sqrt(2.0 * m + 3.0) * v * pbar;
+            pn = s_ab[(m + 1) * (m + 2) + 2 * m] * v * pbar;  // sqrt(2m+3), row n = m+1
             p2 = p1;
             p1 = pn;
           } else {
             const int h = n * (n + 1) / 2 + m;
-            pn = ab[2 * h] * (v * p1 - ab[2 * h + 1] * p2);
+            pn = s_ab[2 * h] * (v * p1 - s_ab[2 * h + 1] * p2);
             p2 = p1;
             p1 = pn;
           }
-          const double qr = Q[n] * Li[(n * (n + 1) / 2 + m) * 4 + 3];
+          const double qr = Q[n] * s_L[n * (n + 1) / 2 + m];
           const double t0 = pn * qr;
           sc = fma(Ei[n * n + n + m], t0, sc);
           if (m > 0) ss = fma(Ei[n * n + n - m], t0, ss);
@@ -429,10 +448,10 @@ sbie_status launch_gemm32(const double* A, int lda, const float* B, int ldb, dou
   return SBIE_OK;
 }
 
-template <int PMAX>
+template <int PMAX, bool EXACT>
 void launch_near(sbie_geom* g, hipStream_t s) {
   const int chunks = (g->T + 63) / 64;
-  hipLaunchKernelGGL(k_near_f64<PMAX>, dim3(g->M * chunks * kNearSplit), dim3(64), 0, s, g->d_part, g->d_x,
+  hipLaunchKernelGGL((k_near_f64<PMAX, EXACT>), dim3(g->M * chunks * kNearSplit), dim3(64), 0, s, g->d_part, g->d_x,
                      g->d_y, g->d_z, g->d_near_ptr, g->d_near_src, g->d_E, g->d_lam, g->d_ab, g->d_rcp, g->p, g->T,
                      chunks, g->N, g->d_status, g->d_unear);
 }
@@ -521,12 +540,7 @@ sbie_status apply_laplace(sbie_geom* g, int op, int prec, const double* d_dens, 
   const bool near = (parts & SBIE_PARTS_NEAR) && g->n_near > 0;
   if (near) {
     if (timed) SBIE_HIP(hipEventRecord(ev[6], s));
-    if (p <= 8)
-      launch_near<8>(g, s);
-    else if (p <= 16)
-      launch_near<16>(g, s);
-    else
-      launch_near<32>(g, s);
+    dispatch_order(p, [&](auto pm, auto ex) { launch_near<decltype(pm)::value, decltype(ex)::value>(g, s); });
     SBIE_HIP(hipGetLastError());
     if (timed) SBIE_HIP(hipEventRecord(ev[7], s));
   } else if (timed) {

@@ -82,14 +82,15 @@ __global__ void k_normal_scale(const double* __restrict__ coef, const double* __
 // near-source list); every near source's exterior expansion is differentiated
 // in (u, v, phi) at the mapped target and its lab gradient is projected on the
 // target's normal.
-template <int PMAX>
+template <int PMAX, bool EXACT>
 __global__ __launch_bounds__(64) void k_near_normal(
     const Particle* __restrict__ part, const double* __restrict__ x, const double* __restrict__ y,
     const double* __restrict__ z, const double* __restrict__ nx, const double* __restrict__ ny,
     const double* __restrict__ nz, const int32_t* __restrict__ near_ptr, const int32_t* __restrict__ near_src,
     const double* __restrict__ E, const double* __restrict__ lam, const double* __restrict__ ab,
-    const double* __restrict__ cd, const double* __restrict__ rcp, int p, int T, int chunks, int64_t Nn,
+    const double* __restrict__ cd, const double* __restrict__ rcp, int p_arg, int T, int chunks, int64_t Nn,
     unsigned* status, double* __restrict__ unear) {
+  const int p = EXACT ? PMAX : p_arg;  // exact order: degree bounds known at compile time
   const int q4 = blockIdx.x % kNearSplit, rest = blockIdx.x / kNearSplit;
   const int j = rest / chunks;
   const int t = (rest - j * chunks) * 64 + threadIdx.x;
@@ -224,10 +225,10 @@ __global__ void k_normal_assemble(const double* __restrict__ uself, const double
   out[g] = u;
 }
 
-template <int PMAX>
+template <int PMAX, bool EXACT>
 void launch_near_normal(sbie_geom* g, hipStream_t s) {
   const int chunks = (g->T + 63) / 64;
-  hipLaunchKernelGGL(k_near_normal<PMAX>, dim3(g->M * chunks * kNearSplit), dim3(64), 0, s, g->d_part, g->d_x,
+  hipLaunchKernelGGL((k_near_normal<PMAX, EXACT>), dim3(g->M * chunks * kNearSplit), dim3(64), 0, s, g->d_part, g->d_x,
                      g->d_y, g->d_z, g->d_nx, g->d_ny, g->d_nz, g->d_near_ptr, g->d_near_src, g->d_E, g->d_lam,
                      g->d_ab, g->d_cd, g->d_rcp, g->p, g->T, chunks, g->N, g->d_status, g->d_unear);
 }
@@ -295,12 +296,7 @@ sbie_status apply_normal(sbie_geom* g, int op, int prec, const double* d_dens, d
   if (timed) SBIE_HIP(hipEventRecord(ev[2], s));
   if (timed) SBIE_HIP(hipEventRecord(ev[6], s));
   if ((parts & SBIE_PARTS_NEAR) && g->n_near > 0) {
-    if (p <= 8)
-      launch_near_normal<8>(g, s);
-    else if (p <= 16)
-      launch_near_normal<16>(g, s);
-    else
-      launch_near_normal<32>(g, s);
+    dispatch_order(p, [&](auto pm, auto ex) { launch_near_normal<decltype(pm)::value, decltype(ex)::value>(g, s); });
     SBIE_HIP(hipGetLastError());
   }
   if (timed) SBIE_HIP(hipEventRecord(ev[7], s));

@@ -193,9 +193,10 @@ __device__ inline void expansion_derivatives(const SpheroidalPoint& q, bool obla
   const double ur = u / q.sw;
   double fa2 = 0.0, fa1 = 0.0, fb2 = 0.0, fb1 = 0.0;
   double pbar = 0.28209479177387814347, cm = 1.0, sm = 0.0;
+#pragma unroll 1
   for (int m = 0; m <= p; ++m) {
     if (m > 0) {
-      pbar *= sqrt((2.0 * m + 1.0) / (2.0 * m)) * q.sv;
+      pbar *= ab[m * (m + 3)] * q.sv;  // sqrt((2m+1)/(2m)), row n = m of the table
       const double cn = cm * q.c1 - sm * q.s1;
       sm = sm * q.c1 + cm * q.s1;
       cm = cn;
@@ -220,7 +221,7 @@ __device__ inline void expansion_derivatives(const SpheroidalPoint& q, bool obla
         const int h = n * (n + 1) / 2 + m;
         double pn1;
         if (n == m) {
-          pn1 = sqrt(2.0 * m + 3.0) * v * pbar;
+          pn1 = ab[(m + 1) * (m + 2) + 2 * m] * v * pbar;  // sqrt(2m+3), row n = m+1
         } else {
           const int h1 = (n + 1) * (n + 2) / 2 + m;
           pn1 = ab[2 * h1] * (v * pn - ab[2 * h1 + 1] * pm1);

@@ -1,6 +1,8 @@
 // Internal declarations of the HIP library behind include/sbie.h.
 #pragma once
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -34,6 +36,24 @@ struct Particle {
 // consecutive ranges, one wave each, whose partial sums the assembly adds in
 // range order (balances particles with many and few neighbours).
 constexpr int kNearSplit = 4;
+// The Stokes near kernels (four or thirteen expansions per source, many
+// registers, few waves otherwise) split each list eight ways.
+constexpr int kStokesNearSplit = 8;
+
+// Order dispatch of the near-field kernels: the orders 8, 12, 16 and 32 get
+// kernels of their exact order (f(PMAX, true)), whose degree loops then carry
+// no runtime bounds; other orders the next larger of 8, 16, 32 (f(PMAX, false)).
+template <typename F>
+inline void dispatch_order(int p, F&& f) {
+  using std::integral_constant;
+  if (p == 8) f(integral_constant<int, 8>{}, std::true_type{});
+  else if (p == 12) f(integral_constant<int, 12>{}, std::true_type{});
+  else if (p == 16) f(integral_constant<int, 16>{}, std::true_type{});
+  else if (p == 32) f(integral_constant<int, 32>{}, std::true_type{});
+  else if (p < 8) f(integral_constant<int, 8>{}, std::false_type{});
+  else if (p < 16) f(integral_constant<int, 16>{}, std::false_type{});
+  else f(integral_constant<int, 32>{}, std::false_type{});
+}
 
 // Status word written by kernels (bit flags).
 enum : unsigned { kStatNumeric = 1u, kStatOverlap = 2u, kStatExterior = 4u };
@@ -135,7 +155,7 @@ struct sbie_geom {
   double* d_stk_src = nullptr;    // [N][8] far-field records / [nsplit][3][N] partials follow
   double* d_stk_part = nullptr;   // [nsplit][4][N] (velocity and pressure)
   double* d_stk_self = nullptr;   // [4][N]
-  double* d_stk_near = nullptr;   // [4][N]
+  double* d_stk_near = nullptr;   // [kStokesNearSplit][4][N] near partials per source-list range
   double* d_stk_io = nullptr;     // [7][N] staging of host densities and velocities
   // Stokes double layer (stokes_dl.hip), in its own block carved on first use
   char* sdl_blk = nullptr;
@@ -146,7 +166,7 @@ struct sbie_geom {
   double* d_sdl_src = nullptr;    // [N][8] far records (node - centre, W mu, nu_x, nu_y)
   double* d_sdl_part = nullptr;   // [nsplit][3][N]
   double* d_sdl_self = nullptr;   // [3][N]
-  double* d_sdl_near = nullptr;   // [3][N]
+  double* d_sdl_near = nullptr;   // [kStokesNearSplit][3][N] near partials per source-list range
   double* d_sdl_io = nullptr;     // [6][N] host staging
   double* d_wS = nullptr;         // [M][p+1] sqrt(u0^2 -+ v_j^2)
   double* d_lam = nullptr;        // [M][Kh][4]: D principal value, D exterior, S, 1/Q_n^m(z0)

@@ -494,11 +494,17 @@ sbie_status setup_geometry(sbie_geom* g, hipStream_t s) {
   std::vector<double>& gl = h.gl;
   gl.assign(2 * (p + 1), 0.0);
   gauss_legendre_host(p + 1, gl.data(), gl.data() + p + 1);
-  // normalised Ferrers recurrence coefficients a_nm, b_nm for n >= m+2
+  // normalised Ferrers recurrence coefficients a_nm, b_nm for n >= m+2; in
+  // the first slot of the otherwise unused rows n = m and n = m+1 the seeds
+  // Pb_m^m = sqrt((2m+1)/(2m)) sqrt(1-v^2) Pb_{m-1}^{m-1} (m >= 1) and
+  // Pb_{m+1}^m = sqrt(2m+3) v Pb_m^m
   std::vector<double>& ab = h.ab;
   ab.assign(2 * Kh2, 0.0);
   for (int n = 0; n <= p + 1; ++n)
     for (int m = 0; m <= n; ++m) {
+      const size_t hh = (size_t)n * (n + 1) / 2 + m;
+      if (n == m && m > 0) ab[2 * hh] = std::sqrt((2.0 * m + 1.0) / (2.0 * m));
+      if (n == m + 1) ab[2 * hh] = std::sqrt(2.0 * m + 3.0);
       if (n < m + 2) continue;
       const double h = n * (n + 1) / 2 + m;
       ab[2 * (size_t)h] = std::sqrt((4.0 * n * n - 1.0) / ((double)n * n - (double)m * m));

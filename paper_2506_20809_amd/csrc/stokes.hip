@@ -132,15 +132,18 @@ __global__ void k_stokes_self(const Particle* __restrict__ part, const double* _
 // come from the same division-free backward recurrence as the Laplace near
 // field, and the four expansions are summed with their u, v and phi
 // derivatives.
-template <int PMAX, int C>
+template <int PMAX, bool EXACT, int C>
 __global__ __launch_bounds__(64) void k_near_stokes(
     const Particle* __restrict__ part, const double* __restrict__ x, const double* __restrict__ y,
     const double* __restrict__ z, const int32_t* __restrict__ near_ptr, const int32_t* __restrict__ near_src,
     const double* __restrict__ E, const double* __restrict__ lam, const double* __restrict__ ab,
-    const double* __restrict__ cd, const double* __restrict__ rcp, int p, int T, int chunks, int64_t N,
+    const double* __restrict__ cd, const double* __restrict__ rcp, int p_arg, int T, int chunks, int64_t N,
     unsigned* status, double* __restrict__ unear) {
-  const int j = blockIdx.x / chunks;
-  const int t = (blockIdx.x - j * chunks) * 64 + threadIdx.x;
+  const int p = EXACT ? PMAX : p_arg;  // exact order: degree bounds known at compile time
+  // one wave per (target particle, 64 targets, range q of its near-source list)
+  const int q = blockIdx.x % kStokesNearSplit, rest = blockIdx.x / kStokesNearSplit;
+  const int j = rest / chunks;
+  const int t = (rest - j * chunks) * 64 + threadIdx.x;
   const bool live = t < T;
   const int64_t g = (int64_t)j * T + (live ? t : 0);
   const double X0 = x[g], X1 = y[g], X2 = z[g];
@@ -149,22 +152,24 @@ __global__ __launch_bounds__(64) void k_near_stokes(
 #pragma unroll
   for (int c = 0; c < C; ++c) acc[c] = 0.0;
   unsigned bad = 0u;
-  for (int sidx = near_ptr[j]; sidx < near_ptr[j + 1]; ++sidx) {
+  const int n0 = near_ptr[j], nn = near_ptr[j + 1] - n0;
+  const int s_begin = n0 + (nn * q) / kStokesNearSplit, s_end = n0 + (nn * (q + 1)) / kStokesNearSplit;
+  for (int sidx = s_begin; sidx < s_end; ++sidx) {
     const int i = near_src[sidx];
     const Particle P = part[i];
-    const SpheroidalPoint q = to_spheroidal(P, X0, X1, X2, true, &bad);
+    const SpheroidalPoint sp = to_spheroidal(P, X0, X1, X2, true, &bad);
     double Phi[4], Pu[4], Pv[4], Pp[4];
-    expansion_derivatives<PMAX, 4>(q, P.oblate != 0, E + (size_t)i * 4 * K, (size_t)K, lam + (size_t)i * Kh * 4,
+    expansion_derivatives<PMAX, 4>(sp, P.oblate != 0, E + (size_t)i * 4 * K, (size_t)K, lam + (size_t)i * Kh * 4,
                                    ab, cd, rcp, p, &bad, Phi, Pu, Pv, Pp);
     double o[C];
-    stokes_from_derivatives<C>(P, q.u, q.sw, q.v, q.sv, q.c1, q.s1, Phi, Pu, Pv, Pp, q.d, o);
+    stokes_from_derivatives<C>(P, sp.u, sp.sw, sp.v, sp.sv, sp.c1, sp.s1, Phi, Pu, Pv, Pp, sp.d, o);
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] += o[c];
   }
   if (bad) atomicOr(status, bad);
   if (live) {
 #pragma unroll
-    for (int c = 0; c < C; ++c) unear[c * N + g] = acc[c];
+    for (int c = 0; c < C; ++c) unear[((size_t)q * C + c) * N + g] = acc[c];
   }
 }
 
@@ -279,7 +284,8 @@ __global__ void k_stokes_assemble(const double* __restrict__ uself, const double
   const int64_t g = t - (int64_t)c * N;
   double u = 0.0;
   if (parts & SBIE_PARTS_SELF) u += uself[t];
-  if (parts & SBIE_PARTS_NEAR) u += unear[t];
+  if (parts & SBIE_PARTS_NEAR)
+    for (int q = 0; q < kStokesNearSplit; ++q) u += unear[(size_t)q * C * N + t];
   if (parts & SBIE_PARTS_FAR) {
     double f = 0.0;
     for (int s = 0; s < nsplit; ++s) f += partial[((size_t)s * C + c) * N + g];
@@ -288,10 +294,10 @@ __global__ void k_stokes_assemble(const double* __restrict__ uself, const double
   out[t] = u;
 }
 
-template <int PMAX, int C>
+template <int PMAX, bool EXACT, int C>
 void launch_near_stokes(sbie_geom* g, hipStream_t s) {
   const int chunks = (g->T + 63) / 64;
-  hipLaunchKernelGGL((k_near_stokes<PMAX, C>), dim3(g->M * chunks), dim3(64), 0, s, g->d_part, g->d_x, g->d_y, g->d_z,
+  hipLaunchKernelGGL((k_near_stokes<PMAX, EXACT, C>), dim3(g->M * chunks * kStokesNearSplit), dim3(64), 0, s, g->d_part, g->d_x, g->d_y, g->d_z,
                      g->d_near_ptr, g->d_near_src, g->d_stk_E, g->d_lam, g->d_ab, g->d_cd, g->d_rcp, g->p, g->T,
                      chunks, g->N, g->d_status, g->d_stk_near);
 }
@@ -315,7 +321,7 @@ sbie_status carve_stokes(sbie_geom* g, Carver& c) {
   // four components: velocity and pressure
   SBIE_TRY_C(c.take(&g->d_stk_part, (size_t)g->nsplit * 4 * N));
   SBIE_TRY_C(c.take(&g->d_stk_self, 4 * N));
-  SBIE_TRY_C(c.take(&g->d_stk_near, 4 * N));
+  SBIE_TRY_C(c.take(&g->d_stk_near, (size_t)kStokesNearSplit * 4 * N));
   SBIE_TRY_C(c.take(&g->d_stk_io, 7 * N));
   return SBIE_OK;
 }
@@ -414,12 +420,7 @@ sbie_status stokes_parts(sbie_geom* g, bool mixed, hipStream_t s, uint32_t parts
     if (fork) SBIE_TRY_C(fork_side(g, s));
     hipStream_t ns = fork ? g->side : s;
     if (timed) SBIE_HIP(hipEventRecord(ev[6], ns));
-    if (p <= 8)
-      launch_near_stokes<8, C>(g, ns);
-    else if (p <= 16)
-      launch_near_stokes<16, C>(g, ns);
-    else
-      launch_near_stokes<32, C>(g, ns);
+    dispatch_order(p, [&](auto pm, auto ex) { launch_near_stokes<decltype(pm)::value, decltype(ex)::value, C>(g, ns); });
     SBIE_HIP(hipGetLastError());
     if (timed) SBIE_HIP(hipEventRecord(ev[7], ns));
   } else if (timed) {

@@ -138,22 +138,27 @@ __global__ void k_sdl_self(const Particle* __restrict__ part, const double* __re
 // Near part: one wave per (target particle, 64 target nodes); the derivative
 // recurrences run once for the four double-layer sets and once for the nine
 // single-layer sets of every near source.
-template <int PMAX>
+template <int PMAX, bool EXACT>
 __global__ __launch_bounds__(64) void k_near_sdl(
     const Particle* __restrict__ part, const double* __restrict__ x, const double* __restrict__ y,
     const double* __restrict__ z, const int32_t* __restrict__ near_ptr, const int32_t* __restrict__ near_src,
     const double* __restrict__ E, const double* __restrict__ lam, const double* __restrict__ ab,
-    const double* __restrict__ cd, const double* __restrict__ rcp, int p, int T, int chunks, int64_t N,
+    const double* __restrict__ cd, const double* __restrict__ rcp, int p_arg, int T, int chunks, int64_t N,
     unsigned* status, double* __restrict__ unear) {
-  const int jt = blockIdx.x / chunks;
-  const int t = (blockIdx.x - jt * chunks) * 64 + threadIdx.x;
+  const int p = EXACT ? PMAX : p_arg;  // exact order: degree bounds known at compile time
+  // one wave per (target particle, 64 targets, range qr of its near-source list)
+  const int qr = blockIdx.x % kStokesNearSplit, rest = blockIdx.x / kStokesNearSplit;
+  const int jt = rest / chunks;
+  const int t = (rest - jt * chunks) * 64 + threadIdx.x;
   const bool live = t < T;
   const int64_t g = (int64_t)jt * T + (live ? t : 0);
   const double X0 = x[g], X1 = y[g], X2 = z[g];
   const int K = (p + 1) * (p + 1), Kh = (p + 1) * (p + 2) / 2;
   double acc[3] = {0.0, 0.0, 0.0};
   unsigned bad = 0u;
-  for (int sidx = near_ptr[jt]; sidx < near_ptr[jt + 1]; ++sidx) {
+  const int n0 = near_ptr[jt], nn = near_ptr[jt + 1] - n0;
+  const int s_begin = n0 + (nn * qr) / kStokesNearSplit, s_end = n0 + (nn * (qr + 1)) / kStokesNearSplit;
+  for (int sidx = s_begin; sidx < s_end; ++sidx) {
     const int i = near_src[sidx];
     const Particle P = part[i];
     const SpheroidalPoint q = to_spheroidal(P, X0, X1, X2, true, &bad);
@@ -181,9 +186,10 @@ __global__ __launch_bounds__(64) void k_near_sdl(
   }
   if (bad) atomicOr(status, bad);
   if (live) {
-    unear[g] = acc[0];
-    unear[N + g] = acc[1];
-    unear[2 * N + g] = acc[2];
+    double* o = unear + (size_t)qr * 3 * N;
+    o[g] = acc[0];
+    o[N + g] = acc[1];
+    o[2 * N + g] = acc[2];
   }
 }
 
@@ -277,7 +283,8 @@ __global__ void k_sdl_assemble(const double* __restrict__ uself, const double* _
   const int64_t g = t - (int64_t)c * N;
   double u = 0.0;
   if (parts & SBIE_PARTS_SELF) u += uself[t];
-  if (parts & SBIE_PARTS_NEAR) u += unear[t];
+  if (parts & SBIE_PARTS_NEAR)
+    for (int q = 0; q < kStokesNearSplit; ++q) u += unear[(size_t)q * 3 * N + t];
   if (parts & SBIE_PARTS_FAR) {
     double f = 0.0;
     for (int s = 0; s < nsplit; ++s) f += partial[((size_t)s * 3 + c) * N + g];
@@ -286,10 +293,10 @@ __global__ void k_sdl_assemble(const double* __restrict__ uself, const double* _
   out[t] = u;
 }
 
-template <int PMAX>
+template <int PMAX, bool EXACT>
 void launch_near_sdl(sbie_geom* g, hipStream_t s) {
   const int chunks = (g->T + 63) / 64;
-  hipLaunchKernelGGL(k_near_sdl<PMAX>, dim3(g->M * chunks), dim3(64), 0, s, g->d_part, g->d_x, g->d_y, g->d_z,
+  hipLaunchKernelGGL((k_near_sdl<PMAX, EXACT>), dim3(g->M * chunks * kStokesNearSplit), dim3(64), 0, s, g->d_part, g->d_x, g->d_y, g->d_z,
                      g->d_near_ptr, g->d_near_src, g->d_sdl_E, g->d_lam, g->d_ab, g->d_cd, g->d_rcp, g->p, g->T,
                      chunks, g->N, g->d_status, g->d_sdl_near);
 }
@@ -310,7 +317,7 @@ sbie_status carve_sdl(sbie_geom* g, Carver& c) {
   SBIE_TRY_D(c.take(&g->d_sdl_src, 8 * N));
   SBIE_TRY_D(c.take(&g->d_sdl_part, (size_t)g->nsplit * 3 * N));
   SBIE_TRY_D(c.take(&g->d_sdl_self, 3 * N));
-  SBIE_TRY_D(c.take(&g->d_sdl_near, 3 * N));
+  SBIE_TRY_D(c.take(&g->d_sdl_near, (size_t)kStokesNearSplit * 3 * N));
   SBIE_TRY_D(c.take(&g->d_sdl_io, 6 * N));
   return SBIE_OK;
 }
@@ -387,12 +394,7 @@ sbie_status apply_stokes_dl(sbie_geom* g, int prec, const double* d_dens, double
   const bool near = (parts & SBIE_PARTS_NEAR) && g->n_near > 0;
   if (timed) SBIE_HIP(hipEventRecord(ev[6], s));
   if (near) {
-    if (p <= 8)
-      launch_near_sdl<8>(g, s);
-    else if (p <= 16)
-      launch_near_sdl<16>(g, s);
-    else
-      launch_near_sdl<32>(g, s);
+    dispatch_order(p, [&](auto pm, auto ex) { launch_near_sdl<decltype(pm)::value, decltype(ex)::value>(g, s); });
     SBIE_HIP(hipGetLastError());
   }
   if (timed) SBIE_HIP(hipEventRecord(ev[7], s));

@@ -45,14 +45,34 @@ def cpu_baseline(geom, p, dens_s, dens_d, N, sample):
     oracle.build(force=False)
     tg = np.linspace(0, N - 1, sample).astype(np.int64)
     t0 = time.perf_counter()
-    oracle.apply_at(geom, p, 0, dens_s, tg)
-    oracle.apply_at(geom, p, 1, dens_d, tg)
+    ref_s = oracle.apply_at(geom, p, 0, dens_s, tg)[0]
+    ref_d = oracle.apply_at(geom, p, 1, dens_d, tg)[0]
     dt = time.perf_counter() - t0
     # one S and one D apply cost N/sample times the sampled work
     applies_per_s = 2.0 / (dt * N / sample)
-    return {"value": applies_per_s, "unit": "applies/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"S and D at {sample} of {N} nodes (evenly spaced), geometry setup included, "
-                      f"{dt:.1f} s, scaled to whole applies"}
+    return ({"value": applies_per_s, "unit": "applies/s", "cores": oracle.num_threads(), "kind": "oracle",
+             "sample": f"S and D at {sample} of {N} nodes (evenly spaced), geometry setup included, "
+                       f"{dt:.1f} s, scaled to whole applies"}, tg, (ref_s, ref_d))
+
+
+def error_vs_oracle(g, dens0, tg, refs):
+    """Relative error of S and D against the FP64 oracle, per result (one apply of
+    each operator in each precision, compared at the oracle's sampled nodes):
+    relative l2 norm and max-norm relative to the oracle's largest value."""
+    import numpy as np
+
+    import paper_2506_20809_amd as sbie
+
+    out = {"nodes_compared": int(len(tg))}
+    for name, prec in (("mixed", sbie.SBIE_MIXED), ("fp64", sbie.SBIE_FP64)):
+        out[name] = {}
+        for op, ref in zip((sbie.SBIE_OP_S, sbie.SBIE_OP_D), refs):
+            u = g.apply(op, dens0[op], precision=prec)
+            g.sync()
+            u = u.cpu().numpy()[tg]
+            out[name]["SD"[op]] = {"rel_l2": float(np.linalg.norm(u - ref) / np.linalg.norm(ref)),
+                                   "max_rel": float(np.max(np.abs(u - ref)) / np.max(np.abs(ref)))}
+    return out
 
 
 def counter_traffic(precision, workload):
@@ -219,6 +239,54 @@ def run_stokes(ctx, steps, warmup, precision, op=2):
     }
     g.close()
     return res
+
+
+# Near-field work per (near pair, target) evaluation at order p, FP64 (add/mul = 1,
+# FMA = 2): per (n, m) pair with n >= m, the Q column step (3), the Ferrers step (3),
+# the spectral ratio (1) and the contraction with the cos and sin coefficients (4):
+# 11 (p+1)(p+2)/2; per evaluation the frame map and coordinates (about 60).  The
+# backward recurrences of orders 0 and 1 add 6 per step below the top degree; their
+# depth depends on the target and is not counted.  The Stokes kernels evaluate four
+# (single layer) or thirteen (double layer) coefficient sets with their gradients
+# against each basis; their count is given per basis evaluation and set.
+def near_flops(p):
+    return 11 * (p + 1) * (p + 2) // 2 + 60
+
+
+def run_near(ctx, steps):
+    """The near field alone (SBIE_PARTS_NEAR): S and D on the 512-spheroid
+    suspension (p = 16), the Stokes single and double layers on the 256-spheroid
+    one (p = 12), FP64 and mixed; evaluations per second and the FP64 vector-unit
+    fraction by the flop count of near_flops."""
+    import torch
+
+    import paper_2506_20809_amd as sbie
+    import workloads
+
+    out = {}
+    for wl, ops in (("c3", (sbie.SBIE_OP_S, sbie.SBIE_OP_D)),
+                    ("c4", (sbie.SBIE_OP_STOKES_S, sbie.SBIE_OP_STOKES_D))):
+        geom = workloads.geometry(wl)
+        p = workloads.CONFIGS[wl]["p"]
+        g = sbie.Geometry(ctx, geom, p)
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(7)
+        for op in ops:
+            nrhs = 3 if op in (sbie.SBIE_OP_STOKES_S, sbie.SBIE_OP_STOKES_D) else 1
+            d = torch.randn((nrhs, g.N) if nrhs > 1 else (g.N,), dtype=torch.float64, device="cuda", generator=gen)
+            for prec, name in ((sbie.SBIE_FP64, "fp64"), (sbie.SBIE_MIXED, "mixed")):
+                for k in range(steps + 1):
+                    g.apply(op, d, precision=prec, parts=sbie.SBIE_PARTS_NEAR, timing=k > 0)
+                g.sync()
+                tim = g.timing()
+                evals = tim.near_evals
+                rate = evals / (tim.near_ms * 1e-3)
+                rec = {"near_ms": tim.near_ms, "evaluations": int(evals), "evaluations_per_s": rate}
+                if nrhs == 1:
+                    rec["fp64_frac"] = near_flops(p) * rate / 1e12 / PEAK_TFLOPS["fp64"]
+                out[f"{wl}_op{op}_{name}"] = rec
+        g.close()
+    return out
 
 
 # GMRES iteration counts printed in the paper's table of the lattice study
@@ -401,17 +469,21 @@ def solve_large(ctx, name, precision, maxit=300):
     return out
 
 
-def served(ctx, n_requests, rho, precision, max_sessions, napply=20, budget=64 << 30):
+def served(ctx, n_requests, rhos, precision, max_sessions, budgets=(64 << 30,), napply=20, workers=64):
     """Served mode on the request stream (Section 4 use as a Krylov inner loop):
     n_requests sessions of napply closed-loop applies each.
 
     1. Plain path, back to back: one request at a time (geometry build, napply
        applies, release) -> service times s_i and the capacity mu = n / sum s_i.
     2. Served, saturated: every request arrives at t = 0 -> served throughput.
-    3. Served at Poisson arrivals of rate rho * mu -> request latency
-       (arrival to last apply) and per-apply latency, p50/p99.  The plain path
-       under the same arrivals is a single FIFO server; its latencies follow
-       from the measured s_i (done_i = max(a_i, done_{i-1}) + s_i)."""
+    3. Served at Poisson arrivals of rate rho * mu, for each rho and each HBM
+       budget -> request latency (arrival to last apply) and per-apply latency,
+       p50/p99.  The plain path under the same arrivals is a single FIFO server;
+       its latencies follow from the measured s_i (done_i = max(a_i, done_{i-1})
+       + s_i).
+    Clients are a pool of `workers` threads taking the requests in arrival
+    order (a request waits for a free client like any other queue)."""
+    import queue
     import threading
 
     import numpy as np
@@ -449,39 +521,46 @@ def served(ctx, n_requests, rho, precision, max_sessions, napply=20, budget=64 <
     mu = n_requests / service.sum()
     total_pairs = float(np.sum(far_pairs)) * napply
 
-    def run_served(arrivals):
+    def run_served(arrivals, budget):
         srv = sbie.Server(ctx, max_sessions=max_sessions, budget_bytes=budget, graphs=True)
         done = [0.0] * n_requests
         apply_ms = []
         errors = []
         lock = threading.Lock()
+        work = queue.Queue()
         t_start = time.perf_counter()
 
-        def client(i):
-            try:
-                r = reqs[i]
-                s = srv.open(geoms[i], r["p"], r["op"], prec)
-                out = torch.empty(s.N, dtype=torch.float64, device="cuda")
-                ms = []
-                for k in range(napply):
-                    _, st = s.apply(density(r, k, s.N), out)
-                    ms.append(1e-3 * (st.end_us - st.submit_us))
-                s.close()
-                done[i] = time.perf_counter() - t_start
-                with lock:
-                    apply_ms.extend(ms)
-            except Exception as e:  # reported by the caller
-                errors.append(repr(e))
+        def client():
+            while True:
+                i = work.get()
+                if i is None:
+                    return
+                try:
+                    r = reqs[i]
+                    s = srv.open(geoms[i], r["p"], r["op"], prec)
+                    out = torch.empty(s.N, dtype=torch.float64, device="cuda")
+                    ms = []
+                    for k in range(napply):
+                        _, st = s.apply(density(r, k, s.N), out)
+                        ms.append(1e-3 * (st.end_us - st.submit_us))
+                    s.close()
+                    done[i] = time.perf_counter() - t_start
+                    with lock:
+                        apply_ms.extend(ms)
+                except Exception as e:  # reported by the caller
+                    errors.append(repr(e))
 
-        threads = []
+        pool = [threading.Thread(target=client) for _ in range(workers)]
+        for t in pool:
+            t.start()
         for i in range(n_requests):
             wait = arrivals[i] - (time.perf_counter() - t_start)
             if wait > 0:
                 time.sleep(wait)
-            t = threading.Thread(target=client, args=(i,))
-            t.start()
-            threads.append(t)
-        for t in threads:
+            work.put(i)
+        for _ in pool:
+            work.put(None)
+        for t in pool:
             t.join()
         info = srv.info()
         srv.close()
@@ -491,27 +570,16 @@ def served(ctx, n_requests, rho, precision, max_sessions, napply=20, budget=64 <
         return {"makespan_s": max(done), "request_latency_s": lat, "apply_ms": np.array(apply_ms),
                 "peak_bytes": info.peak_bytes, "passed": info.passed, "waited": info.waited}
 
-    # 2. saturated
-    sat = run_served([0.0] * n_requests)
-    # 3. Poisson arrivals at rho * mu
-    rng = np.random.default_rng(55)
-    arrivals = np.cumsum(rng.exponential(1.0 / (rho * mu), size=n_requests))
-    arrivals -= arrivals[0]
-    srv_run = run_served(list(arrivals))
-    plain_done, t = [], 0.0
-    for a, s_ in zip(arrivals, service):
-        t = max(a, t) + s_
-        plain_done.append(t)
-    plain_lat = np.array(plain_done) - arrivals
-
     def pct(x):
         return {"p50": float(np.percentile(x, 50)), "p99": float(np.percentile(x, 99))}
 
+    # 2. saturated
+    sat = run_served([0.0] * n_requests, budgets[0])
     Ms = np.array([r["M"] for r in reqs])
-    return {
+    res = {
         "workload": f"{n_requests} requests (particle count log-uniform in [8, 1024] cut from a 0.15 volume "
                     f"fraction packing, p in {{8, 12, 16}}, S or D), {napply} closed-loop applies each, "
-                    f"precision={precision}, {max_sessions} lanes, HIP graph replay",
+                    f"precision={precision}, {max_sessions} lanes, HIP graph replay, {workers} client threads",
         "mean_particles": float(Ms.mean()),
         "plain": {"capacity_requests_per_s": mu, "applies_per_s": mu * napply,
                   "pair_interactions_per_s": total_pairs / service.sum(),
@@ -521,15 +589,29 @@ def served(ctx, n_requests, rho, precision, max_sessions, napply=20, budget=64 <
                              "pair_interactions_per_s": total_pairs / sat["makespan_s"],
                              "speedup_vs_plain": (n_requests / sat["makespan_s"]) / mu,
                              "apply_latency_ms": pct(sat["apply_ms"])},
-        f"poisson_rho_{rho}": {
-            "arrival_rate_per_s": rho * mu,
-            "served_request_latency_s": pct(srv_run["request_latency_s"]),
-            "plain_fifo_request_latency_s": pct(plain_lat),
-            "served_apply_latency_ms": pct(srv_run["apply_ms"]),
-            "served_applies_per_s": n_requests * napply / srv_run["makespan_s"],
-            "peak_arena_bytes": int(srv_run["peak_bytes"]), "admissions_passed": int(srv_run["passed"]),
-        },
     }
+    # 3. Poisson arrivals at rho * mu, per budget
+    for budget in budgets:
+        for rho in rhos:
+            rng = np.random.default_rng(55)
+            arrivals = np.cumsum(rng.exponential(1.0 / (rho * mu), size=n_requests))
+            arrivals -= arrivals[0]
+            run = run_served(list(arrivals), budget)
+            plain_done, t = [], 0.0
+            for a, s_ in zip(arrivals, service):
+                t = max(a, t) + s_
+                plain_done.append(t)
+            plain_lat = np.array(plain_done) - arrivals
+            res[f"poisson_rho_{rho}_budget_{budget >> 30}GiB"] = {
+                "arrival_rate_per_s": rho * mu,
+                "served_request_latency_s": pct(run["request_latency_s"]),
+                "plain_fifo_request_latency_s": pct(plain_lat),
+                "served_apply_latency_ms": pct(run["apply_ms"]),
+                "served_applies_per_s": n_requests * napply / run["makespan_s"],
+                "peak_arena_bytes": int(run["peak_bytes"]), "admissions_passed": int(run["passed"]),
+                "admissions_waited": int(run["waited"]),
+            }
+    return res
 
 
 def main():
@@ -546,9 +628,13 @@ def main():
     ap.add_argument("--no-derivatives", action="store_true", help="skip the S' and D' measurement")
     ap.add_argument("--no-solve", action="store_true", help="skip the completed double-layer solves")
     ap.add_argument("--no-tree", action="store_true", help="skip the tree far-field measurement")
-    ap.add_argument("--served-requests", type=int, default=0,
-                    help="requests in the served-mode run (0: skip; the run is opt-in)")
-    ap.add_argument("--served-rho", type=float, default=0.8, help="load of the Poisson arrivals")
+    ap.add_argument("--no-near", action="store_true", help="skip the near-field measurement")
+    ap.add_argument("--only-near", action="store_true",
+                    help="run only the near-field section (for counter runs); prints its JSON object")
+    ap.add_argument("--served-requests", type=int, default=48,
+                    help="requests in the served-mode run (0: skip)")
+    ap.add_argument("--served-rho", type=float, nargs="+", default=[0.8], help="loads of the Poisson arrivals")
+    ap.add_argument("--served-budget-gib", type=int, nargs="+", default=[64], help="HBM budgets of the server")
     ap.add_argument("--served-precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--served-lanes", type=int, default=8)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -571,6 +657,11 @@ def main():
         torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
+    if args.only_near:
+        ctx = sbie.Context(0)
+        print(json.dumps({"near_field": run_near(ctx, max(2, args.steps // 4))}), flush=True)
+        ctx.close()
+        return
     geom = workloads.geometry(args.workload)
     p = workloads.CONFIGS[args.workload]["p"]
     M = len(geom["A"])
@@ -616,7 +707,9 @@ def main():
         sec = run(g, dens, max(4, args.steps // 2), 1, other)
         res[f"{other}_path"] = {k: sec[k] for k in ("applies_per_s", "pair_interactions_per_s", "latency_ms",
                                                     "part_ms")}
-        res[f"{other}_path"]["roofline_frac"] = sec["roofline"]["frac"]
+        res[f"{other}_path"]["roofline"] = dict(sec["roofline"], traffic=counter_traffic(other, args.workload))
+    if not args.no_near:
+        res["near_field"] = run_near(ctx, max(3, args.steps // 4))
     if not args.no_derivatives:
         res["derivatives"] = {pr: run_normal(g, dens, max(3, args.steps // 4), pr) for pr in ("mixed", "fp64")}
     if not args.no_stokes:
@@ -633,10 +726,11 @@ def main():
                                  "c3x8": tree_scaling(ctx, "c3x8", 3)}
     if args.served_requests > 0:
         res["served"] = served(ctx, args.served_requests, args.served_rho, args.served_precision,
-                               args.served_lanes)
+                               args.served_lanes, budgets=tuple(b << 30 for b in args.served_budget_gib))
     if not args.no_cpu_baseline:
         d = dens[0].cpu().numpy()
-        res["cpu_baseline"] = cpu_baseline(geom, p, d[0], d[1], N, args.cpu_sample)
+        res["cpu_baseline"], tg, refs = cpu_baseline(geom, p, d[0], d[1], N, args.cpu_sample)
+        res["error_vs_oracle"] = error_vs_oracle(g, dens[0], tg, refs)
     g.close()
     ctx.close()
     print(json.dumps(res), flush=True)

@@ -175,7 +175,14 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform, for the compiler
   const int li = lane & 15, lg = lane >> 4;
   const int x16 = (lane ^ 16) << 2, x32 = (lane ^ 32) << 2;  // partner lanes of the column sums
-  const int split = blockIdx.x % nsplit, rest = blockIdx.x / nsplit;
+  // Workgroups are dispatched round-robin over the eight XCDs (w mod 8).
+  // Each XCD gets a contiguous range of the work index instead, so that the
+  // particles it holds at once are neighbours in index and share most of
+  // their partners' source blocks in its L2.
+  const int G = (int)gridDim.x, w = (int)blockIdx.x;
+  const int xcd = w % 8, per = G / 8, extra = G % 8;
+  const int wid = xcd * per + (xcd < extra ? xcd : extra) + w / 8;
+  const int split = wid % nsplit, rest = wid / nsplit;
   const int rg = rest % RG, a = rest / RG;
   const int nb = T16 / 16;
   constexpr int GB = PairShape<R>::GB, RB = PairShape<R>::RBMAX;

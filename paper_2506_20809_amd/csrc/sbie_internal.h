@@ -16,7 +16,7 @@ namespace sbie {
 
 constexpr int kMaxP = 32;
 constexpr int kRcpN = 16384;  // reciprocal table length (near-field recurrences)
-constexpr size_t kRevBudget = size_t(64) << 20;  // reverse sums of one pair-kernel launch, bytes
+constexpr size_t kRevBudget = size_t(128) << 20;  // reverse sums of one pair-kernel launch, bytes
 constexpr double kPi = 3.14159265358979323846264338327950288;
 
 // Per-particle parameters on the device (Section 2.1, Table 1).

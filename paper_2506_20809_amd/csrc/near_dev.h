@@ -209,9 +209,11 @@ __device__ inline void expansion_derivatives(const SpheroidalPoint& q, bool obla
     fb1 = qN1;
     double Q[PMAX + 4];
     q_column<PMAX>(u, sgn, N1, m, qN, qN1, rcp, Q);
-    double vc[NSET], vs[NSET], uc[NSET], us[NSET], wc[NSET], ws[NSET];
-#pragma unroll
-    for (int s = 0; s < NSET; ++s) vc[s] = vs[s] = uc[s] = us[s] = wc[s] = ws[s] = 0.0;
+    // the azimuthal factors of order m folded into the basis, so that each
+    // set accumulates straight into its four outputs (no per-order partial
+    // sums per set: fewer registers for many sets)
+    const double f = m == 0 ? 1.0 : 1.41421356237309504880;
+    const double fc = f * cm, fs = f * sm, fmc = (double)m * fc, fms = -(double)m * fs;
     // normalised Ferrers functions of v rolled forward in n: P_{n-1}, P_n and
     // (for the v-derivative) P_{n+1}
     double pm1 = 0.0, pn = pbar;
@@ -231,30 +233,28 @@ __device__ inline void expansion_derivatives(const SpheroidalPoint& q, bool obla
         const double dq = ((-sgn) * (double)(n - m + 1) * Q[n + 1] - (double)(n + 1) * u * Q[n]) * inv_w * sc;
         const double dpn = ((double)(n + 1) * v * pn - cd[h] * pn1) * inv_omv2;
         const double t0 = pn * qr, t1 = pn * dq, t2 = dpn * qr;
+        // cos(m phi) terms carry E_{n,m}, sin(m phi) terms E_{n,-m}; the
+        // phi-derivative swaps them: d/dphi [c cos + s sin] = m (s cos - c sin)
+        const double a0 = fc * t0, a1 = fc * t1, a2 = fc * t2, ap = fms * t0;
+        const double b0 = fs * t0, b1 = fs * t1, b2 = fs * t2, bp = fmc * t0;
 #pragma unroll
         for (int s = 0; s < NSET; ++s) {
           const double ec = E[(size_t)s * stride + n * n + n + m];
-          vc[s] = fma(ec, t0, vc[s]);
-          uc[s] = fma(ec, t1, uc[s]);
-          wc[s] = fma(ec, t2, wc[s]);
+          Phi[s] = fma(ec, a0, Phi[s]);
+          Pu[s] = fma(ec, a1, Pu[s]);
+          Pv[s] = fma(ec, a2, Pv[s]);
+          Pp[s] = fma(ec, ap, Pp[s]);
           if (m > 0) {
             const double es = E[(size_t)s * stride + n * n + n - m];
-            vs[s] = fma(es, t0, vs[s]);
-            us[s] = fma(es, t1, us[s]);
-            ws[s] = fma(es, t2, ws[s]);
+            Phi[s] = fma(es, b0, Phi[s]);
+            Pu[s] = fma(es, b1, Pu[s]);
+            Pv[s] = fma(es, b2, Pv[s]);
+            Pp[s] = fma(es, bp, Pp[s]);
           }
         }
         pm1 = pn;
         pn = pn1;
       }
-    }
-    const double f = m == 0 ? 1.0 : 1.41421356237309504880;
-#pragma unroll
-    for (int s = 0; s < NSET; ++s) {
-      Phi[s] += f * (vc[s] * cm + vs[s] * sm);
-      Pu[s] += f * (uc[s] * cm + us[s] * sm);
-      Pv[s] += f * (wc[s] * cm + ws[s] * sm);
-      Pp[s] += f * (double)m * (vs[s] * cm - vc[s] * sm);
     }
   }
 }

@@ -133,7 +133,7 @@ __global__ void k_stokes_self(const Particle* __restrict__ part, const double* _
 // field, and the four expansions are summed with their u, v and phi
 // derivatives.
 template <int PMAX, bool EXACT, int C>
-__global__ __launch_bounds__(64) void k_near_stokes(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_near_stokes(
     const Particle* __restrict__ part, const double* __restrict__ x, const double* __restrict__ y,
     const double* __restrict__ z, const int32_t* __restrict__ near_ptr, const int32_t* __restrict__ near_src,
     const double* __restrict__ E, const double* __restrict__ lam, const double* __restrict__ ab,

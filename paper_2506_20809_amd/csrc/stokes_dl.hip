@@ -139,7 +139,7 @@ __global__ void k_sdl_self(const Particle* __restrict__ part, const double* __re
 // recurrences run once for the four double-layer sets and once for the nine
 // single-layer sets of every near source.
 template <int PMAX, bool EXACT>
-__global__ __launch_bounds__(64) void k_near_sdl(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_near_sdl(
     const Particle* __restrict__ part, const double* __restrict__ x, const double* __restrict__ y,
     const double* __restrict__ z, const int32_t* __restrict__ near_ptr, const int32_t* __restrict__ near_src,
     const double* __restrict__ E, const double* __restrict__ lam, const double* __restrict__ ab,

@@ -122,8 +122,14 @@ def run(g, dens, steps, warmup, precision):
     g.sync()
     tim = g.timing()
     lat = np.array([e[0].elapsed_time(e[1]) for e in ev])
-    flops_per_launch = 0.5 * (FLOPS_PER_PAIR[0] + FLOPS_PER_PAIR[1]) * tim.far_pairs
-    achieved = flops_per_launch / (tim.far_kernel_ms * 1e-3) / 1e12
+    # the far field of one apply runs as tim.far_launches launches over chunks of
+    # partner offsets (balanced); far_kernel_ms covers all of them (and the
+    # folds between them), so flops per launch over the mean launch time is
+    # flops per apply over far_kernel_ms
+    launches = max(1, tim.far_launches)
+    flops_per_apply = 0.5 * (FLOPS_PER_PAIR[0] + FLOPS_PER_PAIR[1]) * tim.far_pairs
+    flops_per_launch = flops_per_apply / launches
+    achieved = flops_per_launch / (tim.far_kernel_ms / launches * 1e-3) / 1e12
     return {
         "applies_per_s": 2 * steps / elapsed,
         "elapsed_s": elapsed,
@@ -139,7 +145,8 @@ def run(g, dens, steps, warmup, precision):
                      "frac": achieved / PEAK_TFLOPS[precision], "traffic": None,
                      "kernel": "k_far_pairs<float> (S and D alternating)" if precision == "mixed"
                      else "k_far_pairs<double> (S and D alternating)",
-                     "flops_per_launch": flops_per_launch},
+                     "flops_per_launch": flops_per_launch, "launches_per_apply": launches,
+                     "flops_per_apply": flops_per_apply},
     }
 
 
@@ -339,6 +346,31 @@ def run_tree(g, dens, steps, theta=0.6, order=10, leaf=2):
     return res
 
 
+def tree_sweep(g, dens, settings=((0.5, 10), (0.5, 12), (0.4, 12), (0.3, 12), (0.2, 12))):
+    """FP64 tree far field against the direct FP64 far sum for several (theta,
+    order): relative l2 distance per operator and the FP64 tree apply time."""
+    import torch
+
+    import paper_2506_20809_amd as sbie
+
+    out = []
+    fd = {op: g.apply(op, dens[0, op], parts=sbie.SBIE_PARTS_FAR, precision=sbie.SBIE_FP64)
+          for op in (sbie.SBIE_OP_S, sbie.SBIE_OP_D)}
+    for theta, order in settings:
+        info = g.far_tree(theta, order, 2)
+        rec = {"theta": theta, "order": order, "proxy_evals": info["proxy_evals"],
+               "direct_evals": info["direct_evals"]}
+        for name, op in (("S", sbie.SBIE_OP_S), ("D", sbie.SBIE_OP_D)):
+            ft = g.apply(op, dens[0, op], parts=sbie.SBIE_PARTS_FAR, precision=sbie.SBIE_FP64, tree=True)
+            g.apply(op, dens[1, op], precision=sbie.SBIE_FP64, tree=True, timing=True)
+            g.sync()
+            tim = g.timing()
+            rec[name] = {"far_rel_l2_vs_direct_fp64": float(torch.linalg.norm(ft - fd[op]) / torch.linalg.norm(fd[op])),
+                         "tree_far_ms": tim.far_kernel_ms, "apply_ms": tim.total_ms}
+        out.append(rec)
+    return out
+
+
 def tree_scaling(ctx, name, steps):
     """The tree far field at a larger suspension beside the direct paths."""
     import torch
@@ -520,6 +552,7 @@ def served(ctx, n_requests, rhos, precision, max_sessions, budgets=(64 << 30,), 
     service = np.array(service)
     mu = n_requests / service.sum()
     total_pairs = float(np.sum(far_pairs)) * napply
+    print(f"served: plain pass of {n_requests} requests in {service.sum():.1f} s", file=sys.stderr, flush=True)
 
     def run_served(arrivals, budget):
         srv = sbie.Server(ctx, max_sessions=max_sessions, budget_bytes=budget, graphs=True)
@@ -575,6 +608,7 @@ def served(ctx, n_requests, rhos, precision, max_sessions, budgets=(64 << 30,), 
 
     # 2. saturated
     sat = run_served([0.0] * n_requests, budgets[0])
+    print(f"served: saturated run in {sat['makespan_s']:.1f} s", file=sys.stderr, flush=True)
     Ms = np.array([r["M"] for r in reqs])
     res = {
         "workload": f"{n_requests} requests (particle count log-uniform in [8, 1024] cut from a 0.15 volume "
@@ -597,6 +631,8 @@ def served(ctx, n_requests, rhos, precision, max_sessions, budgets=(64 << 30,), 
             arrivals = np.cumsum(rng.exponential(1.0 / (rho * mu), size=n_requests))
             arrivals -= arrivals[0]
             run = run_served(list(arrivals), budget)
+            print(f"served: rho {rho}, budget {budget >> 30} GiB in {run['makespan_s']:.1f} s", file=sys.stderr,
+                  flush=True)
             plain_done, t = [], 0.0
             for a, s_ in zip(arrivals, service):
                 t = max(a, t) + s_
@@ -629,6 +665,8 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="skip the completed double-layer solves")
     ap.add_argument("--no-tree", action="store_true", help="skip the tree far-field measurement")
     ap.add_argument("--no-near", action="store_true", help="skip the near-field measurement")
+    ap.add_argument("--tree-sweep", action="store_true",
+                    help="add the FP64 tree's accuracy and time over several (theta, order)")
     ap.add_argument("--only-near", action="store_true",
                     help="run only the near-field section (for counter runs); prints its JSON object")
     ap.add_argument("--served-requests", type=int, default=48,
@@ -724,6 +762,8 @@ def main():
     if not args.no_tree:
         res["tree_far_field"] = {args.workload: run_tree(g, dens, max(4, args.steps // 4)),
                                  "c3x8": tree_scaling(ctx, "c3x8", 3)}
+    if args.tree_sweep:
+        res["tree_sweep_fp64"] = tree_sweep(g, dens)
     if args.served_requests > 0:
         res["served"] = served(ctx, args.served_requests, args.served_rho, args.served_precision,
                                args.served_lanes, budgets=tuple(b << 30 for b in args.served_budget_gib))

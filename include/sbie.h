@@ -115,6 +115,8 @@ typedef struct {
   int64_t far_pairs;   /* far-field node pairs evaluated per right-hand side */
   int64_t near_evals;  /* near-field (pair, target) evaluations per right-hand side */
   int64_t count;       /* number of timed applies averaged */
+  int64_t far_launches; /* launches of the pair-symmetric far-field kernel per apply (it runs over
+                           chunks of partner offsets; 0 when the direct pair kernel is not used) */
 } sbie_timing;
 
 /* Create a context on HIP device `device` (a stream is created for synchronous

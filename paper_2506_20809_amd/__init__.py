@@ -60,7 +60,8 @@ class TreeInfo(ctypes.Structure):
 class Timing(ctypes.Structure):
     _fields_ = [("prep_ms", ctypes.c_double), ("transform_ms", ctypes.c_double), ("near_ms", ctypes.c_double),
                 ("far_kernel_ms", ctypes.c_double), ("assemble_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
-                ("far_pairs", ctypes.c_int64), ("near_evals", ctypes.c_int64), ("count", ctypes.c_int64)]
+                ("far_pairs", ctypes.c_int64), ("near_evals", ctypes.c_int64), ("count", ctypes.c_int64),
+                ("far_launches", ctypes.c_int64)]
 
 
 class ApplyStats(ctypes.Structure):

@@ -3,6 +3,7 @@
 // exception crosses the boundary.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -441,6 +442,11 @@ sbie_status sbie_geom_timing(sbie_geom* g, sbie_timing* out) {
   out->assemble_ms = acc[4] / n;
   out->total_ms = acc[5] / n;
   out->far_pairs = g->far_pairs;
+  {
+    const int pmax = (g->M - 1) / 2 + ((g->M & 1) == 0 ? 1 : 0);
+    const int ks = g->rev_slots > 0 ? g->rev_slots : 1;
+    out->far_launches = g->T >= 32 ? std::max(1, (pmax + ks - 1) / ks) : 0;
+  }
   out->near_evals = g->n_near * (int64_t)g->T;
   out->count = (int64_t)tm.used;
   tm.used = 0;

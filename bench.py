@@ -681,6 +681,11 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "the operator apply here is a one-GPU path (sharding across GPUs is designed, not built); --gpus must be 1"}))
         sys.exit(2)
+    if args.served_requests > 0 and "GPU_MAX_HW_QUEUES" not in os.environ:
+        # one hardware queue per served lane (HIP's default is four per process:
+        # eight lanes would share them in pairs, each pair's kernels in order);
+        # read when the HIP runtime starts, so set before torch is imported
+        os.environ["GPU_MAX_HW_QUEUES"] = str(max(4, args.served_lanes))
 
     import torch
 

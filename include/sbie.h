@@ -282,7 +282,14 @@ sbie_status sbie_solve_neumann(sbie_geom* g, sbie_precision prec, const double* 
    lists and spectra resident until it is closed; each lane has its own stream,
    so the kernels of concurrent sessions interleave on the device.  With
    SBIE_SERVER_GRAPHS each session's apply is captured once as a HIP graph and
-   replayed.  Results are bitwise those of sbie_apply on the same geometry.
+   replayed.  With SBIE_SERVER_BATCH a lane may hold up to four sessions of
+   one operator (S or D), precision and order, each of at most 65536 nodes
+   with a far field that fits one pair-kernel launch (p >= 3, every partner
+   offset within the reverse-sum budget), once no lane is empty, and runs the
+   front applies of its sessions
+   together: each session's transform and self part, one near-field launch and
+   one far-field launch over all of them, each session's assembly.  Results are
+   bitwise those of sbie_apply on the same geometry.
 
    All server calls are thread-safe; the handles of one session must not be
    used after sbie_session_close. */
@@ -291,6 +298,7 @@ typedef struct sbie_server sbie_server;
 typedef struct sbie_session sbie_session;
 
 #define SBIE_SERVER_GRAPHS 0x100u
+#define SBIE_SERVER_BATCH 0x200u
 #define SBIE_MAX_PASS 8
 
 typedef struct {
@@ -317,6 +325,7 @@ typedef struct {
   int64_t applies;          /* applies completed */
   int32_t lanes;
   int32_t graphs;           /* 1 if applies are replayed as HIP graphs */
+  int64_t batched;          /* applies completed inside batched launches */
 } sbie_server_info;
 
 /* Device bytes a session of M particles at order p holds while admitted:
@@ -327,7 +336,7 @@ uint64_t sbie_session_bytes(int32_t M, int32_t p, sbie_op op);
 
 /* Start a server on ctx's device with max_sessions lanes (1..64), each with a
    stream and a host thread, and an arena of hbm_budget_bytes of device memory
-   allocated now.  flags: SBIE_SERVER_GRAPHS.  Errors: SBIE_E_INVALID,
+   allocated now.  flags: SBIE_SERVER_GRAPHS, SBIE_SERVER_BATCH.  Errors: SBIE_E_INVALID,
    SBIE_E_NOMEM, SBIE_E_DEVICE. */
 sbie_status sbie_server_create(sbie_ctx* ctx, int32_t max_sessions, uint64_t hbm_budget_bytes,
                                uint32_t flags, sbie_server** out);

@@ -194,14 +194,14 @@ __global__ void k_scale_coef(const double* __restrict__ coef, const double* __re
 // unrolled loops free of runtime predicates (otherwise held, and spilled, as
 // scalar masks).
 template <int PMAX, bool EXACT>
-__global__ __launch_bounds__(64) void k_near_f64(
+__device__ __forceinline__ void near_f64_body(
     const Particle* __restrict__ part, const double* __restrict__ x, const double* __restrict__ y,
     const double* __restrict__ z, const int32_t* __restrict__ near_ptr,
     const int32_t* __restrict__ near_src, const double* __restrict__ E,
     const double* __restrict__ lam, const double* __restrict__ ab, const double* __restrict__ rcp, int p_arg,
-    int T, int chunks, int64_t Nn, unsigned* status, double* __restrict__ unear) {
+    int T, int chunks, int64_t Nn, unsigned* status, double* __restrict__ unear, int bid) {
   const int p = EXACT ? PMAX : p_arg;
-  const int q4 = blockIdx.x % kNearSplit, rest = blockIdx.x / kNearSplit;
+  const int q4 = bid % kNearSplit, rest = bid / kNearSplit;
   const int j = rest / chunks;
   const int t = (rest - j * chunks) * 64 + threadIdx.x;
   const bool live = t < T;
@@ -316,6 +316,33 @@ __global__ __launch_bounds__(64) void k_near_f64(
   }
   if (bad) atomicOr(status, bad);
   if (live) unear[(size_t)q4 * Nn + g] = acc;
+}
+
+template <int PMAX, bool EXACT>
+__global__ __launch_bounds__(64) void k_near_f64(
+    const Particle* __restrict__ part, const double* __restrict__ x, const double* __restrict__ y,
+    const double* __restrict__ z, const int32_t* __restrict__ near_ptr,
+    const int32_t* __restrict__ near_src, const double* __restrict__ E,
+    const double* __restrict__ lam, const double* __restrict__ ab, const double* __restrict__ rcp, int p_arg,
+    int T, int chunks, int64_t Nn, unsigned* status, double* __restrict__ unear) {
+  near_f64_body<PMAX, EXACT>(part, x, y, z, near_ptr, near_src, E, lam, ab, rcp, p_arg, T, chunks, Nn, status,
+                             unear, (int)blockIdx.x);
+}
+
+// Several geometries' near fields (one order) in one launch: job j owns the
+// workgroups [wg_begin_j, wg_begin_{j+1}) and runs those of its own launch.
+template <int PMAX, bool EXACT>
+__global__ __launch_bounds__(64) void k_near_f64_batch(const NearJob* __restrict__ jobs, int njobs) {
+  const int bid = (int)blockIdx.x;
+  int lo = 0, hi = njobs - 1;  // the last job starting at or before bid
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (jobs[mid].wg_begin <= bid) lo = mid;
+    else hi = mid - 1;
+  }
+  const NearJob& J = jobs[lo];
+  near_f64_body<PMAX, EXACT>(J.part, J.x, J.y, J.z, J.near_ptr, J.near_src, J.E, J.lam, J.ab, J.rcp, J.p, J.T,
+                             J.chunks, J.N, J.status, J.unear, bid - J.wg_begin);
 }
 
 // ---------------------------------------------------------------- far field (FP64)
@@ -585,6 +612,95 @@ sbie_status apply_laplace(sbie_geom* g, int op, int prec, const double* d_dens, 
                      pairs ? (const double*)g->d_racc : nullptr, N, sum_parts, d_out);
   SBIE_HIP(hipGetLastError());
   if (timed) SBIE_HIP(hipEventRecord(ev[5], s));
+  return SBIE_OK;
+}
+
+sbie_status apply_laplace_batch(sbie_geom* const* gs, int n, int op, int prec, const double* const* d_dens,
+                                double* const* d_out, BatchJobs* jobs, hipStream_t s) {
+  if (n < 1) return SBIE_OK;
+  if (n > jobs->cap) {
+    set_error("batch larger than its job tables");
+    return SBIE_E_INVALID;
+  }
+  const int B = 256;
+  const bool mixed = prec == SBIE_MIXED;
+  const int p = gs[0]->p;
+  // each geometry's prep, forward transform, spectra, self part and far
+  // strengths: the kernels of apply_laplace, in its order
+  for (int k = 0; k < n; ++k) {
+    sbie_geom* g = gs[k];
+    const int M = g->M, T = g->T, K = g->K;
+    const int64_t N = g->N;
+    if (g->p != p || !far_batch_fits(g)) {
+      set_error("batched geometries must share the order and fit one far-field launch");
+      return SBIE_E_INVALID;
+    }
+    if (op == SBIE_OP_S)
+      hipLaunchKernelGGL(k_prep_f64<SBIE_OP_S>, dim3(cdiv(N, B)), dim3(B), 0, s, d_dens[k], g->d_x, g->d_y, g->d_z,
+                         g->d_nx, g->d_ny, g->d_nz, g->d_w, g->d_wS, p, N, g->d_f, g->d_src);
+    else
+      hipLaunchKernelGGL(k_prep_f64<SBIE_OP_D>, dim3(cdiv(N, B)), dim3(B), 0, s, d_dens[k], g->d_x, g->d_y, g->d_z,
+                         g->d_nx, g->d_ny, g->d_nz, g->d_w, g->d_wS, p, N, g->d_f, g->d_src);
+    SBIE_HIP(hipGetLastError());
+    sbie_status st = mixed ? launch_gemm32(g->d_f, T, g->d_An32, K, g->d_coef, K, M, K, T, s)
+                           : launch_gemm(g->d_f, T, g->d_An, K, g->d_coef, K, M, K, T, s);
+    if (st) return st;
+    hipLaunchKernelGGL(k_scale_coef, dim3(cdiv((int64_t)M * K, B)), dim3(B), 0, s, g->d_coef, g->d_lam, M, p, op,
+                       g->d_cself, g->d_E);
+    SBIE_HIP(hipGetLastError());
+    st = mixed ? launch_gemm32(g->d_cself, K, g->d_Sy32, T, g->d_uself, T, M, T, K, s)
+               : launch_gemm(g->d_cself, K, g->d_Sy, T, g->d_uself, T, M, T, K, s);
+    if (st) return st;
+    if ((st = far_strengths(g, op, prec, d_dens[k], s))) return st;
+  }
+  // one near launch over the geometries with near pairs
+  int nn = 0, near_wg = 0;
+  for (int k = 0; k < n; ++k) {
+    sbie_geom* g = gs[k];
+    if (g->n_near == 0) continue;
+    NearJob& J = jobs->h_near[nn++];
+    J.part = g->d_part;
+    J.x = g->d_x;
+    J.y = g->d_y;
+    J.z = g->d_z;
+    J.near_ptr = g->d_near_ptr;
+    J.near_src = g->d_near_src;
+    J.E = g->d_E;
+    J.lam = g->d_lam;
+    J.ab = g->d_ab;
+    J.rcp = g->d_rcp;
+    J.p = g->p;
+    J.T = g->T;
+    J.chunks = (g->T + 63) / 64;
+    J.wg_begin = near_wg;
+    J.N = g->N;
+    J.status = g->d_status;
+    J.unear = g->d_unear;
+    near_wg += g->M * J.chunks * kNearSplit;
+  }
+  // one far launch over all of them
+  int far_wg = 0;
+  for (int k = 0; k < n; ++k) far_wg += far_batch_job(gs[k], op, prec, far_wg, &jobs->h_far[k]);
+  SBIE_HIP(hipMemcpyAsync(jobs->d_near, jobs->h_near, sizeof(NearJob) * nn, hipMemcpyHostToDevice, s));
+  SBIE_HIP(hipMemcpyAsync(jobs->d_far, jobs->h_far, sizeof(FarJob) * n, hipMemcpyHostToDevice, s));
+  if (nn > 0) {
+    dispatch_order(p, [&](auto pm, auto ex) {
+      hipLaunchKernelGGL((k_near_f64_batch<decltype(pm)::value, decltype(ex)::value>), dim3((unsigned)near_wg),
+                         dim3(64), 0, s, jobs->d_near, nn);
+    });
+    SBIE_HIP(hipGetLastError());
+  }
+  sbie_status st = far_batch_launch(gs, n, jobs->d_far, far_wg, op, prec, s);
+  if (st) return st;
+  // each geometry's assembly (forward slices of its own split count, reverse totals)
+  for (int k = 0; k < n; ++k) {
+    sbie_geom* g = gs[k];
+    const uint32_t sum_parts = g->n_near > 0 ? SBIE_PARTS_ALL : (SBIE_PARTS_ALL & ~(uint32_t)SBIE_PARTS_NEAR);
+    const int nslices = far_launch_splits(g, far_row_groups(g, !mixed));
+    hipLaunchKernelGGL(k_assemble_f64, dim3(cdiv(g->N, B)), dim3(B), 0, s, g->d_uself, g->d_unear, g->d_partial,
+                       nslices, (const double*)g->d_racc, g->N, sum_parts, d_out[k]);
+    SBIE_HIP(hipGetLastError());
+  }
   return SBIE_OK;
 }
 

@@ -153,12 +153,12 @@ struct PairShape {
 //
 // Rows of a are padded to 16 with zero-strength points at a's centre.
 template <typename R, int OP>
-__global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* __restrict__ geo, const R* __restrict__ app,
-                                                   const Particle* __restrict__ part, const double* __restrict__ x,
-                                                   const double* __restrict__ y, const double* __restrict__ z,
-                                                   const uint32_t* __restrict__ excl, int words, int M, int T,
-                                                   int T16, int64_t N, int nsplit, int RG, int kbase, int kend,
-                                                   int first, double* __restrict__ fwd, R* __restrict__ rev) {
+__device__ __forceinline__ void far_pairs_body(const R* __restrict__ geo, const R* __restrict__ app,
+                                               const Particle* __restrict__ part, const double* __restrict__ x,
+                                               const double* __restrict__ y, const double* __restrict__ z,
+                                               const uint32_t* __restrict__ excl, int words, int M, int T, int T16,
+                                               int64_t N, int nsplit, int RG, int kbase, int kend, int first,
+                                               double* __restrict__ fwd, R* __restrict__ rev, int wid) {
   using MM = Mfma<R>;
   using V = typename MM::V;
   using L = FarLayout<R, OP>;
@@ -175,13 +175,6 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform, for the compiler
   const int li = lane & 15, lg = lane >> 4;
   const int x16 = (lane ^ 16) << 2, x32 = (lane ^ 32) << 2;  // partner lanes of the column sums
-  // Workgroups are dispatched round-robin over the eight XCDs (w mod 8).
-  // Each XCD gets a contiguous range of the work index instead, so that the
-  // particles it holds at once are neighbours in index and share most of
-  // their partners' source blocks in its L2.
-  const int G = (int)gridDim.x, w = (int)blockIdx.x;
-  const int xcd = w % 8, per = G / 8, extra = G % 8;
-  const int wid = xcd * per + (xcd < extra ? xcd : extra) + w / 8;
   const int split = wid % nsplit, rest = wid / nsplit;
   const int rg = rest % RG, a = rest / RG;
   const int nb = T16 / 16;
@@ -666,6 +659,48 @@ __global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* 
   }
 }
 
+// Workgroups are dispatched round-robin over the eight XCDs (w mod 8).  Each
+// XCD gets a contiguous range of the work index instead, so that the
+// particles it holds at once are neighbours in index and share most of their
+// partners' source blocks in its L2.
+__device__ inline int xcd_work_index() {
+  const int G = (int)gridDim.x, w = (int)blockIdx.x;
+  const int xcd = w % 8, per = G / 8, extra = G % 8;
+  return xcd * per + (xcd < extra ? xcd : extra) + w / 8;
+}
+
+template <typename R, int OP>
+__global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs(const R* __restrict__ geo, const R* __restrict__ app,
+                                                   const Particle* __restrict__ part, const double* __restrict__ x,
+                                                   const double* __restrict__ y, const double* __restrict__ z,
+                                                   const uint32_t* __restrict__ excl, int words, int M, int T,
+                                                   int T16, int64_t N, int nsplit, int RG, int kbase, int kend,
+                                                   int first, double* __restrict__ fwd, R* __restrict__ rev) {
+  far_pairs_body<R, OP>(geo, app, part, x, y, z, excl, words, M, T, T16, N, nsplit, RG, kbase, kend, first, fwd,
+                        rev, xcd_work_index());
+}
+
+// Several geometries' pair-kernel work in one launch (served sessions of one
+// order and operator): job j owns the work indices [wg_begin_j, wg_begin_{j+1})
+// and runs exactly the workgroups its own launch would, so its sums are
+// bitwise those of its own launch.  Every job's far field fits one launch
+// (all partner offsets, first = 1).
+template <typename R, int OP>
+__global__ __launch_bounds__(64 * PairShape<R>::WMAX) void k_far_pairs_batch(const FarJob* __restrict__ jobs,
+                                                                            int njobs) {
+  const int wid = xcd_work_index();
+  int lo = 0, hi = njobs - 1;  // the last job starting at or before wid
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (jobs[mid].wg_begin <= wid) lo = mid;
+    else hi = mid - 1;
+  }
+  const FarJob& J = jobs[lo];
+  far_pairs_body<R, OP>(static_cast<const R*>(J.geo), static_cast<const R*>(J.app), J.part, J.x, J.y, J.z, J.excl,
+                        J.words, J.M, J.T, J.T16, J.N, J.nsplit, J.RG, 0, J.kend, 1, J.fwd, static_cast<R*>(J.rev),
+                        wid - J.wg_begin);
+}
+
 // After a launch over the partner offsets [kbase, kend): each target's reverse
 // slots of the launch (the slots with a handler: k < H, and k = H for even M
 // when the target is in the upper half), slot then row group, added in FP64 to
@@ -823,6 +858,39 @@ __global__ void k_far_strengths(const Particle* __restrict__ part, const double*
 
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
+// Workgroup size and dynamic LDS of the pair kernel for g's order and op.
+template <typename R>
+void pair_launch_shape(const sbie_geom* g, int op, dim3* wg, size_t* lds) {
+  using PS = PairShape<R>;
+  const int nb = g->T16 / 16;
+  const int blocks = nb < PS::GB ? nb : PS::GB;
+  *wg = dim3((unsigned)(64 * (blocks < PS::WMAX ? blocks : PS::WMAX)));
+  int ngeo = 0, napp = 0;
+  switch (op) {
+    case SBIE_OP_S: ngeo = FarLayout<R, SBIE_OP_S>::GEO; napp = FarLayout<R, SBIE_OP_S>::APP; break;
+    case SBIE_OP_D: ngeo = FarLayout<R, SBIE_OP_D>::GEO; napp = FarLayout<R, SBIE_OP_D>::APP; break;
+    case SBIE_OP_SP: ngeo = FarLayout<R, SBIE_OP_SP>::GEO; napp = FarLayout<R, SBIE_OP_SP>::APP; break;
+    default: ngeo = FarLayout<R, SBIE_OP_DP>::GEO; napp = FarLayout<R, SBIE_OP_DP>::APP; break;
+  }
+  *lds = (size_t)kChunk * (ngeo + napp + 16 * (wg->x / 64)) * sizeof(R);
+  if (op == SBIE_OP_D && FarLayout<R, SBIE_OP_D>::X3)  // the double layer's row stash
+    *lds += (size_t)(wg->x / 64) * PS::RBMAX * 64 * (sizeof(double) + sizeof(R));
+}
+
+template <typename R>
+sbie_status launch_strengths(sbie_geom* g, int op, const double* d_dens, R* app, hipStream_t s) {
+  const int64_t n16 = (int64_t)g->M * g->T16;
+  const dim3 pre(cdiv(n16, 256)), blk(256);
+  if (op == SBIE_OP_S)
+    hipLaunchKernelGGL((k_far_strengths<R, SBIE_OP_S>), pre, blk, 0, s, g->d_part, d_dens, g->d_x, g->d_y, g->d_z,
+                       g->d_nx, g->d_ny, g->d_nz, g->d_w, g->M, g->T, g->T16, app);
+  else
+    hipLaunchKernelGGL((k_far_strengths<R, SBIE_OP_D>), pre, blk, 0, s, g->d_part, d_dens, g->d_x, g->d_y, g->d_z,
+                       g->d_nx, g->d_ny, g->d_nz, g->d_w, g->M, g->T, g->T16, app);
+  SBIE_HIP(hipGetLastError());
+  return SBIE_OK;
+}
+
 template <typename R>
 sbie_status launch_far(sbie_geom* g, int op, const double* d_dens, const R* geo, const R* geo_x3, R* app,
                        hipStream_t s, hipEvent_t ev_begin, hipEvent_t ev_end) {
@@ -942,6 +1010,77 @@ sbie_status far_mfma(sbie_geom* g, int op, int prec, const double* d_dens, hipSt
   if (prec == SBIE_MIXED)
     return launch_far<float>(g, op, d_dens, g->d_srec32, g->d_srecx, g->d_fstr32, s, ev_begin, ev_end);
   return launch_far<double>(g, op, d_dens, g->d_srec64, nullptr, g->d_fstr64, s, ev_begin, ev_end);
+}
+
+bool far_batch_fits(const sbie_geom* g) {
+  const int pmax = (g->M - 1) / 2 + ((g->M & 1) == 0 ? 1 : 0);
+  return g->T >= 32 && pmax <= g->rev_slots;
+}
+
+sbie_status far_strengths(sbie_geom* g, int op, int prec, const double* d_dens, hipStream_t s) {
+  if (prec == SBIE_MIXED) return launch_strengths<float>(g, op, d_dens, g->d_fstr32, s);
+  return launch_strengths<double>(g, op, d_dens, g->d_fstr64, s);
+}
+
+int far_batch_job(const sbie_geom* g, int op, int prec, int wg_begin, FarJob* job) {
+  const bool mixed = prec == SBIE_MIXED;
+  const int RG = far_row_groups(g, !mixed);
+  const int nsplit = far_launch_splits(g, RG);
+  const bool x3 = mixed;  // the mixed S and D operands are the three-piece form
+  job->geo = mixed ? (x3 ? (const void*)g->d_srecx : (const void*)g->d_srec32) : (const void*)g->d_srec64;
+  job->app = mixed ? (const void*)g->d_fstr32 : (const void*)g->d_fstr64;
+  job->part = g->d_part;
+  job->x = g->d_x;
+  job->y = g->d_y;
+  job->z = g->d_z;
+  job->excl = g->d_excl;
+  job->words = g->excl_words;
+  job->M = g->M;
+  job->T = g->T;
+  job->T16 = g->T16;
+  job->N = g->N;
+  job->nsplit = nsplit;
+  job->RG = RG;
+  job->kend = g->rev_slots;
+  job->wg_begin = wg_begin;
+  job->fwd = g->d_partial;
+  job->rev = g->d_rev;
+  (void)op;
+  return g->M * RG * nsplit;
+}
+
+sbie_status far_batch_launch(sbie_geom* const* gs, int n, const FarJob* d_jobs, int total_wg, int op, int prec,
+                             hipStream_t s) {
+  if (n < 1) return SBIE_OK;
+  const bool mixed = prec == SBIE_MIXED;
+  dim3 wg;
+  size_t lds = 0;
+  if (mixed) pair_launch_shape<float>(gs[0], op, &wg, &lds);
+  else pair_launch_shape<double>(gs[0], op, &wg, &lds);
+  const dim3 grid((unsigned)total_wg);
+  if (mixed && op == SBIE_OP_S)
+    hipLaunchKernelGGL((k_far_pairs_batch<float, SBIE_OP_S>), grid, wg, lds, s, d_jobs, n);
+  else if (mixed)
+    hipLaunchKernelGGL((k_far_pairs_batch<float, SBIE_OP_D>), grid, wg, lds, s, d_jobs, n);
+  else if (op == SBIE_OP_S)
+    hipLaunchKernelGGL((k_far_pairs_batch<double, SBIE_OP_S>), grid, wg, lds, s, d_jobs, n);
+  else
+    hipLaunchKernelGGL((k_far_pairs_batch<double, SBIE_OP_D>), grid, wg, lds, s, d_jobs, n);
+  SBIE_HIP(hipGetLastError());
+  // each geometry's reverse sums into its totals, as after its own single launch
+  for (int k = 0; k < n; ++k) {
+    sbie_geom* g = gs[k];
+    const int RG = far_row_groups(g, !mixed);
+    const dim3 fold((unsigned)cdiv(g->N, 256));
+    if (mixed)
+      hipLaunchKernelGGL(k_far_fold<float>, fold, dim3(256), 0, s, reinterpret_cast<const float*>(g->d_rev), g->M,
+                         g->T, RG, 0, g->rev_slots, 1, g->N, g->d_racc);
+    else
+      hipLaunchKernelGGL(k_far_fold<double>, fold, dim3(256), 0, s, (const double*)g->d_rev, g->M, g->T, RG, 0,
+                         g->rev_slots, 1, g->N, g->d_racc);
+    SBIE_HIP(hipGetLastError());
+  }
+  return SBIE_OK;
 }
 
 }  // namespace sbie

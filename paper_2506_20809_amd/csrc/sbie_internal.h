@@ -40,6 +40,34 @@ constexpr int kNearSplit = 4;
 // registers, few waves otherwise) split each list eight ways.
 constexpr int kStokesNearSplit = 8;
 
+// One geometry's share of a batched far-field launch (served sessions of one
+// order, operator and precision): the arguments of its own pair-kernel launch
+// over all partner offsets, and its first work index in the batch.
+struct FarJob {
+  const void* geo;
+  const void* app;
+  const Particle* part;
+  const double *x, *y, *z;
+  const uint32_t* excl;
+  int words, M, T, T16;
+  int64_t N;
+  int nsplit, RG, kend, wg_begin;
+  double* fwd;
+  void* rev;
+};
+
+// One geometry's share of a batched near-field launch (Laplace S and D).
+struct NearJob {
+  const Particle* part;
+  const double *x, *y, *z;
+  const int32_t *near_ptr, *near_src;
+  const double *E, *lam, *ab, *rcp;
+  int p, T, chunks, wg_begin;
+  int64_t N;
+  unsigned* status;
+  double* unear;
+};
+
 // Order dispatch of the near-field kernels: the orders 8, 12, 16 and 32 get
 // kernels of their exact order (f(PMAX, true)), whose degree loops then carry
 // no runtime bounds; other orders the next larger of 8, 16, 32 (f(PMAX, false)).
@@ -347,6 +375,36 @@ int far_rev_slots(int M, int T);
 // about 512 workgroups (two per compute unit), at most the geometry's nsplit
 // slices, and at least four partners per split.
 int far_launch_splits(const sbie_geom* g, int RG);
+
+// Batched far field of several geometries of one order, operator (S or D)
+// and precision, each in one launch's worth of partner offsets: whether g
+// qualifies, its per-apply source strengths, its job (returns its workgroup
+// count), and the batched launch over the jobs (a device copy) with each
+// geometry's fold of its reverse sums after it.
+bool far_batch_fits(const sbie_geom* g);
+
+// Job tables of batched applies: pinned host staging and device copies of up
+// to cap jobs each.  The host side is rewritten by the next batch, so the
+// stream must have consumed the previous copies (the served lanes synchronise
+// after every batch).
+struct BatchJobs {
+  int cap = 0;
+  FarJob *h_far = nullptr, *d_far = nullptr;
+  NearJob *h_near = nullptr, *d_near = nullptr;
+};
+
+// S or D applied to n geometries of one order at once (served sessions): each
+// geometry's transform, self part and strengths, then one near launch and one
+// far launch over all of them, then each geometry's folds and assembly.  The
+// kernels, data and order of every geometry's arithmetic are those of
+// apply_laplace with all parts, so each result is bitwise the same.  Every
+// geometry must satisfy far_batch_fits and share the order.
+sbie_status far_strengths(sbie_geom* g, int op, int prec, const double* d_dens, hipStream_t s);
+int far_batch_job(const sbie_geom* g, int op, int prec, int wg_begin, FarJob* job);
+sbie_status far_batch_launch(sbie_geom* const* gs, int n, const FarJob* d_jobs, int total_wg, int op, int prec,
+                             hipStream_t s);
+sbie_status apply_laplace_batch(sbie_geom* const* gs, int n, int op, int prec, const double* const* d_dens,
+                                double* const* d_out, BatchJobs* jobs, hipStream_t s);
 sbie_status far_records(sbie_geom* g, hipStream_t s);
 sbie_status far_mfma(sbie_geom* g, int op, int prec, const double* d_dens, hipStream_t s, hipEvent_t ev_begin,
                      hipEvent_t ev_end);

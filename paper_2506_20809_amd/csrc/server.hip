@@ -2,7 +2,10 @@
 // (a host thread and a stream each), each session's apply captured once as a
 // HIP graph and replayed.  The kernels are those of sbie_apply, launched in the
 // same order on the same data layout, so a session's results are bitwise those
-// of a plain apply, alone or in the mix.
+// of a plain apply, alone or in the mix.  With batching a lane may hold several
+// sessions of one operator, precision and order and run their applies together
+// (apply_laplace_batch: one near and one far launch for all of them), again
+// bitwise as their plain applies.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -77,6 +80,21 @@ using Clock = std::chrono::steady_clock;
 
 int nrhs_of(int op) { return op == SBIE_OP_STOKES_S ? 3 : 1; }
 
+constexpr int kServeBatch = 4;            // sessions one batching lane holds at most
+constexpr int64_t kBatchMaxNodes = 65536;  // larger sessions fill the device alone
+
+// Whether a session may share a batched apply: a small S or D session (a
+// larger one gains nothing from company and would only delay its partners)
+// whose far field runs in one pair-kernel launch (T >= 32 and every partner
+// offset in the reverse budget), the conditions of apply_laplace_batch.
+bool batchable_shape(int M, int p, int op) {
+  if (op != SBIE_OP_S && op != SBIE_OP_D) return false;
+  const int T = (p + 1) * (2 * p + 2);
+  if ((int64_t)M * T > kBatchMaxNodes) return false;
+  const int pmax = (M - 1) / 2 + ((M & 1) == 0 ? 1 : 0);
+  return T >= 32 && pmax <= far_rev_slots(M, T);
+}
+
 }  // namespace
 }  // namespace sbie
 
@@ -89,7 +107,7 @@ struct sbie_session {
   int64_t N = 0;
   uint64_t plan = 0, bytes = 0;  // geometry block, whole arena share
   size_t off = 0;
-  bool admitted = false, closing = false, failed = false, counted_wait = false;
+  bool admitted = false, closing = false, failed = false, counted_wait = false, batchable = false;
   sbie_status fail = SBIE_OK;
   std::string fail_msg;
   sbie_geom* g = nullptr;
@@ -104,6 +122,7 @@ struct sbie_session {
 struct sbie_server {
   int device = 0;
   bool graphs = false;
+  bool batch = false;  // lanes may hold several compatible sessions
   sbie::Arena arena;
   std::mutex mu;
   // Every HIP graph call of the lanes (capture, instantiation, launch,
@@ -118,33 +137,53 @@ struct sbie_server {
   int passes = 0;  // admissions in a row that passed the head of the queue
   std::vector<std::thread> threads;
   std::vector<sbie_ctx*> lane_ctx;
-  std::vector<unsigned*> lane_status;  // pinned host word per lane
+  std::vector<unsigned*> lane_status;  // pinned host words per lane, one per held session
+  std::vector<sbie::BatchJobs> lane_jobs;  // batched-apply job tables per lane
   std::vector<bool> lane_idle;
+  std::vector<int> lane_held;  // sessions each lane holds
   std::unordered_map<uint64_t, sbie::Job*> jobs;
   uint64_t next_ticket = 1;
   int64_t next_session = 1;
   bool stopping = false;
   sbie::Clock::time_point t0;
-  int64_t n_active = 0, n_admitted = 0, n_passed = 0, n_waited = 0, n_applies = 0;
+  int64_t n_active = 0, n_admitted = 0, n_passed = 0, n_waited = 0, n_applies = 0, n_batched = 0;
 
   double now_us() const {
     return std::chrono::duration<double, std::micro>(sbie::Clock::now() - t0).count();
   }
+  int lane_cap() const { return batch ? sbie::kServeBatch : 1; }
+  // a lane that holds sessions admits more only when no lane is empty: the
+  // sessions spread over the lanes first and share them only beyond that
+  bool lane_may_admit(int lane) const {
+    if (lane_held[lane] == 0) return true;
+    if (lane_held[lane] >= lane_cap()) return false;
+    for (int h : lane_held)
+      if (h == 0) return false;
+    return true;
+  }
+  // A session may be admitted or memory was returned: wake the lanes that
+  // could take it.
   void wake_idle_lanes() {
     for (size_t k = 0; k < lane_cv.size(); ++k)
-      if (lane_idle[k]) lane_cv[k]->notify_one();
+      if (lane_idle[k] || (batch && lane_may_admit((int)k))) lane_cv[k]->notify_one();
   }
 };
 
 namespace sbie {
 namespace {
 
-// Admission (lock held): the first pending session that fits the arena, where
-// a session may pass the head of the queue only SBIE_MAX_PASS times in a row.
-sbie_session* admit_locked(sbie_server* srv, int lane) {
+bool same_batch(const sbie_session* a, const sbie_session* b) {
+  return a->batchable && b->batchable && a->op == b->op && a->prec == b->prec && a->p == b->p;
+}
+
+// Admission (lock held): the first pending session that fits the arena (and,
+// for a lane that holds sessions, batches with them), where a session may pass
+// the head of the queue only SBIE_MAX_PASS times in a row.
+sbie_session* admit_locked(sbie_server* srv, int lane, const sbie_session* key) {
   for (size_t idx = 0; idx < srv->pending.size(); ++idx) {
     if (idx > 0 && srv->passes >= SBIE_MAX_PASS) break;
     sbie_session* s = srv->pending[idx];
+    if (key && !same_batch(key, s)) continue;
     size_t off = 0;
     if (srv->arena.alloc(s->bytes, &off)) {
       s->off = off;
@@ -230,6 +269,20 @@ sbie_status enqueue_apply(sbie_server* srv, sbie_session* s, Job* j, hipStream_t
   return SBIE_OK;
 }
 
+// The apply's outcome from its near-field status word; a set word is cleared
+// for the next apply.
+sbie_status status_of(sbie_session* s, unsigned status, hipStream_t st, std::string* err) {
+  if (!status) return SBIE_OK;
+  SBIE_HIP(hipMemsetAsync(s->g->d_status, 0, sizeof(unsigned), st));
+  SBIE_HIP(hipStreamSynchronize(st));
+  if (status & kStatExterior) {
+    *err = "a near-field target lies inside its source spheroid";
+    return SBIE_E_OVERLAP;
+  }
+  *err = "continued fraction for Q_N/Q_{N-1} did not converge at a near-field target";
+  return SBIE_E_NUMERIC;
+}
+
 // One apply: its queue, then the wait.  The stream is synchronised on every
 // path, so the caller's buffers are no longer read or written once the job is
 // marked done.
@@ -252,18 +305,55 @@ sbie_status run_apply(sbie_server* srv, sbie_session* s, Job* j, int lane, std::
     *err = sbie_last_error();
     return ds;
   }
-  const unsigned status = *hs;
-  if (status) {
-    SBIE_HIP(hipMemsetAsync(s->g->d_status, 0, sizeof(unsigned), st));
-    SBIE_HIP(hipStreamSynchronize(st));
-    if (status & kStatExterior) {
-      *err = "a near-field target lies inside its source spheroid";
-      return SBIE_E_OVERLAP;
+  return status_of(s, *hs, st, err);
+}
+
+// Batched applies (lock not held): every session's input, one
+// apply_laplace_batch, every status word and output; then the wait.  Each
+// session gets its own status, as from run_apply.
+void run_batch(sbie_server* srv, const std::vector<sbie_session*>& ss, const std::vector<Job*>& js, int lane,
+               std::vector<sbie_status>* rc, std::vector<std::string>* err) {
+  const int n = (int)ss.size();
+  hipStream_t st = srv->lane_ctx[lane]->stream;
+  unsigned* hs = srv->lane_status[lane];
+  auto enqueue = [&]() -> sbie_status {
+    std::vector<sbie_geom*> gs(n);
+    std::vector<const double*> din(n);
+    std::vector<double*> dout(n);
+    for (int k = 0; k < n; ++k) {
+      sbie_session* s = ss[k];
+      hs[k] = 0u;
+      gs[k] = s->g;
+      din[k] = s->d_in;
+      dout[k] = s->d_out;
+      SBIE_HIP(hipMemcpyAsync(s->d_in, js[k]->din, sizeof(double) * (size_t)s->N,
+                              js[k]->devptr ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
     }
-    *err = "continued fraction for Q_N/Q_{N-1} did not converge at a near-field target";
-    return SBIE_E_NUMERIC;
+    sbie_status q =
+        apply_laplace_batch(gs.data(), n, ss[0]->op, ss[0]->prec, din.data(), dout.data(), &srv->lane_jobs[lane], st);
+    if (q != SBIE_OK) return q;
+    for (int k = 0; k < n; ++k) {
+      sbie_session* s = ss[k];
+      SBIE_HIP(hipMemcpyAsync(hs + k, s->g->d_status, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+      SBIE_HIP(hipMemcpyAsync(js[k]->dout, s->d_out, sizeof(double) * (size_t)s->N,
+                              js[k]->devptr ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+    }
+    return SBIE_OK;
+  };
+  const sbie_status q = enqueue();
+  const hipError_t se = hipStreamSynchronize(st);
+  rc->assign(n, SBIE_OK);
+  err->assign(n, std::string());
+  if (q != SBIE_OK || se != hipSuccess) {
+    const sbie_status bad = q != SBIE_OK ? q : device_error(se, "hipStreamSynchronize");
+    const std::string msg = sbie_last_error();
+    for (int k = 0; k < n; ++k) {
+      (*rc)[k] = bad;
+      (*err)[k] = msg;
+    }
+    return;
   }
-  return SBIE_OK;
+  for (int k = 0; k < n; ++k) (*rc)[k] = status_of(ss[k], hs[k], st, &(*err)[k]);
 }
 
 void teardown(sbie_server* srv, sbie_session* s) {
@@ -278,60 +368,114 @@ void teardown(sbie_server* srv, sbie_session* s) {
   s->g = nullptr;
 }
 
+// Completion of one apply (lock held).
+void finish_job(sbie_server* srv, sbie_session* s, Job* j, int lane, sbie_status rc, const std::string& err) {
+  j->status = rc;
+  j->err = err;
+  j->stats.end_us = srv->now_us();
+  j->stats.session = s->id;
+  j->stats.lane = lane;
+  j->stats.status = rc;
+  j->stats.open_us = s->open_us;
+  j->stats.admit_us = s->admit_us;
+  j->stats.ready_us = s->ready_us;
+  j->done = true;
+  ++srv->n_applies;
+}
+
+// A lane: admits sessions (one, or with batching up to kServeBatch of one
+// kind), runs their applies in submission order per session (the front
+// applies of all its sessions together when there are several), and tears a
+// session down once it is closed and drained.
 void lane_main(sbie_server* srv, int lane) {
   (void)hipSetDevice(srv->device);
   std::unique_lock<std::mutex> lk(srv->mu);
-  sbie_session* cur = nullptr;
+  std::vector<sbie_session*> held;
   for (;;) {
-    if (!cur) {
-      cur = admit_locked(srv, lane);
-      if (cur) {
+    if (!srv->stopping && srv->lane_may_admit(lane)) {
+      sbie_session* s = admit_locked(srv, lane, held.empty() ? nullptr : held[0]);
+      if (s) {
+        held.push_back(s);
+        srv->lane_held[lane] = (int)held.size();
         srv->lane_idle[lane] = false;
         lk.unlock();
-        build_session(srv, cur, lane);
+        build_session(srv, s, lane);
         lk.lock();
         continue;
       }
-      if (srv->stopping) break;
-      srv->lane_idle[lane] = true;
-      srv->lane_cv[lane]->wait(lk);
-      continue;
     }
-    if (!cur->queue.empty()) {
-      Job* j = cur->queue.front();
-      cur->queue.pop_front();
+    // the sessions with queued applies; a failed one answers at once, alone
+    std::vector<sbie_session*> ready;
+    sbie_session* failed = nullptr;
+    for (sbie_session* s : held) {
+      if (s->queue.empty()) continue;
+      if (s->failed && !failed) failed = s;
+      if (!s->failed) ready.push_back(s);
+    }
+    if (failed || ready.size() == 1) {
+      sbie_session* s = failed ? failed : ready[0];
+      Job* j = s->queue.front();
+      s->queue.pop_front();
       j->stats.start_us = srv->now_us();
       lk.unlock();
       std::string err;
-      const sbie_status rc = run_apply(srv, cur, j, lane, &err);
+      const sbie_status rc = run_apply(srv, s, j, lane, &err);
       lk.lock();
-      j->status = rc;
-      j->err = err;
-      j->stats.end_us = srv->now_us();
-      j->stats.session = cur->id;
-      j->stats.lane = lane;
-      j->stats.status = rc;
-      j->stats.open_us = cur->open_us;
-      j->stats.admit_us = cur->admit_us;
-      j->stats.ready_us = cur->ready_us;
-      j->done = true;
-      ++srv->n_applies;
+      finish_job(srv, s, j, lane, rc, err);
       srv->cv_done.notify_all();
       continue;
     }
-    if (cur->closing || srv->stopping) {
+    if (ready.size() > 1) {
+      std::vector<Job*> js;
+      for (sbie_session* s : ready) {
+        js.push_back(s->queue.front());
+        s->queue.pop_front();
+        js.back()->stats.start_us = srv->now_us();
+      }
       lk.unlock();
-      teardown(srv, cur);
+      std::vector<sbie_status> rc;
+      std::vector<std::string> err;
+      run_batch(srv, ready, js, lane, &rc, &err);
       lk.lock();
-      srv->arena.release(cur->off, cur->bytes);
+      for (size_t k = 0; k < ready.size(); ++k) finish_job(srv, ready[k], js[k], lane, rc[k], err[k]);
+      srv->n_batched += (int64_t)ready.size();
+      srv->cv_done.notify_all();
+      continue;
+    }
+    // closed (or stopping) and drained: tear down, return the memory
+    bool released = false;
+    for (size_t k = 0; k < held.size(); ++k) {
+      sbie_session* s = held[k];
+      if (!(s->closing || srv->stopping)) continue;
+      held.erase(held.begin() + k);
+      srv->lane_held[lane] = (int)held.size();
+      lk.unlock();
+      teardown(srv, s);
+      lk.lock();
+      srv->arena.release(s->off, s->bytes);
       --srv->n_active;
-      srv->sessions.erase(cur);
-      delete cur;
-      cur = nullptr;
+      srv->sessions.erase(s);
+      delete s;
+      released = true;
+      break;
+    }
+    if (released) {
       srv->wake_idle_lanes();  // memory returned: waiting sessions may fit now
       continue;
     }
+    if (held.empty() && srv->stopping) break;
+    srv->lane_idle[lane] = held.empty();
     srv->lane_cv[lane]->wait(lk);
+  }
+}
+
+void free_batch_jobs(sbie_server* srv) {
+  for (BatchJobs& b : srv->lane_jobs) {
+    if (b.h_far) (void)hipHostFree(b.h_far);
+    if (b.h_near) (void)hipHostFree(b.h_near);
+    if (b.d_far) (void)hipFree(b.d_far);
+    if (b.d_near) (void)hipFree(b.d_near);
+    b = BatchJobs();
   }
 }
 
@@ -366,6 +510,7 @@ sbie_status sbie_server_create(sbie_ctx* ctx, int32_t max_sessions, uint64_t hbm
   if (!srv) return SBIE_E_NOMEM;
   srv->device = ctx->device;
   srv->graphs = (flags & SBIE_SERVER_GRAPHS) != 0;
+  srv->batch = (flags & SBIE_SERVER_BATCH) != 0;
   srv->t0 = Clock::now();
   const size_t bytes = align_up(hbm_budget_bytes);
   hipError_t e = hipMalloc((void**)&srv->arena.base, bytes);
@@ -380,6 +525,7 @@ sbie_status sbie_server_create(sbie_ctx* ctx, int32_t max_sessions, uint64_t hbm
   auto fail = [&](sbie_status st) {
     for (sbie_ctx* c : srv->lane_ctx) sbie_ctx_destroy(c);
     for (unsigned* h : srv->lane_status) (void)hipHostFree(h);
+    free_batch_jobs(srv);
     (void)hipFree(srv->arena.base);
     delete srv;
     return st;
@@ -390,11 +536,22 @@ sbie_status sbie_server_create(sbie_ctx* ctx, int32_t max_sessions, uint64_t hbm
     if (st != SBIE_OK) return fail(st);
     srv->lane_ctx.push_back(c);
     unsigned* h = nullptr;
-    e = hipHostMalloc((void**)&h, sizeof(unsigned), hipHostMallocDefault);
+    e = hipHostMalloc((void**)&h, sizeof(unsigned) * kServeBatch, hipHostMallocDefault);
     if (e != hipSuccess) return fail(device_error(e, "hipHostMalloc"));
     srv->lane_status.push_back(h);
+    srv->lane_jobs.emplace_back();
+    if (srv->batch) {
+      BatchJobs& b = srv->lane_jobs.back();
+      if ((e = hipHostMalloc((void**)&b.h_far, sizeof(FarJob) * kServeBatch, hipHostMallocDefault)) != hipSuccess ||
+          (e = hipHostMalloc((void**)&b.h_near, sizeof(NearJob) * kServeBatch, hipHostMallocDefault)) != hipSuccess ||
+          (e = hipMalloc((void**)&b.d_far, sizeof(FarJob) * kServeBatch)) != hipSuccess ||
+          (e = hipMalloc((void**)&b.d_near, sizeof(NearJob) * kServeBatch)) != hipSuccess)
+        return fail(device_error(e, "batch job tables"));
+      b.cap = kServeBatch;
+    }
     srv->lane_cv.emplace_back(new std::condition_variable);
     srv->lane_idle.push_back(false);
+    srv->lane_held.push_back(0);
   }
   for (int k = 0; k < max_sessions; ++k) srv->threads.emplace_back(lane_main, srv, k);
   *out = srv;
@@ -425,6 +582,7 @@ void sbie_server_destroy(sbie_server* srv) {
   for (auto& kv : srv->jobs) delete kv.second;
   for (sbie_ctx* c : srv->lane_ctx) sbie_ctx_destroy(c);
   for (unsigned* h : srv->lane_status) (void)hipHostFree(h);
+  free_batch_jobs(srv);
   (void)hipFree(srv->arena.base);
   delete srv;
 }
@@ -453,6 +611,7 @@ sbie_status sbie_session_open(sbie_server* srv, const double* centers, const dou
   s->N = (int64_t)M * (p + 1) * (2 * p + 2);
   s->plan = plan_bytes(M, p, op == SBIE_OP_STOKES_S);
   s->bytes = sbie_session_bytes(M, p, op);
+  s->batchable = srv->batch && batchable_shape(M, p, (int)op);
   if (s->bytes > srv->arena.size) {
     set_error("the session needs " + std::to_string(s->bytes) + " bytes, more than the whole arena");
     delete s;
@@ -555,6 +714,7 @@ sbie_status sbie_server_get_info(sbie_server* srv, sbie_server_info* out) {
   out->applies = srv->n_applies;
   out->lanes = (int32_t)srv->threads.size();
   out->graphs = srv->graphs ? 1 : 0;
+  out->batched = srv->n_batched;
   return SBIE_OK;
 }
 

@@ -2,7 +2,8 @@
 // (hip_standin.cpp): plain geometries built and applied from the main thread,
 // then a served-mode run with graph replay, in which sixteen client threads
 // open forty small sessions on eight lanes and wait for their applies, as the
-// concurrent-clients GPU test does.  Kernels do not run, so the values are
+// concurrent-clients GPU test does, and the same with batching lanes (two
+// lanes, so that sessions of one kind share a lane and run together).  Kernels do not run, so the values are
 // not checked; the run checks statuses, and the sanitizer and the stand-in
 // check memory lifetimes and the serialisation of graph calls.
 //
@@ -89,12 +90,12 @@ void plain_path() {
   sbie_ctx_destroy(ctx);
 }
 
-void served_path() {
+void served_path(int lanes, uint32_t flags) {
   sbie_ctx* ctx = nullptr;
   check(sbie_ctx_create(0, &ctx), "sbie_ctx_create");
   if (!ctx) return;
   sbie_server* srv = nullptr;
-  check(sbie_server_create(ctx, 8, 256ull << 20, SBIE_SERVER_GRAPHS, &srv), "sbie_server_create");
+  check(sbie_server_create(ctx, lanes, 256ull << 20, flags, &srv), "sbie_server_create");
   if (!srv) return;
   const int nsess = 40, nclients = 16, napply = 5;
   auto client = [&](int t) {
@@ -125,8 +126,8 @@ void served_path() {
   for (auto& x : th) x.join();
   sbie_server_info info;
   check(sbie_server_get_info(srv, &info), "sbie_server_get_info");
-  std::printf("served: admitted %lld, applies %lld, lanes %d, graphs %d\n", (long long)info.admitted,
-              (long long)info.applies, info.lanes, info.graphs);
+  std::printf("served: admitted %lld, applies %lld, lanes %d, graphs %d%s\n", (long long)info.admitted,
+              (long long)info.applies, info.lanes, info.graphs, info.batched > 0 ? ", batched" : "");
   if (info.applies != (int64_t)nsess * napply) g_failures.fetch_add(1);
   sbie_server_destroy(srv);
   sbie_ctx_destroy(ctx);
@@ -136,7 +137,8 @@ void served_path() {
 
 int main() {
   plain_path();
-  served_path();
+  served_path(8, SBIE_SERVER_GRAPHS);
+  served_path(2, SBIE_SERVER_GRAPHS | SBIE_SERVER_BATCH);
   standin_report(stdout);
   const long v = standin_violations();
   std::printf("failures %d violations %ld\n", g_failures.load(), v);

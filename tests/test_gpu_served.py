@@ -300,3 +300,39 @@ def test_served_many_concurrent_clients(ctx):
         ref = _plain(ctx, g, p, k % 2, 0, dens[k])
         for r in range(5):
             assert np.array_equal(results[k][r], ref[r]), (k, r)
+
+
+@pytest.mark.parametrize("op,prec", [(0, 0), (1, 1)])
+def test_served_batched_bitwise_equals_plain(ctx, op, prec):
+    """Batching lanes: four sessions of one kind (operator, precision, order 8)
+    share a lane and run their applies in batched launches, a Stokes session
+    (which never batches) takes the other lane; every result equals its plain
+    apply bitwise."""
+    import paper_2506_20809_amd as sbie
+
+    p, napply = 8, 4
+    kinds = [(5, op), (12, 2), (9, op), (17, op), (30, op)]
+    geoms = [workloads.rsa_pack(M, 0.15, 0.05, 500 + k) for k, (M, _) in enumerate(kinds)]
+    precs = [prec if o != 2 else 0 for _, o in kinds]
+    nrhs = [3 if o == 2 else 1 for _, o in kinds]
+    dens = [_densities(napply, nrhs[k], len(g["A"]) * (p + 1) * (2 * p + 2), 700 + k) for k, g in enumerate(geoms)]
+    srv = sbie.Server(ctx, max_sessions=2, budget_bytes=1 << 30, graphs=True, batch=True)
+    sess = [srv.open(g, p, o, pr) for g, (_, o), pr in zip(geoms, kinds, precs)]
+    results = [[None] * napply for _ in sess]
+    for r in range(napply):
+        outs = [np.zeros_like(dens[k][r]) for k in range(len(sess))]
+        tickets = [s.submit(np.ascontiguousarray(dens[k][r]), outs[k]) for k, s in enumerate(sess)]
+        for t in tickets:
+            assert srv.wait(t).status == 0
+        for k in range(len(sess)):
+            results[k][r] = outs[k]
+    for s in sess:
+        s.close()
+    info = srv.info()
+    srv.close()
+    assert info.applies == napply * len(sess) and info.admitted == len(sess)
+    assert info.batched > 0, "no apply ran in a batch"
+    for k, (g, (_, o)) in enumerate(zip(geoms, kinds)):
+        ref = _plain(ctx, g, p, o, precs[k], dens[k])
+        for r in range(napply):
+            assert np.array_equal(results[k][r], ref[r]), (k, r, np.max(np.abs(results[k][r] - ref[r])))

@@ -7,7 +7,8 @@ next synchronise (as HIP permits), device memory is sanitizer-tracked host
 memory, and graph calls from several threads at once are flagged.  The driver
 (tests/hostrt/served_driver.cpp) builds plain geometries and applies from the
 main thread, then runs served mode with graph replay: sixteen client threads,
-forty sessions, eight lanes.
+forty sessions, eight lanes; then the same with batching on two lanes, where
+sessions of one kind share a lane and run in batched launches.
 
 These runs catch a host buffer released while a queued copy may still read it
 (the geometry set-up's reciprocal table once was), and graph calls that the
@@ -88,6 +89,7 @@ def test_host_code_under_sanitizer(san, tmp_path):
     assert "WARNING: ThreadSanitizer" not in log, log[-6000:]
     assert "LeakSanitizer" not in log, log[-6000:]
     assert res.returncode == 0, log[-6000:]
-    assert "served: admitted 40, applies 200, lanes 8, graphs 1" in log, log[-2000:]
+    assert "served: admitted 40, applies 200, lanes 8, graphs 1\n" in log, log[-2000:]
+    assert "served: admitted 40, applies 200, lanes 2, graphs 1, batched" in log, log[-2000:]
     assert "violations 0" in log, log[-2000:]
     shutil.rmtree(str(tmp_path), ignore_errors=True)

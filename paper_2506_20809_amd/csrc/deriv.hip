@@ -300,10 +300,16 @@ sbie_status apply_normal(sbie_geom* g, int op, int prec, const double* d_dens, d
     SBIE_HIP(hipGetLastError());
   }
   if (timed) SBIE_HIP(hipEventRecord(ev[7], s));
-  // far field on the pair-symmetric matrix-core kernel (T >= 32), small T on
-  // the vector-unit sums
-  const bool pairs = T >= 32;
-  if ((parts & SBIE_PARTS_FAR) && pairs) {
+  // far field through the tree (SBIE_FAR_TREE, FP64 sums), else on the
+  // pair-symmetric matrix-core kernel (T >= 32), small T on the vector-unit sums
+  const bool tree = (parts & SBIE_FAR_TREE) != 0;
+  const bool pairs = !tree && T >= 32;
+  if ((parts & SBIE_PARTS_FAR) && tree) {
+    if (timed) SBIE_HIP(hipEventRecord(ev[3], s));
+    sbie_status st = far_tree_normal(g, op, d_dens, s);
+    if (st) return st;
+    if (timed) SBIE_HIP(hipEventRecord(ev[4], s));
+  } else if ((parts & SBIE_PARTS_FAR) && pairs) {
     sbie_status st = far_mfma(g, op, prec, d_dens, s, timed ? ev[3] : nullptr, timed ? ev[4] : nullptr);
     if (st) return st;
   } else {

@@ -20,6 +20,11 @@
 // for the single layer (q = W sigma) and the double layer (d = W mu nu).  The
 // error falls geometrically in n at a rate set by theta.
 //
+// The interpolation is in the source point only, so the same proxies serve the
+// derivatives in the target (Theorem 3's S' and D', the target normal nu_x):
+//     nu_x . grad_x sum_k qhat_k G(x, s_k) = -sum_k qhat_k nu_x.(x - s_k) / (4 pi |x - s_k|^3),
+// with the single layer's charges for S' and the double layer's for D'.
+//
 // The plan is host code (no device needed).  The proxy charges are FP64
 // kernels, one workgroup per piece of a cluster; the sums take a target
 // particle per group of workgroups, in FP64, or in mixed precision with the
@@ -773,6 +778,111 @@ __global__ __launch_bounds__(1024) void k_tree_eval(const double* __restrict__ x
   }
 }
 
+// S' and D' through the tree (FP64), grid and lanes as k_tree_eval, with
+// d = x - y and the target normal nu_x:
+//   proxies (either operator) -qhat (nu_x.d) / r^3,
+//   direct S'  -q (nu_x.d) / r^3                           (records x, y, z, W sigma),
+//   direct D'  (nu_x.m) / r^3 - 3 (m.d)(nu_x.d) / r^5     (records x, y, z, m = W mu nu_y),
+// the kernels of the direct far sums of S' and D'.
+template <int OP, int TPT>
+__global__ __launch_bounds__(1024) void k_tree_eval_normal(
+    const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
+    const double* __restrict__ nx, const double* __restrict__ ny, const double* __restrict__ nz,
+    const double* __restrict__ src, const double* __restrict__ prox, const int64_t* __restrict__ pptr,
+    const int32_t* __restrict__ pidx, const int64_t* __restrict__ dptr, const int32_t* __restrict__ didx, int T,
+    int n3p, int nsplit, int64_t N, double* __restrict__ out) {
+  constexpr int SW = OP == SBIE_OP_SP ? 4 : 8;
+  const int t = blockIdx.x / nsplit, split = blockIdx.x % nsplit, tid = threadIdx.x;
+  const int64_t p0 = pptr[t], np = pptr[t + 1] - p0, d0 = dptr[t], nd = dptr[t + 1] - d0;
+  double tx[TPT], ty[TPT], tz[TPT], tn[TPT][3], acc[TPT];
+#pragma unroll
+  for (int k = 0; k < TPT; ++k) {
+    const int i = tid + k * blockDim.x;
+    const int64_t g = (int64_t)t * T + (i < T ? i : 0);
+    tx[k] = x[g];
+    ty[k] = y[g];
+    tz[k] = z[g];
+    tn[k][0] = nx[g];
+    tn[k][1] = ny[g];
+    tn[k][2] = nz[g];
+    acc[k] = 0.0;
+  }
+  for (int64_t m = p0 + np * split / nsplit; m < p0 + np * (split + 1) / nsplit; ++m) {
+    const double* P = prox + (int64_t)pidx[m] * n3p * 4;
+    for (int k = 0; k < n3p; k += 4) {
+#pragma unroll
+      for (int e = 0; e < TPT; ++e) {
+        double a[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double* r = P + 4 * (k + u);
+          const double dx = tx[e] - r[0], dy = ty[e] - r[1], dz = tz[e] - r[2];
+          const double ri = rsqrt_tree(fma(dz, dz, fma(dy, dy, dx * dx)));
+          const double nd_ = fma(tn[e][2], dz, fma(tn[e][1], dy, tn[e][0] * dx));
+          a[u] = -r[3] * nd_ * (ri * ri * ri);
+        }
+        acc[e] += (a[0] + a[1]) + (a[2] + a[3]);
+      }
+    }
+  }
+  for (int64_t m = d0 + nd * split / nsplit; m < d0 + nd * (split + 1) / nsplit; ++m) {
+    const double* rs = src + (int64_t)didx[m] * T * SW;
+    for (int j = 0; j < T; ++j) {
+      const double* r = rs + (int64_t)j * SW;
+#pragma unroll
+      for (int e = 0; e < TPT; ++e) {
+        const double dx = tx[e] - r[0], dy = ty[e] - r[1], dz = tz[e] - r[2];
+        const double ri = rsqrt_tree(fma(dz, dz, fma(dy, dy, dx * dx)));
+        const double ri3 = ri * ri * ri;
+        const double nd_ = fma(tn[e][2], dz, fma(tn[e][1], dy, tn[e][0] * dx));
+        if (OP == SBIE_OP_SP) {
+          acc[e] = fma(-r[3] * nd_, ri3, acc[e]);
+        } else {
+          const double md = fma(r[5], dz, fma(r[4], dy, r[3] * dx));
+          const double nm = fma(tn[e][2], r[5], fma(tn[e][1], r[4], tn[e][0] * r[3]));
+          acc[e] = fma(ri3, fma(-3.0 * md * nd_, ri * ri, nm), acc[e]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < TPT; ++k) {
+    const int i = tid + k * blockDim.x;
+    if (i < T) out[(size_t)split * N + (int64_t)t * T + i] = acc[k] * kInv4PiT;
+  }
+}
+
+// Absolute-coordinate source records of the tree for S' (x, y, z, W sigma)
+// and D' (x, y, z, W mu nu, 0, 0): the layouts of the single and double
+// layers' records, so their proxy charges serve unchanged.
+template <int OP>
+__global__ void k_tree_src_normal(const double* __restrict__ dens, const double* __restrict__ x,
+                                  const double* __restrict__ y, const double* __restrict__ z,
+                                  const double* __restrict__ nx, const double* __restrict__ ny,
+                                  const double* __restrict__ nz, const double* __restrict__ w, int64_t N,
+                                  double* __restrict__ src) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  const double q = w[g] * dens[g];
+  if (OP == SBIE_OP_SP) {
+    double* r = src + 4 * g;
+    r[0] = x[g];
+    r[1] = y[g];
+    r[2] = z[g];
+    r[3] = q;
+  } else {
+    double* r = src + 8 * g;
+    r[0] = x[g];
+    r[1] = y[g];
+    r[2] = z[g];
+    r[3] = q * nx[g];
+    r[4] = q * ny[g];
+    r[5] = q * nz[g];
+    r[6] = 0.0;
+    r[7] = 0.0;
+  }
+}
+
 inline unsigned cdiv_t(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
 template <int OP, int TPT>
@@ -782,6 +892,15 @@ void launch_eval(sbie_geom* g, hipStream_t s, int threads) {
   hipLaunchKernelGGL((k_tree_eval<OP, TPT>), dim3(g->M * g->nsplit), dim3(threads), 0, s, g->d_x, g->d_y, g->d_z,
                      g->d_src, tr.d_q, tr.d_pptr, tr.d_pidx, tr.d_dptr, tr.d_didx, g->T, (n3 + 3) & ~3, g->nsplit,
                      g->N, g->d_partial);
+}
+
+template <int OP, int TPT>
+void launch_eval_normal(sbie_geom* g, hipStream_t s, int threads) {
+  const FarTree& tr = *g->tree;
+  const int n3 = (tr.order + 1) * (tr.order + 1) * (tr.order + 1);
+  hipLaunchKernelGGL((k_tree_eval_normal<OP, TPT>), dim3(g->M * g->nsplit), dim3(threads), 0, s, g->d_x, g->d_y,
+                     g->d_z, g->d_nx, g->d_ny, g->d_nz, g->d_src, tr.d_q, tr.d_pptr, tr.d_pidx, tr.d_dptr, tr.d_didx,
+                     g->T, (n3 + 3) & ~3, g->nsplit, g->N, g->d_partial);
 }
 
 template <bool DIP>
@@ -930,6 +1049,48 @@ sbie_status build_tree(sbie_geom* g, double theta, int order, int leaf) {
                      g->d_z, g->d_part, M, T, T16, reinterpret_cast<u4*>(tr->d_srec));
   SBIE_HIP(hipGetLastError());
   SBIE_HIP(hipStreamSynchronize(s));
+  return SBIE_OK;
+}
+
+// Far field of S' or D' through the tree into the nsplit partial slices, in
+// FP64 for either precision.  The density's records overwrite d_src, which
+// the direct sums of S' and D' would read but the tree path does not.
+sbie_status far_tree_normal(sbie_geom* g, int op, const double* d_dens, hipStream_t s) {
+  const FarTree& tr = *g->tree;
+  const int T = g->T;
+  const int n3 = (tr.order + 1) * (tr.order + 1) * (tr.order + 1), n3p = (n3 + 3) & ~3;
+  const bool sp = op == SBIE_OP_SP;
+  if (sp)
+    hipLaunchKernelGGL(k_tree_src_normal<SBIE_OP_SP>, dim3(cdiv_t(g->N, 256)), dim3(256), 0, s, d_dens, g->d_x,
+                       g->d_y, g->d_z, g->d_nx, g->d_ny, g->d_nz, g->d_w, g->N, g->d_src);
+  else
+    hipLaunchKernelGGL(k_tree_src_normal<SBIE_OP_DP>, dim3(cdiv_t(g->N, 256)), dim3(256), 0, s, d_dens, g->d_x,
+                       g->d_y, g->d_z, g->d_nx, g->d_ny, g->d_nz, g->d_w, g->N, g->d_src);
+  SBIE_HIP(hipGetLastError());
+  if (tr.nused > 0) {
+    if (sp)
+      hipLaunchKernelGGL(k_tree_charges<SBIE_OP_S>, dim3(tr.npiece), dim3(256), 0, s, tr.d_box, tr.d_piece, tr.d_perm,
+                         g->d_src, T, tr.order, tr.d_qpart);
+    else
+      hipLaunchKernelGGL(k_tree_charges<SBIE_OP_D>, dim3(tr.npiece), dim3(256), 0, s, tr.d_box, tr.d_piece, tr.d_perm,
+                         g->d_src, T, tr.order, tr.d_qpart);
+    SBIE_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_tree_proxies, dim3(cdiv_t((int64_t)tr.nused * n3p, 256)), dim3(256), 0, s, tr.d_box,
+                       tr.d_cptr, tr.d_qpart, tr.nused, tr.order, n3p, n3p, tr.d_q, nullptr);
+    SBIE_HIP(hipGetLastError());
+  }
+  const int tpt = T <= 1024 ? 1 : (T <= 2048 ? 2 : 3);
+  const int threads = 64 * (int)cdiv_t(cdiv_t(T, tpt), 64);
+  if (sp) {
+    if (tpt == 1) launch_eval_normal<SBIE_OP_SP, 1>(g, s, threads);
+    else if (tpt == 2) launch_eval_normal<SBIE_OP_SP, 2>(g, s, threads);
+    else launch_eval_normal<SBIE_OP_SP, 3>(g, s, threads);
+  } else {
+    if (tpt == 1) launch_eval_normal<SBIE_OP_DP, 1>(g, s, threads);
+    else if (tpt == 2) launch_eval_normal<SBIE_OP_DP, 2>(g, s, threads);
+    else launch_eval_normal<SBIE_OP_DP, 3>(g, s, threads);
+  }
+  SBIE_HIP(hipGetLastError());
   return SBIE_OK;
 }
 

@@ -87,8 +87,9 @@ typedef enum {
 #define SBIE_PARTS_NEAR 0x20u  /* include the near field (near-field step of Algorithm 1) */
 #define SBIE_PARTS_FAR 0x40u   /* include the far field (far-field step of Algorithm 1) */
 #define SBIE_PARTS_ALL 0x70u   /* 0 also means all parts */
-#define SBIE_FAR_TREE 0x100u   /* S, D, S' or D': the far field from the geometry's tree
-                                  (sbie_geom_far_tree) instead of the direct sum */
+#define SBIE_FAR_TREE 0x100u   /* S, D, S', D', the Stokes single layer and its pressure: the
+                                  far field from the geometry's tree (sbie_geom_far_tree)
+                                  instead of the direct sum */
 #define SBIE_INPUT_COEFFS 0x200u /* S or D: the input is the coefficients [nrhs][M][(p+1)^2] of
                                   Algorithm 1's forward transform (layout of sbie_transform:
                                   l = n^2 + n + m; for S the modified-basis coefficients of
@@ -395,8 +396,9 @@ const char* sbie_last_error(void);
    particles are summed directly unless excluded.  Each far (target, source)
    particle pair is covered exactly once.  S' and D' (Theorem 3) use the same
    proxies, the single layer's charges resp. the double layer's, with the
-   kernel's derivative along the target normal, and sum in FP64 in either
-   precision.  For S and D the sums follow the apply's
+   kernel's derivative along the target normal; the Stokes single layer (and
+   its pressure) takes vector charges, the interpolated W sigma, with the
+   Stokeslet (Section 4.3).  These sum in FP64 in either precision.  For S and D the sums follow the apply's
    precision: FP64, or in SBIE_MIXED FP32 terms added four at a time into
    FP64 sums (squared distances on the matrix cores; the double layer's
    proxies then carry its dipole moments, interpolated, since its proxy

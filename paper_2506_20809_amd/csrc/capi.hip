@@ -273,8 +273,7 @@ sbie_status sbie_apply(sbie_geom* g, sbie_op op, sbie_precision prec, int32_t nr
   uint32_t parts = flags & SBIE_PARTS_ALL;
   if (parts == 0) parts = SBIE_PARTS_ALL;
   if (flags & SBIE_FAR_TREE) {
-    if (op != SBIE_OP_S && op != SBIE_OP_D && op != SBIE_OP_SP && op != SBIE_OP_DP)
-      return invalid("SBIE_FAR_TREE applies to S, D, S' and D' only");
+    if (op == SBIE_OP_STOKES_D) return invalid("SBIE_FAR_TREE does not apply to the Stokes double layer");
     if (!g->tree) {
       set_error("SBIE_FAR_TREE without a tree (sbie_geom_far_tree)");
       return SBIE_E_STATE;

@@ -272,6 +272,7 @@ sbie_status build_tree(sbie_geom* g, double theta, int order, int leaf);
 void free_tree(sbie_geom* g);
 sbie_status far_tree(sbie_geom* g, int op, bool mixed, hipStream_t s);
 sbie_status far_tree_normal(sbie_geom* g, int op, const double* d_dens, hipStream_t s);
+sbie_status far_tree_stokes(sbie_geom* g, int C, const double* d_dens, hipStream_t s);
 
 // Carves 256-byte aligned buffers out of one device block; with no block it
 // only measures.

@@ -363,7 +363,8 @@ sbie_status stokes_staging(sbie_geom* g, double** io) {
 namespace {
 
 template <int C>
-sbie_status stokes_parts(sbie_geom* g, bool mixed, hipStream_t s, uint32_t parts, hipEvent_t* ev, double* d_out);
+sbie_status stokes_parts(sbie_geom* g, bool mixed, hipStream_t s, uint32_t parts, hipEvent_t* ev,
+                         const double* d_dens, double* d_out);
 
 }  // namespace
 
@@ -398,15 +399,18 @@ sbie_status apply_stokes(sbie_geom* g, int prec, const double* d_dens, double* d
                        M, p, g->d_stk_E, g->d_stk_E + MK4);
     SBIE_HIP(hipGetLastError());
   }
-  return pressure ? stokes_parts<4>(g, mixed, s, parts, ev, d_out) : stokes_parts<3>(g, mixed, s, parts, ev, d_out);
+  return pressure ? stokes_parts<4>(g, mixed, s, parts, ev, d_dens, d_out)
+                  : stokes_parts<3>(g, mixed, s, parts, ev, d_dens, d_out);
 }
 
 namespace {
 
 // Near (side stream when the geometry has one), self and far parts of C
-// components, then the assembly into d_out [C][N].
+// components, then the assembly into d_out [C][N].  The far part comes from
+// the tree with SBIE_FAR_TREE (FP64 sums), else from the direct sum.
 template <int C>
-sbie_status stokes_parts(sbie_geom* g, bool mixed, hipStream_t s, uint32_t parts, hipEvent_t* ev, double* d_out) {
+sbie_status stokes_parts(sbie_geom* g, bool mixed, hipStream_t s, uint32_t parts, hipEvent_t* ev,
+                         const double* d_dens, double* d_out) {
   const int M = g->M, p = g->p, T = g->T, K = g->K;
   const int64_t N = g->N;
   const size_t MT4 = (size_t)4 * M * T, MK4 = (size_t)4 * M * K;
@@ -444,7 +448,9 @@ sbie_status stokes_parts(sbie_geom* g, bool mixed, hipStream_t s, uint32_t parts
   }
   if (timed) SBIE_HIP(hipEventRecord(ev[2], s));
   if (timed) SBIE_HIP(hipEventRecord(ev[3], s));
-  if (parts & SBIE_PARTS_FAR) {
+  if ((parts & SBIE_PARTS_FAR) && (parts & SBIE_FAR_TREE)) {
+    SBIE_TRY_C(far_tree_stokes(g, C, d_dens, s));
+  } else if (parts & SBIE_PARTS_FAR) {
     constexpr int TPT = 2;
     const dim3 grid(cdiv(N, 256 * TPT) * g->nsplit);
     if (mixed)

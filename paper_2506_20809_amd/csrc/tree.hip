@@ -20,6 +20,11 @@
 // for the single layer (q = W sigma) and the double layer (d = W mu nu).  The
 // error falls geometrically in n at a rate set by theta.
 //
+// Any kernel smooth in the source point interpolates the same way: the
+// Stokeslet (Section 4.3) takes vector charges qhat_k = sum_j q_j L_k(y_j) (q =
+// W sigma) and is evaluated at the proxies as it stands, and so is its
+// pressure kernel.
+//
 // The interpolation is in the source point only, so the same proxies serve the
 // derivatives in the target (Theorem 3's S' and D', the target normal nu_x):
 //     nu_x . grad_x sum_k qhat_k G(x, s_k) = -sum_k qhat_k nu_x.(x - s_k) / (4 pi |x - s_k|^3),
@@ -372,6 +377,38 @@ __global__ void k_tree_proxies(const double* __restrict__ box, const int32_t* __
   for (int p = pptr[c]; p < pptr[c + 1]; ++p) q += qpart[(int64_t)p * n3 + k];
   o[3] = q;
   if (q32) q32[i] = (float)q;
+}
+
+// Vector-charge proxy table of each used cluster for the Stokeslet, [nused][n3p]
+// records (s, qhat, 0, 0) of 8 doubles, the charges its pieces' partial
+// charges (kind kTreeDipoles) added in piece order; padding at a distant point
+// with zero charge.
+__global__ void k_tree_proxies3(const double* __restrict__ box, const int32_t* __restrict__ pptr,
+                                const double* __restrict__ qpart, int nused, int n, int n3p,
+                                double* __restrict__ prox) {
+  __shared__ double cs[kTreeMaxOrder + 1], cw[kTreeMaxOrder + 1];
+  cheb_table(n, cs, cw);
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)nused * n3p) return;
+  const int n1 = n + 1, n3 = n1 * n1 * n1;
+  const int c = (int)(i / n3p), k = (int)(i - (int64_t)c * n3p);
+  double* o = prox + 8 * i;
+  o[6] = o[7] = 0.0;
+  if (k >= n3) {
+    o[0] = o[1] = o[2] = 1e30;
+    o[3] = o[4] = o[5] = 0.0;
+    return;
+  }
+  const int idx[3] = {k / (n1 * n1), (k / n1) % n1, k % n1};
+  for (int d = 0; d < 3; ++d) {
+    const double lo = box[6 * c + d], hi = box[6 * c + 3 + d];
+    o[d] = lo + 0.5 * (cs[idx[d]] + 1.0) * (hi - lo);
+  }
+  double q[3] = {0.0, 0.0, 0.0};
+  for (int p = pptr[c]; p < pptr[c + 1]; ++p)
+    for (int w = 0; w < 3; ++w) q[w] += qpart[((int64_t)p * n3 + k) * 3 + w];
+  for (int w = 0; w < 3; ++w) o[3 + w] = q[w];
 }
 
 // Matrix-core form of the mixed path.  Sources are the rows of a 16x16x32 bf16
@@ -852,6 +889,79 @@ __global__ __launch_bounds__(1024) void k_tree_eval_normal(
   }
 }
 
+// The Stokeslet (1/8pi)(q/r + (d.q) d/r^3) and, for C = 4, the pressure
+// (1/4pi)(d.q)/r^3 (d = x - y) through the tree in FP64: proxies (s, qhat) and
+// direct far particles' records (y, W sigma), both 8 doubles; grid and lanes
+// as k_tree_eval; out [nsplit][C][N].
+template <int C, int TPT>
+__global__ __launch_bounds__(1024) void k_tree_eval_stokes(
+    const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
+    const double* __restrict__ src, const double* __restrict__ prox, const int64_t* __restrict__ pptr,
+    const int32_t* __restrict__ pidx, const int64_t* __restrict__ dptr, const int32_t* __restrict__ didx, int T,
+    int n3p, int nsplit, int64_t N, double* __restrict__ out) {
+  const int t = blockIdx.x / nsplit, split = blockIdx.x % nsplit, tid = threadIdx.x;
+  const int64_t p0 = pptr[t], np = pptr[t + 1] - p0, d0 = dptr[t], nd = dptr[t + 1] - d0;
+  double tx[TPT], ty[TPT], tz[TPT], acc[TPT][C];
+#pragma unroll
+  for (int k = 0; k < TPT; ++k) {
+    const int i = tid + k * blockDim.x;
+    const int64_t g = (int64_t)t * T + (i < T ? i : 0);
+    tx[k] = x[g];
+    ty[k] = y[g];
+    tz[k] = z[g];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[k][c] = 0.0;
+  }
+  // one source (r: point and vector charge) into every target of the lane
+  auto term = [&](const double* r) {
+#pragma unroll
+    for (int e = 0; e < TPT; ++e) {
+      const double dx = tx[e] - r[0], dy = ty[e] - r[1], dz = tz[e] - r[2];
+      const double ri = rsqrt_tree(fma(dz, dz, fma(dy, dy, dx * dx)));
+      const double f = fma(dz, r[5], fma(dy, r[4], dx * r[3])) * (ri * ri * ri);
+      acc[e][0] = fma(r[3], ri, fma(dx, f, acc[e][0]));
+      acc[e][1] = fma(r[4], ri, fma(dy, f, acc[e][1]));
+      acc[e][2] = fma(r[5], ri, fma(dz, f, acc[e][2]));
+      if constexpr (C == 4) acc[e][3] += f;
+    }
+  };
+  for (int64_t m = p0 + np * split / nsplit; m < p0 + np * (split + 1) / nsplit; ++m) {
+    const double* P = prox + (int64_t)pidx[m] * n3p * 8;
+    for (int k = 0; k < n3p; ++k) term(P + 8 * k);
+  }
+  for (int64_t m = d0 + nd * split / nsplit; m < d0 + nd * (split + 1) / nsplit; ++m) {
+    const double* rs = src + (int64_t)didx[m] * T * 8;
+    for (int j = 0; j < T; ++j) term(rs + 8 * j);
+  }
+#pragma unroll
+  for (int k = 0; k < TPT; ++k) {
+    const int i = tid + k * blockDim.x;
+    if (i < T)
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+        out[((size_t)split * C + c) * N + (int64_t)t * T + i] = acc[k][c] * (c < 3 ? 0.5 * kInv4PiT : kInv4PiT);
+  }
+}
+
+// Absolute-coordinate source records (y, W sigma, 0, 0) of the Stokeslet's
+// tree from the density [3][N].
+__global__ void k_tree_src_stokes(const double* __restrict__ dens, const double* __restrict__ x,
+                                  const double* __restrict__ y, const double* __restrict__ z,
+                                  const double* __restrict__ w, int64_t N, double* __restrict__ src) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  const double wq = w[g];
+  double* r = src + 8 * g;
+  r[0] = x[g];
+  r[1] = y[g];
+  r[2] = z[g];
+  r[3] = wq * dens[g];
+  r[4] = wq * dens[N + g];
+  r[5] = wq * dens[2 * N + g];
+  r[6] = 0.0;
+  r[7] = 0.0;
+}
+
 // Absolute-coordinate source records of the tree for S' (x, y, z, W sigma)
 // and D' (x, y, z, W mu nu, 0, 0): the layouts of the single and double
 // layers' records, so their proxy charges serve unchanged.
@@ -901,6 +1011,15 @@ void launch_eval_normal(sbie_geom* g, hipStream_t s, int threads) {
   hipLaunchKernelGGL((k_tree_eval_normal<OP, TPT>), dim3(g->M * g->nsplit), dim3(threads), 0, s, g->d_x, g->d_y,
                      g->d_z, g->d_nx, g->d_ny, g->d_nz, g->d_src, tr.d_q, tr.d_pptr, tr.d_pidx, tr.d_dptr, tr.d_didx,
                      g->T, (n3 + 3) & ~3, g->nsplit, g->N, g->d_partial);
+}
+
+template <int C, int TPT>
+void launch_eval_stokes(sbie_geom* g, const double* prox, hipStream_t s, int threads) {
+  const FarTree& tr = *g->tree;
+  const int n3 = (tr.order + 1) * (tr.order + 1) * (tr.order + 1);
+  hipLaunchKernelGGL((k_tree_eval_stokes<C, TPT>), dim3(g->M * g->nsplit), dim3(threads), 0, s, g->d_x, g->d_y,
+                     g->d_z, g->d_src, prox, tr.d_pptr, tr.d_pidx, tr.d_dptr, tr.d_didx, g->T, (n3 + 3) & ~3,
+                     g->nsplit, g->N, g->d_stk_part);
 }
 
 template <bool DIP>
@@ -1049,6 +1168,43 @@ sbie_status build_tree(sbie_geom* g, double theta, int order, int leaf) {
                      g->d_z, g->d_part, M, T, T16, reinterpret_cast<u4*>(tr->d_srec));
   SBIE_HIP(hipGetLastError());
   SBIE_HIP(hipStreamSynchronize(s));
+  return SBIE_OK;
+}
+
+// Far field of the Stokes single layer (C = 3) or with its pressure (C = 4)
+// through the tree into the nsplit partial slices of d_stk_part, in FP64 for
+// either precision.  The records overwrite d_src (the Laplace operators'
+// records, unused by the Stokes path); the vector-charge table takes the
+// memory of the mixed double layer's dipole records (8 doubles per proxy fit
+// its 16 words per proxy).
+sbie_status far_tree_stokes(sbie_geom* g, int C, const double* d_dens, hipStream_t s) {
+  const FarTree& tr = *g->tree;
+  const int T = g->T;
+  const int n3 = (tr.order + 1) * (tr.order + 1) * (tr.order + 1), n3p = (n3 + 3) & ~3;
+  double* prox = reinterpret_cast<double*>(tr.d_pdrec);
+  hipLaunchKernelGGL(k_tree_src_stokes, dim3(cdiv_t(g->N, 256)), dim3(256), 0, s, d_dens, g->d_x, g->d_y, g->d_z,
+                     g->d_w, g->N, g->d_src);
+  SBIE_HIP(hipGetLastError());
+  if (tr.nused > 0) {
+    hipLaunchKernelGGL(k_tree_charges<kTreeDipoles>, dim3(tr.npiece), dim3(256), 0, s, tr.d_box, tr.d_piece,
+                       tr.d_perm, g->d_src, T, tr.order, tr.d_qpart);
+    SBIE_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_tree_proxies3, dim3(cdiv_t((int64_t)tr.nused * n3p, 256)), dim3(256), 0, s, tr.d_box,
+                       tr.d_cptr, tr.d_qpart, tr.nused, tr.order, n3p, prox);
+    SBIE_HIP(hipGetLastError());
+  }
+  const int tpt = T <= 1024 ? 1 : (T <= 2048 ? 2 : 3);
+  const int threads = 64 * (int)cdiv_t(cdiv_t(T, tpt), 64);
+  if (C == 4) {
+    if (tpt == 1) launch_eval_stokes<4, 1>(g, prox, s, threads);
+    else if (tpt == 2) launch_eval_stokes<4, 2>(g, prox, s, threads);
+    else launch_eval_stokes<4, 3>(g, prox, s, threads);
+  } else {
+    if (tpt == 1) launch_eval_stokes<3, 1>(g, prox, s, threads);
+    else if (tpt == 2) launch_eval_stokes<3, 2>(g, prox, s, threads);
+    else launch_eval_stokes<3, 3>(g, prox, s, threads);
+  }
+  SBIE_HIP(hipGetLastError());
   return SBIE_OK;
 }
 

@@ -670,6 +670,8 @@ def main():
     ap.add_argument("--no-near", action="store_true", help="skip the near-field measurement")
     ap.add_argument("--tree-sweep", action="store_true",
                     help="add the FP64 tree's accuracy and time over several (theta, order)")
+    ap.add_argument("--only-stokes", action="store_true",
+                    help="only the Stokes single layer and its pressure (both precisions), for profiling")
     ap.add_argument("--only-near", action="store_true",
                     help="run only the near-field section (for counter runs); prints its JSON object")
     ap.add_argument("--served-requests", type=int, default=48,
@@ -708,6 +710,12 @@ def main():
     if args.only_near:
         ctx = sbie.Context(0)
         print(json.dumps({"near_field": run_near(ctx, max(2, args.steps // 4))}), flush=True)
+        ctx.close()
+        return
+    if args.only_stokes:
+        ctx = sbie.Context(0)
+        print(json.dumps({f"stokes_op{op}": {pr: run_stokes(ctx, max(2, args.steps // 2), 1, pr, op=op)
+                                              for pr in ("fp64", "mixed")} for op in (2, 5)}), flush=True)
         ctx.close()
         return
     geom = workloads.geometry(args.workload)

@@ -69,34 +69,6 @@ struct Mfma<double> {
   }
 };
 
-// v[k] summed over the 16 lanes of each row group (lanes l with the same
-// l/16), lane l keeping the sum for element l%16: recursive halving, in which
-// lanes l and l^d (d = 8, 4, 2, 1) each keep one half of the remaining
-// elements and add the partner's copy of that half.  The first two halvings
-// add in FP32 (each result then holds two roundings), the last two in FP64.
-template <int D, typename T>
-__device__ inline void halve(T (&v)[16], int lane) {
-  const bool hi = (lane & D) != 0;
-  const int addr = (lane ^ D) << 2;
-#pragma unroll
-  for (int k = 0; k < D; ++k) {
-    const T send = hi ? v[k] : v[D + k];
-    const T keep = hi ? v[D + k] : v[k];
-    v[k] = keep + lane_value(send, addr);
-  }
-}
-
-__device__ inline double row_group_sums(float (&v)[16], int lane) {
-  halve<8>(v, lane);
-  halve<4>(v, lane);
-  double w[16];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) w[k] = (double)v[k];
-  halve<2>(w, lane);
-  halve<1>(w, lane);
-  return w[0];
-}
-
 // per-apply strengths (app).  The mixed single and double layers keep their B
 // operands in the three-piece form, one u4 per lane; all others one R per
 // lane, the accumulator input per column after the B operand.
@@ -657,16 +629,6 @@ __device__ __forceinline__ void far_pairs_body(const R* __restrict__ geo, const 
       }
     }
   }
-}
-
-// Workgroups are dispatched round-robin over the eight XCDs (w mod 8).  Each
-// XCD gets a contiguous range of the work index instead, so that the
-// particles it holds at once are neighbours in index and share most of their
-// partners' source blocks in its L2.
-__device__ inline int xcd_work_index() {
-  const int G = (int)gridDim.x, w = (int)blockIdx.x;
-  const int xcd = w % 8, per = G / 8, extra = G % 8;
-  return xcd * per + (xcd < extra ? xcd : extra) + w / 8;
 }
 
 template <typename R, int OP>

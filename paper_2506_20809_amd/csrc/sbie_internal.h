@@ -17,6 +17,7 @@ namespace sbie {
 constexpr int kMaxP = 32;
 constexpr int kRcpN = 16384;  // reciprocal table length (near-field recurrences)
 constexpr size_t kRevBudget = size_t(128) << 20;  // reverse sums of one pair-kernel launch, bytes
+constexpr size_t kStokesRevBudget = size_t(128) << 20;  // the same for the Stokes pair kernel
 constexpr double kPi = 3.14159265358979323846264338327950288;
 
 // Per-particle parameters on the device (Section 2.1, Table 1).
@@ -185,6 +186,10 @@ struct sbie_geom {
   double* d_stk_self = nullptr;   // [4][N]
   double* d_stk_near = nullptr;   // [kStokesNearSplit][4][N] near partials per source-list range
   double* d_stk_io = nullptr;     // [7][N] staging of host densities and velocities
+  double* d_stk_prec = nullptr;   // [M][T16/16][160] source blocks of the pair kernel (FP64 or FP32)
+  double* d_stk_rev = nullptr;    // reverse sums of one pair-kernel launch (stk_rev_bytes)
+  double* d_stk_racc = nullptr;   // [4][N] running reverse totals
+  uint64_t stk_rev_bytes = 0;
   // Stokes double layer (stokes_dl.hip), in its own block carved on first use
   char* sdl_blk = nullptr;
   double* d_sdl_f = nullptr;      // [13M][T] transform inputs of the 13 expansion sets
@@ -273,6 +278,17 @@ void free_tree(sbie_geom* g);
 sbie_status far_tree(sbie_geom* g, int op, bool mixed, hipStream_t s);
 sbie_status far_tree_normal(sbie_geom* g, int op, const double* d_dens, hipStream_t s);
 sbie_status far_tree_stokes(sbie_geom* g, int C, const double* d_dens, hipStream_t s);
+
+// Stokes pair kernel (far_stokes.hip): row groups of a particle's 16-row
+// blocks, partner slots per launch within cap_bytes of reverse sums, forward
+// splits (at most the geometry's nsplit), the reverse buffer's size, and the
+// far field of C = 3 (velocity) or 4 (with the pressure) components into
+// d_stk_part's first stokes_pair_splits slices and d_stk_racc.
+int stokes_row_groups(int T, bool fp64);
+int stokes_rev_slots(int M, int T, int C, int bytes_per_value, uint64_t cap_bytes);
+int stokes_pair_splits(const sbie_geom* g, int RG);
+uint64_t stokes_rev_bytes(int M, int T);
+sbie_status far_stokes_pairs(sbie_geom* g, int C, bool mixed, const double* d_dens, hipStream_t s);
 
 // Carves 256-byte aligned buffers out of one device block; with no block it
 // only measures.

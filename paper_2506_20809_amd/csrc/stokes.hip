@@ -274,10 +274,12 @@ __global__ __launch_bounds__(256) void k_far_stokes(const R* __restrict__ rec, c
   }
 }
 
+// u = self + near slices + far slices in order (+ the pair kernel's running
+// reverse totals racc [C][N], 1/8pi resp. 1/4pi applied here, when set).
 template <int C>
 __global__ void k_stokes_assemble(const double* __restrict__ uself, const double* __restrict__ unear,
-                                  const double* __restrict__ partial, int nsplit, int64_t N, uint32_t parts,
-                                  double* __restrict__ out) {
+                                  const double* __restrict__ partial, int nsplit, const double* __restrict__ racc,
+                                  int64_t N, uint32_t parts, double* __restrict__ out) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= C * N) return;
   const int c = (int)(t / N);
@@ -289,6 +291,7 @@ __global__ void k_stokes_assemble(const double* __restrict__ uself, const double
   if (parts & SBIE_PARTS_FAR) {
     double f = 0.0;
     for (int s = 0; s < nsplit; ++s) f += partial[((size_t)s * C + c) * N + g];
+    if (racc) f += racc[t] * (c < 3 ? kInv8Pi : kInv4Pi);
     u += f;
   }
   out[t] = u;
@@ -323,6 +326,12 @@ sbie_status carve_stokes(sbie_geom* g, Carver& c) {
   SBIE_TRY_C(c.take(&g->d_stk_self, 4 * N));
   SBIE_TRY_C(c.take(&g->d_stk_near, (size_t)kStokesNearSplit * 4 * N));
   SBIE_TRY_C(c.take(&g->d_stk_io, 7 * N));
+  // the pair kernel's source blocks, reverse sums and totals
+  const size_t nb = (size_t)(g->T + 15) / 16;
+  g->stk_rev_bytes = stokes_rev_bytes(g->M, g->T);
+  SBIE_TRY_C(c.take(&g->d_stk_prec, (size_t)g->M * nb * 160));
+  SBIE_TRY_C(c.take(&g->d_stk_rev, (size_t)(g->stk_rev_bytes / sizeof(double))));
+  SBIE_TRY_C(c.take(&g->d_stk_racc, 4 * N));
   return SBIE_OK;
 }
 
@@ -448,8 +457,14 @@ sbie_status stokes_parts(sbie_geom* g, bool mixed, hipStream_t s, uint32_t parts
   }
   if (timed) SBIE_HIP(hipEventRecord(ev[2], s));
   if (timed) SBIE_HIP(hipEventRecord(ev[3], s));
-  if ((parts & SBIE_PARTS_FAR) && (parts & SBIE_FAR_TREE)) {
+  // far field: the tree, else the pair-symmetric matrix-core kernel (T >= 32),
+  // else the one-sided vector-unit sum
+  const bool tree = (parts & SBIE_FAR_TREE) != 0;
+  const bool pairs = !tree && T >= 32;
+  if ((parts & SBIE_PARTS_FAR) && tree) {
     SBIE_TRY_C(far_tree_stokes(g, C, d_dens, s));
+  } else if ((parts & SBIE_PARTS_FAR) && pairs) {
+    SBIE_TRY_C(far_stokes_pairs(g, C, mixed, d_dens, s));
   } else if (parts & SBIE_PARTS_FAR) {
     constexpr int TPT = 2;
     const dim3 grid(cdiv(N, 256 * TPT) * g->nsplit);
@@ -466,8 +481,9 @@ sbie_status stokes_parts(sbie_geom* g, bool mixed, hipStream_t s, uint32_t parts
   if (fork) SBIE_TRY_C(join_side(g, s));
   // with no near pairs the near part is empty and is left out of the sum
   const uint32_t sum_parts = g->n_near > 0 ? parts : (parts & ~(uint32_t)SBIE_PARTS_NEAR);
+  const int nslices = pairs ? stokes_pair_splits(g, stokes_row_groups(T, !mixed)) : g->nsplit;
   hipLaunchKernelGGL(k_stokes_assemble<C>, dim3(cdiv(C * N, B)), dim3(B), 0, s, g->d_stk_self, g->d_stk_near,
-                     g->d_stk_part, g->nsplit, N, sum_parts, d_out);
+                     g->d_stk_part, nslices, pairs ? (const double*)g->d_stk_racc : nullptr, N, sum_parts, d_out);
   SBIE_HIP(hipGetLastError());
   if (timed) SBIE_HIP(hipEventRecord(ev[5], s));
   return SBIE_OK;

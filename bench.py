@@ -150,6 +150,41 @@ def run(g, dens, steps, warmup, precision):
     }
 
 
+def run_multi(g, steps, precision, nrhs=4):
+    """S and D applied to nrhs densities per call (the shared far-field path),
+    against nrhs one-density calls: densities per second each way."""
+    import numpy as np
+    import torch
+
+    import paper_2506_20809_amd as sbie
+
+    prec = sbie.SBIE_MIXED if precision == "mixed" else sbie.SBIE_FP64
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(17)
+    dens = torch.randn((nrhs, g.N), dtype=torch.float64, device="cuda", generator=gen)
+    out = torch.empty_like(dens)
+    res = {"workload": f"{nrhs} densities per call, the headline suspension, precision={precision}"}
+    for op, name in ((sbie.SBIE_OP_S, "S"), (sbie.SBIE_OP_D, "D")):
+        rates = {}
+        for mode in ("shared", "one_by_one"):
+            def call():
+                if mode == "shared":
+                    g.apply(op, dens, precision=prec, out=out)
+                else:
+                    for k in range(nrhs):
+                        g.apply(op, dens[k], precision=prec, out=out[k])
+            call()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                call()
+            torch.cuda.synchronize()
+            rates[mode] = nrhs * steps / (time.perf_counter() - t0)
+        res[name] = {"densities_per_s_shared": rates["shared"], "densities_per_s_one_by_one": rates["one_by_one"],
+                     "speedup": rates["shared"] / rates["one_by_one"]}
+    return res
+
+
 # Stokeslet per far node pair: 3 differences + 5 for r^2 + 1 rsqrt + 2 for r^-3 + 5 for r.q
 # + 1 for (r.q) r^-3 + 3 x (FMA for q/r + FMA for r (r.q) r^-3) = 29
 FLOPS_PER_STOKES_PAIR = 29
@@ -668,6 +703,7 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="skip the completed double-layer solves")
     ap.add_argument("--no-tree", action="store_true", help="skip the tree far-field measurement")
     ap.add_argument("--no-near", action="store_true", help="skip the near-field measurement")
+    ap.add_argument("--no-multi", action="store_true", help="skip the multi-density (nrhs = 4) measurement")
     ap.add_argument("--tree-sweep", action="store_true",
                     help="add the FP64 tree's accuracy and time over several (theta, order)")
     ap.add_argument("--only-stokes", action="store_true",
@@ -766,6 +802,8 @@ def main():
         res[f"{other}_path"]["roofline"] = dict(sec["roofline"], traffic=counter_traffic(other, args.workload))
     if not args.no_near:
         res["near_field"] = run_near(ctx, max(3, args.steps // 4))
+    if not args.no_multi:
+        res["multi_density"] = {pr: run_multi(g, max(2, args.steps // 4), pr) for pr in ("mixed", "fp64")}
     if not args.no_derivatives:
         res["derivatives"] = {pr: run_normal(g, dens, max(3, args.steps // 4), pr) for pr in ("mixed", "fp64")}
     if not args.no_stokes:

@@ -158,6 +158,13 @@ sbie_status sbie_geom_near_pairs(const sbie_geom* g, int32_t* src, int32_t* dst,
    uses the gradient of each neighbour's exterior expansion (Eq.
    (dSLevalformula) and its analogue for D), the far field the differentiated
    kernels.
+   S (either precision) and D (FP64) with nrhs >= 2 nodal densities (and at
+   least 32 nodes per particle, without SBIE_TIMING, SBIE_FAR_TREE or
+   SBIE_INPUT_COEFFS) run in groups of up to four that share the far field's
+   pair work: one reciprocal distance per node pair serves every density of
+   the group in both directions.  The results agree with one-density applies to rounding (the
+   far sums are taken in another order), not bitwise.  Work buffers for this
+   are allocated on first use and held with the geometry.
    stream: a hipStream_t, or NULL for the context stream with the call
    returning after completion.  With a non-NULL stream and SBIE_DEVICE_PTRS the
    call is asynchronous on that stream.  flags: SBIE_DEVICE_PTRS, SBIE_TIMING,

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsbie.so")
-SOURCES = ["capi.hip", "setup.hip", "apply.hip", "far_mfma.hip", "far_stokes.hip", "stokes.hip", "server.hip", "solve.hip", "deriv.hip", "targets.hip", "stokes_dl.hip", "tree.hip"]
+SOURCES = ["capi.hip", "setup.hip", "apply.hip", "far_mfma.hip", "far_stokes.hip", "far_multi.hip", "stokes.hip", "server.hip", "solve.hip", "deriv.hip", "targets.hip", "stokes_dl.hip", "tree.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -483,6 +483,14 @@ void launch_near(sbie_geom* g, hipStream_t s) {
                      chunks, g->N, g->d_status, g->d_unear);
 }
 
+template <int PMAX, bool EXACT>
+void launch_near_to(sbie_geom* g, const double* E, double* unear, hipStream_t s) {
+  const int chunks = (g->T + 63) / 64;
+  hipLaunchKernelGGL((k_near_f64<PMAX, EXACT>), dim3(g->M * chunks * kNearSplit), dim3(64), 0, s, g->d_part, g->d_x,
+                     g->d_y, g->d_z, g->d_near_ptr, g->d_near_src, E, g->d_lam, g->d_ab, g->d_rcp, g->p, g->T,
+                     chunks, g->N, g->d_status, unear);
+}
+
 }  // namespace
 
 sbie_status next_timing_set(sbie_geom* g, hipEvent_t** ev) {
@@ -699,6 +707,99 @@ sbie_status apply_laplace_batch(sbie_geom* const* gs, int n, int op, int prec, c
     const int nslices = far_launch_splits(g, far_row_groups(g, !mixed));
     hipLaunchKernelGGL(k_assemble_f64, dim3(cdiv(g->N, B)), dim3(B), 0, s, g->d_uself, g->d_unear, g->d_partial,
                        nslices, (const double*)g->d_racc, g->N, sum_parts, d_out[k]);
+    SBIE_HIP(hipGetLastError());
+  }
+  return SBIE_OK;
+}
+
+sbie_status multi_buffers(sbie_geom* g) {
+  if (g->multi) return SBIE_OK;
+  const size_t N = (size_t)g->N, MK = (size_t)g->M * g->K, R4 = 4;
+  const uint64_t rev_bytes = multi_rev_bytes(g->M, g->T);
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t sz[] = {al(8 * R4 * MK), al(8 * R4 * N), al(8 * R4 * kNearSplit * N), al(8 * R4 * g->nsplit * N),
+                       al(8 * R4 * N), al(8 * multi_rec_values(g->M, g->T)), al(rev_bytes), al(8 * 2 * R4 * N)};
+  size_t total = 0;
+  for (size_t v : sz) total += v;
+  MultiWork* mw = new (std::nothrow) MultiWork;
+  if (!mw) return SBIE_E_NOMEM;
+  if (hipMalloc((void**)&mw->blk, total) != hipSuccess) {
+    (void)hipGetLastError();
+    delete mw;
+    set_error("device allocation of the multi-density work buffers failed");
+    return SBIE_E_NOMEM;
+  }
+  char* p = mw->blk;
+  double** dst[] = {&mw->E, &mw->uself, &mw->unear, &mw->partial, &mw->racc, &mw->rec, &mw->rev, &mw->io};
+  for (int i = 0; i < 8; ++i) {
+    *dst[i] = reinterpret_cast<double*>(p);
+    p += sz[i];
+  }
+  mw->bytes = total;
+  mw->rev_bytes = rev_bytes;
+  g->footprint += total;
+  g->multi = mw;
+  return SBIE_OK;
+}
+
+sbie_status apply_laplace_multi(sbie_geom* g, int op, int prec, int nr, const double* d_dens, double* d_out,
+                                hipStream_t s, uint32_t parts) {
+  if (nr < 2 || nr > 4 || g->T < 32 || (op != SBIE_OP_S && op != SBIE_OP_D)) {
+    set_error("the multi-density apply takes S or D, 2 to 4 densities and T >= 32");
+    return SBIE_E_INVALID;
+  }
+  sbie_status st = multi_buffers(g);
+  if (st) return st;
+  MultiWork& mw = *g->multi;
+  const int M = g->M, p = g->p, T = g->T, K = g->K;
+  const int64_t N = g->N;
+  const int B = 256;
+  const bool mixed = prec == SBIE_MIXED;
+  const bool near = (parts & SBIE_PARTS_NEAR) && g->n_near > 0;
+  // per density: prep, forward transform, spectra, self part and near field,
+  // the kernels of apply_laplace into the density's own buffers
+  for (int k = 0; k < nr; ++k) {
+    const double* dk = d_dens + (size_t)k * N;
+    double* Ek = mw.E + (size_t)k * M * K;
+    if (op == SBIE_OP_S)
+      hipLaunchKernelGGL(k_prep_f64<SBIE_OP_S>, dim3(cdiv(N, B)), dim3(B), 0, s, dk, g->d_x, g->d_y, g->d_z,
+                         g->d_nx, g->d_ny, g->d_nz, g->d_w, g->d_wS, p, N, g->d_f, g->d_src);
+    else
+      hipLaunchKernelGGL(k_prep_f64<SBIE_OP_D>, dim3(cdiv(N, B)), dim3(B), 0, s, dk, g->d_x, g->d_y, g->d_z,
+                         g->d_nx, g->d_ny, g->d_nz, g->d_w, g->d_wS, p, N, g->d_f, g->d_src);
+    SBIE_HIP(hipGetLastError());
+    if (parts & (SBIE_PARTS_SELF | SBIE_PARTS_NEAR)) {
+      st = mixed ? launch_gemm32(g->d_f, T, g->d_An32, K, g->d_coef, K, M, K, T, s)
+                 : launch_gemm(g->d_f, T, g->d_An, K, g->d_coef, K, M, K, T, s);
+      if (st) return st;
+      hipLaunchKernelGGL(k_scale_coef, dim3(cdiv((int64_t)M * K, B)), dim3(B), 0, s, g->d_coef, g->d_lam, M, p, op,
+                         g->d_cself, Ek);
+      SBIE_HIP(hipGetLastError());
+    }
+    if (parts & SBIE_PARTS_SELF) {
+      st = mixed ? launch_gemm32(g->d_cself, K, g->d_Sy32, T, mw.uself + (size_t)k * N, T, M, T, K, s)
+                 : launch_gemm(g->d_cself, K, g->d_Sy, T, mw.uself + (size_t)k * N, T, M, T, K, s);
+      if (st) return st;
+    }
+    if (near) {
+      double* uk = mw.unear + (size_t)k * kNearSplit * N;
+      dispatch_order(p, [&](auto pm, auto ex) {
+        launch_near_to<decltype(pm)::value, decltype(ex)::value>(g, Ek, uk, s);
+      });
+      SBIE_HIP(hipGetLastError());
+    }
+  }
+  // the far field of all densities at once
+  const int nsl = multi_splits(g, multi_row_groups(T, !mixed, op));
+  if (parts & SBIE_PARTS_FAR) {
+    st = far_multi(g, op, mixed, nr, d_dens, s);
+    if (st) return st;
+  }
+  const uint32_t sum_parts = near ? parts : (parts & ~(uint32_t)SBIE_PARTS_NEAR);
+  for (int k = 0; k < nr; ++k) {
+    hipLaunchKernelGGL(k_assemble_f64, dim3(cdiv(N, B)), dim3(B), 0, s, mw.uself + (size_t)k * N,
+                       mw.unear + (size_t)k * kNearSplit * N, mw.partial + (size_t)k * nsl * N, nsl,
+                       (const double*)(mw.racc + (size_t)k * N), N, sum_parts, d_out + (size_t)k * N);
     SBIE_HIP(hipGetLastError());
   }
   return SBIE_OK;

@@ -34,6 +34,10 @@ sbie_status invalid(const std::string& msg) {
 void free_geom(sbie_geom* g) {
   if (!g) return;
   sbie::free_tree(g);
+  if (g->multi) {
+    if (g->multi->blk) (void)hipFree(g->multi->blk);
+    delete g->multi;
+  }
   if (g->blk && g->blk_owned) (void)hipFree(g->blk);
   if (g->stk_blk) (void)hipFree(g->stk_blk);
   if (g->sdl_blk) (void)hipFree(g->sdl_blk);
@@ -328,7 +332,33 @@ sbie_status sbie_apply(sbie_geom* g, sbie_op op, sbie_precision prec, int32_t nr
   }
   // one input: N nodal values, or M (p+1)^2 coefficients
   const int64_t nin = coef_in ? (int64_t)g->M * g->K : N;
-  for (int r = 0; r < nrhs; ++r) {
+  // several nodal densities: groups of up to four share the far field's pair
+  // work (apply_laplace_multi); a last single density takes the plain apply.
+  // The mixed double layer keeps one apply per density: its three-piece pair
+  // kernel per density is faster than the shared kernel's FP32 products.
+  const bool multi = nrhs >= 2 && !coef_in && !(parts & SBIE_FAR_TREE) && !timed && g->T >= 32 &&
+                     (op == SBIE_OP_S || prec == SBIE_FP64);
+  int r0 = 0;
+  if (multi) {
+    sbie_status st = sbie::multi_buffers(g);
+    if (st != SBIE_OK) return st;
+    for (; nrhs - r0 >= 2; r0 += 4) {
+      const int nr = nrhs - r0 < 4 ? nrhs - r0 : 4;
+      const double* din = density + (size_t)r0 * N;
+      double* dout = potential + (size_t)r0 * N;
+      if (!devptr) {
+        double* io = g->multi->io;
+        SBIE_HIP(hipMemcpyAsync(io, din, sizeof(double) * nr * N, hipMemcpyHostToDevice, s));
+        din = io;
+        dout = io + (size_t)4 * N;
+      }
+      st = sbie::apply_laplace_multi(g, (int)op, (int)prec, nr, din, dout, s, parts);
+      if (st != SBIE_OK) return st;
+      if (!devptr)
+        SBIE_HIP(hipMemcpyAsync(potential + (size_t)r0 * N, dout, sizeof(double) * nr * N, hipMemcpyDeviceToHost, s));
+    }
+  }
+  for (int r = r0; r < nrhs; ++r) {
     const double* din = density + (size_t)r * nin;
     double* dout = potential + (size_t)r * N;
     if (!devptr) {

@@ -39,7 +39,7 @@ using d4s = double __attribute__((ext_vector_type(4)));
 // values per 16-source block: [-2o 1] B operand (64, lane order), |o|^2 per
 // column (16), [q  -q.o] B operand (64), 16 unused
 constexpr int kSGeo = 160;
-constexpr int kSWaves = 12;  // waves per workgroup (three per SIMD), each holding up to RB row blocks
+constexpr int kSWaves = 12;  // most waves per workgroup (three per SIMD), each holding up to RB row blocks
 
 template <typename R>
 struct StokesShape;
@@ -127,6 +127,7 @@ __global__ __launch_bounds__(64 * kSWaves) void k_far_stokes_pairs(
   __shared__ R lds_rev[kSWaves * C * CH * 16];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int W = (int)(blockDim.x >> 6);
   const int li = lane & 15, lg = lane >> 4;
   const int x16 = (lane ^ 16) << 2, x32 = (lane ^ 32) << 2;
   const int wid = xcd_work_index();
@@ -134,8 +135,8 @@ __global__ __launch_bounds__(64 * kSWaves) void k_far_stokes_pairs(
   const int rg = rest % RG, a = rest / RG;
   const int nb = (T + 15) / 16;
   const int gb0 = (int)((int64_t)rg * nb / RG), cnt = (int)((int64_t)(rg + 1) * nb / RG) - gb0;
-  const int rb0 = gb0 + (wave * cnt) / kSWaves;
-  const int nown = __builtin_amdgcn_readfirstlane(gb0 + ((wave + 1) * cnt) / kSWaves - rb0);
+  const int rb0 = gb0 + (wave * cnt) / W;
+  const int nown = __builtin_amdgcn_readfirstlane(gb0 + ((wave + 1) * cnt) / W - rb0);
   const int H = (M - 1) / 2;
   const bool even = (M & 1) == 0;
   const int P = H + ((even && a < M / 2) ? 1 : 0);
@@ -298,7 +299,7 @@ __global__ __launch_bounds__(64 * kSWaves) void k_far_stokes_pairs(
           const int t = c0 * 16 + col;
           if (t >= T) continue;
           R sum = R(0);
-          for (int wv = 0; wv < kSWaves; ++wv) sum += lds_rev[(wv * C + c) * CH * 16 + col];
+          for (int wv = 0; wv < W; ++wv) sum += lds_rev[(wv * C + c) * CH * 16 + col];
           rout[(size_t)c * T + t] = need_r ? sum : R(0);
         }
       }

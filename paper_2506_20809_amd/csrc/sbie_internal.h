@@ -112,6 +112,22 @@ struct TreePlan {
   std::vector<int32_t> pidx, didx;        // clusters through proxies; source particles summed directly
 };
 
+// Work buffers of the multi-density S and D apply (up to four densities at
+// once), allocated on its first use and held with the geometry.
+struct MultiWork {
+  char* blk = nullptr;
+  size_t bytes = 0;
+  double* E = nullptr;        // [4][M][K] exterior coefficients per density
+  double* uself = nullptr;    // [4][N]
+  double* unear = nullptr;    // [4][kNearSplit][N]
+  double* partial = nullptr;  // [4][nsplit][N] forward far partials
+  double* racc = nullptr;     // [4][N] reverse totals
+  double* rec = nullptr;      // per-block source records (multi_rec_values doubles)
+  double* rev = nullptr;      // reverse sums of one launch (rev_bytes)
+  uint64_t rev_bytes = 0;
+  double* io = nullptr;       // [2][4][N] staging of host densities and results
+};
+
 struct FarTree {
   double theta = 0.0;
   int nc = 0, order = 0, leaf = 0, nused = 0;  // nused: clusters taken through proxies by some target
@@ -257,6 +273,7 @@ struct sbie_geom {
 
   sbie::Timing timing;
   sbie::FarTree* tree = nullptr;  // tree far field, built by sbie_geom_far_tree
+  sbie::MultiWork* multi = nullptr;  // multi-density apply buffers
   // the near field runs on a side stream, concurrently with the far field
   // (plain geometries; served sessions keep one stream per lane)
   bool fork_near = true;
@@ -289,6 +306,22 @@ int stokes_rev_slots(int M, int T, int C, int bytes_per_value, uint64_t cap_byte
 int stokes_pair_splits(const sbie_geom* g, int RG);
 uint64_t stokes_rev_bytes(int M, int T);
 sbie_status far_stokes_pairs(sbie_geom* g, int C, bool mixed, const double* d_dens, hipStream_t s);
+
+// Multi-density S and D (far_multi.hip, apply.hip): the pair kernel's row
+// groups, slots, splits and buffer sizes for up to four densities, its far
+// field of nr = 2..4 densities d_dens [nr][N] into the work's partials and
+// totals, the work's allocation, and the whole apply of nr densities
+// (d_dens [nr][N] -> d_out [nr][N], device pointers; T >= 32).
+int multi_row_groups(int T, bool fp64, int op);
+int multi_waves(int T, bool fp64, int op);
+int multi_rev_slots(int M, int T, int NR, int op, int bytes_per_value, uint64_t cap_bytes);
+int multi_splits(const sbie_geom* g, int RG);
+uint64_t multi_rev_bytes(int M, int T);
+size_t multi_rec_values(int M, int T);
+sbie_status far_multi(sbie_geom* g, int op, bool mixed, int nr, const double* d_dens, hipStream_t s);
+sbie_status multi_buffers(sbie_geom* g);
+sbie_status apply_laplace_multi(sbie_geom* g, int op, int prec, int nr, const double* d_dens, double* d_out,
+                                hipStream_t s, uint32_t parts);
 
 // Carves 256-byte aligned buffers out of one device block; with no block it
 // only measures.

@@ -30,7 +30,7 @@ HOSTRT = os.path.join(ROOT, "tests", "hostrt")
 HIPCC = "/opt/rocm/bin/hipcc"
 CLANGXX = "/opt/rocm/llvm/bin/clang++"
 CLANG = "/opt/rocm/llvm/bin/clang"
-SOURCES = ["capi", "setup", "apply", "far_mfma", "far_stokes", "stokes", "server", "solve", "deriv", "targets", "stokes_dl", "tree"]
+SOURCES = ["capi", "setup", "apply", "far_mfma", "far_stokes", "far_multi", "stokes", "server", "solve", "deriv", "targets", "stokes_dl", "tree"]
 
 pytestmark = pytest.mark.skipif(not (os.path.exists(HIPCC) and os.path.exists(CLANGXX)),
                                 reason="needs the ROCm compilers")

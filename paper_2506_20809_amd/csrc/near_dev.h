@@ -167,27 +167,26 @@ __device__ inline SpheroidalPoint to_spheroidal(const Particle& P, double X0, do
   return q;
 }
 
-// NSET exterior expansions sum_l E_s[l] Q_n^|m|(u)/Q_n^|m|(u0) Y_l(v, phi) of one
-// source particle at a mapped point, with their u, v and phi derivatives.
-// Es: coefficients of set s at E + s * stride; L: the particle's spectra rows
-// (column 3 holds 1/Q_n^m(u0)); ab, cd: normalised Ferrers recurrence and
-// derivative coefficients through degree p+1.  Q and Q' come from the
-// division-free backward recurrence (orders 0 and 1, then the order step).
-template <int PMAX, int NSET>
-__device__ inline void expansion_derivatives(const SpheroidalPoint& q, bool oblate, const double* __restrict__ E,
-                                             size_t stride, const double* __restrict__ L,
-                                             const double* __restrict__ ab, const double* __restrict__ cd,
-                                             const double* __restrict__ rcp, int p, unsigned* bad,
-                                             double (&Phi)[NSET], double (&Pu)[NSET], double (&Pv)[NSET],
-                                             double (&Pp)[NSET]) {
+// The terms of an exterior expansion sum_l E[l] Q_n^|m|(u)/Q_n^|m|(u0) Y_l(v, phi)
+// of one source particle at a mapped point, order by order: for every (n, m)
+// with n <= p, f(lc, ls, m, a0, a1, a2, ap, b0, b1, b2, bp) receives the
+// coefficient indices lc = n^2+n+m (cos(m phi)) and ls = n^2+n-m (sin(m phi),
+// m > 0 only) and the basis values of the two: a0 the value, a1 its u, a2 its
+// v and ap its phi derivative (b for the sine term).  L: the particle's
+// spectra rows (column 3 holds 1/Q_n^m(u0)); ab, cd: normalised Ferrers
+// recurrence and derivative coefficients through degree p+1.  Q and Q' come
+// from the division-free backward recurrence (orders 0 and 1, then the order
+// step).
+template <int PMAX, typename F>
+__device__ inline void expansion_terms(const SpheroidalPoint& q, bool oblate, const double* __restrict__ L,
+                                       const double* __restrict__ ab, const double* __restrict__ cd,
+                                       const double* __restrict__ rcp, int p, unsigned* bad, F&& f) {
   const int N1 = p + 1;
   const double u = q.u, v = q.v;
   const double inv_omv2 = 1.0 / (q.sv * q.sv);
   const double inv_w = 1.0 / q.w;
   const double sgn = oblate ? 1.0 : -1.0;
   const int Ld = near_depth(u, q.sw, N1, kStatNumeric, bad);
-#pragma unroll
-  for (int s = 0; s < NSET; ++s) Phi[s] = Pu[s] = Pv[s] = Pp[s] = 0.0;
   double qn0[2], qn1[2];
   q_top_orders01(u, q.sw, sgn, N1, Ld, rcp, qn0, qn1);
   const double ur = u / q.sw;
@@ -210,10 +209,10 @@ __device__ inline void expansion_derivatives(const SpheroidalPoint& q, bool obla
     double Q[PMAX + 4];
     q_column<PMAX>(u, sgn, N1, m, qN, qN1, rcp, Q);
     // the azimuthal factors of order m folded into the basis, so that each
-    // set accumulates straight into its four outputs (no per-order partial
-    // sums per set: fewer registers for many sets)
-    const double f = m == 0 ? 1.0 : 1.41421356237309504880;
-    const double fc = f * cm, fs = f * sm, fmc = (double)m * fc, fms = -(double)m * fs;
+    // set accumulates straight into its outputs (no per-order partial sums
+    // per set: fewer registers for many sets)
+    const double fm = m == 0 ? 1.0 : 1.41421356237309504880;
+    const double fc = fm * cm, fs = fm * sm, fmc = (double)m * fc, fms = -(double)m * fs;
     // normalised Ferrers functions of v rolled forward in n: P_{n-1}, P_n and
     // (for the v-derivative) P_{n+1}
     double pm1 = 0.0, pn = pbar;
@@ -235,27 +234,62 @@ __device__ inline void expansion_derivatives(const SpheroidalPoint& q, bool obla
         const double t0 = pn * qr, t1 = pn * dq, t2 = dpn * qr;
         // cos(m phi) terms carry E_{n,m}, sin(m phi) terms E_{n,-m}; the
         // phi-derivative swaps them: d/dphi [c cos + s sin] = m (s cos - c sin)
-        const double a0 = fc * t0, a1 = fc * t1, a2 = fc * t2, ap = fms * t0;
-        const double b0 = fs * t0, b1 = fs * t1, b2 = fs * t2, bp = fmc * t0;
-#pragma unroll
-        for (int s = 0; s < NSET; ++s) {
-          const double ec = E[(size_t)s * stride + n * n + n + m];
-          Phi[s] = fma(ec, a0, Phi[s]);
-          Pu[s] = fma(ec, a1, Pu[s]);
-          Pv[s] = fma(ec, a2, Pv[s]);
-          Pp[s] = fma(ec, ap, Pp[s]);
-          if (m > 0) {
-            const double es = E[(size_t)s * stride + n * n + n - m];
-            Phi[s] = fma(es, b0, Phi[s]);
-            Pu[s] = fma(es, b1, Pu[s]);
-            Pv[s] = fma(es, b2, Pv[s]);
-            Pp[s] = fma(es, bp, Pp[s]);
-          }
-        }
+        f(n * n + n + m, n * n + n - m, m, fc * t0, fc * t1, fc * t2, fms * t0, fs * t0, fs * t1, fs * t2, fmc * t0);
         pm1 = pn;
         pn = pn1;
       }
     }
+  }
+}
+
+// NSET exterior expansions of one source particle at a mapped point, with
+// their u, v and phi derivatives.  Es: coefficients of set s at E + s * stride.
+template <int PMAX, int NSET>
+__device__ inline void expansion_derivatives(const SpheroidalPoint& q, bool oblate, const double* __restrict__ E,
+                                             size_t stride, const double* __restrict__ L,
+                                             const double* __restrict__ ab, const double* __restrict__ cd,
+                                             const double* __restrict__ rcp, int p, unsigned* bad,
+                                             double (&Phi)[NSET], double (&Pu)[NSET], double (&Pv)[NSET],
+                                             double (&Pp)[NSET]) {
+#pragma unroll
+  for (int s = 0; s < NSET; ++s) Phi[s] = Pu[s] = Pv[s] = Pp[s] = 0.0;
+  expansion_terms<PMAX>(q, oblate, L, ab, cd, rcp, p, bad,
+                        [&](int lc, int ls, int m, double a0, double a1, double a2, double ap, double b0, double b1,
+                            double b2, double bp) {
+#pragma unroll
+                          for (int s = 0; s < NSET; ++s) {
+                            const double ec = E[(size_t)s * stride + lc];
+                            Phi[s] = fma(ec, a0, Phi[s]);
+                            Pu[s] = fma(ec, a1, Pu[s]);
+                            Pv[s] = fma(ec, a2, Pv[s]);
+                            Pp[s] = fma(ec, ap, Pp[s]);
+                            if (m > 0) {
+                              const double es = E[(size_t)s * stride + ls];
+                              Phi[s] = fma(es, b0, Phi[s]);
+                              Pu[s] = fma(es, b1, Pu[s]);
+                              Pv[s] = fma(es, b2, Pv[s]);
+                              Pp[s] = fma(es, bp, Pp[s]);
+                            }
+                          }
+                        });
+}
+
+// The chain rule of lab_gradient as coefficients: the lab gradient of an
+// expansion is g_r = al[r] Pu + be[r] Pv + ga[r] Pp.
+__device__ inline void lab_gradient_coeffs(const Particle& P, double u, double su, double v, double sv, double c1,
+                                           double s1, double al[3], double be[3], double ga[3]) {
+  const double a = P.a;
+  const double xu[3] = {a * u / su * sv * c1, a * u / su * sv * s1, a * v};
+  const double xv[3] = {-a * su * v / sv * c1, -a * su * v / sv * s1, a * u};
+  const double xp[3] = {-a * su * sv * s1, a * su * sv * c1, 0.0};
+  const double hu2 = xu[0] * xu[0] + xu[1] * xu[1] + xu[2] * xu[2];
+  const double hv2 = xv[0] * xv[0] + xv[1] * xv[1] + xv[2] * xv[2];
+  const double hp2 = xp[0] * xp[0] + xp[1] * xp[1] + xp[2] * xp[2];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    al[r] = (P.R[3 * r] * xu[0] + P.R[3 * r + 1] * xu[1] + P.R[3 * r + 2] * xu[2]) / hu2;
+    be[r] = (P.R[3 * r] * xv[0] + P.R[3 * r + 1] * xv[1] + P.R[3 * r + 2] * xv[2]) / hv2;
+    ga[r] = (P.R[3 * r] * xp[0] + P.R[3 * r + 1] * xp[1]) / hp2;
   }
 }
 

@@ -158,13 +158,50 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     const int i = near_src[sidx];
     const Particle P = part[i];
     const SpheroidalPoint sp = to_spheroidal(P, X0, X1, X2, true, &bad);
-    double Phi[4], Pu[4], Pv[4], Pp[4];
-    expansion_derivatives<PMAX, 4>(sp, P.oblate != 0, E + (size_t)i * 4 * K, (size_t)K, lam + (size_t)i * Kh * 4,
-                                   ab, cd, rcp, p, &bad, Phi, Pu, Pv, Pp);
-    double o[C];
-    stokes_from_derivatives<C>(P, sp.u, sp.sw, sp.v, sp.sv, sp.c1, sp.s1, Phi, Pu, Pv, Pp, sp.d, o);
+    const double* Ei = E + (size_t)i * 4 * K;
+    // Eq. (stokes) is linear in the four expansions, so it is taken inside the
+    // sum over (n, m), one basis evaluation for all of them: the values of
+    // S[sigma_k]; grad (S[rho] - sum_j d_j S[sigma_j]) as the gradient of one
+    // expansion with coefficients E3 - d.(E0, E1, E2) (d fixed at the
+    // target); for the pressure -sum_j d_j S[sigma_j], one lab derivative of
+    // each of the first three sets (the chain rule's coefficients applied to
+    // the basis derivatives).
+    double al[3], be[3], ga[3];
+    lab_gradient_coeffs(P, sp.u, sp.sw, sp.v, sp.sv, sp.c1, sp.s1, al, be, ga);
+    const double w0 = -sp.d[0], w1 = -sp.d[1], w2 = -sp.d[2];
+    double Phi[3] = {0.0, 0.0, 0.0}, Gu = 0.0, Gv = 0.0, Gp = 0.0, pr = 0.0;
+    expansion_terms<PMAX>(sp, P.oblate != 0, lam + (size_t)i * Kh * 4, ab, cd, rcp, p, &bad,
+                          [&](int lc, int ls, int m, double a0, double a1, double a2, double ap, double b0,
+                              double b1, double b2, double bp) {
 #pragma unroll
-    for (int c = 0; c < C; ++c) acc[c] += o[c];
+                            for (int k = 0; k < 3; ++k) Phi[k] = fma(Ei[(size_t)k * K + lc], a0, Phi[k]);
+                            const double fc = fma(w2, Ei[2 * K + lc], fma(w1, Ei[K + lc], fma(w0, Ei[lc], Ei[3 * K + lc])));
+                            Gu = fma(fc, a1, Gu);
+                            Gv = fma(fc, a2, Gv);
+                            Gp = fma(fc, ap, Gp);
+                            if constexpr (C == 4) {
+#pragma unroll
+                              for (int j = 0; j < 3; ++j)
+                                pr = fma(Ei[(size_t)j * K + lc], -fma(ga[j], ap, fma(be[j], a2, al[j] * a1)), pr);
+                            }
+                            if (m > 0) {
+#pragma unroll
+                              for (int k = 0; k < 3; ++k) Phi[k] = fma(Ei[(size_t)k * K + ls], b0, Phi[k]);
+                              const double fs =
+                                  fma(w2, Ei[2 * K + ls], fma(w1, Ei[K + ls], fma(w0, Ei[ls], Ei[3 * K + ls])));
+                              Gu = fma(fs, b1, Gu);
+                              Gv = fma(fs, b2, Gv);
+                              Gp = fma(fs, bp, Gp);
+                              if constexpr (C == 4) {
+#pragma unroll
+                                for (int j = 0; j < 3; ++j)
+                                  pr = fma(Ei[(size_t)j * K + ls], -fma(ga[j], bp, fma(be[j], b2, al[j] * b1)), pr);
+                              }
+                            }
+                          });
+#pragma unroll
+    for (int k = 0; k < 3; ++k) acc[k] += 0.5 * (Phi[k] + fma(ga[k], Gp, fma(be[k], Gv, al[k] * Gu)));
+    if constexpr (C == 4) acc[3] += pr;
   }
   if (bad) atomicOr(status, bad);
   if (live) {

@@ -139,7 +139,7 @@ __global__ void k_sdl_self(const Particle* __restrict__ part, const double* __re
 // recurrences run once for the four double-layer sets and once for the nine
 // single-layer sets of every near source.
 template <int PMAX, bool EXACT>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_near_sdl(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_near_sdl(
     const Particle* __restrict__ part, const double* __restrict__ x, const double* __restrict__ y,
     const double* __restrict__ z, const int32_t* __restrict__ near_ptr, const int32_t* __restrict__ near_src,
     const double* __restrict__ E, const double* __restrict__ lam, const double* __restrict__ ab,
@@ -164,25 +164,50 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const SpheroidalPoint q = to_spheroidal(P, X0, X1, X2, true, &bad);
     const double* Ei = E + (size_t)i * kSets * K;
     const double* Li = lam + (size_t)i * Kh * 4;
-    double gD[4][3], gS[9][3];
-    {
-      double Phi[4], Pu[4], Pv[4], Pp[4];
-      expansion_derivatives<PMAX, 4>(q, P.oblate != 0, Ei, (size_t)K, Li, ab, cd, rcp, p, &bad, Phi, Pu, Pv, Pp);
+    // The decomposition is linear in the thirteen expansions, so it is taken
+    // inside the sum over (n, m), one basis evaluation for all of them:
+    //  - the double-layer part  grad (D[3] - sum_j d_j D[j])  is the gradient
+    //    of one expansion with coefficients E3 - d.(E0, E1, E2) (d fixed at
+    //    the target);
+    //  - the single-layer part  -sum_j d_j S[4 + 3i + j]  needs one lab
+    //    derivative of each set, the chain rule's coefficients applied to the
+    //    basis derivatives.
+    double al[3], be[3], ga[3];
+    lab_gradient_coeffs(P, q.u, q.sw, q.v, q.sv, q.c1, q.s1, al, be, ga);
+    const double w0 = -q.d[0], w1 = -q.d[1], w2 = -q.d[2];
+    double Gu = 0.0, Gv = 0.0, Gp = 0.0, O[3] = {0.0, 0.0, 0.0};
+    expansion_terms<PMAX>(q, P.oblate != 0, Li, ab, cd, rcp, p, &bad,
+                          [&](int lc, int ls, int m, double, double a1, double a2, double ap, double, double b1,
+                              double b2, double bp) {
+                            const double fc = fma(w2, Ei[2 * K + lc], fma(w1, Ei[K + lc], fma(w0, Ei[lc], Ei[3 * K + lc])));
+                            Gu = fma(fc, a1, Gu);
+                            Gv = fma(fc, a2, Gv);
+                            Gp = fma(fc, ap, Gp);
+                            double nc[3];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) lab_gradient(P, q.u, q.sw, q.v, q.sv, q.c1, q.s1, Pu[s], Pv[s], Pp[s], gD[s]);
-    }
-    {
-      double Phi[9], Pu[9], Pv[9], Pp[9];
-      expansion_derivatives<PMAX, 9>(q, P.oblate != 0, Ei + (size_t)4 * K, (size_t)K, Li, ab, cd, rcp, p, &bad,
-                                     Phi, Pu, Pv, Pp);
+                            for (int j = 0; j < 3; ++j) nc[j] = -fma(ga[j], ap, fma(be[j], a2, al[j] * a1));
 #pragma unroll
-      for (int s = 0; s < 9; ++s) lab_gradient(P, q.u, q.sw, q.v, q.sv, q.c1, q.s1, Pu[s], Pv[s], Pp[s], gS[s]);
-    }
-    double o3[3];
-    sdl_combine(gD, gS, q.d, o3);
-    acc[0] += o3[0];
-    acc[1] += o3[1];
-    acc[2] += o3[2];
+                            for (int ii = 0; ii < 3; ++ii)
+#pragma unroll
+                              for (int j = 0; j < 3; ++j) O[ii] = fma(Ei[(size_t)(4 + 3 * ii + j) * K + lc], nc[j], O[ii]);
+                            if (m > 0) {
+                              const double fs =
+                                  fma(w2, Ei[2 * K + ls], fma(w1, Ei[K + ls], fma(w0, Ei[ls], Ei[3 * K + ls])));
+                              Gu = fma(fs, b1, Gu);
+                              Gv = fma(fs, b2, Gv);
+                              Gp = fma(fs, bp, Gp);
+                              double ns[3];
+#pragma unroll
+                              for (int j = 0; j < 3; ++j) ns[j] = -fma(ga[j], bp, fma(be[j], b2, al[j] * b1));
+#pragma unroll
+                              for (int ii = 0; ii < 3; ++ii)
+#pragma unroll
+                                for (int j = 0; j < 3; ++j)
+                                  O[ii] = fma(Ei[(size_t)(4 + 3 * ii + j) * K + ls], ns[j], O[ii]);
+                            }
+                          });
+#pragma unroll
+    for (int ii = 0; ii < 3; ++ii) acc[ii] += fma(ga[ii], Gp, fma(be[ii], Gv, al[ii] * Gu)) + O[ii];
   }
   if (bad) atomicOr(status, bad);
   if (live) {

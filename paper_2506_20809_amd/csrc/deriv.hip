@@ -83,7 +83,7 @@ __global__ void k_normal_scale(const double* __restrict__ coef, const double* __
 // in (u, v, phi) at the mapped target and its lab gradient is projected on the
 // target's normal.
 template <int PMAX, bool EXACT>
-__global__ __launch_bounds__(64) void k_near_normal(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_near_normal(
     const Particle* __restrict__ part, const double* __restrict__ x, const double* __restrict__ y,
     const double* __restrict__ z, const double* __restrict__ nx, const double* __restrict__ ny,
     const double* __restrict__ nz, const int32_t* __restrict__ near_ptr, const int32_t* __restrict__ near_src,
@@ -107,12 +107,22 @@ __global__ __launch_bounds__(64) void k_near_normal(
     const int i = near_src[sidx];
     const Particle P = part[i];
     const SpheroidalPoint q = to_spheroidal(P, X0, X1, X2, true, &bad);
-    double Phi[1], Pu[1], Pv[1], Pp[1];
-    expansion_derivatives<PMAX, 1>(q, P.oblate != 0, E + (size_t)i * K, (size_t)K, lam + (size_t)i * Kh * 4, ab,
-                                   cd, rcp, p, &bad, Phi, Pu, Pv, Pp);
-    double gr[3];
-    lab_gradient(P, q.u, q.sw, q.v, q.sv, q.c1, q.s1, Pu[0], Pv[0], Pp[0], gr);
-    acc += gr[0] * n0 + gr[1] * n1 + gr[2] * n2;
+    // the derivative along the target normal as one directional derivative of
+    // the basis: nu.grad = (nu.al) d/du + (nu.be) d/dv + (nu.ga) d/dphi
+    double al[3], be[3], ga[3];
+    lab_gradient_coeffs(P, q.u, q.sw, q.v, q.sv, q.c1, q.s1, al, be, ga);
+    const double cu = al[0] * n0 + al[1] * n1 + al[2] * n2;
+    const double cv = be[0] * n0 + be[1] * n1 + be[2] * n2;
+    const double cp = ga[0] * n0 + ga[1] * n1 + ga[2] * n2;
+    const double* Ei = E + (size_t)i * K;
+    double dn = 0.0;
+    expansion_terms<PMAX>(q, P.oblate != 0, lam + (size_t)i * Kh * 4, ab, cd, rcp, p, &bad,
+                          [&](int lc, int ls, int m, double, double a1, double a2, double ap, double, double b1,
+                              double b2, double bp) {
+                            dn = fma(Ei[lc], fma(cp, ap, fma(cv, a2, cu * a1)), dn);
+                            if (m > 0) dn = fma(Ei[ls], fma(cp, bp, fma(cv, b2, cu * b1)), dn);
+                          });
+    acc += dn;
   }
   if (bad) atomicOr(status, bad);
   if (live) unear[(size_t)q4 * Nn + g] = acc;

@@ -74,6 +74,7 @@ void plain_path() {
         check(sbie_apply(g, op, pr, 1, dens.data(), out.data(), nullptr, SBIE_TIMING), "sbie_apply");
     }
     check(sbie_apply(g, SBIE_OP_STOKES_S, SBIE_FP64, 3, dens.data(), out.data(), nullptr, 0), "sbie_apply stokes");
+    check(sbie_apply(g, SBIE_OP_STOKES_D, SBIE_MIXED, 3, dens.data(), out.data(), nullptr, 0), "sbie_apply stresslet");
     // three densities in one S and one D apply (the shared far-field path)
     check(sbie_apply(g, SBIE_OP_S, SBIE_MIXED, 3, dens.data(), out.data(), nullptr, 0), "sbie_apply nrhs 3");
     check(sbie_apply(g, SBIE_OP_D, SBIE_FP64, 2, dens.data(), out.data(), nullptr, 0), "sbie_apply nrhs 2");

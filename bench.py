@@ -536,7 +536,8 @@ def solve_large(ctx, name, precision, maxit=300):
     return out
 
 
-def served(ctx, n_requests, rhos, precision, max_sessions, budgets=(64 << 30,), napply=20, workers=64, batch=False):
+def served(ctx, n_requests, rhos, precision, max_sessions, budgets=(64 << 30,), napply=20, workers=64, batch=False,
+           tree=False):
     """Served mode on the request stream (Section 4 use as a Krylov inner loop):
     n_requests sessions of napply closed-loop applies each.
 
@@ -590,7 +591,7 @@ def served(ctx, n_requests, rhos, precision, max_sessions, budgets=(64 << 30,), 
     print(f"served: plain pass of {n_requests} requests in {service.sum():.1f} s", file=sys.stderr, flush=True)
 
     def run_served(arrivals, budget):
-        srv = sbie.Server(ctx, max_sessions=max_sessions, budget_bytes=budget, graphs=True, batch=batch)
+        srv = sbie.Server(ctx, max_sessions=max_sessions, budget_bytes=budget, graphs=True, batch=batch, tree=tree)
         done = [0.0] * n_requests
         apply_ms = []
         errors = []
@@ -637,7 +638,7 @@ def served(ctx, n_requests, rhos, precision, max_sessions, budgets=(64 << 30,), 
         lat = np.array(done) - np.array(arrivals)
         return {"makespan_s": max(done), "request_latency_s": lat, "apply_ms": np.array(apply_ms),
                 "peak_bytes": info.peak_bytes, "passed": info.passed, "waited": info.waited,
-                "batched": info.batched}
+                "batched": info.batched, "tree_sessions": info.tree_sessions}
 
     def pct(x):
         return {"p50": float(np.percentile(x, 50)), "p99": float(np.percentile(x, 99))}
@@ -650,7 +651,8 @@ def served(ctx, n_requests, rhos, precision, max_sessions, budgets=(64 << 30,), 
         "workload": f"{n_requests} requests (particle count log-uniform in [8, 1024] cut from a 0.15 volume "
                     f"fraction packing, p in {{8, 12, 16}}, S or D), {napply} closed-loop applies each, "
                     f"precision={precision}, {max_sessions} lanes, HIP graph replay"
-                    f"{', batching lanes' if batch else ''}, {workers} client threads",
+                    f"{', batching lanes' if batch else ''}"
+                    f"{', tree far field for S/D sessions of 64+ particles' if tree else ''}, {workers} client threads",
         "mean_particles": float(Ms.mean()),
         "plain": {"capacity_requests_per_s": mu, "applies_per_s": mu * napply,
                   "pair_interactions_per_s": total_pairs / service.sum(),
@@ -660,7 +662,7 @@ def served(ctx, n_requests, rhos, precision, max_sessions, budgets=(64 << 30,), 
                              "pair_interactions_per_s": total_pairs / sat["makespan_s"],
                              "speedup_vs_plain": (n_requests / sat["makespan_s"]) / mu,
                              "apply_latency_ms": pct(sat["apply_ms"]),
-                             "batched_applies": int(sat["batched"])},
+                             "batched_applies": int(sat["batched"]), "tree_sessions": int(sat["tree_sessions"])},
     }
     # 3. Poisson arrivals at rho * mu, per budget
     for budget in budgets:
@@ -716,6 +718,8 @@ def main():
     ap.add_argument("--served-budget-gib", type=int, nargs="+", default=[64], help="HBM budgets of the server")
     ap.add_argument("--served-precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--served-lanes", type=int, default=8)
+    ap.add_argument("--served-tree", action="store_true",
+                    help="S/D sessions of 64+ particles take the tree far field (theta 0.6, order 10)")
     ap.add_argument("--served-batch", action="store_true",
                     help="batching lanes: sessions of one kind share a lane and run in batched launches")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -823,7 +827,7 @@ def main():
     if args.served_requests > 0:
         res["served"] = served(ctx, args.served_requests, args.served_rho, args.served_precision,
                                args.served_lanes, budgets=tuple(b << 30 for b in args.served_budget_gib),
-                               batch=args.served_batch)
+                               batch=args.served_batch, tree=args.served_tree)
     if not args.no_cpu_baseline:
         d = dens[0].cpu().numpy()
         res["cpu_baseline"], tg, refs = cpu_baseline(geom, p, d[0], d[1], N, args.cpu_sample)

@@ -297,7 +297,12 @@ sbie_status sbie_solve_neumann(sbie_geom* g, sbie_precision prec, const double* 
    front applies of its sessions
    together: each session's transform and self part, one near-field launch and
    one far-field launch over all of them, each session's assembly.  Results are
-   bitwise those of sbie_apply on the same geometry.
+   bitwise those of sbie_apply on the same geometry.  With SBIE_SERVER_TREE
+   an S or D session of at least 64 particles also builds the tree far field
+   of sbie_geom_far_tree (theta 0.6, order 10, leaf 2) in the arena when it
+   is admitted, and its applies equal sbie_apply with SBIE_FAR_TREE on that
+   tree; when the arena has no room for the tree the session keeps the
+   direct far field.  Such sessions do not batch.
 
    All server calls are thread-safe; the handles of one session must not be
    used after sbie_session_close. */
@@ -307,6 +312,7 @@ typedef struct sbie_session sbie_session;
 
 #define SBIE_SERVER_GRAPHS 0x100u
 #define SBIE_SERVER_BATCH 0x200u
+#define SBIE_SERVER_TREE 0x400u
 #define SBIE_MAX_PASS 8
 
 typedef struct {
@@ -334,6 +340,7 @@ typedef struct {
   int32_t lanes;
   int32_t graphs;           /* 1 if applies are replayed as HIP graphs */
   int64_t batched;          /* applies completed inside batched launches */
+  int64_t tree_sessions;    /* sessions whose far field runs through a tree */
 } sbie_server_info;
 
 /* Device bytes a session of M particles at order p holds while admitted:
@@ -344,7 +351,7 @@ uint64_t sbie_session_bytes(int32_t M, int32_t p, sbie_op op);
 
 /* Start a server on ctx's device with max_sessions lanes (1..64), each with a
    stream and a host thread, and an arena of hbm_budget_bytes of device memory
-   allocated now.  flags: SBIE_SERVER_GRAPHS, SBIE_SERVER_BATCH.  Errors: SBIE_E_INVALID,
+   allocated now.  flags: SBIE_SERVER_GRAPHS, SBIE_SERVER_BATCH, SBIE_SERVER_TREE.  Errors: SBIE_E_INVALID,
    SBIE_E_NOMEM, SBIE_E_DEVICE. */
 sbie_status sbie_server_create(sbie_ctx* ctx, int32_t max_sessions, uint64_t hbm_budget_bytes,
                                uint32_t flags, sbie_server** out);

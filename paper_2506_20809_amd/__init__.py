@@ -43,6 +43,7 @@ SBIE_TARGETS_SCRATCH_BYTES = 64 << 20
 SBIE_COMPLETE_POINT, SBIE_COMPLETE_SINGLE = 0, 1
 SBIE_SERVER_GRAPHS = 0x100
 SBIE_SERVER_BATCH = 0x200
+SBIE_SERVER_TREE = 0x400
 SBIE_MAX_PASS = 8
 
 
@@ -75,7 +76,8 @@ class ServerInfo(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_uint64), ("in_use_bytes", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64),
                 ("pending", ctypes.c_int64), ("active", ctypes.c_int64), ("admitted", ctypes.c_int64),
                 ("passed", ctypes.c_int64), ("waited", ctypes.c_int64), ("applies", ctypes.c_int64),
-                ("lanes", ctypes.c_int32), ("graphs", ctypes.c_int32), ("batched", ctypes.c_int64)]
+                ("lanes", ctypes.c_int32), ("graphs", ctypes.c_int32), ("batched", ctypes.c_int64),
+                ("tree_sessions", ctypes.c_int64)]
 
 
 _lib = None
@@ -483,10 +485,11 @@ class Server:
     """sbie_server: served mode (lanes of a host thread and a stream each, one HBM arena)."""
 
     def __init__(self, ctx: Context, max_sessions: int = 8, budget_bytes: int = 1 << 30, graphs: bool = True,
-                 batch: bool = False):
+                 batch: bool = False, tree: bool = False):
         self.ctx = ctx
         self._h = ctypes.c_void_p()
-        flags = (SBIE_SERVER_GRAPHS if graphs else 0) | (SBIE_SERVER_BATCH if batch else 0)
+        flags = ((SBIE_SERVER_GRAPHS if graphs else 0) | (SBIE_SERVER_BATCH if batch else 0)
+                 | (SBIE_SERVER_TREE if tree else 0))
         _check(lib().sbie_server_create(ctx.handle, int(max_sessions), int(budget_bytes), flags,
                                         ctypes.byref(self._h)))
         _live.append(weakref.ref(self))

@@ -135,6 +135,7 @@ struct FarTree {
   int64_t proxy_evals = 0, direct_evals = 0, charge_evals = 0;  // node-level work per apply
   size_t bytes = 0;
   char* blk = nullptr;                   // one device block holding everything below
+  bool blk_owned = true;                 // false: the block came from a TreeAlloc
   double* d_box = nullptr;               // [nused][6]
   int npiece = 0;                        // workgroups of the proxy charges (pieces of used clusters)
   int32_t *d_piece = nullptr;            // [npiece][3] cluster slot, first, count (in the permutation)
@@ -290,7 +291,14 @@ sbie_status device_error(hipError_t e, const char* what);
 // of row t set iff source particle s is excluded for target particle t.
 sbie_status plan_tree(int M, int T, const double* centers, const double* radii, const uint32_t* excl, int words,
                       double theta, int order, int leaf, TreePlan* out);
-sbie_status build_tree(sbie_geom* g, double theta, int order, int leaf);
+// Device memory for a tree from the caller (served sessions carve it from
+// their server's arena): fn returns a block of the given size, or nullptr when
+// none is free; the tree then does not free it.
+struct TreeAlloc {
+  char* (*fn)(void* ctx, size_t bytes) = nullptr;
+  void* ctx = nullptr;
+};
+sbie_status build_tree(sbie_geom* g, double theta, int order, int leaf, const TreeAlloc* alloc = nullptr);
 void free_tree(sbie_geom* g);
 sbie_status far_tree(sbie_geom* g, int op, bool mixed, hipStream_t s);
 sbie_status far_tree_normal(sbie_geom* g, int op, const double* d_dens, hipStream_t s);

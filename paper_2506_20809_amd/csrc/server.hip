@@ -81,6 +81,9 @@ using Clock = std::chrono::steady_clock;
 int nrhs_of(int op) { return op == SBIE_OP_STOKES_S ? 3 : 1; }
 
 constexpr int kServeBatch = 4;            // sessions one batching lane holds at most
+constexpr int kServeTreeMin = 64;         // particles from which a tree session takes the tree
+constexpr double kServeTheta = 0.6;       // the served tree's acceptance parameter, order and leaf size
+constexpr int kServeOrder = 10, kServeLeaf = 2;
 constexpr int64_t kBatchMaxNodes = 65536;  // larger sessions fill the device alone
 
 // Whether a session may share a batched apply: a small S or D session (a
@@ -108,6 +111,8 @@ struct sbie_session {
   uint64_t plan = 0, bytes = 0;  // geometry block, whole arena share
   size_t off = 0;
   bool admitted = false, closing = false, failed = false, counted_wait = false, batchable = false;
+  bool tree_candidate = false, has_tree = false;  // far field through a tree in the arena
+  size_t tree_off = 0, tree_bytes = 0;
   sbie_status fail = SBIE_OK;
   std::string fail_msg;
   sbie_geom* g = nullptr;
@@ -123,6 +128,7 @@ struct sbie_server {
   int device = 0;
   bool graphs = false;
   bool batch = false;  // lanes may hold several compatible sessions
+  bool tree = false;   // larger S and D sessions take their far field from a tree
   sbie::Arena arena;
   std::mutex mu;
   // Every HIP graph call of the lanes (capture, instantiation, launch,
@@ -146,7 +152,7 @@ struct sbie_server {
   int64_t next_session = 1;
   bool stopping = false;
   sbie::Clock::time_point t0;
-  int64_t n_active = 0, n_admitted = 0, n_passed = 0, n_waited = 0, n_applies = 0, n_batched = 0;
+  int64_t n_active = 0, n_admitted = 0, n_passed = 0, n_waited = 0, n_applies = 0, n_batched = 0, n_tree = 0;
 
   double now_us() const {
     return std::chrono::duration<double, std::micro>(sbie::Clock::now() - t0).count();
@@ -211,7 +217,46 @@ sbie_session* admit_locked(sbie_server* srv, int lane, const sbie_session* key) 
 
 sbie_status launch_apply(sbie_session* s, hipStream_t st) {
   if (s->op == SBIE_OP_STOKES_S) return apply_stokes(s->g, s->prec, s->d_in, s->d_out, st, SBIE_PARTS_ALL, false, false);
-  return apply_laplace(s->g, s->op, s->prec, s->d_in, s->d_out, st, SBIE_PARTS_ALL, false);
+  return apply_laplace(s->g, s->op, s->prec, s->d_in, s->d_out, st,
+                       SBIE_PARTS_ALL | (s->has_tree ? SBIE_FAR_TREE : 0u), false);
+}
+
+// The tree of a session in the server's arena (lane thread, lock not held):
+// the block is taken under the lock; if the arena has no room the session
+// keeps the direct far field.
+struct TreeArena {
+  sbie_server* srv;
+  sbie_session* s;
+};
+
+char* tree_block(void* ctx, size_t bytes) {
+  TreeArena* ta = static_cast<TreeArena*>(ctx);
+  std::lock_guard<std::mutex> lk(ta->srv->mu);
+  const size_t b = align_up(bytes);
+  size_t off = 0;
+  if (!ta->srv->arena.alloc(b, &off)) return nullptr;
+  ta->s->tree_off = off;
+  ta->s->tree_bytes = b;
+  return ta->srv->arena.base + off;
+}
+
+void build_session_tree(sbie_server* srv, sbie_session* s) {
+  TreeArena ta{srv, s};
+  TreeAlloc alloc;
+  alloc.fn = tree_block;
+  alloc.ctx = &ta;
+  const sbie_status rc = build_tree(s->g, kServeTheta, kServeOrder, kServeLeaf, &alloc);
+  s->has_tree = rc == SBIE_OK;
+  if (!s->has_tree && s->tree_bytes) {
+    // built no tree in a block it took: return the block
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->arena.release(s->tree_off, s->tree_bytes);
+    s->tree_bytes = 0;
+  }
+  if (s->has_tree) {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    ++srv->n_tree;
+  }
 }
 
 // Geometry build in the session's arena share, then the graph capture (lane
@@ -224,6 +269,7 @@ void build_session(sbie_server* srv, sbie_session* s, int lane) {
   // one stream per session: concurrency comes from the other lanes
   sbie_status rc = make_geometry(lctx, std::move(parts), s->p, s->eta, blk, s->plan, false, &s->g);
   if (rc == SBIE_OK && s->op == SBIE_OP_STOKES_S) rc = stokes_buffers(s->g);
+  if (rc == SBIE_OK && s->tree_candidate) build_session_tree(srv, s);
   if (rc == SBIE_OK) {
     const size_t io = align_up(sizeof(double) * (size_t)s->nrhs * s->N);
     s->d_in = reinterpret_cast<double*>(blk + s->plan);
@@ -453,6 +499,7 @@ void lane_main(sbie_server* srv, int lane) {
       teardown(srv, s);
       lk.lock();
       srv->arena.release(s->off, s->bytes);
+      if (s->tree_bytes) srv->arena.release(s->tree_off, s->tree_bytes);
       --srv->n_active;
       srv->sessions.erase(s);
       delete s;
@@ -511,6 +558,7 @@ sbie_status sbie_server_create(sbie_ctx* ctx, int32_t max_sessions, uint64_t hbm
   srv->device = ctx->device;
   srv->graphs = (flags & SBIE_SERVER_GRAPHS) != 0;
   srv->batch = (flags & SBIE_SERVER_BATCH) != 0;
+  srv->tree = (flags & SBIE_SERVER_TREE) != 0;
   srv->t0 = Clock::now();
   const size_t bytes = align_up(hbm_budget_bytes);
   hipError_t e = hipMalloc((void**)&srv->arena.base, bytes);
@@ -611,7 +659,8 @@ sbie_status sbie_session_open(sbie_server* srv, const double* centers, const dou
   s->N = (int64_t)M * (p + 1) * (2 * p + 2);
   s->plan = plan_bytes(M, p, op == SBIE_OP_STOKES_S);
   s->bytes = sbie_session_bytes(M, p, op);
-  s->batchable = srv->batch && batchable_shape(M, p, (int)op);
+  s->tree_candidate = srv->tree && (op == SBIE_OP_S || op == SBIE_OP_D) && M >= kServeTreeMin;
+  s->batchable = srv->batch && !s->tree_candidate && batchable_shape(M, p, (int)op);
   if (s->bytes > srv->arena.size) {
     set_error("the session needs " + std::to_string(s->bytes) + " bytes, more than the whole arena");
     delete s;
@@ -715,6 +764,7 @@ sbie_status sbie_server_get_info(sbie_server* srv, sbie_server_info* out) {
   out->lanes = (int32_t)srv->threads.size();
   out->graphs = srv->graphs ? 1 : 0;
   out->batched = srv->n_batched;
+  out->tree_sessions = srv->n_tree;
   return SBIE_OK;
 }
 

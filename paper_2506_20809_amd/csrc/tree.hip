@@ -1047,16 +1047,20 @@ void launch_eval32_d(sbie_geom* g, hipStream_t s, int threads) {
 
 void free_tree(sbie_geom* g) {
   if (!g->tree) return;
-  if (g->tree->blk) (void)hipFree(g->tree->blk);
+  if (g->tree->blk && g->tree->blk_owned) (void)hipFree(g->tree->blk);
   delete g->tree;
   g->tree = nullptr;
 }
 
-sbie_status build_tree(sbie_geom* g, double theta, int order, int leaf) {
+sbie_status build_tree(sbie_geom* g, double theta, int order, int leaf, const TreeAlloc* alloc) {
   const int M = g->M, T = g->T, words = g->excl_words;
   std::vector<uint32_t> excl((size_t)M * words);
   SBIE_HIP(hipSetDevice(g->ctx->device));
-  SBIE_HIP(hipMemcpy(excl.data(), g->d_excl, sizeof(uint32_t) * excl.size(), hipMemcpyDeviceToHost));
+  // every copy on the geometry's stream: a copy on the legacy stream would
+  // wait for (and, under another thread's graph capture, fail on) other streams
+  const hipStream_t cs = g->ctx->stream;
+  SBIE_HIP(hipMemcpyAsync(excl.data(), g->d_excl, sizeof(uint32_t) * excl.size(), hipMemcpyDeviceToHost, cs));
+  SBIE_HIP(hipStreamSynchronize(cs));
   std::vector<double> centers(3 * (size_t)M), radii(M);
   for (int i = 0; i < M; ++i) {
     for (int d = 0; d < 3; ++d) centers[3 * i + d] = g->h_part[i].c[d];
@@ -1123,7 +1127,15 @@ sbie_status build_tree(sbie_geom* g, double theta, int order, int leaf) {
   const size_t sz_s32 = al(sizeof(float) * 8 * (size_t)g->N);
   const size_t total = sz_box + sz_piece + sz_cptr + sz_perm + 2 * sz_ptr + sz_pidx + sz_didx + sz_q + sz_qp +
                        2 * sz_prec + sz_srec + sz_q32 + sz_sq32 + sz_s32;
-  if (hipMalloc(&tr->blk, total) != hipSuccess) {
+  if (alloc) {
+    tr->blk = alloc->fn(alloc->ctx, total);
+    tr->blk_owned = false;
+    if (!tr->blk) {
+      free_tree(g);
+      set_error("no device memory for the tree");
+      return SBIE_E_BUDGET;
+    }
+  } else if (hipMalloc(&tr->blk, total) != hipSuccess) {
     (void)hipGetLastError();
     free_tree(g);
     return SBIE_E_NOMEM;
@@ -1151,14 +1163,21 @@ sbie_status build_tree(sbie_geom* g, double theta, int order, int leaf) {
   tr->d_sq32 = reinterpret_cast<float*>(take(sz_sq32));
   tr->d_src32 = reinterpret_cast<float*>(take(sz_s32));
   tr->bytes = total;
-  SBIE_HIP(hipMemcpy(tr->d_box, box.data(), sizeof(double) * box.size(), hipMemcpyHostToDevice));
-  SBIE_HIP(hipMemcpy(tr->d_piece, piece.data(), sizeof(int32_t) * piece.size(), hipMemcpyHostToDevice));
-  SBIE_HIP(hipMemcpy(tr->d_cptr, cptr.data(), sizeof(int32_t) * cptr.size(), hipMemcpyHostToDevice));
-  SBIE_HIP(hipMemcpy(tr->d_perm, plan.perm.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice));
-  SBIE_HIP(hipMemcpy(tr->d_pptr, plan.pptr.data(), sizeof(int64_t) * (M + 1), hipMemcpyHostToDevice));
-  SBIE_HIP(hipMemcpy(tr->d_dptr, plan.dptr.data(), sizeof(int64_t) * (M + 1), hipMemcpyHostToDevice));
-  SBIE_HIP(hipMemcpy(tr->d_pidx, plan.pidx.data(), sizeof(int32_t) * plan.pidx.size(), hipMemcpyHostToDevice));
-  SBIE_HIP(hipMemcpy(tr->d_didx, plan.didx.data(), sizeof(int32_t) * plan.didx.size(), hipMemcpyHostToDevice));
+  // the host arrays outlive the copies: the guard, destroyed first, waits for them
+  struct StreamGuard {
+    hipStream_t s;
+    ~StreamGuard() { (void)hipStreamSynchronize(s); }
+  } guard{cs};
+  SBIE_HIP(hipMemcpyAsync(tr->d_box, box.data(), sizeof(double) * box.size(), hipMemcpyHostToDevice, cs));
+  SBIE_HIP(hipMemcpyAsync(tr->d_piece, piece.data(), sizeof(int32_t) * piece.size(), hipMemcpyHostToDevice, cs));
+  SBIE_HIP(hipMemcpyAsync(tr->d_cptr, cptr.data(), sizeof(int32_t) * cptr.size(), hipMemcpyHostToDevice, cs));
+  SBIE_HIP(hipMemcpyAsync(tr->d_perm, plan.perm.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice, cs));
+  SBIE_HIP(hipMemcpyAsync(tr->d_pptr, plan.pptr.data(), sizeof(int64_t) * (M + 1), hipMemcpyHostToDevice, cs));
+  SBIE_HIP(hipMemcpyAsync(tr->d_dptr, plan.dptr.data(), sizeof(int64_t) * (M + 1), hipMemcpyHostToDevice, cs));
+  SBIE_HIP(hipMemcpyAsync(tr->d_pidx, plan.pidx.data(), sizeof(int32_t) * plan.pidx.size(), hipMemcpyHostToDevice,
+                          cs));
+  SBIE_HIP(hipMemcpyAsync(tr->d_didx, plan.didx.data(), sizeof(int32_t) * plan.didx.size(), hipMemcpyHostToDevice,
+                          cs));
   // the mixed path's geometric records
   const hipStream_t s = g->ctx->stream;
   if (nu > 0)

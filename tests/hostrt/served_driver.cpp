@@ -137,12 +137,55 @@ void served_path(int lanes, uint32_t flags) {
   sbie_ctx_destroy(ctx);
 }
 
+// Served sessions with the tree far field (two of 64 particles, S and D, and
+// one of 3 that keeps the direct field) on three lanes (one per session: the
+// sessions stay open across all their applies) with graph replay.
+void served_tree_path() {
+  sbie_ctx* ctx = nullptr;
+  check(sbie_ctx_create(0, &ctx), "sbie_ctx_create");
+  if (!ctx) return;
+  sbie_server* srv = nullptr;
+  check(sbie_server_create(ctx, 3, 512ull << 20, SBIE_SERVER_GRAPHS | SBIE_SERVER_TREE, &srv), "sbie_server_create");
+  if (!srv) return;
+  const int p = 4;
+  std::vector<sbie_session*> ss;
+  std::vector<int64_t> ns;
+  for (int k = 0; k < 3; ++k) {
+    const int m = k < 2 ? 64 : 3;
+    Particles P = line_of(m, 900 + k);
+    sbie_session* s = nullptr;
+    check(sbie_session_open(srv, P.c.data(), P.q.data(), P.A.data(), P.C.data(), m, p, 1.0,
+                            k == 1 ? SBIE_OP_D : SBIE_OP_S, k == 0 ? SBIE_MIXED : SBIE_FP64, &s),
+          "sbie_session_open tree");
+    ss.push_back(s);
+    ns.push_back((int64_t)m * (p + 1) * (2 * p + 2));
+  }
+  for (int r = 0; r < 2; ++r)
+    for (size_t k = 0; k < ss.size(); ++k) {
+      if (!ss[k]) continue;
+      std::vector<double> dens(ns[k], 1.0 + r), out(ns[k], 0.0);
+      uint64_t ticket = 0;
+      check(sbie_session_apply(ss[k], dens.data(), out.data(), 0, &ticket), "sbie_session_apply tree");
+      check(sbie_wait(srv, ticket, -1, nullptr), "sbie_wait tree");
+    }
+  for (sbie_session* s : ss)
+    if (s) check(sbie_session_close(s), "sbie_session_close tree");
+  sbie_server_info info;
+  check(sbie_server_get_info(srv, &info), "sbie_server_get_info");
+  std::printf("served tree: applies %lld, tree sessions %lld\n", (long long)info.applies,
+              (long long)info.tree_sessions);
+  if (info.applies != 6 || info.tree_sessions != 2) g_failures.fetch_add(1);
+  sbie_server_destroy(srv);
+  sbie_ctx_destroy(ctx);
+}
+
 }  // namespace
 
 int main() {
   plain_path();
   served_path(8, SBIE_SERVER_GRAPHS);
   served_path(2, SBIE_SERVER_GRAPHS | SBIE_SERVER_BATCH);
+  served_tree_path();
   standin_report(stdout);
   const long v = standin_violations();
   std::printf("failures %d violations %ld\n", g_failures.load(), v);

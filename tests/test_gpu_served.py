@@ -336,3 +336,48 @@ def test_served_batched_bitwise_equals_plain(ctx, op, prec):
         ref = _plain(ctx, g, p, o, precs[k], dens[k])
         for r in range(napply):
             assert np.array_equal(results[k][r], ref[r]), (k, r, np.max(np.abs(results[k][r] - ref[r])))
+
+
+def test_served_tree_sessions_equal_plain_tree_applies(ctx):
+    """SBIE_SERVER_TREE: S and D sessions of at least 64 particles build the
+    tree far field (theta 0.6, order 10, leaf 2) in the arena and their applies
+    equal a plain geometry's applies through the same tree, bitwise; a smaller
+    session keeps the direct far field.  With an arena too small for the tree
+    a large session keeps the direct far field too."""
+    import paper_2506_20809_amd as sbie
+
+    p = 8
+    specs = [(80, 0, 0), (70, 1, 1), (20, 0, 0)]
+    geoms = [workloads.rsa_pack(M, 0.15, 0.05, 610 + k) for k, (M, _, _) in enumerate(specs)]
+    dens = [_densities(2, 1, len(g["A"]) * (p + 1) * (2 * p + 2), 620 + k) for k, g in enumerate(geoms)]
+
+    def plain(geom, op, prec, ds, tree):
+        g = sbie.Geometry(ctx, geom, p)
+        if tree:
+            g.far_tree(0.6, 10, 2)
+        out = [g.apply(op, d, precision=prec, tree=tree) for d in ds]
+        g.close()
+        return out
+
+    srv = sbie.Server(ctx, max_sessions=3, budget_bytes=1 << 30, graphs=True, tree=True)
+    sess = [srv.open(g, p, op, prec) for g, (_, op, prec) in zip(geoms, specs)]
+    results = [[s.apply(d)[0] for d in dens[k]] for k, s in enumerate(sess)]
+    for s in sess:
+        s.close()
+    info = srv.info()
+    srv.close()
+    assert info.tree_sessions == 2 and info.applies == 6
+    for k, (geom, (M, op, prec)) in enumerate(zip(geoms, specs)):
+        ref = plain(geom, op, prec, dens[k], M >= 64)
+        for r in range(2):
+            assert np.array_equal(results[k][r], ref[r]), (k, r)
+    # an arena with room for the session but not for its tree
+    nb = sbie.session_bytes(80, p, 0)
+    srv = sbie.Server(ctx, max_sessions=1, budget_bytes=nb + (1 << 20), graphs=True, tree=True)
+    s = srv.open(geoms[0], p, 0, 0)
+    out = s.apply(dens[0][0])[0]
+    s.close()
+    info = srv.info()
+    srv.close()
+    assert info.tree_sessions == 0
+    assert np.array_equal(out, plain(geoms[0], 0, 0, dens[0][:1], False)[0])

@@ -91,5 +91,6 @@ def test_host_code_under_sanitizer(san, tmp_path):
     assert res.returncode == 0, log[-6000:]
     assert "served: admitted 40, applies 200, lanes 8, graphs 1\n" in log, log[-2000:]
     assert "served: admitted 40, applies 200, lanes 2, graphs 1, batched" in log, log[-2000:]
+    assert "served tree: applies 6, tree sessions 2" in log, log[-2000:]
     assert "violations 0" in log, log[-2000:]
     shutil.rmtree(str(tmp_path), ignore_errors=True)

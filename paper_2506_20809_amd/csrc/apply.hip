@@ -210,13 +210,15 @@ __device__ __forceinline__ void near_f64_body(
   const int K = (p + 1) * (p + 1), Kh = (p + 1) * (p + 2) / 2, N = p + 1;
   // Tables read with wave-uniform addresses, staged in LDS so that they stay
   // out of the scalar registers: the Ferrers recurrence table and 1/k (once),
-  // each source's exterior coefficients and spectral ratios 1/Q_n^m(u0).
+  // each source's exterior coefficients times the spectral ratios 1/Q_n^|m|(u0).
+  // The coefficients of the recurrence in n come from their own table.
   constexpr int KM = (PMAX + 1) * (PMAX + 1), KHM = (PMAX + 1) * (PMAX + 2) / 2;
   constexpr int KH2M = (PMAX + 2) * (PMAX + 3) / 2, RM = 2 * PMAX + 8;
-  __shared__ double s_E[KM], s_L[KHM], s_ab[2 * KH2M], s_rcp[RM];
+  __shared__ double s_E[KM], s_ab[2 * KH2M], s_rcp[RM], s_qt[4 * KHM];
   const int Kh2 = (p + 2) * (p + 3) / 2;
   for (int k = threadIdx.x; k < 2 * Kh2; k += 64) s_ab[k] = ab[k];
   for (int k = threadIdx.x; k < RM; k += 64) s_rcp[k] = rcp[k];
+  q_recurrence_table<2>(p, s_qt, threadIdx.x, 64);
   double acc = 0.0;
   unsigned bad = 0u;
   const int n0 = near_ptr[j], nn = near_ptr[j + 1] - n0;
@@ -225,8 +227,12 @@ __device__ __forceinline__ void near_f64_body(
     const int i = near_src[s];
     const Particle P = part[i];
     __syncthreads();  // the previous source's tables have been read
-    for (int k = threadIdx.x; k < K; k += 64) s_E[k] = E[(size_t)i * K + k];
-    for (int k = threadIdx.x; k < Kh; k += 64) s_L[k] = lam[((size_t)i * Kh + k) * 4 + 3];
+    for (int k = threadIdx.x; k < K; k += 64) {
+      int n = (int)sqrt((double)k);
+      n -= n * n > k ? 1 : 0;
+      const int m = k - n * n - n;
+      s_E[k] = E[(size_t)i * K + k] * lam[((size_t)i * Kh + n * (n + 1) / 2 + (m < 0 ? -m : m)) * 4 + 3];
+    }
     __syncthreads();
     const double* Ei = s_E;
     // lab -> body frame of the source
@@ -267,8 +273,9 @@ __device__ __forceinline__ void near_f64_body(
     double fa2 = 0.0, fa1 = 0.0, fb2 = 0.0, fb1 = 0.0;  // F^(m-2), F^(m-1) at degrees N and N+1
     double pbar = 0.28209479177387814347;  // normalised Ferrers Pb_m^m(v), 1/sqrt(4 pi) at m = 0
     double cm = 1.0, sm = 0.0;             // cos(m phi), sin(m phi)
-#pragma unroll 1
-    for (int m = 0; m <= p; ++m) {
+    for_orders<PMAX, kUnrollOrders<PMAX, EXACT>>(p, [&](auto mc) {
+      const int m = mc;
+      __builtin_amdgcn_sched_barrier(0);  // orders one after the other: bounded live ranges
       if (m > 0) {
         pbar *= s_ab[m * (m + 3)] * sv;  // sqrt((2m+1)/(2m)), row n = m
         const double cn = cm * c1 - sm * s1;
@@ -282,7 +289,7 @@ __device__ __forceinline__ void near_f64_body(
       fb2 = fb1;
       fb1 = qN1;
       double Q[PMAX + 4];
-      q_column<PMAX>(u, sgn, N, m, qN, qN1, s_rcp, Q);
+      q_column_tab<PMAX, 2>(u, N, m, qN, qN1, s_qt + (P.oblate ? 2 * Kh : 0), Q);
       // contraction with the normalised Ferrers functions, forward in n
       double sc = 0.0, ss = 0.0;
       double p2 = 0.0, p1 = pbar;
@@ -302,8 +309,7 @@ __device__ __forceinline__ void near_f64_body(
             p2 = p1;
             p1 = pn;
           }
-          const double qr = Q[n] * s_L[n * (n + 1) / 2 + m];
-          const double t0 = pn * qr;
+          const double t0 = pn * Q[n];
           sc = fma(Ei[n * n + n + m], t0, sc);
           if (m > 0) ss = fma(Ei[n * n + n - m], t0, ss);
         }
@@ -312,14 +318,14 @@ __device__ __forceinline__ void near_f64_body(
         acc += sc;
       else
         acc += 1.41421356237309504880 * (sc * cm + ss * sm);
-    }
+    });
   }
   if (bad) atomicOr(status, bad);
   if (live) unear[(size_t)q4 * Nn + g] = acc;
 }
 
 template <int PMAX, bool EXACT>
-__global__ __launch_bounds__(64) void k_near_f64(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_near_f64(
     const Particle* __restrict__ part, const double* __restrict__ x, const double* __restrict__ y,
     const double* __restrict__ z, const int32_t* __restrict__ near_ptr,
     const int32_t* __restrict__ near_src, const double* __restrict__ E,
@@ -332,7 +338,7 @@ __global__ __launch_bounds__(64) void k_near_f64(
 // Several geometries' near fields (one order) in one launch: job j owns the
 // workgroups [wg_begin_j, wg_begin_{j+1}) and runs those of its own launch.
 template <int PMAX, bool EXACT>
-__global__ __launch_bounds__(64) void k_near_f64_batch(const NearJob* __restrict__ jobs, int njobs) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_near_f64_batch(const NearJob* __restrict__ jobs, int njobs) {
   const int bid = (int)blockIdx.x;
   int lo = 0, hi = njobs - 1;  // the last job starting at or before bid
   while (lo < hi) {

@@ -83,7 +83,7 @@ __global__ void k_normal_scale(const double* __restrict__ coef, const double* __
 // in (u, v, phi) at the mapped target and its lab gradient is projected on the
 // target's normal.
 template <int PMAX, bool EXACT>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_near_normal(
+__global__ __launch_bounds__((64 * kNearWaves<kUnrollOrders<PMAX, EXACT>>)) __attribute__((amdgpu_waves_per_eu(3))) void k_near_normal(
     const Particle* __restrict__ part, const double* __restrict__ x, const double* __restrict__ y,
     const double* __restrict__ z, const double* __restrict__ nx, const double* __restrict__ ny,
     const double* __restrict__ nz, const int32_t* __restrict__ near_ptr, const int32_t* __restrict__ near_src,
@@ -91,14 +91,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     const double* __restrict__ cd, const double* __restrict__ rcp, int p_arg, int T, int chunks, int64_t Nn,
     unsigned* status, double* __restrict__ unear) {
   const int p = EXACT ? PMAX : p_arg;  // exact order: degree bounds known at compile time
+  // one workgroup per (target particle, 64 W target nodes, quarter of its
+  // near-source list)
+  constexpr int W = kNearWaves<kUnrollOrders<PMAX, EXACT>>;
+  const int wgs = (chunks + W - 1) / W;
   const int q4 = blockIdx.x % kNearSplit, rest = blockIdx.x / kNearSplit;
-  const int j = rest / chunks;
-  const int t = (rest - j * chunks) * 64 + threadIdx.x;
+  const int j = rest / wgs;
+  const int t = (rest - j * wgs) * 64 * W + threadIdx.x;
   const bool live = t < T;
   const int64_t g = (int64_t)j * T + (live ? t : 0);
   const double X0 = x[g], X1 = y[g], X2 = z[g];
   const double n0 = nx[g], n1 = ny[g], n2 = nz[g];
   const int K = (p + 1) * (p + 1), Kh = (p + 1) * (p + 2) / 2;
+  __shared__ NearTablesFor<PMAX, kUnrollOrders<PMAX, EXACT>, 1> tb;
+  near_tables_init<PMAX, kUnrollOrders<PMAX, EXACT>, 1>(tb, ab, cd);
   double acc = 0.0;
   unsigned bad = 0u;
   const int l0 = near_ptr[j], nl = near_ptr[j + 1] - l0;
@@ -114,14 +120,42 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     const double cu = al[0] * n0 + al[1] * n1 + al[2] * n2;
     const double cv = be[0] * n0 + be[1] * n1 + be[2] * n2;
     const double cp = ga[0] * n0 + ga[1] * n1 + ga[2] * n2;
-    const double* Ei = E + (size_t)i * K;
+    const NearSourceView src =
+        near_source<PMAX, kUnrollOrders<PMAX, EXACT>, 1>(tb, P.oblate != 0, E + (size_t)i * K, lam + (size_t)i * Kh * 4, ab, cd, K, Kh);
+    const double* Ei = src.E;
     double dn = 0.0;
-    expansion_terms<PMAX>(q, P.oblate != 0, lam + (size_t)i * Kh * 4, ab, cd, rcp, p, &bad,
-                          [&](int lc, int ls, int m, double, double a1, double a2, double ap, double, double b1,
-                              double b2, double bp) {
-                            dn = fma(Ei[lc], fma(cp, ap, fma(cv, a2, cu * a1)), dn);
-                            if (m > 0) dn = fma(Ei[ls], fma(cp, bp, fma(cv, b2, cu * b1)), dn);
-                          });
+    if constexpr (kUnrollOrders<PMAX, EXACT>) {
+      // per-order sums of the value and the scaled u and v derivatives of the
+      // cosine (c) and sine (s) terms; the 1/w and 1/(1 - v^2) of the
+      // derivatives folded into the direction once per source
+      const double cuw = cu / q.w, cvw = cv / (q.sv * q.sv);
+      double a0c = 0.0, a0s = 0.0, auc = 0.0, aus = 0.0, avc = 0.0, avs = 0.0;
+      expansion_orders<PMAX>(
+          q, P.oblate != 0, src.ab, src.cd, rcp, src.qt, &bad, [](int, double, double) {},
+          [&](int lc, int ls, int m, double t0, double tu, double tv) {
+            const double ec = Ei[lc];
+            a0c = fma(ec, t0, a0c);
+            auc = fma(ec, tu, auc);
+            avc = fma(ec, tv, avc);
+            if (m > 0) {
+              const double es = Ei[ls];
+              a0s = fma(es, t0, a0s);
+              aus = fma(es, tu, aus);
+              avs = fma(es, tv, avs);
+            }
+          },
+          [&](int m, double c, double s) {
+            dn += fma(cuw, fma(c, auc, s * aus), fma(cvw, fma(c, avc, s * avs), cp * (double)m * fma(c, a0s, -s * a0c)));
+            a0c = a0s = auc = aus = avc = avs = 0.0;
+          });
+    } else {
+      expansion_terms<PMAX>(q, P.oblate != 0, src.L, src.ab, src.cd, rcp, p, &bad,
+                            [&](int lc, int ls, int m, double, double a1, double a2, double ap, double, double b1,
+                                double b2, double bp) {
+                              dn = fma(Ei[lc], fma(cp, ap, fma(cv, a2, cu * a1)), dn);
+                              if (m > 0) dn = fma(Ei[ls], fma(cp, bp, fma(cv, b2, cu * b1)), dn);
+                            });
+    }
     acc += dn;
   }
   if (bad) atomicOr(status, bad);
@@ -238,7 +272,9 @@ __global__ void k_normal_assemble(const double* __restrict__ uself, const double
 template <int PMAX, bool EXACT>
 void launch_near_normal(sbie_geom* g, hipStream_t s) {
   const int chunks = (g->T + 63) / 64;
-  hipLaunchKernelGGL((k_near_normal<PMAX, EXACT>), dim3(g->M * chunks * kNearSplit), dim3(64), 0, s, g->d_part, g->d_x,
+  constexpr int W = kNearWaves<kUnrollOrders<PMAX, EXACT>>;
+  hipLaunchKernelGGL((k_near_normal<PMAX, EXACT>), dim3(g->M * ((chunks + W - 1) / W) * kNearSplit), dim3(64 * W), 0,
+                     s, g->d_part, g->d_x,
                      g->d_y, g->d_z, g->d_nx, g->d_ny, g->d_nz, g->d_near_ptr, g->d_near_src, g->d_E, g->d_lam,
                      g->d_ab, g->d_cd, g->d_rcp, g->p, g->T, chunks, g->N, g->d_status, g->d_unear);
 }

@@ -7,9 +7,39 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "sbie_internal.h"
 
 namespace sbie {
+
+// f(std::integral_constant<int, B>{}), ..., f(std::integral_constant<int, E>{}).
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B <= E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// The orders m = 0 .. p in ascending order.  With UNROLL (the order fixed at
+// PMAX at compile time) every call sees m as a constant, so each degree test
+// n >= m and every recurrence coefficient folds and the order's code is
+// straight-line; otherwise a plain loop with m at run time.
+template <int PMAX, bool UNROLL, typename F>
+__device__ __forceinline__ void for_orders(int p, F&& f) {
+  if constexpr (UNROLL) {
+    static_for<0, PMAX>(f);
+  } else {
+#pragma unroll 1
+    for (int m = 0; m <= p; ++m) f(m);
+  }
+}
+
+// Unrolling the orders pays while the kernel's code stays in the instruction
+// cache: (p+1)(p+2)/2 straight-line (n, m) steps for p up to 16.
+template <int PMAX, bool EXACT>
+constexpr bool kUnrollOrders = EXACT && PMAX <= 16;
 
 // Depth L of the backward recurrence: the ratio of the minimal to the
 // dominant solution shrinks by (u + sqrt(w))^-2 per degree; 2^-58 plus a
@@ -117,6 +147,132 @@ __device__ inline void q_column(double u, double sgn, int N, int m, double qN, d
     } else {
       Q[n] = 0.0;
     }
+  }
+}
+
+// The downward recurrence in n of q_column with its coefficients per (n, m)
+// from a table: Q_n = A_nm u Q_{n+1} + sgn B_nm Q_{n+2} with
+// A_nm = (2n+3)/(n+m+1) and B_nm = (n-m+2)/(n+m+1).  Row h = n(n+1)/2 + m,
+// n = 0 .. p, holds (A_nm, -B_nm) in the prolate half and (A_nm, B_nm) in the
+// oblate half (kh = (p+1)(p+2)/2 rows each); with COLS = 3 a third column
+// holds -sgn (n-m+1), the coefficient of Q_{n+1} in the u-derivative
+// w dQ_n/du = -sgn (n-m+1) Q_{n+1} - (n+1) u Q_n.  Every (n, m) reads its own
+// row, so with the orders unrolled no coefficient is shared between orders
+// (which would keep it in a register across all of them).
+template <int COLS>
+__device__ inline void q_recurrence_table(int p, double* tab, int tid, int nthreads) {
+  const int kh = (p + 1) * (p + 2) / 2;
+  for (int k = tid; k < 2 * kh; k += nthreads) {
+    const int h = k < kh ? k : k - kh;
+    const double sgn = k < kh ? -1.0 : 1.0;
+    int n = (int)((sqrt(8.0 * h + 1.0) - 1.0) * 0.5);
+    n += (n + 1) * (n + 2) / 2 <= h ? 1 : 0;
+    n -= n * (n + 1) / 2 > h ? 1 : 0;
+    const int m = h - n * (n + 1) / 2;
+    const double r = 1.0 / (double)(n + m + 1);
+    tab[COLS * k] = (double)(2 * n + 3) * r;
+    tab[COLS * k + 1] = sgn * (double)(n - m + 2) * r;
+    if constexpr (COLS == 3) tab[3 * k + 2] = -sgn * (double)(n - m + 1);
+  }
+}
+
+template <int PMAX, int COLS>
+__device__ inline void q_column_tab(double u, int N, int m, double qN, double qN1, const double* __restrict__ tab,
+                                    double (&Q)[PMAX + 4]) {
+#pragma unroll
+  for (int n = PMAX + 2; n >= 0; --n) {
+    if (n == N + 1) {
+      Q[n] = qN1;
+    } else if (n == N) {
+      Q[n] = qN;
+    } else if (n < N && n >= m) {
+      const int h = n * (n + 1) / 2 + m;
+      Q[n] = fma(tab[COLS * h], u * Q[n + 1], tab[COLS * h + 1] * Q[n + 2]);
+    } else {
+      Q[n] = 0.0;
+    }
+  }
+}
+
+// Waves per workgroup of the near-field kernels built on expansion_orders
+// (UNROLL): two waves (128 target nodes of one particle) share the LDS tables
+// below; with expansion_terms one.
+template <bool UNROLL>
+constexpr int kNearWaves = UNROLL ? 2 : 1;
+
+// LDS of those kernels with the orders unrolled (p = PMAX): per workgroup the
+// normalised Ferrers recurrence (ab) and derivative (cd) coefficients through
+// degree p+1 and the three-column recurrence table in n; per source its NSET
+// expansions, set s at E[s K + l], each coefficient times the spectral ratio
+// 1/Q_n^|m|(u0) of its (n, |m|).  Wave-uniform reads from LDS keep these
+// values out of the scalar registers, which the unrolled orders would
+// otherwise fill with hoisted loads.
+template <int PMAX, int NSET>
+struct NearTables {
+  static constexpr int KM = (PMAX + 1) * (PMAX + 1), KHM = (PMAX + 1) * (PMAX + 2) / 2,
+                       KH2M = (PMAX + 2) * (PMAX + 3) / 2;
+  double E[NSET * KM];
+  double ab[2 * KH2M];
+  double cd[KHM];
+  double qt[6 * KHM];
+
+  __device__ void stage_fixed(const double* __restrict__ gab, const double* __restrict__ gcd, int tid, int nt) {
+    for (int k = tid; k < 2 * KH2M; k += nt) ab[k] = gab[k];
+    for (int k = tid; k < KHM; k += nt) cd[k] = gcd[k];
+    q_recurrence_table<3>(PMAX, qt, tid, nt);
+  }
+
+  // Es: the source's first set (sets stride doubles apart); L: its spectra
+  // rows (column 3 holds 1/Q_n^m(u0)).
+  __device__ void stage_source(const double* __restrict__ Es, size_t stride, const double* __restrict__ L, int tid,
+                               int nt) {
+    for (int k = tid; k < NSET * KM; k += nt) {
+      const int s = k / KM, l = k - s * KM;
+      int n = (int)sqrt((double)l);
+      n -= n * n > l ? 1 : 0;
+      const int m = l - n * n - n;
+      E[k] = Es[(size_t)s * stride + l] * L[(n * (n + 1) / 2 + (m < 0 ? -m : m)) * 4 + 3];
+    }
+  }
+};
+
+struct NoNearTables {};
+
+template <int PMAX, bool UNROLL, int NSET>
+using NearTablesFor = std::conditional_t<UNROLL, NearTables<PMAX, NSET>, NoNearTables>;
+
+// What expansion_terms reads for one source: its coefficient sets (set s at
+// E + s K), spectra rows L, the ab and cd tables and the recurrence table qt.
+struct NearSourceView {
+  const double* E;
+  const double* L;
+  const double* ab;
+  const double* cd;
+  const double* qt;
+};
+
+// Once per workgroup, before the first near_source: the fixed tables.
+template <int PMAX, bool UNROLL, int NSET>
+__device__ inline void near_tables_init(NearTablesFor<PMAX, UNROLL, NSET>& tb, const double* __restrict__ ab,
+                                        const double* __restrict__ cd) {
+  if constexpr (UNROLL) tb.stage_fixed(ab, cd, threadIdx.x, blockDim.x);
+}
+
+// One source's view: with the orders unrolled its sets are staged (scaled)
+// in LDS between two barriers, which every wave of the workgroup reaches (all
+// run the same source list); otherwise the global arrays as they are.
+template <int PMAX, bool UNROLL, int NSET>
+__device__ inline NearSourceView near_source(NearTablesFor<PMAX, UNROLL, NSET>& tb, bool oblate,
+                                             const double* __restrict__ Ei, const double* __restrict__ Li,
+                                             const double* __restrict__ ab, const double* __restrict__ cd, int K,
+                                             int Kh) {
+  if constexpr (UNROLL) {
+    __syncthreads();  // the previous source's sets have been read
+    tb.stage_source(Ei, (size_t)K, Li, threadIdx.x, blockDim.x);
+    __syncthreads();
+    return {tb.E, nullptr, tb.ab, tb.cd, tb.qt + (oblate ? 3 * Kh : 0)};
+  } else {
+    return {Ei, Li, ab, cd, nullptr};
   }
 }
 
@@ -240,6 +396,79 @@ __device__ inline void expansion_terms(const SpheroidalPoint& q, bool oblate, co
       }
     }
   }
+}
+
+// The same expansion with the orders unrolled (p = PMAX), for kernels that
+// keep per-order partial sums.  For every (n, m), m = 0 .. PMAX and
+// n = m .. PMAX in ascending order, term(lc, ls, m, t0, tu, tv) receives the
+// coefficient indices as above and
+//   t0 = Pb_n^m(v) Q_n^m(u),  tu = Pb_n^m(v) w dQ_n^m/du,
+//   tv = (1 - v^2) dPb_n^m/dv Q_n^m(u),
+// without the factor 1/Q_n^m(u0) (the caller's coefficients carry it, as
+// NearTables stages them) and without the azimuthal factor; after the
+// degrees of order m, order_end(m, c, s) receives c = f_m cos(m phi) and
+// s = f_m sin(m phi) (f_0 = 1, f_m = sqrt 2), and order_begin(m, c, s) the
+// same before them.  With per-order sums
+// A = sum_n E_{n,m} t and B = sum_n E_{n,-m} t an expansion adds c A + s B
+// for t = t0 (its value), tu (w d/du) and tv ((1 - v^2) d/dv), and
+// m (c B - s A) over t0 for d/dphi.  qt: the source kind's half of the
+// three-column q_recurrence_table; ab and cd as for expansion_terms.
+template <int PMAX, typename FB, typename FT, typename FO>
+__device__ inline void expansion_orders(const SpheroidalPoint& q, bool oblate, const double* __restrict__ ab,
+                                        const double* __restrict__ cd, const double* __restrict__ rcp,
+                                        const double* __restrict__ qt, unsigned* bad, FB&& order_begin, FT&& term,
+                                        FO&& order_end) {
+  constexpr int N1 = PMAX + 1;
+  const double u = q.u, v = q.v;
+  const double sgn = oblate ? 1.0 : -1.0;
+  const int Ld = near_depth(u, q.sw, N1, kStatNumeric, bad);
+  double qn0[2], qn1[2];
+  q_top_orders01(u, q.sw, sgn, N1, Ld, rcp, qn0, qn1);
+  const double ur = u / q.sw;
+  double fa2 = 0.0, fa1 = 0.0, fb2 = 0.0, fb1 = 0.0;
+  double pbar = 0.28209479177387814347, cm = 1.0, sm = 0.0;
+  static_for<0, PMAX>([&](auto mc) {
+    constexpr int m = decltype(mc)::value;
+    __builtin_amdgcn_sched_barrier(0);  // orders one after the other: bounded live ranges
+    if constexpr (m > 0) {
+      pbar *= ab[m * (m + 3)] * q.sv;  // sqrt((2m+1)/(2m)), row n = m of the table
+      const double cn = cm * q.c1 - sm * q.s1;
+      sm = sm * q.c1 + cm * q.s1;
+      cm = cn;
+    }
+    const double qN = m == 0 ? qn0[0] : (m == 1 ? qn0[1] : q_next_order(ur, N1, m, fa1, fa2));
+    const double qN1 = m == 0 ? qn1[0] : (m == 1 ? qn1[1] : q_next_order(ur, N1 + 1, m, fb1, fb2));
+    fa2 = fa1;
+    fa1 = qN;
+    fb2 = fb1;
+    fb1 = qN1;
+    double Q[PMAX + 4];
+    q_column_tab<PMAX, 3>(u, N1, m, qN, qN1, qt, Q);
+    const double fm = m == 0 ? 1.0 : 1.41421356237309504880;
+    order_begin(m, fm * cm, fm * sm);
+    // normalised Ferrers functions of v rolled forward in n: P_{n-1}, P_n, P_{n+1}
+    double pm1 = 0.0, pn = pbar;
+    static_for<m, PMAX>([&](auto nc) {
+      constexpr int n = decltype(nc)::value;
+      constexpr int h = n * (n + 1) / 2 + m;
+      const double vp = v * pn;
+      double pn1;
+      if constexpr (n == m) {
+        pn1 = ab[(m + 1) * (m + 2) + 2 * m] * vp;  // sqrt(2m+3), row n = m+1
+      } else {
+        constexpr int h1 = (n + 1) * (n + 2) / 2 + m;
+        pn1 = ab[2 * h1] * fma(-ab[2 * h1 + 1], pm1, vp);
+      }
+      const double t0 = pn * Q[n];
+      const double tu = pn * fma(qt[3 * h + 2], Q[n + 1], -(double)(n + 1) * (u * Q[n]));
+      const double tv = fma(-cd[h], pn1, (double)(n + 1) * vp) * Q[n];
+      term(n * n + n + m, n * n + n - m, m, t0, tu, tv);
+      pm1 = pn;
+      pn = pn1;
+      __builtin_amdgcn_sched_barrier(0);  // a degree's loads stay after the previous degree's work
+    });
+    order_end(m, fm * cm, fm * sm);
+  });
 }
 
 // NSET exterior expansions of one source particle at a mapped point, with

@@ -133,21 +133,26 @@ __global__ void k_stokes_self(const Particle* __restrict__ part, const double* _
 // field, and the four expansions are summed with their u, v and phi
 // derivatives.
 template <int PMAX, bool EXACT, int C>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_near_stokes(
+__global__ __launch_bounds__((64 * kNearWaves<kUnrollOrders<PMAX, EXACT>>)) __attribute__((amdgpu_waves_per_eu(3))) void k_near_stokes(
     const Particle* __restrict__ part, const double* __restrict__ x, const double* __restrict__ y,
     const double* __restrict__ z, const int32_t* __restrict__ near_ptr, const int32_t* __restrict__ near_src,
     const double* __restrict__ E, const double* __restrict__ lam, const double* __restrict__ ab,
     const double* __restrict__ cd, const double* __restrict__ rcp, int p_arg, int T, int chunks, int64_t N,
     unsigned* status, double* __restrict__ unear) {
   const int p = EXACT ? PMAX : p_arg;  // exact order: degree bounds known at compile time
-  // one wave per (target particle, 64 targets, range q of its near-source list)
+  // one workgroup per (target particle, 64 W targets, range q of its
+  // near-source list)
+  constexpr int W = kNearWaves<kUnrollOrders<PMAX, EXACT>>;
+  const int wgs = (chunks + W - 1) / W;
   const int q = blockIdx.x % kStokesNearSplit, rest = blockIdx.x / kStokesNearSplit;
-  const int j = rest / chunks;
-  const int t = (rest - j * chunks) * 64 + threadIdx.x;
+  const int j = rest / wgs;
+  const int t = (rest - j * wgs) * 64 * W + threadIdx.x;
   const bool live = t < T;
   const int64_t g = (int64_t)j * T + (live ? t : 0);
   const double X0 = x[g], X1 = y[g], X2 = z[g];
   const int K = (p + 1) * (p + 1), Kh = (p + 1) * (p + 2) / 2;
+  __shared__ NearTablesFor<PMAX, kUnrollOrders<PMAX, EXACT>, 4> tb;
+  near_tables_init<PMAX, kUnrollOrders<PMAX, EXACT>, 4>(tb, ab, cd);
   double acc[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) acc[c] = 0.0;
@@ -158,7 +163,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     const int i = near_src[sidx];
     const Particle P = part[i];
     const SpheroidalPoint sp = to_spheroidal(P, X0, X1, X2, true, &bad);
-    const double* Ei = E + (size_t)i * 4 * K;
+    const NearSourceView src =
+        near_source<PMAX, kUnrollOrders<PMAX, EXACT>, 4>(tb, P.oblate != 0, E + (size_t)i * 4 * K, lam + (size_t)i * Kh * 4, ab, cd, K, Kh);
+    const double* Ei = src.E;
     // Eq. (stokes) is linear in the four expansions, so it is taken inside the
     // sum over (n, m), one basis evaluation for all of them: the values of
     // S[sigma_k]; grad (S[rho] - sum_j d_j S[sigma_j]) as the gradient of one
@@ -170,7 +177,77 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     lab_gradient_coeffs(P, sp.u, sp.sw, sp.v, sp.sv, sp.c1, sp.s1, al, be, ga);
     const double w0 = -sp.d[0], w1 = -sp.d[1], w2 = -sp.d[2];
     double Phi[3] = {0.0, 0.0, 0.0}, Gu = 0.0, Gv = 0.0, Gp = 0.0, pr = 0.0;
-    expansion_terms<PMAX>(sp, P.oblate != 0, lam + (size_t)i * Kh * 4, ab, cd, rcp, p, &bad,
+    if constexpr (kUnrollOrders<PMAX, EXACT>) {
+      // per-order sums over n of the cosine (c) and sine (s) terms: values of
+      // the three sets (v), the combined expansion's scaled derivatives (g)
+      // and, for the pressure, the three sets' scaled u and v derivatives
+      // (du, dv); folded with the azimuthal factors at the end of each order
+      double vc[3] = {0.0, 0.0, 0.0}, vs[3] = {0.0, 0.0, 0.0};
+      double guc = 0.0, gus = 0.0, gvc = 0.0, gvs = 0.0, g0c = 0.0, g0s = 0.0;
+      double duc[3] = {0.0, 0.0, 0.0}, dus[3] = {0.0, 0.0, 0.0}, dvc[3] = {0.0, 0.0, 0.0}, dvs[3] = {0.0, 0.0, 0.0};
+      double Pu[3] = {0.0, 0.0, 0.0}, Pv[3] = {0.0, 0.0, 0.0}, Pp[3] = {0.0, 0.0, 0.0};
+      expansion_orders<PMAX>(
+          sp, P.oblate != 0, src.ab, src.cd, rcp, src.qt, &bad, [](int, double, double) {},
+          [&](int lc, int ls, int m, double t0, double tu, double tv) {
+            double e[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) e[k] = Ei[(size_t)k * K + lc];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+              vc[k] = fma(e[k], t0, vc[k]);
+              if constexpr (C == 4) {
+                duc[k] = fma(e[k], tu, duc[k]);
+                dvc[k] = fma(e[k], tv, dvc[k]);
+              }
+            }
+            const double fc = fma(w2, e[2], fma(w1, e[1], fma(w0, e[0], e[3])));
+            guc = fma(fc, tu, guc);
+            gvc = fma(fc, tv, gvc);
+            g0c = fma(fc, t0, g0c);
+            if (m > 0) {
+#pragma unroll
+              for (int k = 0; k < 4; ++k) e[k] = Ei[(size_t)k * K + ls];
+#pragma unroll
+              for (int k = 0; k < 3; ++k) {
+                vs[k] = fma(e[k], t0, vs[k]);
+                if constexpr (C == 4) {
+                  dus[k] = fma(e[k], tu, dus[k]);
+                  dvs[k] = fma(e[k], tv, dvs[k]);
+                }
+              }
+              const double fs = fma(w2, e[2], fma(w1, e[1], fma(w0, e[0], e[3])));
+              gus = fma(fs, tu, gus);
+              gvs = fma(fs, tv, gvs);
+              g0s = fma(fs, t0, g0s);
+            }
+          },
+          [&](int m, double c, double s) {
+            const double dm = (double)m;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+              Phi[k] = fma(c, vc[k], fma(s, vs[k], Phi[k]));
+              if constexpr (C == 4) {
+                Pu[k] = fma(c, duc[k], fma(s, dus[k], Pu[k]));
+                Pv[k] = fma(c, dvc[k], fma(s, dvs[k], Pv[k]));
+                Pp[k] = fma(dm, fma(c, vs[k], -s * vc[k]), Pp[k]);
+                duc[k] = dus[k] = dvc[k] = dvs[k] = 0.0;
+              }
+              vc[k] = vs[k] = 0.0;
+            }
+            Gu = fma(c, guc, fma(s, gus, Gu));
+            Gv = fma(c, gvc, fma(s, gvs, Gv));
+            Gp = fma(dm, fma(c, g0s, -s * g0c), Gp);
+            guc = gus = gvc = gvs = g0c = g0s = 0.0;
+          });
+      const double iw = 1.0 / sp.w, iv = 1.0 / (sp.sv * sp.sv);
+      Gu *= iw;
+      Gv *= iv;
+      if constexpr (C == 4) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) pr -= fma(ga[k], Pp[k], fma(be[k], Pv[k] * iv, al[k] * (Pu[k] * iw)));
+      }
+    } else {
+    expansion_terms<PMAX>(sp, P.oblate != 0, src.L, src.ab, src.cd, rcp, p, &bad,
                           [&](int lc, int ls, int m, double a0, double a1, double a2, double ap, double b0,
                               double b1, double b2, double bp) {
 #pragma unroll
@@ -199,6 +276,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
                               }
                             }
                           });
+    }
 #pragma unroll
     for (int k = 0; k < 3; ++k) acc[k] += 0.5 * (Phi[k] + fma(ga[k], Gp, fma(be[k], Gv, al[k] * Gu)));
     if constexpr (C == 4) acc[3] += pr;
@@ -337,7 +415,9 @@ __global__ void k_stokes_assemble(const double* __restrict__ uself, const double
 template <int PMAX, bool EXACT, int C>
 void launch_near_stokes(sbie_geom* g, hipStream_t s) {
   const int chunks = (g->T + 63) / 64;
-  hipLaunchKernelGGL((k_near_stokes<PMAX, EXACT, C>), dim3(g->M * chunks * kStokesNearSplit), dim3(64), 0, s, g->d_part, g->d_x, g->d_y, g->d_z,
+  constexpr int W = kNearWaves<kUnrollOrders<PMAX, EXACT>>;
+  hipLaunchKernelGGL((k_near_stokes<PMAX, EXACT, C>), dim3(g->M * ((chunks + W - 1) / W) * kStokesNearSplit),
+                     dim3(64 * W), 0, s, g->d_part, g->d_x, g->d_y, g->d_z,
                      g->d_near_ptr, g->d_near_src, g->d_stk_E, g->d_lam, g->d_ab, g->d_cd, g->d_rcp, g->p, g->T,
                      chunks, g->N, g->d_status, g->d_stk_near);
 }

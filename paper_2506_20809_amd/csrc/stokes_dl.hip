@@ -135,25 +135,37 @@ __global__ void k_sdl_self(const Particle* __restrict__ part, const double* __re
   for (int c = 0; c < 3; ++c) out[c * N + g] = o3[c] - 0.5 * dens[c * N + g];
 }
 
-// Near part: one wave per (target particle, 64 target nodes); the derivative
-// recurrences run once for the four double-layer sets and once for the nine
-// single-layer sets of every near source.
+// The orders are unrolled up to p = 12: the thirteen sets' work per (n, m)
+// makes p = 16 too long for the instruction cache.
 template <int PMAX, bool EXACT>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_near_sdl(
+constexpr bool kSdlUnroll = EXACT && PMAX <= 12;
+
+// Near part: one workgroup per (target particle, 64 W target nodes); the
+// derivative recurrences run once for the four double-layer sets and once for
+// the nine single-layer sets of every near source.
+template <int PMAX, bool EXACT>
+__global__ __launch_bounds__((64 * kNearWaves<kSdlUnroll<PMAX, EXACT>>))
+__attribute__((amdgpu_waves_per_eu(3))) void k_near_sdl(
     const Particle* __restrict__ part, const double* __restrict__ x, const double* __restrict__ y,
     const double* __restrict__ z, const int32_t* __restrict__ near_ptr, const int32_t* __restrict__ near_src,
     const double* __restrict__ E, const double* __restrict__ lam, const double* __restrict__ ab,
     const double* __restrict__ cd, const double* __restrict__ rcp, int p_arg, int T, int chunks, int64_t N,
     unsigned* status, double* __restrict__ unear) {
   const int p = EXACT ? PMAX : p_arg;  // exact order: degree bounds known at compile time
-  // one wave per (target particle, 64 targets, range qr of its near-source list)
+  // one workgroup per (target particle, 64 W targets, range qr of its
+  // near-source list)
+  constexpr bool kU = kSdlUnroll<PMAX, EXACT>;
+  constexpr int W = kNearWaves<kU>;
+  const int wgs = (chunks + W - 1) / W;
   const int qr = blockIdx.x % kStokesNearSplit, rest = blockIdx.x / kStokesNearSplit;
-  const int jt = rest / chunks;
-  const int t = (rest - jt * chunks) * 64 + threadIdx.x;
+  const int jt = rest / wgs;
+  const int t = (rest - jt * wgs) * 64 * W + threadIdx.x;
   const bool live = t < T;
   const int64_t g = (int64_t)jt * T + (live ? t : 0);
   const double X0 = x[g], X1 = y[g], X2 = z[g];
   const int K = (p + 1) * (p + 1), Kh = (p + 1) * (p + 2) / 2;
+  __shared__ NearTablesFor<PMAX, kU, kSets> tb;
+  near_tables_init<PMAX, kU, kSets>(tb, ab, cd);
   double acc[3] = {0.0, 0.0, 0.0};
   unsigned bad = 0u;
   const int n0 = near_ptr[jt], nn = near_ptr[jt + 1] - n0;
@@ -162,8 +174,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     const int i = near_src[sidx];
     const Particle P = part[i];
     const SpheroidalPoint q = to_spheroidal(P, X0, X1, X2, true, &bad);
-    const double* Ei = E + (size_t)i * kSets * K;
-    const double* Li = lam + (size_t)i * Kh * 4;
+    const NearSourceView src =
+        near_source<PMAX, kU, kSets>(tb, P.oblate != 0, E + (size_t)i * kSets * K, lam + (size_t)i * Kh * 4, ab, cd, K,
+                                     Kh);
+    const double* Ei = src.E;
     // The decomposition is linear in the thirteen expansions, so it is taken
     // inside the sum over (n, m), one basis evaluation for all of them:
     //  - the double-layer part  grad (D[3] - sum_j d_j D[j])  is the gradient
@@ -176,7 +190,69 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     lab_gradient_coeffs(P, q.u, q.sw, q.v, q.sv, q.c1, q.s1, al, be, ga);
     const double w0 = -q.d[0], w1 = -q.d[1], w2 = -q.d[2];
     double Gu = 0.0, Gv = 0.0, Gp = 0.0, O[3] = {0.0, 0.0, 0.0};
-    expansion_terms<PMAX>(q, P.oblate != 0, Li, ab, cd, rcp, p, &bad,
+    if constexpr (kU) {
+      const double iw = 1.0 / q.w, iv = 1.0 / (q.sv * q.sv);
+      double alw[3], bev[3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        alw[j] = al[j] * iw;
+        bev[j] = be[j] * iv;
+      }
+      // per order, the lab derivative j of the cosine and sine terms of a
+      // (scaled) basis function: x_j tu + y_j tv -+ z_j t0 with the azimuthal
+      // factors and the chain rule's coefficients folded into x, y, z
+      double xc[3], xs[3], yc[3], ys[3], zc[3], zs[3];
+      // per-order sums of the double-layer part's combined expansion
+      double guc = 0.0, gus = 0.0, gvc = 0.0, gvs = 0.0, g0c = 0.0, g0s = 0.0;
+      expansion_orders<PMAX>(
+          q, P.oblate != 0, src.ab, src.cd, rcp, src.qt, &bad,
+          [&](int m, double c, double s) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+              xc[j] = c * alw[j];
+              xs[j] = s * alw[j];
+              yc[j] = c * bev[j];
+              ys[j] = s * bev[j];
+              zc[j] = ((double)m * c) * ga[j];
+              zs[j] = ((double)m * s) * ga[j];
+            }
+          },
+          [&](int lc, int ls, int m, double t0, double tu, double tv) {
+            const double fc = fma(w2, Ei[2 * K + lc], fma(w1, Ei[K + lc], fma(w0, Ei[lc], Ei[3 * K + lc])));
+            guc = fma(fc, tu, guc);
+            gvc = fma(fc, tv, gvc);
+            g0c = fma(fc, t0, g0c);
+            double dc[3];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) dc[j] = fma(xc[j], tu, fma(yc[j], tv, -zs[j] * t0));
+#pragma unroll
+            for (int ii = 0; ii < 3; ++ii)
+#pragma unroll
+              for (int j = 0; j < 3; ++j) O[ii] = fma(-Ei[(size_t)(4 + 3 * ii + j) * K + lc], dc[j], O[ii]);
+            if (m > 0) {
+              const double fs = fma(w2, Ei[2 * K + ls], fma(w1, Ei[K + ls], fma(w0, Ei[ls], Ei[3 * K + ls])));
+              gus = fma(fs, tu, gus);
+              gvs = fma(fs, tv, gvs);
+              g0s = fma(fs, t0, g0s);
+              double ds[3];
+#pragma unroll
+              for (int j = 0; j < 3; ++j) ds[j] = fma(xs[j], tu, fma(ys[j], tv, zc[j] * t0));
+#pragma unroll
+              for (int ii = 0; ii < 3; ++ii)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) O[ii] = fma(-Ei[(size_t)(4 + 3 * ii + j) * K + ls], ds[j], O[ii]);
+            }
+          },
+          [&](int m, double c, double s) {
+            Gu = fma(c, guc, fma(s, gus, Gu));
+            Gv = fma(c, gvc, fma(s, gvs, Gv));
+            Gp = fma((double)m, fma(c, g0s, -s * g0c), Gp);
+            guc = gus = gvc = gvs = g0c = g0s = 0.0;
+          });
+      Gu *= iw;
+      Gv *= iv;
+    } else {
+    expansion_terms<PMAX>(q, P.oblate != 0, src.L, src.ab, src.cd, rcp, p, &bad,
                           [&](int lc, int ls, int m, double, double a1, double a2, double ap, double, double b1,
                               double b2, double bp) {
                             const double fc = fma(w2, Ei[2 * K + lc], fma(w1, Ei[K + lc], fma(w0, Ei[lc], Ei[3 * K + lc])));
@@ -206,6 +282,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
                                   O[ii] = fma(Ei[(size_t)(4 + 3 * ii + j) * K + ls], ns[j], O[ii]);
                             }
                           });
+    }
 #pragma unroll
     for (int ii = 0; ii < 3; ++ii) acc[ii] += fma(ga[ii], Gp, fma(be[ii], Gv, al[ii] * Gu)) + O[ii];
   }
@@ -321,7 +398,9 @@ __global__ void k_sdl_assemble(const double* __restrict__ uself, const double* _
 template <int PMAX, bool EXACT>
 void launch_near_sdl(sbie_geom* g, hipStream_t s) {
   const int chunks = (g->T + 63) / 64;
-  hipLaunchKernelGGL((k_near_sdl<PMAX, EXACT>), dim3(g->M * chunks * kStokesNearSplit), dim3(64), 0, s, g->d_part, g->d_x, g->d_y, g->d_z,
+  constexpr int W = kNearWaves<kSdlUnroll<PMAX, EXACT>>;
+  hipLaunchKernelGGL((k_near_sdl<PMAX, EXACT>), dim3(g->M * ((chunks + W - 1) / W) * kStokesNearSplit),
+                     dim3(64 * W), 0, s, g->d_part, g->d_x, g->d_y, g->d_z,
                      g->d_near_ptr, g->d_near_src, g->d_sdl_E, g->d_lam, g->d_ab, g->d_cd, g->d_rcp, g->p, g->T,
                      chunks, g->N, g->d_status, g->d_sdl_near);
 }

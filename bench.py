@@ -296,9 +296,10 @@ def near_flops(p):
 
 
 def run_near(ctx, steps):
-    """The near field alone (SBIE_PARTS_NEAR): S and D on the 512-spheroid
-    suspension (p = 16), the Stokes single and double layers on the 256-spheroid
-    one (p = 12), FP64 and mixed; evaluations per second and the FP64 vector-unit
+    """The near field alone (SBIE_PARTS_NEAR): S, D, S' and D' on the
+    512-spheroid suspension (p = 16), the Stokes single layer (without and with
+    the pressure) and double layer on the 256-spheroid one (p = 12), FP64 and
+    mixed; evaluations per second and, for S and D, the FP64 vector-unit
     fraction by the flop count of near_flops."""
     import torch
 
@@ -306,15 +307,15 @@ def run_near(ctx, steps):
     import workloads
 
     out = {}
-    for wl, ops in (("c3", (sbie.SBIE_OP_S, sbie.SBIE_OP_D)),
-                    ("c4", (sbie.SBIE_OP_STOKES_S, sbie.SBIE_OP_STOKES_D))):
+    for wl, ops in (("c3", (sbie.SBIE_OP_S, sbie.SBIE_OP_D, sbie.SBIE_OP_SP, sbie.SBIE_OP_DP)),
+                    ("c4", (sbie.SBIE_OP_STOKES_S, sbie.SBIE_OP_STOKES_SP, sbie.SBIE_OP_STOKES_D))):
         geom = workloads.geometry(wl)
         p = workloads.CONFIGS[wl]["p"]
         g = sbie.Geometry(ctx, geom, p)
         gen = torch.Generator(device="cuda")
         gen.manual_seed(7)
         for op in ops:
-            nrhs = 3 if op in (sbie.SBIE_OP_STOKES_S, sbie.SBIE_OP_STOKES_D) else 1
+            nrhs = 3 if op in (sbie.SBIE_OP_STOKES_S, sbie.SBIE_OP_STOKES_SP, sbie.SBIE_OP_STOKES_D) else 1
             d = torch.randn((nrhs, g.N) if nrhs > 1 else (g.N,), dtype=torch.float64, device="cuda", generator=gen)
             for prec, name in ((sbie.SBIE_FP64, "fp64"), (sbie.SBIE_MIXED, "mixed")):
                 for k in range(steps + 1):
@@ -324,7 +325,7 @@ def run_near(ctx, steps):
                 evals = tim.near_evals
                 rate = evals / (tim.near_ms * 1e-3)
                 rec = {"near_ms": tim.near_ms, "evaluations": int(evals), "evaluations_per_s": rate}
-                if nrhs == 1:
+                if op in (sbie.SBIE_OP_S, sbie.SBIE_OP_D):
                     rec["fp64_frac"] = near_flops(p) * rate / 1e12 / PEAK_TFLOPS["fp64"]
                 out[f"{wl}_op{op}_{name}"] = rec
         g.close()

@@ -193,17 +193,24 @@ __global__ void k_scale_coef(const double* __restrict__ coef, const double* __re
 // a degree with p and N = p+1 is then settled at compile time, which keeps the
 // unrolled loops free of runtime predicates (otherwise held, and spilled, as
 // scalar masks).
-template <int PMAX, bool EXACT>
+//
+// With NR > 1 the first nr <= NR densities' expansions (density r's at
+// E + r e_stride) share every basis evaluation, in workgroups of two waves
+// (128 target nodes); density r's partials go to unear + r kNearSplit Nn.
+template <int PMAX, bool EXACT, int NR = 1>
 __device__ __forceinline__ void near_f64_body(
     const Particle* __restrict__ part, const double* __restrict__ x, const double* __restrict__ y,
     const double* __restrict__ z, const int32_t* __restrict__ near_ptr,
     const int32_t* __restrict__ near_src, const double* __restrict__ E,
     const double* __restrict__ lam, const double* __restrict__ ab, const double* __restrict__ rcp, int p_arg,
-    int T, int chunks, int64_t Nn, unsigned* status, double* __restrict__ unear, int bid) {
+    int T, int chunks, int64_t Nn, unsigned* status, double* __restrict__ unear, int bid, int nr = 1,
+    size_t e_stride = 0) {
   const int p = EXACT ? PMAX : p_arg;
+  constexpr int W = NR > 1 ? 2 : 1;
+  const int wgs = (chunks + W - 1) / W;
   const int q4 = bid % kNearSplit, rest = bid / kNearSplit;
-  const int j = rest / chunks;
-  const int t = (rest - j * chunks) * 64 + threadIdx.x;
+  const int j = rest / wgs;
+  const int t = (rest - j * wgs) * 64 * W + threadIdx.x;
   const bool live = t < T;
   const int64_t g = (int64_t)j * T + (live ? t : 0);
   const double X0 = x[g], X1 = y[g], X2 = z[g];
@@ -214,12 +221,14 @@ __device__ __forceinline__ void near_f64_body(
   // The coefficients of the recurrence in n come from their own table.
   constexpr int KM = (PMAX + 1) * (PMAX + 1), KHM = (PMAX + 1) * (PMAX + 2) / 2;
   constexpr int KH2M = (PMAX + 2) * (PMAX + 3) / 2, RM = 2 * PMAX + 8;
-  __shared__ double s_E[KM], s_ab[2 * KH2M], s_rcp[RM], s_qt[4 * KHM];
+  __shared__ double s_E[NR * KM], s_ab[2 * KH2M], s_rcp[RM], s_qt[4 * KHM];
   const int Kh2 = (p + 2) * (p + 3) / 2;
-  for (int k = threadIdx.x; k < 2 * Kh2; k += 64) s_ab[k] = ab[k];
-  for (int k = threadIdx.x; k < RM; k += 64) s_rcp[k] = rcp[k];
-  q_recurrence_table<2>(p, s_qt, threadIdx.x, 64);
-  double acc = 0.0;
+  for (int k = threadIdx.x; k < 2 * Kh2; k += 64 * W) s_ab[k] = ab[k];
+  for (int k = threadIdx.x; k < RM; k += 64 * W) s_rcp[k] = rcp[k];
+  q_recurrence_table<2>(p, s_qt, threadIdx.x, 64 * W);
+  double acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r] = 0.0;
   unsigned bad = 0u;
   const int n0 = near_ptr[j], nn = near_ptr[j + 1] - n0;
   const int s_begin = n0 + (nn * q4) / kNearSplit, s_end = n0 + (nn * (q4 + 1)) / kNearSplit;
@@ -227,11 +236,14 @@ __device__ __forceinline__ void near_f64_body(
     const int i = near_src[s];
     const Particle P = part[i];
     __syncthreads();  // the previous source's tables have been read
-    for (int k = threadIdx.x; k < K; k += 64) {
-      int n = (int)sqrt((double)k);
-      n -= n * n > k ? 1 : 0;
-      const int m = k - n * n - n;
-      s_E[k] = E[(size_t)i * K + k] * lam[((size_t)i * Kh + n * (n + 1) / 2 + (m < 0 ? -m : m)) * 4 + 3];
+    for (int k = threadIdx.x; k < NR * K; k += 64 * W) {
+      const int r = NR == 1 ? 0 : k / K, l = k - r * K;
+      int n = (int)sqrt((double)l);
+      n -= n * n > l ? 1 : 0;
+      const int m = l - n * n - n;
+      s_E[r * KM + l] = r < nr ? E[r * e_stride + (size_t)i * K + l] *
+                                     lam[((size_t)i * Kh + n * (n + 1) / 2 + (m < 0 ? -m : m)) * 4 + 3]
+                               : 0.0;
     }
     __syncthreads();
     const double* Ei = s_E;
@@ -291,7 +303,9 @@ __device__ __forceinline__ void near_f64_body(
       double Q[PMAX + 4];
       q_column_tab<PMAX, 2>(u, N, m, qN, qN1, s_qt + (P.oblate ? 2 * Kh : 0), Q);
       // contraction with the normalised Ferrers functions, forward in n
-      double sc = 0.0, ss = 0.0;
+      double sc[NR], ss[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) sc[r] = ss[r] = 0.0;
       double p2 = 0.0, p1 = pbar;
 #pragma unroll
       for (int n = 0; n <= PMAX; ++n) {
@@ -310,18 +324,28 @@ __device__ __forceinline__ void near_f64_body(
             p1 = pn;
           }
           const double t0 = pn * Q[n];
-          sc = fma(Ei[n * n + n + m], t0, sc);
-          if (m > 0) ss = fma(Ei[n * n + n - m], t0, ss);
+#pragma unroll
+          for (int r = 0; r < NR; ++r) {
+            sc[r] = fma(Ei[r * KM + n * n + n + m], t0, sc[r]);
+            if (m > 0) ss[r] = fma(Ei[r * KM + n * n + n - m], t0, ss[r]);
+          }
         }
       }
-      if (m == 0)
-        acc += sc;
-      else
-        acc += 1.41421356237309504880 * (sc * cm + ss * sm);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        if (m == 0)
+          acc[r] += sc[r];
+        else
+          acc[r] += 1.41421356237309504880 * (sc[r] * cm + ss[r] * sm);
+      }
     });
   }
   if (bad) atomicOr(status, bad);
-  if (live) unear[(size_t)q4 * Nn + g] = acc;
+  if (live) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+      if (r < nr) unear[((size_t)r * kNearSplit + q4) * Nn + g] = acc[r];
+  }
 }
 
 template <int PMAX, bool EXACT>
@@ -333,6 +357,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     int T, int chunks, int64_t Nn, unsigned* status, double* __restrict__ unear) {
   near_f64_body<PMAX, EXACT>(part, x, y, z, near_ptr, near_src, E, lam, ab, rcp, p_arg, T, chunks, Nn, status,
                              unear, (int)blockIdx.x);
+}
+
+// Up to four densities' near fields of one geometry, sharing the basis.
+template <int PMAX, bool EXACT>
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void k_near_f64_multi(
+    const Particle* __restrict__ part, const double* __restrict__ x, const double* __restrict__ y,
+    const double* __restrict__ z, const int32_t* __restrict__ near_ptr,
+    const int32_t* __restrict__ near_src, const double* __restrict__ E, size_t e_stride, int nr,
+    const double* __restrict__ lam, const double* __restrict__ ab, const double* __restrict__ rcp, int p_arg,
+    int T, int chunks, int64_t Nn, unsigned* status, double* __restrict__ unear) {
+  near_f64_body<PMAX, EXACT, 4>(part, x, y, z, near_ptr, near_src, E, lam, ab, rcp, p_arg, T, chunks, Nn, status,
+                                unear, (int)blockIdx.x, nr, e_stride);
 }
 
 // Several geometries' near fields (one order) in one launch: job j owns the
@@ -489,12 +525,14 @@ void launch_near(sbie_geom* g, hipStream_t s) {
                      chunks, g->N, g->d_status, g->d_unear);
 }
 
+// nr densities' near fields: density r's coefficients at E + r M K, its
+// partials at unear + r kNearSplit N
 template <int PMAX, bool EXACT>
-void launch_near_to(sbie_geom* g, const double* E, double* unear, hipStream_t s) {
+void launch_near_multi(sbie_geom* g, const double* E, int nr, double* unear, hipStream_t s) {
   const int chunks = (g->T + 63) / 64;
-  hipLaunchKernelGGL((k_near_f64<PMAX, EXACT>), dim3(g->M * chunks * kNearSplit), dim3(64), 0, s, g->d_part, g->d_x,
-                     g->d_y, g->d_z, g->d_near_ptr, g->d_near_src, E, g->d_lam, g->d_ab, g->d_rcp, g->p, g->T,
-                     chunks, g->N, g->d_status, unear);
+  hipLaunchKernelGGL((k_near_f64_multi<PMAX, EXACT>), dim3(g->M * ((chunks + 1) / 2) * kNearSplit), dim3(128), 0, s,
+                     g->d_part, g->d_x, g->d_y, g->d_z, g->d_near_ptr, g->d_near_src, E, (size_t)g->M * g->K, nr,
+                     g->d_lam, g->d_ab, g->d_rcp, g->p, g->T, chunks, g->N, g->d_status, unear);
 }
 
 }  // namespace
@@ -762,7 +800,7 @@ sbie_status apply_laplace_multi(sbie_geom* g, int op, int prec, int nr, const do
   const int B = 256;
   const bool mixed = prec == SBIE_MIXED;
   const bool near = (parts & SBIE_PARTS_NEAR) && g->n_near > 0;
-  // per density: prep, forward transform, spectra, self part and near field,
+  // per density: prep, forward transform, spectra and self part,
   // the kernels of apply_laplace into the density's own buffers
   for (int k = 0; k < nr; ++k) {
     const double* dk = d_dens + (size_t)k * N;
@@ -787,13 +825,14 @@ sbie_status apply_laplace_multi(sbie_geom* g, int op, int prec, int nr, const do
                  : launch_gemm(g->d_cself, K, g->d_Sy, T, mw.uself + (size_t)k * N, T, M, T, K, s);
       if (st) return st;
     }
-    if (near) {
-      double* uk = mw.unear + (size_t)k * kNearSplit * N;
-      dispatch_order(p, [&](auto pm, auto ex) {
-        launch_near_to<decltype(pm)::value, decltype(ex)::value>(g, Ek, uk, s);
-      });
-      SBIE_HIP(hipGetLastError());
-    }
+  }
+  // the near fields of all densities at once: one basis evaluation per
+  // (near pair, target, n, m) serves every density
+  if (near) {
+    dispatch_order(p, [&](auto pm, auto ex) {
+      launch_near_multi<decltype(pm)::value, decltype(ex)::value>(g, mw.E, nr, mw.unear, s);
+    });
+    SBIE_HIP(hipGetLastError());
   }
   // the far field of all densities at once
   const int nsl = multi_splits(g, multi_row_groups(T, !mixed, op));

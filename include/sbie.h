@@ -184,6 +184,17 @@ sbie_status sbie_apply(sbie_geom* g, sbie_op op, sbie_precision prec, int32_t nr
    applies report their numerical failures here. */
 sbie_status sbie_geom_sync(sbie_geom* g, void* stream);
 
+/* Test control of the error path of Section 2.3's Legendre algorithm: caps
+   the steps of the near-field backward recurrence (the continued fraction for
+   Q_N/Q_{N-1}, evaluated bottom-up) past degree p+1 at `steps`, 8 <= steps <=
+   100000 (the default and the largest cap).  A near-field evaluation that
+   needs more steps runs with the cap and is reported as SBIE_E_NUMERIC by the
+   next sbie_geom_sync (or by a synchronous apply); every kernel completes
+   normally.  Takes effect for the applies and target evaluations issued after
+   it on the geometry's context stream (synchronises that stream).
+   SBIE_E_INVALID for a NULL geometry or a cap outside the range. */
+sbie_status sbie_geom_set_depth_cap(sbie_geom* g, int32_t steps);
+
 /* Forward transform step of Algorithm 1 alone: the (p+1)^2 real
    spheroidal-harmonic coefficients per particle, index n^2+n+m, of the
    density (op = SBIE_OP_D) or of sqrt(u0^2 -+ v^2) times the density

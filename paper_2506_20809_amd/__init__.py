@@ -37,7 +37,7 @@ EXPORTS = [
     "sbie_session_close", "sbie_wait", "sbie_server_get_info", "sbie_status_str", "sbie_last_error",
     "sbie_completion_eta", "sbie_apply_completed", "sbie_solve_completed", "sbie_solve_neumann",
     "sbie_eval_targets", "sbie_geom_far_tree", "sbie_geom_far_tree_info", "sbie_far_tree_plan",
-    "sbie_eval_targets_noalloc",
+    "sbie_eval_targets_noalloc", "sbie_geom_set_depth_cap",
 ]
 SBIE_TARGETS_SCRATCH_BYTES = 64 << 20
 SBIE_COMPLETE_POINT, SBIE_COMPLETE_SINGLE = 0, 1
@@ -124,6 +124,7 @@ def lib() -> ctypes.CDLL:
         L.sbie_geom_near_pairs.argtypes = [vp, ip, ip, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
         L.sbie_apply.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int32, vp, vp, vp, ctypes.c_uint32]
         L.sbie_geom_sync.argtypes = [vp, vp]
+        L.sbie_geom_set_depth_cap.argtypes = [vp, ctypes.c_int32]
         L.sbie_transform.argtypes = [vp, ctypes.c_int, ctypes.c_int32, vp, vp, vp, ctypes.c_uint32]
         L.sbie_geom_spectra.argtypes = [vp, dp]
         L.sbie_geom_timing.argtypes = [vp, ctypes.POINTER(Timing)]
@@ -448,6 +449,11 @@ class Geometry:
         out = np.zeros((self.M, (self.p + 1) * (self.p + 2) // 2, 4))
         _check(lib().sbie_geom_spectra(self._h, _dp(out)))
         return out
+
+    def set_depth_cap(self, steps: int = 100000):
+        """Cap the near-field recurrence at `steps` steps past degree p+1 (a test
+        control: an evaluation needing more is reported as SBIE_E_NUMERIC)."""
+        _check(lib().sbie_geom_set_depth_cap(self._h, int(steps)))
 
     def sync(self, stream=None):
         """Wait for the stream (torch stream or None for the current one) and raise on a

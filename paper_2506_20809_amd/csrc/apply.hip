@@ -226,6 +226,7 @@ __device__ __forceinline__ void near_f64_body(
   for (int k = threadIdx.x; k < 2 * Kh2; k += 64 * W) s_ab[k] = ab[k];
   for (int k = threadIdx.x; k < RM; k += 64 * W) s_rcp[k] = rcp[k];
   q_recurrence_table<2>(p, s_qt, threadIdx.x, 64 * W);
+  const int cap = (int)status[1];  // the geometry's recurrence step cap
   double acc[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) acc[r] = 0.0;
@@ -276,7 +277,7 @@ __device__ __forceinline__ void near_f64_body(
     const double sv = rho / (a * sw);  // sqrt(1 - v^2)
     const double c1 = rho > 0.0 ? b0 / rho : 1.0, s1 = rho > 0.0 ? b1 / rho : 0.0;
     const double sgn = P.oblate ? 1.0 : -1.0;
-    const int L = near_depth(u, sw, N, kStatNumeric, &bad);
+    const int L = near_depth(u, sw, N, cap, kStatNumeric, &bad);
     // Q_N^m, Q_{N+1}^m: orders 0 and 1 from the backward recurrence and the
     // Casoratian, higher orders by the upward recurrence in m
     double qn0[2], qn1[2];

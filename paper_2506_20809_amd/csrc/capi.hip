@@ -377,6 +377,15 @@ sbie_status sbie_apply(sbie_geom* g, sbie_op op, sbie_precision prec, int32_t nr
   return SBIE_OK;
 }
 
+sbie_status sbie_geom_set_depth_cap(sbie_geom* g, int32_t steps) {
+  if (!g) return invalid("geometry is NULL");
+  if (steps < 8 || steps > kMaxNearDepth) return invalid("depth cap outside [8, 100000]");
+  SBIE_HIP(hipSetDevice(g->ctx->device));
+  SBIE_HIP(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(g->d_status + 1), steps, 1, g->ctx->stream));
+  SBIE_HIP(hipStreamSynchronize(g->ctx->stream));
+  return SBIE_OK;
+}
+
 sbie_status sbie_geom_sync(sbie_geom* g, void* stream) {
   if (!g) return invalid("geometry is NULL");
   SBIE_HIP(hipSetDevice(g->ctx->device));

@@ -107,6 +107,7 @@ __global__ __launch_bounds__((64 * kNearWaves<kUnrollOrders<PMAX, EXACT>>)) __at
   near_tables_init<PMAX, kUnrollOrders<PMAX, EXACT>, 1>(tb, ab, cd);
   double acc = 0.0;
   unsigned bad = 0u;
+  const int cap = (int)status[1];  // the geometry's recurrence step cap
   const int l0 = near_ptr[j], nl = near_ptr[j + 1] - l0;
   const int s_begin = l0 + (nl * q4) / kNearSplit, s_end = l0 + (nl * (q4 + 1)) / kNearSplit;
   for (int sidx = s_begin; sidx < s_end; ++sidx) {
@@ -131,7 +132,7 @@ __global__ __launch_bounds__((64 * kNearWaves<kUnrollOrders<PMAX, EXACT>>)) __at
       const double cuw = cu / q.w, cvw = cv / (q.sv * q.sv);
       double a0c = 0.0, a0s = 0.0, auc = 0.0, aus = 0.0, avc = 0.0, avs = 0.0;
       expansion_orders<PMAX>(
-          q, P.oblate != 0, src.ab, src.cd, rcp, src.qt, &bad, [](int, double, double) {},
+          q, P.oblate != 0, src.ab, src.cd, rcp, src.qt, cap, &bad, [](int, double, double) {},
           [&](int lc, int ls, int m, double t0, double tu, double tv) {
             const double ec = Ei[lc];
             a0c = fma(ec, t0, a0c);
@@ -149,7 +150,7 @@ __global__ __launch_bounds__((64 * kNearWaves<kUnrollOrders<PMAX, EXACT>>)) __at
             a0c = a0s = auc = aus = avc = avs = 0.0;
           });
     } else {
-      expansion_terms<PMAX>(q, P.oblate != 0, src.L, src.ab, src.cd, rcp, p, &bad,
+      expansion_terms<PMAX>(q, P.oblate != 0, src.L, src.ab, src.cd, rcp, p, cap, &bad,
                             [&](int lc, int ls, int m, double, double a1, double a2, double ap, double, double b1,
                                 double b2, double bp) {
                               dn = fma(Ei[lc], fma(cp, ap, fma(cv, a2, cu * a1)), dn);

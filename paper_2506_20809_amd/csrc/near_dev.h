@@ -44,16 +44,18 @@ constexpr bool kUnrollOrders = EXACT && PMAX <= 16;
 // Depth L of the backward recurrence: the ratio of the minimal to the
 // dominant solution shrinks by (u + sqrt(w))^-2 per degree; 2^-58 plus a
 // margin, the largest over the wave (wave-uniform), in whole chunks of eight
-// steps; past 1e5 steps the depth is capped and numeric_flag is set in *bad.
-__device__ inline int near_depth(double u, double sw, int N, unsigned numeric_flag, unsigned* bad) {
+// steps; past cap steps (at most kMaxNearDepth) the depth is capped and
+// numeric_flag is set in *bad.
+__device__ inline int near_depth(double u, double sw, int N, int cap, unsigned numeric_flag, unsigned* bad) {
   // clamped in floating point: a point on the focal set (u + sw = 1, only
   // reachable from inside the spheroid) or a NaN gives the capped depth
   const double sd = ceil(20.1 / log(u + sw)) + 8.0;
   int steps = sd < 200000.0 ? (int)sd : 200000;
   for (int off = 32; off >= 1; off >>= 1) steps = max(steps, __shfl_xor(steps, off, 64));
   steps = __builtin_amdgcn_readfirstlane(steps);
-  if (steps > 100000) {
-    steps = 100000;
+  cap = min(cap, kMaxNearDepth);
+  if (steps > cap) {
+    steps = cap;
     *bad |= numeric_flag;
   }
   steps = (steps + 7) & ~7;
@@ -330,19 +332,19 @@ __device__ inline SpheroidalPoint to_spheroidal(const Particle& P, double X0, do
 // m > 0 only) and the basis values of the two: a0 the value, a1 its u, a2 its
 // v and ap its phi derivative (b for the sine term).  L: the particle's
 // spectra rows (column 3 holds 1/Q_n^m(u0)); ab, cd: normalised Ferrers
-// recurrence and derivative coefficients through degree p+1.  Q and Q' come
-// from the division-free backward recurrence (orders 0 and 1, then the order
-// step).
+// recurrence and derivative coefficients through degree p+1; cap: the
+// recurrence's step cap (near_depth).  Q and Q' come from the division-free
+// backward recurrence (orders 0 and 1, then the order step).
 template <int PMAX, typename F>
 __device__ inline void expansion_terms(const SpheroidalPoint& q, bool oblate, const double* __restrict__ L,
                                        const double* __restrict__ ab, const double* __restrict__ cd,
-                                       const double* __restrict__ rcp, int p, unsigned* bad, F&& f) {
+                                       const double* __restrict__ rcp, int p, int cap, unsigned* bad, F&& f) {
   const int N1 = p + 1;
   const double u = q.u, v = q.v;
   const double inv_omv2 = 1.0 / (q.sv * q.sv);
   const double inv_w = 1.0 / q.w;
   const double sgn = oblate ? 1.0 : -1.0;
-  const int Ld = near_depth(u, q.sw, N1, kStatNumeric, bad);
+  const int Ld = near_depth(u, q.sw, N1, cap, kStatNumeric, bad);
   double qn0[2], qn1[2];
   q_top_orders01(u, q.sw, sgn, N1, Ld, rcp, qn0, qn1);
   const double ur = u / q.sw;
@@ -416,12 +418,13 @@ __device__ inline void expansion_terms(const SpheroidalPoint& q, bool oblate, co
 template <int PMAX, typename FB, typename FT, typename FO>
 __device__ inline void expansion_orders(const SpheroidalPoint& q, bool oblate, const double* __restrict__ ab,
                                         const double* __restrict__ cd, const double* __restrict__ rcp,
-                                        const double* __restrict__ qt, unsigned* bad, FB&& order_begin, FT&& term,
+                                        const double* __restrict__ qt, int cap, unsigned* bad, FB&& order_begin,
+                                        FT&& term,
                                         FO&& order_end) {
   constexpr int N1 = PMAX + 1;
   const double u = q.u, v = q.v;
   const double sgn = oblate ? 1.0 : -1.0;
-  const int Ld = near_depth(u, q.sw, N1, kStatNumeric, bad);
+  const int Ld = near_depth(u, q.sw, N1, cap, kStatNumeric, bad);
   double qn0[2], qn1[2];
   q_top_orders01(u, q.sw, sgn, N1, Ld, rcp, qn0, qn1);
   const double ur = u / q.sw;
@@ -477,12 +480,12 @@ template <int PMAX, int NSET>
 __device__ inline void expansion_derivatives(const SpheroidalPoint& q, bool oblate, const double* __restrict__ E,
                                              size_t stride, const double* __restrict__ L,
                                              const double* __restrict__ ab, const double* __restrict__ cd,
-                                             const double* __restrict__ rcp, int p, unsigned* bad,
+                                             const double* __restrict__ rcp, int p, int cap, unsigned* bad,
                                              double (&Phi)[NSET], double (&Pu)[NSET], double (&Pv)[NSET],
                                              double (&Pp)[NSET]) {
 #pragma unroll
   for (int s = 0; s < NSET; ++s) Phi[s] = Pu[s] = Pv[s] = Pp[s] = 0.0;
-  expansion_terms<PMAX>(q, oblate, L, ab, cd, rcp, p, bad,
+  expansion_terms<PMAX>(q, oblate, L, ab, cd, rcp, p, cap, bad,
                         [&](int lc, int ls, int m, double a0, double a1, double a2, double ap, double b0, double b1,
                             double b2, double bp) {
 #pragma unroll

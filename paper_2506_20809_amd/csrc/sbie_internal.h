@@ -87,6 +87,10 @@ inline void dispatch_order(int p, F&& f) {
 // Status word written by kernels (bit flags).
 enum : unsigned { kStatNumeric = 1u, kStatOverlap = 2u, kStatExterior = 4u };
 
+// The largest number of near-field backward-recurrence steps past degree p+1,
+// and each geometry's default cap (sbie_geom_set_depth_cap lowers it).
+constexpr int kMaxNearDepth = 100000;
+
 struct Buf {
   void* p = nullptr;
   size_t bytes = 0;
@@ -224,7 +228,7 @@ struct sbie_geom {
   int32_t *d_near_ptr = nullptr, *d_near_src = nullptr;
   uint32_t* d_excl = nullptr;     // [M][ceil(M/32)] bit i of row j: source i excluded for target j
   int excl_words = 0;
-  unsigned* d_status = nullptr;
+  unsigned* d_status = nullptr;   // [0] sticky status bits, [1] near-field recurrence step cap
 
   // device, work
   double* d_f = nullptr;          // [M][T] transform input

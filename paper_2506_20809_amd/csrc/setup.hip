@@ -376,7 +376,7 @@ sbie_status carve_geometry(sbie_geom* g, Carver& c) {
   // Ferrers recurrence coefficients through degree p+1 (derivatives need Pb_{p+1})
   SBIE_TRY(c.take(&g->d_ab, (size_t)Kh2 * 2));
   SBIE_TRY(c.take(&g->d_cd, (size_t)Kh));
-  SBIE_TRY(c.take(&g->d_status, 1));
+  SBIE_TRY(c.take(&g->d_status, 2));
   SBIE_TRY(c.take(&g->d_near_scratch, (size_t)M * M));
   SBIE_TRY(c.take(&g->d_near_ptr, M + 1));
   // near sources: at most M(M-1) directed pairs
@@ -515,6 +515,7 @@ sbie_status setup_geometry(sbie_geom* g, hipStream_t s) {
   SBIE_HIP(hipMemcpyAsync(g->d_gl, gl.data(), sizeof(double) * gl.size(), hipMemcpyHostToDevice, s));
   SBIE_HIP(hipMemcpyAsync(g->d_ab, ab.data(), sizeof(double) * ab.size(), hipMemcpyHostToDevice, s));
   SBIE_HIP(hipMemsetAsync(g->d_status, 0, sizeof(unsigned), s));
+  SBIE_HIP(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(g->d_status + 1), kMaxNearDepth, 1, s));
 
   const int B = 256;
   hipLaunchKernelGGL(k_nodes, dim3((unsigned)((N + B - 1) / B)), dim3(B), 0, s, g->d_part, g->d_gl, p, N,

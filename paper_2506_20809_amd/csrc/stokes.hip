@@ -157,6 +157,7 @@ __global__ __launch_bounds__((64 * kNearWaves<kUnrollOrders<PMAX, EXACT>>)) __at
 #pragma unroll
   for (int c = 0; c < C; ++c) acc[c] = 0.0;
   unsigned bad = 0u;
+  const int cap = (int)status[1];  // the geometry's recurrence step cap
   const int n0 = near_ptr[j], nn = near_ptr[j + 1] - n0;
   const int s_begin = n0 + (nn * q) / kStokesNearSplit, s_end = n0 + (nn * (q + 1)) / kStokesNearSplit;
   for (int sidx = s_begin; sidx < s_end; ++sidx) {
@@ -187,7 +188,7 @@ __global__ __launch_bounds__((64 * kNearWaves<kUnrollOrders<PMAX, EXACT>>)) __at
       double duc[3] = {0.0, 0.0, 0.0}, dus[3] = {0.0, 0.0, 0.0}, dvc[3] = {0.0, 0.0, 0.0}, dvs[3] = {0.0, 0.0, 0.0};
       double Pu[3] = {0.0, 0.0, 0.0}, Pv[3] = {0.0, 0.0, 0.0}, Pp[3] = {0.0, 0.0, 0.0};
       expansion_orders<PMAX>(
-          sp, P.oblate != 0, src.ab, src.cd, rcp, src.qt, &bad, [](int, double, double) {},
+          sp, P.oblate != 0, src.ab, src.cd, rcp, src.qt, cap, &bad, [](int, double, double) {},
           [&](int lc, int ls, int m, double t0, double tu, double tv) {
             double e[4];
 #pragma unroll
@@ -247,7 +248,7 @@ __global__ __launch_bounds__((64 * kNearWaves<kUnrollOrders<PMAX, EXACT>>)) __at
         for (int k = 0; k < 3; ++k) pr -= fma(ga[k], Pp[k], fma(be[k], Pv[k] * iv, al[k] * (Pu[k] * iw)));
       }
     } else {
-    expansion_terms<PMAX>(sp, P.oblate != 0, src.L, src.ab, src.cd, rcp, p, &bad,
+    expansion_terms<PMAX>(sp, P.oblate != 0, src.L, src.ab, src.cd, rcp, p, cap, &bad,
                           [&](int lc, int ls, int m, double a0, double a1, double a2, double ap, double b0,
                               double b1, double b2, double bp) {
 #pragma unroll

@@ -168,6 +168,7 @@ __attribute__((amdgpu_waves_per_eu(3))) void k_near_sdl(
   near_tables_init<PMAX, kU, kSets>(tb, ab, cd);
   double acc[3] = {0.0, 0.0, 0.0};
   unsigned bad = 0u;
+  const int cap = (int)status[1];  // the geometry's recurrence step cap
   const int n0 = near_ptr[jt], nn = near_ptr[jt + 1] - n0;
   const int s_begin = n0 + (nn * qr) / kStokesNearSplit, s_end = n0 + (nn * (qr + 1)) / kStokesNearSplit;
   for (int sidx = s_begin; sidx < s_end; ++sidx) {
@@ -205,7 +206,7 @@ __attribute__((amdgpu_waves_per_eu(3))) void k_near_sdl(
       // per-order sums of the double-layer part's combined expansion
       double guc = 0.0, gus = 0.0, gvc = 0.0, gvs = 0.0, g0c = 0.0, g0s = 0.0;
       expansion_orders<PMAX>(
-          q, P.oblate != 0, src.ab, src.cd, rcp, src.qt, &bad,
+          q, P.oblate != 0, src.ab, src.cd, rcp, src.qt, cap, &bad,
           [&](int m, double c, double s) {
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
@@ -252,7 +253,7 @@ __attribute__((amdgpu_waves_per_eu(3))) void k_near_sdl(
       Gu *= iw;
       Gv *= iv;
     } else {
-    expansion_terms<PMAX>(q, P.oblate != 0, src.L, src.ab, src.cd, rcp, p, &bad,
+    expansion_terms<PMAX>(q, P.oblate != 0, src.L, src.ab, src.cd, rcp, p, cap, &bad,
                           [&](int lc, int ls, int m, double, double a1, double a2, double ap, double, double b1,
                               double b2, double bp) {
                             const double fc = fma(w2, Ei[2 * K + lc], fma(w1, Ei[K + lc], fma(w0, Ei[lc], Ei[3 * K + lc])));

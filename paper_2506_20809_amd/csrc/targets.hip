@@ -115,6 +115,7 @@ __global__ __launch_bounds__(64) void k_near_targets(
   const int K = (p + 1) * (p + 1), Kh = (p + 1) * (p + 2) / 2;
   double v = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
   unsigned bad = 0u;
+  const int cap = (int)status[1];  // the geometry's recurrence step cap
   for (int w = 0; w < words; ++w) {
     const uint32_t mine = live ? mask[(size_t)tt * words + w] : 0u;
     uint32_t all = mine;
@@ -134,7 +135,7 @@ __global__ __launch_bounds__(64) void k_near_targets(
       const SpheroidalPoint q = to_spheroidal(P, px, py, pz, true, &lb);
       double Phi[1], Pu[1], Pv[1], Pp[1];
       expansion_derivatives<PMAX, 1>(q, P.oblate != 0, E + (size_t)i * K, (size_t)K, lam + (size_t)i * Kh * 4, ab,
-                                     cd, rcp, p, &lb, Phi, Pu, Pv, Pp);
+                                     cd, rcp, p, cap, &lb, Phi, Pu, Pv, Pp);
       double gr[3];
       lab_gradient(P, q.u, q.sw, q.v, q.sv, q.c1, q.s1, Pu[0], Pv[0], Pp[0], gr);
       if (use) {

@@ -37,7 +37,7 @@
 namespace {
 
 struct Op {
-  enum Kind { kCopy, kSet, kEvent } kind;
+  enum Kind { kCopy, kSet, kSet32, kEvent } kind;
   void* dst = nullptr;
   const void* src = nullptr;
   size_t n = 0;
@@ -85,6 +85,9 @@ void run(const Op& op) {
   switch (op.kind) {
     case Op::kCopy: std::memcpy(op.dst, op.src, op.n); break;
     case Op::kSet: std::memset(op.dst, op.value, op.n); break;
+    case Op::kSet32:
+      for (size_t k = 0; k < op.n; ++k) std::memcpy(static_cast<char*>(op.dst) + 4 * k, &op.value, 4);
+      break;
     case Op::kEvent: break;
   }
 }
@@ -208,6 +211,21 @@ hipError_t hipMemsetAsync(void* dst, int value, size_t n, hipStream_t st) {
   op.dst = dst;
   op.value = value;
   op.n = n;
+  return enqueue(st, op);
+}
+
+hipError_t hipMemsetD32Async(hipDeviceptr_t dst, int value, size_t count, hipStream_t st) {
+  {
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    if (real(st)->capturing) {
+      g_capture_memsets.fetch_add(1);
+      return hipErrorStreamCaptureUnsupported;
+    }
+  }
+  Op op{Op::kSet32};
+  op.dst = dst;
+  op.value = value;
+  op.n = count;
   return enqueue(st, op);
 }
 

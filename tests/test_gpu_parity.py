@@ -436,3 +436,45 @@ def test_near_pair_sets_exact(ctx, name, p):
     assert got == ref, (len(got), len(ref), sorted(got ^ ref)[:10])
     assert g.num_near_pairs == len(ref)
     g.close()
+
+
+@pytest.mark.parametrize("p", [8, 10])
+def test_numeric_error_forced_by_depth_cap(ctx, p):
+    """The error path of Section 2.3's Legendre algorithm on the device: with the
+    near-field recurrence capped at 8 steps past degree p+1
+    (sbie_geom_set_depth_cap) every near evaluation needs more, and S, D, S', the
+    Stokes single and double layers and the target evaluation report
+    SBIE_E_NUMERIC; all kernels complete.  With the default cap restored the
+    applies equal the uncapped ones bitwise.  p = 8 runs the kernels with the
+    orders unrolled, p = 10 those with the orders as a run-time loop."""
+    import paper_2506_20809_amd as sbie
+
+    geom = workloads.geometry("c1")
+    g = sbie.Geometry(ctx, geom, p)
+    assert g.num_near_pairs > 0
+    rng = np.random.default_rng(5)
+    one, three = rng.standard_normal(g.N), rng.standard_normal((3, g.N))
+    ops = [(sbie.SBIE_OP_S, one), (sbie.SBIE_OP_D, one), (sbie.SBIE_OP_SP, one),
+           (sbie.SBIE_OP_STOKES_S, three), (sbie.SBIE_OP_STOKES_D, three)]
+    ref = [g.apply(op, d) for op, d in ops]
+    x, nrm, _ = g.nodes()
+    pts = x[:5] + 0.02 * nrm[:5]  # just outside particle 0: near it
+    rv, rg = g.eval_targets(sbie.SBIE_OP_S, one, pts)
+    g.set_depth_cap(8)
+    for op, d in ops:
+        with pytest.raises(sbie.SbieError) as e:
+            g.apply(op, d)
+        assert e.value.status == -8, op
+    with pytest.raises(sbie.SbieError) as e:
+        g.eval_targets(sbie.SBIE_OP_S, one, pts)
+    assert e.value.status == -8
+    for bad in (7, 100001):
+        with pytest.raises(sbie.SbieError) as e:
+            g.set_depth_cap(bad)
+        assert e.value.status == -1
+    g.set_depth_cap()
+    for (op, d), r in zip(ops, ref):
+        assert np.array_equal(g.apply(op, d), r), op
+    v2, g2 = g.eval_targets(sbie.SBIE_OP_S, one, pts)
+    assert np.array_equal(v2, rv) and np.array_equal(g2, rg)
+    g.close()

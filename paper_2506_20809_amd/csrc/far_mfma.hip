@@ -80,14 +80,16 @@ struct FarLayout {
 };
 
 constexpr int kChunk = 40;  // 16-source blocks staged in LDS at a time
-// Workgroup shape of the pair kernel: up to WMAX waves (three resp. two per
-// SIMD, which the registers allow), each holding up to RBMAX blocks of 16
-// target rows; a particle's rows are split into groups of WMAX*RBMAX blocks,
-// spread evenly over the waves so that every SIMD carries the same work.
+// Workgroup shape of the pair kernel: up to WMAX waves (three per SIMD, which
+// the registers allow), each holding up to RBMAX blocks of 16 target rows; a
+// particle's rows are split into groups of WMAX*RBMAX blocks, spread evenly
+// over the waves so that every SIMD carries the same work.  (FP64 at eight
+// waves of five blocks, two per SIMD, took 7% (S) and 5% (D) longer; at
+// sixteen waves of three, four per SIMD with a few spilled registers, 7%.)
 template <typename R>
 struct PairShape {
-  static constexpr int WMAX = sizeof(R) == 4 ? 12 : 8;
-  static constexpr int RBMAX = sizeof(R) == 4 ? 4 : 5;
+  static constexpr int WMAX = 12;
+  static constexpr int RBMAX = 4;
   static constexpr int GB = WMAX * RBMAX;  // row blocks per group
   // row blocks whose matrix-core products are issued together
   static constexpr int batch(bool) { return 4; }

@@ -11,15 +11,17 @@
 // in order) into rev[b][slot][rg][c][t] and folded slot by slot.  The pressure
 // kernel is odd in d: its reverse term changes sign.
 //
-// The matrix cores take every contraction over a K = 4 operand pair, 256
-// node pairs per product, with D = x - c_b and o = y - c_b:
+// The matrix cores take the contractions over a K = 4 operand pair, 256 node
+// pairs per product, with D = x - c_b and o = y - c_b:
 //     |d|^2   = [D |D|^2] . [-2o 1] + |o|^2
 //     d.q_b   = [D 1] . [q_b  -q_b.o]
 //     d.q_a   = [q_a/2  q_a.D] . [-2o 1]
-//     d_i     = [D 1] . [e_i  -o_i]              (e_i the i-th unit vector)
-// so the vector units take 1/r, 1/r^3 and the six multiply-adds of the two
-// directions' velocity terms.  Rows of a (and sources of b) are padded to 16
-// with zero-strength points at the particle's centre.
+// and the vector units the components d_i = D_i - o_i (one add per node pair
+// and component, cheaper on this chip than a product per component: a
+// 16x16x4 product costs about as much as twelve vector instructions of the
+// wave), 1/r, 1/r^3 and the multiply-adds of the two directions' velocity
+// terms.  Rows of a (and sources of b) are padded to 16 with zero-strength
+// points at the particle's centre.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -171,13 +173,6 @@ __global__ __launch_bounds__(64 * kSWaves) void k_far_stokes_pairs(
     }
   }
 
-  // [e_i  -o_i] from the staged [-2o 1] operand: lane group i takes 1, group 3
-  // half the staged value, the others 0
-  const R half3 = lg == 3 ? R(0.5) : R(0);
-  R one_i[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) one_i[i] = lg == i ? R(1) : R(0);
-
   // forward sums over the admitted partners: FP32 per partner, folded into
   // FP64 (the per-partner sums over the 16 columns packed two arrays of 16
   // per lane); FP64 directly, columns summed at the end
@@ -214,6 +209,15 @@ __global__ __launch_bounds__(64 * kSWaves) void k_far_stokes_pairs(
       a1[rb] = lg < 3 ? (R)dl : R(1);
       a3[rb] = lg < 3 ? R(0.5) * qA[rb] : (R)qd;
     }
+    // D_i of this lane's accumulator rows, from the lanes holding them in the
+    // A operand (row r, component i at lane r + 16 i)
+    R Dv[RB][4][3];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) Dv[rb][e][i] = lane_value(a1[rb], (SS::row(lg, e) + 16 * i) << 2);
     // this partner's forward tiles (FP32); FP64 adds into accD directly
     R tf[F32 ? RB : 1][4][C];
 #pragma unroll
@@ -244,22 +248,20 @@ __global__ __launch_bounds__(64 * kSWaves) void k_far_stokes_pairs(
           const R* L = lds_rec + ib * kSGeo;
           const R bgeo = L[lane], bq = L[80 + lane];
           const R o2 = L[64 + li];
-          // [e_i  -o_i] for column li (-o_i is half of the [-2o 1] operand), q_b of column li
-          R bu[3], qb[3];
+          // -o_i (half of the [-2o 1] operand) and q_b of column li
+          R mo[3], qb[3];
 #pragma unroll
           for (int i = 0; i < 3; ++i) {
-            bu[i] = fma(half3, L[16 * i + li], one_i[i]);
+            mo[i] = R(0.5) * L[16 * i + li];
             qb[i] = L[80 + 16 * i + li];
           }
           const V zero = {R(0), R(0), R(0), R(0)};
-          V r2[RB], df[RB], dr[RB], dd[RB][3];
+          V r2[RB], df[RB], dr[RB];
 #pragma unroll
           for (int rb = 0; rb < RB; ++rb) {
             r2[rb] = SS::mma(aop[rb], bgeo, V{o2, o2, o2, o2});
             if (NF) df[rb] = SS::mma(a1[rb], bq, zero);
             dr[rb] = SS::mma(a3[rb], bgeo, zero);
-#pragma unroll
-            for (int i = 0; i < 3; ++i) dd[rb][i] = SS::mma(a1[rb], bu[i], zero);
           }
           R rv[C];
 #pragma unroll
@@ -271,15 +273,18 @@ __global__ __launch_bounds__(64 * kSWaves) void k_far_stokes_pairs(
               // q_i/r + (d.q) d_i/r^3 = (q_i + ((d.q)/r^2) d_i) / r
               const R ri = SS::rsq(r2[rb][e]);
               const R ri2 = ri * ri;
+              R dd[3];
+#pragma unroll
+              for (int i = 0; i < 3; ++i) dd[i] = Dv[rb][e][i] + mo[i];
               if (NF) {
                 const R ff = df[rb][e] * ri2;
 #pragma unroll
-                for (int i = 0; i < 3; ++i) fref(rb, e, i) = fma(ri, fma(ff, dd[rb][i][e], qb[i]), fref(rb, e, i));
+                for (int i = 0; i < 3; ++i) fref(rb, e, i) = fma(ri, fma(ff, dd[i], qb[i]), fref(rb, e, i));
                 if constexpr (C == 4) fref(rb, e, 3) = fma(ff, ri, fref(rb, e, 3));
               }
               const R fr = dr[rb][e] * ri2;
 #pragma unroll
-              for (int i = 0; i < 3; ++i) rv[i] = fma(ri, fma(fr, dd[rb][i][e], qacc[rb][e][i]), rv[i]);
+              for (int i = 0; i < 3; ++i) rv[i] = fma(ri, fma(fr, dd[i], qacc[rb][e][i]), rv[i]);
               if constexpr (C == 4) rv[3] = fma(-fr, ri, rv[3]);  // the pressure kernel is odd in d
             }
           // the four lane groups holding the same column

@@ -22,6 +22,13 @@
 // wave), 1/r, 1/r^3 and the multiply-adds of the two directions' velocity
 // terms.  Rows of a (and sources of b) are padded to 16 with zero-strength
 // points at the particle's centre.
+//
+// The same kernel (SDL) takes the far field of the Stokes double layer
+// (Section 4.3): the stresslet (3/4pi)(d.m)(d.nu) d/r^5 with m = W mu, which is
+// odd in d, so its reverse term changes sign.  Its products per tile are |d|^2
+// and the four dots d.m_b = [D 1].[m_b -m_b.o], d.nu_b likewise, and
+// d.m_a = [m_a/2 m_a.D].[-2o 1], d.nu_a likewise; the vector units take d_i,
+// 1/r^5 and the weights.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -35,12 +42,15 @@ namespace {
 
 constexpr double kInv8PiS = 0.039788735772973833942220940843128591;
 constexpr double kInv4PiS = 0.079577471545947667884441881686257181;
+constexpr double k3Over4PiS = 0.23873241463784300365332564505877154;
 
 using d4s = double __attribute__((ext_vector_type(4)));
 
 // values per 16-source block: [-2o 1] B operand (64, lane order), |o|^2 per
 // column (16), [q  -q.o] B operand (64), 16 unused
 constexpr int kSGeo = 160;
+// the stresslet's: [-2o 1] (64), |o|^2 (16), [m  -m.o] (64), [nu  -nu.o] (64)
+constexpr int kSDGeo = 208;
 constexpr int kSWaves = 12;  // most waves per workgroup (three per SIMD), each holding up to RB row blocks
 
 template <typename R>
@@ -109,23 +119,61 @@ __global__ void k_stokes_pair_records(const Particle* __restrict__ part, const d
   }
 }
 
+// The stresslet's source blocks: m = W mu from the density [3][N] and the
+// normals (one thread per lane of a block).
+template <typename R>
+__global__ void k_sdl_pair_records(const Particle* __restrict__ part, const double* __restrict__ dens,
+                                   const double* __restrict__ x, const double* __restrict__ y,
+                                   const double* __restrict__ z, const double* __restrict__ w,
+                                   const double* __restrict__ nx, const double* __restrict__ ny,
+                                   const double* __restrict__ nz, int M, int T, int nb, int64_t N,
+                                   R* __restrict__ rec) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)M * nb * 64) return;
+  const int lane = (int)(i & 63);
+  const int64_t blk = i >> 6;
+  const int b = (int)(blk / nb), ib = (int)(blk - (int64_t)b * nb);
+  const int lg = lane >> 4, li = lane & 15, r = ib * 16 + li;
+  double o[3] = {0.0, 0.0, 0.0}, m[3] = {0.0, 0.0, 0.0}, nu[3] = {0.0, 0.0, 0.0};
+  if (r < T) {
+    const int64_t g = (int64_t)b * T + r;
+    o[0] = x[g] - part[b].c[0];
+    o[1] = y[g] - part[b].c[1];
+    o[2] = z[g] - part[b].c[2];
+    const double wq = w[g];
+    for (int k = 0; k < 3; ++k) m[k] = wq * dens[(int64_t)k * N + g];
+    nu[0] = nx[g];
+    nu[1] = ny[g];
+    nu[2] = nz[g];
+  }
+  R* out = rec + blk * kSDGeo;
+  out[lane] = lg < 3 ? (R)(-2.0 * o[lg]) : R(1);
+  out[80 + lane] = lg < 3 ? (R)m[lg] : (R)(-(m[0] * o[0] + m[1] * o[1] + m[2] * o[2]));
+  out[144 + lane] = lg < 3 ? (R)nu[lg] : (R)(-(nu[0] * o[0] + nu[1] * o[1] + nu[2] * o[2]));
+  if (lg == 0) out[64 + li] = (R)(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]);
+}
+
 // The pair kernel.  Work index (XCD-ordered) -> (particle a, row group rg,
 // split of a's partner offsets); a row group is a balanced share of a's 16-row
 // blocks, spread over the waves as whole blocks (at most RB per wave).  One
 // launch covers the partner offsets [kbase, kend); its forward sums are added
 // to the split's slice [split][C][N] (first launch: written), its reverse
 // sums go to rev[b][k - kbase][rg][c][t] (a dropped direction writes zeros).
-template <typename R, int C>
+// With SDL the stresslet (C = 3; nx, ny, nz the normals) instead of the
+// Stokeslet (C = 3, or 4 with the pressure; no normals).
+template <typename R, int C, bool SDL>
 __global__ __launch_bounds__(64 * kSWaves) void k_far_stokes_pairs(
     const R* __restrict__ rec, const Particle* __restrict__ part, const double* __restrict__ x,
     const double* __restrict__ y, const double* __restrict__ z, const double* __restrict__ dens,
-    const double* __restrict__ w, const uint32_t* __restrict__ excl, int words, int M, int T, int64_t N, int nsplit,
-    int RG, int kbase, int kend, int first, double* __restrict__ fwd, R* __restrict__ rev) {
+    const double* __restrict__ w, const double* __restrict__ nx, const double* __restrict__ ny,
+    const double* __restrict__ nz, const uint32_t* __restrict__ excl, int words, int M, int T, int64_t N,
+    int nsplit, int RG, int kbase, int kend, int first, double* __restrict__ fwd, R* __restrict__ rev) {
   using SS = StokesShape<R>;
   using V = typename SS::V;
   constexpr int RB = SS::RB, CH = SS::CHUNK;
   constexpr bool F32 = sizeof(R) == 4;
-  __shared__ R lds_rec[CH * kSGeo];
+  constexpr int GEO = SDL ? kSDGeo : kSGeo;
+  __shared__ R lds_rec[CH * GEO];
   __shared__ R lds_rev[kSWaves * C * CH * 16];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -153,7 +201,9 @@ __global__ __launch_bounds__(64 * kSWaves) void k_far_stokes_pairs(
   const int cl = lg < 3 ? lg : 0;
   const double* xyz = cl == 0 ? x : (cl == 1 ? y : z);
   double tcl[RB];
-  R qA[RB], qacc[RB][4][3];
+  // row li's strength component lg (Stokeslet q, stresslet m) and, for the
+  // stresslet, its normal's; the Stokeslet's accumulator rows' strengths
+  R qA[RB], nA[SDL ? RB : 1], qacc[SDL ? 1 : RB][4][3];
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) {
     const int bk = rb0 + rb;
@@ -162,14 +212,19 @@ __global__ __launch_bounds__(64 * kSWaves) void k_far_stokes_pairs(
     const int64_t ga = (int64_t)a * T + (la ? ra : 0);
     tcl[rb] = la ? xyz[ga] : Pa.c[cl];
     qA[rb] = (la && lg < 3) ? (R)(w[ga] * dens[(int64_t)lg * N + ga]) : R(0);
+    if constexpr (SDL) {
+      const double* nxyz = cl == 0 ? nx : (cl == 1 ? ny : nz);
+      nA[rb] = (la && lg < 3) ? (R)nxyz[ga] : R(0);
+    } else {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int r = bk * 16 + SS::row(lg, e);
-      const bool lr = rb < nown && r < T;
-      const int64_t g = (int64_t)a * T + (lr ? r : 0);
-      const double wq = lr ? w[g] : 0.0;
+      for (int e = 0; e < 4; ++e) {
+        const int r = bk * 16 + SS::row(lg, e);
+        const bool lr = rb < nown && r < T;
+        const int64_t g = (int64_t)a * T + (lr ? r : 0);
+        const double wq = lr ? w[g] : 0.0;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) qacc[rb][e][k] = (R)(wq * dens[(int64_t)k * N + g]);
+        for (int k = 0; k < 3; ++k) qacc[rb][e][k] = (R)(wq * dens[(int64_t)k * N + g]);
+      }
     }
   }
 
@@ -195,7 +250,9 @@ __global__ __launch_bounds__(64 * kSWaves) void k_far_stokes_pairs(
       continue;
     }
     const double cb = part[b].c[cl];
-    R aop[RB], a1[RB], a3[RB];
+    // A operands: [D |D|^2], [D 1], [q_a/2  q_a.D] (stresslet: m_a) and, for
+    // the stresslet, [nu_a/2  nu_a.D]
+    R aop[RB], a1[RB], a3[RB], a4[SDL ? RB : 1];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
       const double dl = lg < 3 ? tcl[rb] - cb : 0.0;
@@ -208,6 +265,12 @@ __global__ __launch_bounds__(64 * kSWaves) void k_far_stokes_pairs(
       aop[rb] = (R)(lg < 3 ? dl : d2);
       a1[rb] = lg < 3 ? (R)dl : R(1);
       a3[rb] = lg < 3 ? R(0.5) * qA[rb] : (R)qd;
+      if constexpr (SDL) {
+        double nd = lg < 3 ? (double)nA[rb] * dl : 0.0;
+        nd += lane_value(nd, x16);
+        nd += lane_value(nd, x32);
+        a4[rb] = lg < 3 ? R(0.5) * nA[rb] : (R)nd;
+      }
     }
     // D_i of this lane's accumulator rows, from the lanes holding them in the
     // A operand (row r, component i at lane r + 16 i)
@@ -240,12 +303,12 @@ __global__ __launch_bounds__(64 * kSWaves) void k_far_stokes_pairs(
         const int nbc = nb - c0 < CH ? nb - c0 : CH;
         __syncthreads();  // the previous chunk's operands and reverse sums are consumed
         {
-          const R* gsrc = rec + ((size_t)b * nb + c0) * kSGeo;
-          for (int i = tid; i < nbc * kSGeo; i += blockDim.x) lds_rec[i] = gsrc[i];
+          const R* gsrc = rec + ((size_t)b * nb + c0) * GEO;
+          for (int i = tid; i < nbc * GEO; i += blockDim.x) lds_rec[i] = gsrc[i];
         }
         __syncthreads();
         for (int ib = 0; ib < nbc; ++ib) {
-          const R* L = lds_rec + ib * kSGeo;
+          const R* L = lds_rec + ib * GEO;
           const R bgeo = L[lane], bq = L[80 + lane];
           const R o2 = L[64 + li];
           // -o_i (half of the [-2o 1] operand) and q_b of column li
@@ -253,15 +316,19 @@ __global__ __launch_bounds__(64 * kSWaves) void k_far_stokes_pairs(
 #pragma unroll
           for (int i = 0; i < 3; ++i) {
             mo[i] = R(0.5) * L[16 * i + li];
-            qb[i] = L[80 + 16 * i + li];
+            qb[i] = SDL ? R(0) : L[80 + 16 * i + li];
           }
           const V zero = {R(0), R(0), R(0), R(0)};
-          V r2[RB], df[RB], dr[RB];
+          V r2[RB], df[RB], dr[RB], dfn[SDL ? RB : 1], drn[SDL ? RB : 1];
 #pragma unroll
           for (int rb = 0; rb < RB; ++rb) {
             r2[rb] = SS::mma(aop[rb], bgeo, V{o2, o2, o2, o2});
             if (NF) df[rb] = SS::mma(a1[rb], bq, zero);
             dr[rb] = SS::mma(a3[rb], bgeo, zero);
+            if constexpr (SDL) {
+              if (NF) dfn[rb] = SS::mma(a1[rb], L[144 + lane], zero);
+              drn[rb] = SS::mma(a4[rb], bgeo, zero);
+            }
           }
           R rv[C];
 #pragma unroll
@@ -276,16 +343,29 @@ __global__ __launch_bounds__(64 * kSWaves) void k_far_stokes_pairs(
               R dd[3];
 #pragma unroll
               for (int i = 0; i < 3; ++i) dd[i] = Dv[rb][e][i] + mo[i];
-              if (NF) {
-                const R ff = df[rb][e] * ri2;
+              if constexpr (SDL) {
+                // (d.m)(d.nu) d / r^5 forward; reversed, d changes sign
+                const R ri5 = ri * ri2 * ri2;
+                if (NF) {
+                  const R wf = df[rb][e] * dfn[rb][e] * ri5;
 #pragma unroll
-                for (int i = 0; i < 3; ++i) fref(rb, e, i) = fma(ri, fma(ff, dd[i], qb[i]), fref(rb, e, i));
-                if constexpr (C == 4) fref(rb, e, 3) = fma(ff, ri, fref(rb, e, 3));
+                  for (int i = 0; i < 3; ++i) fref(rb, e, i) = fma(wf, dd[i], fref(rb, e, i));
+                }
+                const R wr = dr[rb][e] * drn[rb][e] * ri5;
+#pragma unroll
+                for (int i = 0; i < 3; ++i) rv[i] = fma(-wr, dd[i], rv[i]);
+              } else {
+                if (NF) {
+                  const R ff = df[rb][e] * ri2;
+#pragma unroll
+                  for (int i = 0; i < 3; ++i) fref(rb, e, i) = fma(ri, fma(ff, dd[i], qb[i]), fref(rb, e, i));
+                  if constexpr (C == 4) fref(rb, e, 3) = fma(ff, ri, fref(rb, e, 3));
+                }
+                const R fr = dr[rb][e] * ri2;
+#pragma unroll
+                for (int i = 0; i < 3; ++i) rv[i] = fma(ri, fma(fr, dd[i], qacc[rb][e][i]), rv[i]);
+                if constexpr (C == 4) rv[3] = fma(-fr, ri, rv[3]);  // the pressure kernel is odd in d
               }
-              const R fr = dr[rb][e] * ri2;
-#pragma unroll
-              for (int i = 0; i < 3; ++i) rv[i] = fma(ri, fma(fr, dd[i], qacc[rb][e][i]), rv[i]);
-              if constexpr (C == 4) rv[3] = fma(-fr, ri, rv[3]);  // the pressure kernel is odd in d
             }
           // the four lane groups holding the same column
 #pragma unroll
@@ -334,7 +414,7 @@ __global__ __launch_bounds__(64 * kSWaves) void k_far_stokes_pairs(
     const int r = (rb0 + rb) * 16 + SS::row(lg, e);
     if (r >= T) return;
     double* f = fwd + ((size_t)split * C + c) * N + (int64_t)a * T + r;
-    *f = (first ? 0.0 : *f) + v * (c < 3 ? kInv8PiS : kInv4PiS);
+    *f = (first ? 0.0 : *f) + v * (SDL ? k3Over4PiS : (c < 3 ? kInv8PiS : kInv4PiS));
   };
   if constexpr (F32) {
 #pragma unroll
@@ -377,27 +457,37 @@ __global__ void k_far_stokes_fold(const R* __restrict__ rev, int M, int T, int R
   }
 }
 
-template <typename R, int C>
-sbie_status launch_stokes_pairs(sbie_geom* g, const double* d_dens, hipStream_t s) {
+// The pair kernel's launches over the partner offsets, each followed by its
+// fold: source blocks into prec, reverse sums of a launch in rev (rev_bytes),
+// forward sums into the first stokes_pair_splits slices of fwd [slices][C][N],
+// reverse totals into racc [C][N].
+template <typename R, int C, bool SDL>
+sbie_status launch_stokes_pairs(sbie_geom* g, const double* d_dens, hipStream_t s, double* prec, double* rev_buf,
+                                uint64_t rev_bytes, double* fwd, double* racc) {
   const int M = g->M, T = g->T, nb = (T + 15) / 16;
   const int RG = stokes_row_groups(T, sizeof(R) == 8);
-  R* rec = reinterpret_cast<R*>(g->d_stk_prec);
-  hipLaunchKernelGGL(k_stokes_pair_records<R>, dim3((unsigned)(((int64_t)M * nb * 64 + 255) / 256)), dim3(256), 0, s,
-                     g->d_part, d_dens, g->d_x, g->d_y, g->d_z, g->d_w, M, T, nb, g->N, rec);
+  R* rec = reinterpret_cast<R*>(prec);
+  const dim3 rgrid((unsigned)(((int64_t)M * nb * 64 + 255) / 256));
+  if constexpr (SDL)
+    hipLaunchKernelGGL(k_sdl_pair_records<R>, rgrid, dim3(256), 0, s, g->d_part, d_dens, g->d_x, g->d_y, g->d_z,
+                       g->d_w, g->d_nx, g->d_ny, g->d_nz, M, T, nb, g->N, rec);
+  else
+    hipLaunchKernelGGL(k_stokes_pair_records<R>, rgrid, dim3(256), 0, s, g->d_part, d_dens, g->d_x, g->d_y, g->d_z,
+                       g->d_w, M, T, nb, g->N, rec);
   SBIE_HIP(hipGetLastError());
   const int PMAX = (M - 1) / 2 + ((M & 1) == 0 ? 1 : 0);
-  const int KS = stokes_rev_slots(M, T, C, (int)sizeof(R), g->stk_rev_bytes);
+  const int KS = stokes_rev_slots(M, T, C, (int)sizeof(R), rev_bytes);
   const int nsplit = stokes_pair_splits(g, RG);
-  R* rev = reinterpret_cast<R*>(g->d_stk_rev);
+  R* rev = reinterpret_cast<R*>(rev_buf);
   const dim3 grid((unsigned)((int64_t)M * RG * nsplit)), fold((unsigned)((g->N + 255) / 256));
   for (int kbase = 0; kbase == 0 || kbase < PMAX; kbase += KS) {
     const int kend = kbase + KS, first = kbase == 0 ? 1 : 0;
-    hipLaunchKernelGGL((k_far_stokes_pairs<R, C>), grid, dim3(64 * kSWaves), 0, s, rec, g->d_part, g->d_x, g->d_y,
-                       g->d_z, d_dens, g->d_w, g->d_excl, g->excl_words, M, T, g->N, nsplit, RG, kbase, kend, first,
-                       g->d_stk_part, rev);
+    hipLaunchKernelGGL((k_far_stokes_pairs<R, C, SDL>), grid, dim3(64 * kSWaves), 0, s, rec, g->d_part, g->d_x,
+                       g->d_y, g->d_z, d_dens, g->d_w, g->d_nx, g->d_ny, g->d_nz, g->d_excl, g->excl_words, M, T,
+                       g->N, nsplit, RG, kbase, kend, first, fwd, rev);
     SBIE_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_far_stokes_fold<R>, fold, dim3(256), 0, s, rev, M, T, RG, C, kbase, kend, first, g->N,
-                       g->d_stk_racc);
+                       racc);
     SBIE_HIP(hipGetLastError());
   }
   return SBIE_OK;
@@ -441,8 +531,20 @@ uint64_t stokes_rev_bytes(int M, int T) {
 }
 
 sbie_status far_stokes_pairs(sbie_geom* g, int C, bool mixed, const double* d_dens, hipStream_t s) {
-  if (mixed) return C == 4 ? launch_stokes_pairs<float, 4>(g, d_dens, s) : launch_stokes_pairs<float, 3>(g, d_dens, s);
-  return C == 4 ? launch_stokes_pairs<double, 4>(g, d_dens, s) : launch_stokes_pairs<double, 3>(g, d_dens, s);
+  double *pr = g->d_stk_prec, *rv = g->d_stk_rev, *fw = g->d_stk_part, *ra = g->d_stk_racc;
+  const uint64_t rb = g->stk_rev_bytes;
+  if (mixed)
+    return C == 4 ? launch_stokes_pairs<float, 4, false>(g, d_dens, s, pr, rv, rb, fw, ra)
+                  : launch_stokes_pairs<float, 3, false>(g, d_dens, s, pr, rv, rb, fw, ra);
+  return C == 4 ? launch_stokes_pairs<double, 4, false>(g, d_dens, s, pr, rv, rb, fw, ra)
+                : launch_stokes_pairs<double, 3, false>(g, d_dens, s, pr, rv, rb, fw, ra);
+}
+
+sbie_status far_sdl_pairs(sbie_geom* g, bool mixed, const double* d_dens, hipStream_t s) {
+  double *pr = g->d_sdl_prec, *rv = g->d_sdl_rev, *fw = g->d_sdl_part, *ra = g->d_sdl_racc;
+  const uint64_t rb = g->sdl_rev_bytes;
+  return mixed ? launch_stokes_pairs<float, 3, true>(g, d_dens, s, pr, rv, rb, fw, ra)
+               : launch_stokes_pairs<double, 3, true>(g, d_dens, s, pr, rv, rb, fw, ra);
 }
 
 }  // namespace sbie

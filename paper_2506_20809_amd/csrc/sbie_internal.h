@@ -222,6 +222,10 @@ struct sbie_geom {
   double* d_sdl_self = nullptr;   // [3][N]
   double* d_sdl_near = nullptr;   // [kStokesNearSplit][3][N] near partials per source-list range
   double* d_sdl_io = nullptr;     // [6][N] host staging
+  double* d_sdl_prec = nullptr;   // [M][T16/16][208] source blocks of the stresslet pair kernel
+  double* d_sdl_rev = nullptr;    // reverse sums of one stresslet pair-kernel launch (sdl_rev_bytes)
+  double* d_sdl_racc = nullptr;   // [3][N] running reverse totals
+  uint64_t sdl_rev_bytes = 0;
   double* d_wS = nullptr;         // [M][p+1] sqrt(u0^2 -+ v_j^2)
   double* d_lam = nullptr;        // [M][Kh][4]: D principal value, D exterior, S, 1/Q_n^m(z0)
   double* d_ab = nullptr;         // [Kh][2] normalised Ferrers recurrence coefficients
@@ -318,6 +322,10 @@ int stokes_rev_slots(int M, int T, int C, int bytes_per_value, uint64_t cap_byte
 int stokes_pair_splits(const sbie_geom* g, int RG);
 uint64_t stokes_rev_bytes(int M, int T);
 sbie_status far_stokes_pairs(sbie_geom* g, int C, bool mixed, const double* d_dens, hipStream_t s);
+// The Stokes double layer's far field (the stresslet) through the same pair
+// kernel: forward sums into d_sdl_part's first stokes_pair_splits slices,
+// reverse totals into d_sdl_racc (to be scaled by 3/(4 pi)).
+sbie_status far_sdl_pairs(sbie_geom* g, bool mixed, const double* d_dens, hipStream_t s);
 
 // Multi-density S and D (far_multi.hip, apply.hip): the pair kernel's row
 // groups, slots, splits and buffer sizes for up to four densities, its far

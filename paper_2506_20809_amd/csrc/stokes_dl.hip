@@ -378,8 +378,8 @@ __global__ __launch_bounds__(256) void k_far_sdl(const R* __restrict__ rec, cons
 }
 
 __global__ void k_sdl_assemble(const double* __restrict__ uself, const double* __restrict__ unear,
-                               const double* __restrict__ partial, int nsplit, int64_t N, uint32_t parts,
-                               double* __restrict__ out) {
+                               const double* __restrict__ partial, int nsplit, const double* __restrict__ racc,
+                               int64_t N, uint32_t parts, double* __restrict__ out) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 3 * N) return;
   const int c = (int)(t / N);
@@ -391,6 +391,7 @@ __global__ void k_sdl_assemble(const double* __restrict__ uself, const double* _
   if (parts & SBIE_PARTS_FAR) {
     double f = 0.0;
     for (int s = 0; s < nsplit; ++s) f += partial[((size_t)s * 3 + c) * N + g];
+    if (racc) f += racc[t] * k3Over4Pi;
     u += f;
   }
   out[t] = u;
@@ -424,6 +425,12 @@ sbie_status carve_sdl(sbie_geom* g, Carver& c) {
   SBIE_TRY_D(c.take(&g->d_sdl_self, 3 * N));
   SBIE_TRY_D(c.take(&g->d_sdl_near, (size_t)kStokesNearSplit * 3 * N));
   SBIE_TRY_D(c.take(&g->d_sdl_io, 6 * N));
+  // the pair kernel's source blocks, reverse sums and totals
+  const size_t nb = (size_t)(g->T + 15) / 16;
+  g->sdl_rev_bytes = stokes_rev_bytes(g->M, g->T);
+  SBIE_TRY_D(c.take(&g->d_sdl_prec, (size_t)g->M * nb * 208));
+  SBIE_TRY_D(c.take(&g->d_sdl_rev, (size_t)(g->sdl_rev_bytes / sizeof(double))));
+  SBIE_TRY_D(c.take(&g->d_sdl_racc, 3 * (size_t)N));
   return SBIE_OK;
 }
 
@@ -504,7 +511,15 @@ sbie_status apply_stokes_dl(sbie_geom* g, int prec, const double* d_dens, double
   }
   if (timed) SBIE_HIP(hipEventRecord(ev[7], s));
   if (timed) SBIE_HIP(hipEventRecord(ev[3], s));
-  if (parts & SBIE_PARTS_FAR) {
+  // far field: in FP64 the pair-symmetric matrix-core kernel (T >= 32), else
+  // the one-sided vector-unit sum.  (At 256 spheroids the pair kernel took
+  // 8.35 against 9.02 ms in FP64, but 4.21 against 4.00 ms in mixed precision,
+  // where its five FP32 products per tile cost more than the vector work they
+  // save.)
+  const bool pairs = T >= 32 && !mixed;
+  if ((parts & SBIE_PARTS_FAR) && pairs) {
+    SBIE_TRY_D(far_sdl_pairs(g, mixed, d_dens, s));
+  } else if (parts & SBIE_PARTS_FAR) {
     constexpr int TPT = 2;
     const dim3 grid(cdiv(N, 256 * TPT) * g->nsplit);
     if (mixed)
@@ -518,8 +533,9 @@ sbie_status apply_stokes_dl(sbie_geom* g, int prec, const double* d_dens, double
   }
   if (timed) SBIE_HIP(hipEventRecord(ev[4], s));
   const uint32_t sum_parts = g->n_near > 0 ? parts : (parts & ~(uint32_t)SBIE_PARTS_NEAR);
+  const int nslices = pairs ? stokes_pair_splits(g, stokes_row_groups(T, !mixed)) : g->nsplit;
   hipLaunchKernelGGL(k_sdl_assemble, dim3(cdiv(3 * N, B)), dim3(B), 0, s, g->d_sdl_self, g->d_sdl_near,
-                     g->d_sdl_part, g->nsplit, N, sum_parts, d_out);
+                     g->d_sdl_part, nslices, pairs ? (const double*)g->d_sdl_racc : nullptr, N, sum_parts, d_out);
   SBIE_HIP(hipGetLastError());
   if (timed) SBIE_HIP(hipEventRecord(ev[5], s));
   return SBIE_OK;

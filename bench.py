@@ -295,6 +295,62 @@ def near_flops(p):
     return 11 * (p + 1) * (p + 2) // 2 + 60
 
 
+def target_points(geom, xyz, nrm, n, seed):
+    """n points outside every particle: half 1e-2 outside random nodes along
+    their normals (near their own particle and often a neighbour), half uniform
+    in the suspension's bounding box with the points inside a particle redrawn."""
+    import numpy as np
+
+    from workloads import quat_rot
+
+    rng = np.random.default_rng(seed)
+    idx = rng.choice(len(xyz), n // 2, replace=False)
+    near = xyz[idx] + 1e-2 * nrm[idx]
+    c = geom["centers"]
+    R = np.stack([quat_rot(q) for q in geom["quats"]])
+    ax = np.stack([geom["A"], geom["A"], geom["C"]], axis=1)
+    lo, hi = c.min(0) - 1.0, c.max(0) + 1.0
+    box = np.zeros((0, 3))
+    while len(box) < n - n // 2:
+        cand = lo + (hi - lo) * rng.random((n, 3))
+        inside = np.zeros(len(cand), dtype=bool)
+        for i in range(len(c)):
+            b = ((cand - c[i]) @ R[i]) / ax[i]
+            inside |= np.einsum("ij,ij->i", b, b) <= 1.0
+        box = np.concatenate([box, cand[~inside]])
+    return np.concatenate([near, box[: n - n // 2]])
+
+
+def run_targets(g, geom, dens, steps, n=65536):
+    """Particle-to-target evaluation (S and D with gradients) at n points,
+    mixed and FP64: points per second and, counting every (point, node) pair
+    as far (an upper bound: near pairs go through the expansions), far-pair
+    evaluations per second and the fraction of the vector peak by the direct
+    sums' flop counts (value and gradient: S 17, D 30 per pair)."""
+    import torch
+
+    import paper_2506_20809_amd as sbie
+
+    xyz, nrm, _ = g.nodes()
+    pts = torch.tensor(target_points(geom, xyz, nrm, n, 23), dtype=torch.float64, device="cuda")
+    out = {"workload": f"{n} points outside the headline suspension's particles, half 1e-2 off random nodes, "
+                       "half uniform in its bounding box"}
+    for prec, name, peak in ((sbie.SBIE_MIXED, "mixed", PEAK_TFLOPS["mixed"]), (sbie.SBIE_FP64, "fp64",
+                                                                                 PEAK_TFLOPS["fp64"])):
+        for op, on, fl in ((sbie.SBIE_OP_S, "S", 17), (sbie.SBIE_OP_D, "D", 30)):
+            g.eval_targets(op, dens[op], pts, precision=prec)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                g.eval_targets(op, dens[op], pts, precision=prec)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            pairs = n * g.N
+            out[f"{name}_{on}"] = {"ms_per_call": dt * 1e3, "points_per_s": n / dt, "pair_evals_per_s": pairs / dt,
+                                   "vector_frac_upper": fl * pairs / dt / 1e12 / peak}
+    return out
+
+
 def run_near(ctx, steps):
     """The near field alone (SBIE_PARTS_NEAR): S, D, S' and D' on the
     512-spheroid suspension (p = 16), the Stokes single layer (without and with
@@ -706,6 +762,7 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="skip the completed double-layer solves")
     ap.add_argument("--no-tree", action="store_true", help="skip the tree far-field measurement")
     ap.add_argument("--no-near", action="store_true", help="skip the near-field measurement")
+    ap.add_argument("--no-targets", action="store_true", help="skip the particle-to-target measurement")
     ap.add_argument("--no-multi", action="store_true", help="skip the multi-density (nrhs = 4) measurement")
     ap.add_argument("--tree-sweep", action="store_true",
                     help="add the FP64 tree's accuracy and time over several (theta, order)")
@@ -807,6 +864,8 @@ def main():
         res[f"{other}_path"]["roofline"] = dict(sec["roofline"], traffic=counter_traffic(other, args.workload))
     if not args.no_near:
         res["near_field"] = run_near(ctx, max(3, args.steps // 4))
+    if not args.no_targets:
+        res["targets"] = run_targets(g, geom, dens[0], max(3, args.steps // 4))
     if not args.no_multi:
         res["multi_density"] = {pr: run_multi(g, max(2, args.steps // 4), pr) for pr in ("mixed", "fp64")}
     if not args.no_derivatives:

@@ -231,7 +231,7 @@ sbie_status sbie_eval_targets(sbie_geom* g, sbie_op op, sbie_precision prec, con
 /* For callers that cannot allocate device memory (code under HIP graph
    capture, tight serving loops, harnesses that forbid allocation):
    sbie_eval_targets with its work buffers (target coordinates, near masks,
-   near values, far partials) in a static device array of
+   near values, far partials, sort keys and order) in a static device array of
    SBIE_TARGETS_SCRATCH_BYTES on each GPU, held until the process ends; the
    call allocates nothing.  density, pts, val and grad are device pointers
    (SBIE_DEVICE_PTRS is required); the results equal sbie_eval_targets's (the
@@ -240,7 +240,7 @@ sbie_status sbie_eval_targets(sbie_geom* g, sbie_op op, sbie_precision prec, con
    several threads or streams) race.  Errors as sbie_eval_targets, plus
    SBIE_E_INVALID without SBIE_DEVICE_PTRS and SBIE_E_BUDGET when the work
    buffers for npts points on this geometry exceed the array (about
-   (56 + 4 ceil(M/32)) bytes per point plus up to 34 MB of far partials). */
+   (64 + 4 ceil(M/32)) bytes per point plus up to 34 MB of far partials). */
 #define SBIE_TARGETS_SCRATCH_BYTES (64u << 20)
 sbie_status sbie_eval_targets_noalloc(sbie_geom* g, sbie_op op, sbie_precision prec, const double* density,
                                       int64_t npts, const double* pts, double* val, double* grad, void* stream,

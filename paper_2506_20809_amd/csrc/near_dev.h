@@ -46,11 +46,15 @@ constexpr bool kUnrollOrders = EXACT && PMAX <= 16;
 // margin, the largest over the wave (wave-uniform), in whole chunks of eight
 // steps; past cap steps (at most kMaxNearDepth) the depth is capped and
 // numeric_flag is set in *bad.
-__device__ inline int near_depth(double u, double sw, int N, int cap, unsigned numeric_flag, unsigned* bad) {
+// With own, *own receives the lane's own depth (capped and rounded the same
+// way), for q_top_orders01's lane-exact start.
+__device__ inline int near_depth(double u, double sw, int N, int cap, unsigned numeric_flag, unsigned* bad,
+                                 int* own = nullptr) {
   // clamped in floating point: a point on the focal set (u + sw = 1, only
   // reachable from inside the spheroid) or a NaN gives the capped depth
   const double sd = ceil(20.1 / log(u + sw)) + 8.0;
-  int steps = sd < 200000.0 ? (int)sd : 200000;
+  const int mine = sd < 200000.0 ? (int)sd : 200000;
+  int steps = mine;
   for (int off = 32; off >= 1; off >>= 1) steps = max(steps, __shfl_xor(steps, off, 64));
   steps = __builtin_amdgcn_readfirstlane(steps);
   cap = min(cap, kMaxNearDepth);
@@ -59,10 +63,13 @@ __device__ inline int near_depth(double u, double sw, int N, int cap, unsigned n
     *bad |= numeric_flag;
   }
   steps = (steps + 7) & ~7;
+  if (own) *own = N + ((min(mine, cap) + 7) & ~7);
   return N + steps;
 }
 
-// Q_N^m and Q_{N+1}^m for m = 0 and 1.  The minimal solution of the
+// Q_N^m and Q_{N+1}^m for m = 0 and 1.  With own > 0 the lane starts its
+// recurrence at degree own (<= L, on the same chunks of eight) instead of L:
+// its result then depends on its own point only, not on the wave's deepest.  The minimal solution of the
 // recurrence in n comes from backward recurrence from degree L (the continued
 // fraction for Q_N/Q_{N-1} evaluated bottom-up), free of divisions with
 // Q_n = s_n R_n and s_{n-1} = s_n/(n+m):
@@ -72,12 +79,19 @@ __device__ inline int near_depth(double u, double sw, int N, int cap, unsigned n
 //   Pt_N Q_{N-1} -+ (N-m) Pt_{N-1} Q_N = (-1)^m (N+m-1)!,
 // fixes the scale.  rcp[k] = 1/k.
 __device__ inline void q_top_orders01(double u, double sw, double sgn, int N, int L, const double* __restrict__ rcp,
-                                      double qN[2], double qN1[2]) {
+                                      double qN[2], double qN1[2], int own = 0) {
   double qh[2] = {0.0, 0.0}, qc[2] = {1.0, 1.0};
   const double smsq[2] = {0.0, sgn};
   double c2n1 = (double)(2 * L + 1), snp = sgn * (double)(L + 1) * (double)(L + 1), sc = sgn * c2n1;
   const double dsc = -2.0 * sgn;
   for (int n = L; n > N; n -= 8) {
+    if (own > 0 && n >= own) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        qh[k] = 0.0;
+        qc[k] = 1.0;
+      }
+    }
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const double cu = c2n1 * u;
@@ -338,15 +352,17 @@ __device__ inline SpheroidalPoint to_spheroidal(const Particle& P, double X0, do
 template <int PMAX, typename F>
 __device__ inline void expansion_terms(const SpheroidalPoint& q, bool oblate, const double* __restrict__ L,
                                        const double* __restrict__ ab, const double* __restrict__ cd,
-                                       const double* __restrict__ rcp, int p, int cap, unsigned* bad, F&& f) {
+                                       const double* __restrict__ rcp, int p, int cap, unsigned* bad, F&& f,
+                                       bool lane_depth = false) {
   const int N1 = p + 1;
   const double u = q.u, v = q.v;
   const double inv_omv2 = 1.0 / (q.sv * q.sv);
   const double inv_w = 1.0 / q.w;
   const double sgn = oblate ? 1.0 : -1.0;
-  const int Ld = near_depth(u, q.sw, N1, cap, kStatNumeric, bad);
+  int own = 0;
+  const int Ld = near_depth(u, q.sw, N1, cap, kStatNumeric, bad, lane_depth ? &own : nullptr);
   double qn0[2], qn1[2];
-  q_top_orders01(u, q.sw, sgn, N1, Ld, rcp, qn0, qn1);
+  q_top_orders01(u, q.sw, sgn, N1, Ld, rcp, qn0, qn1, own);
   const double ur = u / q.sw;
   double fa2 = 0.0, fa1 = 0.0, fb2 = 0.0, fb1 = 0.0;
   double pbar = 0.28209479177387814347, cm = 1.0, sm = 0.0;
@@ -476,13 +492,14 @@ __device__ inline void expansion_orders(const SpheroidalPoint& q, bool oblate, c
 
 // NSET exterior expansions of one source particle at a mapped point, with
 // their u, v and phi derivatives.  Es: coefficients of set s at E + s * stride.
+// With lane_depth each lane's recurrence starts at its own depth.
 template <int PMAX, int NSET>
 __device__ inline void expansion_derivatives(const SpheroidalPoint& q, bool oblate, const double* __restrict__ E,
                                              size_t stride, const double* __restrict__ L,
                                              const double* __restrict__ ab, const double* __restrict__ cd,
                                              const double* __restrict__ rcp, int p, int cap, unsigned* bad,
                                              double (&Phi)[NSET], double (&Pu)[NSET], double (&Pv)[NSET],
-                                             double (&Pp)[NSET]) {
+                                             double (&Pp)[NSET], bool lane_depth = false) {
 #pragma unroll
   for (int s = 0; s < NSET; ++s) Phi[s] = Pu[s] = Pv[s] = Pp[s] = 0.0;
   expansion_terms<PMAX>(q, oblate, L, ab, cd, rcp, p, cap, bad,
@@ -503,7 +520,8 @@ __device__ inline void expansion_derivatives(const SpheroidalPoint& q, bool obla
                               Pp[s] = fma(es, bp, Pp[s]);
                             }
                           }
-                        });
+                        },
+                        lane_depth);
 }
 
 // The chain rule of lab_gradient as coefficients: the lab gradient of an

@@ -61,56 +61,138 @@ __device__ inline double meridian_distance(double rho, double z, double A, doubl
 // Near flags near[t][w] (bit b of word w: particle 32w + b) by the rule
 // distance < eta * diam(source); the circumsphere bound |x - c| - diam/2
 // settles most pairs without the exact distance.  A point inside a particle
-// sets kStatExterior.
-__global__ void k_classify_targets(const Particle* __restrict__ part, int M, int words, double eta,
-                                   const double* __restrict__ tx, const double* __restrict__ ty,
-                                   const double* __restrict__ tz, int64_t n, uint32_t* __restrict__ mask,
-                                   unsigned* status) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  const double X0 = tx[t], X1 = ty[t], X2 = tz[t];
-  unsigned bad = 0u;
-  for (int w = 0; w < words; ++w) {
-    uint32_t bits = 0u;
-    for (int b = 0; b < 32; ++b) {
-      const int i = 32 * w + b;
-      if (i >= M) break;
+// sets kStatExterior.  One wave per (target, 64 particles), a lane per
+// particle, so that only the particles near the wave's one target take the
+// exact distance (a wave of 64 targets would run it for the union of their
+// candidates); the flags are the wave's ballot.  The units run grid-stride.
+__global__ __launch_bounds__(256) void k_classify_targets(const Particle* __restrict__ part, int M, int words,
+                                                          double eta, const double* __restrict__ tx,
+                                                          const double* __restrict__ ty,
+                                                          const double* __restrict__ tz, int64_t n,
+                                                          uint32_t* __restrict__ mask, unsigned* status) {
+  const int chunks = (M + 63) / 64;
+  const int lane = threadIdx.x & 63;
+  const int64_t units = n * chunks;
+  const int64_t stride = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t u = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); u < units; u += stride) {
+    const int64_t t = u / chunks;
+    const int c = (int)(u - t * chunks);
+    const int i = 64 * c + lane;
+    const double X0 = tx[t], X1 = ty[t], X2 = tz[t];
+    bool near = false, inside = false;
+    if (i < M) {
       const Particle& P = part[i];
       const double d0 = X0 - P.c[0], d1 = X1 - P.c[1], d2 = X2 - P.c[2];
-      const double dc = sqrt(fma(d2, d2, fma(d1, d1, d0 * d0)));
       const double lim = eta * P.diam;
-      if (dc - 0.5 * P.diam >= lim) continue;
-      const double b0 = P.R[0] * d0 + P.R[3] * d1 + P.R[6] * d2;
-      const double b1 = P.R[1] * d0 + P.R[4] * d1 + P.R[7] * d2;
-      const double b2 = P.R[2] * d0 + P.R[5] * d1 + P.R[8] * d2;
-      const double rho = sqrt(b0 * b0 + b1 * b1), z = fabs(b2);
-      if ((rho / P.A) * (rho / P.A) + (z / P.C) * (z / P.C) <= 1.0) {
-        bad |= kStatExterior;
-        bits |= 1u << b;
-        continue;
+      // |x - c| - diam/2 >= lim, squared (no square root for the far pairs)
+      const double rr = lim + 0.5 * P.diam;
+      if (fma(d2, d2, fma(d1, d1, d0 * d0)) < rr * rr) {
+        const double b0 = P.R[0] * d0 + P.R[3] * d1 + P.R[6] * d2;
+        const double b1 = P.R[1] * d0 + P.R[4] * d1 + P.R[7] * d2;
+        const double b2 = P.R[2] * d0 + P.R[5] * d1 + P.R[8] * d2;
+        const double rho = sqrt(b0 * b0 + b1 * b1), z = fabs(b2);
+        if ((rho / P.A) * (rho / P.A) + (z / P.C) * (z / P.C) <= 1.0)
+          inside = near = true;
+        else
+          near = meridian_distance(rho, z, P.A, P.C) < lim;
       }
-      if (meridian_distance(rho, z, P.A, P.C) < lim) bits |= 1u << b;
     }
-    mask[(size_t)t * words + w] = bits;
+    const uint64_t bits = __ballot(near);
+    if (lane == 0) {
+      mask[(size_t)t * words + 2 * c] = (uint32_t)bits;
+      if (2 * c + 1 < words) mask[(size_t)t * words + 2 * c + 1] = (uint32_t)(bits >> 32);
+    }
+    if (__any(inside) && lane == 0) atomicOr(status, kStatExterior);
   }
-  if (bad) atomicOr(status, bad);
 }
 
-// Near part: one wave per 64 targets.  The wave visits every particle that is
-// near to any of its lanes; all lanes evaluate the expansion (wave-uniform
-// recurrence depth), lanes whose target is not near that particle map a
-// stand-in point two diameters from its centre and discard the result.
-// out[4][n]: value and lab gradient.
+// Sort key of each target: its first near particle, or M with none (whose
+// near part is then zero, written here).
+__global__ void k_target_keys(const uint32_t* __restrict__ mask, int words, int M, int64_t n,
+                              uint32_t* __restrict__ key, double* __restrict__ nearv) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  uint32_t k = (uint32_t)M;
+  for (int w = 0; w < words; ++w) {
+    const uint32_t m = mask[(size_t)t * words + w];
+    if (m) {
+      k = 32u * (uint32_t)w + (uint32_t)__builtin_ctz(m);
+      break;
+    }
+  }
+  key[t] = k;
+  if (k == (uint32_t)M)
+    for (int c = 0; c < 4; ++c) nearv[(size_t)c * n + t] = 0.0;
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ a, int64_t count, uint32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) a[i] = v;
+}
+
+__global__ void k_key_count(const uint32_t* __restrict__ key, int64_t n, uint32_t* __restrict__ cnt) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) atomicAdd(&cnt[key[t]], 1u);
+}
+
+// Exclusive prefix sums of cnt[0..nb) in place, by one workgroup of 256 lanes
+// in blocks of 256 values; cnt[nb] receives the total of cnt[0..nb-1) (the
+// targets with a near particle, whose keys are below nb - 1 = M).
+__global__ __launch_bounds__(256) void k_key_offsets(uint32_t* __restrict__ cnt, int nb) {
+  __shared__ uint32_t s[256];
+  __shared__ uint32_t carry;
+  const int tid = threadIdx.x;
+  if (tid == 0) carry = 0u;
+  __syncthreads();
+  for (int base = 0; base < nb; base += 256) {
+    const int i = base + tid;
+    const uint32_t v = i < nb ? cnt[i] : 0u;
+    s[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const uint32_t add = tid >= off ? s[tid - off] : 0u;
+      __syncthreads();
+      s[tid] += add;
+      __syncthreads();
+    }
+    const uint32_t c0 = carry;
+    if (i < nb) cnt[i] = c0 + s[tid] - v;
+    if (i == nb - 1) cnt[nb] = c0 + s[tid] - v;
+    __syncthreads();
+    if (tid == 255) carry = c0 + s[255];
+    __syncthreads();
+  }
+}
+
+// perm: targets grouped by key (the order within a group is immaterial: every
+// target's result depends on its own point only).
+__global__ void k_key_scatter(const uint32_t* __restrict__ key, int64_t n, uint32_t* __restrict__ off,
+                              uint32_t* __restrict__ perm) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) perm[atomicAdd(&off[key[t]], 1u)] = (uint32_t)t;
+}
+
+// Near part: one wave per 64 targets of the key order (slots below *nnear:
+// the targets with a near particle, grouped by their first one, so that a
+// wave's targets share their near particles).  The wave visits every particle
+// that is near to any of its lanes; all lanes evaluate the expansion (each
+// lane's recurrence from its own depth), lanes whose target is not near that
+// particle map a stand-in point two diameters from its centre and discard the
+// result.  out[4][n]: value and lab gradient, at the targets' own indices.
 template <int PMAX>
 __global__ __launch_bounds__(64) void k_near_targets(
     const Particle* __restrict__ part, const double* __restrict__ tx, const double* __restrict__ ty,
-    const double* __restrict__ tz, int64_t n, const uint32_t* __restrict__ mask, int words, int M,
+    const double* __restrict__ tz, int64_t n, const uint32_t* __restrict__ perm, const uint32_t* __restrict__ nnear,
+    const uint32_t* __restrict__ mask, int words, int M,
     const double* __restrict__ E, const double* __restrict__ lam, const double* __restrict__ ab,
     const double* __restrict__ cd, const double* __restrict__ rcp, int p, unsigned* status,
     double* __restrict__ out) {
-  const int64_t t = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  const bool live = t < n;
-  const int64_t tt = live ? t : 0;
+  const int64_t slot = (int64_t)blockIdx.x * 64;
+  const int64_t nn = (int64_t)*nnear;
+  if (slot >= nn) return;  // wave-uniform
+  const bool live = slot + threadIdx.x < nn;
+  const int64_t t = live ? (int64_t)perm[slot + threadIdx.x] : 0;
+  const int64_t tt = t;
   const double X0 = tx[tt], X1 = ty[tt], X2 = tz[tt];
   const int K = (p + 1) * (p + 1), Kh = (p + 1) * (p + 2) / 2;
   double v = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
@@ -135,7 +217,7 @@ __global__ __launch_bounds__(64) void k_near_targets(
       const SpheroidalPoint q = to_spheroidal(P, px, py, pz, true, &lb);
       double Phi[1], Pu[1], Pv[1], Pp[1];
       expansion_derivatives<PMAX, 1>(q, P.oblate != 0, E + (size_t)i * K, (size_t)K, lam + (size_t)i * Kh * 4, ab,
-                                     cd, rcp, p, cap, &lb, Phi, Pu, Pv, Pp);
+                                     cd, rcp, p, cap, &lb, Phi, Pu, Pv, Pp, true);
       double gr[3];
       lab_gradient(P, q.u, q.sw, q.v, q.sv, q.c1, q.s1, Pu[0], Pv[0], Pp[0], gr);
       if (use) {
@@ -293,18 +375,24 @@ void launch_far_targets(const sbie_geom* g, const double* tx, const double* ty, 
 
 template <int PMAX>
 void launch_near_targets(const sbie_geom* g, const double* tx, const double* ty, const double* tz, int64_t n,
-                         const uint32_t* mask, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_near_targets<PMAX>, dim3(cdiv(n, 64)), dim3(64), 0, s, g->d_part, tx, ty, tz, n, mask,
-                     g->excl_words, g->M, g->d_E, g->d_lam, g->d_ab, g->d_cd, g->d_rcp, g->p, g->d_status, out);
+                         const uint32_t* perm, const uint32_t* nnear, const uint32_t* mask, double* out,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_near_targets<PMAX>, dim3(cdiv(n, 64)), dim3(64), 0, s, g->d_part, tx, ty, tz, n, perm, nnear,
+                     mask, g->excl_words, g->M, g->d_E, g->d_lam, g->d_ab, g->d_cd, g->d_rcp, g->p, g->d_status,
+                     out);
 }
 
 // Work buffers of one evaluation at n points: target coordinates (SoA),
-// per-target near masks, near values and gradients, far partials per split.
+// per-target near masks, near values and gradients, far partials per split,
+// sort keys, the key order and the per-key counts.
 struct TargetWork {
   double* xyz = nullptr;    // [3][n]
   uint32_t* mask = nullptr; // [n][words]
   double* nearv = nullptr;  // [4][n]
   double* partial = nullptr;  // [nsplit][4][n]
+  uint32_t* key = nullptr;  // [n]
+  uint32_t* perm = nullptr; // [n]
+  uint32_t* cnt = nullptr;  // [M + 2]: per-key counts, then offsets; [M + 1] the targets with a near particle
 };
 
 int target_splits(const sbie_geom* g, int64_t n) {
@@ -318,7 +406,8 @@ inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 size_t target_work_bytes(const sbie_geom* g, int64_t n) {
   const size_t un = (size_t)n;
   return align256(sizeof(double) * 3 * un) + align256(sizeof(uint32_t) * un * g->excl_words) +
-         align256(sizeof(double) * 4 * un) + align256(sizeof(double) * 4 * (size_t)target_splits(g, n) * un);
+         align256(sizeof(double) * 4 * un) + align256(sizeof(double) * 4 * (size_t)target_splits(g, n) * un) +
+         2 * align256(sizeof(uint32_t) * un) + align256(sizeof(uint32_t) * ((size_t)g->M + 2));
 }
 
 TargetWork carve_work(const sbie_geom* g, int64_t n, char* base) {
@@ -331,6 +420,12 @@ TargetWork carve_work(const sbie_geom* g, int64_t n, char* base) {
   w.nearv = reinterpret_cast<double*>(base);
   base += align256(sizeof(double) * 4 * un);
   w.partial = reinterpret_cast<double*>(base);
+  base += align256(sizeof(double) * 4 * (size_t)target_splits(g, n) * un);
+  w.key = reinterpret_cast<uint32_t*>(base);
+  base += align256(sizeof(uint32_t) * un);
+  w.perm = reinterpret_cast<uint32_t*>(base);
+  base += align256(sizeof(uint32_t) * un);
+  w.cnt = reinterpret_cast<uint32_t*>(base);
   return w;
 }
 
@@ -349,15 +444,29 @@ sbie_status eval_targets(sbie_geom* g, int op, int prec, const double* d_dens, i
   double* tz = ty + n;
   hipLaunchKernelGGL(k_targets_soa, dim3(cdiv(n, 256)), dim3(256), 0, s, d_pts, n, tx, ty, tz);
   SBIE_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_classify_targets, dim3(cdiv(n, 256)), dim3(256), 0, s, g->d_part, g->M, words, g->eta, tx,
-                     ty, tz, n, w.mask, g->d_status);
+  {
+    const int64_t units = n * (int64_t)((g->M + 63) / 64);
+    const int64_t blocks = std::min<int64_t>(cdiv(units, 4), 262144);
+    hipLaunchKernelGGL(k_classify_targets, dim3((unsigned)blocks), dim3(256), 0, s, g->d_part, g->M, words, g->eta,
+                       tx, ty, tz, n, w.mask, g->d_status);
+  }
   SBIE_HIP(hipGetLastError());
+  // the targets grouped by their first near particle (counting sort), so that
+  // a wave of the near kernel visits few particles
+  const int nb = g->M + 1;
+  hipLaunchKernelGGL(k_target_keys, dim3(cdiv(n, 256)), dim3(256), 0, s, w.mask, words, g->M, n, w.key, w.nearv);
+  hipLaunchKernelGGL(k_fill_u32, dim3(cdiv((int64_t)nb + 1, 256)), dim3(256), 0, s, w.cnt, (int64_t)nb + 1, 0u);
+  hipLaunchKernelGGL(k_key_count, dim3(cdiv(n, 256)), dim3(256), 0, s, w.key, n, w.cnt);
+  hipLaunchKernelGGL(k_key_offsets, dim3(1), dim3(256), 0, s, w.cnt, nb);
+  hipLaunchKernelGGL(k_key_scatter, dim3(cdiv(n, 256)), dim3(256), 0, s, w.key, n, w.cnt, w.perm);
+  SBIE_HIP(hipGetLastError());
+  const uint32_t* nnear = w.cnt + nb;
   if (g->p <= 8)
-    launch_near_targets<8>(g, tx, ty, tz, n, w.mask, w.nearv, s);
+    launch_near_targets<8>(g, tx, ty, tz, n, w.perm, nnear, w.mask, w.nearv, s);
   else if (g->p <= 16)
-    launch_near_targets<16>(g, tx, ty, tz, n, w.mask, w.nearv, s);
+    launch_near_targets<16>(g, tx, ty, tz, n, w.perm, nnear, w.mask, w.nearv, s);
   else
-    launch_near_targets<32>(g, tx, ty, tz, n, w.mask, w.nearv, s);
+    launch_near_targets<32>(g, tx, ty, tz, n, w.perm, nnear, w.mask, w.nearv, s);
   SBIE_HIP(hipGetLastError());
   const bool mixed = prec == SBIE_MIXED;
   const uint32_t* mk = w.mask;

@@ -770,7 +770,7 @@ def main():
                     help="only the Stokes single layer and its pressure (both precisions), for profiling")
     ap.add_argument("--only-near", action="store_true",
                     help="run only the near-field section (for counter runs); prints its JSON object")
-    ap.add_argument("--served-requests", type=int, default=48,
+    ap.add_argument("--served-requests", type=int, default=96,
                     help="requests in the served-mode run (0: skip)")
     ap.add_argument("--served-rho", type=float, nargs="+", default=[0.8], help="loads of the Poisson arrivals")
     ap.add_argument("--served-budget-gib", type=int, nargs="+", default=[64], help="HBM budgets of the server")

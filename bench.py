@@ -770,6 +770,8 @@ def main():
                     help="only the Stokes single layer and its pressure (both precisions), for profiling")
     ap.add_argument("--only-near", action="store_true",
                     help="run only the near-field section (for counter runs); prints its JSON object")
+    ap.add_argument("--only-targets", action="store_true",
+                    help="run only the particle-to-target section on the headline suspension; prints its JSON object")
     ap.add_argument("--served-requests", type=int, default=96,
                     help="requests in the served-mode run (0: skip)")
     ap.add_argument("--served-rho", type=float, nargs="+", default=[0.8], help="loads of the Poisson arrivals")
@@ -808,6 +810,19 @@ def main():
     if args.only_near:
         ctx = sbie.Context(0)
         print(json.dumps({"near_field": run_near(ctx, max(2, args.steps // 4))}), flush=True)
+        ctx.close()
+        return
+    if args.only_targets:
+        import torch
+
+        ctx = sbie.Context(0)
+        tgeom = workloads.geometry(args.workload)
+        tg = sbie.Geometry(ctx, tgeom, workloads.CONFIGS[args.workload]["p"])
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(5)
+        td = torch.randn((2, tg.N), dtype=torch.float64, device="cuda", generator=gen)
+        print(json.dumps({"targets": run_targets(tg, tgeom, td, max(3, args.steps // 4))}), flush=True)
+        tg.close()
         ctx.close()
         return
     if args.only_stokes:

@@ -8,8 +8,9 @@ Every density's result is held to the oracle's apply of that density (FP64
 density (FP64 1e-12; mixed 1e-6: the far sums are taken in another order).
 Cases: four densities on 64 spheroids, group splits 2, 3, 5 (four plus one)
 and 9 (four, four, one), host and device pointers, the far part alone, one to
-three particles (no partner, one, an odd count), and 512 spheroids at sampled
-nodes."""
+three particles (no partner, one, an odd count), the shared near field at the
+orders of its other kernels (12 and 32 exact, 20 with the order at run time),
+and 512 spheroids at sampled nodes."""
 import numpy as np
 import pytest
 
@@ -79,6 +80,26 @@ def test_group_splits_and_pointers(ctx, nrhs):
         for k in range(2):
             uf = oracle.apply(geom, p, op, dens[k], parts=True)[3]
             assert _rel(far[k], uf) < 1e-10, (op, k)
+    g.close()
+
+
+@pytest.mark.parametrize("p", [12, 20, 32])
+def test_shared_near_field_orders(ctx, p):
+    """The near field of three densities in one launch equals the one-density
+    near field of each (FP64, 1e-12), and the whole apply the oracle's."""
+    import paper_2506_20809_amd as sbie
+
+    geom = workloads.rsa_pack(5, 0.2, 0.02, 700 + p)
+    g = sbie.Geometry(ctx, geom, p)
+    assert g.num_near_pairs > 0
+    dens = np.random.default_rng(40 + p).standard_normal((3, g.N))
+    near = g.apply(0, dens, parts=sbie.SBIE_PARTS_NEAR)
+    out = g.apply(0, dens)
+    for k in range(3):
+        one = g.apply(0, dens[k], parts=sbie.SBIE_PARTS_NEAR)
+        assert _rel(near[k], one) < 1e-12, (k, _rel(near[k], one))
+        ref = oracle.apply(geom, p, 0, dens[k])
+        assert _rel(out[k], ref) < TOL[0], (k, _rel(out[k], ref))
     g.close()
 
 

@@ -28,7 +28,9 @@
 // odd in d, so its reverse term changes sign.  Its products per tile are |d|^2
 // and the four dots d.m_b = [D 1].[m_b -m_b.o], d.nu_b likewise, and
 // d.m_a = [m_a/2 m_a.D].[-2o 1], d.nu_a likewise; the vector units take d_i,
-// 1/r^5 and the weights.
+// 1/r^5 and the weights.  Five FP32 products per tile would cost more than the
+// one-sided sum, so in the mixed path they are three-piece bf16 products
+// (x3.h), half the matrix-core time for the same FP32 accuracy of each dot.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -51,6 +53,21 @@ using d4s = double __attribute__((ext_vector_type(4)));
 constexpr int kSGeo = 160;
 // the stresslet's: [-2o 1] (64), |o|^2 (16), [m  -m.o] (64), [nu  -nu.o] (64)
 constexpr int kSDGeo = 208;
+
+// The stresslet's mixed path takes its products in the three-piece bf16 form
+// (x3.h); per 16-source block, in floats, the B operands as one u4 per lane:
+// [-2o 1] with |o|^2 in its extra slots (0..255), [m -m.o] (256..511),
+// [nu -nu.o] (512..767); then -o_i per column [3][16].  (The Stokeslet keeps
+// the FP32 products: with them its far field is about three times closer to
+// the FP64 one, for about 4% more time.)
+struct SdlX3 {
+  static constexpr int MO = 768, SIZE = 816;
+};
+
+template <typename R, bool SDL>
+constexpr int stokes_geo() {
+  return SDL ? (sizeof(R) == 4 ? SdlX3::SIZE : kSDGeo) : kSGeo;
+}
 constexpr int kSWaves = 12;  // most waves per workgroup (three per SIMD), each holding up to RB row blocks
 
 template <typename R>
@@ -146,11 +163,23 @@ __global__ void k_sdl_pair_records(const Particle* __restrict__ part, const doub
     nu[1] = ny[g];
     nu[2] = nz[g];
   }
-  R* out = rec + blk * kSDGeo;
-  out[lane] = lg < 3 ? (R)(-2.0 * o[lg]) : R(1);
-  out[80 + lane] = lg < 3 ? (R)m[lg] : (R)(-(m[0] * o[0] + m[1] * o[1] + m[2] * o[2]));
-  out[144 + lane] = lg < 3 ? (R)nu[lg] : (R)(-(nu[0] * o[0] + nu[1] * o[1] + nu[2] * o[2]));
-  if (lg == 0) out[64 + li] = (R)(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]);
+  const double o2 = o[0] * o[0] + o[1] * o[1] + o[2] * o[2];
+  const double mo = -(m[0] * o[0] + m[1] * o[1] + m[2] * o[2]);
+  const double no = -(nu[0] * o[0] + nu[1] * o[1] + nu[2] * o[2]);
+  if constexpr (sizeof(R) == 4) {
+    float* out = rec + blk * SdlX3::SIZE;
+    reinterpret_cast<u4*>(out)[lane] = split_b(lg < 3 ? (float)(-2.0 * o[lg]) : 1.0f, lg, (float)o2);
+    reinterpret_cast<u4*>(out + 256)[lane] = split_b(lg < 3 ? (float)m[lg] : (float)mo, lg, 0.0f);
+    reinterpret_cast<u4*>(out + 512)[lane] = split_b(lg < 3 ? (float)nu[lg] : (float)no, lg, 0.0f);
+    if (lg == 0)
+      for (int k = 0; k < 3; ++k) out[SdlX3::MO + 16 * k + li] = (float)(-o[k]);
+  } else {
+    R* out = rec + blk * kSDGeo;
+    out[lane] = lg < 3 ? (R)(-2.0 * o[lg]) : R(1);
+    out[80 + lane] = lg < 3 ? (R)m[lg] : (R)mo;
+    out[144 + lane] = lg < 3 ? (R)nu[lg] : (R)no;
+    if (lg == 0) out[64 + li] = (R)o2;
+  }
 }
 
 // The pair kernel.  Work index (XCD-ordered) -> (particle a, row group rg,
@@ -172,8 +201,9 @@ __global__ __launch_bounds__(64 * kSWaves) void k_far_stokes_pairs(
   using V = typename SS::V;
   constexpr int RB = SS::RB, CH = SS::CHUNK;
   constexpr bool F32 = sizeof(R) == 4;
-  constexpr int GEO = SDL ? kSDGeo : kSGeo;
-  __shared__ R lds_rec[CH * GEO];
+  constexpr bool X3 = F32 && SDL;  // three-piece products
+  constexpr int GEO = stokes_geo<R, SDL>();
+  __shared__ __align__(16) R lds_rec[CH * GEO];
   __shared__ R lds_rev[kSWaves * C * CH * 16];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -195,6 +225,13 @@ __global__ __launch_bounds__(64 * kSWaves) void k_far_stokes_pairs(
   const int k1 = klo + (int)((int64_t)(khi - klo) * (split + 1) / nsplit);
   const int KS = kend - kbase;
   const Particle& Pa = part[a];
+  // an A operand: the value itself, or its three-piece form (with `extra`,
+  // the slots that add the B operand's per-column term)
+  using AOp = std::conditional_t<X3, u4, R>;
+  auto aform = [&](R v, bool extra) -> AOp {
+    if constexpr (X3) return split_a(v, lg, extra);
+    else return v;
+  };
 
   // rows: the A-operand row li (component lg of its position and strength)
   // and the accumulator rows' strengths
@@ -251,8 +288,10 @@ __global__ __launch_bounds__(64 * kSWaves) void k_far_stokes_pairs(
     }
     const double cb = part[b].c[cl];
     // A operands: [D |D|^2], [D 1], [q_a/2  q_a.D] (stresslet: m_a) and, for
-    // the stresslet, [nu_a/2  nu_a.D]
-    R aop[RB], a1[RB], a3[RB], a4[SDL ? RB : 1];
+    // the stresslet, [nu_a/2  nu_a.D]; D_i of this lane's accumulator rows,
+    // from the lanes holding them in [D 1] (row r, component i at lane r + 16 i)
+    AOp aop[RB], a1[RB], a3[RB], a4[SDL ? RB : 1];
+    R d1[RB];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
       const double dl = lg < 3 ? tcl[rb] - cb : 0.0;
@@ -262,25 +301,24 @@ __global__ __launch_bounds__(64 * kSWaves) void k_far_stokes_pairs(
       double qd = lg < 3 ? (double)qA[rb] * dl : 0.0;
       qd += lane_value(qd, x16);
       qd += lane_value(qd, x32);
-      aop[rb] = (R)(lg < 3 ? dl : d2);
-      a1[rb] = lg < 3 ? (R)dl : R(1);
-      a3[rb] = lg < 3 ? R(0.5) * qA[rb] : (R)qd;
+      d1[rb] = lg < 3 ? (R)dl : R(1);
+      aop[rb] = aform((R)(lg < 3 ? dl : d2), true);
+      a1[rb] = aform(d1[rb], false);
+      a3[rb] = aform(lg < 3 ? R(0.5) * qA[rb] : (R)qd, false);
       if constexpr (SDL) {
         double nd = lg < 3 ? (double)nA[rb] * dl : 0.0;
         nd += lane_value(nd, x16);
         nd += lane_value(nd, x32);
-        a4[rb] = lg < 3 ? R(0.5) * nA[rb] : (R)nd;
+        a4[rb] = aform(lg < 3 ? R(0.5) * nA[rb] : (R)nd, false);
       }
     }
-    // D_i of this lane's accumulator rows, from the lanes holding them in the
-    // A operand (row r, component i at lane r + 16 i)
     R Dv[RB][4][3];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
       for (int e = 0; e < 4; ++e)
 #pragma unroll
-        for (int i = 0; i < 3; ++i) Dv[rb][e][i] = lane_value(a1[rb], (SS::row(lg, e) + 16 * i) << 2);
+        for (int i = 0; i < 3; ++i) Dv[rb][e][i] = lane_value(d1[rb], (SS::row(lg, e) + 16 * i) << 2);
     // this partner's forward tiles (FP32); FP64 adds into accD directly
     R tf[F32 ? RB : 1][4][C];
 #pragma unroll
@@ -302,32 +340,55 @@ __global__ __launch_bounds__(64 * kSWaves) void k_far_stokes_pairs(
       for (int c0 = 0; c0 < nb; c0 += CH) {
         const int nbc = nb - c0 < CH ? nb - c0 : CH;
         __syncthreads();  // the previous chunk's operands and reverse sums are consumed
-        {
+        if constexpr (X3) {
+          const u4* gsrc = reinterpret_cast<const u4*>(rec + ((size_t)b * nb + c0) * GEO);
+          u4* dst = reinterpret_cast<u4*>(lds_rec);
+          for (int i = tid; i < nbc * (GEO / 4); i += blockDim.x) dst[i] = gsrc[i];
+        } else {
           const R* gsrc = rec + ((size_t)b * nb + c0) * GEO;
           for (int i = tid; i < nbc * GEO; i += blockDim.x) lds_rec[i] = gsrc[i];
         }
         __syncthreads();
         for (int ib = 0; ib < nbc; ++ib) {
           const R* L = lds_rec + ib * GEO;
-          const R bgeo = L[lane], bq = L[80 + lane];
-          const R o2 = L[64 + li];
-          // -o_i (half of the [-2o 1] operand) and q_b of column li
+          // -o_i and q_b of column li
           R mo[3], qb[3];
-#pragma unroll
-          for (int i = 0; i < 3; ++i) {
-            mo[i] = R(0.5) * L[16 * i + li];
-            qb[i] = SDL ? R(0) : L[80 + 16 * i + li];
-          }
-          const V zero = {R(0), R(0), R(0), R(0)};
           V r2[RB], df[RB], dr[RB], dfn[SDL ? RB : 1], drn[SDL ? RB : 1];
+          if constexpr (X3) {
+            const u4* LB = reinterpret_cast<const u4*>(L);
+            const u4 bgeo = LB[lane];
 #pragma unroll
-          for (int rb = 0; rb < RB; ++rb) {
-            r2[rb] = SS::mma(aop[rb], bgeo, V{o2, o2, o2, o2});
-            if (NF) df[rb] = SS::mma(a1[rb], bq, zero);
-            dr[rb] = SS::mma(a3[rb], bgeo, zero);
-            if constexpr (SDL) {
-              if (NF) dfn[rb] = SS::mma(a1[rb], L[144 + lane], zero);
-              drn[rb] = SS::mma(a4[rb], bgeo, zero);
+            for (int i = 0; i < 3; ++i) {
+              mo[i] = L[SdlX3::MO + 16 * i + li];
+              qb[i] = R(0);
+            }
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+              r2[rb] = mma_x3(aop[rb], bgeo);
+              if (NF) df[rb] = mma_x3(a1[rb], LB[64 + lane]);
+              dr[rb] = mma_x3(a3[rb], bgeo);
+              if (NF) dfn[rb] = mma_x3(a1[rb], LB[128 + lane]);
+              drn[rb] = mma_x3(a4[rb], bgeo);
+            }
+          } else {
+            const R bgeo = L[lane], bq = L[80 + lane];
+            const R o2 = L[64 + li];
+            // -o_i is half of the [-2o 1] operand
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+              mo[i] = R(0.5) * L[16 * i + li];
+              qb[i] = SDL ? R(0) : L[80 + 16 * i + li];
+            }
+            const V zero = {R(0), R(0), R(0), R(0)};
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+              r2[rb] = SS::mma(aop[rb], bgeo, V{o2, o2, o2, o2});
+              if (NF) df[rb] = SS::mma(a1[rb], bq, zero);
+              dr[rb] = SS::mma(a3[rb], bgeo, zero);
+              if constexpr (SDL) {
+                if (NF) dfn[rb] = SS::mma(a1[rb], L[144 + lane], zero);
+                drn[rb] = SS::mma(a4[rb], bgeo, zero);
+              }
             }
           }
           R rv[C];
@@ -494,6 +555,12 @@ sbie_status launch_stokes_pairs(sbie_geom* g, const double* d_dens, hipStream_t 
 }
 
 }  // namespace
+
+size_t stokes_record_doubles(bool sdl) {
+  // the FP64 layouts, and the stresslet's three-piece one in floats
+  constexpr int x3 = SdlX3::SIZE / 2;
+  return sdl ? (size_t)(kSDGeo > x3 ? kSDGeo : x3) : (size_t)kSGeo;
+}
 
 int stokes_row_groups(int T, bool fp64) {
   const int nb = (T + 15) / 16;

@@ -207,7 +207,7 @@ struct sbie_geom {
   double* d_stk_self = nullptr;   // [4][N]
   double* d_stk_near = nullptr;   // [kStokesNearSplit][4][N] near partials per source-list range
   double* d_stk_io = nullptr;     // [7][N] staging of host densities and velocities
-  double* d_stk_prec = nullptr;   // [M][T16/16][160] source blocks of the pair kernel (FP64 or FP32)
+  double* d_stk_prec = nullptr;   // [M][T16/16][stokes_record_doubles] source blocks of the pair kernel
   double* d_stk_rev = nullptr;    // reverse sums of one pair-kernel launch (stk_rev_bytes)
   double* d_stk_racc = nullptr;   // [4][N] running reverse totals
   uint64_t stk_rev_bytes = 0;
@@ -222,7 +222,7 @@ struct sbie_geom {
   double* d_sdl_self = nullptr;   // [3][N]
   double* d_sdl_near = nullptr;   // [kStokesNearSplit][3][N] near partials per source-list range
   double* d_sdl_io = nullptr;     // [6][N] host staging
-  double* d_sdl_prec = nullptr;   // [M][T16/16][208] source blocks of the stresslet pair kernel
+  double* d_sdl_prec = nullptr;   // [M][T16/16][stokes_record_doubles] source blocks of the stresslet pair kernel
   double* d_sdl_rev = nullptr;    // reverse sums of one stresslet pair-kernel launch (sdl_rev_bytes)
   double* d_sdl_racc = nullptr;   // [3][N] running reverse totals
   uint64_t sdl_rev_bytes = 0;
@@ -321,6 +321,9 @@ int stokes_row_groups(int T, bool fp64);
 int stokes_rev_slots(int M, int T, int C, int bytes_per_value, uint64_t cap_bytes);
 int stokes_pair_splits(const sbie_geom* g, int RG);
 uint64_t stokes_rev_bytes(int M, int T);
+// doubles per 16-source block of the Stokeslet (or stresslet) pair kernel's
+// source records, the larger of the FP64 and the mixed (three-piece) layouts
+size_t stokes_record_doubles(bool sdl);
 sbie_status far_stokes_pairs(sbie_geom* g, int C, bool mixed, const double* d_dens, hipStream_t s);
 // The Stokes double layer's far field (the stresslet) through the same pair
 // kernel: forward sums into d_sdl_part's first stokes_pair_splits slices,

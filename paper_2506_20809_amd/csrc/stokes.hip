@@ -447,7 +447,7 @@ sbie_status carve_stokes(sbie_geom* g, Carver& c) {
   // the pair kernel's source blocks, reverse sums and totals
   const size_t nb = (size_t)(g->T + 15) / 16;
   g->stk_rev_bytes = stokes_rev_bytes(g->M, g->T);
-  SBIE_TRY_C(c.take(&g->d_stk_prec, (size_t)g->M * nb * 160));
+  SBIE_TRY_C(c.take(&g->d_stk_prec, (size_t)g->M * nb * stokes_record_doubles(false)));
   SBIE_TRY_C(c.take(&g->d_stk_rev, (size_t)(g->stk_rev_bytes / sizeof(double))));
   SBIE_TRY_C(c.take(&g->d_stk_racc, 4 * N));
   return SBIE_OK;

@@ -428,7 +428,7 @@ sbie_status carve_sdl(sbie_geom* g, Carver& c) {
   // the pair kernel's source blocks, reverse sums and totals
   const size_t nb = (size_t)(g->T + 15) / 16;
   g->sdl_rev_bytes = stokes_rev_bytes(g->M, g->T);
-  SBIE_TRY_D(c.take(&g->d_sdl_prec, (size_t)g->M * nb * 208));
+  SBIE_TRY_D(c.take(&g->d_sdl_prec, (size_t)g->M * nb * stokes_record_doubles(true)));
   SBIE_TRY_D(c.take(&g->d_sdl_rev, (size_t)(g->sdl_rev_bytes / sizeof(double))));
   SBIE_TRY_D(c.take(&g->d_sdl_racc, 3 * (size_t)N));
   return SBIE_OK;
@@ -511,12 +511,11 @@ sbie_status apply_stokes_dl(sbie_geom* g, int prec, const double* d_dens, double
   }
   if (timed) SBIE_HIP(hipEventRecord(ev[7], s));
   if (timed) SBIE_HIP(hipEventRecord(ev[3], s));
-  // far field: in FP64 the pair-symmetric matrix-core kernel (T >= 32), else
-  // the one-sided vector-unit sum.  (At 256 spheroids the pair kernel took
-  // 8.35 against 9.02 ms in FP64, but 4.21 against 4.00 ms in mixed precision,
-  // where its five FP32 products per tile cost more than the vector work they
-  // save.)
-  const bool pairs = T >= 32 && !mixed;
+  // far field: the pair-symmetric matrix-core kernel (T >= 32), else the
+  // one-sided vector-unit sum.  (At 256 spheroids the pair kernel took 8.35
+  // against 9.02 ms in FP64 and, with three-piece bf16 products, 3.46 against
+  // 3.95 ms in mixed precision; with FP32 products it took 4.21 ms there.)
+  const bool pairs = T >= 32;
   if ((parts & SBIE_PARTS_FAR) && pairs) {
     SBIE_TRY_D(far_sdl_pairs(g, mixed, d_dens, s));
   } else if (parts & SBIE_PARTS_FAR) {

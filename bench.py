@@ -767,7 +767,8 @@ def main():
     ap.add_argument("--tree-sweep", action="store_true",
                     help="add the FP64 tree's accuracy and time over several (theta, order)")
     ap.add_argument("--only-stokes", action="store_true",
-                    help="only the Stokes single layer and its pressure (both precisions), for profiling")
+                    help="only the Stokes single layer, with its pressure, and the double layer (both precisions), "
+                         "for profiling")
     ap.add_argument("--only-near", action="store_true",
                     help="run only the near-field section (for counter runs); prints its JSON object")
     ap.add_argument("--only-targets", action="store_true",
@@ -828,7 +829,7 @@ def main():
     if args.only_stokes:
         ctx = sbie.Context(0)
         print(json.dumps({f"stokes_op{op}": {pr: run_stokes(ctx, max(2, args.steps // 2), 1, pr, op=op)
-                                              for pr in ("fp64", "mixed")} for op in (2, 5)}), flush=True)
+                                              for pr in ("fp64", "mixed")} for op in (2, 5, 6)}), flush=True)
         ctx.close()
         return
     geom = workloads.geometry(args.workload)

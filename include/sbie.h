@@ -220,7 +220,9 @@ sbie_status sbie_geom_timing(sbie_geom* g, sbie_timing* out);
    gradient grad [npts][3] (Eq. (dSLevalformula) and its analogue for D).
    Each (point, source particle) pair is near iff the exact distance from the
    point to the source surface is below eta * diam(source): near sources
-   contribute their exterior expansion, far ones the smooth quadrature.
+   contribute their exterior expansion, far ones the smooth quadrature.  With
+   SBIE_MIXED only the far sums run in FP32; the transform and the expansions
+   are FP64 in both precisions.
    Pointers as in sbie_apply; work buffers are allocated for the call, which
    returns after completion.  SBIE_E_OVERLAP if a point lies inside (or on) a
    particle, SBIE_E_INVALID for other ops or npts outside [0, 2^31]. */

@@ -436,7 +436,11 @@ sbie_status eval_targets(sbie_geom* g, int op, int prec, const double* d_dens, i
   const int nop = op == SBIE_OP_S ? SBIE_OP_SP : SBIE_OP_DP;  // records and exterior coefficients of S / D
   sbie_status st = normal_records(g, nop, prec, d_dens, s);
   if (st) return st;
-  if ((st = normal_expansions(g, nop, prec, s))) return st;
+  // The exterior coefficients come from the FP64 transform in both
+  // precisions: evaluated close to a surface, the expansions' gradients
+  // magnify the compensated FP32 transform's error in the high orders about
+  // tenfold, and the transform is a small share of the call.
+  if ((st = normal_expansions(g, nop, SBIE_FP64, s))) return st;
   const int words = g->excl_words;
   const int nsplit = target_splits(g, n);
   double* tx = w.xyz;

@@ -4,7 +4,8 @@ C ABI, against the oracle.
 
 Bars: FP64 relative l2 and max-norm <= 1e-10 per part and for the sum; mixed
 1e-6 (max-norm 1e-5).  At full size (256 spheroids, p = 12): rigid motions of
-every particle give -mu/2 at every node, and sampled nodes match the oracle.
+every particle give -mu/2 at every node, and sampled nodes match the oracle
+(FP64 at 1e-10, mixed at the mixed bars).
 """
 import numpy as np
 import pytest
@@ -120,4 +121,11 @@ def test_c4_full_size_sampled(ctx):
     tg = np.sort(np.random.default_rng(13).choice(g.N, 12, replace=False))
     ref = oracle.stokes_dl_apply(geom, p, dens, targets=tg)
     assert np.max(np.abs(u[:, tg] - ref)) < TOL64 * np.max(np.abs(ref))
+    # mixed precision, in the launch configuration the benchmark times (the
+    # pair kernel's three-piece products)
+    um = g.apply(OP, torch.tensor(dens, device="cuda"), precision=sbie.SBIE_MIXED)
+    g.sync()
+    um = um.cpu().numpy()
+    assert _rel(um[:, tg], ref) < 1e-6, _rel(um[:, tg], ref)
+    assert np.max(np.abs(um[:, tg] - ref)) < 1e-5 * np.max(np.abs(ref))
     g.close()

@@ -3,10 +3,8 @@ particle-to-target variant of Algorithm 1; Eq. (dSLevalformula)) through the C
 ABI, against the oracle.
 
 Bars: FP64 value and gradient within 1e-10 of the oracle's (max-norm relative
-to the largest value resp. gradient); mixed values relative l2 <= 1e-6, mixed
-gradients <= 1e-5 (the far-field gradient of D sums FP32 terms of size q/r^3
-that cancel over each source surface, which costs about one more digit than
-the values; measured 2e-6).  Green's
+to the largest value resp. gradient); mixed values and gradients relative l2
+<= 1e-6 (mixed runs only the far sums in FP32).  Green's
 representation for data harmonic inside the particles is checked on the GPU
 alone at p = 16.
 """
@@ -103,7 +101,7 @@ def test_mixed(ctx, op):
     rv, rg, _ = oracle.eval_targets(geom, p, op, dens, pts)
     val, grad = g.eval_targets(op, dens, pts, precision=sbie.SBIE_MIXED)
     assert np.linalg.norm(val - rv) / np.linalg.norm(rv) < 1e-6
-    assert np.linalg.norm(grad - rg) / np.linalg.norm(rg) < 1e-5
+    assert np.linalg.norm(grad - rg) / np.linalg.norm(rg) < 1e-6, np.linalg.norm(grad - rg) / np.linalg.norm(rg)
     g.close()
 
 
@@ -156,6 +154,7 @@ def test_c3_full_size_sampled(ctx, precision):
         _check(val[sel], grad[sel], rv, rg, TOL64)
     else:
         assert np.linalg.norm(val[sel] - rv) / np.linalg.norm(rv) < 1e-6
+        assert np.linalg.norm(grad[sel] - rg) / np.linalg.norm(rg) < 1e-6
     g.close()
 
 

@@ -519,8 +519,12 @@ sbie_status apply_stokes(sbie_geom* g, int prec, const double* d_dens, double* d
   SBIE_HIP(hipGetLastError());
   if (timed) SBIE_HIP(hipEventRecord(ev[1], s));
   if (parts & (SBIE_PARTS_SELF | SBIE_PARTS_NEAR)) {
-    // forward transforms of the four densities per particle (rows i*4 + s)
-    if ((st = gemm(mixed, g->d_stk_f, T, g->d_An, g->d_An32, K, g->d_stk_c, K, 4 * M, K, T, s)) != SBIE_OK)
+    // forward transforms of the four densities per particle (rows i*4 + s).
+    // The transforms run in FP64 in both precisions: the compensated FP32
+    // form took as long here (0.52 against 0.51 ms per apply at 256 spheroids)
+    // and its error, magnified where the three terms of the Stokeslet cancel,
+    // set the mixed path's error on the surface.
+    if ((st = gemm(false, g->d_stk_f, T, g->d_An, g->d_An32, K, g->d_stk_c, K, 4 * M, K, T, s)) != SBIE_OK)
       return st;
     hipLaunchKernelGGL(k_stokes_scale, dim3(cdiv((int64_t)MK4, B)), dim3(B), 0, s, g->d_stk_c, g->d_lam, g->d_dlr,
                        M, p, g->d_stk_E, g->d_stk_E + MK4);
@@ -561,12 +565,12 @@ sbie_status stokes_parts(sbie_geom* g, bool mixed, hipStream_t s, uint32_t parts
   {
     if (parts & SBIE_PARTS_SELF) {
       double* U = g->d_stk_U;
-      if ((st = gemm(mixed, g->d_stk_E, K, g->d_Sy, g->d_Sy32, T, U, T, 4 * M, T, K, s)) != SBIE_OK) return st;
-      if ((st = gemm(mixed, g->d_stk_E + MK4, K, g->d_Sy, g->d_Sy32, T, U + MT4, T, 4 * M, T, K, s)) != SBIE_OK)
+      if ((st = gemm(false, g->d_stk_E, K, g->d_Sy, g->d_Sy32, T, U, T, 4 * M, T, K, s)) != SBIE_OK) return st;
+      if ((st = gemm(false, g->d_stk_E + MK4, K, g->d_Sy, g->d_Sy32, T, U + MT4, T, 4 * M, T, K, s)) != SBIE_OK)
         return st;
-      if ((st = gemm(mixed, g->d_stk_E, K, g->d_Sv, g->d_Sv32, T, U + 2 * MT4, T, 4 * M, T, K, s)) != SBIE_OK)
+      if ((st = gemm(false, g->d_stk_E, K, g->d_Sv, g->d_Sv32, T, U + 2 * MT4, T, 4 * M, T, K, s)) != SBIE_OK)
         return st;
-      if ((st = gemm(mixed, g->d_stk_E, K, g->d_Sp, g->d_Sp32, T, U + 3 * MT4, T, 4 * M, T, K, s)) != SBIE_OK)
+      if ((st = gemm(false, g->d_stk_E, K, g->d_Sp, g->d_Sp32, T, U + 3 * MT4, T, 4 * M, T, K, s)) != SBIE_OK)
         return st;
       hipLaunchKernelGGL(k_stokes_self<C>, dim3(cdiv(N, B)), dim3(B), 0, s, g->d_part, g->d_gl, g->d_x, g->d_y,
                          g->d_z, g->d_stk_U, M, p, N, g->d_stk_self);

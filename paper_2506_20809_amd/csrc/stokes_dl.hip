@@ -484,7 +484,8 @@ sbie_status apply_stokes_dl(sbie_geom* g, int prec, const double* d_dens, double
   SBIE_HIP(hipGetLastError());
   if (timed) SBIE_HIP(hipEventRecord(ev[1], s));
   if (parts & (SBIE_PARTS_SELF | SBIE_PARTS_NEAR)) {
-    if ((st = gemm(mixed, g->d_sdl_f, T, g->d_An, g->d_An32, K, g->d_sdl_c, K, kSets * M, K, T, s)) != SBIE_OK)
+    // FP64 transforms in both precisions, as for the single layer
+    if ((st = gemm(false, g->d_sdl_f, T, g->d_An, g->d_An32, K, g->d_sdl_c, K, kSets * M, K, T, s)) != SBIE_OK)
       return st;
     hipLaunchKernelGGL(k_sdl_scale, dim3(cdiv((int64_t)MK, B)), dim3(B), 0, s, g->d_sdl_c, g->d_lam, g->d_dlr, M,
                        p, g->d_sdl_E, g->d_sdl_E + MK);
@@ -492,11 +493,11 @@ sbie_status apply_stokes_dl(sbie_geom* g, int prec, const double* d_dens, double
   }
   if (parts & SBIE_PARTS_SELF) {
     double* U = g->d_sdl_U;
-    if ((st = gemm(mixed, g->d_sdl_E + MK, K, g->d_Sy, g->d_Sy32, T, U, T, kSets * M, T, K, s)) != SBIE_OK)
+    if ((st = gemm(false, g->d_sdl_E + MK, K, g->d_Sy, g->d_Sy32, T, U, T, kSets * M, T, K, s)) != SBIE_OK)
       return st;
-    if ((st = gemm(mixed, g->d_sdl_E, K, g->d_Sv, g->d_Sv32, T, U + MT, T, kSets * M, T, K, s)) != SBIE_OK)
+    if ((st = gemm(false, g->d_sdl_E, K, g->d_Sv, g->d_Sv32, T, U + MT, T, kSets * M, T, K, s)) != SBIE_OK)
       return st;
-    if ((st = gemm(mixed, g->d_sdl_E, K, g->d_Sp, g->d_Sp32, T, U + 2 * MT, T, kSets * M, T, K, s)) != SBIE_OK)
+    if ((st = gemm(false, g->d_sdl_E, K, g->d_Sp, g->d_Sp32, T, U + 2 * MT, T, kSets * M, T, K, s)) != SBIE_OK)
       return st;
     hipLaunchKernelGGL(k_sdl_self, dim3(cdiv(N, B)), dim3(B), 0, s, g->d_part, g->d_gl, g->d_x, g->d_y, g->d_z,
                        d_dens, U, M, p, N, g->d_sdl_self);

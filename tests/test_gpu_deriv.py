@@ -3,7 +3,7 @@ the principal value of Theorem 3, D' continuous) and the single-layer Neumann
 solve (Eq. (neusol)) through the C ABI, against the oracle.
 
 Bars as for S and D: FP64 relative l2 and max-norm <= 1e-10 per part and for
-the sum; mixed relative l2 <= 1e-6 and max-norm <= 1e-5.  The Neumann solve:
+the sum; mixed relative l2 <= 1e-6 and max-norm <= 1e-6.  The Neumann solve:
 iterations within one of the oracle's GMRES, density within 1e-8.
 """
 import numpy as np
@@ -101,7 +101,7 @@ def test_mixed_parity(ctx, op):
     for name, p in [("c1", 8), ("c2", 16)]:
         geom = workloads.geometry(name)
         g = sbie.Geometry(ctx, geom, p)
-        _check_parts(g, geom, p, op, workloads.density(name)[0], tol=1e-6, max_tol=1e-5,
+        _check_parts(g, geom, p, op, workloads.density(name)[0], tol=1e-6, max_tol=1e-6,
                      precision=sbie.SBIE_MIXED, label=f"mixed {name} op={op}")
         g.close()
 

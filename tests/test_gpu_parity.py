@@ -53,7 +53,9 @@ def _check_parts(g, geom, p, op, dens, tol=TOL64, label="", precision=0, max_tol
             assert np.max(np.abs(u)) < 1e-13, (label, name)
             continue
         assert _rel(u, r) < tol, (label, name, _rel(u, r))
-        assert np.max(np.abs(u - r)) < max_tol * scale, (label, name, np.max(np.abs(u - r)) / scale)
+        # the result (all parts) in max-norm at the l2 bar; a part alone at max_tol
+        mt = min(tol, max_tol) if name == "all" else max_tol
+        assert np.max(np.abs(u - r)) < mt * scale, (label, name, np.max(np.abs(u - r)) / scale)
 
 
 def _ellipsoid_on_surface(g, geom, p):
@@ -331,6 +333,10 @@ def test_c3_full_size_sampled(ctx, op):
 
 # ---------------------------------------------------------------- mixed precision (FP32 sums, FP64 geometry)
 
+# Mixed bar: relative l2 and max-norm 1e-6 of the result.  A part on its own
+# (the far field alone, a small share of the result) is held to 1e-6 in l2 and
+# 1e-5 of its own maximum in max-norm: the single layer's far part alone
+# reaches 1.5e-6 of its maximum on the small suspensions.
 TOL_MIXED = 1e-6
 
 
@@ -396,7 +402,7 @@ def _c3_reference(op):
 @pytest.mark.parametrize("op", [0, 1])
 def test_c3_full_size_every_node(ctx, op):
     """512 spheroids, p = 16: FP64 within 1e-10 and mixed within 1e-6 (relative
-    l2; max-norm 1e-10 and 1e-5 of the result's max) at all 295936 nodes."""
+    l2; max-norm 1e-10 and 1e-6 of the result's max) at all 295936 nodes."""
     import torch
 
     import paper_2506_20809_amd as sbie
@@ -409,7 +415,7 @@ def test_c3_full_size_every_node(ctx, op):
     g = sbie.Geometry(ctx, geom, p)
     d = torch.tensor(dens, device="cuda")
     scale = np.max(np.abs(ref))
-    for prec, tol, mtol in ((sbie.SBIE_FP64, TOL64, TOL64), (sbie.SBIE_MIXED, TOL_MIXED, 1e-5)):
+    for prec, tol, mtol in ((sbie.SBIE_FP64, TOL64, TOL64), (sbie.SBIE_MIXED, TOL_MIXED, TOL_MIXED)):
         u = g.apply(op, d, precision=prec)
         g.sync()
         u = u.cpu().numpy()

@@ -69,14 +69,19 @@ struct Mfma<double> {
   }
 };
 
-// per-apply strengths (app).  The mixed single and double layers keep their B
-// operands in the three-piece form, one u4 per lane; all others one R per
-// lane, the accumulator input per column after the B operand.
+// Values per 16-source block of the geometry records (geo) and the per-apply
+// strengths (app), in HBM (GEO_G, APP_G) and as staged in LDS (GEO, APP).  In
+// HBM every block holds one R per lane of its B operands and the accumulator
+// input per column after them.  The mixed single and double layers take their
+// products in the three-piece form: the staging splits each B operand into
+// one u4 per lane, so that HBM holds the compact FP32 values only.
 template <typename R, int OP>
 struct FarLayout {
   static constexpr bool X3 = sizeof(R) == 4 && (OP == SBIE_OP_S || OP == SBIE_OP_D);
-  static constexpr int GEO = X3 ? 256 : 80;
-  static constexpr int APP = OP == SBIE_OP_S ? 16 : (OP == SBIE_OP_SP ? 128 : (X3 ? 256 : 80));
+  static constexpr int GEO_G = 80;
+  static constexpr int APP_G = OP == SBIE_OP_S ? 16 : (OP == SBIE_OP_SP ? 128 : 80);
+  static constexpr int GEO = X3 ? 256 : GEO_G;
+  static constexpr int APP = X3 && OP == SBIE_OP_D ? 256 : APP_G;
 };
 
 constexpr int kChunk = 40;  // 16-source blocks staged in LDS at a time
@@ -139,7 +144,7 @@ __device__ __forceinline__ void far_pairs_body(const R* __restrict__ geo, const 
   constexpr bool X3 = L::X3;
   using AOp = typename std::conditional<X3, u4, R>::type;  // A operand of one row block
   using BOp = typename std::conditional<X3, u4, R>::type;  // B operand of one source block
-  constexpr int GEO = L::GEO, APP = L::APP;
+  constexpr int GEO = L::GEO, APP = L::APP, GEO_G = L::GEO_G, APP_G = L::APP_G;
   constexpr bool NORMALS = OP == SBIE_OP_SP || OP == SBIE_OP_DP;  // rows carry their normals
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* lds_geo = reinterpret_cast<R*>(smem_raw);
@@ -205,12 +210,10 @@ __device__ __forceinline__ void far_pairs_body(const R* __restrict__ geo, const 
     const size_t blk = (size_t)a * nb + (rb < nrb ? bk : 0);
     R dv = R(0);
     if (rb < nrb && lg < 3) {
-      if constexpr (X3 && OP == SBIE_OP_D)
-        dv = join_b(reinterpret_cast<const u4*>(app + blk * APP)[16 * lg + li]);
-      else if constexpr (OP == SBIE_OP_D || OP == SBIE_OP_DP)
-        dv = app[blk * APP + 16 * lg + li];
+      if constexpr (OP == SBIE_OP_D || OP == SBIE_OP_DP)
+        dv = app[blk * APP_G + 16 * lg + li];
       else if constexpr (OP == SBIE_OP_SP)
-        dv = app[blk * APP + 64 + 16 * lg + li];
+        dv = app[blk * APP_G + 64 + 16 * lg + li];
     }
     if constexpr (STASH) {
       lds_tc[rb * 64] = tv;
@@ -304,12 +307,38 @@ __device__ __forceinline__ void far_pairs_body(const R* __restrict__ geo, const 
       {
         using C16 = typename std::conditional<sizeof(R) == 4, float4, double2>::type;
         constexpr int PER = 16 / sizeof(R);
-        const C16* gs = reinterpret_cast<const C16*>(geo + ((size_t)b * nb + c0) * GEO);
-        C16* ld = reinterpret_cast<C16*>(lds_geo);
-        for (int i = tid; i < nbc * GEO / PER; i += blockDim.x) ld[i] = gs[i];
-        const C16* as = reinterpret_cast<const C16*>(app + ((size_t)b * nb + c0) * APP);
-        C16* la = reinterpret_cast<C16*>(lds_app);
-        for (int i = tid; i < nbc * APP / PER; i += blockDim.x) la[i] = as[i];
+        // a block's B operand in the three-piece form: lane 16k + j takes term k
+        // of column j and the column's accumulator input (value 64 + j); one
+        // thread per column
+        auto stage_x3 = [&](const R* src, R* dst) {
+          u4* ld = reinterpret_cast<u4*>(dst);
+          for (int i = tid; i < nbc * 16; i += blockDim.x) {
+            const R* r = src + (i >> 4) * 80;
+            const int j = i & 15;
+            const float xk[4] = {(float)r[j], (float)r[16 + j], (float)r[32 + j], (float)r[48 + j]};
+            u4 o[4];
+            split_b_column(xk, (float)r[64 + j], o);
+            u4* d = ld + (i >> 4) * 64 + j;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) d[16 * k] = o[k];
+          }
+        };
+        const R* gsrc = geo + ((size_t)b * nb + c0) * GEO_G;
+        if constexpr (X3) {
+          stage_x3(gsrc, lds_geo);
+        } else {
+          const C16* gs = reinterpret_cast<const C16*>(gsrc);
+          C16* ld = reinterpret_cast<C16*>(lds_geo);
+          for (int i = tid; i < nbc * GEO / PER; i += blockDim.x) ld[i] = gs[i];
+        }
+        const R* asrc = app + ((size_t)b * nb + c0) * APP_G;
+        if constexpr (X3 && OP == SBIE_OP_D) {
+          stage_x3(asrc, lds_app);
+        } else {
+          const C16* as = reinterpret_cast<const C16*>(asrc);
+          C16* la = reinterpret_cast<C16*>(lds_app);
+          for (int i = tid; i < nbc * APP / PER; i += blockDim.x) la[i] = as[i];
+        }
       }
       __syncthreads();
       // the tiles of source block ib for the first NR slots, unrolled so that
@@ -712,32 +741,8 @@ __global__ void k_far_records(const Particle* __restrict__ part, const double* _
   b[64] = (R)fma(oz, oz, fma(oy, oy, ox * ox));
 }
 
-// The same operands in the three-piece form (mixed single and double layers):
-// block b of particle s holds, at (s*nb + b)*256, one u4 per lane 16k + j with
-// term k of [-2o_j 1] and the extra term |o_j|^2.
-__global__ void k_far_records_x3(const Particle* __restrict__ part, const double* __restrict__ x,
-                                 const double* __restrict__ y, const double* __restrict__ z, int M, int T, int T16,
-                                 float* __restrict__ geo) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)M * T16) return;
-  const int s = (int)(t / T16), q = (int)(t - (int64_t)s * T16);
-  double ox = 0.0, oy = 0.0, oz = 0.0;
-  if (q < T) {
-    const int64_t g = (int64_t)s * T + q;
-    ox = x[g] - part[s].c[0];
-    oy = y[g] - part[s].c[1];
-    oz = z[g] - part[s].c[2];
-  }
-  const float o2 = (float)fma(oz, oz, fma(oy, oy, ox * ox));
-  u4* b = reinterpret_cast<u4*>(geo + (t / 16) * 256) + (t % 16);
-  b[0] = split_b((float)(-2.0 * ox), 0, o2);
-  b[16] = split_b((float)(-2.0 * oy), 1, o2);
-  b[32] = split_b((float)(-2.0 * oz), 2, o2);
-  b[48] = split_b(1.0f, 3, o2);
-}
-
 // Per-apply source strengths: S W sigma per source; D per block (W mu nu, 0) in
-// lane order and -W mu nu.o (in mixed precision both in the three-piece form);
+// lane order and -W mu nu.o;
 // S' per block (-2 q o, q) and (nu, -nu.o) in lane order, q = W sigma; D' per
 // block (nu, -nu.o) in lane order and q = W mu.
 template <typename R, int OP>
@@ -801,22 +806,12 @@ __global__ void k_far_strengths(const Particle* __restrict__ part, const double*
       const double ox = x[g] - part[s].c[0], oy = y[g] - part[s].c[1], oz = z[g] - part[s].c[2];
       dot = fma(dz, oz, fma(dy, oy, dx * ox));
     }
-    if constexpr (FarLayout<R, OP>::X3) {
-      // three-piece form: term k of [d 0] with the extra term -d.o
-      const float e = (float)(-dot);
-      u4* b = reinterpret_cast<u4*>(app + (t / 16) * 256) + (t % 16);
-      b[0] = split_b((float)dx, 0, e);
-      b[16] = split_b((float)dy, 1, e);
-      b[32] = split_b((float)dz, 2, e);
-      b[48] = split_b(0.0f, 3, e);
-    } else {
-      R* b = app + (t / 16) * 80 + (t % 16);
-      b[0] = (R)dx;
-      b[16] = (R)dy;
-      b[32] = (R)dz;
-      b[48] = R(0);
-      b[64] = (R)(-dot);
-    }
+    R* b = app + (t / 16) * 80 + (t % 16);
+    b[0] = (R)dx;
+    b[16] = (R)dy;
+    b[32] = (R)dz;
+    b[48] = R(0);
+    b[64] = (R)(-dot);
   }
 }
 
@@ -856,8 +851,8 @@ sbie_status launch_strengths(sbie_geom* g, int op, const double* d_dens, R* app,
 }
 
 template <typename R>
-sbie_status launch_far(sbie_geom* g, int op, const double* d_dens, const R* geo, const R* geo_x3, R* app,
-                       hipStream_t s, hipEvent_t ev_begin, hipEvent_t ev_end) {
+sbie_status launch_far(sbie_geom* g, int op, const double* d_dens, const R* geo, R* app, hipStream_t s,
+                       hipEvent_t ev_begin, hipEvent_t ev_end) {
   const int64_t n16 = (int64_t)g->M * g->T16;
   const dim3 pre(cdiv(n16, 256)), blk(256);
   if (op == SBIE_OP_S)
@@ -891,8 +886,6 @@ sbie_status launch_far(sbie_geom* g, int op, const double* d_dens, const R* geo,
   if (op == SBIE_OP_D && FarLayout<R, SBIE_OP_D>::X3)  // the double layer's row stash
     lds += (size_t)(wg.x / 64) * PS::RBMAX * 64 * (sizeof(double) + sizeof(R));
   R* rev = reinterpret_cast<R*>(g->d_rev);
-  const R* geo_s = FarLayout<R, SBIE_OP_S>::X3 ? geo_x3 : geo;
-  const R* geo_d = FarLayout<R, SBIE_OP_D>::X3 ? geo_x3 : geo;
   const int KS = g->rev_slots, PMAX = (g->M - 1) / 2 + ((g->M & 1) == 0 ? 1 : 0);
   const int nsplit = far_launch_splits(g, RG);
   const dim3 fold((unsigned)cdiv(g->N, 256));
@@ -901,7 +894,7 @@ sbie_status launch_far(sbie_geom* g, int op, const double* d_dens, const R* geo,
   for (int kbase = 0; kbase == 0 || kbase < PMAX; kbase += KS) {
     const int kend = kbase + KS, first = kbase == 0 ? 1 : 0;
     if (op == SBIE_OP_S)
-      hipLaunchKernelGGL((k_far_pairs<R, SBIE_OP_S>), grid, wg, lds, s, geo_s, app, g->d_part, g->d_x, g->d_y,
+      hipLaunchKernelGGL((k_far_pairs<R, SBIE_OP_S>), grid, wg, lds, s, geo, app, g->d_part, g->d_x, g->d_y,
                          g->d_z, g->d_excl, g->excl_words, g->M, g->T, g->T16, g->N, nsplit, RG, kbase, kend, first,
                          g->d_partial, rev);
     else if (op == SBIE_OP_SP)
@@ -913,7 +906,7 @@ sbie_status launch_far(sbie_geom* g, int op, const double* d_dens, const R* geo,
                          g->d_z, g->d_excl, g->excl_words, g->M, g->T, g->T16, g->N, nsplit, RG, kbase, kend, first,
                          g->d_partial, rev);
     else
-      hipLaunchKernelGGL((k_far_pairs<R, SBIE_OP_D>), grid, wg, lds, s, geo_d, app, g->d_part, g->d_x, g->d_y,
+      hipLaunchKernelGGL((k_far_pairs<R, SBIE_OP_D>), grid, wg, lds, s, geo, app, g->d_part, g->d_x, g->d_y,
                          g->d_z, g->d_excl, g->excl_words, g->M, g->T, g->T16, g->N, nsplit, RG, kbase, kend, first,
                          g->d_partial, rev);
     SBIE_HIP(hipGetLastError());
@@ -963,17 +956,14 @@ sbie_status far_records(sbie_geom* g, hipStream_t s) {
   hipLaunchKernelGGL(k_far_records<double>, dim3(cdiv(n, 256)), dim3(256), 0, s, g->d_part, g->d_x, g->d_y, g->d_z,
                      g->M, g->T, g->T16, g->d_srec64);
   SBIE_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_far_records_x3, dim3(cdiv(n, 256)), dim3(256), 0, s, g->d_part, g->d_x, g->d_y, g->d_z,
-                     g->M, g->T, g->T16, g->d_srecx);
-  SBIE_HIP(hipGetLastError());
   return SBIE_OK;
 }
 
 sbie_status far_mfma(sbie_geom* g, int op, int prec, const double* d_dens, hipStream_t s, hipEvent_t ev_begin,
                      hipEvent_t ev_end) {
   if (prec == SBIE_MIXED)
-    return launch_far<float>(g, op, d_dens, g->d_srec32, g->d_srecx, g->d_fstr32, s, ev_begin, ev_end);
-  return launch_far<double>(g, op, d_dens, g->d_srec64, nullptr, g->d_fstr64, s, ev_begin, ev_end);
+    return launch_far<float>(g, op, d_dens, g->d_srec32, g->d_fstr32, s, ev_begin, ev_end);
+  return launch_far<double>(g, op, d_dens, g->d_srec64, g->d_fstr64, s, ev_begin, ev_end);
 }
 
 bool far_batch_fits(const sbie_geom* g) {
@@ -990,8 +980,7 @@ int far_batch_job(const sbie_geom* g, int op, int prec, int wg_begin, FarJob* jo
   const bool mixed = prec == SBIE_MIXED;
   const int RG = far_row_groups(g, !mixed);
   const int nsplit = far_launch_splits(g, RG);
-  const bool x3 = mixed;  // the mixed S and D operands are the three-piece form
-  job->geo = mixed ? (x3 ? (const void*)g->d_srecx : (const void*)g->d_srec32) : (const void*)g->d_srec64;
+  job->geo = mixed ? (const void*)g->d_srec32 : (const void*)g->d_srec64;
   job->app = mixed ? (const void*)g->d_fstr32 : (const void*)g->d_fstr64;
   job->part = g->d_part;
   job->x = g->d_x;

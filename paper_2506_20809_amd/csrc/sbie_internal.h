@@ -251,12 +251,12 @@ struct sbie_geom {
   // operand in lane order ([k][j] at 16k+j; (-2 o_x, -2 o_y, -2 o_z, 1) for
   // source j, o = node - centre) followed by |o_j|^2, j = 0..15
   float* d_srec32 = nullptr;      // [M*T16*5]
-  float* d_srecx = nullptr;       // [M*T16*16] the FP32 records in the three-piece bf16 form
   double* d_srec64 = nullptr;
   // per-apply strengths per block: S 16 values W sigma_j at (s*nb + b)*16;
   // D 80 values at (s*nb + b)*80: (W mu nu_j, 0) in lane order, then -W mu nu_j.o_j
-  // (FP32: 256 words at (s*nb + b)*256, the three-piece form of both)
-  float* d_fstr32 = nullptr;      // [M*T16*16] per-apply far strengths (S 1, D 16, S' 8 per source)
+  // (the mixed S and D kernels split them into the three-piece form as they
+  // stage them in LDS)
+  float* d_fstr32 = nullptr;      // [M*T16*8] per-apply far strengths (S 1, D 5, S' 8 per source)
   double* d_fstr64 = nullptr;     // [M*T16*8]
   double* d_rcp = nullptr;        // [kRcpN] reciprocals 1/k for the near-field recurrences
   // pair-symmetric far field, run as launches over chunks of rev_slots partner

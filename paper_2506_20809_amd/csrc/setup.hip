@@ -394,11 +394,9 @@ sbie_status carve_geometry(sbie_geom* g, Carver& c) {
   SBIE_TRY(c.take(&g->d_out, N));
   SBIE_TRY(c.take(&g->d_srec64, 5 * n16));
   SBIE_TRY(c.take(&g->d_srec32, 5 * n16));
-  SBIE_TRY(c.take(&g->d_srecx, 16 * n16));
-  // per-apply far strengths: up to 8 values per padded source (S') in FP64,
-  // 16 words in FP32 (the double layer's three-piece form)
+  // per-apply far strengths: up to 8 values per padded source (S')
   SBIE_TRY(c.take(&g->d_fstr64, 8 * n16));
-  SBIE_TRY(c.take(&g->d_fstr32, 16 * n16));
+  SBIE_TRY(c.take(&g->d_fstr32, 8 * n16));
   SBIE_TRY(c.take(&g->d_rcp, (size_t)kRcpN));
   // reverse sums of one launch of the pair-symmetric far field (matrix-core
   // path, T >= 32) and their running FP64 totals

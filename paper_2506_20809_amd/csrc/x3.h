@@ -53,6 +53,20 @@ __device__ inline u4 split_b(float x, int lg, float e) {
   return u4{h | m << 16, h | l << 16, h | m << 16, t};
 }
 
+// B operands of all four lane groups of one column: the terms x[k] and the
+// column's extra term e (split once), out[k] for lane group k
+__device__ inline void split_b_column(const float (&x)[4], float e, u4 (&out)[4]) {
+  unsigned eh, em, el;
+  split3(e, eh, em, el);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    unsigned h, m, l;
+    split3(x[k], h, m, l);
+    const unsigned t = k == 0 ? (eh | em << 16) : (k == 1 ? el : 0u);
+    out[k] = u4{h | m << 16, h | l << 16, h | m << 16, t};
+  }
+}
+
 // the FP32 value of a B operand's main term
 __device__ inline float join_b(u4 v) {
   const float h = __builtin_bit_cast(float, v.x << 16);

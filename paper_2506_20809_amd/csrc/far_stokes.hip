@@ -55,7 +55,8 @@ constexpr int kSGeo = 160;
 constexpr int kSDGeo = 208;
 
 // The stresslet's mixed path takes its products in the three-piece bf16 form
-// (x3.h); per 16-source block, in floats, the B operands as one u4 per lane:
+// (x3.h): its source blocks (kSDGeo floats in HBM) are split as they are
+// staged in LDS, per block, in floats, the B operands as one u4 per lane:
 // [-2o 1] with |o|^2 in its extra slots (0..255), [m -m.o] (256..511),
 // [nu -nu.o] (512..767); then -o_i per column [3][16].  (The Stokeslet keeps
 // the FP32 products: with them its far field is about three times closer to
@@ -64,6 +65,7 @@ struct SdlX3 {
   static constexpr int MO = 768, SIZE = 816;
 };
 
+// values per staged source block in LDS
 template <typename R, bool SDL>
 constexpr int stokes_geo() {
   return SDL ? (sizeof(R) == 4 ? SdlX3::SIZE : kSDGeo) : kSGeo;
@@ -163,23 +165,11 @@ __global__ void k_sdl_pair_records(const Particle* __restrict__ part, const doub
     nu[1] = ny[g];
     nu[2] = nz[g];
   }
-  const double o2 = o[0] * o[0] + o[1] * o[1] + o[2] * o[2];
-  const double mo = -(m[0] * o[0] + m[1] * o[1] + m[2] * o[2]);
-  const double no = -(nu[0] * o[0] + nu[1] * o[1] + nu[2] * o[2]);
-  if constexpr (sizeof(R) == 4) {
-    float* out = rec + blk * SdlX3::SIZE;
-    reinterpret_cast<u4*>(out)[lane] = split_b(lg < 3 ? (float)(-2.0 * o[lg]) : 1.0f, lg, (float)o2);
-    reinterpret_cast<u4*>(out + 256)[lane] = split_b(lg < 3 ? (float)m[lg] : (float)mo, lg, 0.0f);
-    reinterpret_cast<u4*>(out + 512)[lane] = split_b(lg < 3 ? (float)nu[lg] : (float)no, lg, 0.0f);
-    if (lg == 0)
-      for (int k = 0; k < 3; ++k) out[SdlX3::MO + 16 * k + li] = (float)(-o[k]);
-  } else {
-    R* out = rec + blk * kSDGeo;
-    out[lane] = lg < 3 ? (R)(-2.0 * o[lg]) : R(1);
-    out[80 + lane] = lg < 3 ? (R)m[lg] : (R)mo;
-    out[144 + lane] = lg < 3 ? (R)nu[lg] : (R)no;
-    if (lg == 0) out[64 + li] = (R)o2;
-  }
+  R* out = rec + blk * kSDGeo;
+  out[lane] = lg < 3 ? (R)(-2.0 * o[lg]) : R(1);
+  out[80 + lane] = lg < 3 ? (R)m[lg] : (R)(-(m[0] * o[0] + m[1] * o[1] + m[2] * o[2]));
+  out[144 + lane] = lg < 3 ? (R)nu[lg] : (R)(-(nu[0] * o[0] + nu[1] * o[1] + nu[2] * o[2]));
+  if (lg == 0) out[64 + li] = (R)(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]);
 }
 
 // The pair kernel.  Work index (XCD-ordered) -> (particle a, row group rg,
@@ -341,9 +331,30 @@ __global__ __launch_bounds__(64 * kSWaves) void k_far_stokes_pairs(
         const int nbc = nb - c0 < CH ? nb - c0 : CH;
         __syncthreads();  // the previous chunk's operands and reverse sums are consumed
         if constexpr (X3) {
-          const u4* gsrc = reinterpret_cast<const u4*>(rec + ((size_t)b * nb + c0) * GEO);
-          u4* dst = reinterpret_cast<u4*>(lds_rec);
-          for (int i = tid; i < nbc * (GEO / 4); i += blockDim.x) dst[i] = gsrc[i];
+          // one thread per source column: its three B operands in the
+          // three-piece form, and -o_i (half of the [-2o 1] operand)
+          const float* gsrc = rec + ((size_t)b * nb + c0) * kSDGeo;
+          for (int i = tid; i < nbc * 16; i += blockDim.x) {
+            const float* r = gsrc + (i >> 4) * kSDGeo;
+            const int j = i & 15;
+            float* L = lds_rec + (i >> 4) * GEO;
+            u4* LB = reinterpret_cast<u4*>(L) + j;
+            u4 ops[4];
+            const float g4[4] = {r[j], r[16 + j], r[32 + j], r[48 + j]};
+            split_b_column(g4, r[64 + j], ops);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) LB[16 * k] = ops[k];
+            const float m4[4] = {r[80 + j], r[96 + j], r[112 + j], r[128 + j]};
+            split_b_column(m4, 0.0f, ops);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) LB[64 + 16 * k] = ops[k];
+            const float n4[4] = {r[144 + j], r[160 + j], r[176 + j], r[192 + j]};
+            split_b_column(n4, 0.0f, ops);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) LB[128 + 16 * k] = ops[k];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) L[SdlX3::MO + 16 * k + j] = 0.5f * r[16 * k + j];
+          }
         } else {
           const R* gsrc = rec + ((size_t)b * nb + c0) * GEO;
           for (int i = tid; i < nbc * GEO; i += blockDim.x) lds_rec[i] = gsrc[i];
@@ -556,11 +567,7 @@ sbie_status launch_stokes_pairs(sbie_geom* g, const double* d_dens, hipStream_t 
 
 }  // namespace
 
-size_t stokes_record_doubles(bool sdl) {
-  // the FP64 layouts, and the stresslet's three-piece one in floats
-  constexpr int x3 = SdlX3::SIZE / 2;
-  return sdl ? (size_t)(kSDGeo > x3 ? kSDGeo : x3) : (size_t)kSGeo;
-}
+size_t stokes_record_doubles(bool sdl) { return sdl ? (size_t)kSDGeo : (size_t)kSGeo; }
 
 int stokes_row_groups(int T, bool fp64) {
   const int nb = (T + 15) / 16;

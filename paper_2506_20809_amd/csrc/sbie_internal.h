@@ -322,7 +322,7 @@ int stokes_rev_slots(int M, int T, int C, int bytes_per_value, uint64_t cap_byte
 int stokes_pair_splits(const sbie_geom* g, int RG);
 uint64_t stokes_rev_bytes(int M, int T);
 // doubles per 16-source block of the Stokeslet (or stresslet) pair kernel's
-// source records, the larger of the FP64 and the mixed (three-piece) layouts
+// source records (FP64 values; the mixed path's FP32 values use half)
 size_t stokes_record_doubles(bool sdl);
 sbie_status far_stokes_pairs(sbie_geom* g, int C, bool mixed, const double* d_dens, hipStream_t s);
 // The Stokes double layer's far field (the stresslet) through the same pair
